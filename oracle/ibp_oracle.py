@@ -1,0 +1,490 @@
+"""FP64 CPU oracle: interval bound propagation (IBP) through the SC-DCOPF graph.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import or run this module.  The product
+path (the HIP library and its Python binding) never calls it, and this module
+imports nothing from the product package: it takes a network as a plain dict
+of numpy arrays (keys as produced by the seeded instance generator) and float32
+box endpoints, and computes everything itself in float64 with numpy/scipy.
+
+What it computes (paper: "Fast and Certified Bounding of Security-Constrained
+DCOPF via Interval Bound Propagation", Tekeler, Chevalier, Zhong, Zhang):
+
+* DC power-flow maps and the reduced PTDF, Sec. II-A, eqs. (DCPF mappings) and
+  (line flow ptdf); the full PTDF pads the slack column with zeros.
+* Device-to-bus maps N_g, N_d and the net injection p_inj = N_g p_g - N_d p_d,
+  Sec. II-A.
+* Nodal-imbalance expression s_inj = |(E^T Phi - I) p_inj|, Sec. III-A eq.
+  (slack-sinj); base overload s_fb = max(|Phi p_inj| - p_fb^max, 0), eq.
+  (slack-sfb).
+* Contingency flows in the paper's loop-free form
+  P_fc = M (x) 1 (Phi p)^T - B (x) (U p) 1^T, Sec. III-A eq. (ctg flow matrix
+  form), with b_i = M_i Y_D E_r u_i g_i, u_i = Y_Br^{-1} e_i,
+  g_i = y_i / (1 + e_i^T u_i y_i), y_i = -(Y_D)_ii, Sec. II-C eqs.
+  (nodal admittance rank-1 update) and (ctg flow simplified).
+* Overloads S_fc = max(|P_fc| - 1 p_fc^max^T, 0) and s_agg = 1^T S_fc 1,
+  eqs. (slack-Sc), (slack-sagg).
+* Objective f_ibp, Appendix eq. (ibp_f) (= eq. (penalized-objective)) with
+  linear costs, and its IBP enclosure over the box of eq. (f-ibp), using the
+  centre-radius rule of Sec. III-C eq. (IBP) for every affine node and the
+  tight interval absolute value for |.| (readings listed below).
+
+Readings taken where the paper is silent (each one is listed in the design doc):
+
+* Slack bus: an explicit parameter (``slack_bus``); row/column removed from
+  the reduced matrices.
+* E^T Phi - I: its exact value is -e_slack 1^T (the non-slack rows of
+  E_r^T Phi_r are the identity and the columns of E^T sum to zero); the oracle
+  uses that exact matrix, and a test checks it against the numerically formed
+  product.
+* |.| under IBP: tight interval magnitude |c| + r and mignitude
+  max(|c| - r, 0); max(. - fmax, 0) is monotone and applied to both ends.
+* Two penalty weights: zeta_inj on s_inj, zeta_f on both base and
+  contingency overloads (as eq. (penalized-objective) is written).
+* Islanding outages (1 - H_cc = 0) are excluded; the default contingency set
+  is every line whose removal leaves the network connected, ascending.
+* Reductions: numpy pairwise sums per chunk, combined with math.fsum.
+* Gradient: sign(0) = 0; max(z, 0) is active iff z > 0.
+
+Parity pins live in tests/test_oracle_*.py.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.linalg
+import scipy.sparse as sp
+import scipy.sparse.csgraph as csgraph
+import scipy.sparse.linalg as spla
+
+__all__ = [
+    "incidence",
+    "reduced_admittance",
+    "factors",
+    "islanding_lines",
+    "lodf",
+    "ibp",
+    "ibp_lodf_form",
+    "grad",
+    "point_eval",
+    "point_eval_many",
+    "center_radius",
+]
+
+
+# ----------------------------------------------------------------------------
+# network matrices (Sec. II-A)
+# ----------------------------------------------------------------------------
+
+def _n_line(net):
+    return int(np.asarray(net["line_from"]).size)
+
+
+def incidence(net) -> sp.csr_matrix:
+    """Branch-bus incidence E (L x N): +1 at the from bus, -1 at the to bus."""
+    L = _n_line(net)
+    N = int(net["n_bus"])
+    rows = np.repeat(np.arange(L), 2)
+    cols = np.stack([np.asarray(net["line_from"]), np.asarray(net["line_to"])], 1).ravel()
+    vals = np.tile([1.0, -1.0], L)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(L, N))
+
+
+def reduced_admittance(net, line_b=None):
+    """(E_r, Y_D, Y_Br, keep): E_r drops the slack column, Y_Br = E_r^T Y_D E_r.
+
+    Sec. II-A: p_inj,r = Y_Br theta_r and p_f = Y_D E_r theta_r.  ``line_b``
+    overrides the susceptances (used to take a line out for direct N-1 flows).
+    """
+    N = int(net["n_bus"])
+    s = int(net["slack_bus"])
+    keep = np.array([n for n in range(N) if n != s], dtype=np.int64)
+    E = incidence(net)
+    E_r = E[:, keep].tocsc()
+    b = np.asarray(net["line_b"] if line_b is None else line_b, dtype=np.float64)
+    Y_D = sp.diags(b)
+    Y_Br = (E_r.T @ Y_D @ E_r).tocsc()
+    return E_r, Y_D, Y_Br, keep
+
+
+def _injection_map(net) -> sp.csr_matrix:
+    """W_inj (N x X) with p_inj = N_g p_g - N_d p_d, inputs ordered gens then loads."""
+    N = int(net["n_bus"])
+    gb = np.asarray(net["gen_bus"])
+    lb = np.asarray(net["load_bus"])
+    G, D = gb.size, lb.size
+    rows = np.concatenate([gb, lb])
+    cols = np.arange(G + D)
+    vals = np.concatenate([np.ones(G), -np.ones(D)])
+    return sp.csr_matrix((vals, (rows, cols)), shape=(N, G + D))
+
+
+def islanding_lines(net) -> np.ndarray:
+    """Mask of lines whose single outage disconnects the network.
+
+    Brute force: remove each line in turn and count connected components.
+    """
+    N = int(net["n_bus"])
+    fr = np.asarray(net["line_from"])
+    to = np.asarray(net["line_to"])
+    L = fr.size
+    out = np.zeros(L, dtype=bool)
+    for l in range(L):
+        m = np.ones(L, dtype=bool)
+        m[l] = False
+        g = sp.coo_matrix((np.ones(m.sum()), (fr[m], to[m])), shape=(N, N))
+        ncomp, _ = csgraph.connected_components(g, directed=False)
+        out[l] = ncomp > 1
+    return out
+
+
+def _spd_inverse(A: np.ndarray) -> np.ndarray:
+    """Inverse of a symmetric positive definite matrix (LAPACK potrf + potri)."""
+    c, info = scipy.linalg.lapack.dpotrf(A, lower=1, clean=1, overwrite_a=0)
+    if info != 0:
+        raise np.linalg.LinAlgError("reduced admittance matrix is not positive definite "
+                                    "(is the network connected?)")
+    inv, info = scipy.linalg.lapack.dpotri(c, lower=1, overwrite_c=1)
+    if info != 0:
+        raise np.linalg.LinAlgError("potri failed")
+    inv = np.tril(inv) + np.tril(inv, -1).T
+    return inv
+
+
+def factors(net, with_paper_form: bool = True) -> dict:
+    """Everything the IBP graph needs that depends on the network only.
+
+    * ``Phi`` (L x N): Phi_r = Y_D E_r (E_r^T Y_D E_r)^{-1}, padded with a zero
+      slack column, eq. (line flow ptdf).
+    * ``ctg`` (K,): outaged line of each contingency.
+    * ``U`` (K x N): rows u'_i = [0 u_i^T] (slack entry zero), u_i = Y_Br^{-1} e_i.
+    * ``B`` (K x L): rows b_i = M_i Y_D E_r u_i g_i, g_i = y_i/(1 + e_i^T u_i y_i).
+    * ``M`` (K x L): all ones except the outaged line, Sec. III-A.
+    """
+    N = int(net["n_bus"])
+    L = _n_line(net)
+    E_r, Y_D, Y_Br, keep = reduced_admittance(net)
+    if N > 1:
+        ncomp, _ = csgraph.connected_components(
+            sp.coo_matrix((np.ones(L), (np.asarray(net["line_from"]), np.asarray(net["line_to"]))),
+                          shape=(N, N)), directed=False)
+        if ncomp > 1:
+            raise ValueError("network is not connected")
+    Binv = _spd_inverse(Y_Br.toarray())
+    YE = (Y_D @ E_r).tocsr()
+    Phi_r = np.asarray(YE @ Binv)                      # L x (N-1)
+    Phi = np.zeros((L, N))
+    Phi[:, keep] = Phi_r
+    b = np.asarray(net["line_b"], dtype=np.float64)
+
+    if net.get("ctg_line") is not None:
+        ctg = np.asarray(net["ctg_line"], dtype=np.int64)
+        if ctg.size and (ctg.min() < 0 or ctg.max() >= L):
+            raise ValueError("contingency line out of range")
+        if np.unique(ctg).size != ctg.size:
+            raise ValueError("duplicate contingency line")
+    else:
+        ctg = np.flatnonzero(~islanding_lines(net)).astype(np.int64)
+    K = ctg.size
+    out = dict(Phi=Phi, ctg=ctg, keep=keep, Binv=Binv, L=L, N=N, K=K)
+    if not with_paper_form:
+        return out
+    # u_i = Y_Br^{-1} e_i with e_i the i-th row of E_r (as a column)
+    E_r_csr = E_r.tocsr()
+    Er_rows = E_r_csr[ctg].toarray()                    # K x (N-1)
+    U_r = Er_rows @ Binv                                # K x (N-1); Binv symmetric
+    y = -b[ctg]
+    eu = np.einsum("kn,kn->k", Er_rows, U_r)           # e_i^T u_i
+    denom = 1.0 + eu * y
+    if K and np.min(np.abs(denom)) < 1e-9:
+        raise ValueError("an outage islands the network (1 + e^T u y = 0)")
+    g = y / denom
+    Bm = np.asarray(YE @ U_r.T).T * g[:, None]          # rows Y_D E_r u_i g_i
+    M = np.ones((K, L))
+    M[np.arange(K), ctg] = 0.0
+    Bm = M * Bm
+    U = np.zeros((K, N))
+    U[:, keep] = U_r
+    out.update(U=U, B=Bm, M=M, g=g)
+    return out
+
+
+def lodf(net, fac) -> np.ndarray:
+    """Line outage distribution factors (L x K): LODF[l, k] = H[l, c] / (1 - H[c, c]),
+    H[:, m] = Phi[:, from(m)] - Phi[:, to(m)], c = outaged line of contingency k.
+
+    The classical rule; the tests use it to check the paper-form factors
+    (M, B, U) of Sec. III-A, to which it is algebraically identical."""
+    Phi = fac["Phi"]
+    ctg = fac["ctg"]
+    fr = np.asarray(net["line_from"])[ctg]
+    to = np.asarray(net["line_to"])[ctg]
+    H = Phi[:, fr] - Phi[:, to]                          # L x K
+    Hcc = H[ctg, np.arange(ctg.size)]
+    return H / (1.0 - Hcc)[None, :]
+
+
+# ----------------------------------------------------------------------------
+# IBP (Sec. III-C) through the graph of Sec. III-A / Appendix
+# ----------------------------------------------------------------------------
+
+def center_radius(lo, hi):
+    """x_mu = (hi + lo)/2, x_sigma = (hi - lo)/2 in float64 (exact for float32 inputs)."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    if not (np.all(np.isfinite(lo)) and np.all(np.isfinite(hi))):
+        raise ValueError("box endpoints must be finite")
+    if np.any(lo > hi):
+        raise ValueError("box has lo > hi")
+    return 0.5 * (hi + lo), 0.5 * (hi - lo)
+
+
+def _abs_interval(c, r):
+    """Tight interval |.|: (mignitude, magnitude)."""
+    a = np.abs(c)
+    return np.maximum(a - r, 0.0), a + r
+
+
+def _fsum_pairwise(x) -> float:
+    return float(np.sum(x))
+
+
+def _imbalance_matrix(net) -> sp.csr_matrix:
+    """E^T Phi - I in closed form: -1 in every column of the slack row, else 0."""
+    N = int(net["n_bus"])
+    s = int(net["slack_bus"])
+    return sp.csr_matrix((-np.ones(N), (np.full(N, s), np.arange(N))), shape=(N, N))
+
+
+def ibp(net, lo, hi, fac=None, chunk: int = 256, keep_intermediates: bool = False) -> dict:
+    """IBP bounds [f_lo, f_hi] of f_ibp over the box [lo, hi] (inputs: gens then loads).
+
+    Returns a dict with ``f_lo``, ``f_hi`` and the interval terms
+    ``S`` (surplus), ``I`` (1^T s_inj), ``Fb`` (1^T s_fb), ``Fc`` (s_agg),
+    each as ``*_lo``/``*_hi``.
+    """
+    if fac is None:
+        fac = factors(net)
+    mu, sg = center_radius(lo, hi)
+    G = np.asarray(net["gen_bus"]).size
+    W = _injection_map(net)
+    c_inj = W @ mu
+    r_inj = abs(W) @ sg
+
+    # surplus sum_j c_j(p_d) - sum_i g_i(p_g), linear costs: affine node
+    w = np.concatenate([-np.asarray(net["gen_cost"], float), np.asarray(net["load_value"], float)])
+    S_c = math.fsum(w * mu)
+    S_r = math.fsum(np.abs(w) * sg)
+
+    # s_inj = |(E^T Phi - I) p_inj|, then 1^T s_inj
+    W2 = _imbalance_matrix(net)
+    cz = W2 @ c_inj
+    rz = abs(W2) @ r_inj
+    mig, mag = _abs_interval(cz, rz)
+    I_lo, I_hi = math.fsum(mig), math.fsum(mag)
+
+    # base flows Phi p_inj and s_fb = max(|.| - fmax, 0)
+    Phi = fac["Phi"]
+    c_f = Phi @ c_inj
+    r_f = np.abs(Phi) @ r_inj
+    fb = np.asarray(net["fmax_base"], float)
+    mig, mag = _abs_interval(c_f, r_f)
+    Fb_lo = math.fsum(np.maximum(mig - fb, 0.0))
+    Fb_hi = math.fsum(np.maximum(mag - fb, 0.0))
+
+    # contingency flows P_fc = M (x) 1 (Phi p)^T - B (x) (U p) 1^T
+    U, Bm, M = fac["U"], fac["B"], fac["M"]
+    c_u = U @ c_inj
+    r_u = np.abs(U) @ r_inj
+    fc = np.asarray(net["fmax_ctg"], float)
+    K = fac["K"]
+    parts_lo, parts_hi = [], []
+    for k0 in range(0, K, chunk):
+        k1 = min(K, k0 + chunk)
+        Mk, Bk = M[k0:k1], Bm[k0:k1]
+        Cc = Mk * c_f[None, :] - Bk * c_u[k0:k1, None]
+        Rc = np.abs(Mk) * r_f[None, :] + np.abs(Bk) * r_u[k0:k1, None]
+        mig, mag = _abs_interval(Cc, Rc)
+        parts_lo.append(_fsum_pairwise(np.maximum(mig - fc[None, :], 0.0)))
+        parts_hi.append(_fsum_pairwise(np.maximum(mag - fc[None, :], 0.0)))
+    Fc_lo, Fc_hi = math.fsum(parts_lo), math.fsum(parts_hi)
+
+    zi, zf = float(net["zeta_inj"]), float(net["zeta_f"])
+    S_lo, S_hi = S_c - S_r, S_c + S_r
+    f_hi = S_hi - zi * I_lo - zf * (Fb_lo + Fc_lo)
+    f_lo = S_lo - zi * I_hi - zf * (Fb_hi + Fc_hi)
+    out = dict(f_lo=f_lo, f_hi=f_hi, S_lo=S_lo, S_hi=S_hi, I_lo=I_lo, I_hi=I_hi,
+               Fb_lo=Fb_lo, Fb_hi=Fb_hi, Fc_lo=Fc_lo, Fc_hi=Fc_hi)
+    if keep_intermediates:
+        out.update(c_inj=c_inj, r_inj=r_inj, c_f=c_f, r_f=r_f, c_u=c_u, r_u=r_u)
+    return out
+
+
+def ibp_lodf_form(net, lo, hi, fac=None, chunk: int = 256) -> dict:
+    """Same bounds through the classical LODF rule f_l + LODF[l, c] f_c, with the
+    outaged line's own entry forced to zero.  Only used to check that the
+    paper's (M, B, U) form gives identical intervals."""
+    if fac is None:
+        fac = factors(net)
+    base = ibp(net, lo, hi, fac, keep_intermediates=True)
+    Lam = lodf(net, fac)                                # L x K
+    ctg = fac["ctg"]
+    c_f, r_f = base["c_f"], base["r_f"]
+    fc = np.asarray(net["fmax_ctg"], float)
+    K = ctg.size
+    parts_lo, parts_hi = [], []
+    for k0 in range(0, K, chunk):
+        k1 = min(K, k0 + chunk)
+        lam = Lam[:, k0:k1].T                            # k x L
+        cc = ctg[k0:k1]
+        C = c_f[None, :] + lam * c_f[cc][:, None]
+        R = r_f[None, :] + np.abs(lam) * r_f[cc][:, None]
+        C[np.arange(k1 - k0), cc] = 0.0
+        R[np.arange(k1 - k0), cc] = 0.0
+        mig, mag = _abs_interval(C, R)
+        parts_lo.append(_fsum_pairwise(np.maximum(mig - fc[None, :], 0.0)))
+        parts_hi.append(_fsum_pairwise(np.maximum(mag - fc[None, :], 0.0)))
+    Fc_lo, Fc_hi = math.fsum(parts_lo), math.fsum(parts_hi)
+    zi, zf = float(net["zeta_inj"]), float(net["zeta_f"])
+    f_hi = base["S_hi"] - zi * base["I_lo"] - zf * (base["Fb_lo"] + Fc_lo)
+    f_lo = base["S_lo"] - zi * base["I_hi"] - zf * (base["Fb_hi"] + Fc_hi)
+    return dict(f_lo=f_lo, f_hi=f_hi, Fc_lo=Fc_lo, Fc_hi=Fc_hi)
+
+
+# ----------------------------------------------------------------------------
+# analytic vector-Jacobian product of (f_lo, f_hi) w.r.t. the box endpoints
+# ----------------------------------------------------------------------------
+
+def grad(net, lo, hi, g_lo: float = 1.0, g_hi: float = 0.0, fac=None, chunk: int = 256):
+    """d(g_lo f_lo + g_hi f_hi) / d(lo, hi) of the IBP map above.
+
+    Subgradient convention: sign(0) = 0, max(z, 0) active iff z > 0.  Returns
+    (d_lo, d_hi) float64 arrays of length X and a count of elements that sit
+    within 1e-9 of a kink (callers use it to decide if a finite difference is
+    meaningful).
+    """
+    if fac is None:
+        fac = factors(net)
+    mu, sg = center_radius(lo, hi)
+    W = _injection_map(net)
+    Wa = abs(W)
+    c_inj = W @ mu
+    r_inj = Wa @ sg
+    zi, zf = float(net["zeta_inj"]), float(net["zeta_f"])
+    near = 0
+
+    # surplus: f_hi gets S_c + S_r, f_lo gets S_c - S_r
+    w = np.concatenate([-np.asarray(net["gen_cost"], float), np.asarray(net["load_value"], float)])
+    d_mu = (g_lo + g_hi) * w
+    d_sg = (g_hi - g_lo) * np.abs(w)
+    d_cinj = np.zeros_like(c_inj)
+    d_rinj = np.zeros_like(r_inj)
+
+    def abs_penalty_grads(c, r, thr):
+        """d/dc, d/dr of max(|c| + r - thr, 0) [used by f_lo] and of
+        max(|c| - r - thr, 0) [used by f_hi], plus near-kink count."""
+        a = np.abs(c)
+        t_hi = a + r - thr
+        t_lo = a - r - thr
+        act_hi = (t_hi > 0).astype(float)
+        act_lo = (t_lo > 0).astype(float)
+        s = np.sign(c)
+        nk = int(np.sum(np.abs(t_hi) < 1e-9) + np.sum(np.abs(t_lo) < 1e-9)
+                 + np.sum((np.abs(c) < 1e-9) & ((act_hi + act_lo) > 0)))
+        dc = -g_lo * s * act_hi - g_hi * s * act_lo
+        dr = -g_lo * act_hi + g_hi * act_lo
+        return dc, dr, nk
+
+    # imbalance: I_hi = sum |cz| + rz ; I_lo = sum max(|cz| - rz, 0)
+    W2 = _imbalance_matrix(net)
+    cz = W2 @ c_inj
+    rz = abs(W2) @ r_inj
+    dcz, drz, nk = abs_penalty_grads(cz, rz, 0.0)
+    near += nk
+    d_cinj += zi * (W2.T @ dcz)
+    d_rinj += zi * (abs(W2).T @ drz)
+
+    Phi = fac["Phi"]
+    c_f = Phi @ c_inj
+    r_f = np.abs(Phi) @ r_inj
+    dcf, drf, nk = abs_penalty_grads(c_f, r_f, np.asarray(net["fmax_base"], float))
+    near += nk
+    dcf = zf * dcf
+    drf = zf * drf
+
+    U, Bm, M = fac["U"], fac["B"], fac["M"]
+    c_u = U @ c_inj
+    r_u = np.abs(U) @ r_inj
+    fc = np.asarray(net["fmax_ctg"], float)
+    K = fac["K"]
+    dcu = np.zeros(K)
+    dru = np.zeros(K)
+    for k0 in range(0, K, chunk):
+        k1 = min(K, k0 + chunk)
+        Mk, Bk = M[k0:k1], Bm[k0:k1]
+        Cc = Mk * c_f[None, :] - Bk * c_u[k0:k1, None]
+        Rc = np.abs(Mk) * r_f[None, :] + np.abs(Bk) * r_u[k0:k1, None]
+        dC, dR, nk = abs_penalty_grads(Cc, Rc, fc[None, :])
+        near += nk
+        dC *= zf
+        dR *= zf
+        dcf += np.sum(Mk * dC, axis=0)
+        drf += np.sum(np.abs(Mk) * dR, axis=0)
+        dcu[k0:k1] = -np.sum(Bk * dC, axis=1)
+        dru[k0:k1] = np.sum(np.abs(Bk) * dR, axis=1)
+
+    d_cinj += Phi.T @ dcf + U.T @ dcu
+    d_rinj += np.abs(Phi).T @ drf + np.abs(U).T @ dru
+    d_mu += W.T @ d_cinj
+    d_sg += Wa.T @ d_rinj
+    d_lo = 0.5 * (d_mu - d_sg)
+    d_hi = 0.5 * (d_mu + d_sg)
+    return d_lo, d_hi, near
+
+
+# ----------------------------------------------------------------------------
+# point evaluation f(x) by direct DC power flow (no PTDF, no LODF, no IBP)
+# ----------------------------------------------------------------------------
+
+def point_eval_many(net, X, ctg=None) -> np.ndarray:
+    """f(x) of eq. (penalized-objective) with the slacks of Remark 1, at each row of X.
+
+    Base flows come from solving Y_Br theta_r = p_inj,r; the imbalance is the
+    literal KCL residual E^T p_f - p_inj (= (E^T Phi - I) p_inj); every
+    outage rebuilds Y_Br without the line and solves again.
+    """
+    X = np.atleast_2d(np.asarray(X, dtype=np.float64))
+    G = np.asarray(net["gen_bus"]).size
+    W = _injection_map(net)
+    P = W @ X.T                                           # N x n
+    E = incidence(net)
+    E_r, Y_D, Y_Br, keep = reduced_admittance(net)
+    lu = spla.splu(Y_Br.tocsc())
+    theta = np.zeros_like(P)
+    theta[keep] = lu.solve(np.ascontiguousarray(P[keep]))
+    pf = Y_D @ (E @ theta)                                # L x n
+    s_inj = np.abs(E.T @ pf - P)
+    fb = np.asarray(net["fmax_base"], float)[:, None]
+    s_fb = np.maximum(np.abs(pf) - fb, 0.0)
+    if ctg is None:
+        ctg = factors(net, with_paper_form=False)["ctg"]
+    fc = np.asarray(net["fmax_ctg"], float)[:, None]
+    b = np.asarray(net["line_b"], float)
+    s_fc = np.zeros(X.shape[0])
+    for c in ctg:
+        bc = b.copy()
+        bc[c] = 0.0
+        _, YDc, YBc, _ = reduced_admittance(net, line_b=bc)
+        luc = spla.splu(YBc.tocsc())
+        th = np.zeros_like(P)
+        th[keep] = luc.solve(np.ascontiguousarray(P[keep]))
+        pfc = YDc @ (E @ th)
+        s_fc += np.sum(np.maximum(np.abs(pfc) - fc, 0.0), axis=0)
+    w = np.concatenate([-np.asarray(net["gen_cost"], float), np.asarray(net["load_value"], float)])
+    zi, zf = float(net["zeta_inj"]), float(net["zeta_f"])
+    return X @ w - zi * s_inj.sum(0) - zf * (s_fb.sum(0) + s_fc)
+
+
+def point_eval(net, x, ctg=None) -> float:
+    return float(point_eval_many(net, np.asarray(x)[None, :], ctg)[0])
