@@ -1,0 +1,178 @@
+/*
+ * ibp.h -- C ABI of libibp: certified interval bounds on the soft-constrained
+ * SC-DCOPF market surplus by interval bound propagation (IBP), on MI355X.
+ *
+ * Paper: "Fast and Certified Bounding of Security-Constrained DCOPF via
+ * Interval Bound Propagation" (Tekeler, Chevalier, Zhong, Zhang).
+ *
+ * For each input box  p_g in [pg_lo, pg_hi],  p_d in [pd_lo, pd_hi]
+ * (Appendix, eq. (f-ibp)) the library returns  [f_lo, f_hi]  with
+ *
+ *     f_lo <= min_box f_ibp  and  f_hi >= max_box f_ibp,
+ *
+ * where f_ibp is the explicit graph of the Appendix, eq. (ibp_f):
+ *   surplus  sum_j value_j p_d,j - sum_i cost_i p_g,i  (linear costs),
+ *   minus zeta_inj * 1^T |(E^T Phi - I) p_inj|        (Sec. III-A, eq. slack-sinj),
+ *   minus zeta_f * 1^T max(|Phi p_inj| - fmax_b, 0)    (eq. slack-sfb),
+ *   minus zeta_f * sum over N-1 outages and lines of
+ *         max(|post-outage flow| - fmax_c, 0)          (eqs. slack-Sc, slack-sagg),
+ * with p_inj = N_g p_g - N_d p_d (Sec. II-A), the PTDF Phi of eq. (line flow
+ * ptdf) and post-outage flows from the rank-1 outage update of Sec. II-C,
+ * eq. (ctg flow simplified).  The bounds are those of IBP (Sec. III-C, eq. IBP)
+ * through that graph, computed in float32 with outward padding so that they
+ * enclose the exact-arithmetic IBP bounds.
+ *
+ * Conventions for every call:
+ *   - Sizes are element counts.  Indices are 0-based int32.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP device
+ *     memory on the device the network was built for.
+ *   - The library never takes ownership of caller memory.
+ *   - Errors that the host can detect are returned synchronously and nothing is
+ *     launched; ibp_last_error() then gives a message (thread-local, valid until
+ *     the next call on the same thread).
+ *   - Compute calls are asynchronous on the given stream (a hipStream_t passed as
+ *     void*; NULL means the default stream).
+ */
+#ifndef IBP_H_
+#define IBP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ibp_status {
+  IBP_OK = 0,
+  IBP_E_INVALID_ARG = 1,     /* NULL pointer, size or index out of range, non-positive b/fmax/zeta */
+  IBP_E_DISCONNECTED = 2,    /* base network not connected (reduced admittance singular) */
+  IBP_E_ISLANDING_CTG = 3,   /* an explicitly listed outage disconnects the network */
+  IBP_E_ILL_CONDITIONED = 4, /* 1 - H_cc < 1e-6 for some outage (rank-1 update near singular) */
+  IBP_E_OUT_OF_MEMORY = 5,   /* host or device allocation failed */
+  IBP_E_DEVICE = 6,          /* a HIP runtime call failed */
+  IBP_E_WORKSPACE = 7,       /* workspace NULL or smaller than ibp_workspace_bytes() */
+  IBP_E_HOST_ONLY = 8        /* compute call on a handle built with IBP_DEVICE_HOST_ONLY */
+} ibp_status;
+
+/* Network description (all host memory; copied by ibp_build_network).
+ * Sec. II-A: buses, lines with susceptance b (Y_D = diag(b)), slack bus whose
+ * row/column is removed from the reduced matrices; Sec. II-B/C: base-case and
+ * post-outage flow limits; Sec. II-D: penalty weights zeta_inj, zeta_f. */
+typedef struct ibp_network_desc {
+  int32_t n_bus;            /* N >= 2 */
+  int32_t n_line;           /* L >= 1 */
+  int32_t slack_bus;        /* in [0, N) */
+  const int32_t* line_from; /* [L] in [0, N), from != to */
+  const int32_t* line_to;   /* [L] */
+  const double* line_b;     /* [L] susceptance > 0 */
+  const double* fmax_base;  /* [L] base-case limit > 0 */
+  const double* fmax_ctg;   /* [L] post-outage limit > 0 */
+  int32_t n_gen;            /* G >= 0 */
+  const int32_t* gen_bus;   /* [G] */
+  const double* gen_cost;   /* [G] linear cost, $/p.u.-h (any sign) */
+  int32_t n_load;           /* D >= 0, G + D >= 1 */
+  const int32_t* load_bus;  /* [D] */
+  const double* load_value; /* [D] linear value, $/p.u.-h (any sign) */
+  double zeta_inj;          /* >= 0 */
+  double zeta_f;            /* >= 0 */
+  int32_t n_ctg;            /* K; ignored when ctg_line is NULL */
+  const int32_t* ctg_line;  /* [K] distinct non-islanding lines, or NULL for
+                               every non-islanding line in ascending order */
+} ibp_network_desc;
+
+typedef struct ibp_network ibp_network;
+
+typedef struct ibp_network_info {
+  int32_t n_bus, n_line, n_ctg, n_gen, n_load, n_input; /* n_input = G + D */
+  int32_t device;             /* HIP device ordinal, or IBP_DEVICE_HOST_ONLY */
+  double min_one_minus_hcc;   /* smallest 1 - H_cc over the outages */
+  double phi_abs_err;         /* a-posteriori bound on |Phi64 - Phi_exact| (max over entries) */
+  size_t device_bytes;        /* device memory held by the handle */
+  double build_seconds;       /* wall time of the float64 construction */
+} ibp_network_info;
+
+#define IBP_DEVICE_HOST_ONLY (-1)
+
+/* ibp_build_network -- float64 construction of PTDF (Sec. II-A, eq. line flow
+ * ptdf) and of the outage factors (Sec. II-C, rank-1 update and eq. ctg flow
+ * simplified), rounding to float32 and upload to `device`.
+ * device = IBP_DEVICE_HOST_ONLY builds on the host only (no HIP call at all);
+ * such a handle supports query/export/free but no compute call.
+ * Synchronous.  On success *out owns host and device memory until
+ * ibp_free_network.  Errors: INVALID_ARG, DISCONNECTED, ISLANDING_CTG,
+ * ILL_CONDITIONED, OUT_OF_MEMORY, DEVICE. */
+ibp_status ibp_build_network(const ibp_network_desc* desc, int device, ibp_network** out);
+
+/* Fills *info (host).  Errors: INVALID_ARG on NULL. */
+ibp_status ibp_network_query(const ibp_network* net, ibp_network_info* info);
+
+/* Copies the K outaged line indices (host int32[K]). */
+ibp_status ibp_network_ctg_lines(const ibp_network* net, int32_t* out);
+
+/* Copies the float64 factors the float32 device copies were rounded from:
+ * ptdf (host, L x N row-major, slack column zero) and lodf (host, K x L
+ * row-major: row k is the outage-distribution column of outage k, entry
+ * (k, c(k)) holds the raw value H_cc / (1 - H_cc) and is never used).
+ * Either pointer may be NULL. */
+ibp_status ibp_network_export(const ibp_network* net, double* ptdf, double* lodf);
+
+/* Releases everything held by the handle.  NULL is allowed. */
+void ibp_free_network(ibp_network* net);
+
+/* Flags for the compute calls. */
+#define IBP_F_NONE 0u
+#define IBP_F_PLAIN 1u /* per-box single-box kernels even for n_box > 1 (reference form for batching) */
+
+/* Bytes of device workspace a compute call needs for n_box boxes (0 on error). */
+size_t ibp_workspace_bytes(const ibp_network* net, int64_t n_box, uint32_t flags);
+
+/* ibp_bound_boxes -- IBP bounds of f_ibp over n_box boxes (Appendix, eqs.
+ * (ibp_f), (f-ibp); Sec. III-C, eq. IBP).
+ *   box_lo, box_hi : device float32 [n_box x X], row-major, X = G + D inputs,
+ *                    generators first, then loads.  The float32 values are the box.
+ *   f_lo, f_hi     : device float64 [n_box], written.
+ *   terms          : device float64 [n_box x 8] or NULL; per box the intervals
+ *                    S_lo, S_hi (surplus), I_lo, I_hi (1^T s_inj), Fb_lo, Fb_hi
+ *                    (1^T s_fb), Fc_lo, Fc_hi (s_agg), each already padded.
+ *   ws, ws_bytes   : device workspace of at least ibp_workspace_bytes(net, n_box, flags).
+ * A box with a non-finite endpoint or lo > hi gets NaN outputs; other boxes are
+ * unaffected.  Concurrent calls on one handle are safe with distinct workspaces.
+ * Errors: INVALID_ARG, WORKSPACE, HOST_ONLY, DEVICE. */
+ibp_status ibp_bound_boxes(const ibp_network* net, int64_t n_box,
+                           const float* box_lo, const float* box_hi,
+                           double* f_lo, double* f_hi, double* terms,
+                           void* ws, size_t ws_bytes, void* stream, uint32_t flags);
+
+/* ibp_bound_backward -- vector-Jacobian product of the (unpadded) IBP map:
+ *   g_box_lo[b, j] = d(g_f_lo[b] f_lo[b] + g_f_hi[b] f_hi[b]) / d box_lo[b, j],
+ *   g_box_hi likewise (device float64 [n_box x X], overwritten).
+ * Subgradient convention: sign(0) = 0 and max(z, 0) is active iff z > 0.
+ * g_f_lo, g_f_hi: device float64 [n_box].  Same workspace rule as the forward
+ * call (it recomputes the forward intermediates).  Errors as the forward call. */
+ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box,
+                              const float* box_lo, const float* box_hi,
+                              const double* g_f_lo, const double* g_f_hi,
+                              double* g_box_lo, double* g_box_hi,
+                              void* ws, size_t ws_bytes, void* stream, uint32_t flags);
+
+/* Kernel timing for benchmarks and profiling.  While enabled, every compute
+ * call on `net` records a HIP event pair around each kernel it queues, on the
+ * call's stream.  ibp_kernel_times() waits for those events and returns, per
+ * kernel id, the summed milliseconds and the number of launches since the last
+ * read (then clears them).  Kernel ids: 0 box preparation, 1 base flows,
+ * 2 outage sweep, 3 finalize, 4 batched base flows, 5 batched outage sweep,
+ * 6 backward outage sweep, 7 backward transposed PTDF, 8 backward endpoints.
+ * Not thread-safe with concurrent compute calls on the same handle. */
+#define IBP_N_KERNEL_IDS 9
+ibp_status ibp_set_kernel_timing(ibp_network* net, int enable);
+ibp_status ibp_kernel_times(ibp_network* net, int32_t n_ids, double* total_ms, int64_t* count);
+
+/* Last error message of the calling thread ("" if none). */
+const char* ibp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IBP_H_ */

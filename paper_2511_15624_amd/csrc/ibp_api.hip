@@ -1,0 +1,362 @@
+// C ABI of libibp (declared in include/ibp.h): handle lifetime, float32
+// packing and upload of the float64 factors, workspace sizing, argument
+// checks and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ibp_device.h"
+#include "ibp_internal.h"
+#include "ibp_kernels.h"
+
+struct ibp_network {
+  ibp::HostNet h;
+  int device = IBP_DEVICE_HOST_ONLY;
+  int num_cus = 256;
+  ibp::DevNet dn{};
+  std::vector<void*> allocs;
+  size_t device_bytes = 0;
+  ibp::KernelTimer timer;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+ibp_status fail(ibp_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+template <typename T>
+ibp_status upload(ibp_network* net, const T* src, size_t count, const T** dst) {
+  void* p = nullptr;
+  const size_t bytes = std::max<size_t>(1, count) * sizeof(T);
+  if (hipMalloc(&p, bytes) != hipSuccess)
+    return fail(IBP_E_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  net->allocs.push_back(p);
+  net->device_bytes += bytes;
+  if (count && hipMemcpy(p, src, count * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(IBP_E_DEVICE, "hipMemcpy to device failed");
+  *dst = static_cast<const T*>(p);
+  return IBP_OK;
+}
+
+void clear_timer(ibp_network* net) {
+  for (auto& r : net->timer.recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  net->timer.recs.clear();
+}
+
+void release_device(ibp_network* net) {
+  if (net->device >= 0) {
+    DeviceGuard g(net->device);
+    clear_timer(net);
+    for (void* p : net->allocs) (void)hipFree(p);
+  }
+  net->allocs.clear();
+  net->device_bytes = 0;
+}
+
+ibp_status to_device(ibp_network* net, int device) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+    return fail(IBP_E_DEVICE, "no HIP device available");
+  if (device < 0 || device >= count)
+    return fail(IBP_E_INVALID_ARG, "device ordinal out of range");
+  DeviceGuard g(device);
+  if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
+  net->device = device;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+    net->num_cus = cus;
+
+  const ibp::HostNet& h = net->h;
+  ibp::DevNet& d = net->dn;
+  d.N = h.N;
+  d.L = h.L;
+  d.K = h.K;
+  d.G = h.G;
+  d.D = h.D;
+  d.X = h.G + h.D;
+  d.Np = round_up(h.N, 64);
+  d.Lp = round_up(h.L, 64);
+  d.zeta_inj = h.zeta_inj;
+  d.zeta_f = h.zeta_f;
+  d.phi_err_max = h.phi_err_max;
+  d.gamma64_n = (double)(h.N + 64) * ibp::kU64 * 1.01;
+
+  ibp_status st;
+  {
+    std::vector<float> phi32((size_t)h.L * d.Np, 0.0f);
+    for (int l = 0; l < h.L; ++l)
+      for (int n = 0; n < h.N; ++n) phi32[(size_t)l * d.Np + n] = (float)h.phi[(size_t)l * h.N + n];
+    if ((st = upload(net, phi32.data(), phi32.size(), &d.phi)) != IBP_OK) return st;
+  }
+  {
+    std::vector<float> lodf32((size_t)std::max(1, h.K) * d.Lp, 0.0f);
+    for (int k = 0; k < h.K; ++k) {
+      float* row = lodf32.data() + (size_t)k * d.Lp;
+      const double* src = h.lodf.data() + (size_t)k * h.L;
+      for (int l = 0; l < h.L; ++l) row[l] = (float)src[l];
+      row[h.ctg_line[k]] = std::numeric_limits<float>::quiet_NaN();  // outaged line's own entry
+    }
+    if ((st = upload(net, lodf32.data(), (size_t)h.K * d.Lp, &d.lodf)) != IBP_OK) return st;
+  }
+  if ((st = upload(net, h.fmax_base.data(), h.L, &d.fmax_b)) != IBP_OK) return st;
+  if ((st = upload(net, h.fmax_ctg.data(), h.L, &d.fmax_c)) != IBP_OK) return st;
+  if ((st = upload(net, h.phi_err.data(), h.L, &d.phi_err)) != IBP_OK) return st;
+  if ((st = upload(net, h.ctg_of_line.data(), h.L, &d.ctg_of_line)) != IBP_OK) return st;
+  if ((st = upload(net, h.ctg_line.data(), h.K, &d.ctg_line)) != IBP_OK) return st;
+  {
+    // outage-factor error from the PTDF error (rank-1 update of Sec. II-C):
+    // |dLam[l,k]| <= (2 eps_l + 2 |Lam| eps_c) / (1 - H_cc); the eps_c part goes into
+    // the outage radius, the eps_l part is applied per tile with the box's
+    // max_k (|c_c| + r_c) / (1 - H_cc)
+    std::vector<double> eps(h.K), inv(h.K);
+    for (int k = 0; k < h.K; ++k) {
+      eps[k] = 2.0 * h.phi_err[h.ctg_line[k]] / h.one_m_hcc[k] * (1.0 + 1e-12);
+      inv[k] = 1.0 / h.one_m_hcc[k] * (1.0 + 1e-12);
+    }
+    if ((st = upload(net, eps.data(), eps.size(), &d.ctg_eps)) != IBP_OK) return st;
+    if ((st = upload(net, inv.data(), inv.size(), &d.ctg_inv)) != IBP_OK) return st;
+    std::vector<float> le(d.Lp, 0.0f);
+    for (int l = 0; l < h.L; ++l) {
+      // 2 eps_l plus the float32 subnormal spacing of a stored factor, rounded up
+      const double v = (2.0 * h.phi_err[l] + std::ldexp(1.0, -149)) * (1.0 + 1.0 / 1024.0);
+      float f = (float)v;
+      if ((double)f < v) f = std::nextafter(f, std::numeric_limits<float>::infinity());
+      le[l] = f;
+    }
+    if ((st = upload(net, le.data(), le.size(), &d.line_eps)) != IBP_OK) return st;
+  }
+  {
+    const int X = h.G + h.D;
+    std::vector<int> ptr(h.N + 1, 0), dev(X);
+    std::vector<double> w(X);
+    for (int g = 0; g < h.G; ++g) ptr[h.gen_bus[g] + 1]++;
+    for (int j = 0; j < h.D; ++j) ptr[h.load_bus[j] + 1]++;
+    for (int n = 0; n < h.N; ++n) ptr[n + 1] += ptr[n];
+    std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+    for (int g = 0; g < h.G; ++g) dev[fill[h.gen_bus[g]]++] = g;
+    for (int j = 0; j < h.D; ++j) dev[fill[h.load_bus[j]]++] = h.G + j;
+    for (int g = 0; g < h.G; ++g) w[g] = -h.gen_cost[g];
+    for (int j = 0; j < h.D; ++j) w[h.G + j] = h.load_value[j];
+    if ((st = upload(net, ptr.data(), ptr.size(), &d.bus_ptr)) != IBP_OK) return st;
+    if ((st = upload(net, dev.data(), dev.size(), &d.bus_dev)) != IBP_OK) return st;
+    if ((st = upload(net, w.data(), w.size(), &d.dev_w)) != IBP_OK) return st;
+  }
+  if (hipDeviceSynchronize() != hipSuccess) return fail(IBP_E_DEVICE, "device synchronize failed");
+  return IBP_OK;
+}
+
+ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
+  (void)flags;
+  const ibp::DevNet& d = net->dn;
+  ibp::WsLayout lay;
+  ibp::plan_single(d, n_box, lay, net->num_cus);
+  if (d.K == 0) lay.n_p3 = 0;
+  const size_t B = (size_t)std::max<int64_t>(1, n_box);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  lay.cinj = take(B * d.Np * sizeof(float));
+  lay.rpp = take(B * d.Np * sizeof(float));
+  lay.box = take(B * ibp::kBoxSlots * sizeof(double));
+  lay.lc = take(B * d.Lp * sizeof(float));
+  lay.lh = take(B * d.Lp * sizeof(float));
+  lay.lg = take(B * d.Lp * sizeof(float));
+  lay.lcf = take(B * d.L * sizeof(double));
+  lay.lrf = take(B * d.L * sizeof(double));
+  lay.ctg = take(B * std::max(1, d.K) * 4 * sizeof(int));
+  lay.p2 = take(B * std::max(1, lay.n_p2) * 2 * sizeof(double));
+  lay.p3 = take(B * std::max(1, lay.n_p3) * 2 * sizeof(double));
+  lay.total = off;
+  return lay;
+}
+
+ibp_status check_compute_args(const ibp_network* net, int64_t n_box, const void* lo, const void* hi,
+                              const void* a, const void* b, void* ws, size_t ws_bytes,
+                              uint32_t flags, ibp::WsLayout& lay) {
+  if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
+  if (net->device < 0) return fail(IBP_E_HOST_ONLY, "network was built host-only");
+  if (n_box < 0) return fail(IBP_E_INVALID_ARG, "n_box < 0");
+  if (flags & ~uint32_t(IBP_F_PLAIN)) return fail(IBP_E_INVALID_ARG, "unknown flag bits");
+  if (n_box == 0) return IBP_OK;
+  if (!lo || !hi || !a || !b) return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
+  lay = layout(net, n_box, flags);
+  if (!ws || ws_bytes < lay.total)
+    return fail(IBP_E_WORKSPACE, "workspace needs " + std::to_string(lay.total) + " bytes, got " +
+                                     std::to_string(ws_bytes));
+  return IBP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ibp_status ibp_build_network(const ibp_network_desc* desc, int device, ibp_network** out) {
+  g_err.clear();
+  if (!out) return fail(IBP_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (device < IBP_DEVICE_HOST_ONLY) return fail(IBP_E_INVALID_ARG, "device ordinal out of range");
+  ibp_network* net = new (std::nothrow) ibp_network();
+  if (!net) return fail(IBP_E_OUT_OF_MEMORY, "host allocation failed");
+  std::string err;
+  ibp_status st;
+  try {
+    st = ibp::build_host(desc, net->h, err);
+  } catch (const std::bad_alloc&) {
+    st = IBP_E_OUT_OF_MEMORY;
+    err = "host allocation failed during construction";
+  }
+  if (st != IBP_OK) {
+    delete net;
+    return fail(st, err);
+  }
+  if (device >= 0) {
+    try {
+      st = to_device(net, device);
+    } catch (const std::bad_alloc&) {
+      st = fail(IBP_E_OUT_OF_MEMORY, "host allocation failed while packing float32 factors");
+    }
+    if (st != IBP_OK) {
+      const std::string keep = g_err;
+      release_device(net);
+      delete net;
+      return fail(st, keep);
+    }
+  }
+  *out = net;
+  return IBP_OK;
+}
+
+ibp_status ibp_network_query(const ibp_network* net, ibp_network_info* info) {
+  if (!net || !info) return fail(IBP_E_INVALID_ARG, "NULL argument");
+  info->n_bus = net->h.N;
+  info->n_line = net->h.L;
+  info->n_ctg = net->h.K;
+  info->n_gen = net->h.G;
+  info->n_load = net->h.D;
+  info->n_input = net->h.G + net->h.D;
+  info->device = net->device;
+  info->min_one_minus_hcc = net->h.min_one_m_hcc;
+  info->phi_abs_err = net->h.phi_err_max;
+  info->device_bytes = net->device_bytes;
+  info->build_seconds = net->h.build_seconds;
+  return IBP_OK;
+}
+
+ibp_status ibp_network_ctg_lines(const ibp_network* net, int32_t* out) {
+  if (!net || (!out && net->h.K > 0)) return fail(IBP_E_INVALID_ARG, "NULL argument");
+  if (net->h.K) std::memcpy(out, net->h.ctg_line.data(), sizeof(int32_t) * net->h.K);
+  return IBP_OK;
+}
+
+ibp_status ibp_network_export(const ibp_network* net, double* ptdf, double* lodf) {
+  if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
+  if (ptdf) std::memcpy(ptdf, net->h.phi.data(), sizeof(double) * net->h.phi.size());
+  if (lodf) std::memcpy(lodf, net->h.lodf.data(), sizeof(double) * net->h.lodf.size());
+  return IBP_OK;
+}
+
+void ibp_free_network(ibp_network* net) {
+  if (!net) return;
+  release_device(net);
+  delete net;
+}
+
+size_t ibp_workspace_bytes(const ibp_network* net, int64_t n_box, uint32_t flags) {
+  if (!net || net->device < 0 || n_box < 0) return 0;
+  return layout(net, n_box, flags).total;
+}
+
+ibp_status ibp_bound_boxes(const ibp_network* net, int64_t n_box, const float* box_lo,
+                           const float* box_hi, double* f_lo, double* f_hi, double* terms, void* ws,
+                           size_t ws_bytes, void* stream, uint32_t flags) {
+  g_err.clear();
+  ibp::WsLayout lay;
+  ibp_status st = check_compute_args(net, n_box, box_lo, box_hi, f_lo, f_hi, ws, ws_bytes, flags, lay);
+  if (st != IBP_OK || n_box == 0) return st;
+  DeviceGuard g(net->device);
+  if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
+  hipError_t e = ibp::launch_forward_single(net->dn, n_box, box_lo, box_hi, f_lo, f_hi, terms, ws, lay,
+                                            static_cast<hipStream_t>(stream),
+                                            const_cast<ibp::KernelTimer*>(&net->timer));
+  if (e != hipSuccess) return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  return IBP_OK;
+}
+
+ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box, const float* box_lo,
+                              const float* box_hi, const double* g_f_lo, const double* g_f_hi,
+                              double* g_box_lo, double* g_box_hi, void* ws, size_t ws_bytes,
+                              void* stream, uint32_t flags) {
+  g_err.clear();
+  (void)net; (void)n_box; (void)box_lo; (void)box_hi; (void)g_f_lo; (void)g_f_hi;
+  (void)g_box_lo; (void)g_box_hi; (void)ws; (void)ws_bytes; (void)stream; (void)flags;
+  return fail(IBP_E_INVALID_ARG, "backward not available yet");
+}
+
+ibp_status ibp_set_kernel_timing(ibp_network* net, int enable) {
+  if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
+  if (net->device < 0) return fail(IBP_E_HOST_ONLY, "network was built host-only");
+  net->timer.enabled = enable != 0;
+  return IBP_OK;
+}
+
+ibp_status ibp_kernel_times(ibp_network* net, int32_t n_ids, double* total_ms, int64_t* count) {
+  if (!net || !total_ms || !count || n_ids < 0) return fail(IBP_E_INVALID_ARG, "NULL argument");
+  if (net->device < 0) return fail(IBP_E_HOST_ONLY, "network was built host-only");
+  DeviceGuard g(net->device);
+  for (int i = 0; i < n_ids; ++i) {
+    total_ms[i] = 0.0;
+    count[i] = 0;
+  }
+  ibp_status st = IBP_OK;
+  for (auto& r : net->timer.recs) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+      st = fail(IBP_E_DEVICE, "reading kernel timing events failed");
+      continue;
+    }
+    if (r.id >= 0 && r.id < n_ids) {
+      total_ms[r.id] += ms;
+      count[r.id] += 1;
+    }
+  }
+  clear_timer(net);
+  return st;
+}
+
+const char* ibp_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,70 @@
+// Device-side data of a built network and the per-call workspace layout.
+// Shared by the kernels and the host launcher code of libibp.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ibp {
+
+// float32 unit roundoff and float64 unit roundoff
+constexpr double kU32 = 5.9604644775390625e-08;  // 2^-24
+constexpr double kU64 = 1.1102230246251565e-16;  // 2^-53
+// relative error of storing a float64 factor as float32 (round to nearest),
+// measured against the stored value: |x - fl(x)| <= u |fl(x)| / (1 - u)
+constexpr double kKappa0 = kU32 * (1.0 + 1.0 / 1048576.0);
+
+// Per-box scalar slots in the workspace (float64).
+enum BoxSlot : int {
+  kS_lo = 0,
+  kS_hi,
+  kI_lo,
+  kI_hi,
+  kMc,    // sum_n |c32_n|
+  kMbox,  // sum_n (|c32_n| + r32_n)
+  kM3,    // upper bound on |c_f[l]| + r_f[l] for every line
+  kBad,   // 1 if the box has a non-finite endpoint or lo > hi
+  kVmax,  // float bits (as a 32-bit slot): max over outages of (|c_c| + r_c) / (1 - H_cc)
+  kBoxSlots = 10
+};
+
+// Network data on the device (everything the kernels read), passed by value.
+struct DevNet {
+  int N, L, K, G, D, X;
+  int Np, Lp;  // padded row strides of the PTDF (buses) and outage factors (lines)
+  const float* phi;         // [L x Np] float32 PTDF, zero padding
+  const float* lodf;        // [K x Lp] float32 outage factors, NaN at (k, c(k)), zero padding
+  const double* fmax_b;     // [L]
+  const double* fmax_c;     // [L]
+  const double* phi_err;    // [L] absolute float64 PTDF error bound of the row
+  const int* ctg_of_line;   // [L] contingency index or -1
+  const int* ctg_line;      // [K]
+  const double* ctg_eps;    // [K] 2 phi_err[c] / (1 - H_cc)
+  const double* ctg_inv;    // [K] 1 / (1 - H_cc)
+  const float* line_eps;    // [Lp] 2 phi_err[l], rounded up (0 on padding lines)
+  const int* bus_ptr;       // [N + 1] CSR over buses of the devices on each bus
+  const int* bus_dev;       // [X] device indices (0..G-1 generators, G..X-1 loads)
+  const double* dev_w;      // [X] -cost for generators, +value for loads
+  double zeta_inj, zeta_f;
+  double phi_err_max;
+  double gamma64_n;         // float64 accumulation bound for one PTDF row
+};
+
+// Workspace carve-up for n_box boxes.  Offsets in bytes from the base pointer.
+struct WsLayout {
+  size_t cinj = 0, rpp = 0;        // float [B][Np]: centre and inflated radius of injections
+  size_t box = 0;                  // double [B][kBoxSlots]
+  size_t lc = 0, lh = 0, lg = 0;   // float [B][Lp]: line centre, h = rho'-fmax, g = rho'+fmax
+  size_t lcf = 0, lrf = 0;         // double [B][L]: base-flow centre and enclosing radius
+  size_t ctg = 0;                  // int4 [B][K]: (line, centre bits, rho' bits, 0)
+  size_t p2 = 0;                   // double2 [B][n_p2]: base-penalty partial sums (hi, lo)
+  size_t p3 = 0;                   // double2 [B][n_p3]: contingency partial sums (hi, lo)
+  size_t gcf = 0, grf = 0;         // float [B][Lp]: backward line gradients (centre, radius)
+  size_t gci = 0, gri = 0;         // double [B][Np]: backward injection gradients
+  size_t total = 0;
+  int n_p2 = 0, n_p3 = 0;
+  int k2_blocks = 0;               // K2 blocks per box
+  int k3_bx = 0, k3_by = 0;        // K3 grid per box
+};
+
+}  // namespace ibp

@@ -1,0 +1,45 @@
+// Launchers of the HIP kernels (defined in the .hip sources).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include <vector>
+
+#include "ibp_device.h"
+
+namespace ibp {
+
+// Optional per-kernel event timing (see ibp_set_kernel_timing).
+struct KernelTimer {
+  bool enabled = false;
+  struct Rec {
+    int id;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  // Records an event before a launch; returns the index to close with stop().
+  int start(int id, hipStream_t s) {
+    if (!enabled) return -1;
+    Rec r{id, nullptr, nullptr};
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return -1;
+    (void)hipEventRecord(r.a, s);
+    recs.push_back(r);
+    return (int)recs.size() - 1;
+  }
+  void stop(int idx, hipStream_t s) {
+    if (idx >= 0) (void)hipEventRecord(recs[idx].b, s);
+  }
+};
+
+// Grid shapes and partial-sum counts of the single-box-per-slice forward path.
+void plan_single(const DevNet& net, int64_t n_box, WsLayout& lay, int num_cus);
+
+// K1..K4 for n_box boxes, each box handled by its own grid slice.
+hipError_t launch_forward_single(const DevNet& net, int64_t n_box, const float* lo, const float* hi,
+                                 double* f_lo, double* f_hi, double* terms, void* ws,
+                                 const WsLayout& lay, hipStream_t s, KernelTimer* tm);
+
+}  // namespace ibp

@@ -1,0 +1,316 @@
+"""Thin ctypes binding of libibp (include/ibp.h): argument marshalling only.
+
+Every step of the bound computation runs in the HIP library; PyTorch is used
+for device memory (tensors whose pointers are handed to the library) and for
+the stream the kernels are queued on.  There is no fallback: if the library
+is missing the calls raise.
+
+Python names mirror the C entry points: ``ibp_build_network``,
+``ibp_bound_boxes``, ``ibp_bound_backward``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libibp.so")
+
+IBP_DEVICE_HOST_ONLY = -1
+IBP_F_NONE = 0
+IBP_F_PLAIN = 1
+
+STATUS = {
+    0: "IBP_OK",
+    1: "IBP_E_INVALID_ARG",
+    2: "IBP_E_DISCONNECTED",
+    3: "IBP_E_ISLANDING_CTG",
+    4: "IBP_E_ILL_CONDITIONED",
+    5: "IBP_E_OUT_OF_MEMORY",
+    6: "IBP_E_DEVICE",
+    7: "IBP_E_WORKSPACE",
+    8: "IBP_E_HOST_ONLY",
+}
+
+EXPORTED = [
+    "ibp_build_network",
+    "ibp_network_query",
+    "ibp_network_ctg_lines",
+    "ibp_network_export",
+    "ibp_free_network",
+    "ibp_workspace_bytes",
+    "ibp_bound_boxes",
+    "ibp_bound_backward",
+    "ibp_set_kernel_timing",
+    "ibp_kernel_times",
+    "ibp_last_error",
+]
+
+KERNEL_IDS = ["box_prep", "base_flows", "outage_sweep", "finalize", "batched_base_flows",
+              "batched_outage_sweep", "backward_outage_sweep", "backward_ptdf_t", "backward_endpoints"]
+
+
+class IBPError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class NetworkDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_bus", ctypes.c_int32),
+        ("n_line", ctypes.c_int32),
+        ("slack_bus", ctypes.c_int32),
+        ("line_from", ctypes.POINTER(ctypes.c_int32)),
+        ("line_to", ctypes.POINTER(ctypes.c_int32)),
+        ("line_b", ctypes.POINTER(ctypes.c_double)),
+        ("fmax_base", ctypes.POINTER(ctypes.c_double)),
+        ("fmax_ctg", ctypes.POINTER(ctypes.c_double)),
+        ("n_gen", ctypes.c_int32),
+        ("gen_bus", ctypes.POINTER(ctypes.c_int32)),
+        ("gen_cost", ctypes.POINTER(ctypes.c_double)),
+        ("n_load", ctypes.c_int32),
+        ("load_bus", ctypes.POINTER(ctypes.c_int32)),
+        ("load_value", ctypes.POINTER(ctypes.c_double)),
+        ("zeta_inj", ctypes.c_double),
+        ("zeta_f", ctypes.c_double),
+        ("n_ctg", ctypes.c_int32),
+        ("ctg_line", ctypes.POINTER(ctypes.c_int32)),
+    ]
+
+
+class NetworkInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_bus", ctypes.c_int32),
+        ("n_line", ctypes.c_int32),
+        ("n_ctg", ctypes.c_int32),
+        ("n_gen", ctypes.c_int32),
+        ("n_load", ctypes.c_int32),
+        ("n_input", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+        ("min_one_minus_hcc", ctypes.c_double),
+        ("phi_abs_err", ctypes.c_double),
+        ("device_bytes", ctypes.c_size_t),
+        ("build_seconds", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libibp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: run `python -m paper_2511_15624_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, sz, i64, u32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64, ctypes.c_uint32
+    lib.ibp_build_network.argtypes = [ctypes.POINTER(NetworkDesc), ctypes.c_int, ctypes.POINTER(vp)]
+    lib.ibp_build_network.restype = ctypes.c_int
+    lib.ibp_network_query.argtypes = [vp, ctypes.POINTER(NetworkInfo)]
+    lib.ibp_network_query.restype = ctypes.c_int
+    lib.ibp_network_ctg_lines.argtypes = [vp, vp]
+    lib.ibp_network_ctg_lines.restype = ctypes.c_int
+    lib.ibp_network_export.argtypes = [vp, vp, vp]
+    lib.ibp_network_export.restype = ctypes.c_int
+    lib.ibp_free_network.argtypes = [vp]
+    lib.ibp_free_network.restype = None
+    lib.ibp_workspace_bytes.argtypes = [vp, i64, u32]
+    lib.ibp_workspace_bytes.restype = sz
+    lib.ibp_bound_boxes.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, sz, vp, u32]
+    lib.ibp_bound_boxes.restype = ctypes.c_int
+    lib.ibp_bound_backward.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp, u32]
+    lib.ibp_bound_backward.restype = ctypes.c_int
+    lib.ibp_set_kernel_timing.argtypes = [vp, ctypes.c_int]
+    lib.ibp_set_kernel_timing.restype = ctypes.c_int
+    lib.ibp_kernel_times.argtypes = [vp, ctypes.c_int32, vp, vp]
+    lib.ibp_kernel_times.restype = ctypes.c_int
+    lib.ibp_last_error.argtypes = []
+    lib.ibp_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise IBPError(status, load_library().ibp_last_error().decode())
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+class Network:
+    """Owns an ``ibp_network*``.  ``net`` is a dict of numpy arrays (see synth)."""
+
+    def __init__(self, net: dict, device: int = 0):
+        lib = load_library()
+        self._keep = {}
+
+        def arr(key, dtype):
+            a = np.ascontiguousarray(np.asarray(net[key]), dtype=dtype)
+            self._keep[key] = a
+            return a
+
+        lf, lt = arr("line_from", np.int32), arr("line_to", np.int32)
+        lb = arr("line_b", np.float64)
+        fb, fc = arr("fmax_base", np.float64), arr("fmax_ctg", np.float64)
+        gb, gc = arr("gen_bus", np.int32), arr("gen_cost", np.float64)
+        db, dv = arr("load_bus", np.int32), arr("load_value", np.float64)
+        d = NetworkDesc()
+        d.n_bus = int(net["n_bus"])
+        d.n_line = lf.size
+        d.slack_bus = int(net["slack_bus"])
+        d.line_from, d.line_to = _ptr(lf, ctypes.c_int32), _ptr(lt, ctypes.c_int32)
+        d.line_b = _ptr(lb, ctypes.c_double)
+        d.fmax_base, d.fmax_ctg = _ptr(fb, ctypes.c_double), _ptr(fc, ctypes.c_double)
+        d.n_gen, d.gen_bus, d.gen_cost = gb.size, _ptr(gb, ctypes.c_int32), _ptr(gc, ctypes.c_double)
+        d.n_load, d.load_bus, d.load_value = db.size, _ptr(db, ctypes.c_int32), _ptr(dv, ctypes.c_double)
+        d.zeta_inj = float(net["zeta_inj"])
+        d.zeta_f = float(net["zeta_f"])
+        if net.get("ctg_line") is not None:
+            cl = arr("ctg_line", np.int32)
+            d.n_ctg = cl.size
+            d.ctg_line = _ptr(cl, ctypes.c_int32)
+        else:
+            d.n_ctg = 0
+            d.ctg_line = ctypes.POINTER(ctypes.c_int32)()
+        h = ctypes.c_void_p()
+        _check(lib.ibp_build_network(ctypes.byref(d), int(device), ctypes.byref(h)))
+        self._h = h
+        self._keep = None
+        info = NetworkInfo()
+        _check(lib.ibp_network_query(h, ctypes.byref(info)))
+        self.info = info
+        self.n_bus, self.n_line, self.n_ctg = info.n_bus, info.n_line, info.n_ctg
+        self.n_gen, self.n_load, self.n_input = info.n_gen, info.n_load, info.n_input
+        self.device = info.device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def ctg_lines(self) -> np.ndarray:
+        out = np.zeros(self.n_ctg, np.int32)
+        _check(load_library().ibp_network_ctg_lines(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def export(self):
+        ptdf = np.zeros((self.n_line, self.n_bus))
+        lodf = np.zeros((self.n_ctg, self.n_line))
+        _check(load_library().ibp_network_export(self._h, ptdf.ctypes.data_as(ctypes.c_void_p),
+                                                 lodf.ctypes.data_as(ctypes.c_void_p)))
+        return ptdf, lodf
+
+    def workspace_bytes(self, n_box: int, flags: int = 0) -> int:
+        return int(load_library().ibp_workspace_bytes(self._h, int(n_box), int(flags)))
+
+    def set_kernel_timing(self, enable: bool):
+        _check(load_library().ibp_set_kernel_timing(self._h, int(bool(enable))))
+
+    def kernel_times(self) -> dict:
+        """{kernel name: (total_ms, launches)} since the last read."""
+        n = len(KERNEL_IDS)
+        ms = np.zeros(n)
+        cnt = np.zeros(n, np.int64)
+        _check(load_library().ibp_kernel_times(self._h, n, ms.ctypes.data_as(ctypes.c_void_p),
+                                               cnt.ctypes.data_as(ctypes.c_void_p)))
+        return {KERNEL_IDS[i]: (float(ms[i]), int(cnt[i])) for i in range(n) if cnt[i] > 0}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().ibp_free_network(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ibp_build_network(net: dict, device: int = 0) -> Network:
+    return Network(net, device)
+
+
+# ---------------------------------------------------------------- torch helpers
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p()
+
+
+class Workspace:
+    """Grow-only device workspace (a uint8 tensor) for one network."""
+
+    def __init__(self, net: Network):
+        self.net = net
+        self.buf = None
+
+    def get(self, n_box: int, flags: int = 0):
+        torch = _torch()
+        need = self.net.workspace_bytes(n_box, flags)
+        if self.buf is None or self.buf.numel() < need:
+            self.buf = torch.empty(max(need, 256), dtype=torch.uint8, device=f"cuda:{self.net.device}")
+        return self.buf, need
+
+
+def _check_boxes(net: Network, lo, hi):
+    torch = _torch()
+    if lo.dtype != torch.float32 or hi.dtype != torch.float32:
+        raise TypeError("box endpoints must be float32")
+    if lo.shape != hi.shape or lo.dim() != 2 or lo.shape[1] != net.n_input:
+        raise ValueError(f"boxes must be [n_box, {net.n_input}]")
+    if not (lo.is_cuda and hi.is_cuda):
+        raise ValueError("boxes must be device tensors")
+    return lo.contiguous(), hi.contiguous()
+
+
+def ibp_bound_boxes(net: Network, lo, hi, terms: bool = False, flags: int = 0, ws: Workspace = None,
+                    stream=None):
+    """Bounds [f_lo, f_hi] (float64 device tensors) for float32 device boxes [n_box, X]."""
+    torch = _torch()
+    lo, hi = _check_boxes(net, lo, hi)
+    n = lo.shape[0]
+    f_lo = torch.empty(n, dtype=torch.float64, device=lo.device)
+    f_hi = torch.empty(n, dtype=torch.float64, device=lo.device)
+    t = torch.empty((n, 8), dtype=torch.float64, device=lo.device) if terms else None
+    ws = ws or Workspace(net)
+    buf, need = ws.get(n, flags)
+    _check(load_library().ibp_bound_boxes(net.handle, n, _dev_ptr(lo), _dev_ptr(hi), _dev_ptr(f_lo),
+                                          _dev_ptr(f_hi), _dev_ptr(t), _dev_ptr(buf), buf.numel(),
+                                          _stream_ptr(stream), flags))
+    return (f_lo, f_hi, t) if terms else (f_lo, f_hi)
+
+
+def ibp_bound_backward(net: Network, lo, hi, g_lo, g_hi, flags: int = 0, ws: Workspace = None,
+                       stream=None):
+    """d(g_lo . f_lo + g_hi . f_hi) / d(lo, hi) as float64 device tensors [n_box, X]."""
+    torch = _torch()
+    lo, hi = _check_boxes(net, lo, hi)
+    n = lo.shape[0]
+    g_lo = g_lo.to(device=lo.device, dtype=torch.float64).contiguous()
+    g_hi = g_hi.to(device=lo.device, dtype=torch.float64).contiguous()
+    d_lo = torch.empty((n, net.n_input), dtype=torch.float64, device=lo.device)
+    d_hi = torch.empty((n, net.n_input), dtype=torch.float64, device=lo.device)
+    ws = ws or Workspace(net)
+    buf, need = ws.get(n, flags)
+    _check(load_library().ibp_bound_backward(net.handle, n, _dev_ptr(lo), _dev_ptr(hi), _dev_ptr(g_lo),
+                                             _dev_ptr(g_hi), _dev_ptr(d_lo), _dev_ptr(d_hi),
+                                             _dev_ptr(buf), buf.numel(), _stream_ptr(stream), flags))
+    return d_lo, d_hi

@@ -1,0 +1,126 @@
+"""C-ABI host path (no GPU): the library loads, exports every declared symbol,
+validates descriptions, and its float64 construction matches the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2511_15624_amd import ibp, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    with open(os.path.join(ROOT, "include", "ibp.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(ibp_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return ibp.load_library()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = _declared_functions()
+    assert set(names) == set(ibp.EXPORTED)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_last_error_empty_initially(lib):
+    assert isinstance(lib.ibp_last_error(), bytes)
+
+
+def _host(net):
+    return ibp.Network(net, device=ibp.IBP_DEVICE_HOST_ONLY)
+
+
+@pytest.mark.parametrize("name", ["tiny", "c500"])
+def test_host_construction_matches_oracle(name):
+    net = synth.make_config(name)
+    h = _host(net)
+    fac = oracle.factors(net)
+    assert list(h.ctg_lines()) == list(fac["ctg"])
+    ptdf, lodf = h.export()
+    np.testing.assert_allclose(ptdf, fac["Phi"], atol=1e-11, rtol=0)
+    ref = oracle.lodf(net, fac).T          # K x L
+    mask = np.ones_like(ref, dtype=bool)
+    mask[np.arange(ref.shape[0]), fac["ctg"]] = False
+    np.testing.assert_allclose(lodf[mask], ref[mask], atol=1e-10, rtol=0)
+    # the a-posteriori PTDF error bound covers the actual difference to the oracle
+    assert np.max(np.abs(ptdf - fac["Phi"])) <= h.info.phi_abs_err
+    assert 0 < h.info.min_one_minus_hcc <= 1
+    assert h.info.device == ibp.IBP_DEVICE_HOST_ONLY
+    h.close()
+
+
+def test_explicit_contingency_list():
+    net = synth.make_config("c500")
+    fac = oracle.factors(net)
+    pick = np.sort(np.random.default_rng(0).choice(fac["ctg"], 50, replace=False)).astype(np.int32)
+    h = _host(dict(net, ctg_line=pick))
+    assert list(h.ctg_lines()) == list(pick)
+    _, lodf = h.export()
+    assert lodf.shape == (50, 700)
+
+
+def _expect(status_name, net):
+    with pytest.raises(ibp.IBPError) as e:
+        _host(net)
+    assert e.value.name == status_name, str(e.value)
+    return str(e.value)
+
+
+def test_invalid_descriptions():
+    net = synth.make_config("tiny")
+    bad = dict(net, line_to=net["line_from"].copy())
+    _expect("IBP_E_INVALID_ARG", bad)                       # self loops
+    b = net["line_b"].copy()
+    b[3] = 0.0
+    _expect("IBP_E_INVALID_ARG", dict(net, line_b=b))      # b must be > 0
+    f = net["fmax_base"].copy()
+    f[0] = -1.0
+    _expect("IBP_E_INVALID_ARG", dict(net, fmax_base=f))   # limits must be > 0
+    _expect("IBP_E_INVALID_ARG", dict(net, slack_bus=99))
+    gb = net["gen_bus"].copy()
+    gb[0] = 14
+    _expect("IBP_E_INVALID_ARG", dict(net, gen_bus=gb))
+    _expect("IBP_E_INVALID_ARG", dict(net, zeta_f=-1.0))
+    _expect("IBP_E_INVALID_ARG", dict(net, ctg_line=np.array([0, 0], np.int32)))
+    _expect("IBP_E_INVALID_ARG", dict(net, ctg_line=np.array([20], np.int32)))
+
+
+def test_disconnected_network():
+    net = synth.make_config("tiny")
+    # drop every line touching bus 5: bus 5 becomes unreachable
+    keep = (net["line_from"] != 5) & (net["line_to"] != 5)
+    sub = dict(net)
+    for k in ("line_from", "line_to", "line_b", "fmax_base", "fmax_ctg"):
+        sub[k] = net[k][keep]
+    msg = _expect("IBP_E_DISCONNECTED", sub)
+    assert "not connected" in msg
+
+
+def test_islanding_contingency_rejected():
+    net = synth.make_config("tiny")
+    br = synth.find_bridges(net["n_bus"], net["line_from"], net["line_to"])
+    assert br.any()
+    _expect("IBP_E_ISLANDING_CTG", dict(net, ctg_line=np.flatnonzero(br)[:1].astype(np.int32)))
+
+
+def test_compute_calls_need_a_device_handle(lib):
+    import ctypes
+    h = _host(synth.make_config("tiny"))
+    assert lib.ibp_workspace_bytes(h.handle, 1, 0) == 0
+    st = lib.ibp_bound_boxes(h.handle, 1, None, None, None, None, None, None, 0, None, 0)
+    assert ibp.STATUS[st] == "IBP_E_HOST_ONLY"
+    st = lib.ibp_bound_backward(h.handle, 1, None, None, None, None, None, None, None, 0, None, 0)
+    assert ibp.STATUS[st] == "IBP_E_HOST_ONLY"
+    st = lib.ibp_bound_boxes(None, 1, None, None, None, None, None, None, 0, None, 0)
+    assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"
+    lib.ibp_free_network(None)
+    info = ibp.NetworkInfo()
+    assert ibp.STATUS[lib.ibp_network_query(None, ctypes.byref(info))] == "IBP_E_INVALID_ARG"
