@@ -161,12 +161,26 @@ ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box,
  * call's stream.  ibp_kernel_times() waits for those events and returns, per
  * kernel id, the summed milliseconds and the number of launches since the last
  * read (then clears them).  Kernel ids: 0 box preparation, 1 base flows,
- * 2 outage sweep, 3 finalize, 4 batched base flows, 5 batched outage sweep,
- * 6 backward outage sweep, 7 backward transposed PTDF, 8 backward endpoints.
+ * 2 outage sweep, 3 finalize, 4 line epilogue, 5 batched base flows,
+ * 6 batched outage sweep, 7 backward outage sweep, 8 backward transposed PTDF,
+ * 9 backward endpoints.
  * Not thread-safe with concurrent compute calls on the same handle. */
-#define IBP_N_KERNEL_IDS 9
+#define IBP_N_KERNEL_IDS 10
 ibp_status ibp_set_kernel_timing(ibp_network* net, int enable);
 ibp_status ibp_kernel_times(ibp_network* net, int32_t n_ids, double* total_ms, int64_t* count);
+
+/* Tile parameters of the two streaming kernels: k2_nc buses per wave in the
+ * base-flow sweep (32, 64, 128, 256) and k3_kc outages per block in the outage
+ * sweep (16, 32, 64, 128).  They change the workspace size; results do not
+ * depend on them beyond float64 summation order.  ibp_autotune() times every
+ * pair on the caller's boxes (forward calls on `stream`, synchronizing) and
+ * keeps the fastest; `chosen` (host int32[2], nullable) receives it.  The
+ * workspace must hold ibp_workspace_bytes(net, n_box, IBP_F_AUTOTUNE).
+ * Neither call may run concurrently with compute calls on the same handle. */
+#define IBP_F_AUTOTUNE 2u /* workspace query only: size for every tile pair */
+ibp_status ibp_set_tile(ibp_network* net, int32_t k2_nc, int32_t k3_kc);
+ibp_status ibp_autotune(ibp_network* net, int64_t n_box, const float* box_lo, const float* box_hi,
+                        void* ws, size_t ws_bytes, void* stream, int32_t* chosen);
 
 /* Last error message of the calling thread ("" if none). */
 const char* ibp_last_error(void);

@@ -24,6 +24,7 @@ struct ibp_network {
   std::vector<void*> allocs;
   size_t device_bytes = 0;
   ibp::KernelTimer timer;
+  ibp::Tune tune;
 };
 
 namespace {
@@ -114,10 +115,16 @@ ibp_status to_device(ibp_network* net, int device) {
 
   ibp_status st;
   {
-    std::vector<float> phi32((size_t)h.L * d.Np, 0.0f);
-    for (int l = 0; l < h.L; ++l)
-      for (int n = 0; n < h.N; ++n) phi32[(size_t)l * d.Np + n] = (float)h.phi[(size_t)l * h.N + n];
-    if ((st = upload(net, phi32.data(), phi32.size(), &d.phi)) != IBP_OK) return st;
+    // transposed PTDF, bus-major: row n holds the flows on every line for a unit
+    // injection at bus n (column n of Phi); padding lines are zero
+    std::vector<float> phiT((size_t)h.N * d.Lp, 0.0f);
+    ibp::parallel_for(h.N, 64, [&](int64_t a, int64_t b) {
+      for (int64_t n = a; n < b; ++n) {
+        float* row = phiT.data() + (size_t)n * d.Lp;
+        for (int l = 0; l < h.L; ++l) row[l] = (float)h.phi[(size_t)l * h.N + n];
+      }
+    });
+    if ((st = upload(net, phiT.data(), phiT.size(), &d.phiT)) != IBP_OK) return st;
   }
   {
     std::vector<float> lodf32((size_t)std::max(1, h.K) * d.Lp, 0.0f);
@@ -173,15 +180,47 @@ ibp_status to_device(ibp_network* net, int device) {
     if ((st = upload(net, w.data(), w.size(), &d.dev_w)) != IBP_OK) return st;
   }
   if (hipDeviceSynchronize() != hipSuccess) return fail(IBP_E_DEVICE, "device synchronize failed");
+  // default tiles: the longest bus chunk that still gives the base-flow sweep
+  // about six waves per CU, and short outage chunks (many waves in flight)
+  {
+    const int lt = (d.Lp / 4 + 63) / 64;
+    int nc = 32;
+    for (int c : {256, 128, 64}) {
+      if ((int64_t)lt * ((h.N + c - 1) / c) >= 6LL * net->num_cus) {
+        nc = c;
+        break;
+      }
+    }
+    net->tune.k2_nc = nc;
+    net->tune.k3_kc = 16;
+  }
+  if (const char* e = std::getenv("IBP_TILE")) {
+    ibp::Tune t = net->tune;
+    int v = 0;
+    if (const char* p = std::strstr(e, "k2nc=")) t.k2_nc = (v = std::atoi(p + 5)) ? v : t.k2_nc;
+    if (const char* p = std::strstr(e, "k3kc=")) t.k3_kc = (v = std::atoi(p + 5)) ? v : t.k3_kc;
+    if (ibp::tune_valid(t)) net->tune = t;
+  }
   return IBP_OK;
 }
 
+ibp::WsLayout layout_for(const ibp_network* net, int64_t n_box, const ibp::Tune& tune);
+
 ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
-  (void)flags;
+  if (flags & IBP_F_AUTOTUNE) {
+    // the largest layout over every tile pair (smallest tiles give most partials)
+    ibp::Tune t;
+    t.k2_nc = 32;
+    t.k3_kc = 16;
+    return layout_for(net, n_box, t);
+  }
+  return layout_for(net, n_box, net->tune);
+}
+
+ibp::WsLayout layout_for(const ibp_network* net, int64_t n_box, const ibp::Tune& tune) {
   const ibp::DevNet& d = net->dn;
   ibp::WsLayout lay;
-  ibp::plan_single(d, n_box, lay, net->num_cus);
-  if (d.K == 0) lay.n_p3 = 0;
+  ibp::plan_single(d, n_box, lay, tune);
   const size_t B = (size_t)std::max<int64_t>(1, n_box);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -189,8 +228,9 @@ ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
     off = align256(off + bytes);
     return o;
   };
-  lay.cinj = take(B * d.Np * sizeof(float));
-  lay.rpp = take(B * d.Np * sizeof(float));
+  lay.inj = take(B * d.Np * 2 * sizeof(double));
+  lay.p1 = take(B * lay.n_p1 * ibp::kP1Fields * sizeof(double));
+  lay.part2 = take(B * lay.k2_by * d.Lp * 2 * sizeof(double));
   lay.box = take(B * ibp::kBoxSlots * sizeof(double));
   lay.lc = take(B * d.Lp * sizeof(float));
   lay.lh = take(B * d.Lp * sizeof(float));
@@ -355,6 +395,76 @@ ibp_status ibp_kernel_times(ibp_network* net, int32_t n_ids, double* total_ms, i
   }
   clear_timer(net);
   return st;
+}
+
+ibp_status ibp_set_tile(ibp_network* net, int32_t k2_nc, int32_t k3_kc) {
+  if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
+  ibp::Tune t;
+  t.k2_nc = k2_nc;
+  t.k3_kc = k3_kc;
+  if (!ibp::tune_valid(t)) return fail(IBP_E_INVALID_ARG, "unsupported tile parameters");
+  net->tune = t;
+  return IBP_OK;
+}
+
+ibp_status ibp_autotune(ibp_network* net, int64_t n_box, const float* box_lo, const float* box_hi,
+                        void* ws, size_t ws_bytes, void* stream, int32_t* chosen) {
+  g_err.clear();
+  if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
+  if (net->device < 0) return fail(IBP_E_HOST_ONLY, "network was built host-only");
+  if (n_box <= 0 || !box_lo || !box_hi) return fail(IBP_E_INVALID_ARG, "need at least one device box");
+  const ibp::WsLayout big = layout(net, n_box, IBP_F_AUTOTUNE);
+  if (!ws || ws_bytes < big.total)
+    return fail(IBP_E_WORKSPACE, "autotune workspace needs " + std::to_string(big.total) + " bytes");
+  DeviceGuard g(net->device);
+  if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // scratch outputs for the timing runs
+  double* f = nullptr;
+  if (hipMalloc(&f, sizeof(double) * 2 * n_box) != hipSuccess)
+    return fail(IBP_E_OUT_OF_MEMORY, "autotune output buffer");
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const int ncs[] = {32, 64, 128, 256};
+  const int kcs[] = {16, 32, 64, 128};
+  float best = 1e30f;
+  ibp::Tune best_t = net->tune;
+  ibp::KernelTimer off;
+  ibp_status st = IBP_OK;
+  for (int nc : ncs) {
+    for (int kc : kcs) {
+      ibp::Tune t;
+      t.k2_nc = nc;
+      t.k3_kc = kc;
+      const ibp::WsLayout lay = layout_for(net, n_box, t);
+      float ms = 0.0f;
+      for (int rep = 0; rep < 2; ++rep) {  // first round warms up
+        (void)hipEventRecord(e0, s);
+        for (int it = 0; it < 3; ++it)
+          if (ibp::launch_forward_single(net->dn, n_box, box_lo, box_hi, f, f + n_box, nullptr, ws, lay, s,
+                                         &off) != hipSuccess)
+            st = fail(IBP_E_DEVICE, "autotune launch failed");
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) st = fail(IBP_E_DEVICE, "autotune synchronize failed");
+        (void)hipEventElapsedTime(&ms, e0, e1);
+      }
+      if (st == IBP_OK && ms < best) {
+        best = ms;
+        best_t = t;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(f);
+  if (st != IBP_OK) return st;
+  net->tune = best_t;
+  if (chosen) {
+    chosen[0] = best_t.k2_nc;
+    chosen[1] = best_t.k3_kc;
+  }
+  return IBP_OK;
 }
 
 const char* ibp_last_error(void) { return g_err.c_str(); }

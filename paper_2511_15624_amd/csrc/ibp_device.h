@@ -16,23 +16,29 @@ constexpr double kKappa0 = kU32 * (1.0 + 1.0 / 1048576.0);
 
 // Per-box scalar slots in the workspace (float64).
 enum BoxSlot : int {
-  kS_lo = 0,
-  kS_hi,
-  kI_lo,
-  kI_hi,
-  kMc,    // sum_n |c32_n|
-  kMbox,  // sum_n (|c32_n| + r32_n)
-  kM3,    // upper bound on |c_f[l]| + r_f[l] for every line
-  kBad,   // 1 if the box has a non-finite endpoint or lo > hi
-  kVmax,  // float bits (as a 32-bit slot): max over outages of (|c_c| + r_c) / (1 - H_cc)
-  kBoxSlots = 10
+  kVmax = 0,  // float bits (low 32 bits): max over outages of (|c_c| + r_c) / (1 - H_cc)
+  kBoxSlots = 2
+};
+
+// Fields of the per-block partial record written by the box-preparation kernel.
+enum P1Field : int {
+  kP1Mc = 0,   // sum |c32_n|
+  kP1Mbox,     // sum (|c32_n| + r32_n)
+  kP1Sc,       // sum w_j c_j        (surplus centre)
+  kP1Sr,       // sum |w_j| r_j      (surplus radius)
+  kP1Sabs,     // sum |w_j c_j| + |w_j| r_j
+  kP1cI,       // sum gens c - sum loads c   (total injection centre)
+  kP1rI,       // sum r                      (total injection radius)
+  kP1cIabs,    // sum |c|
+  kP1Bad,      // number of invalid inputs
+  kP1Fields = 10
 };
 
 // Network data on the device (everything the kernels read), passed by value.
 struct DevNet {
   int N, L, K, G, D, X;
   int Np, Lp;  // padded row strides of the PTDF (buses) and outage factors (lines)
-  const float* phi;         // [L x Np] float32 PTDF, zero padding
+  const float* phiT;        // [N x Lp] float32 PTDF transposed (row n = column n of Phi), zero padding
   const float* lodf;        // [K x Lp] float32 outage factors, NaN at (k, c(k)), zero padding
   const double* fmax_b;     // [L]
   const double* fmax_c;     // [L]
@@ -52,7 +58,9 @@ struct DevNet {
 
 // Workspace carve-up for n_box boxes.  Offsets in bytes from the base pointer.
 struct WsLayout {
-  size_t cinj = 0, rpp = 0;        // float [B][Np]: centre and inflated radius of injections
+  size_t inj = 0;                  // double2 [B][Np]: (c32, r'') of the injections, as float64
+  size_t p1 = 0;                   // double [B][n_p1][kP1Fields]: box-preparation partial sums
+  size_t part2 = 0;                // double2 [B][n_by][Lp]: base-flow partial sums (centre, radius)
   size_t box = 0;                  // double [B][kBoxSlots]
   size_t lc = 0, lh = 0, lg = 0;   // float [B][Lp]: line centre, h = rho'-fmax, g = rho'+fmax
   size_t lcf = 0, lrf = 0;         // double [B][L]: base-flow centre and enclosing radius
@@ -62,9 +70,10 @@ struct WsLayout {
   size_t gcf = 0, grf = 0;         // float [B][Lp]: backward line gradients (centre, radius)
   size_t gci = 0, gri = 0;         // double [B][Np]: backward injection gradients
   size_t total = 0;
-  int n_p2 = 0, n_p3 = 0;
-  int k2_blocks = 0;               // K2 blocks per box
-  int k3_bx = 0, k3_by = 0;        // K3 grid per box
+  int n_p1 = 0, n_p2 = 0, n_p3 = 0;
+  int k2_bx = 0, k2_by = 0;        // K2 grid per box (line tiles x bus chunks)
+  int k3_bx = 0, k3_by = 0;        // K3 grid per box (line tiles x outage chunks)
+  int k2_nc = 0, k3_kc = 0;        // tile parameters used
 };
 
 }  // namespace ibp

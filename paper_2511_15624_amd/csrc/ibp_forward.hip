@@ -66,6 +66,14 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
   return t;
 }
 
+// Streaming load of a float4 that is read exactly once (nontemporal hint: the
+// line is not kept in the caches).
+typedef float vf4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld_stream(const float4* p) {
+  const vf4_t t = __builtin_nontemporal_load(reinterpret_cast<const vf4_t*>(p));
+  return make_float4(t.x, t.y, t.z, t.w);
+}
+
 template <typename T>
 __device__ __forceinline__ T* ws_ptr(void* ws, size_t off) {
   return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + off);
@@ -73,106 +81,87 @@ __device__ __forceinline__ T* ws_ptr(void* ws, size_t off) {
 
 // ---------------------------------------------------------------- K1
 
-__global__ __launch_bounds__(256) void k1_box_prep(DevNet net, const float* __restrict__ box_lo,
-                                                   const float* __restrict__ box_hi, void* ws,
-                                                   WsLayout lay, int64_t box0) {
-  __shared__ double sh[4];
-  const int64_t b = box0 + blockIdx.x;
+// One wave per 64 buses / 64 inputs of a box: injection intervals rounded
+// outward to float32, and partial float64 sums for the surplus, the total
+// injection and the padding constants.
+__global__ __launch_bounds__(64) void k1_box_prep(DevNet net, const float* __restrict__ box_lo,
+                                                  const float* __restrict__ box_hi, void* ws,
+                                                  WsLayout lay, int64_t box0) {
+  const int64_t b = box0 + blockIdx.y;
+  const int i = blockIdx.x * 64 + threadIdx.x;
   const int X = net.X, G = net.G;
   const float* lo = box_lo + b * X;
   const float* hi = box_hi + b * X;
 
-  // surplus and total-injection sums over the inputs (float64; centre and
-  // radius of float32 endpoints are exact in float64)
-  double Sc = 0, Sr = 0, Sabs = 0, cI = 0, rI = 0, cIabs = 0, bad = 0;
-  for (int j = threadIdx.x; j < X; j += 256) {
-    const double l = lo[j], h = hi[j];
-    if (!(l <= h) || !isfinite(l) || !isfinite(h)) bad = 1.0;
+  double v[kP1Fields];
+#pragma unroll
+  for (int f = 0; f < kP1Fields; ++f) v[f] = 0.0;
+
+  // buses: p_inj = N_g p_g - N_d p_d as an interval, rounded outward
+  if (i < net.Np) {
+    double2* inj = ws_ptr<double2>(ws, lay.inj) + b * net.Np;
+    if (i < net.N) {
+      double c = 0, r = 0, a = 0;
+      int cnt = 0;
+      const int e0 = net.bus_ptr[i], e1 = net.bus_ptr[i + 1];
+      for (int e = e0; e < e1; ++e) {
+        const int j = net.bus_dev[e];
+        const double l = lo[j], h = hi[j];
+        const double cj = 0.5 * (l + h), rj = 0.5 * (h - l);
+        c += (j < G) ? cj : -cj;
+        r += rj;
+        a += fabs(cj);
+        ++cnt;
+      }
+      // float64 summation error of c and r (cnt terms each)
+      const double e64 = (cnt + 1) * kU64 * (a + r) * 1.01;
+      const float c32 = (float)c;
+      const float r32 = ru32((r + 2.0 * e64 + fabs(c - (double)c32)) * (1.0 + 4.0 * kU64));
+      // radius inflated for the float32 rounding of the PTDF entries
+      const float rp = ru32(((1.0 + kKappa0) * (double)r32 + kKappa0 * fabs((double)c32)) *
+                            (1.0 + 4.0 * kU64));
+      inj[i] = make_double2((double)c32, (double)rp);
+      v[kP1Mc] = fabs((double)c32);
+      v[kP1Mbox] = fabs((double)c32) + (double)r32;
+    } else {
+      inj[i] = make_double2(0.0, 0.0);
+    }
+  }
+  // inputs: surplus and total injection (centre and radius of float32
+  // endpoints are exact in float64)
+  if (i < X) {
+    const double l = lo[i], h = hi[i];
+    if (!(l <= h) || !isfinite(l) || !isfinite(h)) v[kP1Bad] = 1.0;
     const double c = 0.5 * (l + h), r = 0.5 * (h - l);
-    const double w = net.dev_w[j];
-    Sc += w * c;
-    Sr += fabs(w) * r;
-    Sabs += fabs(w * c) + fabs(w) * r;
-    cI += (j < G) ? c : -c;
-    rI += r;
-    cIabs += fabs(c);
+    const double w = net.dev_w[i];
+    v[kP1Sc] = w * c;
+    v[kP1Sr] = fabs(w) * r;
+    v[kP1Sabs] = fabs(w * c) + fabs(w) * r;
+    v[kP1cI] = (i < G) ? c : -c;
+    v[kP1rI] = r;
+    v[kP1cIabs] = fabs(c);
   }
-  Sc = block_sum256(Sc, sh);
-  Sr = block_sum256(Sr, sh);
-  Sabs = block_sum256(Sabs, sh);
-  cI = block_sum256(cI, sh);
-  rI = block_sum256(rI, sh);
-  cIabs = block_sum256(cIabs, sh);
-  bad = block_sum256(bad, sh);
-
-  // per-bus injection intervals, rounded outward to float32
-  float* cinj = ws_ptr<float>(ws, lay.cinj) + b * net.Np;
-  float* rpp = ws_ptr<float>(ws, lay.rpp) + b * net.Np;
-  double Mc = 0, Mbox = 0, M2 = 0;
-  for (int n = threadIdx.x; n < net.Np; n += 256) {
-    if (n >= net.N) {
-      cinj[n] = 0.0f;
-      rpp[n] = 0.0f;
-      continue;
+#pragma unroll
+  for (int f = 0; f < kP1Fields; ++f) v[f] = wave_sum(v[f]);
+  if (threadIdx.x < kP1Fields) {
+    double* rec = ws_ptr<double>(ws, lay.p1) + (b * lay.n_p1 + blockIdx.x) * kP1Fields;
+    double val = 0.0;
+#pragma unroll
+    for (int f = 0; f < kP1Fields; ++f)
+      if (threadIdx.x == f) val = v[f];
+    rec[threadIdx.x] = val;
+  }
+  if (blockIdx.x == 0) {
+    // neutral padding lines for K3: zero centre, h = -FLT_MAX, g = +FLT_MAX
+    float* lc = ws_ptr<float>(ws, lay.lc) + b * net.Lp;
+    float* lh = ws_ptr<float>(ws, lay.lh) + b * net.Lp;
+    float* lg = ws_ptr<float>(ws, lay.lg) + b * net.Lp;
+    for (int l = net.L + threadIdx.x; l < net.Lp; l += 64) {
+      lc[l] = 0.0f;
+      lh[l] = -FLT_MAX;
+      lg[l] = FLT_MAX;
     }
-    double c = 0, r = 0, a = 0;
-    int cnt = 0;
-    for (int e = net.bus_ptr[n]; e < net.bus_ptr[n + 1]; ++e) {
-      const int j = net.bus_dev[e];
-      const double l = lo[j], h = hi[j];
-      const double cj = 0.5 * (l + h), rj = 0.5 * (h - l);
-      c += (j < G) ? cj : -cj;
-      r += rj;
-      a += fabs(cj);
-      ++cnt;
-    }
-    // float64 summation error of c and r (cnt terms each)
-    const double e64 = (cnt + 1) * kU64 * (a + r) * 1.01;
-    const float c32 = (float)c;
-    const float r32 = ru32((r + 2.0 * e64 + fabs(c - (double)c32)) * (1.0 + 4.0 * kU64));
-    // radius inflated for the float32 rounding of the PTDF entries
-    const float rp = ru32(((1.0 + kKappa0) * (double)r32 + kKappa0 * fabs((double)c32)) *
-                          (1.0 + 4.0 * kU64));
-    cinj[n] = c32;
-    rpp[n] = rp;
-    Mc += fabs((double)c32);
-    Mbox += fabs((double)c32) + (double)r32;
-    M2 += fabs((double)c32) + (double)rp;
-  }
-  Mc = block_sum256(Mc, sh);
-  Mbox = block_sum256(Mbox, sh);
-  M2 = block_sum256(M2, sh);
-
-  // neutral padding lines for K3: zero centre, h = -FLT_MAX, g = +FLT_MAX
-  float* lc = ws_ptr<float>(ws, lay.lc) + b * net.Lp;
-  float* lh = ws_ptr<float>(ws, lay.lh) + b * net.Lp;
-  float* lg = ws_ptr<float>(ws, lay.lg) + b * net.Lp;
-  for (int l = net.L + threadIdx.x; l < net.Lp; l += 256) {
-    lc[l] = 0.0f;
-    lh[l] = -FLT_MAX;
-    lg[l] = FLT_MAX;
-  }
-
-  if (threadIdx.x == 0) {
-    double* bs = ws_ptr<double>(ws, lay.box) + b * kBoxSlots;
-    // float64 reduction depth: X/256 serial terms plus the 8-level tree
-    const double gam = (X / 256 + 12) * kU64 * 1.01;
-    const double eS = gam * Sabs + 4.0 * kU64 * (fabs(Sc) + Sr);
-    bs[kS_lo] = (Sc - Sr) - eS;
-    bs[kS_hi] = (Sc + Sr) + eS;
-    // 1^T s_inj interval: |sum p_inj| over the box (E^T Phi - I = -e_slack 1^T)
-    const double eI = 2.0 * gam * (cIabs + rI);
-    const double mag = (fabs(cI) + rI + eI) * (1.0 + 4.0 * kU64);
-    const double mig = fabs(cI) - rI - eI;
-    bs[kI_lo] = mig > 0.0 ? mig * (1.0 - 4.0 * kU64) : 0.0;
-    bs[kI_hi] = mag;
-    const double gN = (net.Np / 256 + 12) * kU64 * 1.01;
-    bs[kMc] = Mc * (1.0 + gN);
-    bs[kMbox] = Mbox * (1.0 + gN);
-    // |c_f| + r_f <= sum |Phi| (|c| + r'') + pads <= M2 (1 + small) + phi_err_max Mbox
-    bs[kM3] = (M2 * (1.0 + gN) * (1.0 + 1e-6) + 2.0 * net.phi_err_max * Mbox) * (1.0 + 1e-6);
-    bs[kBad] = bad > 0.0 ? 1.0 : 0.0;
-    bs[kVmax] = 0.0;  // K2 raises it with atomic max on the float bit pattern
+    if (threadIdx.x == 0) ws_ptr<double>(ws, lay.box)[b * kBoxSlots + kVmax] = 0.0;
   }
 }
 
@@ -180,11 +169,12 @@ __global__ __launch_bounds__(256) void k1_box_prep(DevNet net, const float* __re
 
 // Per-line float64 epilogue: enclosing radius of the base flow, base penalties,
 // and the per-line / per-outage constants of K3 (see the error model at K3).
-__device__ __forceinline__ void k2_line_epilogue(const DevNet& net, int l, double cf, double rh,
-                                                 double* bs, float* lc, float* lh, float* lg,
-                                                 double* lcf, double* lrf, int4* ctg,
-                                                 double& pb_hi, double& pb_lo) {
-  const double Mc = bs[kMc], Mbox = bs[kMbox];
+// Returns the float bits of (|c_c| + r_c) / (1 - H_cc) rounded up if the line
+// is an outage line (0 otherwise), for the caller's max reduction.
+__device__ __forceinline__ unsigned line_epilogue(const DevNet& net, int l, double cf, double rh, double Mc,
+                                                  double Mbox, float* lc, float* lh, float* lg,
+                                                  double* lcf, double* lrf, int4* ctg, double& pb_hi,
+                                                  double& pb_lo) {
   const double gam = net.gamma64_n;
   // enclosing radius around the float64 centre cf: float64 accumulation of
   // |Phi32| r'' and Phi32 c32, and the float64 construction error of Phi
@@ -204,10 +194,11 @@ __device__ __forceinline__ void k2_line_epilogue(const DevNet& net, int l, doubl
 
   // K3 per-line constants
   const double phic = net.fmax_c[l];
-  const double u1 = kU32 * (1.0 + kU32);
-  const double dl = 2.0 * kU32 * (1.0 + kU32) * (1.0 + kU32);
+  constexpr double u1 = kU32 * (1.0 + kU32);
+  constexpr double dl = 2.0 * kU32 * (1.0 + kU32) * (1.0 + kU32);
+  constexpr double inv1md = 1.0 / (1.0 - dl);  // the 16 u64 factor covers its rounding
   const double rho = rl + kU32 * acl;
-  const double rhop = ((rho + dl * phic + u1 * acl) / (1.0 - dl)) * (1.0 + 16.0 * kU64) + 1e-36;
+  const double rhop = ((rho + dl * phic + u1 * acl) * inv1md) * (1.0 + 16.0 * kU64) + 1e-36;
   lc[l] = cl;
   lh[l] = ru32(rhop - phic + 4.0 * kU64 * (rhop + phic));
   lg[l] = ru32((rhop + phic) * (1.0 + 4.0 * kU64));
@@ -216,78 +207,258 @@ __device__ __forceinline__ void k2_line_epilogue(const DevNet& net, int l, doubl
   if (k >= 0) {
     const double Ek = net.ctg_eps[k] * (acl + rl);
     const double rk = (1.0 + kKappa0) * rl + (kKappa0 + kU32) * acl + Ek;
-    const double rkp = ((rk + u1 * acl) / (1.0 - dl)) * (1.0 + 16.0 * kU64) + 1e-36;
+    const double rkp = ((rk + u1 * acl) * inv1md) * (1.0 + 16.0 * kU64) + 1e-36;
     ctg[k] = make_int4(l, __float_as_int(cl), __float_as_int(ru32(rkp)), 0);
     const float v = ru32((acl + rl) * net.ctg_inv[k] * (1.0 + 4.0 * kU64));
-    atomicMax(reinterpret_cast<unsigned int*>(bs + kVmax), __float_as_uint(v));
+    return __float_as_uint(v);
+  }
+  return 0u;
+}
+
+// One wave per 64 lines: combine the K2 partials of every bus chunk and run
+// the line epilogue; one base-penalty partial per wave.
+__global__ __launch_bounds__(64) void k2e_lines(DevNet net, void* ws, WsLayout lay, int64_t box0) {
+  const int64_t b = box0 + blockIdx.y;
+  const int l = blockIdx.x * 64 + threadIdx.x;
+  const double* p1 = ws_ptr<double>(ws, lay.p1) + b * lay.n_p1 * kP1Fields;
+  double mc = 0.0, mb = 0.0;
+  for (int j = threadIdx.x; j < lay.n_p1; j += 64) {
+    mc += p1[j * kP1Fields + kP1Mc];
+    mb += p1[j * kP1Fields + kP1Mbox];
+  }
+  const double g = (lay.n_p1 + 16) * kU64 * 1.01;
+  mc = wave_sum(mc) * (1.0 + g);
+  mb = wave_sum(mb) * (1.0 + g);
+  double pb_hi = 0.0, pb_lo = 0.0;
+  unsigned vm = 0u;
+  if (l < net.L) {
+    const double2* part = ws_ptr<double2>(ws, lay.part2) + (size_t)b * lay.k2_by * net.Lp + l;
+    double cf[4] = {0, 0, 0, 0}, rh[4] = {0, 0, 0, 0};
+    int y = 0;
+    for (; y + 4 <= lay.k2_by; y += 4) {
+      double2 t[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) t[q] = part[(size_t)(y + q) * net.Lp];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        cf[q] += t[q].x;
+        rh[q] += t[q].y;
+      }
+    }
+    for (; y < lay.k2_by; ++y) {
+      const double2 t = part[(size_t)y * net.Lp];
+      cf[0] += t.x;
+      rh[0] += t.y;
+    }
+    vm = line_epilogue(net, l, (cf[0] + cf[1]) + (cf[2] + cf[3]), (rh[0] + rh[1]) + (rh[2] + rh[3]), mc, mb,
+                       ws_ptr<float>(ws, lay.lc) + b * net.Lp, ws_ptr<float>(ws, lay.lh) + b * net.Lp,
+                       ws_ptr<float>(ws, lay.lg) + b * net.Lp, ws_ptr<double>(ws, lay.lcf) + b * net.L,
+                       ws_ptr<double>(ws, lay.lrf) + b * net.L, ws_ptr<int4>(ws, lay.ctg) + b * net.K,
+                       pb_hi, pb_lo);
+  }
+  // max over the wave, then one atomic (non-negative floats order like their bit patterns)
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) vm = max(vm, (unsigned)__shfl_xor((int)vm, m, 64));
+  pb_hi = wave_sum(pb_hi);
+  pb_lo = wave_sum(pb_lo);
+  if (threadIdx.x == 0) {
+    if (vm != 0u)
+      atomicMax(reinterpret_cast<unsigned int*>(ws_ptr<double>(ws, lay.box) + b * kBoxSlots + kVmax), vm);
+    ws_ptr<double2>(ws, lay.p2)[b * lay.n_p2 + blockIdx.x] = make_double2(pb_hi, pb_lo);
   }
 }
 
-template <int ROWS>
-__global__ __launch_bounds__(256) void k2_base_flows(DevNet net, void* ws, WsLayout lay, int64_t box0) {
-  const int64_t b = box0 + blockIdx.y;
+// Base flows c_f = Phi c and rho = |Phi| r'' in float64, streaming the
+// transposed PTDF: each lane owns four lines, each wave a chunk of NC buses
+// whose (c, r'') it reads as wave-uniform scalars.  The four waves of a block
+// share the line tile; their sums are combined in LDS and written as one
+// partial per block row (bus chunk).
+template <int NC>
+__global__ __launch_bounds__(256) void k2_base_flows(DevNet net, void* ws, WsLayout lay, int64_t box0,
+                                                     const double2* __restrict__ inj_all) {
+  __shared__ double sh[3][64][8];
+  const int64_t b = box0 + blockIdx.z;
   const int lane = threadIdx.x & 63;
-  const int gwave = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int nwaves = gridDim.x * 4;
-  const int n4 = net.Np / 4;
-  const float4* cv = reinterpret_cast<const float4*>(ws_ptr<float>(ws, lay.cinj) + b * net.Np);
-  const float4* rv = reinterpret_cast<const float4*>(ws_ptr<float>(ws, lay.rpp) + b * net.Np);
-  double* bs = ws_ptr<double>(ws, lay.box) + b * kBoxSlots;
-  float* lc = ws_ptr<float>(ws, lay.lc) + b * net.Lp;
-  float* lh = ws_ptr<float>(ws, lay.lh) + b * net.Lp;
-  float* lg = ws_ptr<float>(ws, lay.lg) + b * net.Lp;
-  double* lcf = ws_ptr<double>(ws, lay.lcf) + b * net.L;
-  double* lrf = ws_ptr<double>(ws, lay.lrf) + b * net.L;
-  int4* ctg = ws_ptr<int4>(ws, lay.ctg) + b * net.K;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const int col = blockIdx.x * 64 + lane;  // float4 column
+  const int Lp4 = net.Lp / 4;
+  const int n0 = (blockIdx.y * 4 + w) * NC;
+  const int n1 = min(net.N, n0 + NC);
+  double ac0 = 0, ac1 = 0, ac2 = 0, ac3 = 0, ar0 = 0, ar1 = 0, ar2 = 0, ar3 = 0;
+  if (col < Lp4) {
+    const double2* __restrict__ inj = inj_all + b * net.Np;
+    const float4* ph = reinterpret_cast<const float4*>(net.phiT) + col;
+    int n = n0;
+    for (; n + 8 <= n1; n += 8) {
+      float4 x[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) x[i] = ld_stream(ph + (size_t)(n + i) * Lp4);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const double2 cr = inj[n + i];
+        ac0 = fma((double)x[i].x, cr.x, ac0);
+        ac1 = fma((double)x[i].y, cr.x, ac1);
+        ac2 = fma((double)x[i].z, cr.x, ac2);
+        ac3 = fma((double)x[i].w, cr.x, ac3);
+        ar0 = fma(fabs((double)x[i].x), cr.y, ar0);
+        ar1 = fma(fabs((double)x[i].y), cr.y, ar1);
+        ar2 = fma(fabs((double)x[i].z), cr.y, ar2);
+        ar3 = fma(fabs((double)x[i].w), cr.y, ar3);
+      }
+    }
+    for (; n < n1; ++n) {
+      const float4 x = ld_stream(ph + (size_t)n * Lp4);
+      const double2 cr = inj[n];
+      ac0 = fma((double)x.x, cr.x, ac0);
+      ac1 = fma((double)x.y, cr.x, ac1);
+      ac2 = fma((double)x.z, cr.x, ac2);
+      ac3 = fma((double)x.w, cr.x, ac3);
+      ar0 = fma(fabs((double)x.x), cr.y, ar0);
+      ar1 = fma(fabs((double)x.y), cr.y, ar1);
+      ar2 = fma(fabs((double)x.z), cr.y, ar2);
+      ar3 = fma(fabs((double)x.w), cr.y, ar3);
+    }
+  }
+  if (w > 0) {
+    double* d = sh[w - 1][lane];
+    d[0] = ac0; d[1] = ac1; d[2] = ac2; d[3] = ac3;
+    d[4] = ar0; d[5] = ar1; d[6] = ar2; d[7] = ar3;
+  }
+  __syncthreads();
+  if (w == 0 && col < Lp4) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const double* d = sh[q][lane];
+      ac0 += d[0]; ac1 += d[1]; ac2 += d[2]; ac3 += d[3];
+      ar0 += d[4]; ar1 += d[5]; ar2 += d[6]; ar3 += d[7];
+    }
+    double2* out = ws_ptr<double2>(ws, lay.part2) + ((size_t)b * lay.k2_by + blockIdx.y) * net.Lp + 4 * col;
+    out[0] = make_double2(ac0, ar0);
+    out[1] = make_double2(ac1, ar1);
+    out[2] = make_double2(ac2, ar2);
+    out[3] = make_double2(ac3, ar3);
+  }
+}
 
-  double pb_hi = 0.0, pb_lo = 0.0;
-  for (int r0 = gwave * ROWS; r0 < net.L; r0 += nwaves * ROWS) {
-    double ac[ROWS], ar[ROWS];
+// ---------------------------------------------------------------- K4
+
+constexpr int kK4Threads = 256;
+
+// Objective interval of one box from all partial sums (run by one block of
+// kK4Threads threads after every partial is visible).
+__device__ void finalize_box(const DevNet& net, void* ws, const WsLayout& lay, int64_t b,
+                             double* __restrict__ f_lo, double* __restrict__ f_hi,
+                             double* __restrict__ terms) {
+  const double* p1 = ws_ptr<double>(ws, lay.p1) + b * lay.n_p1 * kP1Fields;
+  const double2* p2 = ws_ptr<double2>(ws, lay.p2) + b * lay.n_p2;
+  const double2* p3 = ws_ptr<double2>(ws, lay.p3) + b * lay.n_p3;
+  double v[kP1Fields];
 #pragma unroll
-    for (int i = 0; i < ROWS; ++i) ac[i] = ar[i] = 0.0;
-    const float4* prow[ROWS];
+  for (int f = 0; f < kP1Fields; ++f) v[f] = 0.0;
+  for (int j = threadIdx.x; j < lay.n_p1; j += kK4Threads)
 #pragma unroll
-    for (int i = 0; i < ROWS; ++i) {
-      const int row = min(r0 + i, net.L - 1);
-      prow[i] = reinterpret_cast<const float4*>(net.phi + (size_t)row * net.Np);
-    }
-    for (int j = lane; j < n4; j += 64) {
-      const float4 c4 = cv[j];
-      const float4 r4 = rv[j];
-      const double c0 = c4.x, c1 = c4.y, c2 = c4.z, c3 = c4.w;
-      const double q0 = r4.x, q1 = r4.y, q2 = r4.z, q3 = r4.w;
-#pragma unroll
-      for (int i = 0; i < ROWS; ++i) {
-        const float4 p = prow[i][j];
-        ac[i] = fma((double)p.x, c0, ac[i]);
-        ac[i] = fma((double)p.y, c1, ac[i]);
-        ac[i] = fma((double)p.z, c2, ac[i]);
-        ac[i] = fma((double)p.w, c3, ac[i]);
-        ar[i] = fma(fabs((double)p.x), q0, ar[i]);
-        ar[i] = fma(fabs((double)p.y), q1, ar[i]);
-        ar[i] = fma(fabs((double)p.z), q2, ar[i]);
-        ar[i] = fma(fabs((double)p.w), q3, ar[i]);
-      }
-    }
-    double cf = 0.0, rh = 0.0;
-#pragma unroll
-    for (int i = 0; i < ROWS; ++i) {
-      const double s = wave_sum(ac[i]);
-      const double t = wave_sum(ar[i]);
-      if (lane == i) {
-        cf = s;
-        rh = t;
-      }
-    }
-    if (lane < ROWS && r0 + lane < net.L)
-      k2_line_epilogue(net, r0 + lane, cf, rh, bs, lc, lh, lg, lcf, lrf, ctg, pb_hi, pb_lo);
+    for (int f = kP1Sc; f < kP1Fields; ++f) v[f] += p1[j * kP1Fields + f];
+  double bh = 0, bl = 0;
+  for (int i = threadIdx.x; i < lay.n_p2; i += kK4Threads) {
+    const double2 t = p2[i];
+    bh += t.x;
+    bl += t.y;
   }
-  pb_hi = wave_sum(pb_hi);
-  pb_lo = wave_sum(pb_lo);
-  if (lane == 0) {
-    double2* p2 = ws_ptr<double2>(ws, lay.p2) + b * lay.n_p2;
-    p2[gwave] = make_double2(pb_hi, pb_lo);
+  // four independent partial sums keep several loads in flight
+  double ch[4] = {0, 0, 0, 0}, cl[4] = {0, 0, 0, 0};
+  int i = threadIdx.x;
+  for (; i + 7 * kK4Threads < lay.n_p3; i += 8 * kK4Threads) {
+    double2 t[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) t[q] = p3[i + q * kK4Threads];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      ch[q & 3] += t[q].x;
+      cl[q & 3] += t[q].y;
+    }
   }
+  for (; i < lay.n_p3; i += kK4Threads) {
+    const double2 t = p3[i];
+    ch[0] += t.x;
+    cl[0] += t.y;
+  }
+  // one combined block reduction of the 12 running sums
+  constexpr int W = kK4Threads / 64;
+  __shared__ double red[W][12];
+  double x[12];
+#pragma unroll
+  for (int f = 0; f < 8; ++f) x[f] = v[kP1Sc + f];
+  x[8] = bh;
+  x[9] = bl;
+  x[10] = (ch[0] + ch[1]) + (ch[2] + ch[3]);
+  x[11] = (cl[0] + cl[1]) + (cl[2] + cl[3]);
+#pragma unroll
+  for (int f = 0; f < 12; ++f) x[f] = wave_sum(x[f]);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int f = 0; f < 12; ++f) red[threadIdx.x >> 6][f] = x[f];
+  __syncthreads();
+  __shared__ double tot[12];
+  if (threadIdx.x < 12) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < W; ++q) t += red[q][threadIdx.x];
+    tot[threadIdx.x] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+#pragma unroll
+  for (int f = 0; f < 12; ++f) x[f] = tot[f];
+#pragma unroll
+  for (int f = 0; f < 8; ++f) v[kP1Sc + f] = x[f];
+  bh = x[8];
+  bl = x[9];
+  const double chs = x[10], cls = x[11];
+
+  // surplus and imbalance intervals; float64 reduction depth <= n_p1 + 16
+  const double gam = (lay.n_p1 + 16) * kU64 * 1.01;
+  const double Sc = v[kP1Sc], Sr = v[kP1Sr];
+  const double eS = gam * v[kP1Sabs] + 4.0 * kU64 * (fabs(Sc) + Sr);
+  const double S_lo = (Sc - Sr) - eS, S_hi = (Sc + Sr) + eS;
+  // 1^T s_inj = |sum p_inj| since E^T Phi - I = -e_slack 1^T
+  const double cI = v[kP1cI], rI = v[kP1rI];
+  const double eI = 2.0 * gam * (v[kP1cIabs] + rI);
+  const double I_hi = (fabs(cI) + rI + eI) * (1.0 + 4.0 * kU64);
+  const double mig = fabs(cI) - rI - eI;
+  const double I_lo = mig > 0.0 ? mig * (1.0 - 4.0 * kU64) : 0.0;
+
+  // float64 accumulation depth is far below L + K + 4096 additions per term
+  const double gF = (double)(net.L + net.K + 4096) * kU64;
+  const double Fb_hi = bh * (1.0 + gF), Fb_lo = bl * (1.0 - gF);
+  const double Fc_hi = chs * (1.0 + 4.0 * kU32) * (1.0 + gF);
+  const double Fc_lo = cls * (1.0 - 4.0 * kU32) * (1.0 - gF);
+  const double zi = net.zeta_inj, zf = net.zeta_f;
+  double hi = S_hi - zi * I_lo - zf * (Fb_lo + Fc_lo);
+  hi += 8.0 * kU64 * (fabs(S_hi) + zi * I_lo + zf * (Fb_lo + Fc_lo));
+  double lo = S_lo - zi * I_hi - zf * (Fb_hi + Fc_hi);
+  lo -= 8.0 * kU64 * (fabs(S_lo) + zi * I_hi + zf * (Fb_hi + Fc_hi));
+  const bool bad = v[kP1Bad] != 0.0;
+  if (bad) lo = hi = NAN;
+  f_lo[b] = lo;
+  f_hi[b] = hi;
+  if (terms) {
+    double* t = terms + b * 8;
+    t[0] = bad ? NAN : S_lo;
+    t[1] = bad ? NAN : S_hi;
+    t[2] = bad ? NAN : I_lo;
+    t[3] = bad ? NAN : I_hi;
+    t[4] = bad ? NAN : Fb_lo;
+    t[5] = bad ? NAN : Fb_hi;
+    t[6] = bad ? NAN : Fc_lo;
+    t[7] = bad ? NAN : Fc_hi;
+  }
+}
+
+__global__ __launch_bounds__(kK4Threads) void k4_finalize(DevNet net, void* ws, WsLayout lay, int64_t box0,
+                                                          double* __restrict__ f_lo,
+                                                          double* __restrict__ f_hi,
+                                                          double* __restrict__ terms) {
+  finalize_box(net, ws, lay, box0 + blockIdx.x, f_lo, f_hi, terms);
 }
 
 // ---------------------------------------------------------------- K3
@@ -369,15 +540,16 @@ __global__ __launch_bounds__(256) void k3_contingency(DevNet net, void* ws, WsLa
     for (; k + 8 <= k1; k += 8) {
       float4 x[8];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) x[i] = lam[(size_t)(k + i) * Lp4];
+      for (int i = 0; i < 8; ++i) x[i] = ld_stream(lam + (size_t)(k + i) * Lp4);
 #pragma unroll
       for (int i = 0; i < 8; i += 2) k3_pair(x[i], cd[k + i], x[i + 1], cd[k + i + 1], c4, h4, g4, acc_hi, acc_lo);
     }
     for (; k + 2 <= k1; k += 2)
-      k3_pair(lam[(size_t)k * Lp4], cd[k], lam[(size_t)(k + 1) * Lp4], cd[k + 1], c4, h4, g4, acc_hi, acc_lo);
+      k3_pair(ld_stream(lam + (size_t)k * Lp4), cd[k], ld_stream(lam + (size_t)(k + 1) * Lp4), cd[k + 1], c4, h4,
+              g4, acc_hi, acc_lo);
     if (k < k1) {  // odd tail
       float a0, a1, a2, a3, b0, b1, b2, b3;
-      const float4 x0 = lam[(size_t)k * Lp4];
+      const float4 x0 = ld_stream(lam + (size_t)k * Lp4);
       const int4 d0 = cd[k];
       const float cc0 = __int_as_float(d0.y), rk0 = __int_as_float(d0.z);
       k3_elem(x0.x, cc0, rk0, c4.x, h4.x, g4.x, a0, b0);
@@ -404,76 +576,38 @@ __global__ __launch_bounds__(256) void k3_contingency(DevNet net, void* ws, WsLa
 
 // ---------------------------------------------------------------- K4
 
-__global__ __launch_bounds__(256) void k4_finalize(DevNet net, void* ws, WsLayout lay, int64_t box0,
-                                                   double* __restrict__ f_lo,
-                                                   double* __restrict__ f_hi,
-                                                   double* __restrict__ terms) {
-  __shared__ double sh[4];
-  const int64_t b = box0 + blockIdx.x;
-  const double2* p2 = ws_ptr<double2>(ws, lay.p2) + b * lay.n_p2;
-  const double2* p3 = ws_ptr<double2>(ws, lay.p3) + b * lay.n_p3;
-  double bh = 0, bl = 0, ch = 0, cl = 0;
-  for (int i = threadIdx.x; i < lay.n_p2; i += 256) {
-    bh += p2[i].x;
-    bl += p2[i].y;
-  }
-  for (int i = threadIdx.x; i < lay.n_p3; i += 256) {
-    ch += p3[i].x;
-    cl += p3[i].y;
-  }
-  bh = block_sum256(bh, sh);
-  bl = block_sum256(bl, sh);
-  ch = block_sum256(ch, sh);
-  cl = block_sum256(cl, sh);
-  if (threadIdx.x != 0) return;
-  const double* bs = ws_ptr<double>(ws, lay.box) + b * kBoxSlots;
-  // float64 accumulation depth is far below L + K + 4096 additions per term
-  const double gF = (double)(net.L + net.K + 4096) * kU64;
-  const double Fb_hi = bh * (1.0 + gF), Fb_lo = bl * (1.0 - gF);
-  const double Fc_hi = ch * (1.0 + 4.0 * kU32) * (1.0 + gF);
-  const double Fc_lo = cl * (1.0 - 4.0 * kU32) * (1.0 - gF);
-  const double zi = net.zeta_inj, zf = net.zeta_f;
-  const double S_lo = bs[kS_lo], S_hi = bs[kS_hi], I_lo = bs[kI_lo], I_hi = bs[kI_hi];
-  double hi = S_hi - zi * I_lo - zf * (Fb_lo + Fc_lo);
-  hi += 8.0 * kU64 * (fabs(S_hi) + zi * I_lo + zf * (Fb_lo + Fc_lo));
-  double lo = S_lo - zi * I_hi - zf * (Fb_hi + Fc_hi);
-  lo -= 8.0 * kU64 * (fabs(S_lo) + zi * I_hi + zf * (Fb_hi + Fc_hi));
-  if (bs[kBad] != 0.0) {
-    lo = hi = NAN;
-  }
-  f_lo[b] = lo;
-  f_hi[b] = hi;
-  if (terms) {
-    double* t = terms + b * 8;
-    const bool bad = bs[kBad] != 0.0;
-    t[0] = bad ? NAN : S_lo;
-    t[1] = bad ? NAN : S_hi;
-    t[2] = bad ? NAN : I_lo;
-    t[3] = bad ? NAN : I_hi;
-    t[4] = bad ? NAN : Fb_lo;
-    t[5] = bad ? NAN : Fb_hi;
-    t[6] = bad ? NAN : Fc_lo;
-    t[7] = bad ? NAN : Fc_hi;
-  }
-}
-
 // ---------------------------------------------------------------- launchers
 
-constexpr int kK2Rows = 4;
-constexpr int kK3Kc = 32;
+bool tune_valid(const Tune& t) {
+  const bool nc = t.k2_nc == 32 || t.k2_nc == 64 || t.k2_nc == 128 || t.k2_nc == 256;
+  const bool kc = t.k3_kc == 16 || t.k3_kc == 32 || t.k3_kc == 64 || t.k3_kc == 128;
+  return nc && kc;
+}
 
-void plan_single(const DevNet& net, int64_t n_box, WsLayout& lay, int num_cus) {
-  // K2: grid-stride over groups of kK2Rows rows, a few waves per SIMD
-  const int groups = (net.L + kK2Rows - 1) / kK2Rows;
-  const int want_waves = num_cus * 4 * 4;
-  lay.k2_blocks = std::max(1, std::min((groups + 3) / 4, want_waves / 4));
-  lay.n_p2 = lay.k2_blocks * 4;
-  // K3: 4 waves x 256 lines per block, kK3Kc outages per block
-  const int lp4 = net.Lp / 4;
-  lay.k3_bx = (lp4 + 255) / 256;
-  lay.k3_by = std::max(1, (net.K + kK3Kc - 1) / kK3Kc);
-  lay.n_p3 = lay.k3_bx * lay.k3_by;
+void plan_single(const DevNet& net, int64_t n_box, WsLayout& lay, const Tune& t) {
   (void)n_box;
+  const int lp4 = net.Lp / 4;
+  lay.k2_nc = t.k2_nc;
+  lay.k3_kc = t.k3_kc;
+  lay.n_p1 = (std::max(net.Np, net.X) + 63) / 64;
+  lay.k2_bx = (lp4 + 63) / 64;
+  lay.k2_by = std::max(1, (net.N + 4 * t.k2_nc - 1) / (4 * t.k2_nc));
+  lay.n_p2 = (net.L + 63) / 64;
+  // K3: 4 waves x 256 lines per block, k3_kc outages per block
+  lay.k3_bx = (lp4 + 255) / 256;
+  lay.k3_by = std::max(1, (net.K + t.k3_kc - 1) / t.k3_kc);
+  lay.n_p3 = net.K > 0 ? lay.k3_bx * lay.k3_by : 0;
+}
+
+template <int NC>
+static void launch_k2(const DevNet& net, void* ws, const WsLayout& lay, int64_t b0, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k2_base_flows<NC>, dim3(lay.k2_bx, lay.k2_by, nb), dim3(256), 0, s, net, ws, lay, b0,
+                     reinterpret_cast<const double2*>(static_cast<char*>(ws) + lay.inj));
+}
+
+template <int KC>
+static void launch_k3(const DevNet& net, void* ws, const WsLayout& lay, int64_t b0, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k3_contingency<KC>, dim3(lay.k3_bx, lay.k3_by, nb), dim3(256), 0, s, net, ws, lay, b0);
 }
 
 hipError_t launch_forward_single(const DevNet& net, int64_t n_box, const float* lo, const float* hi,
@@ -482,19 +616,31 @@ hipError_t launch_forward_single(const DevNet& net, int64_t n_box, const float* 
   for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
     const int nb = (int)std::min<int64_t>(65535, n_box - b0);
     int t = tm->start(0, s);
-    hipLaunchKernelGGL(k1_box_prep, dim3(nb), dim3(256), 0, s, net, lo, hi, ws, lay, b0);
+    hipLaunchKernelGGL(k1_box_prep, dim3(lay.n_p1, nb), dim3(64), 0, s, net, lo, hi, ws, lay, b0);
     tm->stop(t, s);
     t = tm->start(1, s);
-    hipLaunchKernelGGL(k2_base_flows<kK2Rows>, dim3(lay.k2_blocks, nb), dim3(256), 0, s, net, ws, lay, b0);
+    switch (lay.k2_nc) {
+      case 32: launch_k2<32>(net, ws, lay, b0, nb, s); break;
+      case 64: launch_k2<64>(net, ws, lay, b0, nb, s); break;
+      case 256: launch_k2<256>(net, ws, lay, b0, nb, s); break;
+      default: launch_k2<128>(net, ws, lay, b0, nb, s); break;
+    }
+    tm->stop(t, s);
+    t = tm->start(4, s);
+    hipLaunchKernelGGL(k2e_lines, dim3(lay.n_p2, nb), dim3(64), 0, s, net, ws, lay, b0);
     tm->stop(t, s);
     if (net.K > 0) {
       t = tm->start(2, s);
-      hipLaunchKernelGGL(k3_contingency<kK3Kc>, dim3(lay.k3_bx, lay.k3_by, nb), dim3(256), 0, s, net, ws,
-                         lay, b0);
+      switch (lay.k3_kc) {
+        case 32: launch_k3<32>(net, ws, lay, b0, nb, s); break;
+        case 64: launch_k3<64>(net, ws, lay, b0, nb, s); break;
+        case 128: launch_k3<128>(net, ws, lay, b0, nb, s); break;
+        default: launch_k3<16>(net, ws, lay, b0, nb, s); break;
+      }
       tm->stop(t, s);
     }
     t = tm->start(3, s);
-    hipLaunchKernelGGL(k4_finalize, dim3(nb), dim3(256), 0, s, net, ws, lay, b0, f_lo, f_hi, terms);
+    hipLaunchKernelGGL(k4_finalize, dim3(nb), dim3(kK4Threads), 0, s, net, ws, lay, b0, f_lo, f_hi, terms);
     tm->stop(t, s);
   }
   return hipGetLastError();

@@ -34,8 +34,16 @@ struct KernelTimer {
   }
 };
 
+// Tile parameters of the streaming kernels (chosen by the autotuner or the
+// IBP_TILE environment variable, e.g. "k2nc=64,k3kc=32").
+struct Tune {
+  int k2_nc = 128;  // buses per wave in the base-flow sweep: 32, 64, 128 or 256
+  int k3_kc = 16;   // outages per block in the outage sweep: 16, 32, 64 or 128
+};
+bool tune_valid(const Tune& t);
+
 // Grid shapes and partial-sum counts of the single-box-per-slice forward path.
-void plan_single(const DevNet& net, int64_t n_box, WsLayout& lay, int num_cus);
+void plan_single(const DevNet& net, int64_t n_box, WsLayout& lay, const Tune& t);
 
 // K1..K4 for n_box boxes, each box handled by its own grid slice.
 hipError_t launch_forward_single(const DevNet& net, int64_t n_box, const float* lo, const float* hi,

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libibp.so")
 IBP_DEVICE_HOST_ONLY = -1
 IBP_F_NONE = 0
 IBP_F_PLAIN = 1
+IBP_F_AUTOTUNE = 2
 
 STATUS = {
     0: "IBP_OK",
@@ -45,10 +46,12 @@ EXPORTED = [
     "ibp_bound_backward",
     "ibp_set_kernel_timing",
     "ibp_kernel_times",
+    "ibp_set_tile",
+    "ibp_autotune",
     "ibp_last_error",
 ]
 
-KERNEL_IDS = ["box_prep", "base_flows", "outage_sweep", "finalize", "batched_base_flows",
+KERNEL_IDS = ["box_prep", "base_flows", "outage_sweep", "finalize", "line_epilogue", "batched_base_flows",
               "batched_outage_sweep", "backward_outage_sweep", "backward_ptdf_t", "backward_endpoints"]
 
 
@@ -130,6 +133,10 @@ def load_library(path: str = LIB_PATH):
     lib.ibp_set_kernel_timing.restype = ctypes.c_int
     lib.ibp_kernel_times.argtypes = [vp, ctypes.c_int32, vp, vp]
     lib.ibp_kernel_times.restype = ctypes.c_int
+    lib.ibp_set_tile.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    lib.ibp_set_tile.restype = ctypes.c_int
+    lib.ibp_autotune.argtypes = [vp, i64, vp, vp, vp, sz, vp, vp]
+    lib.ibp_autotune.restype = ctypes.c_int
     lib.ibp_last_error.argtypes = []
     lib.ibp_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -221,6 +228,9 @@ class Network:
         _check(load_library().ibp_kernel_times(self._h, n, ms.ctypes.data_as(ctypes.c_void_p),
                                                cnt.ctypes.data_as(ctypes.c_void_p)))
         return {KERNEL_IDS[i]: (float(ms[i]), int(cnt[i])) for i in range(n) if cnt[i] > 0}
+
+    def set_tile(self, k2_nc: int, k3_kc: int):
+        _check(load_library().ibp_set_tile(self._h, int(k2_nc), int(k3_kc)))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -314,3 +324,16 @@ def ibp_bound_backward(net: Network, lo, hi, g_lo, g_hi, flags: int = 0, ws: Wor
                                              _dev_ptr(g_hi), _dev_ptr(d_lo), _dev_ptr(d_hi),
                                              _dev_ptr(buf), buf.numel(), _stream_ptr(stream), flags))
     return d_lo, d_hi
+
+
+def ibp_autotune(net: Network, lo, hi, stream=None):
+    """Times every tile pair on these device boxes and keeps the fastest; returns it."""
+    torch = _torch()
+    lo, hi = _check_boxes(net, lo, hi)
+    n = lo.shape[0]
+    need = net.workspace_bytes(n, IBP_F_AUTOTUNE)
+    buf = torch.empty(max(need, 256), dtype=torch.uint8, device=lo.device)
+    chosen = np.zeros(2, np.int32)
+    _check(load_library().ibp_autotune(net.handle, n, _dev_ptr(lo), _dev_ptr(hi), _dev_ptr(buf), buf.numel(),
+                                       _stream_ptr(stream), chosen.ctypes.data_as(ctypes.c_void_p)))
+    return int(chosen[0]), int(chosen[1])
