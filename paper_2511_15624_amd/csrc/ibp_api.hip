@@ -204,7 +204,7 @@ ibp_status to_device(ibp_network* net, int device) {
   return IBP_OK;
 }
 
-ibp::WsLayout layout_for(const ibp_network* net, int64_t n_box, const ibp::Tune& tune);
+ibp::WsLayout layout_for(const ibp_network* net, int64_t n_box, const ibp::Tune& tune, bool batched);
 
 ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
   if (flags & IBP_F_AUTOTUNE) {
@@ -212,15 +212,19 @@ ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
     ibp::Tune t;
     t.k2_nc = 32;
     t.k3_kc = 16;
-    return layout_for(net, n_box, t);
+    return layout_for(net, n_box, t, false);
   }
-  return layout_for(net, n_box, net->tune);
+  const bool batched = n_box >= ibp::kBatchMin && !(flags & IBP_F_PLAIN);
+  return layout_for(net, n_box, net->tune, batched);
 }
 
-ibp::WsLayout layout_for(const ibp_network* net, int64_t n_box, const ibp::Tune& tune) {
+ibp::WsLayout layout_for(const ibp_network* net, int64_t n_box, const ibp::Tune& tune, bool batched = false) {
   const ibp::DevNet& d = net->dn;
   ibp::WsLayout lay;
-  ibp::plan_single(d, n_box, lay, tune);
+  if (batched)
+    ibp::plan_batched(d, n_box, lay);
+  else
+    ibp::plan_single(d, n_box, lay, tune);
   const size_t B = (size_t)std::max<int64_t>(1, n_box);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -349,7 +353,7 @@ ibp_status ibp_bound_boxes(const ibp_network* net, int64_t n_box, const float* b
   if (st != IBP_OK || n_box == 0) return st;
   DeviceGuard g(net->device);
   if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
-  hipError_t e = ibp::launch_forward_single(net->dn, n_box, box_lo, box_hi, f_lo, f_hi, terms, ws, lay,
+  hipError_t e = ibp::launch_forward(net->dn, n_box, box_lo, box_hi, f_lo, f_hi, terms, ws, lay,
                                             static_cast<hipStream_t>(stream),
                                             const_cast<ibp::KernelTimer*>(&net->timer));
   if (e != hipSuccess) return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
@@ -437,7 +441,7 @@ ibp_status ibp_autotune(ibp_network* net, int64_t n_box, const float* box_lo, co
       ibp::Tune t;
       t.k2_nc = nc;
       t.k3_kc = kc;
-      const ibp::WsLayout lay = layout_for(net, n_box, t);
+      const ibp::WsLayout lay = layout_for(net, n_box, t, false);
       float ms = 0.0f;
       for (int rep = 0; rep < 2; ++rep) {  // first round warms up
         (void)hipEventRecord(e0, s);

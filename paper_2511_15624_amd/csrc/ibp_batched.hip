@@ -1,0 +1,218 @@
+// Box-tiled forward kernels for many boxes at once (sub-boxes and periods).
+//
+// Every box still gets the IBP of Sec. III-C through the graph of the
+// Appendix; what changes is the data reuse.  A wave owns 256 lines and a tile
+// of kBT boxes, and the four waves of a block take four box tiles of the same
+// line tile, so each PTDF / outage-factor tile read from memory serves
+// 4 x kBT boxes.  Grids are laid out so that blocks sharing a tile get the same
+// linear id modulo 8: dispatch places consecutive ids on the 8 XCDs in turn,
+// so those blocks run on one XCD and hit its L2.
+//
+// The arithmetic per element and the error model are those of the single-box
+// kernels (float64 base-flow accumulation; float32 outage sweep with radii
+// padded per line and per outage).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstdint>
+
+#include "ibp_device.h"
+#include "ibp_devfun.h"
+#include "ibp_kernels.h"
+
+namespace ibp {
+
+constexpr int kBT = 4;  // boxes per wave tile
+
+// Base flows for kBT boxes x 256 lines per wave, over every bus.
+__global__ __launch_bounds__(256) void k2b_base_flows(DevNet net, void* ws, WsLayout lay, int64_t n_box,
+                                                      const double2* __restrict__ inj_all) {
+  const int Lp4 = net.Lp / 4;
+  if ((int)blockIdx.x * 64 >= Lp4) return;  // padding block of the grid
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t b0 = ((int64_t)blockIdx.y * 4 + w) * kBT;
+  if (b0 >= n_box) return;
+  const int col = blockIdx.x * 64 + lane;
+  int64_t bb[kBT];
+#pragma unroll
+  for (int i = 0; i < kBT; ++i) bb[i] = min(b0 + i, n_box - 1);
+  double ac[kBT][4], ar[kBT][4];
+#pragma unroll
+  for (int i = 0; i < kBT; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) ac[i][j] = ar[i][j] = 0.0;
+  if (col < Lp4) {
+    const float4* ph = reinterpret_cast<const float4*>(net.phiT) + col;
+    int n = 0;
+    for (; n + 4 <= net.N; n += 4) {
+      float4 x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[u] = ph[(size_t)(n + u) * Lp4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double p0 = x[u].x, p1 = x[u].y, p2 = x[u].z, p3 = x[u].w;
+#pragma unroll
+        for (int i = 0; i < kBT; ++i) {
+          const double2 cr = inj_all[bb[i] * net.Np + n + u];
+          ac[i][0] = fma(p0, cr.x, ac[i][0]);
+          ac[i][1] = fma(p1, cr.x, ac[i][1]);
+          ac[i][2] = fma(p2, cr.x, ac[i][2]);
+          ac[i][3] = fma(p3, cr.x, ac[i][3]);
+          ar[i][0] = fma(fabs(p0), cr.y, ar[i][0]);
+          ar[i][1] = fma(fabs(p1), cr.y, ar[i][1]);
+          ar[i][2] = fma(fabs(p2), cr.y, ar[i][2]);
+          ar[i][3] = fma(fabs(p3), cr.y, ar[i][3]);
+        }
+      }
+    }
+    for (; n < net.N; ++n) {
+      const float4 x = ph[(size_t)n * Lp4];
+      const double p0 = x.x, p1 = x.y, p2 = x.z, p3 = x.w;
+#pragma unroll
+      for (int i = 0; i < kBT; ++i) {
+        const double2 cr = inj_all[bb[i] * net.Np + n];
+        ac[i][0] = fma(p0, cr.x, ac[i][0]);
+        ac[i][1] = fma(p1, cr.x, ac[i][1]);
+        ac[i][2] = fma(p2, cr.x, ac[i][2]);
+        ac[i][3] = fma(p3, cr.x, ac[i][3]);
+        ar[i][0] = fma(fabs(p0), cr.y, ar[i][0]);
+        ar[i][1] = fma(fabs(p1), cr.y, ar[i][1]);
+        ar[i][2] = fma(fabs(p2), cr.y, ar[i][2]);
+        ar[i][3] = fma(fabs(p3), cr.y, ar[i][3]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kBT; ++i) {
+      if (b0 + i >= n_box) break;
+      double2* out = ws_ptr<double2>(ws, lay.part2) + (size_t)(b0 + i) * net.Lp + 4 * col;
+      out[0] = make_double2(ac[i][0], ar[i][0]);
+      out[1] = make_double2(ac[i][1], ar[i][1]);
+      out[2] = make_double2(ac[i][2], ar[i][2]);
+      out[3] = make_double2(ac[i][3], ar[i][3]);
+    }
+  }
+}
+
+// Outage sweep for kBT boxes x 256 lines per wave over one block row of outages.
+__global__ __launch_bounds__(256) void k3b_contingency(DevNet net, void* ws, WsLayout lay, int64_t n_box) {
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t b0 = ((int64_t)blockIdx.z * 4 + w) * kBT;
+  if (b0 >= n_box) return;
+  const int col = blockIdx.x * 64 + lane;
+  const int Lp4 = net.Lp / 4;
+  const int k0 = blockIdx.y * lay.k3_kper;
+  const int k1 = min(net.K, k0 + lay.k3_kper);
+  int64_t bb[kBT];
+#pragma unroll
+  for (int i = 0; i < kBT; ++i) bb[i] = min(b0 + i, n_box - 1);
+  double acc_hi[kBT], acc_lo[kBT];
+#pragma unroll
+  for (int i = 0; i < kBT; ++i) acc_hi[i] = acc_lo[i] = 0.0;
+  if (col < Lp4) {
+    float4 c4[kBT], h4[kBT], g4[kBT];
+    const int4* cd[kBT];
+    const float4 e4 = reinterpret_cast<const float4*>(net.line_eps)[col];
+#pragma unroll
+    for (int i = 0; i < kBT; ++i) {
+      const double* bs = ws_ptr<double>(ws, lay.box) + bb[i] * kBoxSlots;
+      const float vmax = __uint_as_float(*reinterpret_cast<const unsigned int*>(bs + kVmax));
+      c4[i] = reinterpret_cast<const float4*>(ws_ptr<float>(ws, lay.lc) + bb[i] * net.Lp)[col];
+      const float4 h = reinterpret_cast<const float4*>(ws_ptr<float>(ws, lay.lh) + bb[i] * net.Lp)[col];
+      const float4 g = reinterpret_cast<const float4*>(ws_ptr<float>(ws, lay.lg) + bb[i] * net.Lp)[col];
+      const float ex = next_up_f32(e4.x * vmax), ey = next_up_f32(e4.y * vmax);
+      const float ez = next_up_f32(e4.z * vmax), ew = next_up_f32(e4.w * vmax);
+      h4[i] = make_float4(add_ru(h.x, ex), add_ru(h.y, ey), add_ru(h.z, ez), add_ru(h.w, ew));
+      g4[i] = make_float4(add_ru(g.x, ex), add_ru(g.y, ey), add_ru(g.z, ez), add_ru(g.w, ew));
+      cd[i] = ws_ptr<int4>(ws, lay.ctg) + bb[i] * net.K;
+    }
+    const float4* lam = reinterpret_cast<const float4*>(net.lodf) + col;
+    int k = k0;
+    for (; k + 4 <= k1; k += 4) {
+      float4 x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[u] = lam[(size_t)(k + u) * Lp4];
+#pragma unroll
+      for (int i = 0; i < kBT; ++i) {
+        k3_pair(x[0], cd[i][k], x[1], cd[i][k + 1], c4[i], h4[i], g4[i], acc_hi[i], acc_lo[i]);
+        k3_pair(x[2], cd[i][k + 2], x[3], cd[i][k + 3], c4[i], h4[i], g4[i], acc_hi[i], acc_lo[i]);
+      }
+    }
+    for (; k < k1; ++k) {
+      const float4 x0 = lam[(size_t)k * Lp4];
+#pragma unroll
+      for (int i = 0; i < kBT; ++i) {
+        const int4 d0 = cd[i][k];
+        const float cc0 = __int_as_float(d0.y), rk0 = __int_as_float(d0.z);
+        float a0, a1, a2, a3, q0, q1, q2, q3;
+        k3_elem(x0.x, cc0, rk0, c4[i].x, h4[i].x, g4[i].x, a0, q0);
+        k3_elem(x0.y, cc0, rk0, c4[i].y, h4[i].y, g4[i].y, a1, q1);
+        k3_elem(x0.z, cc0, rk0, c4[i].z, h4[i].z, g4[i].z, a2, q2);
+        k3_elem(x0.w, cc0, rk0, c4[i].w, h4[i].w, g4[i].w, a3, q3);
+        acc_hi[i] += (double)((a0 + a1) + (a2 + a3));
+        acc_lo[i] += (double)((q0 + q1) + (q2 + q3));
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kBT; ++i) {
+    const double hs = wave_sum(acc_hi[i]);
+    const double ls = wave_sum(acc_lo[i]);
+    if (lane == 0 && b0 + i < n_box) {
+      double2* p3 = ws_ptr<double2>(ws, lay.p3) + (b0 + i) * lay.n_p3;
+      p3[blockIdx.y * gridDim.x + blockIdx.x] = make_double2(hs, ls);
+    }
+  }
+}
+
+void plan_batched(const DevNet& net, int64_t n_box, WsLayout& lay) {
+  const int lp4 = net.Lp / 4;
+  lay.batched = 1;
+  lay.n_p1 = (std::max(net.Np, net.X) + 63) / 64;
+  lay.k2_bx = (lp4 + 63) / 64;
+  lay.k2_gx = (lay.k2_bx + 7) / 8 * 8;  // blocks of one line tile share an XCD
+  lay.k2_by = 1;
+  lay.n_p2 = (net.L + 63) / 64;
+  const int64_t nbt = (n_box + kBT - 1) / kBT;
+  const int64_t groups = (nbt + 3) / 4;
+  lay.k3_bx = (lp4 + 63) / 64;
+  // split the outages so that there are enough waves in flight, keep at least
+  // 32 outages per row, and prefer k3_bx * rows to be a multiple of 8 (blocks
+  // that share an outage tile then share an XCD)
+  int rows = 1;
+  const int max_rows = std::max(1, net.K / 32);
+  while (rows < max_rows && (int64_t)lay.k3_bx * rows * groups * 4 < 16384) rows *= 2;
+  rows = std::min(rows, max_rows);
+  for (int r = rows; r <= std::min(max_rows, rows * 2); ++r)
+    if ((lay.k3_bx * r) % 8 == 0) {
+      rows = r;
+      break;
+    }
+  lay.k3_by = rows;
+  lay.k3_kper = net.K > 0 ? (net.K + rows - 1) / rows : 0;
+  lay.n_p3 = net.K > 0 ? lay.k3_bx * rows : 0;
+  lay.k2_nc = 0;
+  lay.k3_kc = lay.k3_kper;
+}
+
+hipError_t launch_batched_sweeps(const DevNet& net, int64_t n_box, void* ws, const WsLayout& lay, hipStream_t s,
+                                 KernelTimer* tm, int phase) {
+  const int64_t nbt = (n_box + kBT - 1) / kBT;
+  const unsigned groups = (unsigned)((nbt + 3) / 4);
+  if (phase == 0) {
+    const int t = tm->start(5, s);
+    hipLaunchKernelGGL(k2b_base_flows, dim3(lay.k2_gx, groups), dim3(256), 0, s, net, ws, lay, n_box,
+                       reinterpret_cast<const double2*>(static_cast<char*>(ws) + lay.inj));
+    tm->stop(t, s);
+  } else if (net.K > 0) {
+    const int t = tm->start(6, s);
+    hipLaunchKernelGGL(k3b_contingency, dim3(lay.k3_bx, lay.k3_by, groups), dim3(256), 0, s, net, ws, lay, n_box);
+    tm->stop(t, s);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ibp

@@ -74,6 +74,9 @@ struct WsLayout {
   int k2_bx = 0, k2_by = 0;        // K2 grid per box (line tiles x bus chunks)
   int k3_bx = 0, k3_by = 0;        // K3 grid per box (line tiles x outage chunks)
   int k2_nc = 0, k3_kc = 0;        // tile parameters used
+  int batched = 0;                 // 1: box-tiled kernels (boxes share every streamed tile)
+  int k2_gx = 0;                   // batched base flows: grid x (line tiles padded to a multiple of 8)
+  int k3_kper = 0;                 // batched outage sweep: outages per block row
 };
 
 }  // namespace ibp

@@ -23,61 +23,10 @@
 #include <cstdint>
 
 #include "ibp_device.h"
+#include "ibp_devfun.h"
 #include "ibp_kernels.h"
 
 namespace ibp {
-
-// ---------------------------------------------------------------- helpers
-
-__device__ __forceinline__ float next_up_f32(float f) {
-  if (!(f < INFINITY)) return f;  // +inf or NaN
-  if (f == 0.0f) return __int_as_float(1);
-  int b = __float_as_int(f);
-  return __int_as_float(f > 0.0f ? b + 1 : b - 1);
-}
-
-// Smallest float32 >= x.
-__device__ __forceinline__ float ru32(double x) {
-  float f = (float)x;
-  return ((double)f < x) ? next_up_f32(f) : f;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-  return v;
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
-  return v;
-}
-
-// Block-wide sum over 256 threads (4 waves); every thread gets the result.
-__device__ __forceinline__ double block_sum256(double v, double* sh) {
-  v = wave_sum(v);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[w] = v;
-  __syncthreads();
-  double t = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-  __syncthreads();
-  return t;
-}
-
-// Streaming load of a float4 that is read exactly once (nontemporal hint: the
-// line is not kept in the caches).
-typedef float vf4_t __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ float4 ld_stream(const float4* p) {
-  const vf4_t t = __builtin_nontemporal_load(reinterpret_cast<const vf4_t*>(p));
-  return make_float4(t.x, t.y, t.z, t.w);
-}
-
-template <typename T>
-__device__ __forceinline__ T* ws_ptr(void* ws, size_t off) {
-  return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + off);
-}
 
 // ---------------------------------------------------------------- K1
 
@@ -480,36 +429,6 @@ __global__ __launch_bounds__(kK4Threads) void k4_finalize(DevNet net, void* ws, 
 // max(NaN, 0) = 0 (IEEE maxNum), which removes it (the paper's mask M)
 // without a branch.  Eight penalties are summed in float32 (three levels)
 // before the float64 accumulation; K4 scales the totals by (1 +- 4u) for that.
-__device__ __forceinline__ void k3_elem(float lam, float cc, float rk, float cl, float h, float g,
-                                        float& phi, float& plo) {
-  const float C = fmaf(lam, cc, cl);
-  const float A = fmaf(fabsf(lam), rk, h);
-  const float B = fmaf(fabsf(lam), rk, g);
-  phi = fmaxf(fabsf(C) + A, 0.0f);
-  plo = fmaxf(fabsf(C) - B, 0.0f);
-}
-
-// Two outages x four lines, summed in float32 (depth 3) and added in float64.
-__device__ __forceinline__ void k3_pair(const float4& x0, const int4& d0, const float4& x1,
-                                        const int4& d1, const float4& c4, const float4& h4,
-                                        const float4& g4, double& acc_hi, double& acc_lo) {
-  const float cc0 = __int_as_float(d0.y), rk0 = __int_as_float(d0.z);
-  const float cc1 = __int_as_float(d1.y), rk1 = __int_as_float(d1.z);
-  float a0, a1, a2, a3, b0, b1, b2, b3, e0, e1, e2, e3, f0, f1, f2, f3;
-  k3_elem(x0.x, cc0, rk0, c4.x, h4.x, g4.x, a0, b0);
-  k3_elem(x0.y, cc0, rk0, c4.y, h4.y, g4.y, a1, b1);
-  k3_elem(x0.z, cc0, rk0, c4.z, h4.z, g4.z, a2, b2);
-  k3_elem(x0.w, cc0, rk0, c4.w, h4.w, g4.w, a3, b3);
-  k3_elem(x1.x, cc1, rk1, c4.x, h4.x, g4.x, e0, f0);
-  k3_elem(x1.y, cc1, rk1, c4.y, h4.y, g4.y, e1, f1);
-  k3_elem(x1.z, cc1, rk1, c4.z, h4.z, g4.z, e2, f2);
-  k3_elem(x1.w, cc1, rk1, c4.w, h4.w, g4.w, e3, f3);
-  acc_hi += (double)(((a0 + a1) + (a2 + a3)) + ((e0 + e1) + (e2 + e3)));
-  acc_lo += (double)(((b0 + b1) + (b2 + b3)) + ((f0 + f1) + (f2 + f3)));
-}
-
-__device__ __forceinline__ float add_ru(float a, float b) { return next_up_f32(a + b); }
-
 template <int KC>
 __global__ __launch_bounds__(256) void k3_contingency(DevNet net, void* ws, WsLayout lay, int64_t box0) {
   __shared__ double sh[8];
@@ -640,6 +559,33 @@ hipError_t launch_forward_single(const DevNet& net, int64_t n_box, const float* 
       tm->stop(t, s);
     }
     t = tm->start(3, s);
+    hipLaunchKernelGGL(k4_finalize, dim3(nb), dim3(kK4Threads), 0, s, net, ws, lay, b0, f_lo, f_hi, terms);
+    tm->stop(t, s);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_forward(const DevNet& net, int64_t n_box, const float* lo, const float* hi, double* f_lo,
+                          double* f_hi, double* terms, void* ws, const WsLayout& lay, hipStream_t s,
+                          KernelTimer* tm) {
+  if (!lay.batched) return launch_forward_single(net, n_box, lo, hi, f_lo, f_hi, terms, ws, lay, s, tm);
+  for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
+    const int nb = (int)std::min<int64_t>(65535, n_box - b0);
+    const int t = tm->start(0, s);
+    hipLaunchKernelGGL(k1_box_prep, dim3(lay.n_p1, nb), dim3(64), 0, s, net, lo, hi, ws, lay, b0);
+    tm->stop(t, s);
+  }
+  launch_batched_sweeps(net, n_box, ws, lay, s, tm, 0);
+  for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
+    const int nb = (int)std::min<int64_t>(65535, n_box - b0);
+    const int t = tm->start(4, s);
+    hipLaunchKernelGGL(k2e_lines, dim3(lay.n_p2, nb), dim3(64), 0, s, net, ws, lay, b0);
+    tm->stop(t, s);
+  }
+  launch_batched_sweeps(net, n_box, ws, lay, s, tm, 1);
+  for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
+    const int nb = (int)std::min<int64_t>(65535, n_box - b0);
+    const int t = tm->start(3, s);
     hipLaunchKernelGGL(k4_finalize, dim3(nb), dim3(kK4Threads), 0, s, net, ws, lay, b0, f_lo, f_hi, terms);
     tm->stop(t, s);
   }

@@ -45,6 +45,19 @@ bool tune_valid(const Tune& t);
 // Grid shapes and partial-sum counts of the single-box-per-slice forward path.
 void plan_single(const DevNet& net, int64_t n_box, WsLayout& lay, const Tune& t);
 
+// Box-tiled plan (n_box >= kBatchMin and no IBP_F_PLAIN).
+void plan_batched(const DevNet& net, int64_t n_box, WsLayout& lay);
+constexpr int64_t kBatchMin = 4;
+
+// Batched base-flow sweep (phase 0) or outage sweep (phase 1).
+hipError_t launch_batched_sweeps(const DevNet& net, int64_t n_box, void* ws, const WsLayout& lay, hipStream_t s,
+                                 KernelTimer* tm, int phase);
+
+// Forward bounds for n_box boxes with the plan in `lay` (single or batched).
+hipError_t launch_forward(const DevNet& net, int64_t n_box, const float* lo, const float* hi, double* f_lo,
+                          double* f_hi, double* terms, void* ws, const WsLayout& lay, hipStream_t s,
+                          KernelTimer* tm);
+
 // K1..K4 for n_box boxes, each box handled by its own grid slice.
 hipError_t launch_forward_single(const DevNet& net, int64_t n_box, const float* lo, const float* hi,
                                  double* f_lo, double* f_hi, double* terms, void* ws,
