@@ -122,7 +122,8 @@ void ibp_free_network(ibp_network* net);
 
 /* Flags for the compute calls. */
 #define IBP_F_NONE 0u
-#define IBP_F_PLAIN 1u /* per-box single-box kernels even for n_box > 1 (reference form for batching) */
+#define IBP_F_PLAIN 1u    /* per-box single-box kernels even for n_box > 1 (reference form for batching) */
+#define IBP_F_BACKWARD 4u /* workspace query only: size for ibp_bound_backward (includes the forward's) */
 
 /* Bytes of device workspace a compute call needs for n_box boxes (0 on error). */
 size_t ibp_workspace_bytes(const ibp_network* net, int64_t n_box, uint32_t flags);
@@ -148,8 +149,10 @@ ibp_status ibp_bound_boxes(const ibp_network* net, int64_t n_box,
  *   g_box_lo[b, j] = d(g_f_lo[b] f_lo[b] + g_f_hi[b] f_hi[b]) / d box_lo[b, j],
  *   g_box_hi likewise (device float64 [n_box x X], overwritten).
  * Subgradient convention: sign(0) = 0 and max(z, 0) is active iff z > 0.
- * g_f_lo, g_f_hi: device float64 [n_box].  Same workspace rule as the forward
- * call (it recomputes the forward intermediates).  Errors as the forward call. */
+ * g_f_lo, g_f_hi: device float64 [n_box].  The workspace must hold
+ * ibp_workspace_bytes(net, n_box, flags | IBP_F_BACKWARD); the call recomputes
+ * the forward intermediates in it.  A box with invalid endpoints gets NaN
+ * gradients.  Errors as the forward call. */
 ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box,
                               const float* box_lo, const float* box_hi,
                               const double* g_f_lo, const double* g_f_hi,

@@ -164,6 +164,15 @@ ibp_status to_device(ibp_network* net, int device) {
     if ((st = upload(net, le.data(), le.size(), &d.line_eps)) != IBP_OK) return st;
   }
   {
+    std::vector<float> fc(d.Lp, std::numeric_limits<float>::max());
+    for (int l = 0; l < h.L; ++l) fc[l] = (float)h.fmax_ctg[l];
+    if ((st = upload(net, fc.data(), fc.size(), &d.fmax_c32)) != IBP_OK) return st;
+    std::vector<int> db(h.G + h.D);
+    for (int g = 0; g < h.G; ++g) db[g] = h.gen_bus[g];
+    for (int j = 0; j < h.D; ++j) db[h.G + j] = h.load_bus[j];
+    if ((st = upload(net, db.data(), db.size(), &d.dev_bus)) != IBP_OK) return st;
+  }
+  {
     const int X = h.G + h.D;
     std::vector<int> ptr(h.N + 1, 0), dev(X);
     std::vector<double> w(X);
@@ -215,7 +224,26 @@ ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
     return layout_for(net, n_box, t, false);
   }
   const bool batched = n_box >= ibp::kBatchMin && !(flags & IBP_F_PLAIN);
-  return layout_for(net, n_box, net->tune, batched);
+  ibp::WsLayout lay = layout_for(net, n_box, net->tune, batched);
+  if (flags & IBP_F_BACKWARD) {
+    const ibp::DevNet& d = net->dn;
+    const size_t B = (size_t)std::max<int64_t>(1, n_box);
+    ibp::plan_backward(d, lay);
+    size_t off = lay.total;
+    auto take = [&](size_t bytes) {
+      const size_t o = off;
+      off = align256(off + bytes);
+      return o;
+    };
+    lay.lpart = take(B * lay.k5_by * d.Lp * 2 * sizeof(float));
+    lay.cpart = take(B * lay.k5_tiles * std::max(1, d.K) * 2 * sizeof(float));
+    lay.gcf = take(B * d.Lp * sizeof(float));
+    lay.grf = take(B * d.Lp * sizeof(float));
+    lay.gci = take(B * d.Np * sizeof(double));
+    lay.gri = take(B * d.Np * sizeof(double));
+    lay.total = off;
+  }
+  return lay;
 }
 
 ibp::WsLayout layout_for(const ibp_network* net, int64_t n_box, const ibp::Tune& tune, bool batched = false) {
@@ -254,7 +282,7 @@ ibp_status check_compute_args(const ibp_network* net, int64_t n_box, const void*
   if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
   if (net->device < 0) return fail(IBP_E_HOST_ONLY, "network was built host-only");
   if (n_box < 0) return fail(IBP_E_INVALID_ARG, "n_box < 0");
-  if (flags & ~uint32_t(IBP_F_PLAIN)) return fail(IBP_E_INVALID_ARG, "unknown flag bits");
+  if (flags & ~uint32_t(IBP_F_PLAIN | IBP_F_BACKWARD)) return fail(IBP_E_INVALID_ARG, "unknown flag bits");
   if (n_box == 0) return IBP_OK;
   if (!lo || !hi || !a || !b) return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
   lay = layout(net, n_box, flags);
@@ -365,9 +393,20 @@ ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box, const float
                               double* g_box_lo, double* g_box_hi, void* ws, size_t ws_bytes,
                               void* stream, uint32_t flags) {
   g_err.clear();
-  (void)net; (void)n_box; (void)box_lo; (void)box_hi; (void)g_f_lo; (void)g_f_hi;
-  (void)g_box_lo; (void)g_box_hi; (void)ws; (void)ws_bytes; (void)stream; (void)flags;
-  return fail(IBP_E_INVALID_ARG, "backward not available yet");
+  ibp::WsLayout lay;
+  ibp_status st = check_compute_args(net, n_box, box_lo, box_hi, g_f_lo, g_f_hi, ws, ws_bytes,
+                                     flags | IBP_F_BACKWARD, lay);
+  if (st != IBP_OK || n_box == 0) return st;
+  if (!g_box_lo || !g_box_hi) return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
+  DeviceGuard g(net->device);
+  if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ibp::KernelTimer* tm = const_cast<ibp::KernelTimer*>(&net->timer);
+  hipError_t e = ibp::launch_forward_prep(net->dn, n_box, box_lo, box_hi, ws, lay, s, tm);
+  if (e == hipSuccess)
+    e = ibp::launch_backward_sweeps(net->dn, n_box, ws, lay, g_f_lo, g_f_hi, g_box_lo, g_box_hi, s, tm);
+  if (e != hipSuccess) return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  return IBP_OK;
 }
 
 ibp_status ibp_set_kernel_timing(ibp_network* net, int enable) {

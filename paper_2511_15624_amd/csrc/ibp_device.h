@@ -48,6 +48,8 @@ struct DevNet {
   const double* ctg_eps;    // [K] 2 phi_err[c] / (1 - H_cc)
   const double* ctg_inv;    // [K] 1 / (1 - H_cc)
   const float* line_eps;    // [Lp] 2 phi_err[l], rounded up (0 on padding lines)
+  const float* fmax_c32;    // [Lp] post-outage limit as float32 (FLT_MAX on padding lines)
+  const int* dev_bus;       // [X] bus of each input (generators, then loads)
   const int* bus_ptr;       // [N + 1] CSR over buses of the devices on each bus
   const int* bus_dev;       // [X] device indices (0..G-1 generators, G..X-1 loads)
   const double* dev_w;      // [X] -cost for generators, +value for loads
@@ -64,9 +66,11 @@ struct WsLayout {
   size_t box = 0;                  // double [B][kBoxSlots]
   size_t lc = 0, lh = 0, lg = 0;   // float [B][Lp]: line centre, h = rho'-fmax, g = rho'+fmax
   size_t lcf = 0, lrf = 0;         // double [B][L]: base-flow centre and enclosing radius
-  size_t ctg = 0;                  // int4 [B][K]: (line, centre bits, rho' bits, 0)
+  size_t ctg = 0;                  // int4 [B][K]: (line, centre bits, rho' bits, unpadded radius bits)
   size_t p2 = 0;                   // double2 [B][n_p2]: base-penalty partial sums (hi, lo)
   size_t p3 = 0;                   // double2 [B][n_p3]: contingency partial sums (hi, lo)
+  size_t lpart = 0;                // float2 [B][k5_by][Lp]: backward per-line partials (d centre, d radius)
+  size_t cpart = 0;                // float2 [B][k5_tiles][K]: backward per-outage partials
   size_t gcf = 0, grf = 0;         // float [B][Lp]: backward line gradients (centre, radius)
   size_t gci = 0, gri = 0;         // double [B][Np]: backward injection gradients
   size_t total = 0;
@@ -77,6 +81,7 @@ struct WsLayout {
   int batched = 0;                 // 1: box-tiled kernels (boxes share every streamed tile)
   int k2_gx = 0;                   // batched base flows: grid x (line tiles padded to a multiple of 8)
   int k3_kper = 0;                 // batched outage sweep: outages per block row
+  int k5_by = 0, k5_tiles = 0;     // backward outage sweep: outage chunks, line tiles
 };
 
 }  // namespace ibp

@@ -157,7 +157,8 @@ __device__ __forceinline__ unsigned line_epilogue(const DevNet& net, int l, doub
     const double Ek = net.ctg_eps[k] * (acl + rl);
     const double rk = (1.0 + kKappa0) * rl + (kKappa0 + kU32) * acl + Ek;
     const double rkp = ((rk + u1 * acl) * inv1md) * (1.0 + 16.0 * kU64) + 1e-36;
-    ctg[k] = make_int4(l, __float_as_int(cl), __float_as_int(ru32(rkp)), 0);
+    // fourth field: the unpadded radius, read by the backward sweep
+    ctg[k] = make_int4(l, __float_as_int(cl), __float_as_int(ru32(rkp)), __float_as_int((float)rf));
     const float v = ru32((acl + rl) * net.ctg_inv[k] * (1.0 + 4.0 * kU64));
     return __float_as_uint(v);
   }
@@ -560,6 +561,38 @@ hipError_t launch_forward_single(const DevNet& net, int64_t n_box, const float* 
     }
     t = tm->start(3, s);
     hipLaunchKernelGGL(k4_finalize, dim3(nb), dim3(kK4Threads), 0, s, net, ws, lay, b0, f_lo, f_hi, terms);
+    tm->stop(t, s);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_forward_prep(const DevNet& net, int64_t n_box, const float* lo, const float* hi, void* ws,
+                               const WsLayout& lay, hipStream_t s, KernelTimer* tm) {
+  for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
+    const int nb = (int)std::min<int64_t>(65535, n_box - b0);
+    const int t = tm->start(0, s);
+    hipLaunchKernelGGL(k1_box_prep, dim3(lay.n_p1, nb), dim3(64), 0, s, net, lo, hi, ws, lay, b0);
+    tm->stop(t, s);
+  }
+  if (lay.batched) {
+    launch_batched_sweeps(net, n_box, ws, lay, s, tm, 0);
+  } else {
+    for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
+      const int nb = (int)std::min<int64_t>(65535, n_box - b0);
+      const int t = tm->start(1, s);
+      switch (lay.k2_nc) {
+        case 32: launch_k2<32>(net, ws, lay, b0, nb, s); break;
+        case 64: launch_k2<64>(net, ws, lay, b0, nb, s); break;
+        case 256: launch_k2<256>(net, ws, lay, b0, nb, s); break;
+        default: launch_k2<128>(net, ws, lay, b0, nb, s); break;
+      }
+      tm->stop(t, s);
+    }
+  }
+  for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
+    const int nb = (int)std::min<int64_t>(65535, n_box - b0);
+    const int t = tm->start(4, s);
+    hipLaunchKernelGGL(k2e_lines, dim3(lay.n_p2, nb), dim3(64), 0, s, net, ws, lay, b0);
     tm->stop(t, s);
   }
   return hipGetLastError();

@@ -58,6 +58,17 @@ hipError_t launch_forward(const DevNet& net, int64_t n_box, const float* lo, con
                           double* f_hi, double* terms, void* ws, const WsLayout& lay, hipStream_t s,
                           KernelTimer* tm);
 
+// Forward preparation only (K1, base flows, line epilogue): everything the
+// backward kernels read.
+hipError_t launch_forward_prep(const DevNet& net, int64_t n_box, const float* lo, const float* hi, void* ws,
+                               const WsLayout& lay, hipStream_t s, KernelTimer* tm);
+
+// Backward grid shapes, and the backward kernels after launch_forward_prep.
+void plan_backward(const DevNet& net, WsLayout& lay);
+hipError_t launch_backward_sweeps(const DevNet& net, int64_t n_box, void* ws, const WsLayout& lay,
+                                  const double* g_lo, const double* g_hi, double* d_lo, double* d_hi,
+                                  hipStream_t s, KernelTimer* tm);
+
 // K1..K4 for n_box boxes, each box handled by its own grid slice.
 hipError_t launch_forward_single(const DevNet& net, int64_t n_box, const float* lo, const float* hi,
                                  double* f_lo, double* f_hi, double* terms, void* ws,

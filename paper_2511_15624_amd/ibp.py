@@ -22,6 +22,7 @@ IBP_DEVICE_HOST_ONLY = -1
 IBP_F_NONE = 0
 IBP_F_PLAIN = 1
 IBP_F_AUTOTUNE = 2
+IBP_F_BACKWARD = 4
 
 STATUS = {
     0: "IBP_OK",
@@ -319,7 +320,7 @@ def ibp_bound_backward(net: Network, lo, hi, g_lo, g_hi, flags: int = 0, ws: Wor
     d_lo = torch.empty((n, net.n_input), dtype=torch.float64, device=lo.device)
     d_hi = torch.empty((n, net.n_input), dtype=torch.float64, device=lo.device)
     ws = ws or Workspace(net)
-    buf, need = ws.get(n, flags)
+    buf, need = ws.get(n, flags | IBP_F_BACKWARD)
     _check(load_library().ibp_bound_backward(net.handle, n, _dev_ptr(lo), _dev_ptr(hi), _dev_ptr(g_lo),
                                              _dev_ptr(g_hi), _dev_ptr(d_lo), _dev_ptr(d_hi),
                                              _dev_ptr(buf), buf.numel(), _stream_ptr(stream), flags))

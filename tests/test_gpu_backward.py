@@ -1,0 +1,156 @@
+"""GPU parity of the backward (VJP) kernels against the FP64 oracle's analytic
+gradient, finite differences of the GPU forward, batched vs per-box, and the
+autograd wrapper.
+
+The gradient is that of the unpadded IBP map; GPU and oracle take the kink
+decisions in different precisions (float32 vs float64), so an element that
+sits within rounding of a kink can switch sides.  Parity is therefore asserted
+as a relative L2 error <= 1e-4 over all coordinates (1e-3 at full size).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2511_15624_amd import ibp, synth
+from tests.test_gpu_forward import setup
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def gpu_grad(n, lo, hi, g_lo, g_hi, flags=0):
+    torch = _torch()
+    tlo = torch.from_numpy(np.ascontiguousarray(np.atleast_2d(lo), np.float32)).cuda()
+    thi = torch.from_numpy(np.ascontiguousarray(np.atleast_2d(hi), np.float32)).cuda()
+    gl = torch.as_tensor(np.atleast_1d(g_lo), dtype=torch.float64).cuda()
+    gh = torch.as_tensor(np.atleast_1d(g_hi), dtype=torch.float64).cuda()
+    d_lo, d_hi = ibp.ibp_bound_backward(n, tlo, thi, gl, gh, flags=flags)
+    torch.cuda.synchronize()
+    return d_lo.cpu().numpy(), d_hi.cpu().numpy()
+
+
+def rel_l2(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+@pytest.mark.parametrize("gw", [(1.0, 0.0), (0.0, 1.0), (0.3, -0.7)])
+def test_tiny_gradient_matches_oracle(gw):
+    net, fac, n = setup("tiny")
+    blo, bhi = synth.sub_boxes(net, 6, seed=12)
+    lo, hi = synth.full_box(net)
+    LO = np.vstack([lo[None], blo])
+    HI = np.vstack([hi[None], bhi])
+    G_lo = np.full(LO.shape[0], gw[0])
+    G_hi = np.full(LO.shape[0], gw[1])
+    d_lo, d_hi = gpu_grad(n, LO, HI, G_lo, G_hi)
+    for b in range(LO.shape[0]):
+        o_lo, o_hi, near = oracle.grad(net, LO[b], HI[b], gw[0], gw[1], fac)
+        ref = np.concatenate([o_lo, o_hi])
+        got = np.concatenate([d_lo[b], d_hi[b]])
+        assert rel_l2(got, ref) <= 1e-4, (b, rel_l2(got, ref), near)
+
+
+def test_c500_gradient_matches_oracle():
+    net, fac, n = setup("c500")
+    lo, hi = synth.full_box(net)
+    blo, bhi = synth.sub_boxes(net, 3, seed=77)
+    LO = np.vstack([lo[None], blo])
+    HI = np.vstack([hi[None], bhi])
+    d_lo, d_hi = gpu_grad(n, LO, HI, np.full(4, 0.5), np.full(4, -1.5))
+    for b in range(4):
+        o_lo, o_hi, _ = oracle.grad(net, LO[b], HI[b], 0.5, -1.5, fac)
+        assert rel_l2(np.concatenate([d_lo[b], d_hi[b]]), np.concatenate([o_lo, o_hi])) <= 1e-4, b
+
+
+def test_c8316_gradient_matches_oracle():
+    net, fac, n = setup("c8316")
+    blo, bhi = synth.sub_boxes(net, 1, seed=41)
+    d_lo, d_hi = gpu_grad(n, blo, bhi, np.array([1.0]), np.array([1.0]))
+    o_lo, o_hi, _ = oracle.grad(net, blo[0], bhi[0], 1.0, 1.0, fac)
+    assert rel_l2(np.concatenate([d_lo[0], d_hi[0]]), np.concatenate([o_lo, o_hi])) <= 1e-3
+
+
+def test_gradient_against_central_differences_of_the_gpu_forward():
+    """Central differences (h = 1e-4) of the GPU bounds, on coordinates whose
+    oracle gradient is the same at x - h and x + h (no kink in between)."""
+    torch = _torch()
+    net, fac, n = setup("tiny")
+    blo, bhi = synth.sub_boxes(net, 1, seed=5)
+    a, b = blo[0].astype(np.float64), bhi[0].astype(np.float64)
+    d_lo, d_hi = gpu_grad(n, blo, bhi, np.array([1.0]), np.array([0.0]))
+    h = 1e-4
+    rows_lo, rows_hi, idx = [], [], []
+    for j in range(a.size):
+        for side in (0, 1):
+            lp, hp, lm, hm = a.copy(), b.copy(), a.copy(), b.copy()
+            if side == 0:
+                lp[j] += h
+                lm[j] -= h
+                if lp[j] > b[j]:
+                    continue
+            else:
+                hp[j] += h
+                hm[j] -= h
+                if hm[j] < a[j]:
+                    continue
+            gp = oracle.grad(net, lp, hp, 1.0, 0.0, fac)
+            gm = oracle.grad(net, lm, hm, 1.0, 0.0, fac)
+            if not (np.allclose(gp[side][j], gm[side][j], rtol=1e-9, atol=1e-9)):
+                continue
+            rows_lo += [lp, lm]
+            rows_hi += [hp, hm]
+            idx.append((j, side))
+    # float32 endpoints: evaluate at the float32 grid points actually used
+    LO = np.asarray(rows_lo, np.float32)
+    HI = np.asarray(rows_hi, np.float32)
+    tl = torch.from_numpy(LO).cuda()
+    th = torch.from_numpy(HI).cuda()
+    f_lo, _ = ibp.ibp_bound_boxes(n, tl, th)
+    f = f_lo.cpu().numpy()
+    checked = 0
+    for i, (j, side) in enumerate(idx):
+        step = (float(LO[2 * i, j]) - float(LO[2 * i + 1, j])) if side == 0 else \
+               (float(HI[2 * i, j]) - float(HI[2 * i + 1, j]))
+        fd = (f[2 * i] - f[2 * i + 1]) / step
+        g = d_lo[0, j] if side == 0 else d_hi[0, j]
+        # float32 bounds carry ~1e-7 relative noise: scale the tolerance with |f| / step
+        tol = 1e-3 * max(abs(g), 1.0) + 4e-7 * max(abs(f[2 * i]), 1.0) / abs(step)
+        assert abs(fd - g) <= tol, (j, side, fd, g)
+        checked += 1
+    assert checked >= 10
+
+
+def test_batched_backward_equals_per_box_and_bad_boxes():
+    net, fac, n = setup("c500")
+    blo, bhi = synth.sub_boxes(net, 13, seed=5)
+    blo, bhi = blo.copy(), bhi.copy()
+    blo[3, 0] = np.nan
+    g1 = np.linspace(-1, 1, 13)
+    g2 = np.linspace(2, 0.5, 13)
+    a_lo, a_hi = gpu_grad(n, blo, bhi, g1, g2)
+    p_lo, p_hi = gpu_grad(n, blo, bhi, g1, g2, flags=ibp.IBP_F_PLAIN)
+    assert np.all(np.isnan(a_lo[3])) and np.all(np.isnan(a_hi[3]))
+    ok = np.arange(13) != 3
+    assert rel_l2(a_lo[ok], p_lo[ok]) <= 1e-5 and rel_l2(a_hi[ok], p_hi[ok]) <= 1e-5
+    for b in (0, 12):
+        o_lo, o_hi, _ = oracle.grad(net, blo[b], bhi[b], g1[b], g2[b], fac)
+        assert rel_l2(np.concatenate([a_lo[b], a_hi[b]]), np.concatenate([o_lo, o_hi])) <= 1e-4
+
+
+def test_autograd_function():
+    torch = _torch()
+    from paper_2511_15624_amd.autograd import ibp_bound
+    net, fac, n = setup("tiny")
+    blo, bhi = synth.sub_boxes(net, 5, seed=1)
+    lo = torch.from_numpy(blo).cuda().requires_grad_(True)
+    hi = torch.from_numpy(bhi).cuda().requires_grad_(True)
+    f_lo, f_hi = ibp_bound(n, lo, hi)
+    w = torch.linspace(0.1, 1.0, 5, dtype=torch.float64, device="cuda")
+    (w * f_hi - 0.5 * f_lo).sum().backward()
+    d_lo, d_hi = gpu_grad(n, blo, bhi, np.full(5, -0.5), np.linspace(0.1, 1.0, 5))
+    np.testing.assert_allclose(lo.grad.cpu().numpy(), d_lo.astype(np.float32), rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(hi.grad.cpu().numpy(), d_hi.astype(np.float32), rtol=1e-6, atol=1e-6)
