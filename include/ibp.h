@@ -185,6 +185,39 @@ ibp_status ibp_set_tile(ibp_network* net, int32_t k2_nc, int32_t k3_kc);
 ibp_status ibp_autotune(ibp_network* net, int64_t n_box, const float* box_lo, const float* box_hi,
                         void* ws, size_t ws_bytes, void* stream, int32_t* chosen);
 
+/* Box splitting (branching on the input box; the paper names branch and bound
+ * over the inputs as the way to tighten IBP bounds, Sec. I and Sec. V).
+ * n_root roots each own `slots` leaf slots (leaf i of root r is row r*slots+i
+ * of leaf_lo/leaf_hi, device float32 [n_root*slots x n_input]); slots
+ * [0, n_used) hold leaves that partition the root.  One round:
+ *   ibp_split_select: per root, the leaf with the largest f_hi (leaf_fhi,
+ *     device float64 [n_root*slots]); its row index goes to sel (device int64
+ *     [n_root]) and a copy to sel_lo/sel_hi (device float32 [n_root x n_input]).
+ *   (the caller runs ibp_bound_backward on sel_lo/sel_hi with g_f_lo = 0,
+ *    g_f_hi = 1 to get g_lo/g_hi)
+ *   ibp_split_bisect: per root, splits the selected leaf at the float32
+ *     midpoint of the coordinate j maximising (g_hi_j - g_lo_j) * (hi_j - lo_j)/2;
+ *     the halves replace slot sel and fill slot n_used (requires n_used < slots),
+ *     and are also written to kid_lo/kid_hi (device [2*n_root x n_input], rows
+ *     2r, 2r+1) with their centre points in centers (same shape).  A leaf with no
+ *     float32 strictly inside any coordinate is duplicated.
+ *   (the caller bounds the children and the zero-width centre boxes)
+ *   ibp_split_update: writes the children's f_hi into leaf_fhi, sets
+ *     root_ub[r] = max leaf f_hi and root_lb[r] = max(root_lb[r], centre f_lo)
+ *     (device float64 [n_root]); n_used_after = n_used + 1.
+ * All asynchronous on `stream`; host-checkable errors: INVALID_ARG. */
+ibp_status ibp_split_select(int64_t n_root, int32_t slots, int32_t n_used, int32_t n_input,
+                            const float* leaf_lo, const float* leaf_hi, const double* leaf_fhi,
+                            int64_t* sel, float* sel_lo, float* sel_hi, void* stream);
+ibp_status ibp_split_bisect(int64_t n_root, int32_t slots, int32_t n_used, int32_t n_input,
+                            float* leaf_lo, float* leaf_hi, const int64_t* sel,
+                            const float* sel_lo, const float* sel_hi,
+                            const double* g_lo, const double* g_hi,
+                            float* kid_lo, float* kid_hi, float* centers, void* stream);
+ibp_status ibp_split_update(int64_t n_root, int32_t slots, int32_t n_used_after, const int64_t* sel,
+                            const double* kid_fhi, const double* center_flo, double* leaf_fhi,
+                            double* root_ub, double* root_lb, void* stream);
+
 /* Last error message of the calling thread ("" if none). */
 const char* ibp_last_error(void);
 

@@ -510,6 +510,51 @@ ibp_status ibp_autotune(ibp_network* net, int64_t n_box, const float* box_lo, co
   return IBP_OK;
 }
 
+ibp_status ibp_split_select(int64_t n_root, int32_t slots, int32_t n_used, int32_t n_input,
+                            const float* leaf_lo, const float* leaf_hi, const double* leaf_fhi,
+                            int64_t* sel, float* sel_lo, float* sel_hi, void* stream) {
+  g_err.clear();
+  if (n_root < 0 || slots < 1 || n_used < 1 || n_used > slots || n_input < 1)
+    return fail(IBP_E_INVALID_ARG, "bad split sizes");
+  if (n_root == 0) return IBP_OK;
+  if (!leaf_lo || !leaf_hi || !leaf_fhi || !sel || !sel_lo || !sel_hi)
+    return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
+  hipError_t e = ibp::launch_split_select(n_root, slots, n_used, n_input, leaf_lo, leaf_hi, leaf_fhi, sel, sel_lo,
+                                          sel_hi, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? IBP_OK : fail(IBP_E_DEVICE, hipGetErrorString(e));
+}
+
+ibp_status ibp_split_bisect(int64_t n_root, int32_t slots, int32_t n_used, int32_t n_input,
+                            float* leaf_lo, float* leaf_hi, const int64_t* sel,
+                            const float* sel_lo, const float* sel_hi,
+                            const double* g_lo, const double* g_hi,
+                            float* kid_lo, float* kid_hi, float* centers, void* stream) {
+  g_err.clear();
+  if (n_root < 0 || slots < 2 || n_used < 1 || n_used >= slots || n_input < 1)
+    return fail(IBP_E_INVALID_ARG, "bad split sizes (need n_used < slots)");
+  if (n_root == 0) return IBP_OK;
+  if (!leaf_lo || !leaf_hi || !sel || !sel_lo || !sel_hi || !g_lo || !g_hi || !kid_lo || !kid_hi || !centers)
+    return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
+  if (n_root > 0x7fffffff) return fail(IBP_E_INVALID_ARG, "too many roots");
+  hipError_t e = ibp::launch_split_bisect(n_root, slots, n_used, n_input, leaf_lo, leaf_hi, sel, sel_lo, sel_hi,
+                                          g_lo, g_hi, kid_lo, kid_hi, centers, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? IBP_OK : fail(IBP_E_DEVICE, hipGetErrorString(e));
+}
+
+ibp_status ibp_split_update(int64_t n_root, int32_t slots, int32_t n_used_after, const int64_t* sel,
+                            const double* kid_fhi, const double* center_flo, double* leaf_fhi,
+                            double* root_ub, double* root_lb, void* stream) {
+  g_err.clear();
+  if (n_root < 0 || slots < 2 || n_used_after < 2 || n_used_after > slots)
+    return fail(IBP_E_INVALID_ARG, "bad split sizes");
+  if (n_root == 0) return IBP_OK;
+  if (!sel || !kid_fhi || !center_flo || !leaf_fhi || !root_ub || !root_lb)
+    return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
+  hipError_t e = ibp::launch_split_update(n_root, slots, n_used_after, sel, kid_fhi, center_flo, leaf_fhi,
+                                          root_ub, root_lb, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? IBP_OK : fail(IBP_E_DEVICE, hipGetErrorString(e));
+}
+
 const char* ibp_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"

@@ -49,6 +49,9 @@ EXPORTED = [
     "ibp_kernel_times",
     "ibp_set_tile",
     "ibp_autotune",
+    "ibp_split_select",
+    "ibp_split_bisect",
+    "ibp_split_update",
     "ibp_last_error",
 ]
 
@@ -138,6 +141,13 @@ def load_library(path: str = LIB_PATH):
     lib.ibp_set_tile.restype = ctypes.c_int
     lib.ibp_autotune.argtypes = [vp, i64, vp, vp, vp, sz, vp, vp]
     lib.ibp_autotune.restype = ctypes.c_int
+    i32 = ctypes.c_int32
+    lib.ibp_split_select.argtypes = [i64, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp]
+    lib.ibp_split_select.restype = ctypes.c_int
+    lib.ibp_split_bisect.argtypes = [i64, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.ibp_split_bisect.restype = ctypes.c_int
+    lib.ibp_split_update.argtypes = [i64, i32, i32, vp, vp, vp, vp, vp, vp, vp]
+    lib.ibp_split_update.restype = ctypes.c_int
     lib.ibp_last_error.argtypes = []
     lib.ibp_last_error.restype = ctypes.c_char_p
     _lib = lib
