@@ -30,6 +30,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "ibp_traffic_c8316_single_box.json")
+KERNEL_NAMES = {"base_flows": "ibp::k2_base_flows<256>", "outage_sweep": "ibp::k3_contingency<16>"}
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter record
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's readings), or None when
+    the kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC_RECORD) as f:
+            rec = json.load(f)
+        m = hashlib.sha256()
+        for p in rec["sources"]:
+            with open(os.path.join(ROOT, p), "rb") as g:
+                m.update(g.read())
+        if m.hexdigest()[:16] != rec["source_sha256_16"]:
+            return None
+        k = rec["kernels"][KERNEL_NAMES[kernel]]
+        return k["fetch_bytes"] + k["write_bytes"]
+    except Exception:
+        return None
 
 
 def _threads():
@@ -53,12 +75,106 @@ def cpu_baseline(net, lo, hi):
     return r, t, t_build, int(fac["K"])
 
 
+VALU_PEAK = 78.6e12  # float32 VALU lane-ops/s: 256 CUs x 128 lanes/clock x 2.4 GHz (FMA = one op)
+OPS_PER_EVAL = 9.25  # VALU ops per box-outage-line evaluation in the outage sweep (from the ISA)
+
+
+def _time(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def extras(torch, ibp, synth, n4, net4):
+    """Batched, backward and splitting throughput next to the per-box (plain) form."""
+    res = {}
+    # batched: 2000-bus network, 18 periods x 1024 sub-boxes in one call
+    net3 = synth.make_config("c2000")
+    n3 = ibp.Network(net3, device=0)
+    lo, hi, _ = synth.period_boxes(net3, 18, 1024, seed=31)
+    tlo, thi = torch.from_numpy(lo).cuda(), torch.from_numpy(hi).cuda()
+    ws = ibp.Workspace(n3)
+    ms = _time(torch, lambda: ibp.ibp_bound_boxes(n3, tlo, thi, ws=ws), 3)
+    ev = lo.shape[0] * n3.n_ctg * n3.n_line
+    sub = 1024
+    ms_p = _time(torch, lambda: ibp.ibp_bound_boxes(n3, tlo[:sub], thi[:sub], ws=ws, flags=ibp.IBP_F_PLAIN), 1)
+    ev_p = sub * n3.n_ctg * n3.n_line
+    n3.set_kernel_timing(True)
+    n3.kernel_times()
+    ibp.ibp_bound_boxes(n3, tlo, thi, ws=ws)
+    kt = n3.kernel_times()
+    n3.set_kernel_timing(False)
+    sweep_ms = kt.get("batched_outage_sweep", (float("nan"), 1))[0]
+    res["batched"] = {
+        "workload": f"2000 buses, {n3.n_line} lines, {n3.n_ctg} outages, 18 periods x 1024 sub-boxes = "
+                    f"{lo.shape[0]} boxes in one call",
+        "value": ev / (ms * 1e-3), "unit": "evals/s", "ms_per_call": ms,
+        "plain_value": ev_p / (ms_p * 1e-3), "plain_sample": f"first {sub} boxes, per-box kernels",
+        "speedup_vs_plain": (ev / ms) / (ev_p / ms_p),
+        "kernel_ms": {k: round(v[0], 3) for k, v in kt.items()},
+        "roofline": {"bound": "alu", "kernel": "batched_outage_sweep",
+                     "achieved": ev * OPS_PER_EVAL / (sweep_ms * 1e-3), "peak": VALU_PEAK, "unit": "ops/s",
+                     "frac": ev * OPS_PER_EVAL / (sweep_ms * 1e-3) / VALU_PEAK,
+                     "ops_per_eval": OPS_PER_EVAL},
+    }
+    # batched on the large network: 256 sub-boxes
+    blo, bhi = synth.sub_boxes(net4, 256, seed=41)
+    t4l, t4h = torch.from_numpy(blo).cuda(), torch.from_numpy(bhi).cuda()
+    ws4 = ibp.Workspace(n4)
+    ms4 = _time(torch, lambda: ibp.ibp_bound_boxes(n4, t4l, t4h, ws=ws4), 3)
+    ms4p = _time(torch, lambda: ibp.ibp_bound_boxes(n4, t4l, t4h, ws=ws4, flags=ibp.IBP_F_PLAIN), 1)
+    ev4 = 256 * n4.n_ctg * n4.n_line
+    res["batched_large"] = {"workload": "8316 buses, 256 sub-boxes", "value": ev4 / (ms4 * 1e-3),
+                            "unit": "evals/s", "ms_per_call": ms4, "plain_value": ev4 / (ms4p * 1e-3),
+                            "speedup_vs_plain": ms4p / ms4}
+    # backward: 2000-bus network, 4096 sub-boxes of period 0
+    blo, bhi = synth.sub_boxes(net3, 4096, seed=51)
+    t5l, t5h = torch.from_numpy(blo).cuda(), torch.from_numpy(bhi).cuda()
+    g0 = torch.zeros(4096, dtype=torch.float64, device="cuda")
+    g1 = torch.ones(4096, dtype=torch.float64, device="cuda")
+    wsb = ibp.Workspace(n3)
+    msf = _time(torch, lambda: ibp.ibp_bound_boxes(n3, t5l, t5h, ws=wsb), 3)
+    msb = _time(torch, lambda: ibp.ibp_bound_backward(n3, t5l, t5h, g0, g1, ws=wsb), 3)
+    sub = 256
+    msbp = _time(torch, lambda: ibp.ibp_bound_backward(n3, t5l[:sub], t5h[:sub], g0[:sub], g1[:sub], ws=wsb,
+                                                        flags=ibp.IBP_F_PLAIN), 1)
+    ev5 = 4096 * n3.n_ctg * n3.n_line
+    res["backward"] = {"workload": "2000 buses, 4096 sub-boxes: d(f_hi)/d(box endpoints)",
+                       "value": ev5 / (msb * 1e-3), "unit": "evals/s", "ms_backward": msb,
+                       "ms_forward": msf, "plain_value": sub * n3.n_ctg * n3.n_line / (msbp * 1e-3),
+                       "plain_sample": f"first {sub} boxes, per-box kernels"}
+    # splitting: 4096 roots, 10 rounds of gradient-ranked bisection
+    from paper_2511_15624_amd.split import BoxSplitter
+    sp = BoxSplitter(n3, t5l, t5h, rounds=10)
+    torch.cuda.synchronize()
+    gap0 = float(sp.gap().sum())
+    hist = sp.run(10)
+    gap10, secs = hist[-1]
+    res["splitting"] = {"workload": "2000 buses, 4096 root boxes, 10 rounds (2 children + 2 centre points "
+                                    "per root per round)",
+                        "gap_reduction_per_s": (gap0 - gap10) / secs, "unit": "$/s",
+                        "total_gap_before": gap0, "total_gap_after": gap10, "seconds": secs,
+                        "relative_gap_reduction": (gap0 - gap10) / gap0}
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched / backward / splitting measurements")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -70,6 +186,16 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
+    if args.calibrate_copy:
+        # 1 GiB read + 1 GiB written per copy: divides the profiler's FETCH_SIZE /
+        # WRITE_SIZE readings into bytes
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30, "copies": 5}), flush=True)
+        return 0
     from paper_2511_15624_amd import ibp, synth
 
     name = "c8316"
@@ -119,7 +245,7 @@ def main(argv=None):
     dom = max(bytes_k, key=lambda k: avg.get(k, 0.0))
     achieved = bytes_k[dom] / (avg[dom] * 1e-3) / 1e9
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
             "mean_us": round(avg[dom] * 1e3, 2), "algorithmic_bytes": bytes_k[dom]}
     step_bytes = sum(bytes_k.values())
     step_gbs = step_bytes / (ms_step * 1e-3) / 1e9
@@ -147,6 +273,8 @@ def main(argv=None):
         "setup_s": round(t_setup, 2),
     }
     g_lo, g_hi = float(f_lo.cpu()[0]), float(f_hi.cpu()[0])
+    if not args.no_extras:
+        out.update(extras(torch, ibp, synth, n, net))
     if not args.no_cpu_baseline:
         r, t_cpu, t_build, k_or = cpu_baseline(net, lo, hi)
         out["cpu_baseline"] = {"value": evals / t_cpu, "unit": "evals/s", "cores": _threads(),

@@ -124,3 +124,13 @@ def test_compute_calls_need_a_device_handle(lib):
     lib.ibp_free_network(None)
     info = ibp.NetworkInfo()
     assert ibp.STATUS[lib.ibp_network_query(None, ctypes.byref(info))] == "IBP_E_INVALID_ARG"
+
+
+def test_split_calls_validate_sizes_before_any_device_work(lib):
+    st = lib.ibp_split_bisect(4, 3, 3, 5, None, None, None, None, None, None, None, None, None, None, None)
+    assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"      # needs a free slot (n_used < slots)
+    st = lib.ibp_split_select(4, 3, 1, 5, None, None, None, None, None, None, None)
+    assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"      # NULL device pointers
+    st = lib.ibp_split_update(4, 3, 4, None, None, None, None, None, None, None)
+    assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"      # n_used_after > slots
+    assert lib.ibp_split_select(0, 3, 1, 5, None, None, None, None, None, None, None) == 0

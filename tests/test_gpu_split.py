@@ -82,11 +82,3 @@ def test_split_coordinate_follows_the_gradient():
         changed = np.flatnonzero(k_hi[2 * b] != bhi[b])
         assert list(changed) == [j]
         assert k_lo[2 * b + 1, j] == k_hi[2 * b, j]
-
-
-def test_split_argument_errors():
-    lib = ibp.load_library()
-    st = lib.ibp_split_bisect(4, 3, 3, 5, None, None, None, None, None, None, None, None, None, None, None)
-    assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"
-    st = lib.ibp_split_select(4, 3, 1, 5, None, None, None, None, None, None, None)
-    assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"
