@@ -115,6 +115,13 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise FileNotFoundError(f"{path} is missing: run `python -m paper_2511_15624_amd.build`")
+    # PyTorch ships its own HIP runtime with the same soname as the system one;
+    # whichever is loaded first serves the whole process.  Load torch's first so
+    # that the tensors handed to the library and its kernels share one runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp, sz, i64, u32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64, ctypes.c_uint32
     lib.ibp_build_network.argtypes = [ctypes.POINTER(NetworkDesc), ctypes.c_int, ctypes.POINTER(vp)]

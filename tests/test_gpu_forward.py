@@ -127,12 +127,17 @@ def test_c500_full_box_and_sub_boxes():
 def test_batch_is_independent_and_deterministic():
     net, fac, n = setup("c500")
     blo, bhi = synth.sub_boxes(net, 9, seed=7)
+    # the batched (box-tiled) call is bitwise reproducible
     a_lo, a_hi = gpu_bounds(n, blo, bhi)
     b_lo, b_hi = gpu_bounds(n, blo, bhi)
     assert np.array_equal(a_lo, b_lo) and np.array_equal(a_hi, b_hi)
+    # per-box kernels on a batch give each box exactly its single-box result
+    p_lo, p_hi = gpu_bounds(n, blo, bhi, flags=ibp.IBP_F_PLAIN)
     for b in (0, 4, 8):
         s_lo, s_hi = gpu_bounds(n, blo[b], bhi[b])
-        assert s_lo[0] == a_lo[b] and s_hi[0] == a_hi[b]
+        assert s_lo[0] == p_lo[b] and s_hi[0] == p_hi[b]
+        r = orc(net, blo[b], bhi[b], fac)
+        assert_encloses(a_lo[b], a_hi[b], r, what=f"batched box {b}")
 
 
 def test_bad_boxes_poison_only_themselves():
@@ -198,3 +203,66 @@ def test_c8316_single_full_box():
     blo, bhi = synth.sub_boxes(net, 1, seed=41)
     f_lo, f_hi = gpu_bounds(n, blo, bhi)
     assert_encloses(f_lo[0], f_hi[0], orc(net, blo[0], bhi[0], fac), what="c8316 sub-box")
+
+
+def test_radial_network_without_outages_and_empty_batch():
+    """A tree has no non-islanding outage (K = 0): only base flows and imbalance."""
+    torch = _torch()
+    net = synth.make_network(30, 29, 6, 12, seed=8)
+    fac = oracle.factors(net)
+    assert fac["K"] == 0
+    n = ibp.Network(net, device=0)
+    assert n.n_ctg == 0
+    lo, hi = synth.full_box(net)
+    blo, bhi = synth.sub_boxes(net, 6, seed=2)
+    LO = np.vstack([lo[None], blo])
+    HI = np.vstack([hi[None], bhi])
+    for flags in (0, ibp.IBP_F_PLAIN):
+        f_lo, f_hi = gpu_bounds(n, LO, HI, flags=flags)
+        for b in range(LO.shape[0]):
+            assert_encloses(f_lo[b], f_hi[b], orc(net, LO[b], HI[b], fac), what=f"box {b}")
+    e = torch.empty((0, n.n_input), dtype=torch.float32, device="cuda")
+    a, b = ibp.ibp_bound_boxes(n, e, e)
+    assert a.numel() == 0 and b.numel() == 0
+
+
+def test_huge_limits_and_zero_penalties():
+    """Limits far above every flow leave the surplus and imbalance terms only;
+    zero weights leave the surplus interval exactly (special cases of the objective)."""
+    net = synth.make_config("c500")
+    big = dict(net, fmax_base=np.full(700, 1e30), fmax_ctg=np.full(700, 1e30))
+    n = ibp.Network(big, device=0)
+    blo, bhi = synth.sub_boxes(net, 4, seed=6)
+    f_lo, f_hi, t = gpu_bounds(n, blo, bhi, terms=True)
+    assert np.all(t[:, 4:] == 0.0)
+    fac = oracle.factors(big)
+    for b in range(4):
+        assert_encloses(f_lo[b], f_hi[b], orc(big, blo[b], bhi[b], fac), what=f"box {b}")
+    z = dict(net, zeta_inj=0.0, zeta_f=0.0)
+    n = ibp.Network(z, device=0)
+    f_lo, f_hi = gpu_bounds(n, blo, bhi)
+    G = net["gen_bus"].size
+    for b in range(4):
+        S_hi = np.sum(net["load_value"] * bhi[b, G:].astype(float)) - np.sum(net["gen_cost"] * blo[b, :G].astype(float))
+        S_lo = np.sum(net["load_value"] * blo[b, G:].astype(float)) - np.sum(net["gen_cost"] * bhi[b, :G].astype(float))
+        assert f_lo[b] <= S_lo and f_hi[b] >= S_hi
+        assert abs(f_lo[b] - S_lo) <= 1e-12 * abs(S_lo) + 1e-9 and abs(f_hi[b] - S_hi) <= 1e-12 * abs(S_hi) + 1e-9
+
+
+def test_tile_choices_give_enclosing_bounds():
+    """Every tile pair of the single-box kernels (and the autotuner's pick) encloses the oracle."""
+    torch = _torch()
+    net, fac, n = setup("c500")
+    lo, hi = synth.full_box(net)
+    r = orc(net, lo, hi, fac)
+    for nc in (32, 64, 128, 256):
+        for kc in (16, 32, 64, 128):
+            n.set_tile(nc, kc)
+            f_lo, f_hi = gpu_bounds(n, lo, hi)
+            assert_encloses(f_lo[0], f_hi[0], r, what=f"tile {nc},{kc}", strict_f=True)
+    tl = torch.from_numpy(lo[None].copy()).cuda()
+    th = torch.from_numpy(hi[None].copy()).cuda()
+    nc, kc = ibp.ibp_autotune(n, tl, th)
+    assert nc in (32, 64, 128, 256) and kc in (16, 32, 64, 128)
+    f_lo, f_hi = gpu_bounds(n, lo, hi)
+    assert_encloses(f_lo[0], f_hi[0], r, what="autotuned", strict_f=True)
