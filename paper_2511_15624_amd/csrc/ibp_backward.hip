@@ -37,8 +37,6 @@ namespace ibp {
 constexpr int kK5Chunk = 128;  // outages per block row
 constexpr int kK5Sub = 16;     // outages per butterfly reduction
 
-__device__ __forceinline__ float sgnf(float x) { return x > 0.0f ? 1.0f : (x < 0.0f ? -1.0f : 0.0f); }
-
 // Sums v[0..31] over the 64 lanes of a wave; afterwards lanes 2i and 2i+1
 // hold the total of v[i].
 __device__ __forceinline__ float butterfly32(float (&v)[32]) {
@@ -80,25 +78,48 @@ __device__ __forceinline__ float butterfly32(float (&v)[32]) {
   return v[0] + __shfl_xor(v[0], 1, 64);
 }
 
-// One element of the outage sweep's VJP.  Returns (dC, dR) and adds the
+// One element of the outage sweep's VJP.  rlm = r_l - fmax_l and
+// rlp = r_l + fmax_l per line.  Adds (dC, dR) to (gc, gr) and the
 // outage-side contributions Lam dC, |Lam| dR to (pc, pr).
-__device__ __forceinline__ void k5_elem(float lam, float cc, float rc, float cl, float rl, float fm, float chi,
+__device__ __forceinline__ void k5_elem(float lam, float cc, float rc, float cl, float rlm, float rlp, float chi,
                                         float clo, float& gc, float& gr, float& pc, float& pr) {
-  // The outaged line's own entry holds NaN: C and R are NaN, both activity
-  // tests fail and dC = dR = 0 (the paper's mask M); lam0 keeps the NaN out of
-  // the outage-side products.
+  // The outaged line's own entry holds NaN: both activity tests fail and
+  // dC = dR = 0 (the paper's mask M).  fminf(NaN, FLT_MAX) = FLT_MAX (IEEE
+  // minNum) keeps the NaN out of the outage-side products, which then add 0.
   const float C = fmaf(lam, cc, cl);
-  const float R = fmaf(fabsf(lam), rc, rl);
   const float a = fabsf(C);
-  const float hi = (a + R - fm > 0.0f) ? chi : 0.0f;
-  const float lo = (a - R - fm > 0.0f) ? clo : 0.0f;
-  const float dC = sgnf(C) * (hi + lo);
+  const float thi = a + fmaf(fabsf(lam), rc, rlm);  // |C| + R - fmax
+  const float tlo = a - fmaf(fabsf(lam), rc, rlp);  // |C| - R - fmax
+  const float hi = thi > 0.0f ? chi : 0.0f;
+  const float lo = tlo > 0.0f ? clo : 0.0f;
+  // sign(C) (hi + lo) by flipping the sign bit when C is negative; C = 0
+  // exactly only happens for a line whose flow interval is {0} here, where no
+  // penalty is active and hi + lo = 0
+  const float dC = __int_as_float(__float_as_int(hi + lo) ^ (__float_as_int(C) & (int)0x80000000));
   const float dR = hi - lo;
-  const float lam0 = (lam == lam) ? lam : 0.0f;
+  const float lam0 = fminf(lam, FLT_MAX);
   gc += dC;
   gr += dR;
   pc = fmaf(lam0, dC, pc);
   pr = fmaf(fabsf(lam0), dR, pr);
+}
+
+// Line data of the backward sweep for the four lines of float4 column `col`:
+// centre, r - fmax and r + fmax (padding lines: 0, -FLT_MAX, +FLT_MAX).
+__device__ __forceinline__ void line_radii(const DevNet& net, void* ws, const WsLayout& lay, int64_t b, int col,
+                                           bool on, float4& c4, float4& rm4, float4& rp4) {
+  c4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  rm4 = make_float4(-FLT_MAX, -FLT_MAX, -FLT_MAX, -FLT_MAX);
+  rp4 = make_float4(FLT_MAX, FLT_MAX, FLT_MAX, FLT_MAX);
+  if (!on) return;
+  c4 = reinterpret_cast<const float4*>(ws_ptr<float>(ws, lay.lc) + b * net.Lp)[col];
+  const float4 f4 = reinterpret_cast<const float4*>(net.fmax_c32)[col];
+  const double* rf = ws_ptr<double>(ws, lay.lrf) + b * net.L;
+  const int l0 = 4 * col;
+  const float r0 = l0 < net.L ? (float)rf[l0] : 0.f, r1 = l0 + 1 < net.L ? (float)rf[l0 + 1] : 0.f;
+  const float r2 = l0 + 2 < net.L ? (float)rf[l0 + 2] : 0.f, r3 = l0 + 3 < net.L ? (float)rf[l0 + 3] : 0.f;
+  rm4 = make_float4(r0 - f4.x, r1 - f4.y, r2 - f4.z, r3 - f4.w);
+  rp4 = make_float4(r0 + f4.x, r1 + f4.y, r2 + f4.z, r3 + f4.w);
 }
 
 __global__ __launch_bounds__(256) void k5_outage_vjp(DevNet net, void* ws, WsLayout lay, int64_t box0,
@@ -117,15 +138,8 @@ __global__ __launch_bounds__(256) void k5_outage_vjp(DevNet net, void* ws, WsLay
   const float chi = (float)(-net.zeta_f * g_lo[b]);  // weight of an active P_hi
   const float clo = (float)(-net.zeta_f * g_hi[b]);  // weight of an active P_lo (dR gets -clo)
   // lines of this lane (padding lines: zero centre and radius, limit FLT_MAX)
-  float4 c4 = make_float4(0.f, 0.f, 0.f, 0.f), r4 = c4, f4 = make_float4(FLT_MAX, FLT_MAX, FLT_MAX, FLT_MAX);
-  if (on) {
-    c4 = reinterpret_cast<const float4*>(ws_ptr<float>(ws, lay.lc) + b * net.Lp)[col];
-    const double* rf = ws_ptr<double>(ws, lay.lrf) + b * net.L;
-    const int l0 = 4 * col;
-    r4 = make_float4(l0 < net.L ? (float)rf[l0] : 0.f, l0 + 1 < net.L ? (float)rf[l0 + 1] : 0.f,
-                     l0 + 2 < net.L ? (float)rf[l0 + 2] : 0.f, l0 + 3 < net.L ? (float)rf[l0 + 3] : 0.f);
-    f4 = reinterpret_cast<const float4*>(net.fmax_c32)[col];
-  }
+  float4 c4 = make_float4(0.f, 0.f, 0.f, 0.f), rm4, rp4;
+  line_radii(net, ws, lay, b, col, on, c4, rm4, rp4);
   const int4* cd = ws_ptr<int4>(ws, lay.ctg) + b * net.K;
   const float4* lam = reinterpret_cast<const float4*>(net.lodf) + col;
   float2* cpart = ws_ptr<float2>(ws, lay.cpart) + ((size_t)b * lay.k5_tiles + tile) * net.K;
@@ -143,10 +157,10 @@ __global__ __launch_bounds__(256) void k5_outage_vjp(DevNet net, void* ws, WsLay
         const float cc = __int_as_float(d.y), rc = __int_as_float(d.w);
         const float4 x = on ? lam[(size_t)k * Lp4] : make_float4(0.f, 0.f, 0.f, 0.f);
         float pc = 0.0f, pr = 0.0f;
-        k5_elem(x.x, cc, rc, c4.x, r4.x, f4.x, chi, clo, gc[0], gr[0], pc, pr);
-        k5_elem(x.y, cc, rc, c4.y, r4.y, f4.y, chi, clo, gc[1], gr[1], pc, pr);
-        k5_elem(x.z, cc, rc, c4.z, r4.z, f4.z, chi, clo, gc[2], gr[2], pc, pr);
-        k5_elem(x.w, cc, rc, c4.w, r4.w, f4.w, chi, clo, gc[3], gr[3], pc, pr);
+        k5_elem(x.x, cc, rc, c4.x, rm4.x, rp4.x, chi, clo, gc[0], gr[0], pc, pr);
+        k5_elem(x.y, cc, rc, c4.y, rm4.y, rp4.y, chi, clo, gc[1], gr[1], pc, pr);
+        k5_elem(x.z, cc, rc, c4.z, rm4.z, rp4.z, chi, clo, gc[2], gr[2], pc, pr);
+        k5_elem(x.w, cc, rc, c4.w, rm4.w, rp4.w, chi, clo, gc[3], gr[3], pc, pr);
         v[2 * i] = pc;
         v[2 * i + 1] = pr;
       }
@@ -168,6 +182,86 @@ __global__ __launch_bounds__(256) void k5_outage_vjp(DevNet net, void* ws, WsLay
     float2* lp = ws_ptr<float2>(ws, lay.lpart) + ((size_t)b * lay.k5_by + blockIdx.y) * net.Lp + 4 * col;
 #pragma unroll
     for (int j = 0; j < 4; ++j) lp[j] = make_float2((float)gcl[j], (float)grl[j]);
+  }
+}
+
+// Many boxes: the outage sweep's VJP for 4 boxes x 256 lines per wave; the
+// four waves of a block take four box tiles of the same line tile, so each
+// outage-factor tile serves 16 boxes.  Per-outage sums of 4 outages x 4 boxes
+// x 2 fields go through one 32-value butterfly.
+constexpr int kBT5 = 4;
+
+__global__ __launch_bounds__(256) void k5b_outage_vjp(DevNet net, void* ws, WsLayout lay, int64_t n_box,
+                                                      const double* __restrict__ g_lo,
+                                                      const double* __restrict__ g_hi) {
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t b0 = ((int64_t)blockIdx.z * 4 + w) * kBT5;
+  if (b0 >= n_box) return;
+  const int tile = blockIdx.x;
+  const int col = tile * 64 + lane;
+  const int Lp4 = net.Lp / 4;
+  const bool on = col < Lp4;
+  const int k0 = blockIdx.y * kK5Chunk;
+  const int k1 = min(net.K, k0 + kK5Chunk);
+  int64_t bb[kBT5];
+  float chi[kBT5], clo[kBT5];
+  float4 c4[kBT5], rm4[kBT5], rp4[kBT5];
+  const int4* cd[kBT5];
+#pragma unroll
+  for (int i = 0; i < kBT5; ++i) {
+    bb[i] = min(b0 + i, n_box - 1);
+    chi[i] = (float)(-net.zeta_f * g_lo[bb[i]]);
+    clo[i] = (float)(-net.zeta_f * g_hi[bb[i]]);
+    line_radii(net, ws, lay, bb[i], col, on, c4[i], rm4[i], rp4[i]);
+    cd[i] = ws_ptr<int4>(ws, lay.ctg) + bb[i] * net.K;
+  }
+  const float4* lam = reinterpret_cast<const float4*>(net.lodf) + col;
+  float gc[kBT5][4], gr[kBT5][4];
+#pragma unroll
+  for (int i = 0; i < kBT5; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) gc[i][j] = gr[i][j] = 0.0f;
+  for (int ks = k0; ks < k1; ks += 4) {
+    float v[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) v[q] = 0.0f;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = ks + kk;
+      if (k < k1) {  // uniform
+        const float4 x = on ? lam[(size_t)k * Lp4] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int i = 0; i < kBT5; ++i) {
+          const int4 d = cd[i][k];
+          const float cc = __int_as_float(d.y), rc = __int_as_float(d.w);
+          float pc = 0.0f, pr = 0.0f;
+          k5_elem(x.x, cc, rc, c4[i].x, rm4[i].x, rp4[i].x, chi[i], clo[i], gc[i][0], gr[i][0], pc, pr);
+          k5_elem(x.y, cc, rc, c4[i].y, rm4[i].y, rp4[i].y, chi[i], clo[i], gc[i][1], gr[i][1], pc, pr);
+          k5_elem(x.z, cc, rc, c4[i].z, rm4[i].z, rp4[i].z, chi[i], clo[i], gc[i][2], gr[i][2], pc, pr);
+          k5_elem(x.w, cc, rc, c4[i].w, rm4[i].w, rp4[i].w, chi[i], clo[i], gc[i][3], gr[i][3], pc, pr);
+          v[(kk * kBT5 + i) * 2] = pc;
+          v[(kk * kBT5 + i) * 2 + 1] = pr;
+        }
+      }
+    }
+    const float tot = butterfly32(v);
+    const int idx = lane >> 1;  // (outage ks + idx / 8, box idx / 2 % 4, field idx % 2)
+    const int k = ks + (idx >> 3);
+    const int i = (idx >> 1) & 3;
+    if ((lane & 1) == 0 && k < k1 && b0 + i < n_box) {
+      float2* cp = ws_ptr<float2>(ws, lay.cpart) + ((size_t)(b0 + i) * lay.k5_tiles + tile) * net.K + k;
+      reinterpret_cast<float*>(cp)[idx & 1] = tot;
+    }
+  }
+  if (on) {
+#pragma unroll
+    for (int i = 0; i < kBT5; ++i) {
+      if (b0 + i >= n_box) break;
+      float2* lp = ws_ptr<float2>(ws, lay.lpart) + ((size_t)(b0 + i) * lay.k5_by + blockIdx.y) * net.Lp + 4 * col;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) lp[j] = make_float2(gc[i][j], gr[i][j]);
+    }
   }
 }
 
@@ -254,6 +348,82 @@ __global__ __launch_bounds__(256) void k6_ptdf_t(DevNet net, void* ws, WsLayout 
   }
 }
 
+// Many boxes: d c_inj[b, n] = sum_l dC[b, l] Phi[l, n] and d r_inj[b, n] =
+// sum_l dR[b, l] |Phi[l, n]| as one tiled product over lines.  Tile 64 boxes
+// x 64 buses, 32 lines per step staged in LDS; each thread owns a 4 x 4
+// micro-tile of both products (float32 accumulation).
+constexpr int kGB = 64, kGN = 64, kGK = 32;
+
+__global__ __launch_bounds__(256) void k6b_ptdf_t_tiled(DevNet net, void* ws, WsLayout lay, int64_t n_box) {
+  __shared__ float Ac[kGK][kGB + 4];
+  __shared__ float Ar[kGK][kGB + 4];
+  __shared__ float Bp[kGK][kGN + 4];
+  const int64_t b0 = (int64_t)blockIdx.y * kGB;
+  const int n0 = blockIdx.x * kGN;
+  const int t = threadIdx.x;
+  const int tm = t / 16, tn = t % 16;  // micro-tile row (boxes) and column (buses)
+  const float* gc = ws_ptr<float>(ws, lay.gcf);
+  const float* gr = ws_ptr<float>(ws, lay.grf);
+  float acc_c[4][4], acc_r[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc_c[i][j] = acc_r[i][j] = 0.0f;
+  // loader mapping: 64 rows x 32 lines = 512 float4 per operand -> 2 per thread
+  for (int l0 = 0; l0 < net.Lp; l0 += kGK) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int idx = t + q * 256;      // 0..511
+      const int row = idx / 8;          // 0..63
+      const int c4 = (idx % 8) * 4;     // line offset within the step
+      const int64_t b = b0 + row;
+      float4 vc = make_float4(0.f, 0.f, 0.f, 0.f), vr = vc, vp = vc;
+      if (b < n_box) {
+        vc = *reinterpret_cast<const float4*>(gc + b * net.Lp + l0 + c4);
+        vr = *reinterpret_cast<const float4*>(gr + b * net.Lp + l0 + c4);
+      }
+      const int n = n0 + row;
+      if (n < net.N) vp = *reinterpret_cast<const float4*>(net.phiT + (size_t)n * net.Lp + l0 + c4);
+      Ac[c4 + 0][row] = vc.x; Ac[c4 + 1][row] = vc.y; Ac[c4 + 2][row] = vc.z; Ac[c4 + 3][row] = vc.w;
+      Ar[c4 + 0][row] = vr.x; Ar[c4 + 1][row] = vr.y; Ar[c4 + 2][row] = vr.z; Ar[c4 + 3][row] = vr.w;
+      Bp[c4 + 0][row] = vp.x; Bp[c4 + 1][row] = vp.y; Bp[c4 + 2][row] = vp.z; Bp[c4 + 3][row] = vp.w;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int k = 0; k < kGK; ++k) {
+      float ac[4], ar[4], bp[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        ac[i] = Ac[k][tm * 4 + i];
+        ar[i] = Ar[k][tm * 4 + i];
+        bp[i] = Bp[k][tn * 4 + i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          acc_c[i][j] = fmaf(ac[i], bp[j], acc_c[i][j]);
+          acc_r[i][j] = fmaf(ar[i], fabsf(bp[j]), acc_r[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+  double* gci = ws_ptr<double>(ws, lay.gci);
+  double* gri = ws_ptr<double>(ws, lay.gri);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t b = b0 + tm * 4 + i;
+    if (b >= n_box) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + tn * 4 + j;
+      if (n >= net.Np) continue;
+      gci[b * net.Np + n] = n < net.N ? (double)acc_c[i][j] : 0.0;
+      gri[b * net.Np + n] = n < net.N ? (double)acc_r[i][j] : 0.0;
+    }
+  }
+}
+
 // Per input: endpoint gradients (injection, surplus and imbalance terms).
 __global__ __launch_bounds__(256) void k7_endpoints(DevNet net, void* ws, WsLayout lay, int64_t box0,
                                                     const double* __restrict__ g_lo,
@@ -299,17 +469,36 @@ void plan_backward(const DevNet& net, WsLayout& lay) {
 hipError_t launch_backward_sweeps(const DevNet& net, int64_t n_box, void* ws, const WsLayout& lay,
                                   const double* g_lo, const double* g_hi, double* d_lo, double* d_hi,
                                   hipStream_t s, KernelTimer* tm) {
+  if (n_box >= kBatchMin && lay.batched && net.K > 0) {
+    const int t = tm->start(7, s);
+    const unsigned groups = (unsigned)(((n_box + kBT5 - 1) / kBT5 + 3) / 4);
+    hipLaunchKernelGGL(k5b_outage_vjp, dim3(lay.k5_tiles, lay.k5_by, groups), dim3(256), 0, s, net, ws, lay, n_box,
+                       g_lo, g_hi);
+    tm->stop(t, s);
+  }
   for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
     const int nb = (int)std::min<int64_t>(65535, n_box - b0);
-    int t = tm->start(7, s);
-    if (net.K > 0)
+    const int t = tm->start(7, s);
+    if (net.K > 0 && !(n_box >= kBatchMin && lay.batched))
       hipLaunchKernelGGL(k5_outage_vjp, dim3((lay.k5_tiles + 3) / 4, lay.k5_by, nb), dim3(256), 0, s, net, ws,
                          lay, b0, g_lo, g_hi);
     hipLaunchKernelGGL(k5r_lines, dim3((net.Lp + 255) / 256, nb), dim3(256), 0, s, net, ws, lay, b0, g_lo, g_hi);
     tm->stop(t, s);
-    t = tm->start(8, s);
-    hipLaunchKernelGGL(k6_ptdf_t, dim3((net.Np + 7) / 8, nb), dim3(256), 0, s, net, ws, lay, b0);
+  }
+  if (n_box >= kBatchMin) {
+    const int t = tm->start(8, s);
+    hipLaunchKernelGGL(k6b_ptdf_t_tiled, dim3((net.Np + kGN - 1) / kGN, (unsigned)((n_box + kGB - 1) / kGB)),
+                       dim3(256), 0, s, net, ws, lay, n_box);
     tm->stop(t, s);
+  }
+  for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
+    const int nb = (int)std::min<int64_t>(65535, n_box - b0);
+    int t;
+    if (n_box < kBatchMin) {
+      t = tm->start(8, s);
+      hipLaunchKernelGGL(k6_ptdf_t, dim3((net.Np + 7) / 8, nb), dim3(256), 0, s, net, ws, lay, b0);
+      tm->stop(t, s);
+    }
     t = tm->start(9, s);
     hipLaunchKernelGGL(k7_endpoints, dim3((net.X + 255) / 256, nb), dim3(256), 0, s, net, ws, lay, b0, g_lo, g_hi,
                        d_lo, d_hi);
