@@ -203,7 +203,8 @@ ibp_status ibp_autotune(ibp_network* net, int64_t n_box, const float* box_lo, co
  *     float32 strictly inside any coordinate is duplicated.
  *   (the caller bounds the children and the zero-width centre boxes)
  *   ibp_split_update: writes the children's f_hi into leaf_fhi, sets
- *     root_ub[r] = max leaf f_hi and root_lb[r] = max(root_lb[r], centre f_lo)
+ *     root_ub[r] = min(root_ub[r], max leaf f_hi) and
+ *     root_lb[r] = max(root_lb[r], centre f_lo)
  *     (device float64 [n_root]); n_used_after = n_used + 1.
  * All asynchronous on `stream`; host-checkable errors: INVALID_ARG. */
 ibp_status ibp_split_select(int64_t n_root, int32_t slots, int32_t n_used, int32_t n_input,

@@ -519,6 +519,7 @@ ibp_status ibp_split_select(int64_t n_root, int32_t slots, int32_t n_used, int32
   if (n_root == 0) return IBP_OK;
   if (!leaf_lo || !leaf_hi || !leaf_fhi || !sel || !sel_lo || !sel_hi)
     return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
+  if (n_root > 0x7fffffff) return fail(IBP_E_INVALID_ARG, "too many roots");
   hipError_t e = ibp::launch_split_select(n_root, slots, n_used, n_input, leaf_lo, leaf_hi, leaf_fhi, sel, sel_lo,
                                           sel_hi, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? IBP_OK : fail(IBP_E_DEVICE, hipGetErrorString(e));

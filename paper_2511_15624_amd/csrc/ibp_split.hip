@@ -20,24 +20,36 @@
 
 namespace ibp {
 
-// One thread per root: leaf with the largest f_hi among the used slots.
-// Copies it to sel_lo/sel_hi (row r).
-__global__ void split_select(int64_t R, int S, int n_used, int X, const float* __restrict__ leaf_lo,
-                             const float* __restrict__ leaf_hi, const double* __restrict__ leaf_fhi,
-                             int64_t* __restrict__ sel, float* __restrict__ sel_lo, float* __restrict__ sel_hi) {
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (r >= R) return;
-  int64_t best = r * S;
-  double bv = leaf_fhi[best];
-  for (int q = 1; q < n_used; ++q) {
+// One wave per root: leaf with the largest f_hi among the used slots (ties to
+// the lowest slot; a NaN leaf only wins when every leaf is NaN, then slot 0).
+// The lanes then copy it to sel_lo/sel_hi (row r), coalesced.
+__global__ __launch_bounds__(64) void split_select(int64_t R, int S, int n_used, int X,
+                                                   const float* __restrict__ leaf_lo,
+                                                   const float* __restrict__ leaf_hi,
+                                                   const double* __restrict__ leaf_fhi, int64_t* __restrict__ sel,
+                                                   float* __restrict__ sel_lo, float* __restrict__ sel_hi) {
+  const int64_t r = blockIdx.x;
+  const int lane = threadIdx.x;
+  double bv = -INFINITY;
+  int bq = -1;
+  for (int q = lane; q < n_used; q += 64) {
     const double v = leaf_fhi[r * S + q];
-    if (v > bv || !(bv == bv)) {  // largest f_hi; a NaN leaf only wins when nothing else does
+    if (v == v && (bq < 0 || v > bv)) {
       bv = v;
-      best = r * S + q;
+      bq = q;
     }
   }
-  sel[r] = best;
-  for (int j = 0; j < X; ++j) {
+  for (int m = 32; m >= 1; m >>= 1) {
+    const double ov = __shfl_xor(bv, m, 64);
+    const int oq = __shfl_xor(bq, m, 64);
+    if (oq >= 0 && (bq < 0 || ov > bv || (ov == bv && oq < bq))) {
+      bv = ov;
+      bq = oq;
+    }
+  }
+  const int64_t best = r * S + (bq < 0 ? 0 : bq);
+  if (lane == 0) sel[r] = best;
+  for (int j = lane; j < X; j += 64) {
     sel_lo[r * X + j] = leaf_lo[best * X + j];
     sel_hi[r * X + j] = leaf_hi[best * X + j];
   }
@@ -106,7 +118,8 @@ __global__ __launch_bounds__(64) void split_bisect(int64_t R, int S, int n_used,
 }
 
 // One thread per root: scatter the children's f_hi, refresh the root's upper
-// bound (largest leaf f_hi) and lower bound (largest certified centre value).
+// bound (the smaller of its previous value and the largest leaf f_hi) and
+// lower bound (largest certified centre value).
 __global__ void split_update(int64_t R, int S, int n_used_after, const int64_t* __restrict__ sel,
                              const double* __restrict__ kid_fhi, const double* __restrict__ cen_flo,
                              double* __restrict__ leaf_fhi, double* __restrict__ root_ub,
@@ -117,14 +130,14 @@ __global__ void split_update(int64_t R, int S, int n_used_after, const int64_t* 
   leaf_fhi[r * S + n_used_after - 1] = kid_fhi[2 * r + 1];
   double ub = -INFINITY;
   for (int q = 0; q < n_used_after; ++q) ub = fmax(ub, leaf_fhi[r * S + q]);
-  root_ub[r] = ub;
+  root_ub[r] = fmin(root_ub[r], ub);  // both bound max f over the root; keep the smaller
   root_lb[r] = fmax(root_lb[r], fmax(cen_flo[2 * r], cen_flo[2 * r + 1]));
 }
 
 hipError_t launch_split_select(int64_t R, int S, int n_used, int X, const float* leaf_lo, const float* leaf_hi,
                                const double* leaf_fhi, int64_t* sel, float* sel_lo, float* sel_hi, hipStream_t s) {
-  hipLaunchKernelGGL(split_select, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, R, S, n_used, X, leaf_lo,
-                     leaf_hi, leaf_fhi, sel, sel_lo, sel_hi);
+  hipLaunchKernelGGL(split_select, dim3((unsigned)R), dim3(64), 0, s, R, S, n_used, X, leaf_lo, leaf_hi, leaf_fhi,
+                     sel, sel_lo, sel_hi);
   return hipGetLastError();
 }
 

@@ -12,8 +12,9 @@ Each root box keeps up to ``rounds + 1`` leaves that partition it.  One round
    the largest (d f_hi/d hi_j - d f_hi/d lo_j) * r_j;
 4. ``ibp_bound_boxes`` on the two children, and on their centre points as
    zero-width boxes (f_lo there is a certified value of f at a feasible point);
-5. ``ibp_split_update``: root upper bound = largest leaf f_hi, root lower bound
-   on max f = largest certified centre value.
+5. ``ibp_split_update``: root upper bound = the smaller of its previous value
+   and the largest leaf f_hi, root lower bound on max f = largest certified
+   centre value.
 
 The gap UB - LB of every root can only shrink.  The state (leaves, bounds,
 round counter) can be saved with ``state_dict`` and restored with

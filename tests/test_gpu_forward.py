@@ -266,3 +266,24 @@ def test_tile_choices_give_enclosing_bounds():
     assert nc in (32, 64, 128, 256) and kc in (16, 32, 64, 128)
     f_lo, f_hi = gpu_bounds(n, lo, hi)
     assert_encloses(f_lo[0], f_hi[0], r, what="autotuned", strict_f=True)
+
+
+def test_distinct_contingency_limits():
+    """Post-outage limits different from the base limits (per-line factors in
+    [0.5, 1.5]): single-box, box-tiled and plain forms all enclose the oracle."""
+    from tests.test_oracle_pins import _emergency
+    net = _emergency(synth.make_config("c500"), 4)
+    fac = oracle.factors(net)
+    n = ibp.Network(net, device=0)
+    lo, hi = synth.full_box(net)
+    blo, bhi = synth.sub_boxes(net, 7, seed=31)
+    r = orc(net, lo, hi, fac)
+    f_lo, f_hi, t = gpu_bounds(n, lo, hi, terms=True)
+    assert_encloses(f_lo[0], f_hi[0], r, what="full box", strict_f=True)
+    assert_terms_enclose(t[0], r)
+    refs = [orc(net, blo[b], bhi[b], fac) for b in range(7)]
+    for flags in (0, ibp.IBP_F_PLAIN):
+        f_lo, f_hi, t = gpu_bounds(n, blo, bhi, terms=True, flags=flags)
+        for b in range(7):
+            assert_encloses(f_lo[b], f_hi[b], refs[b], what=f"box {b} flags {flags}")
+            assert_terms_enclose(t[b], refs[b])

@@ -381,6 +381,42 @@ def test_orientation_and_relabelling_invariance(tiny):
     assert r["f_hi"] == pytest.approx(ref["f_hi"], rel=1e-11)
 
 
+def _emergency(net, seed, lo=0.5, hi=1.5):
+    """The same network with post-outage limits that differ from the base limits
+    (separate symbols in the contingency constraints, Sec. II-B)."""
+    rng = np.random.default_rng(seed)
+    f = np.asarray(net["fmax_base"], float)
+    return dict(net, fmax_ctg=f * rng.uniform(lo, hi, f.size))
+
+
+def test_distinct_contingency_limits(tiny):
+    """P5 and P7 with fmax_ctg != fmax_base: point values from direct outage solves
+    (which read the contingency limits on their own) match at zero width and stay
+    inside the bounds; bounds that used the base limits after an outage would not."""
+    net0, fac = tiny
+    net = _emergency(net0, 3)
+    lo, hi = synth.full_box(net)
+    rng = np.random.default_rng(9)
+    X = (lo + rng.random((6, lo.size)) * (hi.astype(float) - lo)).astype(np.float32)
+    moved = 0
+    for x in X:
+        fx = oracle.point_eval(net, x.astype(float), fac["ctg"])
+        r = oracle.ibp(net, x, x, fac)
+        assert r["f_lo"] == pytest.approx(fx, rel=1e-9, abs=1e-9)
+        wrong = oracle.ibp(net0, x, x, fac)        # base limits reused after outages
+        moved += not math.isclose(wrong["f_lo"], fx, rel_tol=1e-9, abs_tol=1e-9)
+    assert moved >= 3
+    blo, bhi = synth.sub_boxes(net, 2, seed=12)
+    for a, b in [(lo, hi)] + list(zip(blo, bhi)):
+        r = oracle.ibp(net, a, b, fac)
+        span = b.astype(float) - a
+        pts = a[None, :] + rng.random((3000, a.size)) * span[None, :]
+        fv = oracle.point_eval_many(net, pts, fac["ctg"])
+        tol = 1e-9 * max(1.0, abs(r["f_lo"]), abs(r["f_hi"]))
+        assert fv.min() >= r["f_lo"] - tol and fv.max() <= r["f_hi"] + tol
+    assert r["f_hi"] >= _lp_max(net, blo[-1].astype(float), bhi[-1].astype(float), fac) - 1e-6
+
+
 # ---------------------------------------------------------------- P11: gradient
 
 def test_gradient_matches_central_differences(tiny):
