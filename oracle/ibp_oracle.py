@@ -28,8 +28,13 @@ DCOPF via Interval Bound Propagation", Tekeler, Chevalier, Zhong, Zhang):
   linear costs, and its IBP enclosure over the box of eq. (f-ibp), using the
   centre-radius rule of Sec. III-C eq. (IBP) for every affine node and the
   tight interval absolute value for |.| (readings listed below).
+* Optional piecewise-linear cost (generators) and value (loads) curves of
+  Sec. III-B, eqs. (single ReLU) and (combined ReLUs): F*_0 = 0,
+  F*_i(x) = min(F*_{i-1}(x) + a_i ReLU(x - b_i), U_i); the surplus adds
+  F* of every load and subtracts F* of every generator, beside the linear
+  terms.  IBP takes the curve node by node.
 
-Readings taken where the paper is silent (each one is listed in the design doc):
+Readings taken where the paper is silent:
 
 * Slack bus: an explicit parameter (``slack_bus``); row/column removed from
   the reduced matrices.
@@ -44,7 +49,8 @@ Readings taken where the paper is silent (each one is listed in the design doc):
 * Islanding outages (1 - H_cc = 0) are excluded; the default contingency set
   is every line whose removal leaves the network connected, ascending.
 * Reductions: numpy pairwise sums per chunk, combined with math.fsum.
-* Gradient: sign(0) = 0; max(z, 0) is active iff z > 0.
+* Gradient: sign(0) = 0; max(z, 0) is active iff z > 0; min(x, U) passes the
+  gradient to x iff x <= U (min(x, U) = x - max(x - U, 0)).
 
 Parity pins live in tests/test_oracle_*.py.
 """
@@ -70,6 +76,8 @@ __all__ = [
     "point_eval",
     "point_eval_many",
     "center_radius",
+    "curve_value",
+    "curve_interval",
 ]
 
 
@@ -257,6 +265,93 @@ def _imbalance_matrix(net) -> sp.csr_matrix:
     return sp.csr_matrix((-np.ones(N), (np.full(N, s), np.arange(N))), shape=(N, N))
 
 
+# ----------------------------------------------------------------------------
+# piecewise-linear curves (Sec. III-B, eqs. (single ReLU) and (combined ReLUs))
+# ----------------------------------------------------------------------------
+
+def _curves(net):
+    """Segment lists per input as (ptr, a, b, U), or None for linear costs only."""
+    ptr = net.get("seg_ptr")
+    if ptr is None:
+        return None
+    return (np.asarray(ptr, dtype=np.int64), np.asarray(net["seg_a"], float),
+            np.asarray(net["seg_b"], float), np.asarray(net["seg_U"], float))
+
+
+def curve_value(a, b, U, x):
+    """F*(x) at points x (scalar or array): F*_0 = 0 and
+    F*_i = min(F*_{i-1} + a_i ReLU(x - b_i), U_i) for i = 1..n."""
+    F = np.zeros_like(np.asarray(x, dtype=np.float64))
+    for ai, bi, Ui in zip(a, b, U):
+        F = np.minimum(F + ai * np.maximum(x - bi, 0.0), Ui)
+    return F
+
+
+def curve_interval(a, b, U, c, r):
+    """IBP of F* over [c - r, c + r], node by node: the affine node a_i (x - b_i)
+    by eq. (IBP) (centre a_i (c - b_i), radius |a_i| r), then the ReLU and the
+    min with U_i (monotone, so applied to both ends), and the sum with the
+    running interval of F*_{i-1}."""
+    lo = hi = 0.0
+    for ai, bi, Ui in zip(a, b, U):
+        cy = ai * (c - bi)
+        ry = abs(ai) * r
+        lo = min(lo + max(cy - ry, 0.0), Ui)
+        hi = min(hi + max(cy + ry, 0.0), Ui)
+    return lo, hi
+
+
+def _curve_vjp(a, b, U, c, r, d_lo, d_hi):
+    """Adjoint of (c, r) for the upstream adjoints (d_lo, d_hi) of curve_interval's
+    output; returns (dc, dr, near-kink count)."""
+    n = len(a)
+    cys, rys, plo, phi = [], [], [], []
+    lo = hi = 0.0
+    for ai, bi, Ui in zip(a, b, U):
+        cy = ai * (c - bi)
+        ry = abs(ai) * r
+        cys.append(cy)
+        rys.append(ry)
+        plo.append(lo + max(cy - ry, 0.0))
+        phi.append(hi + max(cy + ry, 0.0))
+        lo = min(plo[-1], Ui)
+        hi = min(phi[-1], Ui)
+    dc = dr = 0.0
+    near = 0
+    for i in range(n - 1, -1, -1):
+        Ui = U[i]
+        d_lo = d_lo if plo[i] <= Ui else 0.0
+        d_hi = d_hi if phi[i] <= Ui else 0.0
+        near += (abs(plo[i] - Ui) < 1e-9) + (abs(phi[i] - Ui) < 1e-9)
+        zl, zh = cys[i] - rys[i], cys[i] + rys[i]
+        near += (abs(zl) < 1e-9) + (abs(zh) < 1e-9)
+        dcy = (d_lo if zl > 0 else 0.0) + (d_hi if zh > 0 else 0.0)
+        dry = -(d_lo if zl > 0 else 0.0) + (d_hi if zh > 0 else 0.0)
+        dc += a[i] * dcy
+        dr += abs(a[i]) * dry
+    return dc, dr, near
+
+
+def _curve_surplus(net, mu, sg):
+    """[lo, hi] of sum over loads of F*_d minus sum over generators of F*_g."""
+    cv = _curves(net)
+    if cv is None:
+        return 0.0, 0.0
+    ptr, A, B, U = cv
+    G = np.asarray(net["gen_bus"]).size
+    los, his = [], []
+    for j in range(mu.size):
+        s0, s1 = ptr[j], ptr[j + 1]
+        if s1 == s0:
+            continue
+        l, h = curve_interval(A[s0:s1], B[s0:s1], U[s0:s1], mu[j], sg[j])
+        if j < G:
+            l, h = -h, -l
+        los.append(l)
+        his.append(h)
+    return math.fsum(los), math.fsum(his)
+
+
 def ibp(net, lo, hi, fac=None, chunk: int = 256, keep_intermediates: bool = False) -> dict:
     """IBP bounds [f_lo, f_hi] of f_ibp over the box [lo, hi] (inputs: gens then loads).
 
@@ -311,7 +406,8 @@ def ibp(net, lo, hi, fac=None, chunk: int = 256, keep_intermediates: bool = Fals
     Fc_lo, Fc_hi = math.fsum(parts_lo), math.fsum(parts_hi)
 
     zi, zf = float(net["zeta_inj"]), float(net["zeta_f"])
-    S_lo, S_hi = S_c - S_r, S_c + S_r
+    P_lo, P_hi = _curve_surplus(net, mu, sg)
+    S_lo, S_hi = (S_c - S_r) + P_lo, (S_c + S_r) + P_hi
     f_hi = S_hi - zi * I_lo - zf * (Fb_lo + Fc_lo)
     f_lo = S_lo - zi * I_hi - zf * (Fb_hi + Fc_hi)
     out = dict(f_lo=f_lo, f_hi=f_hi, S_lo=S_lo, S_hi=S_hi, I_lo=I_lo, I_hi=I_hi,
@@ -378,6 +474,20 @@ def grad(net, lo, hi, g_lo: float = 1.0, g_hi: float = 0.0, fac=None, chunk: int
     w = np.concatenate([-np.asarray(net["gen_cost"], float), np.asarray(net["load_value"], float)])
     d_mu = (g_lo + g_hi) * w
     d_sg = (g_hi - g_lo) * np.abs(w)
+    cv = _curves(net)
+    if cv is not None:
+        # loads add [F_lo, F_hi] to [S_lo, S_hi]; generators subtract [F_hi, F_lo]
+        ptr, A, B, Uc = cv
+        G = np.asarray(net["gen_bus"]).size
+        for j in range(mu.size):
+            s0, s1 = ptr[j], ptr[j + 1]
+            if s1 == s0:
+                continue
+            a_lo, a_hi = (-g_hi, -g_lo) if j < G else (g_lo, g_hi)
+            dc, dr, nk = _curve_vjp(A[s0:s1], B[s0:s1], Uc[s0:s1], mu[j], sg[j], a_lo, a_hi)
+            d_mu[j] += dc
+            d_sg[j] += dr
+            near += nk
     d_cinj = np.zeros_like(c_inj)
     d_rinj = np.zeros_like(r_inj)
 
@@ -482,8 +592,16 @@ def point_eval_many(net, X, ctg=None) -> np.ndarray:
         pfc = YDc @ (E @ th)
         s_fc += np.sum(np.maximum(np.abs(pfc) - fc, 0.0), axis=0)
     w = np.concatenate([-np.asarray(net["gen_cost"], float), np.asarray(net["load_value"], float)])
+    surplus = X @ w
+    cv = _curves(net)
+    if cv is not None:
+        ptr, A, B, U = cv
+        for j in range(X.shape[1]):
+            s0, s1 = ptr[j], ptr[j + 1]
+            F = curve_value(A[s0:s1], B[s0:s1], U[s0:s1], X[:, j])
+            surplus = surplus - F if j < G else surplus + F
     zi, zf = float(net["zeta_inj"]), float(net["zeta_f"])
-    return X @ w - zi * s_inj.sum(0) - zf * (s_fb.sum(0) + s_fc)
+    return surplus - zi * s_inj.sum(0) - zf * (s_fb.sum(0) + s_fc)
 
 
 def point_eval(net, x, ctg=None) -> float:

@@ -17,6 +17,15 @@ uniform buses with ``peak ~ U[0.2, 1.0]``, ``[dmin, dmax] = [0.6, 1.0] * peak``
 and value ``~ U[60, 120]``.  Slack bus 0, penalty weights 1e3 (imbalance) and
 5e2 (flow overload), as in the soft-constraint objective of Sec. II-D.
 
+Piecewise-linear cost and value curves (``with_pwl_costs``; the curve form of
+Sec. III-B): every device gets 1 to ``max_seg`` segments that split
+``[0, pmax]`` (generators) or ``[0, dmax]`` (loads) at sorted uniform points.
+Generator segment prices are sorted ``U[10, 50]`` draws, ascending (a convex
+cost); load segment values are sorted ``U[60, 120]`` draws, descending (a
+concave value).  Segment i is stored as slope ``a_i``, shift ``b_i`` (its
+start) and cap ``U_i`` (the curve's value at its end); the linear weights are
+set to zero so the curves carry the whole surplus.
+
 Box endpoints are float32 by design: they are rounded outward to float32 and
 those float32 values *are* the box that both the oracle and the kernels bound.
 """
@@ -38,6 +47,7 @@ __all__ = [
     "find_bridges",
     "round_down_f32",
     "round_up_f32",
+    "with_pwl_costs",
 ]
 
 # name -> (n_bus, n_line, n_gen, n_load, n_ctg or None, network seed)
@@ -271,3 +281,38 @@ def period_boxes(net: dict, n_period: int, boxes_per_period: int, seed: int):
         his.append(bhi)
         idx.append(np.full(boxes_per_period, t, dtype=np.int32))
     return np.concatenate(los), np.concatenate(his), np.concatenate(idx)
+
+
+def with_pwl_costs(net: dict, seed: int, max_seg: int = 4) -> dict:
+    """A copy of ``net`` whose surplus comes from piecewise-linear curves.
+
+    Adds ``seg_ptr`` (int32 [X + 1], segments of input j are
+    ``seg_ptr[j]:seg_ptr[j + 1]``), ``seg_a``, ``seg_b``, ``seg_U`` (float64);
+    ``gen_cost`` and ``load_value`` become zero.
+    """
+    rng = np.random.default_rng(seed)
+    caps = np.concatenate([net["gen_pmax"], net["load_dmax"]])
+    G = np.asarray(net["gen_bus"]).size
+    ptr = [0]
+    A, B, U = [], [], []
+    for j, cap in enumerate(caps):
+        n = int(rng.integers(1, max_seg + 1))
+        cuts = np.sort(rng.uniform(0.0, cap, n - 1))
+        starts = np.concatenate([[0.0], cuts])
+        ends = np.concatenate([cuts, [cap]])
+        if j < G:
+            price = np.sort(rng.uniform(10.0, 50.0, n))
+        else:
+            price = np.sort(rng.uniform(60.0, 120.0, n))[::-1]
+        A.extend(price)
+        B.extend(starts)
+        U.extend(np.cumsum(price * (ends - starts)))
+        ptr.append(ptr[-1] + n)
+    out = dict(net)
+    out["gen_cost"] = np.zeros(G)
+    out["load_value"] = np.zeros(caps.size - G)
+    out["seg_ptr"] = np.asarray(ptr, dtype=np.int32)
+    out["seg_a"] = np.asarray(A, dtype=np.float64)
+    out["seg_b"] = np.asarray(B, dtype=np.float64)
+    out["seg_U"] = np.asarray(U, dtype=np.float64)
+    return out

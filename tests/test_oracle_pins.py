@@ -230,8 +230,13 @@ def _lp_max(net, lo, hi, fac):
     n_s = sum(B.shape[0] for B, _ in blocks)
     w = np.concatenate([-np.asarray(net["gen_cost"], float), np.asarray(net["load_value"], float)])
     zeta = [float(net["zeta_inj"])] * N + [float(net["zeta_f"])] * (n_s - N)
-    cost = np.concatenate([-w, zeta])
-    A = np.zeros((2 * n_s, X + n_s))
+    # piecewise-linear curves as epigraph (convex cost) / hypograph (concave
+    # value) variables t_j: one row per segment, the line through that segment
+    curves = net.get("seg_ptr") is not None
+    n_t = X if curves else 0
+    sign_t = np.where(np.arange(X) < G, -1.0, 1.0)
+    cost = np.concatenate([-w, zeta, -sign_t[:n_t]])
+    A = np.zeros((2 * n_s, X + n_s + n_t))
     bvec = np.zeros(2 * n_s)
     r0 = 0
     for B, lim in blocks:
@@ -241,7 +246,22 @@ def _lp_max(net, lo, hi, fac):
             A[off + r0:off + r0 + m, X + r0:X + r0 + m] = -np.eye(m)
             bvec[off + r0:off + r0 + m] = lim
         r0 += m
-    bounds = [(float(a), float(b)) for a, b in zip(lo, hi)] + [(0, None)] * n_s
+    if curves:
+        ptr, sa, sb, su = (np.asarray(net[k]) for k in ("seg_ptr", "seg_a", "seg_b", "seg_U"))
+        rows, rhs = [], []
+        for j in range(X):
+            start_val = 0.0
+            for i in range(ptr[j], ptr[j + 1]):
+                # load: t <= F(b_i) + a_i (x - b_i); generator: t >= the same
+                row = np.zeros(X + n_s + n_t)
+                row[j] = -sa[i] * sign_t[j]
+                row[X + n_s + j] = sign_t[j]
+                rows.append(row)
+                rhs.append(sign_t[j] * (start_val - sa[i] * sb[i]))
+                start_val = su[i]
+        A = np.vstack([A, np.asarray(rows)])
+        bvec = np.concatenate([bvec, rhs])
+    bounds = [(float(a), float(b)) for a, b in zip(lo, hi)] + [(0, None)] * n_s + [(None, None)] * n_t
     res = scipy.optimize.linprog(cost, A_ub=A, b_ub=bvec, bounds=bounds, method="highs")
     assert res.status == 0
     return -res.fun
