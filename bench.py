@@ -150,6 +150,33 @@ def extras(torch, ibp, synth, n4, net4):
                        "value": ev5 / (msb * 1e-3), "unit": "evals/s", "ms_backward": msb,
                        "ms_forward": msf, "plain_value": sub * n3.n_ctg * n3.n_line / (msbp * 1e-3),
                        "plain_sample": f"first {sub} boxes, per-box kernels"}
+    # piecewise-linear cost and value curves (1-4 segments per device) on the
+    # single large box and on the batched workload, beside the linear-cost runs
+    lo4, hi4 = synth.full_box(net4)
+    s4l, s4h = torch.from_numpy(lo4[None].copy()).cuda(), torch.from_numpy(hi4[None].copy()).cuda()
+    ws1 = ibp.Workspace(n4)
+    ms_lin = _time(torch, lambda: ibp.ibp_bound_boxes(n4, s4l, s4h, ws=ws1), 50)
+    n4c = ibp.Network(synth.with_pwl_costs(net4, seed=9), device=0)
+    ms_cur = _time(torch, lambda: ibp.ibp_bound_boxes(n4c, s4l, s4h, ws=ws1), 50)
+    n4c.set_kernel_timing(True)
+    n4c.kernel_times()
+    for _ in range(10):
+        ibp.ibp_bound_boxes(n4c, s4l, s4h, ws=ws1)
+    kt4 = n4c.kernel_times()
+    n4c.set_kernel_timing(False)
+    n4c.close()
+    n3c = ibp.Network(synth.with_pwl_costs(net3, seed=10), device=0)
+    ms3c = _time(torch, lambda: ibp.ibp_bound_boxes(n3c, tlo, thi, ws=ws), 3)
+    n3c.close()
+    ev1 = n4.n_ctg * n4.n_line
+    res["curves"] = {
+        "workload": "piecewise-linear cost/value curves, 1-4 segments per device: the large single box, "
+                    "and 18 periods x 1024 sub-boxes on the 2000-bus network",
+        "single_box_value": ev1 / (ms_cur * 1e-3), "unit": "evals/s", "single_box_ms": ms_cur,
+        "single_box_ms_linear_costs": ms_lin,
+        "single_box_box_prep_us": round(kt4["box_prep"][0] / kt4["box_prep"][1] * 1e3, 2),
+        "batched_value": ev / (ms3c * 1e-3), "batched_ms": ms3c, "batched_ms_linear_costs": ms,
+    }
     # splitting: 4096 roots, 10 rounds of gradient-ranked bisection
     from paper_2511_15624_amd.split import BoxSplitter
     sp = BoxSplitter(n3, t5l, t5h, rounds=10)

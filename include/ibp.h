@@ -11,7 +11,9 @@
  *     f_lo <= min_box f_ibp  and  f_hi >= max_box f_ibp,
  *
  * where f_ibp is the explicit graph of the Appendix, eq. (ibp_f):
- *   surplus  sum_j value_j p_d,j - sum_i cost_i p_g,i  (linear costs),
+ *   surplus  sum_j value_j p_d,j - sum_i cost_i p_g,i  (linear costs), plus
+ *            optional piecewise-linear curves sum_j F*_j(p_d,j) - sum_i F*_i(p_g,i)
+ *            in the ReLU form of Sec. III-B (see ibp_network_desc),
  *   minus zeta_inj * 1^T |(E^T Phi - I) p_inj|        (Sec. III-A, eq. slack-sinj),
  *   minus zeta_f * 1^T max(|Phi p_inj| - fmax_b, 0)    (eq. slack-sfb),
  *   minus zeta_f * sum over N-1 outages and lines of
@@ -79,6 +81,18 @@ typedef struct ibp_network_desc {
   int32_t n_ctg;            /* K; ignored when ctg_line is NULL */
   const int32_t* ctg_line;  /* [K] distinct non-islanding lines, or NULL for
                                every non-islanding line in ascending order */
+  /* Optional piecewise-linear cost (generators) and value (loads) curves of
+   * Sec. III-B, eqs. (single ReLU) and (combined ReLUs).  Input j (generators
+   * first, then loads) owns segments seg_ptr[j] .. seg_ptr[j+1]-1; its curve is
+   *   F*_0(x) = 0,  F*_i(x) = min(F*_{i-1}(x) + a_i max(x - b_i, 0), U_i),
+   * with slope a_i = seg_a[i], shift b_i = seg_b[i], cap U_i = seg_U[i].  The
+   * surplus adds F* of every load and subtracts F* of every generator, on top
+   * of the linear terms (set gen_cost / load_value to 0 for curves only).
+   * seg_ptr == NULL: linear costs only (the other three are then ignored). */
+  const int32_t* seg_ptr;   /* [G + D + 1], seg_ptr[0] = 0, non-decreasing */
+  const double* seg_a;      /* [seg_ptr[G + D]] finite */
+  const double* seg_b;      /* [seg_ptr[G + D]] finite */
+  const double* seg_U;      /* [seg_ptr[G + D]] finite or +infinity */
 } ibp_network_desc;
 
 typedef struct ibp_network ibp_network;

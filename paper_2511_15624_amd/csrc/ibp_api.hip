@@ -188,6 +188,18 @@ ibp_status to_device(ibp_network* net, int device) {
     if ((st = upload(net, dev.data(), dev.size(), &d.bus_dev)) != IBP_OK) return st;
     if ((st = upload(net, w.data(), w.size(), &d.dev_w)) != IBP_OK) return st;
   }
+  d.seg_ptr = nullptr;
+  d.seg = nullptr;
+  if (!h.seg_ptr.empty()) {
+    const size_t S = h.seg_a.size();
+    std::vector<double4> seg(S);
+    for (size_t i = 0; i < S; ++i) {
+      const double U = h.seg_U[i];
+      seg[i] = make_double4(h.seg_a[i], h.seg_b[i], U, std::isfinite(U) ? std::fabs(U) : 0.0);
+    }
+    if ((st = upload(net, h.seg_ptr.data(), h.seg_ptr.size(), &d.seg_ptr)) != IBP_OK) return st;
+    if ((st = upload(net, seg.data(), seg.size(), &d.seg)) != IBP_OK) return st;
+  }
   if (hipDeviceSynchronize() != hipSuccess) return fail(IBP_E_DEVICE, "device synchronize failed");
   // default tiles: the longest bus chunk that still gives the base-flow sweep
   // about six waves per CU, and short outage chunks (many waves in flight)
@@ -404,7 +416,8 @@ ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box, const float
   ibp::KernelTimer* tm = const_cast<ibp::KernelTimer*>(&net->timer);
   hipError_t e = ibp::launch_forward_prep(net->dn, n_box, box_lo, box_hi, ws, lay, s, tm);
   if (e == hipSuccess)
-    e = ibp::launch_backward_sweeps(net->dn, n_box, ws, lay, g_f_lo, g_f_hi, g_box_lo, g_box_hi, s, tm);
+    e = ibp::launch_backward_sweeps(net->dn, n_box, ws, lay, box_lo, box_hi, g_f_lo, g_f_hi, g_box_lo, g_box_hi,
+                                    s, tm);
   if (e != hipSuccess) return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
   return IBP_OK;
 }

@@ -426,6 +426,8 @@ __global__ __launch_bounds__(256) void k6b_ptdf_t_tiled(DevNet net, void* ws, Ws
 
 // Per input: endpoint gradients (injection, surplus and imbalance terms).
 __global__ __launch_bounds__(256) void k7_endpoints(DevNet net, void* ws, WsLayout lay, int64_t box0,
+                                                    const float* __restrict__ box_lo,
+                                                    const float* __restrict__ box_hi,
                                                     const double* __restrict__ g_lo,
                                                     const double* __restrict__ g_hi,
                                                     double* __restrict__ d_lo, double* __restrict__ d_hi) {
@@ -453,8 +455,20 @@ __global__ __launch_bounds__(256) void k7_endpoints(DevNet net, void* ws, WsLayo
   const double sj = j < net.G ? 1.0 : -1.0;
   const int n = net.dev_bus[j];
   const double wj = net.dev_w[j];
-  const double dc = sj * ws_ptr<double>(ws, lay.gci)[b * net.Np + n] + (gl + gh) * wj + sj * dcI;
-  const double dr = ws_ptr<double>(ws, lay.gri)[b * net.Np + n] + (gh - gl) * fabs(wj) + drI;
+  double dc = sj * ws_ptr<double>(ws, lay.gci)[b * net.Np + n] + (gl + gh) * wj + sj * dcI;
+  double dr = ws_ptr<double>(ws, lay.gri)[b * net.Np + n] + (gh - gl) * fabs(wj) + drI;
+  if (net.seg_ptr) {
+    const int s0 = net.seg_ptr[j], s1 = net.seg_ptr[j + 1];
+    if (s1 > s0) {
+      const double l = box_lo[b * net.X + j], h = box_hi[b * net.X + j];
+      double lc, lr, hc, hr;
+      curve_ibp_tangents(net.seg, s0, s1, 0.5 * (l + h), 0.5 * (h - l), lc, lr, hc, hr);
+      // S_lo gets F_lo of a load and -F_hi of a generator; S_hi the other ends
+      const double al = j < net.G ? -gh : gl, ah = j < net.G ? -gl : gh;
+      dc += al * lc + ah * hc;
+      dr += al * lr + ah * hr;
+    }
+  }
   const bool nanb = bad != 0.0;
   d_lo[b * net.X + j] = nanb ? NAN : 0.5 * (dc - dr);
   d_hi[b * net.X + j] = nanb ? NAN : 0.5 * (dc + dr);
@@ -467,7 +481,7 @@ void plan_backward(const DevNet& net, WsLayout& lay) {
 }
 
 hipError_t launch_backward_sweeps(const DevNet& net, int64_t n_box, void* ws, const WsLayout& lay,
-                                  const double* g_lo, const double* g_hi, double* d_lo, double* d_hi,
+                                  const float* box_lo, const float* box_hi, const double* g_lo, const double* g_hi, double* d_lo, double* d_hi,
                                   hipStream_t s, KernelTimer* tm) {
   if (n_box >= kBatchMin && lay.batched && net.K > 0) {
     const int t = tm->start(7, s);
@@ -500,8 +514,8 @@ hipError_t launch_backward_sweeps(const DevNet& net, int64_t n_box, void* ws, co
       tm->stop(t, s);
     }
     t = tm->start(9, s);
-    hipLaunchKernelGGL(k7_endpoints, dim3((net.X + 255) / 256, nb), dim3(256), 0, s, net, ws, lay, b0, g_lo, g_hi,
-                       d_lo, d_hi);
+    hipLaunchKernelGGL(k7_endpoints, dim3((net.X + 255) / 256, nb), dim3(256), 0, s, net, ws, lay, b0, box_lo,
+                       box_hi, g_lo, g_hi, d_lo, d_hi);
     tm->stop(t, s);
   }
   return hipGetLastError();

@@ -18,6 +18,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <limits>
 #include <cstring>
 #include <functional>
 #include <thread>
@@ -343,6 +344,33 @@ ibp_status build_host(const ibp_network_desc* d, HostNet& net, std::string& err)
   if (d->ctg_line && d->n_ctg < 0) {
     err = "n_ctg < 0";
     return IBP_E_INVALID_ARG;
+  }
+  if (d->seg_ptr) {
+    const int X = G + D;
+    if (d->seg_ptr[0] != 0) {
+      err = "seg_ptr[0] must be 0";
+      return IBP_E_INVALID_ARG;
+    }
+    for (int j = 0; j < X; ++j)
+      if (d->seg_ptr[j + 1] < d->seg_ptr[j]) {
+        err = "seg_ptr must be non-decreasing";
+        return IBP_E_INVALID_ARG;
+      }
+    const int S = d->seg_ptr[X];
+    if (S > 0 && (!d->seg_a || !d->seg_b || !d->seg_U)) {
+      err = "seg_a, seg_b and seg_U are required when curves have segments";
+      return IBP_E_INVALID_ARG;
+    }
+    for (int i = 0; i < S; ++i)
+      if (!std::isfinite(d->seg_a[i]) || !std::isfinite(d->seg_b[i]) || std::isnan(d->seg_U[i]) ||
+          d->seg_U[i] == -std::numeric_limits<double>::infinity()) {
+        err = "segment " + std::to_string(i) + ": slope and shift must be finite, cap finite or +inf";
+        return IBP_E_INVALID_ARG;
+      }
+    net.seg_ptr.assign(d->seg_ptr, d->seg_ptr + X + 1);
+    net.seg_a.assign(d->seg_a, d->seg_a + S);
+    net.seg_b.assign(d->seg_b, d->seg_b + S);
+    net.seg_U.assign(d->seg_U, d->seg_U + S);
   }
 
   net.N = N;

@@ -91,5 +91,76 @@ __device__ __forceinline__ void k3_pair(const float4& x0, const int4& d0, const 
 
 __device__ __forceinline__ float add_ru(float a, float b) { return next_up_f32(a + b); }
 
+// IBP of one piecewise-linear curve over x in [c - r, c + r] (Sec. III-B,
+// eqs. (single ReLU) and (combined ReLUs)): F*_0 = 0 and
+// F*_i = min(F*_{i-1} + a_i max(x - b_i, 0), U_i), node by node as in eq. (IBP):
+// the affine node has centre a_i (c - b_i) and radius |a_i| r, the ReLU and the
+// cap are monotone (applied to both ends), the sum adds the two intervals.
+// float64 round-to-nearest; err bounds the distance of both computed ends from
+// the exact ones: with T = sum |a_i| (|c| + |b_i| + r) and Um = max finite |U_i|,
+// every intermediate is below T + Um in magnitude and each segment adds at most
+// 4u |a_i| (|c| + |b_i| + r) + u (T + Um), so err <= (n + 4) u (T + Um).
+__device__ __forceinline__ void curve_ibp(const double4* __restrict__ seg, int s0, int s1, double c, double r,
+                                          double& lo, double& hi, double& err) {
+#pragma clang fp contract(off)
+  lo = 0.0;
+  hi = 0.0;
+  double T = 0.0, Um = 0.0;
+  for (int s = s0; s < s1; ++s) {
+    const double4 q = seg[s];
+    const double cy = q.x * (c - q.y);
+    const double ry = fabs(q.x) * r;
+    lo = fmin(lo + fmax(cy - ry, 0.0), q.z);
+    hi = fmin(hi + fmax(cy + ry, 0.0), q.z);
+    T += fabs(q.x) * (fabs(c) + fabs(q.y) + r);
+    Um = fmax(Um, q.w);
+  }
+  err = ((s1 - s0) + 5) * kU64 * 1.01 * (T + Um);
+}
+
+// Derivatives of the two ends of curve_ibp with respect to c and r (forward
+// mode): (lc, lr) of the lower end, (hc, hr) of the upper end.  max(z, 0)
+// passes the derivative iff z > 0; min(p, U) passes it iff p <= U.  No
+// multiply-add contraction, so that z = a (c - b) -+ |a| r is rounded as
+// written and an exact kink (z = 0, e.g. lo = b) is taken as such.
+__device__ __forceinline__ void curve_ibp_tangents(const double4* __restrict__ seg, int s0, int s1, double c,
+                                                   double r, double& lc, double& lr, double& hc, double& hr) {
+#pragma clang fp contract(off)
+  double lo = 0.0, hi = 0.0;
+  lc = lr = hc = hr = 0.0;
+  for (int s = s0; s < s1; ++s) {
+    const double4 q = seg[s];
+    const double cy = q.x * (c - q.y);
+    const double ry = fabs(q.x) * r;
+    const double zl = cy - ry, zh = cy + ry;
+    const double pl = lo + fmax(zl, 0.0), ph = hi + fmax(zh, 0.0);
+    double plc = lc, plr = lr, phc = hc, phr = hr;
+    if (zl > 0.0) {
+      plc += q.x;
+      plr -= fabs(q.x);
+    }
+    if (zh > 0.0) {
+      phc += q.x;
+      phr += fabs(q.x);
+    }
+    if (pl <= q.z) {
+      lo = pl;
+      lc = plc;
+      lr = plr;
+    } else {
+      lo = q.z;
+      lc = lr = 0.0;
+    }
+    if (ph <= q.z) {
+      hi = ph;
+      hc = phc;
+      hr = phr;
+    } else {
+      hi = q.z;
+      hc = hr = 0.0;
+    }
+  }
+}
+
 
 }  // namespace ibp

@@ -53,6 +53,8 @@ struct DevNet {
   const int* bus_ptr;       // [N + 1] CSR over buses of the devices on each bus
   const int* bus_dev;       // [X] device indices (0..G-1 generators, G..X-1 loads)
   const double* dev_w;      // [X] -cost for generators, +value for loads
+  const int* seg_ptr;       // [X + 1] curve segments of each input, or nullptr (linear costs only)
+  const double4* seg;       // [S] (slope a, shift b, cap U, |U| if finite else 0)
   double zeta_inj, zeta_f;
   double phi_err_max;
   double gamma64_n;         // float64 accumulation bound for one PTDF row

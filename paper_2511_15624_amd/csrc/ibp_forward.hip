@@ -89,6 +89,19 @@ __global__ __launch_bounds__(64) void k1_box_prep(DevNet net, const float* __res
     v[kP1cI] = (i < G) ? c : -c;
     v[kP1rI] = r;
     v[kP1cIabs] = fabs(c);
+    if (net.seg_ptr) {
+      // curve term: loads add [F_lo, F_hi], generators subtract it
+      const int s0 = net.seg_ptr[i], s1 = net.seg_ptr[i + 1];
+      if (s1 > s0) {
+        double F_lo, F_hi, e;
+        curve_ibp(net.seg, s0, s1, c, r, F_lo, F_hi, e);
+        const double sc = (i < G ? -0.5 : 0.5) * (F_lo + F_hi);
+        const double sr = 0.5 * (F_hi - F_lo) + e + 1.01 * kU64 * (fabs(F_lo) + fabs(F_hi));
+        v[kP1Sc] += sc;
+        v[kP1Sr] += sr;
+        v[kP1Sabs] += fabs(sc) + sr;
+      }
+    }
   }
 #pragma unroll
   for (int f = 0; f < kP1Fields; ++f) v[f] = wave_sum(v[f]);

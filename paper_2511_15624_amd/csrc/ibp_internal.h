@@ -21,6 +21,8 @@ struct HostNet {
   std::vector<int32_t> gen_bus, load_bus;
   std::vector<double> gen_cost, load_value;
   double zeta_inj = 0, zeta_f = 0;
+  std::vector<int32_t> seg_ptr;            // [X + 1], empty for linear costs only
+  std::vector<double> seg_a, seg_b, seg_U; // piecewise-linear curve segments
 
   std::vector<int32_t> ctg_line;     // [K] outaged line of each contingency
   std::vector<int32_t> ctg_of_line;  // [L] contingency index of a line, -1 if none

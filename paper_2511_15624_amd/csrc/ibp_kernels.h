@@ -66,8 +66,9 @@ hipError_t launch_forward_prep(const DevNet& net, int64_t n_box, const float* lo
 // Backward grid shapes, and the backward kernels after launch_forward_prep.
 void plan_backward(const DevNet& net, WsLayout& lay);
 hipError_t launch_backward_sweeps(const DevNet& net, int64_t n_box, void* ws, const WsLayout& lay,
-                                  const double* g_lo, const double* g_hi, double* d_lo, double* d_hi,
-                                  hipStream_t s, KernelTimer* tm);
+                                  const float* box_lo, const float* box_hi, const double* g_lo,
+                                  const double* g_hi, double* d_lo, double* d_hi, hipStream_t s,
+                                  KernelTimer* tm);
 
 // Box splitting rounds (see ibp_split.hip).
 hipError_t launch_split_select(int64_t R, int S, int n_used, int X, const float* leaf_lo, const float* leaf_hi,

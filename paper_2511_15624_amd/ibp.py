@@ -86,6 +86,10 @@ class NetworkDesc(ctypes.Structure):
         ("zeta_f", ctypes.c_double),
         ("n_ctg", ctypes.c_int32),
         ("ctg_line", ctypes.POINTER(ctypes.c_int32)),
+        ("seg_ptr", ctypes.POINTER(ctypes.c_int32)),
+        ("seg_a", ctypes.POINTER(ctypes.c_double)),
+        ("seg_b", ctypes.POINTER(ctypes.c_double)),
+        ("seg_U", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -205,6 +209,14 @@ class Network:
         else:
             d.n_ctg = 0
             d.ctg_line = ctypes.POINTER(ctypes.c_int32)()
+        if net.get("seg_ptr") is not None:
+            # piecewise-linear curves: the C side cannot see array lengths
+            sp_ = arr("seg_ptr", np.int32)
+            sa, sb, su = arr("seg_a", np.float64), arr("seg_b", np.float64), arr("seg_U", np.float64)
+            if sp_.size != gb.size + db.size + 1 or not (sa.size == sb.size == su.size == int(sp_[-1])):
+                raise IBPError(1, "seg_ptr needs G + D + 1 entries and seg_a/b/U seg_ptr[-1] each")
+            d.seg_ptr = _ptr(sp_, ctypes.c_int32)
+            d.seg_a, d.seg_b, d.seg_U = (_ptr(a, ctypes.c_double) for a in (sa, sb, su))
         h = ctypes.c_void_p()
         _check(lib.ibp_build_network(ctypes.byref(d), int(device), ctypes.byref(h)))
         self._h = h

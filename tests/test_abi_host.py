@@ -134,3 +134,25 @@ def test_split_calls_validate_sizes_before_any_device_work(lib):
     st = lib.ibp_split_update(4, 3, 4, None, None, None, None, None, None, None)
     assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"      # n_used_after > slots
     assert lib.ibp_split_select(0, 3, 1, 5, None, None, None, None, None, None, None) == 0
+
+
+def test_curve_descriptions_validated():
+    net = synth.with_pwl_costs(synth.make_config("tiny"), seed=5)
+    h = _host(net)                      # well-formed curves are accepted
+    h.close()
+    p = net["seg_ptr"].copy()
+    p[0] = 1
+    _expect("IBP_E_INVALID_ARG", dict(net, seg_ptr=p))
+    p = net["seg_ptr"].copy()
+    p[3], p[4] = p[4], p[3]
+    _expect("IBP_E_INVALID_ARG", dict(net, seg_ptr=p))
+    a = net["seg_a"].copy()
+    a[2] = np.nan
+    _expect("IBP_E_INVALID_ARG", dict(net, seg_a=a))
+    u = net["seg_U"].copy()
+    u[0] = -np.inf
+    _expect("IBP_E_INVALID_ARG", dict(net, seg_U=u))
+    u[0] = np.inf                       # an uncapped segment is allowed
+    _host(dict(net, seg_U=u)).close()
+    with pytest.raises(ibp.IBPError):   # lengths are checked by the binding
+        _host(dict(net, seg_a=net["seg_a"][:-1]))
