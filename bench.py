@@ -54,6 +54,70 @@ def measured_traffic(kernel: str):
         return None
 
 
+def write_traffic_record(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
+    """Turns four rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE of the bound,
+    and of --calibrate-copy) into the committed record read by measured_traffic
+    and a short markdown summary beside it."""
+    import csv
+    import hashlib
+
+    def read(d):
+        rows = {}
+        for fn in os.listdir(d):
+            if fn.endswith("counter_collection.csv"):
+                with open(os.path.join(d, fn)) as f:
+                    for r in csv.DictReader(f):
+                        name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+                        rows.setdefault(name, []).append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in rows.items()}
+
+    fetch, write = read(fetch_dir), read(write_dir)
+    cf = read(copy_fetch_dir)["__amd_rocclr_copyBuffer"]
+    cw = read(copy_write_dir)["__amd_rocclr_copyBuffer"]
+    fs, wsc = (1 << 30) / (cf * 1024), (1 << 30) / (cw * 1024)
+    sources = ["paper_2511_15624_amd/csrc/ibp_forward.hip", "paper_2511_15624_amd/csrc/ibp_devfun.h"]
+    m = hashlib.sha256()
+    for p in sources:
+        with open(os.path.join(ROOT, p), "rb") as g:
+            m.update(g.read())
+    algo = {KERNEL_NAMES["base_flows"]: 465696000, KERNEL_NAMES["outage_sweep"]: 448000000}
+    kern = {}
+    for k in sorted(fetch):
+        if not k.startswith("ibp::"):
+            continue
+        kern[k] = {"fetch_kib": fetch[k], "write_kib": write.get(k, 0.0), "fetch_bytes": fetch[k] * 1024 * fs,
+                   "write_bytes": write.get(k, 0.0) * 1024 * wsc, "algorithmic_bytes": algo.get(k)}
+    rec = {"workload": "8316 buses, 14000 lines, 8000 outages, single whole box", "fetch_scale": fs,
+           "write_scale": wsc, "source_sha256_16": m.hexdigest()[:16], "sources": sources, "kernels": kern}
+    with open(TRAFFIC_RECORD, "w") as f:
+        json.dump(rec, f, indent=1)
+    cmd = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc {c} --output-format csv -d <repo>/gpurun_out/{d} "
+           "-o run -- python3 <repo>/bench.py {a}")
+    lines = ["# HBM traffic counters: forward bound, 8316-bus single box", "",
+             "Commands (repository root on one MI355X; each counter in a run of its own):", "", "```",
+             cmd.format(c="FETCH_SIZE", d="pmc_fetch", a="--steps 3 --warmup 1 --no-cpu-baseline --no-extras"),
+             cmd.format(c="WRITE_SIZE", d="pmc_write", a="--steps 3 --warmup 1 --no-cpu-baseline --no-extras"),
+             cmd.format(c="FETCH_SIZE", d="pmc_copy_fetch", a="--calibrate-copy"),
+             cmd.format(c="WRITE_SIZE", d="pmc_copy_write", a="--calibrate-copy"),
+             "python3 bench.py --traffic-record gpurun_out/pmc_fetch gpurun_out/pmc_write "
+             "gpurun_out/pmc_copy_fetch gpurun_out/pmc_copy_write", "```", "",
+             f"Calibration: a 1 GiB device copy (`__amd_rocclr_copyBuffer`) reads {cf:.1f} KiB FETCH_SIZE and "
+             f"{cw:.1f} KiB WRITE_SIZE per dispatch,",
+             f"so bytes = FETCH_SIZE KiB x 1024 x {fs:.4f} and WRITE_SIZE KiB x 1024 x {wsc:.4f}.", "",
+             "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | read bytes (scaled) | written bytes | algorithmic bytes "
+             "| traffic / algorithmic |", "|---|---|---|---|---|---|---|"]
+    for k, v in kern.items():
+        a = v["algorithmic_bytes"]
+        ratio = f"{(v['fetch_bytes'] + v['write_bytes']) / a:.4f}" if a else "-"
+        lines.append(f"| {k} | {v['fetch_kib']:.1f} | {v['write_kib']:.1f} | {v['fetch_bytes']:.4g} | "
+                     f"{v['write_bytes']:.4g} | {a if a else '-'} | {ratio} |")
+    lines += ["", "Kernel sources hashed for staleness: " + ", ".join(sources) + f" -> {rec['source_sha256_16']}."]
+    with open(TRAFFIC_RECORD[:-5] + ".md", "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(TRAFFIC_RECORD)
+    return 0
+
+
 def _threads():
     try:
         from threadpoolctl import threadpool_info
@@ -202,7 +266,11 @@ def main(argv=None):
                     help="skip the batched / backward / splitting measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
+    ap.add_argument("--traffic-record", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="write the HBM traffic record from four rocprofv3 --pmc output folders (no GPU)")
     args = ap.parse_args(argv)
+    if args.traffic_record:
+        return write_traffic_record(*args.traffic_record)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
