@@ -33,6 +33,10 @@ DCOPF via Interval Bound Propagation", Tekeler, Chevalier, Zhong, Zhang):
   F*_i(x) = min(F*_{i-1}(x) + a_i ReLU(x - b_i), U_i); the surplus adds
   F* of every load and subtracts F* of every generator, beside the linear
   terms.  IBP takes the curve node by node.
+* A linear-relaxation (CROWN-style) upper bound on max f (``crown_upper``):
+  each convex penalty replaced by a global linear minorant whose slope comes
+  from its IBP pre-activation interval, then the exact maximum of the
+  resulting linear function over the box.
 
 Readings taken where the paper is silent:
 
@@ -78,6 +82,7 @@ __all__ = [
     "center_radius",
     "curve_value",
     "curve_interval",
+    "crown_upper",
 ]
 
 
@@ -551,6 +556,96 @@ def grad(net, lo, hi, g_lo: float = 1.0, g_hi: float = 0.0, fac=None, chunk: int
     d_lo = 0.5 * (d_mu - d_sg)
     d_hi = 0.5 * (d_mu + d_sg)
     return d_lo, d_hi, near
+
+
+# ----------------------------------------------------------------------------
+# linear-relaxation (CROWN-style) upper bound on max f over the box
+# ----------------------------------------------------------------------------
+
+def _crown_slopes(c, r, t, near_rel):
+    """Slope s = sign(c) where |c| - r > t (the interval [c - r, c + r] lies on one
+    linear piece of max(|z| - t, 0) with non-zero slope), else 0; and the count
+    of elements within near_rel of that decision."""
+    m = np.abs(c) - r - t
+    s = np.sign(c) * (m > 0)
+    k = int(np.sum((np.abs(m) <= near_rel * (np.abs(c) + r + t)) & (c != 0)))
+    return s, k
+
+
+def crown_upper(net, lo, hi, fac=None, chunk: int = 256, near_rel: float = 1e-5) -> dict:
+    """Upper bound on max f over the box from linear relaxations of the penalties
+    (the convex-relaxation family the paper cites beside IBP, Sec. I).
+
+    Every penalty phi(z) = max(|z| - t, 0) of the graph is convex, so for any
+    s in {-1, 0, 1} the line s z - |s| t lies below it for every z; the
+    imbalance |z| likewise lies above s z.  Replacing each penalty by such a
+    line turns -f into a linear function of the inputs plus the surplus, whose
+    maximum over the box is exact: sum_j max over x_j of (G_j x_j), plus the
+    curve part through its IBP interval.  The slope of an element is the sign
+    of its pre-activation interval (IBP, exact for these affine nodes) when the
+    whole interval lies beyond the threshold, and 0 otherwise, so each line's
+    minimum over the box equals IBP's lower penalty and the bound is never
+    above IBP's f_hi.
+
+    Returns ``f_hi`` (the bound), ``n_active`` (elements with a non-zero
+    slope) and ``near`` (elements whose slope decision sits within
+    ``near_rel`` of switching, relative to |C| + R + t).
+    """
+    if fac is None:
+        fac = factors(net)
+    mu, sg = center_radius(lo, hi)
+    W = _injection_map(net)
+    c_inj = W @ mu
+    r_inj = abs(W) @ sg
+    zi, zf = float(net["zeta_inj"]), float(net["zeta_f"])
+    w = np.concatenate([-np.asarray(net["gen_cost"], float), np.asarray(net["load_value"], float)])
+    near = 0
+    n_active = 0
+
+    def slopes(c, r, t):
+        return _crown_slopes(c, r, t, near_rel)
+
+    # imbalance 1^T |(E^T Phi - I) p_inj|: |z| >= s z
+    W2 = _imbalance_matrix(net)
+    cz = W2 @ c_inj
+    rz = abs(W2) @ r_inj
+    s_I, k = slopes(cz, rz, 0.0)
+    near += k
+    # base lines
+    Phi = fac["Phi"]
+    c_f = Phi @ c_inj
+    r_f = np.abs(Phi) @ r_inj
+    fb = np.asarray(net["fmax_base"], float)
+    s_b, k = slopes(c_f, r_f, fb)
+    near += k
+    n_active += int(np.count_nonzero(s_b))
+    const = [zf * math.fsum(np.abs(s_b) * fb)]
+    # contingency elements, paper form z = M f - B (U p)
+    U, Bm, M = fac["U"], fac["B"], fac["M"]
+    c_u = U @ c_inj
+    r_u = np.abs(U) @ r_inj
+    fc = np.asarray(net["fmax_ctg"], float)
+    K = fac["K"]
+    v_f = s_b.astype(float).copy()
+    v_u = np.zeros(K)
+    for k0 in range(0, K, chunk):
+        k1 = min(K, k0 + chunk)
+        Mk, Bk = M[k0:k1], Bm[k0:k1]
+        Cc = Mk * c_f[None, :] - Bk * c_u[k0:k1, None]
+        Rc = np.abs(Mk) * r_f[None, :] + np.abs(Bk) * r_u[k0:k1, None]
+        s, k = slopes(Cc, Rc, fc[None, :])
+        s = s * (Mk != 0)          # the outaged line's own entry carries no penalty
+        near += k
+        n_active += int(np.count_nonzero(s))
+        const.append(zf * _fsum_pairwise(np.abs(s) * fc[None, :]))
+        v_f += np.sum(Mk * s, axis=0)
+        v_u[k0:k1] = -np.sum(Bk * s, axis=1)
+    # coefficient of x in the relaxed objective: surplus - zeta_inj s_I z_I - zeta_f sum s z
+    G = w - zi * (W.T @ (W2.T @ s_I)) - zf * (W.T @ (Phi.T @ v_f + U.T @ v_u))
+    P_lo, P_hi = _curve_surplus(net, mu, sg)
+    c0 = math.fsum(const)
+    f_hi = c0 + math.fsum(G * mu) + math.fsum(np.abs(G) * sg) + P_hi
+    return dict(f_hi=f_hi, n_active=n_active, near=near, G=G, const=c0)
 
 
 # ----------------------------------------------------------------------------
