@@ -138,6 +138,7 @@ void ibp_free_network(ibp_network* net);
 #define IBP_F_NONE 0u
 #define IBP_F_PLAIN 1u    /* per-box single-box kernels even for n_box > 1 (reference form for batching) */
 #define IBP_F_BACKWARD 4u /* workspace query only: size for ibp_bound_backward (includes the forward's) */
+#define IBP_F_CROWN 8u    /* workspace query only: size for ibp_crown_bound_boxes (includes the forward's) */
 
 /* Bytes of device workspace a compute call needs for n_box boxes (0 on error). */
 size_t ibp_workspace_bytes(const ibp_network* net, int64_t n_box, uint32_t flags);
@@ -173,6 +174,26 @@ ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box,
                               double* g_box_lo, double* g_box_hi,
                               void* ws, size_t ws_bytes, void* stream, uint32_t flags);
 
+/* ibp_crown_bound_boxes -- IBP bounds tightened by a linear relaxation of the
+ * penalties (the CROWN family of convex relaxations the paper cites beside
+ * IBP, Sec. I).  Every penalty max(|z| - t, 0) and the imbalance |z| is
+ * convex, so a supporting line s z - |s| t (s in {-1, 0, 1}) lies below it
+ * everywhere; with these lines the objective is bounded above by a linear
+ * function of the inputs (plus the interval of any piecewise-linear curves)
+ * whose exact maximum over the box is computed with outward rounding.  The
+ * slope of an element is the sign of its flow when IBP's interval for it lies
+ * beyond the limit, else 0, so the relaxation is never looser than IBP.
+ *   f_lo, f_hi : device float64 [n_box]: IBP's f_lo, and min(IBP f_hi,
+ *                relaxation bound) -- both still certified.
+ *   crown_hi   : device float64 [n_box] or NULL: the relaxation bound alone.
+ *   ws, ws_bytes: at least ibp_workspace_bytes(net, n_box, flags | IBP_F_CROWN).
+ * flags: 0 or IBP_F_PLAIN (forward kernels as in ibp_bound_boxes).  Invalid
+ * boxes get NaN.  Errors: INVALID_ARG, WORKSPACE, HOST_ONLY, DEVICE. */
+ibp_status ibp_crown_bound_boxes(const ibp_network* net, int64_t n_box,
+                                 const float* box_lo, const float* box_hi,
+                                 double* f_lo, double* f_hi, double* crown_hi,
+                                 void* ws, size_t ws_bytes, void* stream, uint32_t flags);
+
 /* Kernel timing for benchmarks and profiling.  While enabled, every compute
  * call on `net` records a HIP event pair around each kernel it queues, on the
  * call's stream.  ibp_kernel_times() waits for those events and returns, per
@@ -180,9 +201,10 @@ ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box,
  * read (then clears them).  Kernel ids: 0 box preparation, 1 base flows,
  * 2 outage sweep, 3 finalize, 4 line epilogue, 5 batched base flows,
  * 6 batched outage sweep, 7 backward outage sweep, 8 backward transposed PTDF,
- * 9 backward endpoints.
+ * 9 backward endpoints, 10 relaxation outage sweep, 11 relaxation line adjoint
+ * and transposed PTDF, 12 relaxation inputs and finalize.
  * Not thread-safe with concurrent compute calls on the same handle. */
-#define IBP_N_KERNEL_IDS 10
+#define IBP_N_KERNEL_IDS 13
 ibp_status ibp_set_kernel_timing(ibp_network* net, int enable);
 ibp_status ibp_kernel_times(ibp_network* net, int32_t n_ids, double* total_ms, int64_t* count);
 

@@ -255,6 +255,24 @@ ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
     lay.gri = take(B * d.Np * sizeof(double));
     lay.total = off;
   }
+  if (flags & IBP_F_CROWN) {
+    const ibp::DevNet& d = net->dn;
+    const size_t B = (size_t)std::max<int64_t>(1, n_box);
+    ibp::plan_crown(d, lay);
+    size_t off = lay.total;
+    auto take = [&](size_t bytes) {
+      const size_t o = off;
+      off = align256(off + bytes);
+      return o;
+    };
+    lay.ccnt = take(B * d.Lp * 2 * sizeof(int));
+    lay.cv = take(B * lay.kc_bx * std::max(1, d.K) * 4 * sizeof(double));
+    lay.lv = take(B * d.Lp * 4 * sizeof(double));
+    lay.bpart = take(B * lay.kc3_bx * d.Np * 4 * sizeof(double));
+    lay.cp = take(B * lay.n_cp * 2 * sizeof(double));
+    lay.ct = take(B * lay.n_ct * 2 * sizeof(double));
+    lay.total = off;
+  }
   return lay;
 }
 
@@ -294,7 +312,8 @@ ibp_status check_compute_args(const ibp_network* net, int64_t n_box, const void*
   if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
   if (net->device < 0) return fail(IBP_E_HOST_ONLY, "network was built host-only");
   if (n_box < 0) return fail(IBP_E_INVALID_ARG, "n_box < 0");
-  if (flags & ~uint32_t(IBP_F_PLAIN | IBP_F_BACKWARD)) return fail(IBP_E_INVALID_ARG, "unknown flag bits");
+  if (flags & ~uint32_t(IBP_F_PLAIN | IBP_F_BACKWARD | IBP_F_CROWN))
+    return fail(IBP_E_INVALID_ARG, "unknown flag bits");
   if (n_box == 0) return IBP_OK;
   if (!lo || !hi || !a || !b) return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
   lay = layout(net, n_box, flags);
@@ -418,6 +437,25 @@ ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box, const float
   if (e == hipSuccess)
     e = ibp::launch_backward_sweeps(net->dn, n_box, ws, lay, box_lo, box_hi, g_f_lo, g_f_hi, g_box_lo, g_box_hi,
                                     s, tm);
+  if (e != hipSuccess) return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  return IBP_OK;
+}
+
+ibp_status ibp_crown_bound_boxes(const ibp_network* net, int64_t n_box, const float* box_lo,
+                                 const float* box_hi, double* f_lo, double* f_hi, double* crown_hi, void* ws,
+                                 size_t ws_bytes, void* stream, uint32_t flags) {
+  g_err.clear();
+  if (flags & ~uint32_t(IBP_F_PLAIN)) return fail(IBP_E_INVALID_ARG, "flags: only IBP_F_PLAIN is accepted");
+  ibp::WsLayout lay;
+  ibp_status st = check_compute_args(net, n_box, box_lo, box_hi, f_lo, f_hi, ws, ws_bytes, flags | IBP_F_CROWN,
+                                     lay);
+  if (st != IBP_OK || n_box == 0) return st;
+  DeviceGuard g(net->device);
+  if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ibp::KernelTimer* tm = const_cast<ibp::KernelTimer*>(&net->timer);
+  hipError_t e = ibp::launch_forward(net->dn, n_box, box_lo, box_hi, f_lo, f_hi, nullptr, ws, lay, s, tm);
+  if (e == hipSuccess) e = ibp::launch_crown(net->dn, n_box, box_lo, box_hi, f_hi, crown_hi, ws, lay, s, tm);
   if (e != hipSuccess) return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
   return IBP_OK;
 }

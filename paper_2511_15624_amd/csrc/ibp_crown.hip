@@ -1,0 +1,370 @@
+// Linear-relaxation (CROWN-style) upper bound on max f over a box.
+//
+// The paper names convex relaxations (CROWN and its variants) as the tighter
+// family beside IBP (Sec. I).  On this graph every penalty is a convex
+// function of one affine pre-activation: phi(z) = max(|z| - t, 0) for a flow
+// against its limit, |z| for the total imbalance.  For any s in {-1, 0, 1} the
+// line s z - |s| t lies below phi for every z (a supporting line), so
+//
+//   f(x) <= S(x) - zeta_inj s_I z_I(x) - zeta_f sum_e (s_e z_e(x) - |s_e| t_e)
+//
+// holds at every x whatever the slopes are.  The right side is linear in x
+// (plus the curve part), so its maximum over the box is
+//   sum_j (G_j c_j + |G_j| r_j) + zeta_f sum_e |s_e| t_e  (+ curve interval),
+// with G = w - zeta_inj s_I sign - zeta_f N^T Phi^T v and the line adjoint
+//   v_l = s_l (base) + sum_k s_kl + [l = c(k)] sum_l' s_kl' Lam_l'k.
+// The slope of an element is sign(C) when its padded interval lies beyond the
+// limit (the K3 test t_lo > 0) and 0 otherwise: every line then attains IBP's
+// lower penalty on the box, so the bound is never above IBP's f_hi in exact
+// arithmetic.  The slope decision affects tightness only, never validity.
+//
+// Rigour: s in {-1, 0, 1} and float32 factors make the per-line sums exact
+// small integers (int atomics, order-independent) and every s Lam product
+// exact; per-outage sums and the transposed PTDF product run in float64.  The
+// coefficient error |G^ - G_exact| is bounded per input from
+//   |Lam32 - Lam_exact| <= kappa0 |Lam32| + (2 eps_l + 2 |Lam| eps_c)/(1 - H_cc),
+//   |Phi32 - Phi_exact| <= kappa0 |Phi32| + eps_l,
+// the float64 accumulation bounds, and absolute sums carried beside each sum
+// (vabs, ev); the box maximum adds E_j (|c_j| + r_j).
+//
+//   KC0  zero the per-line counters
+//   KC1  outage sweep: slopes, per-line integer counts, per-outage float64 sums
+//   KC2  per line: adjoint v, its absolute bound and error, limit totals
+//   KC3  per bus: Phi^T v, |Phi|^T vabs, |Phi|^T ev (float64)
+//   KC4  per input: coefficient, error bound, box maximum (and curve interval)
+//   KC5  per box: total, outward padding, min with IBP's f_hi
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstdint>
+
+#include "ibp_devfun.h"
+#include "ibp_kernels.h"
+
+namespace ibp {
+
+namespace {
+constexpr int kKC = 16;   // outages per KC1 block
+constexpr int kNB = 32;   // buses per KC3 block
+}  // namespace
+
+__global__ __launch_bounds__(256) void kc0_zero(int2* __restrict__ cnt, int64_t n) {
+  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  if (i < n) cnt[i] = make_int2(0, 0);
+}
+
+// Slope of one element from the K3 quantities: C = fma(Lam, c_c, c_l),
+// t_lo = |C| - fma(|Lam|, rho'_k, g_l) <= |C*| - R* - fmax.  NaN (the outaged
+// line's own entry) compares false and gets slope 0.
+__device__ __forceinline__ float crown_slope(float lam, float cc, float rk, float cl, float g) {
+  const float C = fmaf(lam, cc, cl);
+  const float tlo = fabsf(C) - fmaf(fabsf(lam), rk, g);
+  return tlo > 0.0f ? copysignf(1.0f, C) : 0.0f;
+}
+
+__global__ __launch_bounds__(256) void kc1_sweep(DevNet net, void* ws, WsLayout lay, int64_t box0) {
+  __shared__ double shv[4][kKC][2];
+  __shared__ float shn[4][kKC];
+  const int64_t b = box0 + blockIdx.z;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int col = (blockIdx.x * 4 + w) * 64 + lane;  // float4 column: four lines per lane
+  const int Lp4 = net.Lp / 4;
+  const int k0 = blockIdx.y * kKC;
+  const int k1 = min(net.K, k0 + kKC);
+  const bool live = col < Lp4;
+  float4 c4 = make_float4(0.f, 0.f, 0.f, 0.f), g4 = make_float4(FLT_MAX, FLT_MAX, FLT_MAX, FLT_MAX);
+  if (live) {
+    const double* bs = ws_ptr<double>(ws, lay.box) + b * kBoxSlots;
+    const float vmax = __uint_as_float(*reinterpret_cast<const unsigned int*>(bs + kVmax));
+    c4 = reinterpret_cast<const float4*>(ws_ptr<float>(ws, lay.lc) + b * net.Lp)[col];
+    g4 = reinterpret_cast<const float4*>(ws_ptr<float>(ws, lay.lg) + b * net.Lp)[col];
+    const float4 e4 = reinterpret_cast<const float4*>(net.line_eps)[col];
+    g4 = make_float4(add_ru(g4.x, next_up_f32(e4.x * vmax)), add_ru(g4.y, next_up_f32(e4.y * vmax)),
+                     add_ru(g4.z, next_up_f32(e4.z * vmax)), add_ru(g4.w, next_up_f32(e4.w * vmax)));
+  }
+  const int4* cd = ws_ptr<int4>(ws, lay.ctg) + b * net.K;
+  const float4* lam = reinterpret_cast<const float4*>(net.lodf) + col;
+  float cs0 = 0.f, cs1 = 0.f, cs2 = 0.f, cs3 = 0.f, ca0 = 0.f, ca1 = 0.f, ca2 = 0.f, ca3 = 0.f;
+  for (int k = k0; k < k1; ++k) {
+    double v = 0.0, a = 0.0;
+    float n = 0.0f;
+    if (live) {
+      const float4 x = ld_stream(lam + (size_t)k * Lp4);
+      const int4 d = cd[k];
+      const float cc = __int_as_float(d.y), rk = __int_as_float(d.z);
+      const float s0 = crown_slope(x.x, cc, rk, c4.x, g4.x);
+      const float s1 = crown_slope(x.y, cc, rk, c4.y, g4.y);
+      const float s2 = crown_slope(x.z, cc, rk, c4.z, g4.z);
+      const float s3 = crown_slope(x.w, cc, rk, c4.w, g4.w);
+      cs0 += s0; cs1 += s1; cs2 += s2; cs3 += s3;
+      ca0 += fabsf(s0); ca1 += fabsf(s1); ca2 += fabsf(s2); ca3 += fabsf(s3);
+      n = (fabsf(s0) + fabsf(s1)) + (fabsf(s2) + fabsf(s3));
+      if (n != 0.0f) {
+        // s Lam is exact in float32; NaN entries carry s = 0 and a finite stand-in
+        const float l0 = fminf(x.x, FLT_MAX), l1 = fminf(x.y, FLT_MAX);
+        const float l2 = fminf(x.z, FLT_MAX), l3 = fminf(x.w, FLT_MAX);
+        v = ((double)(s0 * l0) + (double)(s1 * l1)) + ((double)(s2 * l2) + (double)(s3 * l3));
+        a = ((double)(fabsf(s0 * l0)) + (double)(fabsf(s1 * l1))) +
+            ((double)(fabsf(s2 * l2)) + (double)(fabsf(s3 * l3)));
+      }
+    }
+    // a wave with no active element skips the reduction
+    if (__any(n != 0.0f)) {
+      v = wave_sum(v);
+      a = wave_sum(a);
+#pragma unroll
+      for (int m = 32; m >= 1; m >>= 1) n += __shfl_xor(n, m, 64);
+    }
+    if (lane == 0) {
+      shv[w][k - k0][0] = v;
+      shv[w][k - k0][1] = a;
+      shn[w][k - k0] = n;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < k1 - k0) {
+    const int q = threadIdx.x;
+    const double V = (shv[0][q][0] + shv[1][q][0]) + (shv[2][q][0] + shv[3][q][0]);
+    const double A = (shv[0][q][1] + shv[1][q][1]) + (shv[2][q][1] + shv[3][q][1]);
+    const double N = ((double)shn[0][q] + (double)shn[1][q]) + ((double)shn[2][q] + (double)shn[3][q]);
+    ws_ptr<double4>(ws, lay.cv)[((size_t)b * lay.kc_bx + blockIdx.x) * net.K + k0 + q] =
+        make_double4(V, A, N, 0.0);
+  }
+  if (live) {
+    // per-line counts: integer atomics, so the totals do not depend on the order
+    int2* cnt = ws_ptr<int2>(ws, lay.ccnt) + b * net.Lp + 4 * col;
+    const float cs[4] = {cs0, cs1, cs2, cs3}, ca[4] = {ca0, ca1, ca2, ca3};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (ca[i] != 0.0f) {
+        atomicAdd(&cnt[i].x, (int)cs[i]);
+        atomicAdd(&cnt[i].y, (int)ca[i]);
+      }
+  }
+}
+
+// Per line: v, vabs >= |v_exact|, ev >= |v^ - v_exact|; block partials of the
+// limit total sum |s| t and of sum vabs.
+__global__ __launch_bounds__(256) void kc2_lines(DevNet net, void* ws, WsLayout lay, int64_t box0) {
+  __shared__ double sh[4];
+  const int64_t b = box0 + blockIdx.y;
+  const int l = blockIdx.x * 256 + threadIdx.x;
+  double v = 0.0, va = 0.0, ev = 0.0, T = 0.0;
+  if (l < net.L) {
+    const double cf = ws_ptr<double>(ws, lay.lcf)[b * net.L + l];
+    const double rf = ws_ptr<double>(ws, lay.lrf)[b * net.L + l];
+    const double fb = net.fmax_b[l];
+    const double sb = (fabs(cf) - rf - fb > 0.0) ? copysign(1.0, cf) : 0.0;
+    const int2 n = ws_ptr<int2>(ws, lay.ccnt)[b * net.Lp + l];
+    v = sb + (double)n.x;
+    va = fabs(sb) + (double)n.y;
+    T = fabs(sb) * fb + (double)n.y * net.fmax_c[l];
+    const int k = net.ctg_of_line[l];
+    if (k >= 0) {
+      double V = 0.0, A = 0.0, N = 0.0;
+      const double4* cv = ws_ptr<double4>(ws, lay.cv) + (size_t)b * lay.kc_bx * net.K + k;
+      for (int t = 0; t < lay.kc_bx; ++t) {
+        const double4 q = cv[(size_t)t * net.K];
+        V += q.x;
+        A += q.y;
+        N += q.z;
+      }
+      // float64 sums of exact products (L + tiles terms); stored-factor errors
+      const double gam = (net.Lp + lay.kc_bx + 16) * kU64 * 1.01;
+      const double A1 = A * (1.0 + gam) * (1.0 + kKappa0);
+      ev = (kKappa0 + net.ctg_eps[k] + gam) * A1 + 2.0 * net.phi_err_max * net.ctg_inv[k] * N;
+      v += V;
+      va += A1 + ev;
+    }
+    // rounding of the two additions forming v
+    ev = (ev + 2.0 * kU64 * va) * (1.0 + 4.0 * kU64);
+    va = va * (1.0 + 4.0 * kU64) + ev;
+  }
+  if (l < net.Lp) ws_ptr<double4>(ws, lay.lv)[b * net.Lp + l] = make_double4(v, va, ev, 0.0);
+  T = block_sum256(T, sh);
+  const double S = block_sum256(va, sh);
+  if (threadIdx.x == 0) ws_ptr<double2>(ws, lay.ct)[b * lay.n_ct + blockIdx.x] = make_double2(T, S);
+}
+
+// Per bus n: y = sum_l Phi32[l, n] v_l, ya = sum_l |Phi32| vabs_l,
+// ye = sum_l |Phi32| ev_l, over one 1024-line tile; kNB buses per block.
+__global__ __launch_bounds__(256) void kc3_ptdf_t(DevNet net, void* ws, WsLayout lay, int64_t box0) {
+  __shared__ double sh[4][kNB][3];
+  const int64_t b = box0 + blockIdx.z;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int col = (blockIdx.x * 4 + w) * 64 + lane;
+  const int Lp4 = net.Lp / 4;
+  const bool live = col < Lp4;
+  double v[4] = {0, 0, 0, 0}, va[4] = {0, 0, 0, 0}, ev[4] = {0, 0, 0, 0};
+  if (live) {
+    const double4* lv = ws_ptr<double4>(ws, lay.lv) + b * net.Lp + 4 * col;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double4 q = lv[i];
+      v[i] = q.x;
+      va[i] = q.y;
+      ev[i] = q.z;
+    }
+  }
+  const int n0 = blockIdx.y * kNB;
+  const int n1 = min(net.N, n0 + kNB);
+  const float4* ph = reinterpret_cast<const float4*>(net.phiT) + col;
+  for (int n = n0; n < n1; ++n) {
+    double y = 0.0, ya = 0.0, ye = 0.0;
+    if (live) {
+      const float4 x = ld_stream(ph + (size_t)n * Lp4);
+      const double p[4] = {(double)x.x, (double)x.y, (double)x.z, (double)x.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        y = fma(p[i], v[i], y);
+        ya = fma(fabs(p[i]), va[i], ya);
+        ye = fma(fabs(p[i]), ev[i], ye);
+      }
+    }
+    y = wave_sum(y);
+    ya = wave_sum(ya);
+    ye = wave_sum(ye);
+    if (lane == 0) {
+      sh[w][n - n0][0] = y;
+      sh[w][n - n0][1] = ya;
+      sh[w][n - n0][2] = ye;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < n1 - n0) {
+    const int q = threadIdx.x;
+    double o[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) o[f] = (sh[0][q][f] + sh[1][q][f]) + (sh[2][q][f] + sh[3][q][f]);
+    ws_ptr<double4>(ws, lay.bpart)[((size_t)b * lay.kc3_bx + blockIdx.x) * net.Np + n0 + q] =
+        make_double4(o[0], o[1], o[2], 0.0);
+  }
+}
+
+// Per input: coefficient G_j, its error bound E_j, and max over [lo_j, hi_j] of
+// G_j x_j (plus the curve interval's upper end); block partials (sum, sum |.|).
+__global__ __launch_bounds__(256) void kc4_inputs(DevNet net, void* ws, WsLayout lay, int64_t box0,
+                                                  const float* __restrict__ box_lo,
+                                                  const float* __restrict__ box_hi) {
+  __shared__ double sh[4];
+  const int64_t b = box0 + blockIdx.y;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const double* p1 = ws_ptr<double>(ws, lay.p1) + b * lay.n_p1 * kP1Fields;
+  double cI = 0.0, rI = 0.0;
+  for (int q = threadIdx.x; q < lay.n_p1; q += 256) {
+    cI += p1[q * kP1Fields + kP1cI];
+    rI += p1[q * kP1Fields + kP1rI];
+  }
+  cI = block_sum256(cI, sh);
+  rI = block_sum256(rI, sh);
+  double SV = 0.0;
+  for (int q = threadIdx.x; q < lay.n_ct; q += 256) SV += ws_ptr<double2>(ws, lay.ct)[b * lay.n_ct + q].y;
+  SV = block_sum256(SV, sh) * (1.0 + (lay.n_ct + 16) * kU64 * 1.01);
+  double h = 0.0, ha = 0.0;
+  if (j < net.X) {
+    const int n = net.dev_bus[j];
+    double y = 0.0, ya = 0.0, ye = 0.0;
+    const double4* bp = ws_ptr<double4>(ws, lay.bpart) + (size_t)b * lay.kc3_bx * net.Np + n;
+    for (int t = 0; t < lay.kc3_bx; ++t) {
+      const double4 q = bp[(size_t)t * net.Np];
+      y += q.x;
+      ya += q.y;
+      ye += q.z;
+    }
+    // float64 products of float32 x float64 and sums over Lp lines + tiles
+    const double gam = (net.Lp + lay.kc3_bx + 16) * kU64 * 1.01;
+    ya *= (1.0 + gam);
+    ye *= (1.0 + gam);
+    const double sj = j < net.G ? 1.0 : -1.0;
+    const double sI = (fabs(cI) - rI > 0.0) ? copysign(1.0, cI) : 0.0;
+    const double wj = net.dev_w[j], zi = net.zeta_inj, zf = net.zeta_f;
+    const double G = wj - zi * sI * sj - zf * sj * y;
+    // |y^ - (Phi_exact^T v_exact)_n| <= (kappa0 + gam) ya + (1 + kappa0) ye + 2 eps_max sum vabs
+    const double E = zf * ((kKappa0 + gam) * ya + (1.0 + kKappa0) * ye + 2.0 * net.phi_err_max * SV) *
+                         (1.0 + 8.0 * kU64) +
+                     4.0 * kU64 * (fabs(wj) + zi + zf * fabs(y));
+    const double l = box_lo[b * net.X + j], hh = box_hi[b * net.X + j];
+    const double c = 0.5 * (l + hh), r = 0.5 * (hh - l);
+    const double m = fabs(c) + r;
+    h = G * c + fabs(G) * r + E * m;
+    ha = fabs(G) * m + E * m;
+    h += 4.0 * kU64 * ha;
+    if (net.seg_ptr) {
+      const int s0 = net.seg_ptr[j], s1 = net.seg_ptr[j + 1];
+      if (s1 > s0) {
+        double F_lo, F_hi, e;
+        curve_ibp(net.seg, s0, s1, c, r, F_lo, F_hi, e);
+        const double u = (j < net.G ? -F_lo : F_hi) + e + kU64 * (fabs(F_lo) + fabs(F_hi));
+        h += u;
+        ha += fabs(u);
+      }
+    }
+  }
+  h = block_sum256(h, sh);
+  ha = block_sum256(ha, sh);
+  if (threadIdx.x == 0) ws_ptr<double2>(ws, lay.cp)[b * lay.n_cp + blockIdx.x] = make_double2(h, ha);
+}
+
+__global__ __launch_bounds__(256) void kc5_finalize(DevNet net, void* ws, WsLayout lay, int64_t box0,
+                                                    double* __restrict__ f_hi, double* __restrict__ crown) {
+  __shared__ double sh[4];
+  const int64_t b = box0 + blockIdx.x;
+  double H = 0.0, Ha = 0.0, T = 0.0;
+  for (int q = threadIdx.x; q < lay.n_cp; q += 256) {
+    const double2 t = ws_ptr<double2>(ws, lay.cp)[b * lay.n_cp + q];
+    H += t.x;
+    Ha += t.y;
+  }
+  for (int q = threadIdx.x; q < lay.n_ct; q += 256) T += ws_ptr<double2>(ws, lay.ct)[b * lay.n_ct + q].x;
+  H = block_sum256(H, sh);
+  Ha = block_sum256(Ha, sh);
+  T = block_sum256(T, sh);
+  if (threadIdx.x != 0) return;
+  // sums of n_cp and n_ct partials, each a 256-term tree: float64 bound
+  const double gam = (lay.n_cp + lay.n_ct + 300) * kU64 * 1.01;
+  const double zT = net.zeta_f * T;
+  const double ub = (H + zT) + gam * (Ha + fabs(H) + 2.0 * zT);
+  const double prev = f_hi[b];
+  const double out = (prev != prev || ub != ub) ? NAN : fmin(prev, ub);
+  f_hi[b] = out;
+  if (crown) crown[b] = (prev != prev) ? NAN : ub;
+}
+
+void plan_crown(const DevNet& net, WsLayout& lay) {
+  const int lp4 = net.Lp / 4;
+  lay.kc_bx = (lp4 + 255) / 256;
+  lay.kc_by = std::max(1, (net.K + kKC - 1) / kKC);
+  lay.kc3_bx = (lp4 + 255) / 256;
+  lay.kc3_by = (net.N + kNB - 1) / kNB;
+  lay.n_cp = (net.X + 255) / 256;
+  lay.n_ct = (net.L + 255) / 256;
+}
+
+hipError_t launch_crown(const DevNet& net, int64_t n_box, const float* lo, const float* hi, double* f_hi,
+                        double* crown, void* ws, const WsLayout& lay, hipStream_t s, KernelTimer* tm) {
+  for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
+    const int nb = (int)std::min<int64_t>(65535, n_box - b0);
+    int t = tm->start(10, s);
+    const int64_t nz = (int64_t)nb * net.Lp;
+    int2* cnt = reinterpret_cast<int2*>(static_cast<char*>(ws) + lay.ccnt) + b0 * net.Lp;
+    hipLaunchKernelGGL(kc0_zero, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, cnt, nz);
+    if (net.K > 0)
+      hipLaunchKernelGGL(kc1_sweep, dim3(lay.kc_bx, lay.kc_by, nb), dim3(256), 0, s, net, ws, lay, b0);
+    tm->stop(t, s);
+    t = tm->start(11, s);
+    hipLaunchKernelGGL(kc2_lines, dim3(lay.n_ct, nb), dim3(256), 0, s, net, ws, lay, b0);
+    hipLaunchKernelGGL(kc3_ptdf_t, dim3(lay.kc3_bx, lay.kc3_by, nb), dim3(256), 0, s, net, ws, lay, b0);
+    tm->stop(t, s);
+    t = tm->start(12, s);
+    hipLaunchKernelGGL(kc4_inputs, dim3(lay.n_cp, nb), dim3(256), 0, s, net, ws, lay, b0, lo, hi);
+    hipLaunchKernelGGL(kc5_finalize, dim3(nb), dim3(256), 0, s, net, ws, lay, b0, f_hi, crown);
+    tm->stop(t, s);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ibp

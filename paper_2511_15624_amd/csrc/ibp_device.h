@@ -84,6 +84,14 @@ struct WsLayout {
   int k2_gx = 0;                   // batched base flows: grid x (line tiles padded to a multiple of 8)
   int k3_kper = 0;                 // batched outage sweep: outages per block row
   int k5_by = 0, k5_tiles = 0;     // backward outage sweep: outage chunks, line tiles
+  // linear-relaxation bound (present with the CROWN flag)
+  size_t ccnt = 0;                 // int2 [B][Lp]: per-line (sum s, sum |s|) over outages
+  size_t cv = 0;                   // double4 [B][kc_bx][K]: per-outage (sum s Lam, sum |s Lam|, count)
+  size_t lv = 0;                   // double4 [B][Lp]: per-line (v, vabs, ev)
+  size_t bpart = 0;                // double4 [B][kc3_bx][Np]: per-bus (y, ya, ye) partials
+  size_t cp = 0;                   // double2 [B][n_cp]: per-input partial sums
+  size_t ct = 0;                   // double2 [B][n_ct]: per-line partial sums (limit total, sum vabs)
+  int kc_bx = 0, kc_by = 0, kc3_bx = 0, kc3_by = 0, n_cp = 0, n_ct = 0;
 };
 
 }  // namespace ibp

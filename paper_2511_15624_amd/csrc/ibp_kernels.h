@@ -70,6 +70,11 @@ hipError_t launch_backward_sweeps(const DevNet& net, int64_t n_box, void* ws, co
                                   const double* g_hi, double* d_lo, double* d_hi, hipStream_t s,
                                   KernelTimer* tm);
 
+// Linear-relaxation upper bound after a forward pass (see ibp_crown.hip).
+void plan_crown(const DevNet& net, WsLayout& lay);
+hipError_t launch_crown(const DevNet& net, int64_t n_box, const float* lo, const float* hi, double* f_hi,
+                        double* crown, void* ws, const WsLayout& lay, hipStream_t s, KernelTimer* tm);
+
 // Box splitting rounds (see ibp_split.hip).
 hipError_t launch_split_select(int64_t R, int S, int n_used, int X, const float* leaf_lo, const float* leaf_hi,
                                const double* leaf_fhi, int64_t* sel, float* sel_lo, float* sel_hi, hipStream_t s);

@@ -23,6 +23,7 @@ IBP_F_NONE = 0
 IBP_F_PLAIN = 1
 IBP_F_AUTOTUNE = 2
 IBP_F_BACKWARD = 4
+IBP_F_CROWN = 8
 
 STATUS = {
     0: "IBP_OK",
@@ -45,6 +46,7 @@ EXPORTED = [
     "ibp_workspace_bytes",
     "ibp_bound_boxes",
     "ibp_bound_backward",
+    "ibp_crown_bound_boxes",
     "ibp_set_kernel_timing",
     "ibp_kernel_times",
     "ibp_set_tile",
@@ -56,7 +58,8 @@ EXPORTED = [
 ]
 
 KERNEL_IDS = ["box_prep", "base_flows", "outage_sweep", "finalize", "line_epilogue", "batched_base_flows",
-              "batched_outage_sweep", "backward_outage_sweep", "backward_ptdf_t", "backward_endpoints"]
+              "batched_outage_sweep", "backward_outage_sweep", "backward_ptdf_t", "backward_endpoints",
+              "crown_outage_sweep", "crown_ptdf_t", "crown_inputs"]
 
 
 class IBPError(RuntimeError):
@@ -144,6 +147,8 @@ def load_library(path: str = LIB_PATH):
     lib.ibp_bound_boxes.restype = ctypes.c_int
     lib.ibp_bound_backward.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp, u32]
     lib.ibp_bound_backward.restype = ctypes.c_int
+    lib.ibp_crown_bound_boxes.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, sz, vp, u32]
+    lib.ibp_crown_bound_boxes.restype = ctypes.c_int
     lib.ibp_set_kernel_timing.argtypes = [vp, ctypes.c_int]
     lib.ibp_set_kernel_timing.restype = ctypes.c_int
     lib.ibp_kernel_times.argtypes = [vp, ctypes.c_int32, vp, vp]
@@ -354,6 +359,24 @@ def ibp_bound_backward(net: Network, lo, hi, g_lo, g_hi, flags: int = 0, ws: Wor
                                              _dev_ptr(g_hi), _dev_ptr(d_lo), _dev_ptr(d_hi),
                                              _dev_ptr(buf), buf.numel(), _stream_ptr(stream), flags))
     return d_lo, d_hi
+
+
+def ibp_crown_bound_boxes(net: Network, lo, hi, crown: bool = False, flags: int = 0, ws: Workspace = None,
+                          stream=None):
+    """IBP bounds with f_hi tightened by the linear relaxation of the penalties:
+    (f_lo, f_hi) or, with crown=True, (f_lo, f_hi, relaxation bound alone)."""
+    torch = _torch()
+    lo, hi = _check_boxes(net, lo, hi)
+    n = lo.shape[0]
+    f_lo = torch.empty(n, dtype=torch.float64, device=lo.device)
+    f_hi = torch.empty(n, dtype=torch.float64, device=lo.device)
+    c = torch.empty(n, dtype=torch.float64, device=lo.device) if crown else None
+    ws = ws or Workspace(net)
+    buf, need = ws.get(n, flags | IBP_F_CROWN)
+    _check(load_library().ibp_crown_bound_boxes(net.handle, n, _dev_ptr(lo), _dev_ptr(hi), _dev_ptr(f_lo),
+                                                _dev_ptr(f_hi), _dev_ptr(c), _dev_ptr(buf), buf.numel(),
+                                                _stream_ptr(stream), flags))
+    return (f_lo, f_hi, c) if crown else (f_lo, f_hi)
 
 
 def ibp_autotune(net: Network, lo, hi, stream=None):

@@ -1,0 +1,133 @@
+"""GPU parity of the linear-relaxation (CROWN-style) upper bound against the
+FP64 oracle, through the C ABI.
+
+Bar: where the oracle reports no slope decision within 1e-5 of switching
+(``near == 0``), the GPU bound encloses the oracle's (gpu >= oracle) and lies
+within 1e-5 of it relative to max(|f|, term scale, 1 $); the returned f_hi is
+min(IBP f_hi, relaxation bound) and f_lo is IBP's.  The relaxation is checked
+against the LP of Problem 1 (never below it) on the small network.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2511_15624_amd import ibp, synth
+from tests.test_gpu_forward import gpu_bounds, orc, setup, term_scale
+from tests.test_oracle_pins import _lp_max
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def gpu_crown(n, lo, hi, flags=0):
+    torch = _torch()
+    tlo = torch.from_numpy(np.ascontiguousarray(np.atleast_2d(lo), np.float32)).cuda()
+    thi = torch.from_numpy(np.ascontiguousarray(np.atleast_2d(hi), np.float32)).cuda()
+    out = ibp.ibp_crown_bound_boxes(n, tlo, thi, crown=True, flags=flags)
+    torch.cuda.synchronize()
+    return tuple(o.cpu().numpy() for o in out)
+
+
+def check_box(net, fac, lo, hi, g_lo, g_hi, g_c, ibp_lo, ibp_hi, what):
+    rc = oracle.crown_upper(net, lo, hi, fac)
+    ri = orc(net, lo, hi, fac)
+    # the combined outputs
+    assert g_lo == ibp_lo, what
+    assert g_hi == min(ibp_hi, g_c), what
+    # validity direction: never below the oracle's relaxation when the slopes agree
+    scale = max(abs(rc["f_hi"]), term_scale(ri, "hi"), 1.0)
+    if rc["near"] == 0:
+        assert g_c >= rc["f_hi"], f"{what}: gpu {g_c!r} < oracle {rc['f_hi']!r}"
+        assert (g_c - rc["f_hi"]) / scale <= TOL, f"{what}: gap {g_c - rc['f_hi']!r} (oracle {rc['f_hi']!r})"
+    else:
+        # the GPU's active set is a subset of the oracle's: still above it
+        assert g_c >= rc["f_hi"] - 1e-9 * scale, what
+    print(f"[{what}] ibp {ri['f_hi']:.6e} crown gpu {g_c:.6e} oracle {rc['f_hi']:.6e} "
+          f"active {rc['n_active']} near {rc['near']}", flush=True)
+    return rc
+
+
+def test_tiny_boxes_enclose_the_oracle_and_the_lp():
+    net, fac, n = setup("tiny")
+    lo, hi = synth.full_box(net)
+    blo, bhi = synth.sub_boxes(net, 8, seed=3)
+    x = (0.4 * lo + 0.6 * hi).astype(np.float32)
+    LO = np.vstack([lo[None], blo, x[None]])
+    HI = np.vstack([hi[None], bhi, x[None]])
+    for flags in (0, ibp.IBP_F_PLAIN):
+        f_lo, f_hi, c = gpu_crown(n, LO, HI, flags=flags)
+        i_lo, i_hi = gpu_bounds(n, LO, HI, flags=flags)
+        for b in range(LO.shape[0]):
+            check_box(net, fac, LO[b], HI[b], f_lo[b], f_hi[b], c[b], i_lo[b], i_hi[b], f"tiny box {b} f{flags}")
+            lp = _lp_max(net, LO[b].astype(float), HI[b].astype(float), fac)
+            assert c[b] >= lp - 1e-7 * max(1.0, abs(lp))
+    # tighter than IBP on most sub-boxes
+    assert np.sum(c[1:9] < i_hi[1:9] - 1e-6 * np.abs(i_hi[1:9])) >= 5
+
+
+def test_c500_whole_box_and_sub_boxes():
+    net, fac, n = setup("c500")
+    lo, hi = synth.full_box(net)
+    blo, bhi = synth.sub_boxes(net, 6, seed=9)
+    LO = np.vstack([lo[None], blo])
+    HI = np.vstack([hi[None], bhi])
+    f_lo, f_hi, c = gpu_crown(n, LO, HI)
+    i_lo, i_hi = gpu_bounds(n, LO, HI)
+    for b in range(LO.shape[0]):
+        check_box(net, fac, LO[b], HI[b], f_lo[b], f_hi[b], c[b], i_lo[b], i_hi[b], f"c500 box {b}")
+
+
+def test_c2000_period_boxes_subset():
+    net, fac, n = setup("c2000")
+    lo, hi, _ = synth.period_boxes(net, 2, 4, seed=31)
+    f_lo, f_hi, c = gpu_crown(n, lo, hi)
+    i_lo, i_hi = gpu_bounds(n, lo, hi)
+    for b in (0, 7):
+        check_box(net, fac, lo[b], hi[b], f_lo[b], f_hi[b], c[b], i_lo[b], i_hi[b], f"c2000 box {b}")
+
+
+def test_c8316_whole_box():
+    net, fac, n = setup("c8316")
+    lo, hi = synth.full_box(net)
+    f_lo, f_hi, c = gpu_crown(n, lo, hi)
+    i_lo, i_hi = gpu_bounds(n, lo, hi)
+    check_box(net, fac, lo, hi, f_lo[0], f_hi[0], c[0], i_lo[0], i_hi[0], "c8316 whole box")
+
+
+def test_curves_and_distinct_outage_limits():
+    from tests.test_oracle_pins import _emergency
+    net = _emergency(synth.with_pwl_costs(synth.make_config("c500"), seed=6), 4)
+    fac = oracle.factors(net)
+    n = ibp.Network(net, device=0)
+    blo, bhi = synth.sub_boxes(net, 5, seed=2)
+    f_lo, f_hi, c = gpu_crown(n, blo, bhi)
+    i_lo, i_hi = gpu_bounds(n, blo, bhi)
+    for b in range(5):
+        check_box(net, fac, blo[b], bhi[b], f_lo[b], f_hi[b], c[b], i_lo[b], i_hi[b], f"curves box {b}")
+
+
+def test_bad_boxes_radial_network_and_empty_batch():
+    torch = _torch()
+    net, fac, n = setup("tiny")
+    blo, bhi = synth.sub_boxes(net, 4, seed=5)
+    blo[1, 2] = np.nan
+    bhi[2, 0] = blo[2, 0] - 1.0
+    f_lo, f_hi, c = gpu_crown(n, blo, bhi)
+    assert np.isnan(f_hi[1]) and np.isnan(c[1]) and np.isnan(f_hi[2]) and np.isnan(c[2])
+    for b in (0, 3):
+        assert np.isfinite(c[b]) and c[b] >= oracle.crown_upper(net, blo[b], bhi[b], fac)["f_hi"]
+    rad = synth.make_network(30, 29, 6, 12, seed=8)
+    rfac = oracle.factors(rad)
+    rn = ibp.Network(rad, device=0)
+    lo, hi = synth.full_box(rad)
+    f_lo, f_hi, c = gpu_crown(rn, lo, hi)
+    i_lo, i_hi = gpu_bounds(rn, lo, hi)
+    check_box(rad, rfac, lo, hi, f_lo[0], f_hi[0], c[0], i_lo[0], i_hi[0], "radial")
+    e = torch.empty((0, n.n_input), dtype=torch.float32, device="cuda")
+    a, b = ibp.ibp_crown_bound_boxes(n, e, e)
+    assert a.numel() == 0 and b.numel() == 0
