@@ -241,6 +241,34 @@ def extras(torch, ibp, synth, n4, net4):
         "single_box_box_prep_us": round(kt4["box_prep"][0] / kt4["box_prep"][1] * 1e3, 2),
         "batched_value": ev / (ms3c * 1e-3), "batched_ms": ms3c, "batched_ms_linear_costs": ms,
     }
+    # linear-relaxation upper bound: the large single box, and 1024 sub-boxes of
+    # the 2000-bus network; time and tightening of f_hi against IBP alone
+    wsc = ibp.Workspace(n4)
+    ms_c1 = _time(torch, lambda: ibp.ibp_crown_bound_boxes(n4, s4l, s4h, ws=wsc), 20)
+    n4.set_kernel_timing(True)
+    n4.kernel_times()
+    for _ in range(5):
+        _, c_hi1, c_only1 = ibp.ibp_crown_bound_boxes(n4, s4l, s4h, crown=True, ws=wsc)
+    ktc = n4.kernel_times()
+    n4.set_kernel_timing(False)
+    i_lo1, i_hi1 = ibp.ibp_bound_boxes(n4, s4l, s4h, ws=ws1)
+    c3l, c3h = tlo[:1024].contiguous(), thi[:1024].contiguous()
+    ws3c = ibp.Workspace(n3)
+    ms_c3 = _time(torch, lambda: ibp.ibp_crown_bound_boxes(n3, c3l, c3h, ws=ws3c), 2)
+    ms_i3 = _time(torch, lambda: ibp.ibp_bound_boxes(n3, c3l, c3h, ws=ws3c), 2)
+    _, c_hi3 = ibp.ibp_crown_bound_boxes(n3, c3l, c3h, ws=ws3c)
+    _, i_hi3 = ibp.ibp_bound_boxes(n3, c3l, c3h, ws=ws3c)
+    tight3 = ((i_hi3 - c_hi3) / i_hi3.abs()).cpu()
+    res["crown"] = {
+        "workload": "linear-relaxation upper bound: the large single box; 1024 sub-boxes (2000 buses)",
+        "single_box_ms": ms_c1, "single_box_ms_ibp_only": ms_lin,
+        "single_box_value": ev1 / (ms_c1 * 1e-3), "unit": "evals/s",
+        "single_box_kernel_us": {k: round(v[0] / v[1] * 1e3, 2) for k, v in ktc.items()},
+        "single_box_f_hi_ibp": float(i_hi1[0]), "single_box_f_hi_crown": float(c_only1[0]),
+        "batch_ms": ms_c3, "batch_ms_ibp_only": ms_i3,
+        "batch_value": 1024 * n3.n_ctg * n3.n_line / (ms_c3 * 1e-3),
+        "batch_f_hi_tightening_mean": float(tight3.mean()), "batch_f_hi_tightening_max": float(tight3.max()),
+    }
     # splitting: 4096 roots, 10 rounds of gradient-ranked bisection
     from paper_2511_15624_amd.split import BoxSplitter
     sp = BoxSplitter(n3, t5l, t5h, rounds=10)

@@ -64,6 +64,68 @@ __device__ __forceinline__ float crown_slope(float lam, float cc, float rk, floa
   return tlo > 0.0f ? copysignf(1.0f, C) : 0.0f;
 }
 
+// Sums v[0..23] (eight groups of three) over the 64 lanes of a wave by halving
+// exchanges (12 + 6 + 3, then 3 x 3): afterwards every lane of the 8-lane group
+// g = lane / 8 holds the totals of v[3g], v[3g + 1], v[3g + 2] in v[0..2].
+__device__ __forceinline__ void halving_sum24(double (&v)[24]) {
+  const int lane = threadIdx.x & 63;
+  {
+    const bool up = lane & 32;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      const double send = up ? v[i] : v[i + 12];
+      const double keep = up ? v[i + 12] : v[i];
+      v[i] = keep + __shfl_xor(send, 32, 64);
+    }
+  }
+  {
+    const bool up = lane & 16;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      const double send = up ? v[i] : v[i + 6];
+      const double keep = up ? v[i + 6] : v[i];
+      v[i] = keep + __shfl_xor(send, 16, 64);
+    }
+  }
+  {
+    const bool up = lane & 8;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double send = up ? v[i] : v[i + 3];
+      const double keep = up ? v[i + 3] : v[i];
+      v[i] = keep + __shfl_xor(send, 8, 64);
+    }
+  }
+#pragma unroll
+  for (int m = 4; m >= 1; m >>= 1)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) v[i] += __shfl_xor(v[i], m, 64);
+}
+
+// Slopes of four lines x one outage; per-line counts in registers, the
+// outage's three sums (s Lam, |s Lam|, count) into r[0..2].
+__device__ __forceinline__ void kc1_row(const float4& x, const int4& d, const float4& c4, const float4& g4,
+                                        float (&cs)[4], float (&ca)[4], double* r) {
+  const float cc = __int_as_float(d.y), rk = __int_as_float(d.z);
+  const float s[4] = {crown_slope(x.x, cc, rk, c4.x, g4.x), crown_slope(x.y, cc, rk, c4.y, g4.y),
+                      crown_slope(x.z, cc, rk, c4.z, g4.z), crown_slope(x.w, cc, rk, c4.w, g4.w)};
+  // s Lam is exact in float32; NaN entries carry s = 0 and a finite stand-in
+  const float l[4] = {fminf(x.x, FLT_MAX), fminf(x.y, FLT_MAX), fminf(x.z, FLT_MAX), fminf(x.w, FLT_MAX)};
+  double v = 0.0, a = 0.0;
+  float n = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    cs[i] += s[i];
+    ca[i] += fabsf(s[i]);
+    n += fabsf(s[i]);
+    v += (double)(s[i] * l[i]);
+    a += (double)fabsf(s[i] * l[i]);
+  }
+  r[0] = v;
+  r[1] = a;
+  r[2] = (double)n;
+}
+
 __global__ __launch_bounds__(256) void kc1_sweep(DevNet net, void* ws, WsLayout lay, int64_t box0) {
   __shared__ double shv[4][kKC][2];
   __shared__ float shn[4][kKC];
@@ -87,41 +149,34 @@ __global__ __launch_bounds__(256) void kc1_sweep(DevNet net, void* ws, WsLayout 
   }
   const int4* cd = ws_ptr<int4>(ws, lay.ctg) + b * net.K;
   const float4* lam = reinterpret_cast<const float4*>(net.lodf) + col;
-  float cs0 = 0.f, cs1 = 0.f, cs2 = 0.f, cs3 = 0.f, ca0 = 0.f, ca1 = 0.f, ca2 = 0.f, ca3 = 0.f;
-  for (int k = k0; k < k1; ++k) {
-    double v = 0.0, a = 0.0;
-    float n = 0.0f;
-    if (live) {
-      const float4 x = ld_stream(lam + (size_t)k * Lp4);
-      const int4 d = cd[k];
-      const float cc = __int_as_float(d.y), rk = __int_as_float(d.z);
-      const float s0 = crown_slope(x.x, cc, rk, c4.x, g4.x);
-      const float s1 = crown_slope(x.y, cc, rk, c4.y, g4.y);
-      const float s2 = crown_slope(x.z, cc, rk, c4.z, g4.z);
-      const float s3 = crown_slope(x.w, cc, rk, c4.w, g4.w);
-      cs0 += s0; cs1 += s1; cs2 += s2; cs3 += s3;
-      ca0 += fabsf(s0); ca1 += fabsf(s1); ca2 += fabsf(s2); ca3 += fabsf(s3);
-      n = (fabsf(s0) + fabsf(s1)) + (fabsf(s2) + fabsf(s3));
-      if (n != 0.0f) {
-        // s Lam is exact in float32; NaN entries carry s = 0 and a finite stand-in
-        const float l0 = fminf(x.x, FLT_MAX), l1 = fminf(x.y, FLT_MAX);
-        const float l2 = fminf(x.z, FLT_MAX), l3 = fminf(x.w, FLT_MAX);
-        v = ((double)(s0 * l0) + (double)(s1 * l1)) + ((double)(s2 * l2) + (double)(s3 * l3));
-        a = ((double)(fabsf(s0 * l0)) + (double)(fabsf(s1 * l1))) +
-            ((double)(fabsf(s2 * l2)) + (double)(fabsf(s3 * l3)));
-      }
-    }
-    // a wave with no active element skips the reduction
-    if (__any(n != 0.0f)) {
-      v = wave_sum(v);
-      a = wave_sum(a);
+  float cs[4] = {0.f, 0.f, 0.f, 0.f}, ca[4] = {0.f, 0.f, 0.f, 0.f};
+  // groups of eight outages: eight rows in flight, then one halving reduction
+  for (int kg = k0; kg < k1; kg += 8) {
+    double r[24];
 #pragma unroll
-      for (int m = 32; m >= 1; m >>= 1) n += __shfl_xor(n, m, 64);
+    for (int i = 0; i < 24; ++i) r[i] = 0.0;
+    if (live) {
+      float4 x[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        x[i] = (kg + i < k1) ? ld_stream(lam + (size_t)(kg + i) * Lp4) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (kg + i < k1) kc1_row(x[i], cd[kg + i], c4, g4, cs, ca, r + 3 * i);
     }
-    if (lane == 0) {
-      shv[w][k - k0][0] = v;
-      shv[w][k - k0][1] = a;
-      shn[w][k - k0] = n;
+    // a wave with no active element in the group skips the reduction
+    bool act = false;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) act |= r[3 * i + 2] != 0.0;
+    if (__any(act)) {
+      halving_sum24(r);
+    }
+    // lane 8g holds outage kg + g (zeros when the wave skipped)
+    if ((lane & 7) == 0 && kg + (lane >> 3) < k1) {
+      const int q = kg - k0 + (lane >> 3);
+      shv[w][q][0] = r[0];
+      shv[w][q][1] = r[1];
+      shn[w][q] = (float)r[2];
     }
   }
   __syncthreads();
@@ -136,7 +191,6 @@ __global__ __launch_bounds__(256) void kc1_sweep(DevNet net, void* ws, WsLayout 
   if (live) {
     // per-line counts: integer atomics, so the totals do not depend on the order
     int2* cnt = ws_ptr<int2>(ws, lay.ccnt) + b * net.Lp + 4 * col;
-    const float cs[4] = {cs0, cs1, cs2, cs3}, ca[4] = {ca0, ca1, ca2, ca3};
 #pragma unroll
     for (int i = 0; i < 4; ++i)
       if (ca[i] != 0.0f) {
@@ -213,25 +267,33 @@ __global__ __launch_bounds__(256) void kc3_ptdf_t(DevNet net, void* ws, WsLayout
   const int n0 = blockIdx.y * kNB;
   const int n1 = min(net.N, n0 + kNB);
   const float4* ph = reinterpret_cast<const float4*>(net.phiT) + col;
-  for (int n = n0; n < n1; ++n) {
-    double y = 0.0, ya = 0.0, ye = 0.0;
-    if (live) {
-      const float4 x = ld_stream(ph + (size_t)n * Lp4);
-      const double p[4] = {(double)x.x, (double)x.y, (double)x.z, (double)x.w};
+  // groups of eight buses: eight rows in flight, then one halving reduction
+  for (int ng = n0; ng < n1; ng += 8) {
+    double r[24];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        y = fma(p[i], v[i], y);
-        ya = fma(fabs(p[i]), va[i], ya);
-        ye = fma(fabs(p[i]), ev[i], ye);
+    for (int i = 0; i < 24; ++i) r[i] = 0.0;
+    if (live) {
+      float4 x[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        x[i] = (ng + i < n1) ? ld_stream(ph + (size_t)(ng + i) * Lp4) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const double p[4] = {(double)x[i].x, (double)x[i].y, (double)x[i].z, (double)x[i].w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          r[3 * i] = fma(p[q], v[q], r[3 * i]);
+          r[3 * i + 1] = fma(fabs(p[q]), va[q], r[3 * i + 1]);
+          r[3 * i + 2] = fma(fabs(p[q]), ev[q], r[3 * i + 2]);
+        }
       }
     }
-    y = wave_sum(y);
-    ya = wave_sum(ya);
-    ye = wave_sum(ye);
-    if (lane == 0) {
-      sh[w][n - n0][0] = y;
-      sh[w][n - n0][1] = ya;
-      sh[w][n - n0][2] = ye;
+    halving_sum24(r);
+    if ((lane & 7) == 0 && ng + (lane >> 3) < n1) {
+      const int q = ng - n0 + (lane >> 3);
+      sh[w][q][0] = r[0];
+      sh[w][q][1] = r[1];
+      sh[w][q][2] = r[2];
     }
   }
   __syncthreads();
