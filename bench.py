@@ -275,7 +275,7 @@ def extras(torch, ibp, synth, n4, net4):
     torch.cuda.synchronize()
     gap0 = float(sp.gap().sum())
     hist = sp.run(10)
-    gap10, secs = hist[-1]
+    gap10, secs = hist[-1][:2]
     res["splitting"] = {"workload": "2000 buses, 4096 root boxes, 10 rounds (2 children + 2 centre points "
                                     "per root per round)",
                         "gap_reduction_per_s": (gap0 - gap10) / secs, "unit": "$/s",

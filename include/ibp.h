@@ -186,12 +186,16 @@ ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box,
  *   f_lo, f_hi : device float64 [n_box]: IBP's f_lo, and min(IBP f_hi,
  *                relaxation bound) -- both still certified.
  *   crown_hi   : device float64 [n_box] or NULL: the relaxation bound alone.
+ *   vertex     : device float32 [n_box x X] or NULL: the box vertex that
+ *                maximises the relaxation's linear part (hi_j where its
+ *                coefficient is >= 0, else lo_j), a candidate point for
+ *                lower bounds on max f.
  *   ws, ws_bytes: at least ibp_workspace_bytes(net, n_box, flags | IBP_F_CROWN).
  * flags: 0 or IBP_F_PLAIN (forward kernels as in ibp_bound_boxes).  Invalid
  * boxes get NaN.  Errors: INVALID_ARG, WORKSPACE, HOST_ONLY, DEVICE. */
 ibp_status ibp_crown_bound_boxes(const ibp_network* net, int64_t n_box,
                                  const float* box_lo, const float* box_hi,
-                                 double* f_lo, double* f_hi, double* crown_hi,
+                                 double* f_lo, double* f_hi, double* crown_hi, float* vertex,
                                  void* ws, size_t ws_bytes, void* stream, uint32_t flags);
 
 /* Kernel timing for benchmarks and profiling.  While enabled, every compute
@@ -221,39 +225,58 @@ ibp_status ibp_set_tile(ibp_network* net, int32_t k2_nc, int32_t k3_kc);
 ibp_status ibp_autotune(ibp_network* net, int64_t n_box, const float* box_lo, const float* box_hi,
                         void* ws, size_t ws_bytes, void* stream, int32_t* chosen);
 
-/* Box splitting (branching on the input box; the paper names branch and bound
- * over the inputs as the way to tighten IBP bounds, Sec. I and Sec. V).
- * n_root roots each own `slots` leaf slots (leaf i of root r is row r*slots+i
- * of leaf_lo/leaf_hi, device float32 [n_root*slots x n_input]); slots
- * [0, n_used) hold leaves that partition the root.  One round:
- *   ibp_split_select: per root, the leaf with the largest f_hi (leaf_fhi,
- *     device float64 [n_root*slots]); its row index goes to sel (device int64
- *     [n_root]) and a copy to sel_lo/sel_hi (device float32 [n_root x n_input]).
+/* Branch and bound over input boxes (the paper names branch and bound over
+ * the inputs as the way to tighten IBP bounds, Sec. I and Sec. V, and screens
+ * instances for max f < 0, Sec. III-D eq. (inf-or-wn)).
+ * Every root owns `slots` leaf slots: leaf q of root r is row r*slots + q of
+ * leaf_lo/leaf_hi (device float32 [n_root*slots x n_input]) with its upper
+ * bound in leaf_fhi (device float64 [n_root*slots]); n_leaf (device int32
+ * [n_root]) counts the used slots, which partition the root.  A round works on
+ * n_act active roots: roots (device int64 [n_act], ascending, or NULL for
+ * roots 0..n_act-1).  Rows "i" below are dense over the active list.
+ *   ibp_split_select: per active root, the leaf with the largest f_hi; its
+ *     row index goes to sel (device int64 [n_act]) and a copy to
+ *     sel_lo/sel_hi (device float32 [n_act x n_input]).
  *   (the caller runs ibp_bound_backward on sel_lo/sel_hi with g_f_lo = 0,
  *    g_f_hi = 1 to get g_lo/g_hi)
- *   ibp_split_bisect: per root, splits the selected leaf at the float32
- *     midpoint of the coordinate j maximising (g_hi_j - g_lo_j) * (hi_j - lo_j)/2;
- *     the halves replace slot sel and fill slot n_used (requires n_used < slots),
- *     and are also written to kid_lo/kid_hi (device [2*n_root x n_input], rows
- *     2r, 2r+1) with their centre points in centers (same shape).  A leaf with no
- *     float32 strictly inside any coordinate is duplicated.
- *   (the caller bounds the children and the zero-width centre boxes)
- *   ibp_split_update: writes the children's f_hi into leaf_fhi, sets
- *     root_ub[r] = min(root_ub[r], max leaf f_hi) and
- *     root_lb[r] = max(root_lb[r], centre f_lo)
- *     (device float64 [n_root]); n_used_after = n_used + 1.
+ *   ibp_split_bisect: splits the selected leaf at the float32 midpoint of the
+ *     coordinate j maximising (g_hi_j - g_lo_j) * (hi_j - lo_j)/2; the halves
+ *     replace slot sel and fill slot n_leaf[r] when n_leaf[r] < slots (a root
+ *     with no free slot is left unchanged), and are written to kid_lo/kid_hi
+ *     (device [2*n_act x n_input], rows 2i, 2i+1) with their centre points in
+ *     centers (same shape).  A leaf with no float32 strictly inside any
+ *     coordinate is duplicated.
+ *   (the caller bounds the children and evaluates points_per_root points per
+ *    root as zero-width boxes: points device float32
+ *    [n_act x points_per_root x n_input], their f_lo in point_flo)
+ *   ibp_split_update: writes the children's f_hi into leaf_fhi, increments
+ *     n_leaf, sets root_ub[r] = min(root_ub[r], max leaf f_hi) and
+ *     root_lb[r] = max(root_lb[r], best point value) (device float64
+ *     [n_root]); when the point improves root_lb and root_x is not NULL, the
+ *     point is copied to row r of root_x (device float32 [n_root x n_input]).
+ *   ibp_split_screen: status[r] (device int32 [n_root]) = 1 if root_ub < 0
+ *     (max f < 0 certified: welfare-negative or infeasible), 2 if
+ *     root_lb >= 0 (a point with f >= 0 certified), 3 if
+ *     root_ub - root_lb <= rel_tol * max(1, |root_ub|), 4 if a bound is NaN,
+ *     else 0 (open); the open roots are written to open_roots (device int64
+ *     [n_root], ascending) and their count to *n_open (device int64).
  * All asynchronous on `stream`; host-checkable errors: INVALID_ARG. */
-ibp_status ibp_split_select(int64_t n_root, int32_t slots, int32_t n_used, int32_t n_input,
-                            const float* leaf_lo, const float* leaf_hi, const double* leaf_fhi,
-                            int64_t* sel, float* sel_lo, float* sel_hi, void* stream);
-ibp_status ibp_split_bisect(int64_t n_root, int32_t slots, int32_t n_used, int32_t n_input,
-                            float* leaf_lo, float* leaf_hi, const int64_t* sel,
+ibp_status ibp_split_select(int64_t n_act, const int64_t* roots, int32_t slots, const int32_t* n_leaf,
+                            int32_t n_input, const float* leaf_lo, const float* leaf_hi,
+                            const double* leaf_fhi, int64_t* sel, float* sel_lo, float* sel_hi,
+                            void* stream);
+ibp_status ibp_split_bisect(int64_t n_act, const int64_t* roots, int32_t slots, const int32_t* n_leaf,
+                            int32_t n_input, float* leaf_lo, float* leaf_hi, const int64_t* sel,
                             const float* sel_lo, const float* sel_hi,
                             const double* g_lo, const double* g_hi,
                             float* kid_lo, float* kid_hi, float* centers, void* stream);
-ibp_status ibp_split_update(int64_t n_root, int32_t slots, int32_t n_used_after, const int64_t* sel,
-                            const double* kid_fhi, const double* center_flo, double* leaf_fhi,
-                            double* root_ub, double* root_lb, void* stream);
+ibp_status ibp_split_update(int64_t n_act, const int64_t* roots, int32_t slots, int32_t* n_leaf,
+                            const int64_t* sel, const double* kid_fhi, int32_t points_per_root,
+                            const double* point_flo, const float* points, int32_t n_input,
+                            double* leaf_fhi, double* root_ub, double* root_lb, float* root_x,
+                            void* stream);
+ibp_status ibp_split_screen(int64_t n_root, const double* root_ub, const double* root_lb, double rel_tol,
+                            int32_t* status, int64_t* open_roots, int64_t* n_open, void* stream);
 
 /* Last error message of the calling thread ("" if none). */
 const char* ibp_last_error(void);

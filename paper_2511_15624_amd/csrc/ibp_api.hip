@@ -442,8 +442,8 @@ ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box, const float
 }
 
 ibp_status ibp_crown_bound_boxes(const ibp_network* net, int64_t n_box, const float* box_lo,
-                                 const float* box_hi, double* f_lo, double* f_hi, double* crown_hi, void* ws,
-                                 size_t ws_bytes, void* stream, uint32_t flags) {
+                                 const float* box_hi, double* f_lo, double* f_hi, double* crown_hi,
+                                 float* vertex, void* ws, size_t ws_bytes, void* stream, uint32_t flags) {
   g_err.clear();
   if (flags & ~uint32_t(IBP_F_PLAIN)) return fail(IBP_E_INVALID_ARG, "flags: only IBP_F_PLAIN is accepted");
   ibp::WsLayout lay;
@@ -455,7 +455,8 @@ ibp_status ibp_crown_bound_boxes(const ibp_network* net, int64_t n_box, const fl
   hipStream_t s = static_cast<hipStream_t>(stream);
   ibp::KernelTimer* tm = const_cast<ibp::KernelTimer*>(&net->timer);
   hipError_t e = ibp::launch_forward(net->dn, n_box, box_lo, box_hi, f_lo, f_hi, nullptr, ws, lay, s, tm);
-  if (e == hipSuccess) e = ibp::launch_crown(net->dn, n_box, box_lo, box_hi, f_hi, crown_hi, ws, lay, s, tm);
+  if (e == hipSuccess)
+    e = ibp::launch_crown(net->dn, n_box, box_lo, box_hi, f_hi, crown_hi, vertex, ws, lay, s, tm);
   if (e != hipSuccess) return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
   return IBP_OK;
 }
@@ -561,49 +562,63 @@ ibp_status ibp_autotune(ibp_network* net, int64_t n_box, const float* box_lo, co
   return IBP_OK;
 }
 
-ibp_status ibp_split_select(int64_t n_root, int32_t slots, int32_t n_used, int32_t n_input,
-                            const float* leaf_lo, const float* leaf_hi, const double* leaf_fhi,
+ibp_status ibp_split_select(int64_t n_act, const int64_t* roots, int32_t slots, const int32_t* n_leaf,
+                            int32_t n_input, const float* leaf_lo, const float* leaf_hi, const double* leaf_fhi,
                             int64_t* sel, float* sel_lo, float* sel_hi, void* stream) {
   g_err.clear();
-  if (n_root < 0 || slots < 1 || n_used < 1 || n_used > slots || n_input < 1)
-    return fail(IBP_E_INVALID_ARG, "bad split sizes");
-  if (n_root == 0) return IBP_OK;
-  if (!leaf_lo || !leaf_hi || !leaf_fhi || !sel || !sel_lo || !sel_hi)
+  if (n_act < 0 || slots < 1 || n_input < 1) return fail(IBP_E_INVALID_ARG, "bad split sizes");
+  if (n_act == 0) return IBP_OK;
+  if (n_act > 0x7fffffff) return fail(IBP_E_INVALID_ARG, "too many roots");
+  if (!n_leaf || !leaf_lo || !leaf_hi || !leaf_fhi || !sel || !sel_lo || !sel_hi)
     return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
-  if (n_root > 0x7fffffff) return fail(IBP_E_INVALID_ARG, "too many roots");
-  hipError_t e = ibp::launch_split_select(n_root, slots, n_used, n_input, leaf_lo, leaf_hi, leaf_fhi, sel, sel_lo,
-                                          sel_hi, static_cast<hipStream_t>(stream));
+  hipError_t e = ibp::launch_split_select(n_act, roots, slots, n_leaf, n_input, leaf_lo, leaf_hi, leaf_fhi, sel,
+                                          sel_lo, sel_hi, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? IBP_OK : fail(IBP_E_DEVICE, hipGetErrorString(e));
 }
 
-ibp_status ibp_split_bisect(int64_t n_root, int32_t slots, int32_t n_used, int32_t n_input,
-                            float* leaf_lo, float* leaf_hi, const int64_t* sel,
-                            const float* sel_lo, const float* sel_hi,
-                            const double* g_lo, const double* g_hi,
+ibp_status ibp_split_bisect(int64_t n_act, const int64_t* roots, int32_t slots, const int32_t* n_leaf,
+                            int32_t n_input, float* leaf_lo, float* leaf_hi, const int64_t* sel,
+                            const float* sel_lo, const float* sel_hi, const double* g_lo, const double* g_hi,
                             float* kid_lo, float* kid_hi, float* centers, void* stream) {
   g_err.clear();
-  if (n_root < 0 || slots < 2 || n_used < 1 || n_used >= slots || n_input < 1)
-    return fail(IBP_E_INVALID_ARG, "bad split sizes (need n_used < slots)");
-  if (n_root == 0) return IBP_OK;
-  if (!leaf_lo || !leaf_hi || !sel || !sel_lo || !sel_hi || !g_lo || !g_hi || !kid_lo || !kid_hi || !centers)
+  if (n_act < 0 || slots < 2 || n_input < 1) return fail(IBP_E_INVALID_ARG, "bad split sizes (need slots >= 2)");
+  if (n_act == 0) return IBP_OK;
+  if (n_act > 0x7fffffff) return fail(IBP_E_INVALID_ARG, "too many roots");
+  if (!n_leaf || !leaf_lo || !leaf_hi || !sel || !sel_lo || !sel_hi || !g_lo || !g_hi || !kid_lo || !kid_hi ||
+      !centers)
     return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
-  if (n_root > 0x7fffffff) return fail(IBP_E_INVALID_ARG, "too many roots");
-  hipError_t e = ibp::launch_split_bisect(n_root, slots, n_used, n_input, leaf_lo, leaf_hi, sel, sel_lo, sel_hi,
-                                          g_lo, g_hi, kid_lo, kid_hi, centers, static_cast<hipStream_t>(stream));
+  hipError_t e = ibp::launch_split_bisect(n_act, roots, slots, n_leaf, n_input, leaf_lo, leaf_hi, sel, sel_lo,
+                                          sel_hi, g_lo, g_hi, kid_lo, kid_hi, centers,
+                                          static_cast<hipStream_t>(stream));
   return e == hipSuccess ? IBP_OK : fail(IBP_E_DEVICE, hipGetErrorString(e));
 }
 
-ibp_status ibp_split_update(int64_t n_root, int32_t slots, int32_t n_used_after, const int64_t* sel,
-                            const double* kid_fhi, const double* center_flo, double* leaf_fhi,
-                            double* root_ub, double* root_lb, void* stream) {
+ibp_status ibp_split_update(int64_t n_act, const int64_t* roots, int32_t slots, int32_t* n_leaf,
+                            const int64_t* sel, const double* kid_fhi, int32_t points_per_root,
+                            const double* point_flo, const float* points, int32_t n_input, double* leaf_fhi,
+                            double* root_ub, double* root_lb, float* root_x, void* stream) {
   g_err.clear();
-  if (n_root < 0 || slots < 2 || n_used_after < 2 || n_used_after > slots)
+  if (n_act < 0 || slots < 2 || points_per_root < 0 || n_input < 1)
     return fail(IBP_E_INVALID_ARG, "bad split sizes");
-  if (n_root == 0) return IBP_OK;
-  if (!sel || !kid_fhi || !center_flo || !leaf_fhi || !root_ub || !root_lb)
+  if (n_act == 0) return IBP_OK;
+  if (n_act > 0x7fffffff) return fail(IBP_E_INVALID_ARG, "too many roots");
+  if (!n_leaf || !sel || !kid_fhi || !leaf_fhi || !root_ub || !root_lb ||
+      (points_per_root > 0 && !point_flo) || (root_x && points_per_root > 0 && !points))
     return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
-  hipError_t e = ibp::launch_split_update(n_root, slots, n_used_after, sel, kid_fhi, center_flo, leaf_fhi,
-                                          root_ub, root_lb, static_cast<hipStream_t>(stream));
+  hipError_t e = ibp::launch_split_update(n_act, roots, slots, n_leaf, sel, kid_fhi, points_per_root, point_flo,
+                                          points, n_input, leaf_fhi, root_ub, root_lb, root_x,
+                                          static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? IBP_OK : fail(IBP_E_DEVICE, hipGetErrorString(e));
+}
+
+ibp_status ibp_split_screen(int64_t n_root, const double* root_ub, const double* root_lb, double rel_tol,
+                            int32_t* status, int64_t* open_roots, int64_t* n_open, void* stream) {
+  g_err.clear();
+  if (n_root < 0 || !(rel_tol >= 0.0)) return fail(IBP_E_INVALID_ARG, "bad screening arguments");
+  if (!root_ub || !root_lb || !status || !open_roots || !n_open)
+    return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
+  hipError_t e = ibp::launch_split_screen(n_root, root_ub, root_lb, rel_tol, status, open_roots, n_open,
+                                          static_cast<hipStream_t>(stream));
   return e == hipSuccess ? IBP_OK : fail(IBP_E_DEVICE, hipGetErrorString(e));
 }
 

@@ -31,7 +31,8 @@
 //   KC1  outage sweep: slopes, per-line integer counts, per-outage float64 sums
 //   KC2  per line: adjoint v, its absolute bound and error, limit totals
 //   KC3  per bus: Phi^T v, |Phi|^T vabs, |Phi|^T ev (float64)
-//   KC4  per input: coefficient, error bound, box maximum (and curve interval)
+//   KC4  per input: coefficient, error bound, box maximum (and curve interval),
+//        and the maximising vertex
 //   KC5  per box: total, outward padding, min with IBP's f_hi
 #include <hip/hip_runtime.h>
 
@@ -311,7 +312,8 @@ __global__ __launch_bounds__(256) void kc3_ptdf_t(DevNet net, void* ws, WsLayout
 // G_j x_j (plus the curve interval's upper end); block partials (sum, sum |.|).
 __global__ __launch_bounds__(256) void kc4_inputs(DevNet net, void* ws, WsLayout lay, int64_t box0,
                                                   const float* __restrict__ box_lo,
-                                                  const float* __restrict__ box_hi) {
+                                                  const float* __restrict__ box_hi,
+                                                  float* __restrict__ vertex) {
   __shared__ double sh[4];
   const int64_t b = box0 + blockIdx.y;
   const int j = blockIdx.x * 256 + threadIdx.x;
@@ -349,7 +351,9 @@ __global__ __launch_bounds__(256) void kc4_inputs(DevNet net, void* ws, WsLayout
     const double E = zf * ((kKappa0 + gam) * ya + (1.0 + kKappa0) * ye + 2.0 * net.phi_err_max * SV) *
                          (1.0 + 8.0 * kU64) +
                      4.0 * kU64 * (fabs(wj) + zi + zf * fabs(y));
-    const double l = box_lo[b * net.X + j], hh = box_hi[b * net.X + j];
+    const float l32 = box_lo[b * net.X + j], h32 = box_hi[b * net.X + j];
+    if (vertex) vertex[b * net.X + j] = G >= 0.0 ? h32 : l32;
+    const double l = l32, hh = h32;
     const double c = 0.5 * (l + hh), r = 0.5 * (hh - l);
     const double m = fabs(c) + r;
     h = G * c + fabs(G) * r + E * m;
@@ -407,7 +411,8 @@ void plan_crown(const DevNet& net, WsLayout& lay) {
 }
 
 hipError_t launch_crown(const DevNet& net, int64_t n_box, const float* lo, const float* hi, double* f_hi,
-                        double* crown, void* ws, const WsLayout& lay, hipStream_t s, KernelTimer* tm) {
+                        double* crown, float* vertex, void* ws, const WsLayout& lay, hipStream_t s,
+                        KernelTimer* tm) {
   for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
     const int nb = (int)std::min<int64_t>(65535, n_box - b0);
     int t = tm->start(10, s);
@@ -422,7 +427,7 @@ hipError_t launch_crown(const DevNet& net, int64_t n_box, const float* lo, const
     hipLaunchKernelGGL(kc3_ptdf_t, dim3(lay.kc3_bx, lay.kc3_by, nb), dim3(256), 0, s, net, ws, lay, b0);
     tm->stop(t, s);
     t = tm->start(12, s);
-    hipLaunchKernelGGL(kc4_inputs, dim3(lay.n_cp, nb), dim3(256), 0, s, net, ws, lay, b0, lo, hi);
+    hipLaunchKernelGGL(kc4_inputs, dim3(lay.n_cp, nb), dim3(256), 0, s, net, ws, lay, b0, lo, hi, vertex);
     hipLaunchKernelGGL(kc5_finalize, dim3(nb), dim3(256), 0, s, net, ws, lay, b0, f_hi, crown);
     tm->stop(t, s);
   }

@@ -73,17 +73,22 @@ hipError_t launch_backward_sweeps(const DevNet& net, int64_t n_box, void* ws, co
 // Linear-relaxation upper bound after a forward pass (see ibp_crown.hip).
 void plan_crown(const DevNet& net, WsLayout& lay);
 hipError_t launch_crown(const DevNet& net, int64_t n_box, const float* lo, const float* hi, double* f_hi,
-                        double* crown, void* ws, const WsLayout& lay, hipStream_t s, KernelTimer* tm);
+                        double* crown, float* vertex, void* ws, const WsLayout& lay, hipStream_t s,
+                        KernelTimer* tm);
 
-// Box splitting rounds (see ibp_split.hip).
-hipError_t launch_split_select(int64_t R, int S, int n_used, int X, const float* leaf_lo, const float* leaf_hi,
-                               const double* leaf_fhi, int64_t* sel, float* sel_lo, float* sel_hi, hipStream_t s);
-hipError_t launch_split_bisect(int64_t R, int S, int n_used, int X, float* leaf_lo, float* leaf_hi,
-                               const int64_t* sel, const float* sel_lo, const float* sel_hi, const double* g_lo,
-                               const double* g_hi, float* kid_lo, float* kid_hi, float* cen, hipStream_t s);
-hipError_t launch_split_update(int64_t R, int S, int n_used_after, const int64_t* sel, const double* kid_fhi,
-                               const double* cen_flo, double* leaf_fhi, double* root_ub, double* root_lb,
+// Branch-and-bound rounds over input boxes (see ibp_split.hip).
+hipError_t launch_split_select(int64_t n, const int64_t* roots, int S, const int* n_leaf, int X,
+                               const float* leaf_lo, const float* leaf_hi, const double* leaf_fhi, int64_t* sel,
+                               float* sel_lo, float* sel_hi, hipStream_t s);
+hipError_t launch_split_bisect(int64_t n, const int64_t* roots, int S, const int* n_leaf, int X, float* leaf_lo,
+                               float* leaf_hi, const int64_t* sel, const float* sel_lo, const float* sel_hi,
+                               const double* g_lo, const double* g_hi, float* kid_lo, float* kid_hi, float* cen,
                                hipStream_t s);
+hipError_t launch_split_update(int64_t n, const int64_t* roots, int S, int* n_leaf, const int64_t* sel,
+                               const double* kid_fhi, int pts, const double* point_flo, const float* points, int X,
+                               double* leaf_fhi, double* root_ub, double* root_lb, float* root_x, hipStream_t s);
+hipError_t launch_split_screen(int64_t R, const double* root_ub, const double* root_lb, double rel_tol, int* status,
+                               int64_t* open_roots, int64_t* n_open, hipStream_t s);
 
 // K1..K4 for n_box boxes, each box handled by its own grid slice.
 hipError_t launch_forward_single(const DevNet& net, int64_t n_box, const float* lo, const float* hi,

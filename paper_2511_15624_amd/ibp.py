@@ -54,6 +54,7 @@ EXPORTED = [
     "ibp_split_select",
     "ibp_split_bisect",
     "ibp_split_update",
+    "ibp_split_screen",
     "ibp_last_error",
 ]
 
@@ -147,7 +148,7 @@ def load_library(path: str = LIB_PATH):
     lib.ibp_bound_boxes.restype = ctypes.c_int
     lib.ibp_bound_backward.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp, u32]
     lib.ibp_bound_backward.restype = ctypes.c_int
-    lib.ibp_crown_bound_boxes.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, sz, vp, u32]
+    lib.ibp_crown_bound_boxes.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp, u32]
     lib.ibp_crown_bound_boxes.restype = ctypes.c_int
     lib.ibp_set_kernel_timing.argtypes = [vp, ctypes.c_int]
     lib.ibp_set_kernel_timing.restype = ctypes.c_int
@@ -158,12 +159,14 @@ def load_library(path: str = LIB_PATH):
     lib.ibp_autotune.argtypes = [vp, i64, vp, vp, vp, sz, vp, vp]
     lib.ibp_autotune.restype = ctypes.c_int
     i32 = ctypes.c_int32
-    lib.ibp_split_select.argtypes = [i64, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp]
+    lib.ibp_split_select.argtypes = [i64, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     lib.ibp_split_select.restype = ctypes.c_int
-    lib.ibp_split_bisect.argtypes = [i64, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.ibp_split_bisect.argtypes = [i64, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.ibp_split_bisect.restype = ctypes.c_int
-    lib.ibp_split_update.argtypes = [i64, i32, i32, vp, vp, vp, vp, vp, vp, vp]
+    lib.ibp_split_update.argtypes = [i64, vp, i32, vp, vp, vp, i32, vp, vp, i32, vp, vp, vp, vp, vp]
     lib.ibp_split_update.restype = ctypes.c_int
+    lib.ibp_split_screen.argtypes = [i64, vp, vp, ctypes.c_double, vp, vp, vp, vp]
+    lib.ibp_split_screen.restype = ctypes.c_int
     lib.ibp_last_error.argtypes = []
     lib.ibp_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -362,9 +365,11 @@ def ibp_bound_backward(net: Network, lo, hi, g_lo, g_hi, flags: int = 0, ws: Wor
 
 
 def ibp_crown_bound_boxes(net: Network, lo, hi, crown: bool = False, flags: int = 0, ws: Workspace = None,
-                          stream=None):
+                          stream=None, vertex=None):
     """IBP bounds with f_hi tightened by the linear relaxation of the penalties:
-    (f_lo, f_hi) or, with crown=True, (f_lo, f_hi, relaxation bound alone)."""
+    (f_lo, f_hi) or, with crown=True, (f_lo, f_hi, relaxation bound alone).
+    ``vertex``: optional float32 device tensor [n_box, X] that receives the box
+    vertex maximising the relaxation's linear part."""
     torch = _torch()
     lo, hi = _check_boxes(net, lo, hi)
     n = lo.shape[0]
@@ -373,9 +378,12 @@ def ibp_crown_bound_boxes(net: Network, lo, hi, crown: bool = False, flags: int 
     c = torch.empty(n, dtype=torch.float64, device=lo.device) if crown else None
     ws = ws or Workspace(net)
     buf, need = ws.get(n, flags | IBP_F_CROWN)
+    if vertex is not None and (vertex.dtype != torch.float32 or tuple(vertex.shape) != tuple(lo.shape)
+                               or not vertex.is_contiguous() or vertex.device != lo.device):
+        raise ValueError("vertex must be a contiguous float32 device tensor shaped like the boxes")
     _check(load_library().ibp_crown_bound_boxes(net.handle, n, _dev_ptr(lo), _dev_ptr(hi), _dev_ptr(f_lo),
-                                                _dev_ptr(f_hi), _dev_ptr(c), _dev_ptr(buf), buf.numel(),
-                                                _stream_ptr(stream), flags))
+                                                _dev_ptr(f_hi), _dev_ptr(c), _dev_ptr(vertex), _dev_ptr(buf),
+                                                buf.numel(), _stream_ptr(stream), flags))
     return (f_lo, f_hi, c) if crown else (f_lo, f_hi)
 
 

@@ -127,13 +127,15 @@ def test_compute_calls_need_a_device_handle(lib):
 
 
 def test_split_calls_validate_sizes_before_any_device_work(lib):
-    st = lib.ibp_split_bisect(4, 3, 3, 5, None, None, None, None, None, None, None, None, None, None, None)
-    assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"      # needs a free slot (n_used < slots)
-    st = lib.ibp_split_select(4, 3, 1, 5, None, None, None, None, None, None, None)
+    st = lib.ibp_split_bisect(4, None, 1, None, 5, *([None] * 10), None)
+    assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"      # needs at least two slots
+    st = lib.ibp_split_select(4, None, 3, None, 5, None, None, None, None, None, None, None)
     assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"      # NULL device pointers
-    st = lib.ibp_split_update(4, 3, 4, None, None, None, None, None, None, None)
-    assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"      # n_used_after > slots
-    assert lib.ibp_split_select(0, 3, 1, 5, None, None, None, None, None, None, None) == 0
+    st = lib.ibp_split_update(4, None, 3, None, None, None, -1, None, None, 5, None, None, None, None, None)
+    assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"      # negative point count
+    st = lib.ibp_split_screen(4, None, None, -1.0, None, None, None, None)
+    assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"      # negative tolerance
+    assert lib.ibp_split_select(0, None, 3, None, 5, None, None, None, None, None, None, None) == 0
 
 
 def test_curve_descriptions_validated():
