@@ -30,79 +30,98 @@ namespace ibp {
 
 // ---------------------------------------------------------------- K1
 
-// One wave per 64 buses / 64 inputs of a box: injection intervals rounded
-// outward to float32, and partial float64 sums for the surplus, the total
-// injection and the padding constants.
+// Injection interval of bus n, p_inj = N_g p_g - N_d p_d, rounded outward to
+// float32: out = (c32, r''), where r'' also covers the float32 storage error
+// of the PTDF entries it will multiply; mc = |c32|, mbox = |c32| + r32.
+__device__ __forceinline__ void bus_injection(const DevNet& net, const float* __restrict__ lo,
+                                              const float* __restrict__ hi, int n, double2& out, double& mc,
+                                              double& mbox) {
+  double c = 0, r = 0, a = 0;
+  int cnt = 0;
+  const int e0 = net.bus_ptr[n], e1 = net.bus_ptr[n + 1];
+  for (int e = e0; e < e1; ++e) {
+    const int j = net.bus_dev[e];
+    const double l = lo[j], h = hi[j];
+    const double cj = 0.5 * (l + h), rj = 0.5 * (h - l);
+    c += (j < net.G) ? cj : -cj;
+    r += rj;
+    a += fabs(cj);
+    ++cnt;
+  }
+  // float64 summation error of c and r (cnt terms each)
+  const double e64 = (cnt + 1) * kU64 * (a + r) * 1.01;
+  const float c32 = (float)c;
+  const float r32 = ru32((r + 2.0 * e64 + fabs(c - (double)c32)) * (1.0 + 4.0 * kU64));
+  // radius inflated for the float32 rounding of the PTDF entries
+  const float rp = ru32(((1.0 + kKappa0) * (double)r32 + kKappa0 * fabs((double)c32)) * (1.0 + 4.0 * kU64));
+  out = make_double2((double)c32, (double)rp);
+  mc = fabs((double)c32);
+  mbox = fabs((double)c32) + (double)r32;
+}
+
+// Per-input terms of the box-preparation sums: surplus (linear part and
+// curves), total injection, validity.  Centre and radius of float32 endpoints
+// are exact in float64.
+__device__ __forceinline__ void input_terms(const DevNet& net, const float* __restrict__ lo,
+                                            const float* __restrict__ hi, int i, double (&v)[kP1Fields]) {
+  const double l = lo[i], h = hi[i];
+  if (!(l <= h) || !isfinite(l) || !isfinite(h)) v[kP1Bad] += 1.0;
+  const double c = 0.5 * (l + h), r = 0.5 * (h - l);
+  const double w = net.dev_w[i];
+  v[kP1Sc] += w * c;
+  v[kP1Sr] += fabs(w) * r;
+  v[kP1Sabs] += fabs(w * c) + fabs(w) * r;
+  v[kP1cI] += (i < net.G) ? c : -c;
+  v[kP1rI] += r;
+  v[kP1cIabs] += fabs(c);
+  if (net.seg_ptr) {
+    // curve term: loads add [F_lo, F_hi], generators subtract it
+    const int s0 = net.seg_ptr[i], s1 = net.seg_ptr[i + 1];
+    if (s1 > s0) {
+      double F_lo, F_hi, e;
+      curve_ibp(net.seg, s0, s1, c, r, F_lo, F_hi, e);
+      const double sc = (i < net.G ? -0.5 : 0.5) * (F_lo + F_hi);
+      const double sr = 0.5 * (F_hi - F_lo) + e + 1.01 * kU64 * (fabs(F_lo) + fabs(F_hi));
+      v[kP1Sc] += sc;
+      v[kP1Sr] += sr;
+      v[kP1Sabs] += fabs(sc) + sr;
+    }
+  }
+}
+
+// Neutral padding lines for K3 (zero centre, h = -FLT_MAX, g = +FLT_MAX) and
+// the box's Vmax slot cleared; run by one block per box.
+__device__ __forceinline__ void box_slots_init(const DevNet& net, void* ws, const WsLayout& lay, int64_t b) {
+  float* lc = ws_ptr<float>(ws, lay.lc) + b * net.Lp;
+  float* lh = ws_ptr<float>(ws, lay.lh) + b * net.Lp;
+  float* lg = ws_ptr<float>(ws, lay.lg) + b * net.Lp;
+  for (int l = net.L + (int)threadIdx.x; l < net.Lp; l += blockDim.x) {
+    lc[l] = 0.0f;
+    lh[l] = -FLT_MAX;
+    lg[l] = FLT_MAX;
+  }
+  if (threadIdx.x == 0) ws_ptr<double>(ws, lay.box)[b * kBoxSlots + kVmax] = 0.0;
+}
+
+// One wave per 64 buses / 64 inputs of a box (the box-tiled path): injection
+// intervals to the workspace and partial float64 sums for the surplus, the
+// total injection and the padding constants.
 __global__ __launch_bounds__(64) void k1_box_prep(DevNet net, const float* __restrict__ box_lo,
                                                   const float* __restrict__ box_hi, void* ws,
                                                   WsLayout lay, int64_t box0) {
   const int64_t b = box0 + blockIdx.y;
   const int i = blockIdx.x * 64 + threadIdx.x;
-  const int X = net.X, G = net.G;
-  const float* lo = box_lo + b * X;
-  const float* hi = box_hi + b * X;
-
+  const float* lo = box_lo + b * net.X;
+  const float* hi = box_hi + b * net.X;
   double v[kP1Fields];
 #pragma unroll
   for (int f = 0; f < kP1Fields; ++f) v[f] = 0.0;
-
-  // buses: p_inj = N_g p_g - N_d p_d as an interval, rounded outward
   if (i < net.Np) {
-    double2* inj = ws_ptr<double2>(ws, lay.inj) + b * net.Np;
-    if (i < net.N) {
-      double c = 0, r = 0, a = 0;
-      int cnt = 0;
-      const int e0 = net.bus_ptr[i], e1 = net.bus_ptr[i + 1];
-      for (int e = e0; e < e1; ++e) {
-        const int j = net.bus_dev[e];
-        const double l = lo[j], h = hi[j];
-        const double cj = 0.5 * (l + h), rj = 0.5 * (h - l);
-        c += (j < G) ? cj : -cj;
-        r += rj;
-        a += fabs(cj);
-        ++cnt;
-      }
-      // float64 summation error of c and r (cnt terms each)
-      const double e64 = (cnt + 1) * kU64 * (a + r) * 1.01;
-      const float c32 = (float)c;
-      const float r32 = ru32((r + 2.0 * e64 + fabs(c - (double)c32)) * (1.0 + 4.0 * kU64));
-      // radius inflated for the float32 rounding of the PTDF entries
-      const float rp = ru32(((1.0 + kKappa0) * (double)r32 + kKappa0 * fabs((double)c32)) *
-                            (1.0 + 4.0 * kU64));
-      inj[i] = make_double2((double)c32, (double)rp);
-      v[kP1Mc] = fabs((double)c32);
-      v[kP1Mbox] = fabs((double)c32) + (double)r32;
-    } else {
-      inj[i] = make_double2(0.0, 0.0);
-    }
+    double2 cr = make_double2(0.0, 0.0);
+    if (i < net.N) bus_injection(net, lo, hi, i, cr, v[kP1Mc], v[kP1Mbox]);
+    ws_ptr<double2>(ws, lay.inj)[b * net.Np + i] = cr;
   }
-  // inputs: surplus and total injection (centre and radius of float32
-  // endpoints are exact in float64)
-  if (i < X) {
-    const double l = lo[i], h = hi[i];
-    if (!(l <= h) || !isfinite(l) || !isfinite(h)) v[kP1Bad] = 1.0;
-    const double c = 0.5 * (l + h), r = 0.5 * (h - l);
-    const double w = net.dev_w[i];
-    v[kP1Sc] = w * c;
-    v[kP1Sr] = fabs(w) * r;
-    v[kP1Sabs] = fabs(w * c) + fabs(w) * r;
-    v[kP1cI] = (i < G) ? c : -c;
-    v[kP1rI] = r;
-    v[kP1cIabs] = fabs(c);
-    if (net.seg_ptr) {
-      // curve term: loads add [F_lo, F_hi], generators subtract it
-      const int s0 = net.seg_ptr[i], s1 = net.seg_ptr[i + 1];
-      if (s1 > s0) {
-        double F_lo, F_hi, e;
-        curve_ibp(net.seg, s0, s1, c, r, F_lo, F_hi, e);
-        const double sc = (i < G ? -0.5 : 0.5) * (F_lo + F_hi);
-        const double sr = 0.5 * (F_hi - F_lo) + e + 1.01 * kU64 * (fabs(F_lo) + fabs(F_hi));
-        v[kP1Sc] += sc;
-        v[kP1Sr] += sr;
-        v[kP1Sabs] += fabs(sc) + sr;
-      }
-    }
-  }
+  if (i < net.X) input_terms(net, lo, hi, i, v);
 #pragma unroll
   for (int f = 0; f < kP1Fields; ++f) v[f] = wave_sum(v[f]);
   if (threadIdx.x < kP1Fields) {
@@ -113,18 +132,7 @@ __global__ __launch_bounds__(64) void k1_box_prep(DevNet net, const float* __res
       if (threadIdx.x == f) val = v[f];
     rec[threadIdx.x] = val;
   }
-  if (blockIdx.x == 0) {
-    // neutral padding lines for K3: zero centre, h = -FLT_MAX, g = +FLT_MAX
-    float* lc = ws_ptr<float>(ws, lay.lc) + b * net.Lp;
-    float* lh = ws_ptr<float>(ws, lay.lh) + b * net.Lp;
-    float* lg = ws_ptr<float>(ws, lay.lg) + b * net.Lp;
-    for (int l = net.L + threadIdx.x; l < net.Lp; l += 64) {
-      lc[l] = 0.0f;
-      lh[l] = -FLT_MAX;
-      lg[l] = FLT_MAX;
-    }
-    if (threadIdx.x == 0) ws_ptr<double>(ws, lay.box)[b * kBoxSlots + kVmax] = 0.0;
-  }
+  if (blockIdx.x == 0) box_slots_init(net, ws, lay, b);
 }
 
 // ---------------------------------------------------------------- K2
