@@ -20,7 +20,8 @@
 //
 // Rigour: s in {-1, 0, 1} and float32 factors make the per-line sums exact
 // small integers (int atomics, order-independent) and every s Lam product
-// exact; per-outage sums and the transposed PTDF product run in float64.  The
+// exact; per-outage sums add four products per lane in float32 and the rest
+// in float64, and the transposed PTDF product runs in float64.  The
 // coefficient error |G^ - G_exact| is bounded per input from
 //   |Lam32 - Lam_exact| <= kappa0 |Lam32| + (2 eps_l + 2 |Lam| eps_c)/(1 - H_cc),
 //   |Phi32 - Phi_exact| <= kappa0 |Phi32| + eps_l,
@@ -112,18 +113,19 @@ __device__ __forceinline__ void kc1_row(const float4& x, const int4& d, const fl
                       crown_slope(x.z, cc, rk, c4.z, g4.z), crown_slope(x.w, cc, rk, c4.w, g4.w)};
   // s Lam is exact in float32; NaN entries carry s = 0 and a finite stand-in
   const float l[4] = {fminf(x.x, FLT_MAX), fminf(x.y, FLT_MAX), fminf(x.z, FLT_MAX), fminf(x.w, FLT_MAX)};
-  double v = 0.0, a = 0.0;
-  float n = 0.0f;
+  // the four exact products are summed in float32 (error <= 3u of their
+  // absolute sum, covered in KC2) before the float64 reduction
+  float v = 0.0f, a = 0.0f, n = 0.0f;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     cs[i] += s[i];
     ca[i] += fabsf(s[i]);
     n += fabsf(s[i]);
-    v += (double)(s[i] * l[i]);
-    a += (double)fabsf(s[i] * l[i]);
+    v += s[i] * l[i];
+    a += fabsf(s[i] * l[i]);
   }
-  r[0] = v;
-  r[1] = a;
+  r[0] = (double)v;
+  r[1] = (double)a;
   r[2] = (double)n;
 }
 
@@ -227,10 +229,11 @@ __global__ __launch_bounds__(256) void kc2_lines(DevNet net, void* ws, WsLayout 
         A += q.y;
         N += q.z;
       }
-      // float64 sums of exact products (L + tiles terms); stored-factor errors
+      // float32 sums of four exact products per lane (<= 3u of their absolute
+      // sum), float64 sums over the rest (L + tiles terms); stored-factor errors
       const double gam = (net.Lp + lay.kc_bx + 16) * kU64 * 1.01;
-      const double A1 = A * (1.0 + gam) * (1.0 + kKappa0);
-      ev = (kKappa0 + net.ctg_eps[k] + gam) * A1 + 2.0 * net.phi_err_max * net.ctg_inv[k] * N;
+      const double A1 = A * (1.0 + gam) * (1.0 + kKappa0) * (1.0 + 4.0 * kU32);
+      ev = (kKappa0 + net.ctg_eps[k] + gam + 4.0 * kU32) * A1 + 2.0 * net.phi_err_max * net.ctg_inv[k] * N;
       v += V;
       va += A1 + ev;
     }
@@ -400,6 +403,184 @@ __global__ __launch_bounds__(256) void kc5_finalize(DevNet net, void* ws, WsLayo
   if (crown) crown[b] = (prev != prev) ? NAN : ub;
 }
 
+// ---------------------------------------------------------------- many boxes
+//
+// Box-tiled forms of KC1 and KC3: every lane keeps four lines of four boxes,
+// so each outage-factor or PTDF tile read from memory serves four boxes; the
+// box tile is the fastest-varying block index, so blocks that read the same
+// tile are dispatched together and share it through the L2.  The partial
+// arrays they write are those of the per-box kernels, so KC2, KC4 and KC5 are
+// shared.
+constexpr int kCB = 4;     // boxes per tile
+constexpr int kKPB = 32;   // outages per KC1b block
+
+__global__ __launch_bounds__(256) void kc1b_sweep(DevNet net, void* ws, WsLayout lay, int64_t n_box) {
+  __shared__ double shv[4][kKPB][kCB][2];
+  __shared__ float shn[4][kKPB][kCB];
+  const int64_t bt = (int64_t)blockIdx.x * kCB;  // first box of the tile
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int col = (blockIdx.y * 4 + w) * 64 + lane;  // float4 column: four lines per lane
+  const int Lp4 = net.Lp / 4;
+  const int k0 = blockIdx.z * kKPB;
+  const int k1 = min(net.K, k0 + kKPB);
+  const bool live = col < Lp4;
+  int64_t bb[kCB];
+#pragma unroll
+  for (int i = 0; i < kCB; ++i) bb[i] = min(bt + i, n_box - 1);
+  float4 c4[kCB], g4[kCB];
+  const int4* cd[kCB];
+#pragma unroll
+  for (int i = 0; i < kCB; ++i) {
+    c4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    g4[i] = make_float4(FLT_MAX, FLT_MAX, FLT_MAX, FLT_MAX);
+    cd[i] = ws_ptr<int4>(ws, lay.ctg) + bb[i] * net.K;
+  }
+  if (live) {
+    const float4 e4 = reinterpret_cast<const float4*>(net.line_eps)[col];
+#pragma unroll
+    for (int i = 0; i < kCB; ++i) {
+      const double* bs = ws_ptr<double>(ws, lay.box) + bb[i] * kBoxSlots;
+      const float vmax = __uint_as_float(*reinterpret_cast<const unsigned int*>(bs + kVmax));
+      c4[i] = reinterpret_cast<const float4*>(ws_ptr<float>(ws, lay.lc) + bb[i] * net.Lp)[col];
+      const float4 g = reinterpret_cast<const float4*>(ws_ptr<float>(ws, lay.lg) + bb[i] * net.Lp)[col];
+      g4[i] = make_float4(add_ru(g.x, next_up_f32(e4.x * vmax)), add_ru(g.y, next_up_f32(e4.y * vmax)),
+                          add_ru(g.z, next_up_f32(e4.z * vmax)), add_ru(g.w, next_up_f32(e4.w * vmax)));
+    }
+  }
+  const float4* lam = reinterpret_cast<const float4*>(net.lodf) + col;
+  float cs[kCB][4], ca[kCB][4];
+#pragma unroll
+  for (int i = 0; i < kCB; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) cs[i][j] = ca[i][j] = 0.0f;
+  // pairs of outages: 2 outages x 4 boxes x 3 sums in one halving reduction
+  for (int kg = k0; kg < k1; kg += 2) {
+    double r[24];
+#pragma unroll
+    for (int i = 0; i < 24; ++i) r[i] = 0.0;
+    if (live) {
+      float4 x[2];
+#pragma unroll
+      for (int o = 0; o < 2; ++o)
+        x[o] = (kg + o < k1) ? ld_stream(lam + (size_t)(kg + o) * Lp4) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int o = 0; o < 2; ++o)
+        if (kg + o < k1)
+#pragma unroll
+          for (int i = 0; i < kCB; ++i) kc1_row(x[o], cd[i][kg + o], c4[i], g4[i], cs[i], ca[i], r + 3 * (o * kCB + i));
+    }
+    bool act = false;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) act |= r[3 * i + 2] != 0.0;
+    if (__any(act)) halving_sum24(r);
+    // lane 8g holds outage kg + g / 4 of box g % 4
+    if ((lane & 7) == 0) {
+      const int g = lane >> 3, o = g / kCB, i = g % kCB;
+      if (kg + o < k1) {
+        shv[w][kg - k0 + o][i][0] = r[0];
+        shv[w][kg - k0 + o][i][1] = r[1];
+        shn[w][kg - k0 + o][i] = (float)r[2];
+      }
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < (k1 - k0) * kCB; t += 256) {
+    const int q = t / kCB, i = t % kCB;
+    if (bt + i >= n_box) continue;
+    const double V = (shv[0][q][i][0] + shv[1][q][i][0]) + (shv[2][q][i][0] + shv[3][q][i][0]);
+    const double A = (shv[0][q][i][1] + shv[1][q][i][1]) + (shv[2][q][i][1] + shv[3][q][i][1]);
+    const double N = ((double)shn[0][q][i] + (double)shn[1][q][i]) + ((double)shn[2][q][i] + (double)shn[3][q][i]);
+    ws_ptr<double4>(ws, lay.cv)[((size_t)(bt + i) * lay.kc_bx + blockIdx.y) * net.K + k0 + q] =
+        make_double4(V, A, N, 0.0);
+  }
+  if (live) {
+#pragma unroll
+    for (int i = 0; i < kCB; ++i) {
+      if (bt + i >= n_box) break;
+      int2* cnt = ws_ptr<int2>(ws, lay.ccnt) + (bt + i) * net.Lp + 4 * col;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (ca[i][j] != 0.0f) {
+          atomicAdd(&cnt[j].x, (int)cs[i][j]);
+          atomicAdd(&cnt[j].y, (int)ca[i][j]);
+        }
+    }
+  }
+}
+
+// Per bus n and four boxes: y = sum_l Phi32[l, n] v_l, ya, ye as in KC3, over
+// one 1024-line tile; two buses per halving reduction, kNB buses per block.
+__global__ __launch_bounds__(256) void kc3b_ptdf_t(DevNet net, void* ws, WsLayout lay, int64_t n_box) {
+  __shared__ double sh[4][kNB][kCB][3];
+  const int64_t bt = (int64_t)blockIdx.x * kCB;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int col = (blockIdx.y * 4 + w) * 64 + lane;
+  const int Lp4 = net.Lp / 4;
+  const bool live = col < Lp4;
+  double v[kCB][4], va[kCB][4], ev[kCB][4];
+#pragma unroll
+  for (int i = 0; i < kCB; ++i) {
+    const int64_t b = min(bt + i, n_box - 1);
+    const double4* lv = ws_ptr<double4>(ws, lay.lv) + b * net.Lp + 4 * (live ? col : 0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double4 q = live ? lv[j] : make_double4(0.0, 0.0, 0.0, 0.0);
+      v[i][j] = q.x;
+      va[i][j] = q.y;
+      ev[i][j] = q.z;
+    }
+  }
+  const int n0 = blockIdx.z * kNB;
+  const int n1 = min(net.N, n0 + kNB);
+  const float4* ph = reinterpret_cast<const float4*>(net.phiT) + col;
+  for (int ng = n0; ng < n1; ng += 2) {
+    double r[24];
+#pragma unroll
+    for (int i = 0; i < 24; ++i) r[i] = 0.0;
+    if (live) {
+      float4 x[2];
+#pragma unroll
+      for (int o = 0; o < 2; ++o)
+        x[o] = (ng + o < n1) ? ld_stream(ph + (size_t)(ng + o) * Lp4) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int o = 0; o < 2; ++o) {
+        const double p[4] = {(double)x[o].x, (double)x[o].y, (double)x[o].z, (double)x[o].w};
+#pragma unroll
+        for (int i = 0; i < kCB; ++i) {
+          double* q = r + 3 * (o * kCB + i);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            q[0] = fma(p[j], v[i][j], q[0]);
+            q[1] = fma(fabs(p[j]), va[i][j], q[1]);
+            q[2] = fma(fabs(p[j]), ev[i][j], q[2]);
+          }
+        }
+      }
+    }
+    halving_sum24(r);
+    if ((lane & 7) == 0) {
+      const int g = lane >> 3, o = g / kCB, i = g % kCB;
+      if (ng + o < n1) {
+        sh[w][ng - n0 + o][i][0] = r[0];
+        sh[w][ng - n0 + o][i][1] = r[1];
+        sh[w][ng - n0 + o][i][2] = r[2];
+      }
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < (n1 - n0) * kCB; t += 256) {
+    const int q = t / kCB, i = t % kCB;
+    if (bt + i >= n_box) continue;
+    double o[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) o[f] = (sh[0][q][i][f] + sh[1][q][i][f]) + (sh[2][q][i][f] + sh[3][q][i][f]);
+    ws_ptr<double4>(ws, lay.bpart)[((size_t)(bt + i) * lay.kc3_bx + blockIdx.y) * net.Np + n0 + q] =
+        make_double4(o[0], o[1], o[2], 0.0);
+  }
+}
+
 void plan_crown(const DevNet& net, WsLayout& lay) {
   const int lp4 = net.Lp / 4;
   lay.kc_bx = (lp4 + 255) / 256;
@@ -419,13 +600,33 @@ hipError_t launch_crown(const DevNet& net, int64_t n_box, const float* lo, const
     const int64_t nz = (int64_t)nb * net.Lp;
     int2* cnt = reinterpret_cast<int2*>(static_cast<char*>(ws) + lay.ccnt) + b0 * net.Lp;
     hipLaunchKernelGGL(kc0_zero, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, cnt, nz);
-    if (net.K > 0)
+    if (net.K > 0 && n_box < kCB)
       hipLaunchKernelGGL(kc1_sweep, dim3(lay.kc_bx, lay.kc_by, nb), dim3(256), 0, s, net, ws, lay, b0);
     tm->stop(t, s);
-    t = tm->start(11, s);
-    hipLaunchKernelGGL(kc2_lines, dim3(lay.n_ct, nb), dim3(256), 0, s, net, ws, lay, b0);
-    hipLaunchKernelGGL(kc3_ptdf_t, dim3(lay.kc3_bx, lay.kc3_by, nb), dim3(256), 0, s, net, ws, lay, b0);
+  }
+  const unsigned tiles = (unsigned)((n_box + kCB - 1) / kCB);
+  if (net.K > 0 && n_box >= kCB) {
+    const int t = tm->start(10, s);
+    hipLaunchKernelGGL(kc1b_sweep, dim3(tiles, lay.kc_bx, (net.K + kKPB - 1) / kKPB), dim3(256), 0, s, net, ws,
+                       lay, n_box);
     tm->stop(t, s);
+  }
+  for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
+    const int nb = (int)std::min<int64_t>(65535, n_box - b0);
+    const int t = tm->start(11, s);
+    hipLaunchKernelGGL(kc2_lines, dim3(lay.n_ct, nb), dim3(256), 0, s, net, ws, lay, b0);
+    if (n_box < kCB)
+      hipLaunchKernelGGL(kc3_ptdf_t, dim3(lay.kc3_bx, lay.kc3_by, nb), dim3(256), 0, s, net, ws, lay, b0);
+    tm->stop(t, s);
+  }
+  if (n_box >= kCB) {
+    const int t = tm->start(11, s);
+    hipLaunchKernelGGL(kc3b_ptdf_t, dim3(tiles, lay.kc3_bx, lay.kc3_by), dim3(256), 0, s, net, ws, lay, n_box);
+    tm->stop(t, s);
+  }
+  for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
+    const int nb = (int)std::min<int64_t>(65535, n_box - b0);
+    int t;
     t = tm->start(12, s);
     hipLaunchKernelGGL(kc4_inputs, dim3(lay.n_cp, nb), dim3(256), 0, s, net, ws, lay, b0, lo, hi, vertex);
     hipLaunchKernelGGL(kc5_finalize, dim3(nb), dim3(256), 0, s, net, ws, lay, b0, f_hi, crown);
