@@ -47,12 +47,12 @@ __global__ __launch_bounds__(256) void k2b_base_flows(DevNet net, void* ws, WsLa
   if (col < Lp4) {
     const float4* ph = reinterpret_cast<const float4*>(net.phiT) + col;
     int n = 0;
-    for (; n + 4 <= net.N; n += 4) {
-      float4 x[4];
+    for (; n + 8 <= net.N; n += 8) {
+      float4 x[8];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) x[u] = ph[(size_t)(n + u) * Lp4];
+      for (int u = 0; u < 8; ++u) x[u] = ph[(size_t)(n + u) * Lp4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 8; ++u) {
         const double p0 = x[u].x, p1 = x[u].y, p2 = x[u].z, p3 = x[u].w;
 #pragma unroll
         for (int i = 0; i < kBT; ++i) {
