@@ -83,6 +83,7 @@ __all__ = [
     "curve_value",
     "curve_interval",
     "crown_upper",
+    "crown_upper_iterated",
 ]
 
 
@@ -572,7 +573,16 @@ def _crown_slopes(c, r, t, near_rel):
     return s, k
 
 
-def crown_upper(net, lo, hi, fac=None, chunk: int = 256, near_rel: float = 1e-5) -> dict:
+def _crown_point_slopes(z, t, near_rel):
+    """Slope s = sign(z) where |z| > t at a reference point (the gradient of
+    max(|z| - t, 0) there), else 0; and the count within near_rel of that decision."""
+    m = np.abs(z) - t
+    s = np.sign(z) * (m > 0)
+    k = int(np.sum((np.abs(m) <= near_rel * (np.abs(z) + t)) & (z != 0)))
+    return s, k
+
+
+def crown_upper(net, lo, hi, fac=None, chunk: int = 256, near_rel: float = 1e-5, ref=None) -> dict:
     """Upper bound on max f over the box from linear relaxations of the penalties
     (the convex-relaxation family the paper cites beside IBP, Sec. I).
 
@@ -587,9 +597,15 @@ def crown_upper(net, lo, hi, fac=None, chunk: int = 256, near_rel: float = 1e-5)
     minimum over the box equals IBP's lower penalty and the bound is never
     above IBP's f_hi.
 
+    With ``ref`` (a point), the slopes are instead the gradients of the
+    penalties at that point: sign(z(ref)) where |z(ref)| > t, else 0 (any
+    slopes give a valid bound).
+
     Returns ``f_hi`` (the bound), ``n_active`` (elements with a non-zero
-    slope) and ``near`` (elements whose slope decision sits within
-    ``near_rel`` of switching, relative to |C| + R + t).
+    slope), ``near`` (elements whose slope decision sits within ``near_rel`` of
+    switching, relative to |C| + R + t, or |z| + t at the point), and
+    ``vertex``: the box vertex maximising the linear part (hi_j where its
+    coefficient is >= 0, else lo_j).
     """
     if fac is None:
         fac = factors(net)
@@ -602,21 +618,26 @@ def crown_upper(net, lo, hi, fac=None, chunk: int = 256, near_rel: float = 1e-5)
     near = 0
     n_active = 0
 
-    def slopes(c, r, t):
+    if ref is not None:
+        p_ref = W @ np.asarray(ref, dtype=np.float64)
+
+    def slopes(c, r, t, zref=None):
+        if ref is not None:
+            return _crown_point_slopes(zref, t, near_rel)
         return _crown_slopes(c, r, t, near_rel)
 
     # imbalance 1^T |(E^T Phi - I) p_inj|: |z| >= s z
     W2 = _imbalance_matrix(net)
     cz = W2 @ c_inj
     rz = abs(W2) @ r_inj
-    s_I, k = slopes(cz, rz, 0.0)
+    s_I, k = slopes(cz, rz, 0.0, None if ref is None else W2 @ p_ref)
     near += k
     # base lines
     Phi = fac["Phi"]
     c_f = Phi @ c_inj
     r_f = np.abs(Phi) @ r_inj
     fb = np.asarray(net["fmax_base"], float)
-    s_b, k = slopes(c_f, r_f, fb)
+    s_b, k = slopes(c_f, r_f, fb, None if ref is None else Phi @ p_ref)
     near += k
     n_active += int(np.count_nonzero(s_b))
     const = [zf * math.fsum(np.abs(s_b) * fb)]
@@ -628,12 +649,16 @@ def crown_upper(net, lo, hi, fac=None, chunk: int = 256, near_rel: float = 1e-5)
     K = fac["K"]
     v_f = s_b.astype(float).copy()
     v_u = np.zeros(K)
+    if ref is not None:
+        f_ref = Phi @ p_ref
+        u_ref = U @ p_ref
     for k0 in range(0, K, chunk):
         k1 = min(K, k0 + chunk)
         Mk, Bk = M[k0:k1], Bm[k0:k1]
         Cc = Mk * c_f[None, :] - Bk * c_u[k0:k1, None]
         Rc = np.abs(Mk) * r_f[None, :] + np.abs(Bk) * r_u[k0:k1, None]
-        s, k = slopes(Cc, Rc, fc[None, :])
+        zr = None if ref is None else Mk * f_ref[None, :] - Bk * u_ref[k0:k1, None]
+        s, k = slopes(Cc, Rc, fc[None, :], zr)
         s = s * (Mk != 0)          # the outaged line's own entry carries no penalty
         near += k
         n_active += int(np.count_nonzero(s))
@@ -645,7 +670,29 @@ def crown_upper(net, lo, hi, fac=None, chunk: int = 256, near_rel: float = 1e-5)
     P_lo, P_hi = _curve_surplus(net, mu, sg)
     c0 = math.fsum(const)
     f_hi = c0 + math.fsum(G * mu) + math.fsum(np.abs(G) * sg) + P_hi
-    return dict(f_hi=f_hi, n_active=n_active, near=near, G=G, const=c0)
+    vertex = np.where(G >= 0, np.asarray(hi, np.float64), np.asarray(lo, np.float64))
+    return dict(f_hi=f_hi, n_active=n_active, near=near, G=G, const=c0, vertex=vertex)
+
+
+def crown_upper_iterated(net, lo, hi, fac=None, iters: int = 4, near_rel: float = 1e-5) -> dict:
+    """The smallest of several relaxation bounds: the interval slope rule, then
+    ``iters`` point-gradient slope rules at reference points x_0 = (lo + hi)/2
+    and x_{i+1} = x_i/2 + v_i/2 (float32 arithmetic), where v_i is the vertex
+    that maximised relaxation i.  Returns ``f_hi``, the per-relaxation bounds
+    and the total ``near`` count."""
+    if fac is None:
+        fac = factors(net)
+    r = crown_upper(net, lo, hi, fac, near_rel=near_rel)
+    bounds = [r["f_hi"]]
+    near = r["near"]
+    half = np.float32(0.5)
+    x = half * np.asarray(lo, np.float32) + half * np.asarray(hi, np.float32)
+    for _ in range(iters):
+        r = crown_upper(net, lo, hi, fac, near_rel=near_rel, ref=x.astype(np.float64))
+        bounds.append(r["f_hi"])
+        near += r["near"]
+        x = half * x + half * r["vertex"].astype(np.float32)
+    return dict(f_hi=min(bounds), bounds=bounds, near=near)
 
 
 # ----------------------------------------------------------------------------

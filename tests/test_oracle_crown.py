@@ -133,3 +133,51 @@ def test_planted_mistakes_are_caught(tiny, monkeypatch):
         r = oracle.crown_upper(net, x, y, fac)
         below += r["f_hi"] - r["const"] < lp - 1e-6 * abs(lp)   # intercepts zeta_f sum |s| t dropped
     assert below >= 1
+
+
+def test_point_gradient_slopes_are_valid_anywhere(tiny):
+    """Slopes taken at any reference point, inside the box or not, still give a
+    bound >= the LP; at a zero-width box and its own point the bound is f(x)."""
+    net, fac = tiny
+    rng = np.random.default_rng(21)
+    lo, hi = synth.full_box(net)
+    span = hi.astype(float) - lo
+    for a, b in zip(*synth.sub_boxes(net, 3, seed=3)):
+        lp = _lp_max(net, a.astype(float), b.astype(float), fac)
+        for _ in range(4):
+            ref = lo - 0.2 * span + 1.4 * rng.random(lo.size) * span
+            c = oracle.crown_upper(net, a, b, fac, ref=ref)["f_hi"]
+            assert c >= lp - 1e-7 * max(1.0, abs(lp))
+    x = (0.3 * lo + 0.7 * hi).astype(np.float32)
+    fx = oracle.point_eval(net, x.astype(float), fac["ctg"])
+    assert oracle.crown_upper(net, x, x, fac, ref=x.astype(float))["f_hi"] == pytest.approx(fx, rel=1e-9)
+
+
+def test_iterated_point_slopes_reach_the_lp_optimum(tiny):
+    """The iterated rule (interval slopes, then point-gradient slopes at points
+    moving halfway to each relaxation's maximising vertex) attains the LP optimum
+    of Problem 1 on several sub-boxes (an independent solver), is never below
+    it, and never above the interval rule alone."""
+    net, fac = tiny
+    reached = 0
+    for a, b in zip(*synth.sub_boxes(net, 6, seed=3)):
+        lp = _lp_max(net, a.astype(float), b.astype(float), fac)
+        r = oracle.crown_upper_iterated(net, a, b, fac, iters=8)
+        assert r["f_hi"] >= lp - 1e-7 * max(1.0, abs(lp))
+        assert r["f_hi"] <= r["bounds"][0]
+        reached += abs(min(r["bounds"][1:]) - lp) <= 1e-7 * max(1.0, abs(lp))   # point rules alone
+    assert reached >= 3
+
+
+def test_planted_point_slope_mistake_is_caught(tiny, monkeypatch):
+    """Point slopes with the wrong sign stay valid but no longer reach the LP."""
+    net, fac = tiny
+    real = oracle.ibp_oracle._crown_point_slopes
+    monkeypatch.setattr(oracle.ibp_oracle, "_crown_point_slopes",
+                        lambda z, t, n: (-real(z, t, n)[0], real(z, t, n)[1]))
+    reached = 0
+    for a, b in zip(*synth.sub_boxes(net, 6, seed=3)):
+        lp = _lp_max(net, a.astype(float), b.astype(float), fac)
+        r = oracle.crown_upper_iterated(net, a, b, fac, iters=8)
+        reached += abs(min(r["bounds"][1:]) - lp) <= 1e-7 * max(1.0, abs(lp))
+    assert reached == 0
