@@ -139,6 +139,7 @@ void ibp_free_network(ibp_network* net);
 #define IBP_F_PLAIN 1u    /* per-box single-box kernels even for n_box > 1 (reference form for batching) */
 #define IBP_F_BACKWARD 4u /* workspace query only: size for ibp_bound_backward (includes the forward's) */
 #define IBP_F_CROWN 8u    /* workspace query only: size for ibp_crown_bound_boxes (includes the forward's) */
+#define IBP_F_CROWN_REF 16u /* workspace query only: ibp_crown_bound_boxes with ref_iters > 0 */
 
 /* Bytes of device workspace a compute call needs for n_box boxes (0 on error). */
 size_t ibp_workspace_bytes(const ibp_network* net, int64_t n_box, uint32_t flags);
@@ -181,20 +182,28 @@ ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box,
  * everywhere; with these lines the objective is bounded above by a linear
  * function of the inputs (plus the interval of any piecewise-linear curves)
  * whose exact maximum over the box is computed with outward rounding.  The
- * slope of an element is the sign of its flow when IBP's interval for it lies
- * beyond the limit, else 0, so the relaxation is never looser than IBP.
+ * first relaxation takes the slope of an element as the sign of its flow when
+ * IBP's interval for it lies beyond the limit, else 0 (never looser than IBP).
+ * With ref_iters > 0, ref_iters further relaxations take the slopes from the
+ * flows at reference points (sign where the flow exceeds the limit there, else
+ * 0): first the box centre, then each point moved halfway (float32) towards
+ * the vertex that maximised the previous relaxation.  Every relaxation is a
+ * valid bound; the smallest is kept.
  *   f_lo, f_hi : device float64 [n_box]: IBP's f_lo, and min(IBP f_hi,
  *                relaxation bound) -- both still certified.
- *   crown_hi   : device float64 [n_box] or NULL: the relaxation bound alone.
+ *   ref_iters  : 0 .. 64 reference-point relaxations after the first.
+ *   crown_hi   : device float64 [n_box] or NULL: the smallest relaxation bound
+ *                alone.
  *   vertex     : device float32 [n_box x X] or NULL: the box vertex that
- *                maximises the relaxation's linear part (hi_j where its
+ *                maximises the last relaxation's linear part (hi_j where its
  *                coefficient is >= 0, else lo_j), a candidate point for
  *                lower bounds on max f.
- *   ws, ws_bytes: at least ibp_workspace_bytes(net, n_box, flags | IBP_F_CROWN).
+ *   ws, ws_bytes: at least ibp_workspace_bytes(net, n_box, flags | IBP_F_CROWN)
+ *                (| IBP_F_CROWN_REF when ref_iters > 0).
  * flags: 0 or IBP_F_PLAIN (forward kernels as in ibp_bound_boxes).  Invalid
  * boxes get NaN.  Errors: INVALID_ARG, WORKSPACE, HOST_ONLY, DEVICE. */
 ibp_status ibp_crown_bound_boxes(const ibp_network* net, int64_t n_box,
-                                 const float* box_lo, const float* box_hi,
+                                 const float* box_lo, const float* box_hi, int32_t ref_iters,
                                  double* f_lo, double* f_hi, double* crown_hi, float* vertex,
                                  void* ws, size_t ws_bytes, void* stream, uint32_t flags);
 

@@ -255,7 +255,7 @@ ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
     lay.gri = take(B * d.Np * sizeof(double));
     lay.total = off;
   }
-  if (flags & IBP_F_CROWN) {
+  if (flags & (IBP_F_CROWN | IBP_F_CROWN_REF)) {
     const ibp::DevNet& d = net->dn;
     const size_t B = (size_t)std::max<int64_t>(1, n_box);
     ibp::plan_crown(d, lay);
@@ -271,6 +271,11 @@ ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
     lay.bpart = take(B * lay.kc3_bx * d.Np * 4 * sizeof(double));
     lay.cp = take(B * lay.n_cp * 2 * sizeof(double));
     lay.ct = take(B * lay.n_ct * 2 * sizeof(double));
+    if (flags & IBP_F_CROWN_REF) {
+      lay.ref = take(lay.fwd_total);
+      lay.xref = take(B * d.X * sizeof(float));
+      lay.vtx = take(B * d.X * sizeof(float));
+    }
     lay.total = off;
   }
   return lay;
@@ -303,6 +308,7 @@ ibp::WsLayout layout_for(const ibp_network* net, int64_t n_box, const ibp::Tune&
   lay.p2 = take(B * std::max(1, lay.n_p2) * 2 * sizeof(double));
   lay.p3 = take(B * std::max(1, lay.n_p3) * 2 * sizeof(double));
   lay.total = off;
+  lay.fwd_total = off;
   return lay;
 }
 
@@ -312,7 +318,7 @@ ibp_status check_compute_args(const ibp_network* net, int64_t n_box, const void*
   if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
   if (net->device < 0) return fail(IBP_E_HOST_ONLY, "network was built host-only");
   if (n_box < 0) return fail(IBP_E_INVALID_ARG, "n_box < 0");
-  if (flags & ~uint32_t(IBP_F_PLAIN | IBP_F_BACKWARD | IBP_F_CROWN))
+  if (flags & ~uint32_t(IBP_F_PLAIN | IBP_F_BACKWARD | IBP_F_CROWN | IBP_F_CROWN_REF))
     return fail(IBP_E_INVALID_ARG, "unknown flag bits");
   if (n_box == 0) return IBP_OK;
   if (!lo || !hi || !a || !b) return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
@@ -442,13 +448,15 @@ ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box, const float
 }
 
 ibp_status ibp_crown_bound_boxes(const ibp_network* net, int64_t n_box, const float* box_lo,
-                                 const float* box_hi, double* f_lo, double* f_hi, double* crown_hi,
-                                 float* vertex, void* ws, size_t ws_bytes, void* stream, uint32_t flags) {
+                                 const float* box_hi, int32_t ref_iters, double* f_lo, double* f_hi,
+                                 double* crown_hi, float* vertex, void* ws, size_t ws_bytes, void* stream,
+                                 uint32_t flags) {
   g_err.clear();
   if (flags & ~uint32_t(IBP_F_PLAIN)) return fail(IBP_E_INVALID_ARG, "flags: only IBP_F_PLAIN is accepted");
+  if (ref_iters < 0 || ref_iters > 64) return fail(IBP_E_INVALID_ARG, "ref_iters must be in [0, 64]");
   ibp::WsLayout lay;
-  ibp_status st = check_compute_args(net, n_box, box_lo, box_hi, f_lo, f_hi, ws, ws_bytes, flags | IBP_F_CROWN,
-                                     lay);
+  const uint32_t need = flags | IBP_F_CROWN | (ref_iters > 0 ? IBP_F_CROWN_REF : 0u);
+  ibp_status st = check_compute_args(net, n_box, box_lo, box_hi, f_lo, f_hi, ws, ws_bytes, need, lay);
   if (st != IBP_OK || n_box == 0) return st;
   DeviceGuard g(net->device);
   if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
@@ -456,7 +464,7 @@ ibp_status ibp_crown_bound_boxes(const ibp_network* net, int64_t n_box, const fl
   ibp::KernelTimer* tm = const_cast<ibp::KernelTimer*>(&net->timer);
   hipError_t e = ibp::launch_forward(net->dn, n_box, box_lo, box_hi, f_lo, f_hi, nullptr, ws, lay, s, tm);
   if (e == hipSuccess)
-    e = ibp::launch_crown(net->dn, n_box, box_lo, box_hi, f_hi, crown_hi, vertex, ws, lay, s, tm);
+    e = ibp::launch_crown(net->dn, n_box, box_lo, box_hi, ref_iters, f_hi, crown_hi, vertex, ws, lay, s, tm);
   if (e != hipSuccess) return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
   return IBP_OK;
 }

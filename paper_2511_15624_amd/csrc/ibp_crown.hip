@@ -35,6 +35,13 @@
 //   KC4  per input: coefficient, error bound, box maximum (and curve interval),
 //        and the maximising vertex
 //   KC5  per box: total, outward padding, min with IBP's f_hi
+//
+// Slopes come either from the box (an element has s = sign(C) when its padded
+// interval lies beyond the limit) or from a reference point (s = sign(C) where
+// the flow there exceeds the limit: the penalty's gradient at that point).
+// The second family, taken at the box centre and then at points moving
+// halfway towards each relaxation's maximising vertex, often reaches the LP
+// optimum of the box; every pass gives a valid bound and the smallest is kept.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -64,6 +71,13 @@ __device__ __forceinline__ float crown_slope(float lam, float cc, float rk, floa
   const float C = fmaf(lam, cc, cl);
   const float tlo = fabsf(C) - fmaf(fabsf(lam), rk, g);
   return tlo > 0.0f ? copysignf(1.0f, C) : 0.0f;
+}
+
+// Slope from the flow at a reference point: C = fma(Lam, c_c(ref), c_l(ref)),
+// s = sign(C) where |C| > fmax (the penalty's gradient there), else 0.
+__device__ __forceinline__ float crown_slope_ref(float lam, float cc, float cl, float fmax) {
+  const float C = fmaf(lam, cc, cl);
+  return fabsf(C) > fmax ? copysignf(1.0f, C) : 0.0f;
 }
 
 // Sums v[0..23] (eight groups of three) over the 64 lanes of a wave by halving
@@ -106,11 +120,23 @@ __device__ __forceinline__ void halving_sum24(double (&v)[24]) {
 
 // Slopes of four lines x one outage; per-line counts in registers, the
 // outage's three sums (s Lam, |s Lam|, count) into r[0..2].
+// REF: c4 holds the line flows at the reference point and g4 the limits.
+template <bool REF>
 __device__ __forceinline__ void kc1_row(const float4& x, const int4& d, const float4& c4, const float4& g4,
                                         float (&cs)[4], float (&ca)[4], double* r) {
   const float cc = __int_as_float(d.y), rk = __int_as_float(d.z);
-  const float s[4] = {crown_slope(x.x, cc, rk, c4.x, g4.x), crown_slope(x.y, cc, rk, c4.y, g4.y),
-                      crown_slope(x.z, cc, rk, c4.z, g4.z), crown_slope(x.w, cc, rk, c4.w, g4.w)};
+  float s[4];
+  if (REF) {
+    s[0] = crown_slope_ref(x.x, cc, c4.x, g4.x);
+    s[1] = crown_slope_ref(x.y, cc, c4.y, g4.y);
+    s[2] = crown_slope_ref(x.z, cc, c4.z, g4.z);
+    s[3] = crown_slope_ref(x.w, cc, c4.w, g4.w);
+  } else {
+    s[0] = crown_slope(x.x, cc, rk, c4.x, g4.x);
+    s[1] = crown_slope(x.y, cc, rk, c4.y, g4.y);
+    s[2] = crown_slope(x.z, cc, rk, c4.z, g4.z);
+    s[3] = crown_slope(x.w, cc, rk, c4.w, g4.w);
+  }
   // s Lam is exact in float32; NaN entries carry s = 0 and a finite stand-in
   const float l[4] = {fminf(x.x, FLT_MAX), fminf(x.y, FLT_MAX), fminf(x.z, FLT_MAX), fminf(x.w, FLT_MAX)};
   // the four exact products are summed in float32 (error <= 3u of their
@@ -129,7 +155,10 @@ __device__ __forceinline__ void kc1_row(const float4& x, const int4& d, const fl
   r[2] = (double)n;
 }
 
-__global__ __launch_bounds__(256) void kc1_sweep(DevNet net, void* ws, WsLayout lay, int64_t box0) {
+// wsr: the reference points' forward workspace (REF), else unused.
+template <bool REF>
+__global__ __launch_bounds__(256) void kc1_sweep(DevNet net, void* ws, const void* wsr, WsLayout lay,
+                                                 int64_t box0) {
   __shared__ double shv[4][kKC][2];
   __shared__ float shn[4][kKC];
   const int64_t b = box0 + blockIdx.z;
@@ -141,7 +170,11 @@ __global__ __launch_bounds__(256) void kc1_sweep(DevNet net, void* ws, WsLayout 
   const int k1 = min(net.K, k0 + kKC);
   const bool live = col < Lp4;
   float4 c4 = make_float4(0.f, 0.f, 0.f, 0.f), g4 = make_float4(FLT_MAX, FLT_MAX, FLT_MAX, FLT_MAX);
-  if (live) {
+  void* wd = REF ? const_cast<void*>(wsr) : ws;  // where the slope decisions read from
+  if (live && REF) {
+    c4 = reinterpret_cast<const float4*>(ws_ptr<float>(wd, lay.lc) + b * net.Lp)[col];
+    g4 = reinterpret_cast<const float4*>(net.fmax_c32)[col];
+  } else if (live) {
     const double* bs = ws_ptr<double>(ws, lay.box) + b * kBoxSlots;
     const float vmax = __uint_as_float(*reinterpret_cast<const unsigned int*>(bs + kVmax));
     c4 = reinterpret_cast<const float4*>(ws_ptr<float>(ws, lay.lc) + b * net.Lp)[col];
@@ -150,7 +183,7 @@ __global__ __launch_bounds__(256) void kc1_sweep(DevNet net, void* ws, WsLayout 
     g4 = make_float4(add_ru(g4.x, next_up_f32(e4.x * vmax)), add_ru(g4.y, next_up_f32(e4.y * vmax)),
                      add_ru(g4.z, next_up_f32(e4.z * vmax)), add_ru(g4.w, next_up_f32(e4.w * vmax)));
   }
-  const int4* cd = ws_ptr<int4>(ws, lay.ctg) + b * net.K;
+  const int4* cd = ws_ptr<int4>(wd, lay.ctg) + b * net.K;
   const float4* lam = reinterpret_cast<const float4*>(net.lodf) + col;
   float cs[4] = {0.f, 0.f, 0.f, 0.f}, ca[4] = {0.f, 0.f, 0.f, 0.f};
   // groups of eight outages: eight rows in flight, then one halving reduction
@@ -165,7 +198,7 @@ __global__ __launch_bounds__(256) void kc1_sweep(DevNet net, void* ws, WsLayout 
         x[i] = (kg + i < k1) ? ld_stream(lam + (size_t)(kg + i) * Lp4) : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
       for (int i = 0; i < 8; ++i)
-        if (kg + i < k1) kc1_row(x[i], cd[kg + i], c4, g4, cs, ca, r + 3 * i);
+        if (kg + i < k1) kc1_row<REF>(x[i], cd[kg + i], c4, g4, cs, ca, r + 3 * i);
     }
     // a wave with no active element in the group skips the reduction
     bool act = false;
@@ -205,16 +238,23 @@ __global__ __launch_bounds__(256) void kc1_sweep(DevNet net, void* ws, WsLayout 
 
 // Per line: v, vabs >= |v_exact|, ev >= |v^ - v_exact|; block partials of the
 // limit total sum |s| t and of sum vabs.
-__global__ __launch_bounds__(256) void kc2_lines(DevNet net, void* ws, WsLayout lay, int64_t box0) {
+__global__ __launch_bounds__(256) void kc2_lines(DevNet net, void* ws, const void* wsr, WsLayout lay,
+                                                 int64_t box0) {
   __shared__ double sh[4];
   const int64_t b = box0 + blockIdx.y;
   const int l = blockIdx.x * 256 + threadIdx.x;
   double v = 0.0, va = 0.0, ev = 0.0, T = 0.0;
   if (l < net.L) {
-    const double cf = ws_ptr<double>(ws, lay.lcf)[b * net.L + l];
-    const double rf = ws_ptr<double>(ws, lay.lrf)[b * net.L + l];
     const double fb = net.fmax_b[l];
-    const double sb = (fabs(cf) - rf - fb > 0.0) ? copysign(1.0, cf) : 0.0;
+    double sb;
+    if (wsr) {  // the base flow at the reference point
+      const double cr = ws_ptr<double>(const_cast<void*>(wsr), lay.lcf)[b * net.L + l];
+      sb = (fabs(cr) > fb) ? copysign(1.0, cr) : 0.0;
+    } else {
+      const double cf = ws_ptr<double>(ws, lay.lcf)[b * net.L + l];
+      const double rf = ws_ptr<double>(ws, lay.lrf)[b * net.L + l];
+      sb = (fabs(cf) - rf - fb > 0.0) ? copysign(1.0, cf) : 0.0;
+    }
     const int2 n = ws_ptr<int2>(ws, lay.ccnt)[b * net.Lp + l];
     v = sb + (double)n.x;
     va = fabs(sb) + (double)n.y;
@@ -313,21 +353,23 @@ __global__ __launch_bounds__(256) void kc3_ptdf_t(DevNet net, void* ws, WsLayout
 
 // Per input: coefficient G_j, its error bound E_j, and max over [lo_j, hi_j] of
 // G_j x_j (plus the curve interval's upper end); block partials (sum, sum |.|).
-__global__ __launch_bounds__(256) void kc4_inputs(DevNet net, void* ws, WsLayout lay, int64_t box0,
+__global__ __launch_bounds__(256) void kc4_inputs(DevNet net, void* ws, const void* wsr, WsLayout lay,
+                                                  int64_t box0,
                                                   const float* __restrict__ box_lo,
                                                   const float* __restrict__ box_hi,
                                                   float* __restrict__ vertex) {
   __shared__ double sh[4];
   const int64_t b = box0 + blockIdx.y;
   const int j = blockIdx.x * 256 + threadIdx.x;
-  const double* p1 = ws_ptr<double>(ws, lay.p1) + b * lay.n_p1 * kP1Fields;
+  // imbalance slope: from the total injection interval, or at the reference point
+  const double* p1 = ws_ptr<double>(wsr ? const_cast<void*>(wsr) : ws, lay.p1) + b * lay.n_p1 * kP1Fields;
   double cI = 0.0, rI = 0.0;
   for (int q = threadIdx.x; q < lay.n_p1; q += 256) {
     cI += p1[q * kP1Fields + kP1cI];
     rI += p1[q * kP1Fields + kP1rI];
   }
   cI = block_sum256(cI, sh);
-  rI = block_sum256(rI, sh);
+  rI = block_sum256(rI, sh);  // zero at a reference point
   double SV = 0.0;
   for (int q = threadIdx.x; q < lay.n_ct; q += 256) SV += ws_ptr<double2>(ws, lay.ct)[b * lay.n_ct + q].y;
   SV = block_sum256(SV, sh) * (1.0 + (lay.n_ct + 16) * kU64 * 1.01);
@@ -378,8 +420,10 @@ __global__ __launch_bounds__(256) void kc4_inputs(DevNet net, void* ws, WsLayout
   if (threadIdx.x == 0) ws_ptr<double2>(ws, lay.cp)[b * lay.n_cp + blockIdx.x] = make_double2(h, ha);
 }
 
+// again: a later relaxation of the same call, kept only where it is smaller.
 __global__ __launch_bounds__(256) void kc5_finalize(DevNet net, void* ws, WsLayout lay, int64_t box0,
-                                                    double* __restrict__ f_hi, double* __restrict__ crown) {
+                                                    double* __restrict__ f_hi, double* __restrict__ crown,
+                                                    int again) {
   __shared__ double sh[4];
   const int64_t b = box0 + blockIdx.x;
   double H = 0.0, Ha = 0.0, T = 0.0;
@@ -400,7 +444,7 @@ __global__ __launch_bounds__(256) void kc5_finalize(DevNet net, void* ws, WsLayo
   const double prev = f_hi[b];
   const double out = (prev != prev || ub != ub) ? NAN : fmin(prev, ub);
   f_hi[b] = out;
-  if (crown) crown[b] = (prev != prev) ? NAN : ub;
+  if (crown) crown[b] = (prev != prev) ? NAN : (again ? fmin(crown[b], ub) : ub);
 }
 
 // ---------------------------------------------------------------- many boxes
@@ -414,7 +458,9 @@ __global__ __launch_bounds__(256) void kc5_finalize(DevNet net, void* ws, WsLayo
 constexpr int kCB = 4;     // boxes per tile
 constexpr int kKPB = 32;   // outages per KC1b block
 
-__global__ __launch_bounds__(256) void kc1b_sweep(DevNet net, void* ws, WsLayout lay, int64_t n_box) {
+template <bool REF>
+__global__ __launch_bounds__(256) void kc1b_sweep(DevNet net, void* ws, const void* wsr, WsLayout lay,
+                                                  int64_t n_box) {
   __shared__ double shv[4][kKPB][kCB][2];
   __shared__ float shn[4][kKPB][kCB];
   const int64_t bt = (int64_t)blockIdx.x * kCB;  // first box of the tile
@@ -434,9 +480,16 @@ __global__ __launch_bounds__(256) void kc1b_sweep(DevNet net, void* ws, WsLayout
   for (int i = 0; i < kCB; ++i) {
     c4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     g4[i] = make_float4(FLT_MAX, FLT_MAX, FLT_MAX, FLT_MAX);
-    cd[i] = ws_ptr<int4>(ws, lay.ctg) + bb[i] * net.K;
+    cd[i] = ws_ptr<int4>(REF ? const_cast<void*>(wsr) : ws, lay.ctg) + bb[i] * net.K;
   }
-  if (live) {
+  if (live && REF) {
+    const float4 fc = reinterpret_cast<const float4*>(net.fmax_c32)[col];
+#pragma unroll
+    for (int i = 0; i < kCB; ++i) {
+      c4[i] = reinterpret_cast<const float4*>(ws_ptr<float>(const_cast<void*>(wsr), lay.lc) + bb[i] * net.Lp)[col];
+      g4[i] = fc;
+    }
+  } else if (live) {
     const float4 e4 = reinterpret_cast<const float4*>(net.line_eps)[col];
 #pragma unroll
     for (int i = 0; i < kCB; ++i) {
@@ -468,7 +521,8 @@ __global__ __launch_bounds__(256) void kc1b_sweep(DevNet net, void* ws, WsLayout
       for (int o = 0; o < 2; ++o)
         if (kg + o < k1)
 #pragma unroll
-          for (int i = 0; i < kCB; ++i) kc1_row(x[o], cd[i][kg + o], c4[i], g4[i], cs[i], ca[i], r + 3 * (o * kCB + i));
+          for (int i = 0; i < kCB; ++i)
+            kc1_row<REF>(x[o], cd[i][kg + o], c4[i], g4[i], cs[i], ca[i], r + 3 * (o * kCB + i));
     }
     bool act = false;
 #pragma unroll
@@ -591,30 +645,51 @@ void plan_crown(const DevNet& net, WsLayout& lay) {
   lay.n_ct = (net.L + 255) / 256;
 }
 
-hipError_t launch_crown(const DevNet& net, int64_t n_box, const float* lo, const float* hi, double* f_hi,
-                        double* crown, float* vertex, void* ws, const WsLayout& lay, hipStream_t s,
-                        KernelTimer* tm) {
+// Reference points: the box centre first, then halfway towards the vertex that
+// maximised the previous relaxation (float32; any point gives valid slopes).
+__global__ __launch_bounds__(256) void kc_ref_update(int64_t n, const float* __restrict__ lo,
+                                                     const float* __restrict__ hi, float* __restrict__ xref,
+                                                     const float* __restrict__ vtx, int first) {
+  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  if (i >= n) return;
+  xref[i] = first ? 0.5f * lo[i] + 0.5f * hi[i] : 0.5f * xref[i] + 0.5f * vtx[i];
+}
+
+// One relaxation pass over every box; wsr != nullptr takes the slopes at the
+// reference points whose forward data it holds.
+static void relax_pass(const DevNet& net, int64_t n_box, const float* lo, const float* hi, double* f_hi,
+                       double* crown, float* vertex, void* ws, const void* wsr, int again, const WsLayout& lay,
+                       hipStream_t s, KernelTimer* tm) {
+  const bool ref = wsr != nullptr;
   for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
     const int nb = (int)std::min<int64_t>(65535, n_box - b0);
-    int t = tm->start(10, s);
+    const int t = tm->start(10, s);
     const int64_t nz = (int64_t)nb * net.Lp;
     int2* cnt = reinterpret_cast<int2*>(static_cast<char*>(ws) + lay.ccnt) + b0 * net.Lp;
     hipLaunchKernelGGL(kc0_zero, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, cnt, nz);
-    if (net.K > 0 && n_box < kCB)
-      hipLaunchKernelGGL(kc1_sweep, dim3(lay.kc_bx, lay.kc_by, nb), dim3(256), 0, s, net, ws, lay, b0);
+    if (net.K > 0 && n_box < kCB) {
+      if (ref)
+        hipLaunchKernelGGL(kc1_sweep<true>, dim3(lay.kc_bx, lay.kc_by, nb), dim3(256), 0, s, net, ws, wsr, lay, b0);
+      else
+        hipLaunchKernelGGL(kc1_sweep<false>, dim3(lay.kc_bx, lay.kc_by, nb), dim3(256), 0, s, net, ws, wsr, lay,
+                           b0);
+    }
     tm->stop(t, s);
   }
   const unsigned tiles = (unsigned)((n_box + kCB - 1) / kCB);
   if (net.K > 0 && n_box >= kCB) {
     const int t = tm->start(10, s);
-    hipLaunchKernelGGL(kc1b_sweep, dim3(tiles, lay.kc_bx, (net.K + kKPB - 1) / kKPB), dim3(256), 0, s, net, ws,
-                       lay, n_box);
+    const dim3 grid(tiles, lay.kc_bx, (net.K + kKPB - 1) / kKPB);
+    if (ref)
+      hipLaunchKernelGGL(kc1b_sweep<true>, grid, dim3(256), 0, s, net, ws, wsr, lay, n_box);
+    else
+      hipLaunchKernelGGL(kc1b_sweep<false>, grid, dim3(256), 0, s, net, ws, wsr, lay, n_box);
     tm->stop(t, s);
   }
   for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
     const int nb = (int)std::min<int64_t>(65535, n_box - b0);
     const int t = tm->start(11, s);
-    hipLaunchKernelGGL(kc2_lines, dim3(lay.n_ct, nb), dim3(256), 0, s, net, ws, lay, b0);
+    hipLaunchKernelGGL(kc2_lines, dim3(lay.n_ct, nb), dim3(256), 0, s, net, ws, wsr, lay, b0);
     if (n_box < kCB)
       hipLaunchKernelGGL(kc3_ptdf_t, dim3(lay.kc3_bx, lay.kc3_by, nb), dim3(256), 0, s, net, ws, lay, b0);
     tm->stop(t, s);
@@ -626,11 +701,27 @@ hipError_t launch_crown(const DevNet& net, int64_t n_box, const float* lo, const
   }
   for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
     const int nb = (int)std::min<int64_t>(65535, n_box - b0);
-    int t;
-    t = tm->start(12, s);
-    hipLaunchKernelGGL(kc4_inputs, dim3(lay.n_cp, nb), dim3(256), 0, s, net, ws, lay, b0, lo, hi, vertex);
-    hipLaunchKernelGGL(kc5_finalize, dim3(nb), dim3(256), 0, s, net, ws, lay, b0, f_hi, crown);
+    const int t = tm->start(12, s);
+    hipLaunchKernelGGL(kc4_inputs, dim3(lay.n_cp, nb), dim3(256), 0, s, net, ws, wsr, lay, b0, lo, hi, vertex);
+    hipLaunchKernelGGL(kc5_finalize, dim3(nb), dim3(256), 0, s, net, ws, lay, b0, f_hi, crown, again);
     tm->stop(t, s);
+  }
+}
+
+hipError_t launch_crown(const DevNet& net, int64_t n_box, const float* lo, const float* hi, int ref_iters,
+                        double* f_hi, double* crown, float* vertex, void* ws, const WsLayout& lay, hipStream_t s,
+                        KernelTimer* tm) {
+  float* vtx = reinterpret_cast<float*>(static_cast<char*>(ws) + lay.vtx);
+  float* xref = reinterpret_cast<float*>(static_cast<char*>(ws) + lay.xref);
+  void* wsr = static_cast<char*>(ws) + lay.ref;
+  relax_pass(net, n_box, lo, hi, f_hi, crown, ref_iters > 0 ? vtx : vertex, ws, nullptr, 0, lay, s, tm);
+  const int64_t n = n_box * net.X;
+  for (int it = 0; it < ref_iters; ++it) {
+    hipLaunchKernelGGL(kc_ref_update, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, lo, hi, xref, vtx,
+                       it == 0 ? 1 : 0);
+    hipError_t e = launch_forward_prep(net, n_box, xref, xref, wsr, lay, s, tm);
+    if (e != hipSuccess) return e;
+    relax_pass(net, n_box, lo, hi, f_hi, crown, it + 1 == ref_iters ? vertex : vtx, ws, wsr, 1, lay, s, tm);
   }
   return hipGetLastError();
 }

@@ -92,6 +92,10 @@ struct WsLayout {
   size_t cp = 0;                   // double2 [B][n_cp]: per-input partial sums
   size_t ct = 0;                   // double2 [B][n_ct]: per-line partial sums (limit total, sum vabs)
   int kc_bx = 0, kc_by = 0, kc3_bx = 0, kc3_by = 0, n_cp = 0, n_ct = 0;
+  // reference points of the relaxation (present with the reference flag)
+  size_t fwd_total = 0;            // bytes of the forward arrays above (inj .. p3)
+  size_t ref = 0;                  // a second forward region, for the reference points
+  size_t xref = 0, vtx = 0;        // float [B][X]: reference points, maximising vertices
 };
 
 }  // namespace ibp

@@ -24,6 +24,7 @@ IBP_F_PLAIN = 1
 IBP_F_AUTOTUNE = 2
 IBP_F_BACKWARD = 4
 IBP_F_CROWN = 8
+IBP_F_CROWN_REF = 16
 
 STATUS = {
     0: "IBP_OK",
@@ -132,6 +133,7 @@ def load_library(path: str = LIB_PATH):
         pass
     lib = ctypes.CDLL(path)
     vp, sz, i64, u32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64, ctypes.c_uint32
+    i32 = ctypes.c_int32
     lib.ibp_build_network.argtypes = [ctypes.POINTER(NetworkDesc), ctypes.c_int, ctypes.POINTER(vp)]
     lib.ibp_build_network.restype = ctypes.c_int
     lib.ibp_network_query.argtypes = [vp, ctypes.POINTER(NetworkInfo)]
@@ -148,7 +150,7 @@ def load_library(path: str = LIB_PATH):
     lib.ibp_bound_boxes.restype = ctypes.c_int
     lib.ibp_bound_backward.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp, u32]
     lib.ibp_bound_backward.restype = ctypes.c_int
-    lib.ibp_crown_bound_boxes.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp, u32]
+    lib.ibp_crown_bound_boxes.argtypes = [vp, i64, vp, vp, i32, vp, vp, vp, vp, vp, sz, vp, u32]
     lib.ibp_crown_bound_boxes.restype = ctypes.c_int
     lib.ibp_set_kernel_timing.argtypes = [vp, ctypes.c_int]
     lib.ibp_set_kernel_timing.restype = ctypes.c_int
@@ -158,7 +160,6 @@ def load_library(path: str = LIB_PATH):
     lib.ibp_set_tile.restype = ctypes.c_int
     lib.ibp_autotune.argtypes = [vp, i64, vp, vp, vp, sz, vp, vp]
     lib.ibp_autotune.restype = ctypes.c_int
-    i32 = ctypes.c_int32
     lib.ibp_split_select.argtypes = [i64, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     lib.ibp_split_select.restype = ctypes.c_int
     lib.ibp_split_bisect.argtypes = [i64, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -365,11 +366,12 @@ def ibp_bound_backward(net: Network, lo, hi, g_lo, g_hi, flags: int = 0, ws: Wor
 
 
 def ibp_crown_bound_boxes(net: Network, lo, hi, crown: bool = False, flags: int = 0, ws: Workspace = None,
-                          stream=None, vertex=None):
+                          stream=None, vertex=None, ref_iters: int = 0):
     """IBP bounds with f_hi tightened by the linear relaxation of the penalties:
-    (f_lo, f_hi) or, with crown=True, (f_lo, f_hi, relaxation bound alone).
+    (f_lo, f_hi) or, with crown=True, (f_lo, f_hi, smallest relaxation bound).
+    ``ref_iters``: further relaxations with slopes taken at reference points.
     ``vertex``: optional float32 device tensor [n_box, X] that receives the box
-    vertex maximising the relaxation's linear part."""
+    vertex maximising the last relaxation's linear part."""
     torch = _torch()
     lo, hi = _check_boxes(net, lo, hi)
     n = lo.shape[0]
@@ -377,13 +379,13 @@ def ibp_crown_bound_boxes(net: Network, lo, hi, crown: bool = False, flags: int 
     f_hi = torch.empty(n, dtype=torch.float64, device=lo.device)
     c = torch.empty(n, dtype=torch.float64, device=lo.device) if crown else None
     ws = ws or Workspace(net)
-    buf, need = ws.get(n, flags | IBP_F_CROWN)
+    buf, need = ws.get(n, flags | IBP_F_CROWN | (IBP_F_CROWN_REF if ref_iters > 0 else 0))
     if vertex is not None and (vertex.dtype != torch.float32 or tuple(vertex.shape) != tuple(lo.shape)
                                or not vertex.is_contiguous() or vertex.device != lo.device):
         raise ValueError("vertex must be a contiguous float32 device tensor shaped like the boxes")
-    _check(load_library().ibp_crown_bound_boxes(net.handle, n, _dev_ptr(lo), _dev_ptr(hi), _dev_ptr(f_lo),
-                                                _dev_ptr(f_hi), _dev_ptr(c), _dev_ptr(vertex), _dev_ptr(buf),
-                                                buf.numel(), _stream_ptr(stream), flags))
+    _check(load_library().ibp_crown_bound_boxes(net.handle, n, _dev_ptr(lo), _dev_ptr(hi), int(ref_iters),
+                                                _dev_ptr(f_lo), _dev_ptr(f_hi), _dev_ptr(c), _dev_ptr(vertex),
+                                                _dev_ptr(buf), buf.numel(), _stream_ptr(stream), flags))
     return (f_lo, f_hi, c) if crown else (f_lo, f_hi)
 
 

@@ -131,3 +131,62 @@ def test_bad_boxes_radial_network_and_empty_batch():
     e = torch.empty((0, n.n_input), dtype=torch.float32, device="cuda")
     a, b = ibp.ibp_crown_bound_boxes(n, e, e)
     assert a.numel() == 0 and b.numel() == 0
+
+
+def gpu_crown_ref(n, lo, hi, iters, flags=0):
+    torch = _torch()
+    tlo = torch.from_numpy(np.ascontiguousarray(np.atleast_2d(lo), np.float32)).cuda()
+    thi = torch.from_numpy(np.ascontiguousarray(np.atleast_2d(hi), np.float32)).cuda()
+    out = ibp.ibp_crown_bound_boxes(n, tlo, thi, crown=True, flags=flags, ref_iters=iters)
+    torch.cuda.synchronize()
+    return tuple(o.cpu().numpy() for o in out)
+
+
+@pytest.mark.parametrize("flags", [0, ibp.IBP_F_PLAIN])
+def test_reference_point_relaxations_tiny(flags):
+    """One reference relaxation (at the box centre) matches the oracle's; with six,
+    the bound stays >= the LP, never exceeds the first relaxation, and reaches
+    the LP optimum on several boxes."""
+    net, fac, n = setup("tiny")
+    blo, bhi = synth.sub_boxes(net, 6, seed=3)
+    _, _, c0 = gpu_crown(n, blo, bhi, flags=flags)
+    f_lo, f_hi, c1 = gpu_crown_ref(n, blo, bhi, 1, flags=flags)
+    i_lo, i_hi = gpu_bounds(n, blo, bhi, flags=flags)
+    for b in range(6):
+        r = oracle.crown_upper_iterated(net, blo[b], bhi[b], fac, iters=1)
+        assert f_hi[b] == min(i_hi[b], c1[b])
+        if r["near"] == 0:
+            # relative to max(|f|, term scale, 1 $), as for the IBP bounds
+            scale = max(abs(r["f_hi"]), term_scale(orc(net, blo[b], bhi[b], fac), "hi"), 1.0)
+            assert c1[b] >= r["f_hi"] and (c1[b] - r["f_hi"]) / scale <= 1e-5, (b, c1[b], r["f_hi"])
+    _, _, c6 = gpu_crown_ref(n, blo, bhi, 6, flags=flags)
+    reached = 0
+    for b in range(6):
+        lp = _lp_max(net, blo[b].astype(float), bhi[b].astype(float), fac)
+        assert c6[b] >= lp - 1e-7 * max(1.0, abs(lp))
+        assert c6[b] <= c0[b] and c6[b] <= c1[b]
+        reached += (c6[b] - lp) <= 1e-5 * max(1.0, abs(lp))
+        print(f"[tiny box {b}] lp {lp:.4f} relaxation {c0[b]:.4f} -> {c6[b]:.4f}", flush=True)
+    assert reached >= 3
+
+
+def test_reference_point_relaxations_c500_and_c8316():
+    net, fac, n = setup("c500")
+    blo, bhi = synth.sub_boxes(net, 5, seed=9)
+    _, _, c2 = gpu_crown_ref(n, blo, bhi, 2)
+    _, _, c0 = gpu_crown(n, blo, bhi)
+    for b in range(5):
+        r = oracle.crown_upper_iterated(net, blo[b], bhi[b], fac, iters=2)
+        assert c2[b] <= c0[b]
+        scale = max(abs(r["f_hi"]), term_scale(orc(net, blo[b], bhi[b], fac), "hi"), 1.0)
+        if r["near"] == 0:
+            assert c2[b] >= r["f_hi"] and (c2[b] - r["f_hi"]) / scale <= 1e-5, (b, c2[b], r["f_hi"])
+        print(f"[c500 box {b}] oracle {r['bounds']} gpu {c2[b]:.6e} near {r['near']}", flush=True)
+    net, fac, n = setup("c8316")
+    lo, hi = synth.full_box(net)
+    _, _, c1 = gpu_crown_ref(n, lo, hi, 1)
+    r = oracle.crown_upper_iterated(net, lo, hi, fac, iters=1)
+    print(f"[c8316] oracle {r['bounds']} gpu {c1[0]:.6e} near {r['near']}", flush=True)
+    if r["near"] == 0:
+        scale = max(abs(r["f_hi"]), term_scale(orc(net, lo, hi, fac), "hi"), 1.0)
+        assert c1[0] >= r["f_hi"] and (c1[0] - r["f_hi"]) / scale <= 1e-5
