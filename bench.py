@@ -259,6 +259,9 @@ def extras(torch, ibp, synth, n4, net4):
     _, c_hi3 = ibp.ibp_crown_bound_boxes(n3, c3l, c3h, ws=ws3c)
     _, i_hi3 = ibp.ibp_bound_boxes(n3, c3l, c3h, ws=ws3c)
     tight3 = ((i_hi3 - c_hi3) / i_hi3.abs()).cpu()
+    ms_r3 = _time(torch, lambda: ibp.ibp_crown_bound_boxes(n3, c3l, c3h, ws=ws3c, ref_iters=4), 1)
+    _, r_hi3 = ibp.ibp_crown_bound_boxes(n3, c3l, c3h, ws=ws3c, ref_iters=4)
+    tightr = ((i_hi3 - r_hi3) / i_hi3.abs()).cpu()
     res["crown"] = {
         "workload": "linear-relaxation upper bound: the large single box; 1024 sub-boxes (2000 buses)",
         "single_box_ms": ms_c1, "single_box_ms_ibp_only": ms_lin,
@@ -268,6 +271,9 @@ def extras(torch, ibp, synth, n4, net4):
         "batch_ms": ms_c3, "batch_ms_ibp_only": ms_i3,
         "batch_value": 1024 * n3.n_ctg * n3.n_line / (ms_c3 * 1e-3),
         "batch_f_hi_tightening_mean": float(tight3.mean()), "batch_f_hi_tightening_max": float(tight3.max()),
+        "batch_ms_4_reference_points": ms_r3,
+        "batch_f_hi_tightening_mean_4_reference_points": float(tightr.mean()),
+        "batch_f_hi_tightening_max_4_reference_points": float(tightr.max()),
     }
     # splitting: 4096 roots, 10 rounds of gradient-ranked bisection
     from paper_2511_15624_amd.split import BoxSplitter
@@ -304,11 +310,20 @@ def extras(torch, ibp, synth, n4, net4):
     hist = bb.run(40)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    bbr = BranchAndBound(nt, tl, th, rounds=40, relax=True, ref_iters=4)
+    c_root_r = bbr.counts()
+    hist_r = bbr.run(40)
+    torch.cuda.synchronize()
+    secs_r = time.perf_counter() - t0
     res["branch_and_bound"] = {
         "workload": "14-bus network, 4096 instance boxes; screening for max f < 0 / >= 0; relaxation bounds "
                     "and vertex points; up to 40 rounds on the open roots",
         "statuses_ibp_roots": c_ibp, "statuses_relaxation_roots": c_root, "statuses_final": bb.counts(),
         "rounds_run": len(hist), "open_per_round": [h[2] for h in hist], "seconds": secs,
+        "with_4_reference_points": {"statuses_roots": c_root_r, "statuses_final": bbr.counts(),
+                                    "rounds_run": len(hist_r), "open_per_round": [h[2] for h in hist_r],
+                                    "seconds": secs_r},
     }
     return res
 

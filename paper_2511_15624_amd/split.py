@@ -45,6 +45,8 @@ class BranchAndBound:
 
     relax:   bound children with the linear relaxation (tighter upper bounds,
              and its maximising vertex as a second point per child).
+    ref_iters: further relaxations per bound with slopes taken at reference
+             points (see ``ibp_crown_bound_boxes``).
     screen:  drop roots from the open list once their status is decided
              (max f < 0 or >= 0 certified) or their gap is below rel_tol.
     """
@@ -53,7 +55,7 @@ class BranchAndBound:
               "status", "open_roots")
 
     def __init__(self, net: _ibp.Network, lo: torch.Tensor, hi: torch.Tensor, rounds: int = 10,
-                 relax: bool = True, screen: bool = True, rel_tol: float = 1e-6):
+                 relax: bool = True, screen: bool = True, rel_tol: float = 1e-6, ref_iters: int = 0):
         lo, hi = _ibp._check_boxes(net, lo, hi)
         self.net = net
         self.R, self.X = lo.shape
@@ -61,6 +63,7 @@ class BranchAndBound:
         self.relax = bool(relax)
         self.screen_on = bool(screen)
         self.rel_tol = float(rel_tol)
+        self.ref_iters = int(ref_iters) if relax else 0
         self.round = 0
         dev = lo.device
         R, S, X = self.R, self.S, self.X
@@ -106,7 +109,8 @@ class BranchAndBound:
     def _bound(self, lo, hi, n, stream=None):
         if self.relax:
             vt = self.vtx[:n] if n <= self.vtx.shape[0] else torch.empty_like(lo)
-            _, f_hi = _ibp.ibp_crown_bound_boxes(self.net, lo, hi, ws=self.ws_f, stream=stream, vertex=vt)
+            _, f_hi = _ibp.ibp_crown_bound_boxes(self.net, lo, hi, ws=self.ws_f, stream=stream, vertex=vt,
+                                                 ref_iters=self.ref_iters)
             return f_hi, vt
         _, f_hi = _ibp.ibp_bound_boxes(self.net, lo, hi, ws=self.ws_f, stream=stream)
         return f_hi, None
