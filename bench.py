@@ -159,6 +159,18 @@ def _time(torch, fn, reps):
 def extras(torch, ibp, synth, n4, net4):
     """Batched, backward and splitting throughput next to the per-box (plain) form."""
     res = {}
+    # latency of one whole box on the small networks (one C-ABI call each)
+    lat = {}
+    for name in ("tiny", "c500"):
+        netx = synth.make_config(name)
+        nx = ibp.Network(netx, device=0)
+        lx, hx = synth.full_box(netx)
+        tl, th = torch.from_numpy(lx[None].copy()).cuda(), torch.from_numpy(hx[None].copy()).cuda()
+        wsx = ibp.Workspace(nx)
+        lat[name + "_us"] = round(_time(torch, lambda: ibp.ibp_bound_boxes(nx, tl, th, ws=wsx), 200) * 1e3, 2)
+        nx.close()
+    res["latency"] = {"workload": "whole box, one call: 14 buses / 19 outages and 500 buses / 590 outages",
+                      **lat}
     # batched: 2000-bus network, 18 periods x 1024 sub-boxes in one call
     net3 = synth.make_config("c2000")
     n3 = ibp.Network(net3, device=0)
