@@ -153,6 +153,11 @@ ibp_status to_device(ibp_network* net, int device) {
     }
     if ((st = upload(net, eps.data(), eps.size(), &d.ctg_eps)) != IBP_OK) return st;
     if ((st = upload(net, inv.data(), inv.size(), &d.ctg_inv)) != IBP_OK) return st;
+    // the same constants indexed by line, so that a per-line kernel loads them
+    // together with its other line data
+    std::vector<double2> lk(std::max(1, h.L), make_double2(0.0, 0.0));
+    for (int k = 0; k < h.K; ++k) lk[h.ctg_line[k]] = make_double2(eps[k], inv[k]);
+    if ((st = upload(net, lk.data(), lk.size(), &d.line_ctg)) != IBP_OK) return st;
     std::vector<float> le(d.Lp, 0.0f);
     for (int l = 0; l < h.L; ++l) {
       // 2 eps_l plus the float32 subnormal spacing of a stored factor, rounded up
@@ -186,6 +191,12 @@ ibp_status to_device(ibp_network* net, int device) {
     for (int j = 0; j < h.D; ++j) w[h.G + j] = h.load_value[j];
     if ((st = upload(net, ptr.data(), ptr.size(), &d.bus_ptr)) != IBP_OK) return st;
     if ((st = upload(net, dev.data(), dev.size(), &d.bus_dev)) != IBP_OK) return st;
+    std::vector<int4> dev4(h.N, make_int4(-1, -1, -1, -1));
+    for (int n = 0; n < h.N; ++n) {
+      int* q = &dev4[n].x;
+      for (int e = ptr[n]; e < std::min(ptr[n + 1], ptr[n] + 4); ++e) q[e - ptr[n]] = dev[e];
+    }
+    if ((st = upload(net, dev4.data(), dev4.size(), &d.bus_dev4)) != IBP_OK) return st;
     if ((st = upload(net, w.data(), w.size(), &d.dev_w)) != IBP_OK) return st;
   }
   d.seg_ptr = nullptr;

@@ -47,11 +47,13 @@ struct DevNet {
   const int* ctg_line;      // [K]
   const double* ctg_eps;    // [K] 2 phi_err[c] / (1 - H_cc)
   const double* ctg_inv;    // [K] 1 / (1 - H_cc)
+  const double2* line_ctg;  // [L] (ctg_eps, ctg_inv) of the outage of line l, (0, 0) if it has none
   const float* line_eps;    // [Lp] 2 phi_err[l], rounded up (0 on padding lines)
   const float* fmax_c32;    // [Lp] post-outage limit as float32 (FLT_MAX on padding lines)
   const int* dev_bus;       // [X] bus of each input (generators, then loads)
   const int* bus_ptr;       // [N + 1] CSR over buses of the devices on each bus
   const int* bus_dev;       // [X] device indices (0..G-1 generators, G..X-1 loads)
+  const int4* bus_dev4;     // [N] the first four entries of bus_dev for each bus, -1 where it has fewer
   const double* dev_w;      // [X] -cost for generators, +value for loads
   const int* seg_ptr;       // [X + 1] curve segments of each input, or nullptr (linear costs only)
   const double4* seg;       // [S] (slope a, shift b, cap U, |U| if finite else 0)

@@ -32,21 +32,37 @@ namespace ibp {
 
 // Injection interval of bus n, p_inj = N_g p_g - N_d p_d, rounded outward to
 // float32: out = (c32, r''), where r'' also covers the float32 storage error
-// of the PTDF entries it will multiply; mc = |c32|, mbox = |c32| + r32.
+// of the PTDF entries it will multiply; mc = |c32|, mbox = |c32| + r32.  The
+// endpoints of the bus's first four devices are loaded together; further
+// devices (rare) follow in a loop.  Terms are added in device order.
 __device__ __forceinline__ void bus_injection(const DevNet& net, const float* __restrict__ lo,
                                               const float* __restrict__ hi, int n, double2& out, double& mc,
                                               double& mbox) {
+  const int4 d4 = net.bus_dev4[n];
+  const int e0 = net.bus_ptr[n], e1 = net.bus_ptr[n + 1];
+  const int js[4] = {d4.x, d4.y, d4.z, d4.w};
+  float l4[4], h4[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int j = max(js[q], 0);
+    l4[q] = lo[j];
+    h4[q] = hi[j];
+  }
   double c = 0, r = 0, a = 0;
   int cnt = 0;
-  const int e0 = net.bus_ptr[n], e1 = net.bus_ptr[n + 1];
-  for (int e = e0; e < e1; ++e) {
-    const int j = net.bus_dev[e];
-    const double l = lo[j], h = hi[j];
+  auto add = [&](int j, double l, double h) {
     const double cj = 0.5 * (l + h), rj = 0.5 * (h - l);
     c += (j < net.G) ? cj : -cj;
     r += rj;
     a += fabs(cj);
     ++cnt;
+  };
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (js[q] >= 0) add(js[q], l4[q], h4[q]);
+  for (int e = e0 + 4; e < e1; ++e) {
+    const int j = net.bus_dev[e];
+    add(j, lo[j], hi[j]);
   }
   // float64 summation error of c and r (cnt terms each)
   const double e64 = (cnt + 1) * kU64 * (a + r) * 1.01;
@@ -62,12 +78,10 @@ __device__ __forceinline__ void bus_injection(const DevNet& net, const float* __
 // Per-input terms of the box-preparation sums: surplus (linear part and
 // curves), total injection, validity.  Centre and radius of float32 endpoints
 // are exact in float64.
-__device__ __forceinline__ void input_terms(const DevNet& net, const float* __restrict__ lo,
-                                            const float* __restrict__ hi, int i, double (&v)[kP1Fields]) {
-  const double l = lo[i], h = hi[i];
+__device__ __forceinline__ void input_terms(const DevNet& net, int i, double l, double h, double w,
+                                            double (&v)[kP1Fields]) {
   if (!(l <= h) || !isfinite(l) || !isfinite(h)) v[kP1Bad] += 1.0;
   const double c = 0.5 * (l + h), r = 0.5 * (h - l);
-  const double w = net.dev_w[i];
   v[kP1Sc] += w * c;
   v[kP1Sr] += fabs(w) * r;
   v[kP1Sabs] += fabs(w * c) + fabs(w) * r;
@@ -116,12 +130,13 @@ __global__ __launch_bounds__(64) void k1_box_prep(DevNet net, const float* __res
   double v[kP1Fields];
 #pragma unroll
   for (int f = 0; f < kP1Fields; ++f) v[f] = 0.0;
-  if (i < net.Np) {
-    double2 cr = make_double2(0.0, 0.0);
-    if (i < net.N) bus_injection(net, lo, hi, i, cr, v[kP1Mc], v[kP1Mbox]);
-    ws_ptr<double2>(ws, lay.inj)[b * net.Np + i] = cr;
-  }
-  if (i < net.X) input_terms(net, lo, hi, i, v);
+  // this lane's input, loaded before the bus's dependent loads start
+  const int ix = min(i, net.X - 1);
+  const double li = lo[ix], hi_i = hi[ix], wi = net.dev_w[ix];
+  double2 cr = make_double2(0.0, 0.0);
+  if (i < net.N) bus_injection(net, lo, hi, i, cr, v[kP1Mc], v[kP1Mbox]);
+  if (i < net.X) input_terms(net, i, li, hi_i, wi, v);
+  if (i < net.Np) ws_ptr<double2>(ws, lay.inj)[b * net.Np + i] = cr;
 #pragma unroll
   for (int f = 0; f < kP1Fields; ++f) v[f] = wave_sum(v[f]);
   if (threadIdx.x < kP1Fields) {
@@ -137,18 +152,29 @@ __global__ __launch_bounds__(64) void k1_box_prep(DevNet net, const float* __res
 
 // ---------------------------------------------------------------- K2
 
+// Per-line data of the epilogue, loaded together before any of it is used.
+struct LineConst {
+  double phi_err, fmax_b, fmax_c;
+  double2 ctg;  // (ctg_eps, ctg_inv) of the line's outage
+  int k;        // outage index or -1
+};
+
+__device__ __forceinline__ LineConst load_line_const(const DevNet& net, int l) {
+  return LineConst{net.phi_err[l], net.fmax_b[l], net.fmax_c[l], net.line_ctg[l], net.ctg_of_line[l]};
+}
+
 // Per-line float64 epilogue: enclosing radius of the base flow, base penalties,
 // and the per-line / per-outage constants of K3 (see the error model at K3).
 // Returns the float bits of (|c_c| + r_c) / (1 - H_cc) rounded up if the line
 // is an outage line (0 otherwise), for the caller's max reduction.
-__device__ __forceinline__ unsigned line_epilogue(const DevNet& net, int l, double cf, double rh, double Mc,
-                                                  double Mbox, float* lc, float* lh, float* lg,
-                                                  double* lcf, double* lrf, int4* ctg, double& pb_hi,
+__device__ __forceinline__ unsigned line_epilogue(const DevNet& net, int l, const LineConst& q, double cf,
+                                                  double rh, double Mc, double Mbox, float* lc, float* lh,
+                                                  float* lg, double* lcf, double* lrf, int4* ctg, double& pb_hi,
                                                   double& pb_lo) {
   const double gam = net.gamma64_n;
   // enclosing radius around the float64 centre cf: float64 accumulation of
   // |Phi32| r'' and Phi32 c32, and the float64 construction error of Phi
-  const double rf = (rh * (1.0 + 2.0 * gam) + gam * Mc + net.phi_err[l] * Mbox) * (1.0 + 8.0 * kU64);
+  const double rf = (rh * (1.0 + 2.0 * gam) + gam * Mc + q.phi_err * Mbox) * (1.0 + 8.0 * kU64);
   const float cl = (float)cf;
   const double acl = fabs((double)cl);
   const double rl = rf + fabs(cf - (double)cl);
@@ -156,14 +182,14 @@ __device__ __forceinline__ unsigned line_epilogue(const DevNet& net, int l, doub
   lrf[l] = rf;
 
   // base overload penalty interval [max(|c|-r-fmax, 0), max(|c|+r-fmax, 0)]
-  const double phib = net.fmax_b[l];
+  const double phib = q.fmax_b;
   const double a = fabs(cf);
   const double e = 4.0 * kU64 * (a + rf + phib);
   pb_hi += fmax(a + rf - phib + e, 0.0);
   pb_lo += fmax(a - rf - phib - e, 0.0);
 
   // K3 per-line constants
-  const double phic = net.fmax_c[l];
+  const double phic = q.fmax_c;
   constexpr double u1 = kU32 * (1.0 + kU32);
   constexpr double dl = 2.0 * kU32 * (1.0 + kU32) * (1.0 + kU32);
   constexpr double inv1md = 1.0 / (1.0 - dl);  // the 16 u64 factor covers its rounding
@@ -173,69 +199,102 @@ __device__ __forceinline__ unsigned line_epilogue(const DevNet& net, int l, doub
   lh[l] = ru32(rhop - phic + 4.0 * kU64 * (rhop + phic));
   lg[l] = ru32((rhop + phic) * (1.0 + 4.0 * kU64));
 
-  const int k = net.ctg_of_line[l];
-  if (k >= 0) {
-    const double Ek = net.ctg_eps[k] * (acl + rl);
+  if (q.k >= 0) {
+    const double Ek = q.ctg.x * (acl + rl);
     const double rk = (1.0 + kKappa0) * rl + (kKappa0 + kU32) * acl + Ek;
     const double rkp = ((rk + u1 * acl) * inv1md) * (1.0 + 16.0 * kU64) + 1e-36;
     // fourth field: the unpadded radius, read by the backward sweep
-    ctg[k] = make_int4(l, __float_as_int(cl), __float_as_int(ru32(rkp)), __float_as_int((float)rf));
-    const float v = ru32((acl + rl) * net.ctg_inv[k] * (1.0 + 4.0 * kU64));
+    ctg[q.k] = make_int4(l, __float_as_int(cl), __float_as_int(ru32(rkp)), __float_as_int((float)rf));
+    const float v = ru32((acl + rl) * q.ctg.y * (1.0 + 4.0 * kU64));
     return __float_as_uint(v);
   }
   return 0u;
 }
 
-// One wave per 64 lines: combine the K2 partials of every bus chunk and run
-// the line epilogue; one base-penalty partial per wave.
-__global__ __launch_bounds__(64) void k2e_lines(DevNet net, void* ws, WsLayout lay, int64_t box0) {
+constexpr int kK2eThreads = 256;
+constexpr int kK2eBy = 16;  // base-flow partials per line loaded in one round
+
+// One line per lane, kK2eThreads lines per block: combine the K2 partials of
+// every bus chunk and run the line epilogue; one base-penalty partial per wave
+// (64 lines) and one max-reduction atomic per block.  Every load that does not depend on another is issued before the
+// first use, so the kernel waits on memory about twice instead of once per
+// dependent step; indices are clamped rather than branched on so the loads
+// stay in one group.
+__global__ __launch_bounds__(kK2eThreads) void k2e_lines(DevNet net, void* ws, WsLayout lay, int64_t box0) {
   const int64_t b = box0 + blockIdx.y;
-  const int l = blockIdx.x * 64 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int l = blockIdx.x * kK2eThreads + threadIdx.x;
+  const int lq = min(l, net.L - 1);
   const double* p1 = ws_ptr<double>(ws, lay.p1) + b * lay.n_p1 * kP1Fields;
+  const double2* part = ws_ptr<double2>(ws, lay.part2) + (size_t)b * lay.k2_by * net.Lp + lq;
+  const int nby = lay.k2_by;
+
+  // every wave sums all box-preparation partials of Mc and Mbox itself
   double mc = 0.0, mb = 0.0;
-  for (int j = threadIdx.x; j < lay.n_p1; j += 64) {
+  double2 t[kK2eBy];
+  LineConst q;
+  {
+    double xm[4], xb[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = min(lane + 64 * u, lay.n_p1 - 1);
+      xm[u] = p1[j * kP1Fields + kP1Mc];
+      xb[u] = p1[j * kP1Fields + kP1Mbox];
+    }
+#pragma unroll
+    for (int y = 0; y < kK2eBy; ++y) t[y] = part[(size_t)min(y, nby - 1) * net.Lp];
+    q = load_line_const(net, lq);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (lane + 64 * u < lay.n_p1) {
+        mc += xm[u];
+        mb += xb[u];
+      }
+  }
+  for (int j = lane + 256; j < lay.n_p1; j += 64) {
     mc += p1[j * kP1Fields + kP1Mc];
     mb += p1[j * kP1Fields + kP1Mbox];
+  }
+  double cf[4] = {0, 0, 0, 0}, rh[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int y = 0; y < kK2eBy; ++y)
+    if (y < nby) {
+      cf[y & 3] += t[y].x;
+      rh[y & 3] += t[y].y;
+    }
+  for (int y = kK2eBy; y < nby; ++y) {
+    const double2 u = part[(size_t)y * net.Lp];
+    cf[y & 3] += u.x;
+    rh[y & 3] += u.y;
   }
   const double g = (lay.n_p1 + 16) * kU64 * 1.01;
   mc = wave_sum(mc) * (1.0 + g);
   mb = wave_sum(mb) * (1.0 + g);
   double pb_hi = 0.0, pb_lo = 0.0;
   unsigned vm = 0u;
-  if (l < net.L) {
-    const double2* part = ws_ptr<double2>(ws, lay.part2) + (size_t)b * lay.k2_by * net.Lp + l;
-    double cf[4] = {0, 0, 0, 0}, rh[4] = {0, 0, 0, 0};
-    int y = 0;
-    for (; y + 4 <= lay.k2_by; y += 4) {
-      double2 t[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) t[q] = part[(size_t)(y + q) * net.Lp];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        cf[q] += t[q].x;
-        rh[q] += t[q].y;
-      }
-    }
-    for (; y < lay.k2_by; ++y) {
-      const double2 t = part[(size_t)y * net.Lp];
-      cf[0] += t.x;
-      rh[0] += t.y;
-    }
-    vm = line_epilogue(net, l, (cf[0] + cf[1]) + (cf[2] + cf[3]), (rh[0] + rh[1]) + (rh[2] + rh[3]), mc, mb,
+  if (l < net.L)
+    vm = line_epilogue(net, l, q, (cf[0] + cf[1]) + (cf[2] + cf[3]), (rh[0] + rh[1]) + (rh[2] + rh[3]), mc, mb,
                        ws_ptr<float>(ws, lay.lc) + b * net.Lp, ws_ptr<float>(ws, lay.lh) + b * net.Lp,
                        ws_ptr<float>(ws, lay.lg) + b * net.Lp, ws_ptr<double>(ws, lay.lcf) + b * net.L,
-                       ws_ptr<double>(ws, lay.lrf) + b * net.L, ws_ptr<int4>(ws, lay.ctg) + b * net.K,
-                       pb_hi, pb_lo);
-  }
-  // max over the wave, then one atomic (non-negative floats order like their bit patterns)
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) vm = max(vm, (unsigned)__shfl_xor((int)vm, m, 64));
+                       ws_ptr<double>(ws, lay.lrf) + b * net.L, ws_ptr<int4>(ws, lay.ctg) + b * net.K, pb_hi,
+                       pb_lo);
+  // max over the wave (non-negative floats order like their bit patterns)
+  vm = wave_max_u32(vm);
   pb_hi = wave_sum(pb_hi);
   pb_lo = wave_sum(pb_lo);
+  // one atomic per block: same-address atomics from every wave queue up
+  const int wi = blockIdx.x * (kK2eThreads / 64) + w;
+  __shared__ unsigned svm[kK2eThreads / 64];
+  if (lane == 0) svm[w] = vm;
+  if (lane == 0 && wi < lay.n_p2) ws_ptr<double2>(ws, lay.p2)[b * lay.n_p2 + wi] = make_double2(pb_hi, pb_lo);
+  __syncthreads();
   if (threadIdx.x == 0) {
-    if (vm != 0u)
-      atomicMax(reinterpret_cast<unsigned int*>(ws_ptr<double>(ws, lay.box) + b * kBoxSlots + kVmax), vm);
-    ws_ptr<double2>(ws, lay.p2)[b * lay.n_p2 + blockIdx.x] = make_double2(pb_hi, pb_lo);
+    unsigned m = 0u;
+#pragma unroll
+    for (int q = 0; q < kK2eThreads / 64; ++q) m = max(m, svm[q]);
+    if (m != 0u)
+      atomicMax(reinterpret_cast<unsigned int*>(ws_ptr<double>(ws, lay.box) + b * kBoxSlots + kVmax), m);
   }
 }
 
@@ -313,48 +372,59 @@ __global__ __launch_bounds__(256) void k2_base_flows(DevNet net, void* ws, WsLay
 
 // ---------------------------------------------------------------- K4
 
-constexpr int kK4Threads = 256;
-
-// Objective interval of one box from all partial sums (run by one block of
-// kK4Threads threads after every partial is visible).
+// Objective interval of one box from all partial sums, run by one block of T
+// threads after every partial is visible.  The first T partials of each kind
+// are loaded in one group (clamped indices, masked adds); loops take the rest.
+template <int T>
 __device__ void finalize_box(const DevNet& net, void* ws, const WsLayout& lay, int64_t b,
                              double* __restrict__ f_lo, double* __restrict__ f_hi,
                              double* __restrict__ terms) {
   const double* p1 = ws_ptr<double>(ws, lay.p1) + b * lay.n_p1 * kP1Fields;
   const double2* p2 = ws_ptr<double2>(ws, lay.p2) + b * lay.n_p2;
   const double2* p3 = ws_ptr<double2>(ws, lay.p3) + b * lay.n_p3;
+  constexpr int kQ3 = 32;  // outage-sweep partials per thread in the first group
+  const int tid = threadIdx.x;
   double v[kP1Fields];
+  double bh = 0, bl = 0;
+  double ch[4] = {0, 0, 0, 0}, cl[4] = {0, 0, 0, 0};
+  {
+    const int j1 = min(tid, lay.n_p1 - 1);
+    double x1[kP1Fields];
 #pragma unroll
-  for (int f = 0; f < kP1Fields; ++f) v[f] = 0.0;
-  for (int j = threadIdx.x; j < lay.n_p1; j += kK4Threads)
+    for (int f = kP1Sc; f < kP1Fields; ++f) x1[f] = p1[j1 * kP1Fields + f];
+    const double2 x2 = p2[min(tid, lay.n_p2 - 1)];
+    double2 x3[kQ3];
+    const int n3 = lay.n_p3;
+#pragma unroll
+    for (int q = 0; q < kQ3; ++q) x3[q] = p3[max(0, min(tid + q * T, n3 - 1))];
+#pragma unroll
+    for (int f = 0; f < kP1Fields; ++f) v[f] = (f >= kP1Sc && tid < lay.n_p1) ? x1[f] : 0.0;
+    if (tid < lay.n_p2) {
+      bh = x2.x;
+      bl = x2.y;
+    }
+#pragma unroll
+    for (int q = 0; q < kQ3; ++q)
+      if (tid + q * T < n3) {
+        ch[q & 3] += x3[q].x;
+        cl[q & 3] += x3[q].y;
+      }
+  }
+  for (int j = tid + T; j < lay.n_p1; j += T)
 #pragma unroll
     for (int f = kP1Sc; f < kP1Fields; ++f) v[f] += p1[j * kP1Fields + f];
-  double bh = 0, bl = 0;
-  for (int i = threadIdx.x; i < lay.n_p2; i += kK4Threads) {
-    const double2 t = p2[i];
-    bh += t.x;
-    bl += t.y;
+  for (int i = tid + T; i < lay.n_p2; i += T) {
+    const double2 x = p2[i];
+    bh += x.x;
+    bl += x.y;
   }
-  // four independent partial sums keep several loads in flight
-  double ch[4] = {0, 0, 0, 0}, cl[4] = {0, 0, 0, 0};
-  int i = threadIdx.x;
-  for (; i + 7 * kK4Threads < lay.n_p3; i += 8 * kK4Threads) {
-    double2 t[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) t[q] = p3[i + q * kK4Threads];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      ch[q & 3] += t[q].x;
-      cl[q & 3] += t[q].y;
-    }
-  }
-  for (; i < lay.n_p3; i += kK4Threads) {
-    const double2 t = p3[i];
-    ch[0] += t.x;
-    cl[0] += t.y;
+  for (int i = tid + kQ3 * T; i < lay.n_p3; i += T) {
+    const double2 x = p3[i];
+    ch[0] += x.x;
+    cl[0] += x.y;
   }
   // one combined block reduction of the 12 running sums
-  constexpr int W = kK4Threads / 64;
+  constexpr int W = T / 64;
   __shared__ double red[W][12];
   double x[12];
 #pragma unroll
@@ -365,19 +435,19 @@ __device__ void finalize_box(const DevNet& net, void* ws, const WsLayout& lay, i
   x[11] = (cl[0] + cl[1]) + (cl[2] + cl[3]);
 #pragma unroll
   for (int f = 0; f < 12; ++f) x[f] = wave_sum(x[f]);
-  if ((threadIdx.x & 63) == 0)
+  if ((tid & 63) == 0)
 #pragma unroll
-    for (int f = 0; f < 12; ++f) red[threadIdx.x >> 6][f] = x[f];
+    for (int f = 0; f < 12; ++f) red[tid >> 6][f] = x[f];
   __syncthreads();
   __shared__ double tot[12];
-  if (threadIdx.x < 12) {
+  if (tid < 12) {
     double t = 0.0;
 #pragma unroll
-    for (int q = 0; q < W; ++q) t += red[q][threadIdx.x];
-    tot[threadIdx.x] = t;
+    for (int q = 0; q < W; ++q) t += red[q][tid];
+    tot[tid] = t;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
+  if (tid != 0) return;
 #pragma unroll
   for (int f = 0; f < 12; ++f) x[f] = tot[f];
 #pragma unroll
@@ -425,11 +495,17 @@ __device__ void finalize_box(const DevNet& net, void* ws, const WsLayout& lay, i
   }
 }
 
-__global__ __launch_bounds__(kK4Threads) void k4_finalize(DevNet net, void* ws, WsLayout lay, int64_t box0,
-                                                          double* __restrict__ f_lo,
-                                                          double* __restrict__ f_hi,
-                                                          double* __restrict__ terms) {
-  finalize_box(net, ws, lay, box0 + blockIdx.x, f_lo, f_hi, terms);
+// One block of T threads per box.
+template <int T>
+__global__ __launch_bounds__(T) void k4_finalize(DevNet net, void* ws, WsLayout lay, int64_t box0,
+                                                 double* __restrict__ f_lo, double* __restrict__ f_hi,
+                                                 double* __restrict__ terms) {
+  finalize_box<T>(net, ws, lay, box0 + blockIdx.x, f_lo, f_hi, terms);
+}
+
+static void launch_k4(const DevNet& net, void* ws, const WsLayout& lay, int64_t b0, int nb, double* f_lo,
+                      double* f_hi, double* terms, hipStream_t s) {
+  hipLaunchKernelGGL(k4_finalize<256>, dim3(nb), dim3(256), 0, s, net, ws, lay, b0, f_lo, f_hi, terms);
 }
 
 // ---------------------------------------------------------------- K3
@@ -568,7 +644,8 @@ hipError_t launch_forward_single(const DevNet& net, int64_t n_box, const float* 
     }
     tm->stop(t, s);
     t = tm->start(4, s);
-    hipLaunchKernelGGL(k2e_lines, dim3(lay.n_p2, nb), dim3(64), 0, s, net, ws, lay, b0);
+    hipLaunchKernelGGL(k2e_lines, dim3((net.L + kK2eThreads - 1) / kK2eThreads, nb), dim3(kK2eThreads), 0, s,
+                       net, ws, lay, b0);
     tm->stop(t, s);
     if (net.K > 0) {
       t = tm->start(2, s);
@@ -581,7 +658,7 @@ hipError_t launch_forward_single(const DevNet& net, int64_t n_box, const float* 
       tm->stop(t, s);
     }
     t = tm->start(3, s);
-    hipLaunchKernelGGL(k4_finalize, dim3(nb), dim3(kK4Threads), 0, s, net, ws, lay, b0, f_lo, f_hi, terms);
+    launch_k4(net, ws, lay, b0, nb, f_lo, f_hi, terms, s);
     tm->stop(t, s);
   }
   return hipGetLastError();
@@ -613,7 +690,8 @@ hipError_t launch_forward_prep(const DevNet& net, int64_t n_box, const float* lo
   for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
     const int nb = (int)std::min<int64_t>(65535, n_box - b0);
     const int t = tm->start(4, s);
-    hipLaunchKernelGGL(k2e_lines, dim3(lay.n_p2, nb), dim3(64), 0, s, net, ws, lay, b0);
+    hipLaunchKernelGGL(k2e_lines, dim3((net.L + kK2eThreads - 1) / kK2eThreads, nb), dim3(kK2eThreads), 0, s,
+                       net, ws, lay, b0);
     tm->stop(t, s);
   }
   return hipGetLastError();
@@ -633,14 +711,15 @@ hipError_t launch_forward(const DevNet& net, int64_t n_box, const float* lo, con
   for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
     const int nb = (int)std::min<int64_t>(65535, n_box - b0);
     const int t = tm->start(4, s);
-    hipLaunchKernelGGL(k2e_lines, dim3(lay.n_p2, nb), dim3(64), 0, s, net, ws, lay, b0);
+    hipLaunchKernelGGL(k2e_lines, dim3((net.L + kK2eThreads - 1) / kK2eThreads, nb), dim3(kK2eThreads), 0, s,
+                       net, ws, lay, b0);
     tm->stop(t, s);
   }
   launch_batched_sweeps(net, n_box, ws, lay, s, tm, 1);
   for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
     const int nb = (int)std::min<int64_t>(65535, n_box - b0);
     const int t = tm->start(3, s);
-    hipLaunchKernelGGL(k4_finalize, dim3(nb), dim3(kK4Threads), 0, s, net, ws, lay, b0, f_lo, f_hi, terms);
+    launch_k4(net, ws, lay, b0, nb, f_lo, f_hi, terms, s);
     tm->stop(t, s);
   }
   return hipGetLastError();
