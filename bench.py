@@ -140,6 +140,7 @@ def cpu_baseline(net, lo, hi):
 
 
 VALU_PEAK = 78.6e12  # float32 VALU lane-ops/s: 256 CUs x 128 lanes/clock x 2.4 GHz (FMA = one op)
+MFMA_F64_PEAK = 78.6e12  # float64 dense matrix FLOP/s of MI355X
 OPS_PER_EVAL = 9.25  # VALU ops per box-outage-line evaluation in the outage sweep (from the ISA)
 
 
@@ -210,6 +211,14 @@ def extras(torch, ibp, synth, n4, net4):
                      "frac": ev * OPS_PER_EVAL / (sweep_ms * 1e-3) / VALU_PEAK,
                      "ops_per_eval": OPS_PER_EVAL},
     }
+    # the base flows of the same call on the float64 matrix cores: 2 products
+    # (centre, radius) x 2 flops x lines x buses x boxes
+    bf_ms = kt.get("batched_base_flows", (float("nan"), 1))[0]
+    bf_flops = 4.0 * n3.n_line * n3.n_bus * lo.shape[0]
+    res["batched"]["roofline_base_flows"] = {
+        "bound": "mfma", "kernel": "batched_base_flows", "achieved": bf_flops / (bf_ms * 1e-3),
+        "peak": MFMA_F64_PEAK, "unit": "FLOP/s", "frac": bf_flops / (bf_ms * 1e-3) / MFMA_F64_PEAK,
+        "flops": bf_flops}
     # batched on the large network: 256 sub-boxes
     blo, bhi = synth.sub_boxes(net4, 256, seed=41)
     t4l, t4h = torch.from_numpy(blo).cuda(), torch.from_numpy(bhi).cuda()

@@ -231,6 +231,7 @@ ibp_status to_device(ibp_network* net, int device) {
     int v = 0;
     if (const char* p = std::strstr(e, "k2nc=")) t.k2_nc = (v = std::atoi(p + 5)) ? v : t.k2_nc;
     if (const char* p = std::strstr(e, "k3kc=")) t.k3_kc = (v = std::atoi(p + 5)) ? v : t.k3_kc;
+    if (const char* p = std::strstr(e, "k2b=")) t.k2b_mfma = std::atoi(p + 4) != 0;
     if (ibp::tune_valid(t)) net->tune = t;
   }
   return IBP_OK;
@@ -296,7 +297,7 @@ ibp::WsLayout layout_for(const ibp_network* net, int64_t n_box, const ibp::Tune&
   const ibp::DevNet& d = net->dn;
   ibp::WsLayout lay;
   if (batched)
-    ibp::plan_batched(d, n_box, lay);
+    ibp::plan_batched(d, n_box, lay, tune);
   else
     ibp::plan_single(d, n_box, lay, tune);
   const size_t B = (size_t)std::max<int64_t>(1, n_box);
@@ -513,7 +514,7 @@ ibp_status ibp_kernel_times(ibp_network* net, int32_t n_ids, double* total_ms, i
 
 ibp_status ibp_set_tile(ibp_network* net, int32_t k2_nc, int32_t k3_kc) {
   if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
-  ibp::Tune t;
+  ibp::Tune t = net->tune;
   t.k2_nc = k2_nc;
   t.k3_kc = k3_kc;
   if (!ibp::tune_valid(t)) return fail(IBP_E_INVALID_ARG, "unsupported tile parameters");
@@ -548,7 +549,7 @@ ibp_status ibp_autotune(ibp_network* net, int64_t n_box, const float* box_lo, co
   ibp_status st = IBP_OK;
   for (int nc : ncs) {
     for (int kc : kcs) {
-      ibp::Tune t;
+      ibp::Tune t = net->tune;
       t.k2_nc = nc;
       t.k3_kc = kc;
       const ibp::WsLayout lay = layout_for(net, n_box, t, false);

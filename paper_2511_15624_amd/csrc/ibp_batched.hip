@@ -96,6 +96,80 @@ __global__ __launch_bounds__(256) void k2b_base_flows(DevNet net, void* ws, WsLa
   }
 }
 
+// Base flows on the float64 matrix cores (v_mfma_f64_16x16x4f64): the two
+// products C_c = Phi C and C_r = |Phi| R over 32 boxes at once are dense
+// GEMMs (lines x buses times buses x boxes).  One wave owns 64 lines x 32
+// boxes: per step of four buses each lane loads one float4 of the transposed
+// PTDF (four consecutive lines of one bus) and the (c, r) pairs of two boxes
+// at that bus, and issues 16 MFMAs (four line fragments x two box fragments x
+// centre and radius).  Line fragment m holds the lines l0 + 4 i + m
+// (i = 0..15), so the float4's components are the lane's A operands of the
+// four fragments.  The four waves of a block take the four 64-line tiles of
+// the same 32 boxes, so a box's injections are read once per block from L2.
+// Operand layout (lane t): A[i][k] = lane i + 16 k, B[k][j] = lane j + 16 k,
+// D[i][j] = lane j + 16 (i % 4), element i / 4.  Products of a float32 factor
+// and a float64 injection are accumulated in float64 (any order is covered by
+// the same accumulation bound as the vector kernels).
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256, 2) void k2b_base_flows_mfma(DevNet net, void* ws, WsLayout lay, int64_t n_box,
+                                                              const double2* __restrict__ inj_all) {
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int l0 = (blockIdx.x * 4 + w) * 64;
+  if (l0 >= net.Lp) return;  // whole wave beyond the padded lines; no barrier follows
+  const int64_t b0 = (int64_t)blockIdx.y * 32;
+  const int i16 = lane & 15, k4 = lane >> 4;
+  const int Lp4 = net.Lp / 4;
+  const float4* pa = reinterpret_cast<const float4*>(net.phiT + l0 + 4 * i16);
+  const double2* pb0 = inj_all + min(b0 + i16, n_box - 1) * net.Np + k4;
+  const double2* pb1 = inj_all + min(b0 + 16 + i16, n_box - 1) * net.Np + k4;
+  v4d ac[4][2], ar[4][2];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) ac[m][j] = ar[m][j] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int N = net.N;
+  // rows past the last bus are clamped to it; their injections are zero.  The
+  // next step's operands are loaded before this step's MFMAs (the scheduling
+  // barrier keeps the compiler from sinking the loads to their use; the last
+  // step reloads its own operands).
+  const int n_last = (N - 1) & ~3;
+  float4 xn = pa[(size_t)min(k4, N - 1) * Lp4];
+  double2 c0n = pb0[0], c1n = pb1[0];
+  for (int n = 0; n < N; n += 4) {
+    const float4 x = xn;
+    const double2 c0 = c0n, c1 = c1n;
+    const int nn = min(n + 4, n_last);
+    xn = pa[(size_t)min(nn + k4, N - 1) * Lp4];
+    c0n = pb0[nn];
+    c1n = pb1[nn];
+    __builtin_amdgcn_sched_barrier(0);
+    const double a[4] = {(double)x.x, (double)x.y, (double)x.z, (double)x.w};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      ac[m][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], c0.x, ac[m][0], 0, 0, 0);
+      ac[m][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], c1.x, ac[m][1], 0, 0, 0);
+      ar[m][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fabs(a[m]), c0.y, ar[m][0], 0, 0, 0);
+      ar[m][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fabs(a[m]), c1.y, ar[m][1], 0, 0, 0);
+    }
+  }
+  // element r of lane t is row i = 4 r + t / 16 of each fragment: for box
+  // b0 + 16 j + (t % 16), fragment m gives line l0 + 4 i + m, so the lane
+  // holds four runs of four consecutive lines, l0 + 16 r + 4 (t / 16) + m
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int64_t b = b0 + 16 * j + i16;
+    if (b < n_box) {
+      double2* out = ws_ptr<double2>(ws, lay.part2) + (size_t)b * net.Lp + l0 + 4 * k4;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) out[16 * r + m] = make_double2(ac[m][j][r], ar[m][j][r]);
+    }
+  }
+}
+
 // Outage sweep for kBT boxes x 256 lines per wave over one block row of outages.
 __global__ __launch_bounds__(256) void k3b_contingency(DevNet net, void* ws, WsLayout lay, int64_t n_box) {
   const int lane = threadIdx.x & 63;
@@ -168,7 +242,7 @@ __global__ __launch_bounds__(256) void k3b_contingency(DevNet net, void* ws, WsL
   }
 }
 
-void plan_batched(const DevNet& net, int64_t n_box, WsLayout& lay) {
+void plan_batched(const DevNet& net, int64_t n_box, WsLayout& lay, const Tune& t) {
   const int lp4 = net.Lp / 4;
   lay.batched = 1;
   lay.n_p1 = (std::max(net.Np, net.X) + 63) / 64;
@@ -196,6 +270,7 @@ void plan_batched(const DevNet& net, int64_t n_box, WsLayout& lay) {
   lay.n_p3 = net.K > 0 ? lay.k3_bx * rows : 0;
   lay.k2_nc = 0;
   lay.k3_kc = lay.k3_kper;
+  lay.k2_mfma = t.k2b_mfma;
 }
 
 hipError_t launch_batched_sweeps(const DevNet& net, int64_t n_box, void* ws, const WsLayout& lay, hipStream_t s,
@@ -204,8 +279,12 @@ hipError_t launch_batched_sweeps(const DevNet& net, int64_t n_box, void* ws, con
   const unsigned groups = (unsigned)((nbt + 3) / 4);
   if (phase == 0) {
     const int t = tm->start(5, s);
-    hipLaunchKernelGGL(k2b_base_flows, dim3(lay.k2_gx, groups), dim3(256), 0, s, net, ws, lay, n_box,
-                       reinterpret_cast<const double2*>(static_cast<char*>(ws) + lay.inj));
+    const double2* inj = reinterpret_cast<const double2*>(static_cast<char*>(ws) + lay.inj);
+    if (lay.k2_mfma)
+      hipLaunchKernelGGL(k2b_base_flows_mfma, dim3((net.Lp / 64 + 3) / 4, (unsigned)((n_box + 31) / 32)), dim3(256),
+                         0, s, net, ws, lay, n_box, inj);
+    else
+      hipLaunchKernelGGL(k2b_base_flows, dim3(lay.k2_gx, groups), dim3(256), 0, s, net, ws, lay, n_box, inj);
     tm->stop(t, s);
   } else if (net.K > 0) {
     const int t = tm->start(6, s);

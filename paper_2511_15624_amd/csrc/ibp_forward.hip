@@ -216,10 +216,11 @@ constexpr int kK2eBy = 16;  // base-flow partials per line loaded in one round
 
 // One line per lane, kK2eThreads lines per block: combine the K2 partials of
 // every bus chunk and run the line epilogue; one base-penalty partial per wave
-// (64 lines) and one max-reduction atomic per block.  Every load that does not depend on another is issued before the
-// first use, so the kernel waits on memory about twice instead of once per
-// dependent step; indices are clamped rather than branched on so the loads
-// stay in one group.
+// (64 lines) and one max-reduction atomic per block.  Every load that does
+// not depend on another is issued before the first use (the line index is
+// clamped; partials that do not exist are skipped by wave-uniform or lane
+// masks, not loaded twice), so the kernel waits on memory about twice
+// instead of once per dependent step.
 __global__ __launch_bounds__(kK2eThreads) void k2e_lines(DevNet net, void* ws, WsLayout lay, int64_t box0) {
   const int64_t b = box0 + blockIdx.y;
   const int lane = threadIdx.x & 63;
@@ -238,19 +239,22 @@ __global__ __launch_bounds__(kK2eThreads) void k2e_lines(DevNet net, void* ws, W
     double xm[4], xb[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int j = min(lane + 64 * u, lay.n_p1 - 1);
-      xm[u] = p1[j * kP1Fields + kP1Mc];
-      xb[u] = p1[j * kP1Fields + kP1Mbox];
+      const int j = lane + 64 * u;
+      xm[u] = xb[u] = 0.0;
+      if (j < lay.n_p1) {
+        xm[u] = p1[j * kP1Fields + kP1Mc];
+        xb[u] = p1[j * kP1Fields + kP1Mbox];
+      }
     }
 #pragma unroll
-    for (int y = 0; y < kK2eBy; ++y) t[y] = part[(size_t)min(y, nby - 1) * net.Lp];
+    for (int y = 0; y < kK2eBy; ++y)
+      if (y < nby) t[y] = part[(size_t)y * net.Lp];
     q = load_line_const(net, lq);
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (lane + 64 * u < lay.n_p1) {
-        mc += xm[u];
-        mb += xb[u];
-      }
+    for (int u = 0; u < 4; ++u) {
+      mc += xm[u];
+      mb += xb[u];
+    }
   }
   for (int j = lane + 256; j < lay.n_p1; j += 64) {
     mc += p1[j * kP1Fields + kP1Mc];

@@ -35,10 +35,11 @@ struct KernelTimer {
 };
 
 // Tile parameters of the streaming kernels (chosen by the autotuner or the
-// IBP_TILE environment variable, e.g. "k2nc=64,k3kc=32").
+// IBP_TILE environment variable, e.g. "k2nc=64,k3kc=32,k2b=0").
 struct Tune {
   int k2_nc = 128;  // buses per wave in the base-flow sweep: 32, 64, 128 or 256
   int k3_kc = 16;   // outages per block in the outage sweep: 16, 32, 64 or 128
+  int k2b_mfma = 1; // box-tiled base flows on the float64 matrix cores (0: vector FMA)
 };
 bool tune_valid(const Tune& t);
 
@@ -46,7 +47,7 @@ bool tune_valid(const Tune& t);
 void plan_single(const DevNet& net, int64_t n_box, WsLayout& lay, const Tune& t);
 
 // Box-tiled plan (n_box >= kBatchMin and no IBP_F_PLAIN).
-void plan_batched(const DevNet& net, int64_t n_box, WsLayout& lay);
+void plan_batched(const DevNet& net, int64_t n_box, WsLayout& lay, const Tune& t);
 constexpr int64_t kBatchMin = 4;
 
 // Batched base-flow sweep (phase 0) or outage sweep (phase 1).
