@@ -31,6 +31,7 @@
 #include "ibp_device.h"
 #include "ibp_devfun.h"
 #include "ibp_kernels.h"
+#include "ibp_lanes.h"
 
 namespace ibp {
 
@@ -42,25 +43,15 @@ constexpr int kK5Sub = 16;     // outages per butterfly reduction
 __device__ __forceinline__ float butterfly32(float (&v)[32]) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const bool up = lane & 32;
-    const float send = up ? v[i] : v[i + 16];
-    const float keep = up ? v[i + 16] : v[i];
-    v[i] = keep + __shfl_xor(send, 32, 64);
-  }
+  for (int i = 0; i < 16; ++i) v[i] = halve32(v[i], v[i + 16]);
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const bool up = lane & 16;
-    const float send = up ? v[i] : v[i + 8];
-    const float keep = up ? v[i + 8] : v[i];
-    v[i] = keep + __shfl_xor(send, 16, 64);
-  }
+  for (int i = 0; i < 8; ++i) v[i] = halve16(v[i], v[i + 8]);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const bool up = lane & 8;
     const float send = up ? v[i] : v[i + 4];
     const float keep = up ? v[i + 4] : v[i];
-    v[i] = keep + __shfl_xor(send, 8, 64);
+    v[i] = keep + lane_xor<kDppXor8>(send);
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
@@ -73,9 +64,9 @@ __device__ __forceinline__ float butterfly32(float (&v)[32]) {
     const bool up = lane & 2;
     const float send = up ? v[0] : v[1];
     const float keep = up ? v[1] : v[0];
-    v[0] = keep + __shfl_xor(send, 2, 64);
+    v[0] = keep + lane_xor<kDppXor2>(send);
   }
-  return v[0] + __shfl_xor(v[0], 1, 64);
+  return v[0] + lane_xor<kDppXor1>(v[0]);
 }
 
 // One element of the outage sweep's VJP.  rlm = r_l - fmax_l and

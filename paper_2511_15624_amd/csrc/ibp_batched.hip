@@ -205,14 +205,46 @@ __global__ __launch_bounds__(256) void k3b_contingency(DevNet net, void* ws, WsL
     }
     const float4* lam = reinterpret_cast<const float4*>(net.lodf) + col;
     int k = k0;
-    for (; k + 4 <= k1; k += 4) {
-      float4 x[4];
+    const int n4 = (k1 - k0) / 4;
+    if (n4 > 0) {
+      // per-outage (centre, padded radius) of the next four outages are
+      // loaded (scalar loads) before this step's arithmetic, so the step
+      // waits on scalar memory once instead of once per box (the last step
+      // reloads its own outages)
+      const int k_last = k0 + 4 * (n4 - 1);
+      int2 qn[kBT][4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) x[u] = lam[(size_t)(k + u) * Lp4];
+      for (int i = 0; i < kBT; ++i)
 #pragma unroll
-      for (int i = 0; i < kBT; ++i) {
-        k3_pair(x[0], cd[i][k], x[1], cd[i][k + 1], c4[i], h4[i], g4[i], acc_hi[i], acc_lo[i]);
-        k3_pair(x[2], cd[i][k + 2], x[3], cd[i][k + 3], c4[i], h4[i], g4[i], acc_hi[i], acc_lo[i]);
+        for (int u = 0; u < 4; ++u) {
+          const int4 d = cd[i][k0 + u];
+          qn[i][u] = make_int2(d.y, d.z);
+        }
+      for (; k <= k_last; k += 4) {
+        int2 q[kBT][4];
+#pragma unroll
+        for (int i = 0; i < kBT; ++i)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) q[i][u] = qn[i][u];
+        const int kn = min(k + 4, k_last);
+        float4 x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = lam[(size_t)(k + u) * Lp4];
+#pragma unroll
+        for (int i = 0; i < kBT; ++i)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int4 d = cd[i][kn + u];
+            qn[i][u] = make_int2(d.y, d.z);
+          }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < kBT; ++i) {
+          k3_pair(x[0], make_int4(0, q[i][0].x, q[i][0].y, 0), x[1], make_int4(0, q[i][1].x, q[i][1].y, 0), c4[i],
+                  h4[i], g4[i], acc_hi[i], acc_lo[i]);
+          k3_pair(x[2], make_int4(0, q[i][2].x, q[i][2].y, 0), x[3], make_int4(0, q[i][3].x, q[i][3].y, 0), c4[i],
+                  h4[i], g4[i], acc_hi[i], acc_lo[i]);
+        }
       }
     }
     for (; k < k1; ++k) {

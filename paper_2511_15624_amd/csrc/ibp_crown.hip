@@ -51,6 +51,7 @@
 
 #include "ibp_devfun.h"
 #include "ibp_kernels.h"
+#include "ibp_lanes.h"
 
 namespace ibp {
 
@@ -85,37 +86,25 @@ __device__ __forceinline__ float crown_slope_ref(float lam, float cc, float cl, 
 // g = lane / 8 holds the totals of v[3g], v[3g + 1], v[3g + 2] in v[0..2].
 __device__ __forceinline__ void halving_sum24(double (&v)[24]) {
   const int lane = threadIdx.x & 63;
-  {
-    const bool up = lane & 32;
 #pragma unroll
-    for (int i = 0; i < 12; ++i) {
-      const double send = up ? v[i] : v[i + 12];
-      const double keep = up ? v[i + 12] : v[i];
-      v[i] = keep + __shfl_xor(send, 32, 64);
-    }
-  }
-  {
-    const bool up = lane & 16;
+  for (int i = 0; i < 12; ++i) v[i] = halve32(v[i], v[i + 12]);
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      const double send = up ? v[i] : v[i + 6];
-      const double keep = up ? v[i + 6] : v[i];
-      v[i] = keep + __shfl_xor(send, 16, 64);
-    }
-  }
+  for (int i = 0; i < 6; ++i) v[i] = halve16(v[i], v[i + 6]);
   {
     const bool up = lane & 8;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const double send = up ? v[i] : v[i + 3];
       const double keep = up ? v[i + 3] : v[i];
-      v[i] = keep + __shfl_xor(send, 8, 64);
+      v[i] = keep + lane_xor<kDppXor8>(send);
     }
   }
 #pragma unroll
-  for (int m = 4; m >= 1; m >>= 1)
+  for (int i = 0; i < 3; ++i) v[i] += __shfl_xor(v[i], 4, 64);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) v[i] += __shfl_xor(v[i], m, 64);
+  for (int i = 0; i < 3; ++i) v[i] += lane_xor<kDppXor2>(v[i]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) v[i] += lane_xor<kDppXor1>(v[i]);
 }
 
 // Slopes of four lines x one outage; per-line counts in registers, the
