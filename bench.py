@@ -369,6 +369,9 @@ def main(argv=None):
                     help="skip the batched / backward / splitting measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
+    ap.add_argument("--batched-only", type=int, default=0, metavar="CALLS",
+                    help="only run the batched call (2000 buses, 18 x 1024 sub-boxes) CALLS times after one "
+                         "warm-up call; for profiler runs")
     ap.add_argument("--traffic-record", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write the HBM traffic record from four rocprofv3 --pmc output folders (no GPU)")
     args = ap.parse_args(argv)
@@ -396,6 +399,17 @@ def main(argv=None):
         print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30, "copies": 5}), flush=True)
         return 0
     from paper_2511_15624_amd import ibp, synth
+    if args.batched_only:
+        net3 = synth.make_config("c2000")
+        n3 = ibp.Network(net3, device=0)
+        lo3, hi3, _ = synth.period_boxes(net3, 18, 1024, seed=31)
+        tlo3, thi3 = torch.from_numpy(lo3).cuda(), torch.from_numpy(hi3).cuda()
+        ws3 = ibp.Workspace(n3)
+        ibp.ibp_bound_boxes(n3, tlo3, thi3, ws=ws3)
+        ms3 = _time(torch, lambda: ibp.ibp_bound_boxes(n3, tlo3, thi3, ws=ws3), args.batched_only)
+        print(json.dumps({"workload": "2000 buses, 18 x 1024 sub-boxes", "calls": args.batched_only,
+                          "ms_per_call": ms3}), flush=True)
+        return 0
 
     name = "c8316"
     net = synth.make_config(name)
