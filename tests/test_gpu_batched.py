@@ -70,3 +70,24 @@ def test_batched_c8316_sixteen_boxes():
     _close(b_hi, p_hi)
     for b in (0, 15):
         assert_encloses(b_lo[b], b_hi[b], orc(net, blo[b], bhi[b], fac), what=f"box {b}")
+
+
+def test_vector_and_matrix_core_base_flows_agree(monkeypatch):
+    """The box-tiled base flows run on the float64 matrix cores by default;
+    IBP_TILE=k2b=0 at network build selects the vector-FMA kernel.  Both sum
+    the same float64 products in different orders, so the bounds agree to
+    summation order and both enclose the oracle.  45 boxes: ragged against the
+    32-box MFMA tile and the 16-box vector group."""
+    net, fac, n = setup("c500")
+    monkeypatch.setenv("IBP_TILE", "k2b=0")
+    nv = ibp.Network(net, device=0)
+    monkeypatch.delenv("IBP_TILE")
+    blo, bhi = synth.sub_boxes(net, 45, seed=77)
+    m_lo, m_hi = gpu_bounds(n, blo, bhi)
+    v_lo, v_hi = gpu_bounds(nv, blo, bhi)
+    _close(m_lo, v_lo)
+    _close(m_hi, v_hi)
+    for b in (0, 31, 32, 44):
+        r = orc(net, blo[b], bhi[b], fac)
+        assert_encloses(m_lo[b], m_hi[b], r, what=f"matrix cores, box {b}")
+        assert_encloses(v_lo[b], v_hi[b], r, what=f"vector FMA, box {b}")
