@@ -121,6 +121,11 @@ __global__ __launch_bounds__(256, 2) void k2b_base_flows_mfma(DevNet net, void* 
   const int64_t b0 = (int64_t)blockIdx.y * 32;
   const int i16 = lane & 15, k4 = lane >> 4;
   const int Lp4 = net.Lp / 4;
+  // bus chunk blockIdx.z of k2_by (chunk starts are multiples of four, so no
+  // step reaches into the next chunk; the last chunk ends at N)
+  const int nb0 = blockIdx.z * lay.k2_chunk;
+  const int nb1 = min(net.N, nb0 + lay.k2_chunk);
+  if (nb0 >= nb1) return;
   const float4* pa = reinterpret_cast<const float4*>(net.phiT + l0 + 4 * i16);
   const double2* pb0 = inj_all + min(b0 + i16, n_box - 1) * net.Np + k4;
   const double2* pb1 = inj_all + min(b0 + 16 + i16, n_box - 1) * net.Np + k4;
@@ -134,10 +139,10 @@ __global__ __launch_bounds__(256, 2) void k2b_base_flows_mfma(DevNet net, void* 
   // next step's operands are loaded before this step's MFMAs (the scheduling
   // barrier keeps the compiler from sinking the loads to their use; the last
   // step reloads its own operands).
-  const int n_last = (N - 1) & ~3;
-  float4 xn = pa[(size_t)min(k4, N - 1) * Lp4];
-  double2 c0n = pb0[0], c1n = pb1[0];
-  for (int n = 0; n < N; n += 4) {
+  const int n_last = nb0 + ((nb1 - nb0 - 1) & ~3);
+  float4 xn = pa[(size_t)min(nb0 + k4, N - 1) * Lp4];
+  double2 c0n = pb0[nb0], c1n = pb1[nb0];
+  for (int n = nb0; n < nb1; n += 4) {
     const float4 x = xn;
     const double2 c0 = c0n, c1 = c1n;
     const int nn = min(n + 4, n_last);
@@ -161,7 +166,7 @@ __global__ __launch_bounds__(256, 2) void k2b_base_flows_mfma(DevNet net, void* 
   for (int j = 0; j < 2; ++j) {
     const int64_t b = b0 + 16 * j + i16;
     if (b < n_box) {
-      double2* out = ws_ptr<double2>(ws, lay.part2) + (size_t)b * net.Lp + l0 + 4 * k4;
+      double2* out = ws_ptr<double2>(ws, lay.part2) + ((size_t)b * lay.k2_by + blockIdx.z) * net.Lp + l0 + 4 * k4;
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -281,6 +286,16 @@ void plan_batched(const DevNet& net, int64_t n_box, WsLayout& lay, const Tune& t
   lay.k2_bx = (lp4 + 63) / 64;
   lay.k2_gx = (lay.k2_bx + 7) / 8 * 8;  // blocks of one line tile share an XCD
   lay.k2_by = 1;
+  lay.k2_chunk = net.N;
+  if (t.k2b_mfma) {
+    // split the buses when the line x box tiles alone give few blocks; each
+    // chunk writes its own partial sums, which the line epilogue adds
+    const int64_t blocks = (int64_t)((net.Lp / 64 + 3) / 4) * ((n_box + 31) / 32);
+    int by = (int)std::min<int64_t>(8, (2048 + blocks - 1) / blocks);
+    by = std::max(1, std::min(by, net.N / 256));
+    lay.k2_chunk = ((net.N + by - 1) / by + 3) & ~3;
+    lay.k2_by = (net.N + lay.k2_chunk - 1) / lay.k2_chunk;
+  }
   lay.n_p2 = (net.L + 63) / 64;
   const int64_t nbt = (n_box + kBT - 1) / kBT;
   const int64_t groups = (nbt + 3) / 4;
@@ -313,7 +328,8 @@ hipError_t launch_batched_sweeps(const DevNet& net, int64_t n_box, void* ws, con
     const int t = tm->start(5, s);
     const double2* inj = reinterpret_cast<const double2*>(static_cast<char*>(ws) + lay.inj);
     if (lay.k2_mfma)
-      hipLaunchKernelGGL(k2b_base_flows_mfma, dim3((net.Lp / 64 + 3) / 4, (unsigned)((n_box + 31) / 32)), dim3(256),
+      hipLaunchKernelGGL(k2b_base_flows_mfma,
+                         dim3((net.Lp / 64 + 3) / 4, (unsigned)((n_box + 31) / 32), (unsigned)lay.k2_by), dim3(256),
                          0, s, net, ws, lay, n_box, inj);
     else
       hipLaunchKernelGGL(k2b_base_flows, dim3(lay.k2_gx, groups), dim3(256), 0, s, net, ws, lay, n_box, inj);

@@ -85,6 +85,7 @@ struct WsLayout {
   int batched = 0;                 // 1: box-tiled kernels (boxes share every streamed tile)
   int k2_gx = 0;                   // batched base flows: grid x (line tiles padded to a multiple of 8)
   int k2_mfma = 0;                 // batched base flows on the float64 matrix cores
+  int k2_chunk = 0;                // batched base flows: buses per chunk (k2_by chunks, a multiple of 4)
   int k3_kper = 0;                 // batched outage sweep: outages per block row
   int k5_by = 0, k5_tiles = 0;     // backward outage sweep: outage chunks, line tiles
   // linear-relaxation bound (present with the CROWN flag)
