@@ -270,7 +270,7 @@ ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
   if (flags & (IBP_F_CROWN | IBP_F_CROWN_REF)) {
     const ibp::DevNet& d = net->dn;
     const size_t B = (size_t)std::max<int64_t>(1, n_box);
-    ibp::plan_crown(d, lay);
+    ibp::plan_crown(d, n_box, lay, net->tune);
     size_t off = lay.total;
     auto take = [&](size_t bytes) {
       const size_t o = off;

@@ -624,12 +624,95 @@ __global__ __launch_bounds__(256) void kc3b_ptdf_t(DevNet net, void* ws, WsLayou
   }
 }
 
-void plan_crown(const DevNet& net, WsLayout& lay) {
+// The same three products on the float64 matrix cores (v_mfma_f64_16x16x4f64)
+// for the box-tiled path: D[bus][box] = sum over lines of A[bus][line] B[line][box]
+// with A = Phi32^T (or |Phi32|^T) and B = v (or va, ev).  A wave owns 32
+// buses x 32 boxes over one chunk of lines; per group of 16 lines each lane
+// loads one float4 of the transposed PTDF per bus fragment (four lines of
+// one bus: the A operands of four k-steps, line l0 + 4 k + s in step s) and
+// one (v, va, ev) record per step and box fragment, and issues 48 MFMAs.  The
+// four waves of a block take four 32-bus ranges of the same boxes.  Chunk z
+// writes partial z of bpart (lay.kc3_bx chunks), summed by kc4_inputs.
+// Operand layout as in the base-flow MFMA kernel: A[i][k] at lane i + 16 k,
+// B[k][j] at lane j + 16 k, D[i][j] at lane j + 16 (i % 4), element i / 4.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256, 2) void kc3m_ptdf_t(DevNet net, void* ws, WsLayout lay, int64_t n_box) {
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int n0 = (blockIdx.x * 4 + w) * 32;
+  if (n0 >= net.N) return;  // whole wave past the last bus; no barrier follows
+  const int64_t b0 = (int64_t)blockIdx.y * 32;
+  const int i16 = lane & 15, k4 = lane >> 4;
+  const int l_begin = blockIdx.z * lay.kc3_chunk;
+  const int l_end = min(net.Lp, l_begin + lay.kc3_chunk);
+  const float4* pa0 = reinterpret_cast<const float4*>(net.phiT + (size_t)min(n0 + i16, net.N - 1) * net.Lp + 4 * k4);
+  const float4* pa1 =
+      reinterpret_cast<const float4*>(net.phiT + (size_t)min(n0 + 16 + i16, net.N - 1) * net.Lp + 4 * k4);
+  const double4* lv = ws_ptr<double4>(ws, lay.lv);
+  const double4* pb0 = lv + min(b0 + i16, n_box - 1) * net.Lp + 4 * k4;
+  const double4* pb1 = lv + min(b0 + 16 + i16, n_box - 1) * net.Lp + 4 * k4;
+  v4d y[2][2], ya[2][2], ye[2][2];
+#pragma unroll
+  for (int fi = 0; fi < 2; ++fi)
+#pragma unroll
+    for (int fj = 0; fj < 2; ++fj) y[fi][fj] = ya[fi][fj] = ye[fi][fj] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int l0 = l_begin; l0 < l_end; l0 += 16) {
+    const float4 x0 = pa0[l0 / 4], x1 = pa1[l0 / 4];
+    const float a0[4] = {x0.x, x0.y, x0.z, x0.w}, a1[4] = {x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const double4 q0 = pb0[l0 + st], q1 = pb1[l0 + st];
+      const double p0 = a0[st], p1 = a1[st];
+      y[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(p0, q0.x, y[0][0], 0, 0, 0);
+      y[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(p0, q1.x, y[0][1], 0, 0, 0);
+      y[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(p1, q0.x, y[1][0], 0, 0, 0);
+      y[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(p1, q1.x, y[1][1], 0, 0, 0);
+      ya[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fabs(p0), q0.y, ya[0][0], 0, 0, 0);
+      ya[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fabs(p0), q1.y, ya[0][1], 0, 0, 0);
+      ya[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fabs(p1), q0.y, ya[1][0], 0, 0, 0);
+      ya[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fabs(p1), q1.y, ya[1][1], 0, 0, 0);
+      ye[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fabs(p0), q0.z, ye[0][0], 0, 0, 0);
+      ye[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fabs(p0), q1.z, ye[0][1], 0, 0, 0);
+      ye[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fabs(p1), q0.z, ye[1][0], 0, 0, 0);
+      ye[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fabs(p1), q1.z, ye[1][1], 0, 0, 0);
+    }
+  }
+  // element r of lane t: bus n0 + 16 fi + 4 r + t / 16, box b0 + 16 fj + t % 16
+  double4* out = ws_ptr<double4>(ws, lay.bpart);
+#pragma unroll
+  for (int fj = 0; fj < 2; ++fj) {
+    const int64_t b = b0 + 16 * fj + i16;
+    if (b >= n_box) continue;
+#pragma unroll
+    for (int fi = 0; fi < 2; ++fi)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int n = n0 + 16 * fi + 4 * r + k4;
+        if (n < net.N)
+          out[((size_t)b * lay.kc3_bx + blockIdx.z) * net.Np + n] =
+              make_double4(y[fi][fj][r], ya[fi][fj][r], ye[fi][fj][r], 0.0);
+      }
+  }
+}
+
+void plan_crown(const DevNet& net, int64_t n_box, WsLayout& lay, const Tune& t) {
   const int lp4 = net.Lp / 4;
   lay.kc_bx = (lp4 + 255) / 256;
   lay.kc_by = std::max(1, (net.K + kKC - 1) / kKC);
   lay.kc3_bx = (lp4 + 255) / 256;
   lay.kc3_by = (net.N + kNB - 1) / kNB;
+  lay.kc3_mfma = 0;
+  lay.kc3_chunk = net.Lp;
+  if (t.k2b_mfma && n_box >= kCB) {
+    // line chunks (multiples of 16) so that bus x box tiles x chunks fill the chip
+    const int64_t blocks = (int64_t)((net.N + 127) / 128) * ((n_box + 31) / 32);
+    int sc = (int)std::min<int64_t>(8, (2048 + blocks - 1) / blocks);
+    sc = std::max(1, std::min(sc, net.Lp / 256));
+    lay.kc3_mfma = 1;
+    lay.kc3_chunk = ((net.Lp + sc - 1) / sc + 15) & ~15;
+    lay.kc3_bx = (net.Lp + lay.kc3_chunk - 1) / lay.kc3_chunk;
+  }
   lay.n_cp = (net.X + 255) / 256;
   lay.n_ct = (net.L + 255) / 256;
 }
@@ -685,7 +768,11 @@ static void relax_pass(const DevNet& net, int64_t n_box, const float* lo, const 
   }
   if (n_box >= kCB) {
     const int t = tm->start(11, s);
-    hipLaunchKernelGGL(kc3b_ptdf_t, dim3(tiles, lay.kc3_bx, lay.kc3_by), dim3(256), 0, s, net, ws, lay, n_box);
+    if (lay.kc3_mfma)
+      hipLaunchKernelGGL(kc3m_ptdf_t, dim3((net.N + 127) / 128, (unsigned)((n_box + 31) / 32), lay.kc3_bx),
+                         dim3(256), 0, s, net, ws, lay, n_box);
+    else
+      hipLaunchKernelGGL(kc3b_ptdf_t, dim3(tiles, lay.kc3_bx, lay.kc3_by), dim3(256), 0, s, net, ws, lay, n_box);
     tm->stop(t, s);
   }
   for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {

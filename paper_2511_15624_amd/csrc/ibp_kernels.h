@@ -72,7 +72,7 @@ hipError_t launch_backward_sweeps(const DevNet& net, int64_t n_box, void* ws, co
                                   KernelTimer* tm);
 
 // Linear-relaxation upper bound after a forward pass (see ibp_crown.hip).
-void plan_crown(const DevNet& net, WsLayout& lay);
+void plan_crown(const DevNet& net, int64_t n_box, WsLayout& lay, const Tune& t);
 hipError_t launch_crown(const DevNet& net, int64_t n_box, const float* lo, const float* hi, int ref_iters,
                         double* f_hi, double* crown, float* vertex, void* ws, const WsLayout& lay, hipStream_t s,
                         KernelTimer* tm);

@@ -190,3 +190,26 @@ def test_reference_point_relaxations_c500_and_c8316():
     if r["near"] == 0:
         scale = max(abs(r["f_hi"]), term_scale(orc(net, lo, hi, fac), "hi"), 1.0)
         assert c1[0] >= r["f_hi"] and (c1[0] - r["f_hi"]) / scale <= 1e-5
+
+
+def test_vector_and_matrix_core_relaxation_agree(monkeypatch):
+    """From four boxes on, the relaxation's transposed PTDF products run on the
+    float64 matrix cores; IBP_TILE=k2b=0 at network build keeps them (and the
+    base flows) on the vector ALUs.  Both bound the same quantity with the same
+    error terms, summed in different orders; both stay above the oracle's
+    relaxation where no slope decision is near its switch.  37 boxes: ragged
+    against the 32-box MFMA tile."""
+    torch = _torch()
+    net, fac, n = setup("c500")
+    monkeypatch.setenv("IBP_TILE", "k2b=0")
+    nv = ibp.Network(net, device=0)
+    monkeypatch.delenv("IBP_TILE")
+    blo, bhi = synth.sub_boxes(net, 37, seed=12)
+    _, _, cm = gpu_crown(n, blo, bhi)
+    _, _, cv = gpu_crown(nv, blo, bhi)
+    scale = np.maximum(np.abs(cv), 1.0)
+    assert np.all(np.abs(cm - cv) <= 1e-9 * scale), np.max(np.abs(cm - cv) / scale)
+    for b in (0, 31, 32, 36):
+        rc = oracle.crown_upper(net, blo[b], bhi[b], fac)
+        if rc["near"] == 0:
+            assert cm[b] >= rc["f_hi"] and cv[b] >= rc["f_hi"], b
