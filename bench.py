@@ -91,16 +91,17 @@ def write_traffic_record(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
            "write_scale": wsc, "source_sha256_16": m.hexdigest()[:16], "sources": sources, "kernels": kern}
     with open(TRAFFIC_RECORD, "w") as f:
         json.dump(rec, f, indent=1)
-    cmd = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc {c} --output-format csv -d <repo>/gpurun_out/{d} "
+    # the summary repeats the commands with the output folders this record was made from
+    rel = [os.path.relpath(os.path.abspath(d), ROOT) for d in (fetch_dir, write_dir, copy_fetch_dir, copy_write_dir)]
+    cmd = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc {c} --output-format csv -d <repo>/{d} "
            "-o run -- python3 <repo>/bench.py {a}")
     lines = ["# HBM traffic counters: forward bound, 8316-bus single box", "",
              "Commands (repository root on one MI355X; each counter in a run of its own):", "", "```",
-             cmd.format(c="FETCH_SIZE", d="pmc_fetch", a="--steps 3 --warmup 1 --no-cpu-baseline --no-extras"),
-             cmd.format(c="WRITE_SIZE", d="pmc_write", a="--steps 3 --warmup 1 --no-cpu-baseline --no-extras"),
-             cmd.format(c="FETCH_SIZE", d="pmc_copy_fetch", a="--calibrate-copy"),
-             cmd.format(c="WRITE_SIZE", d="pmc_copy_write", a="--calibrate-copy"),
-             "python3 bench.py --traffic-record gpurun_out/pmc_fetch gpurun_out/pmc_write "
-             "gpurun_out/pmc_copy_fetch gpurun_out/pmc_copy_write", "```", "",
+             cmd.format(c="FETCH_SIZE", d=rel[0], a="--steps 3 --warmup 1 --no-cpu-baseline --no-extras"),
+             cmd.format(c="WRITE_SIZE", d=rel[1], a="--steps 3 --warmup 1 --no-cpu-baseline --no-extras"),
+             cmd.format(c="FETCH_SIZE", d=rel[2], a="--calibrate-copy"),
+             cmd.format(c="WRITE_SIZE", d=rel[3], a="--calibrate-copy"),
+             "python3 bench.py --traffic-record " + " ".join(rel), "```", "",
              f"Calibration: a 1 GiB device copy (`__amd_rocclr_copyBuffer`) reads {cf:.1f} KiB FETCH_SIZE and "
              f"{cw:.1f} KiB WRITE_SIZE per dispatch,",
              f"so bytes = FETCH_SIZE KiB x 1024 x {fs:.4f} and WRITE_SIZE KiB x 1024 x {wsc:.4f}.", "",
