@@ -1,0 +1,68 @@
+"""GPU parity at the full batch sizes, in the launch configurations bench.py
+times: every box of the call is checked against what holds at any size (finite,
+f_lo <= f_hi, agreement with the per-box kernels on a sample), and sampled boxes
+against the FP64 oracle one by one (enclosure and the 1e-5 bar of the forward
+tests; gradients to the 1e-3 relative L2 bar of the full-size backward test).
+
+- 2000 buses, 18 periods x 1024 sub-boxes in one call (18432 boxes);
+- 8316 buses, 256 sub-boxes in one call;
+- 2000 buses, backward over 4096 sub-boxes in one call.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2511_15624_amd import ibp, synth
+from tests.test_gpu_backward import gpu_grad, rel_l2
+from tests.test_gpu_forward import assert_encloses, gpu_bounds, orc, setup
+
+pytestmark = pytest.mark.gpu
+
+
+def _sample(n, k, seed):
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([[0, n - 1], rng.choice(n, k, replace=False)]))
+
+
+def _plain_agrees(n, lo, hi, idx, g_lo, g_hi):
+    p_lo, p_hi = gpu_bounds(n, lo[idx], hi[idx], flags=ibp.IBP_F_PLAIN)
+    for a, b in ((g_lo[idx], p_lo), (g_hi[idx], p_hi)):
+        assert np.all(np.abs(a - b) <= 1e-6 * np.maximum(np.abs(b), 1.0)), np.max(np.abs(a - b))
+
+
+def test_c2000_eighteen_periods_of_1024_boxes():
+    net, fac, n = setup("c2000")
+    lo, hi, _ = synth.period_boxes(net, 18, 1024, seed=31)
+    f_lo, f_hi = gpu_bounds(n, lo, hi)
+    assert f_lo.shape == (18432,) and np.all(np.isfinite(f_lo)) and np.all(np.isfinite(f_hi))
+    assert np.all(f_lo <= f_hi)
+    idx = _sample(18432, 30, seed=5)
+    _plain_agrees(n, lo, hi, idx, f_lo, f_hi)
+    for b in idx[:8]:
+        assert_encloses(f_lo[b], f_hi[b], orc(net, lo[b], hi[b], fac), what=f"box {b}")
+
+
+def test_c8316_256_boxes():
+    net, fac, n = setup("c8316")
+    blo, bhi = synth.sub_boxes(net, 256, seed=41)
+    f_lo, f_hi = gpu_bounds(n, blo, bhi)
+    assert np.all(np.isfinite(f_lo)) and np.all(np.isfinite(f_hi)) and np.all(f_lo <= f_hi)
+    idx = _sample(256, 6, seed=6)
+    _plain_agrees(n, blo, bhi, idx, f_lo, f_hi)
+    for b in (0, 255):
+        assert_encloses(f_lo[b], f_hi[b], orc(net, blo[b], bhi[b], fac), what=f"box {b}")
+
+
+def test_c2000_backward_over_4096_boxes():
+    net, fac, n = setup("c2000")
+    blo, bhi = synth.sub_boxes(net, 4096, seed=51)
+    d_lo, d_hi = gpu_grad(n, blo, bhi, np.zeros(4096), np.ones(4096))
+    assert np.all(np.isfinite(d_lo)) and np.all(np.isfinite(d_hi))
+    idx = _sample(4096, 6, seed=7)
+    p_lo, p_hi = gpu_grad(n, blo[idx], bhi[idx], np.zeros(idx.size), np.ones(idx.size), flags=ibp.IBP_F_PLAIN)
+    for j, b in enumerate(idx):
+        got = np.concatenate([d_lo[b], d_hi[b]])
+        assert rel_l2(got, np.concatenate([p_lo[j], p_hi[j]])) <= 1e-4, b
+    for b in idx[:3]:
+        o_lo, o_hi, _ = oracle.grad(net, blo[b], bhi[b], 0.0, 1.0, fac)
+        assert rel_l2(np.concatenate([d_lo[b], d_hi[b]]), np.concatenate([o_lo, o_hi])) <= 1e-3, b
