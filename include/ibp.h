@@ -140,6 +140,17 @@ void ibp_free_network(ibp_network* net);
 #define IBP_F_BACKWARD 4u /* workspace query only: size for ibp_bound_backward (includes the forward's) */
 #define IBP_F_CROWN 8u    /* workspace query only: size for ibp_crown_bound_boxes (includes the forward's) */
 #define IBP_F_CROWN_REF 16u /* workspace query only: ibp_crown_bound_boxes with ref_iters > 0 */
+/* One-sided calls of ibp_bound_boxes / ibp_crown_bound_boxes, for callers that
+ * use one bound only (branch and bound bounds children from above and
+ * evaluates points from below).  The box-tiled outage sweep then computes only
+ * the penalty side that bound needs (about half its arithmetic).  The other
+ * output stays a valid bound: with IBP_F_UPPER_ONLY f_lo is -INFINITY (terms:
+ * Fc_hi = +INFINITY); with IBP_F_LOWER_ONLY the outage penalties' lower bound
+ * is taken as 0, so f_hi is larger than the two-sided call's (terms: Fc_lo = 0).
+ * The requested bound is the two-sided call's, bit for bit.  At most one of
+ * the two flags. */
+#define IBP_F_UPPER_ONLY 32u
+#define IBP_F_LOWER_ONLY 64u
 
 /* Bytes of device workspace a compute call needs for n_box boxes (0 on error). */
 size_t ibp_workspace_bytes(const ibp_network* net, int64_t n_box, uint32_t flags);
@@ -153,6 +164,8 @@ size_t ibp_workspace_bytes(const ibp_network* net, int64_t n_box, uint32_t flags
  *                    S_lo, S_hi (surplus), I_lo, I_hi (1^T s_inj), Fb_lo, Fb_hi
  *                    (1^T s_fb), Fc_lo, Fc_hi (s_agg), each already padded.
  *   ws, ws_bytes   : device workspace of at least ibp_workspace_bytes(net, n_box, flags).
+ * flags: 0, IBP_F_PLAIN, IBP_F_UPPER_ONLY or IBP_F_LOWER_ONLY (or PLAIN with one
+ * of the other two).
  * A box with a non-finite endpoint or lo > hi gets NaN outputs; other boxes are
  * unaffected.  Concurrent calls on one handle are safe with distinct workspaces.
  * Errors: INVALID_ARG, WORKSPACE, HOST_ONLY, DEVICE. */
@@ -200,8 +213,9 @@ ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box,
  *                lower bounds on max f.
  *   ws, ws_bytes: at least ibp_workspace_bytes(net, n_box, flags | IBP_F_CROWN)
  *                (| IBP_F_CROWN_REF when ref_iters > 0).
- * flags: 0 or IBP_F_PLAIN (forward kernels as in ibp_bound_boxes).  Invalid
- * boxes get NaN.  Errors: INVALID_ARG, WORKSPACE, HOST_ONLY, DEVICE. */
+ * flags: 0, IBP_F_PLAIN, IBP_F_UPPER_ONLY (forward kernels as in
+ * ibp_bound_boxes; with UPPER_ONLY f_lo is -INFINITY).  Invalid boxes get NaN.
+ * Errors: INVALID_ARG, WORKSPACE, HOST_ONLY, DEVICE. */
 ibp_status ibp_crown_bound_boxes(const ibp_network* net, int64_t n_box,
                                  const float* box_lo, const float* box_hi, int32_t ref_iters,
                                  double* f_lo, double* f_hi, double* crown_hi, float* vertex,

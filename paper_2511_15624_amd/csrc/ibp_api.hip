@@ -330,11 +330,17 @@ ibp_status check_compute_args(const ibp_network* net, int64_t n_box, const void*
   if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
   if (net->device < 0) return fail(IBP_E_HOST_ONLY, "network was built host-only");
   if (n_box < 0) return fail(IBP_E_INVALID_ARG, "n_box < 0");
-  if (flags & ~uint32_t(IBP_F_PLAIN | IBP_F_BACKWARD | IBP_F_CROWN | IBP_F_CROWN_REF))
+  if (flags & ~uint32_t(IBP_F_PLAIN | IBP_F_BACKWARD | IBP_F_CROWN | IBP_F_CROWN_REF | IBP_F_UPPER_ONLY |
+                        IBP_F_LOWER_ONLY))
     return fail(IBP_E_INVALID_ARG, "unknown flag bits");
+  if ((flags & IBP_F_UPPER_ONLY) && (flags & IBP_F_LOWER_ONLY))
+    return fail(IBP_E_INVALID_ARG, "IBP_F_UPPER_ONLY and IBP_F_LOWER_ONLY exclude each other");
+  if ((flags & IBP_F_BACKWARD) && (flags & (IBP_F_UPPER_ONLY | IBP_F_LOWER_ONLY)))
+    return fail(IBP_E_INVALID_ARG, "one-sided flags apply to the forward calls only");
   if (n_box == 0) return IBP_OK;
   if (!lo || !hi || !a || !b) return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
   lay = layout(net, n_box, flags);
+  lay.sides = (flags & IBP_F_UPPER_ONLY) ? 1 : (flags & IBP_F_LOWER_ONLY) ? 2 : 3;
   if (!ws || ws_bytes < lay.total)
     return fail(IBP_E_WORKSPACE, "workspace needs " + std::to_string(lay.total) + " bytes, got " +
                                      std::to_string(ws_bytes));
@@ -464,7 +470,8 @@ ibp_status ibp_crown_bound_boxes(const ibp_network* net, int64_t n_box, const fl
                                  double* crown_hi, float* vertex, void* ws, size_t ws_bytes, void* stream,
                                  uint32_t flags) {
   g_err.clear();
-  if (flags & ~uint32_t(IBP_F_PLAIN)) return fail(IBP_E_INVALID_ARG, "flags: only IBP_F_PLAIN is accepted");
+  if (flags & ~uint32_t(IBP_F_PLAIN | IBP_F_UPPER_ONLY))
+    return fail(IBP_E_INVALID_ARG, "flags: only IBP_F_PLAIN and IBP_F_UPPER_ONLY are accepted");
   if (ref_iters < 0 || ref_iters > 64) return fail(IBP_E_INVALID_ARG, "ref_iters must be in [0, 64]");
   ibp::WsLayout lay;
   const uint32_t need = flags | IBP_F_CROWN | (ref_iters > 0 ? IBP_F_CROWN_REF : 0u);

@@ -27,6 +27,7 @@
 #include <cfloat>
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "ibp_device.h"
 #include "ibp_devfun.h"
@@ -71,7 +72,12 @@ __device__ __forceinline__ float butterfly32(float (&v)[32]) {
 
 // One element of the outage sweep's VJP.  rlm = r_l - fmax_l and
 // rlp = r_l + fmax_l per line.  Adds (dC, dR) to (gc, gr) and the
-// outage-side contributions Lam dC, |Lam| dR to (pc, pr).
+// outage-side contributions Lam dC, |Lam| dR to (pc, pr).  SIDES selects
+// the penalty sides with a nonzero upstream weight: 3 both, 1 the lower
+// side only (chi = 0: the gradient of f_hi), 2 the upper side only (clo = 0:
+// the gradient of f_lo); a side whose weight is zero contributes exactly
+// zero, so skipping it changes nothing but the sign of a zero.
+template <int SIDES>
 __device__ __forceinline__ void k5_elem(float lam, float cc, float rc, float cl, float rlm, float rlp, float chi,
                                         float clo, float& gc, float& gr, float& pc, float& pr) {
   // The outaged line's own entry holds NaN: both activity tests fail and
@@ -79,15 +85,21 @@ __device__ __forceinline__ void k5_elem(float lam, float cc, float rc, float cl,
   // minNum) keeps the NaN out of the outage-side products, which then add 0.
   const float C = fmaf(lam, cc, cl);
   const float a = fabsf(C);
-  const float thi = a + fmaf(fabsf(lam), rc, rlm);  // |C| + R - fmax
-  const float tlo = a - fmaf(fabsf(lam), rc, rlp);  // |C| - R - fmax
-  const float hi = thi > 0.0f ? chi : 0.0f;
-  const float lo = tlo > 0.0f ? clo : 0.0f;
+  float hi = 0.0f, lo = 0.0f;
+  if (SIDES & 2) {
+    const float thi = a + fmaf(fabsf(lam), rc, rlm);  // |C| + R - fmax
+    hi = thi > 0.0f ? chi : 0.0f;
+  }
+  if (SIDES & 1) {
+    const float tlo = a - fmaf(fabsf(lam), rc, rlp);  // |C| - R - fmax
+    lo = tlo > 0.0f ? clo : 0.0f;
+  }
+  const float s = SIDES == 3 ? hi + lo : (SIDES == 1 ? lo : hi);
+  const float dR = SIDES == 3 ? hi - lo : (SIDES == 1 ? -lo : hi);
   // sign(C) (hi + lo) by flipping the sign bit when C is negative; C = 0
   // exactly only happens for a line whose flow interval is {0} here, where no
   // penalty is active and hi + lo = 0
-  const float dC = __int_as_float(__float_as_int(hi + lo) ^ (__float_as_int(C) & (int)0x80000000));
-  const float dR = hi - lo;
+  const float dC = __int_as_float(__float_as_int(s) ^ (__float_as_int(C) & (int)0x80000000));
   const float lam0 = fminf(lam, FLT_MAX);
   gc += dC;
   gr += dR;
@@ -148,10 +160,10 @@ __global__ __launch_bounds__(256) void k5_outage_vjp(DevNet net, void* ws, WsLay
         const float cc = __int_as_float(d.y), rc = __int_as_float(d.w);
         const float4 x = on ? lam[(size_t)k * Lp4] : make_float4(0.f, 0.f, 0.f, 0.f);
         float pc = 0.0f, pr = 0.0f;
-        k5_elem(x.x, cc, rc, c4.x, rm4.x, rp4.x, chi, clo, gc[0], gr[0], pc, pr);
-        k5_elem(x.y, cc, rc, c4.y, rm4.y, rp4.y, chi, clo, gc[1], gr[1], pc, pr);
-        k5_elem(x.z, cc, rc, c4.z, rm4.z, rp4.z, chi, clo, gc[2], gr[2], pc, pr);
-        k5_elem(x.w, cc, rc, c4.w, rm4.w, rp4.w, chi, clo, gc[3], gr[3], pc, pr);
+        k5_elem<3>(x.x, cc, rc, c4.x, rm4.x, rp4.x, chi, clo, gc[0], gr[0], pc, pr);
+        k5_elem<3>(x.y, cc, rc, c4.y, rm4.y, rp4.y, chi, clo, gc[1], gr[1], pc, pr);
+        k5_elem<3>(x.z, cc, rc, c4.z, rm4.z, rp4.z, chi, clo, gc[2], gr[2], pc, pr);
+        k5_elem<3>(x.w, cc, rc, c4.w, rm4.w, rp4.w, chi, clo, gc[3], gr[3], pc, pr);
         v[2 * i] = pc;
         v[2 * i + 1] = pr;
       }
@@ -213,38 +225,56 @@ __global__ __launch_bounds__(256) void k5b_outage_vjp(DevNet net, void* ws, WsLa
   for (int i = 0; i < kBT5; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) gc[i][j] = gr[i][j] = 0.0f;
-  for (int ks = k0; ks < k1; ks += 4) {
-    float v[32];
+  // the wave's boxes share the side selection: upstream weights that are zero
+  // for all of them (splitting asks for the gradient of f_hi alone) drop that
+  // side's arithmetic
+  bool no_hi = true, no_lo = true;
 #pragma unroll
-    for (int q = 0; q < 32; ++q) v[q] = 0.0f;
+  for (int i = 0; i < kBT5; ++i) {
+    no_hi = no_hi && chi[i] == 0.0f;
+    no_lo = no_lo && clo[i] == 0.0f;
+  }
+  auto sweep = [&](auto sides) {
+    constexpr int S = decltype(sides)::value;
+    for (int ks = k0; ks < k1; ks += 4) {
+      float v[32];
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int k = ks + kk;
-      if (k < k1) {  // uniform
-        const float4 x = on ? lam[(size_t)k * Lp4] : make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int q = 0; q < 32; ++q) v[q] = 0.0f;
 #pragma unroll
-        for (int i = 0; i < kBT5; ++i) {
-          const int4 d = cd[i][k];
-          const float cc = __int_as_float(d.y), rc = __int_as_float(d.w);
-          float pc = 0.0f, pr = 0.0f;
-          k5_elem(x.x, cc, rc, c4[i].x, rm4[i].x, rp4[i].x, chi[i], clo[i], gc[i][0], gr[i][0], pc, pr);
-          k5_elem(x.y, cc, rc, c4[i].y, rm4[i].y, rp4[i].y, chi[i], clo[i], gc[i][1], gr[i][1], pc, pr);
-          k5_elem(x.z, cc, rc, c4[i].z, rm4[i].z, rp4[i].z, chi[i], clo[i], gc[i][2], gr[i][2], pc, pr);
-          k5_elem(x.w, cc, rc, c4[i].w, rm4[i].w, rp4[i].w, chi[i], clo[i], gc[i][3], gr[i][3], pc, pr);
-          v[(kk * kBT5 + i) * 2] = pc;
-          v[(kk * kBT5 + i) * 2 + 1] = pr;
+      for (int kk = 0; kk < 4; ++kk) {
+        const int k = ks + kk;
+        if (k < k1) {  // uniform
+          const float4 x = on ? lam[(size_t)k * Lp4] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+          for (int i = 0; i < kBT5; ++i) {
+            const int4 d = cd[i][k];
+            const float cc = __int_as_float(d.y), rc = __int_as_float(d.w);
+            float pc = 0.0f, pr = 0.0f;
+            k5_elem<S>(x.x, cc, rc, c4[i].x, rm4[i].x, rp4[i].x, chi[i], clo[i], gc[i][0], gr[i][0], pc, pr);
+            k5_elem<S>(x.y, cc, rc, c4[i].y, rm4[i].y, rp4[i].y, chi[i], clo[i], gc[i][1], gr[i][1], pc, pr);
+            k5_elem<S>(x.z, cc, rc, c4[i].z, rm4[i].z, rp4[i].z, chi[i], clo[i], gc[i][2], gr[i][2], pc, pr);
+            k5_elem<S>(x.w, cc, rc, c4[i].w, rm4[i].w, rp4[i].w, chi[i], clo[i], gc[i][3], gr[i][3], pc, pr);
+            v[(kk * kBT5 + i) * 2] = pc;
+            v[(kk * kBT5 + i) * 2 + 1] = pr;
+          }
         }
       }
+      const float tot = butterfly32(v);
+      const int idx = lane >> 1;  // (outage ks + idx / 8, box idx / 2 % 4, field idx % 2)
+      const int k = ks + (idx >> 3);
+      const int i = (idx >> 1) & 3;
+      if ((lane & 1) == 0 && k < k1 && b0 + i < n_box) {
+        float2* cp = ws_ptr<float2>(ws, lay.cpart) + ((size_t)(b0 + i) * lay.k5_tiles + tile) * net.K + k;
+        reinterpret_cast<float*>(cp)[idx & 1] = tot;
+      }
     }
-    const float tot = butterfly32(v);
-    const int idx = lane >> 1;  // (outage ks + idx / 8, box idx / 2 % 4, field idx % 2)
-    const int k = ks + (idx >> 3);
-    const int i = (idx >> 1) & 3;
-    if ((lane & 1) == 0 && k < k1 && b0 + i < n_box) {
-      float2* cp = ws_ptr<float2>(ws, lay.cpart) + ((size_t)(b0 + i) * lay.k5_tiles + tile) * net.K + k;
-      reinterpret_cast<float*>(cp)[idx & 1] = tot;
-    }
-  }
+  };
+  if (no_hi)
+    sweep(std::integral_constant<int, 1>());
+  else if (no_lo)
+    sweep(std::integral_constant<int, 2>());
+  else
+    sweep(std::integral_constant<int, 3>());
   if (on) {
 #pragma unroll
     for (int i = 0; i < kBT5; ++i) {

@@ -176,6 +176,8 @@ __global__ __launch_bounds__(256, 2) void k2b_base_flows_mfma(DevNet net, void* 
 }
 
 // Outage sweep for kBT boxes x 256 lines per wave over one block row of outages.
+// SIDES as in k3_elem: one-sided calls compute only the penalty bound they need.
+template <int SIDES>
 __global__ __launch_bounds__(256) void k3b_contingency(DevNet net, void* ws, WsLayout lay, int64_t n_box) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -245,10 +247,10 @@ __global__ __launch_bounds__(256) void k3b_contingency(DevNet net, void* ws, WsL
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int i = 0; i < kBT; ++i) {
-          k3_pair(x[0], make_int4(0, q[i][0].x, q[i][0].y, 0), x[1], make_int4(0, q[i][1].x, q[i][1].y, 0), c4[i],
-                  h4[i], g4[i], acc_hi[i], acc_lo[i]);
-          k3_pair(x[2], make_int4(0, q[i][2].x, q[i][2].y, 0), x[3], make_int4(0, q[i][3].x, q[i][3].y, 0), c4[i],
-                  h4[i], g4[i], acc_hi[i], acc_lo[i]);
+          k3_pair<SIDES>(x[0], make_int4(0, q[i][0].x, q[i][0].y, 0), x[1], make_int4(0, q[i][1].x, q[i][1].y, 0),
+                         c4[i], h4[i], g4[i], acc_hi[i], acc_lo[i]);
+          k3_pair<SIDES>(x[2], make_int4(0, q[i][2].x, q[i][2].y, 0), x[3], make_int4(0, q[i][3].x, q[i][3].y, 0),
+                         c4[i], h4[i], g4[i], acc_hi[i], acc_lo[i]);
         }
       }
     }
@@ -259,12 +261,12 @@ __global__ __launch_bounds__(256) void k3b_contingency(DevNet net, void* ws, WsL
         const int4 d0 = cd[i][k];
         const float cc0 = __int_as_float(d0.y), rk0 = __int_as_float(d0.z);
         float a0, a1, a2, a3, q0, q1, q2, q3;
-        k3_elem(x0.x, cc0, rk0, c4[i].x, h4[i].x, g4[i].x, a0, q0);
-        k3_elem(x0.y, cc0, rk0, c4[i].y, h4[i].y, g4[i].y, a1, q1);
-        k3_elem(x0.z, cc0, rk0, c4[i].z, h4[i].z, g4[i].z, a2, q2);
-        k3_elem(x0.w, cc0, rk0, c4[i].w, h4[i].w, g4[i].w, a3, q3);
-        acc_hi[i] += (double)((a0 + a1) + (a2 + a3));
-        acc_lo[i] += (double)((q0 + q1) + (q2 + q3));
+        k3_elem<SIDES>(x0.x, cc0, rk0, c4[i].x, h4[i].x, g4[i].x, a0, q0);
+        k3_elem<SIDES>(x0.y, cc0, rk0, c4[i].y, h4[i].y, g4[i].y, a1, q1);
+        k3_elem<SIDES>(x0.z, cc0, rk0, c4[i].z, h4[i].z, g4[i].z, a2, q2);
+        k3_elem<SIDES>(x0.w, cc0, rk0, c4[i].w, h4[i].w, g4[i].w, a3, q3);
+        if (SIDES & 2) acc_hi[i] += (double)((a0 + a1) + (a2 + a3));
+        if (SIDES & 1) acc_lo[i] += (double)((q0 + q1) + (q2 + q3));
       }
     }
   }
@@ -336,7 +338,13 @@ hipError_t launch_batched_sweeps(const DevNet& net, int64_t n_box, void* ws, con
     tm->stop(t, s);
   } else if (net.K > 0) {
     const int t = tm->start(6, s);
-    hipLaunchKernelGGL(k3b_contingency, dim3(lay.k3_bx, lay.k3_by, groups), dim3(256), 0, s, net, ws, lay, n_box);
+    const dim3 grid(lay.k3_bx, lay.k3_by, groups);
+    if (lay.sides == 1)
+      hipLaunchKernelGGL(k3b_contingency<1>, grid, dim3(256), 0, s, net, ws, lay, n_box);
+    else if (lay.sides == 2)
+      hipLaunchKernelGGL(k3b_contingency<2>, grid, dim3(256), 0, s, net, ws, lay, n_box);
+    else
+      hipLaunchKernelGGL(k3b_contingency<3>, grid, dim3(256), 0, s, net, ws, lay, n_box);
     tm->stop(t, s);
   }
   return hipGetLastError();

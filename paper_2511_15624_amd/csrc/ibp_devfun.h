@@ -96,32 +96,42 @@ __device__ __forceinline__ T* ws_ptr(void* ws, size_t off) {
   return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + off);
 }
 
+// SIDES: 3 both penalty bounds, 1 the lower bound only (f_hi), 2 the upper
+// bound only (f_lo); the side not computed is 0.
+template <int SIDES = 3>
 __device__ __forceinline__ void k3_elem(float lam, float cc, float rk, float cl, float h, float g,
                                         float& phi, float& plo) {
   const float C = fmaf(lam, cc, cl);
-  const float A = fmaf(fabsf(lam), rk, h);
-  const float B = fmaf(fabsf(lam), rk, g);
-  phi = fmaxf(fabsf(C) + A, 0.0f);
-  plo = fmaxf(fabsf(C) - B, 0.0f);
+  phi = 0.0f;
+  plo = 0.0f;
+  if (SIDES & 2) {
+    const float A = fmaf(fabsf(lam), rk, h);
+    phi = fmaxf(fabsf(C) + A, 0.0f);
+  }
+  if (SIDES & 1) {
+    const float B = fmaf(fabsf(lam), rk, g);
+    plo = fmaxf(fabsf(C) - B, 0.0f);
+  }
 }
 
 // Two outages x four lines, summed in float32 (depth 3) and added in float64.
+template <int SIDES = 3>
 __device__ __forceinline__ void k3_pair(const float4& x0, const int4& d0, const float4& x1,
                                         const int4& d1, const float4& c4, const float4& h4,
                                         const float4& g4, double& acc_hi, double& acc_lo) {
   const float cc0 = __int_as_float(d0.y), rk0 = __int_as_float(d0.z);
   const float cc1 = __int_as_float(d1.y), rk1 = __int_as_float(d1.z);
   float a0, a1, a2, a3, b0, b1, b2, b3, e0, e1, e2, e3, f0, f1, f2, f3;
-  k3_elem(x0.x, cc0, rk0, c4.x, h4.x, g4.x, a0, b0);
-  k3_elem(x0.y, cc0, rk0, c4.y, h4.y, g4.y, a1, b1);
-  k3_elem(x0.z, cc0, rk0, c4.z, h4.z, g4.z, a2, b2);
-  k3_elem(x0.w, cc0, rk0, c4.w, h4.w, g4.w, a3, b3);
-  k3_elem(x1.x, cc1, rk1, c4.x, h4.x, g4.x, e0, f0);
-  k3_elem(x1.y, cc1, rk1, c4.y, h4.y, g4.y, e1, f1);
-  k3_elem(x1.z, cc1, rk1, c4.z, h4.z, g4.z, e2, f2);
-  k3_elem(x1.w, cc1, rk1, c4.w, h4.w, g4.w, e3, f3);
-  acc_hi += (double)(((a0 + a1) + (a2 + a3)) + ((e0 + e1) + (e2 + e3)));
-  acc_lo += (double)(((b0 + b1) + (b2 + b3)) + ((f0 + f1) + (f2 + f3)));
+  k3_elem<SIDES>(x0.x, cc0, rk0, c4.x, h4.x, g4.x, a0, b0);
+  k3_elem<SIDES>(x0.y, cc0, rk0, c4.y, h4.y, g4.y, a1, b1);
+  k3_elem<SIDES>(x0.z, cc0, rk0, c4.z, h4.z, g4.z, a2, b2);
+  k3_elem<SIDES>(x0.w, cc0, rk0, c4.w, h4.w, g4.w, a3, b3);
+  k3_elem<SIDES>(x1.x, cc1, rk1, c4.x, h4.x, g4.x, e0, f0);
+  k3_elem<SIDES>(x1.y, cc1, rk1, c4.y, h4.y, g4.y, e1, f1);
+  k3_elem<SIDES>(x1.z, cc1, rk1, c4.z, h4.z, g4.z, e2, f2);
+  k3_elem<SIDES>(x1.w, cc1, rk1, c4.w, h4.w, g4.w, e3, f3);
+  if (SIDES & 2) acc_hi += (double)(((a0 + a1) + (a2 + a3)) + ((e0 + e1) + (e2 + e3)));
+  if (SIDES & 1) acc_lo += (double)(((b0 + b1) + (b2 + b3)) + ((f0 + f1) + (f2 + f3)));
 }
 
 __device__ __forceinline__ float add_ru(float a, float b) { return next_up_f32(a + b); }

@@ -83,6 +83,7 @@ struct WsLayout {
   int k3_bx = 0, k3_by = 0;        // K3 grid per box (line tiles x outage chunks)
   int k2_nc = 0, k3_kc = 0;        // tile parameters used
   int batched = 0;                 // 1: box-tiled kernels (boxes share every streamed tile)
+  int sides = 3;                   // penalty sides of the outage sweep: 3 both, 1 lower (f_hi), 2 upper (f_lo)
   int k2_gx = 0;                   // batched base flows: grid x (line tiles padded to a multiple of 8)
   int k2_mfma = 0;                 // batched base flows on the float64 matrix cores
   int k2_chunk = 0;                // batched base flows: buses per chunk (k2_by chunks, a multiple of 4)

@@ -458,7 +458,10 @@ __device__ void finalize_box(const DevNet& net, void* ws, const WsLayout& lay, i
   for (int f = 0; f < 8; ++f) v[kP1Sc + f] = x[f];
   bh = x[8];
   bl = x[9];
-  const double chs = x[10], cls = x[11];
+  // one-sided calls: the side not computed is bounded trivially (upper bound
+  // of the outage penalties +inf, lower bound 0)
+  const double chs = lay.sides == 1 ? INFINITY : x[10];
+  const double cls = lay.sides == 2 ? 0.0 : x[11];
 
   // surplus and imbalance intervals; float64 reduction depth <= n_p1 + 16
   const double gam = (lay.n_p1 + 16) * kU64 * 1.01;

@@ -25,6 +25,8 @@ IBP_F_AUTOTUNE = 2
 IBP_F_BACKWARD = 4
 IBP_F_CROWN = 8
 IBP_F_CROWN_REF = 16
+IBP_F_UPPER_ONLY = 32   # only f_hi is needed (f_lo = -inf)
+IBP_F_LOWER_ONLY = 64   # only f_lo is needed (f_hi valid but looser)
 
 STATUS = {
     0: "IBP_OK",

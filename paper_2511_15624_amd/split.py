@@ -11,9 +11,10 @@ for every open root at once, all on the device:
    gradient of f_hi with respect to the leaf endpoints;
 3. ``ibp_split_bisect``: split at the float32 midpoint of the coordinate with
    the largest (d f_hi/d hi_j - d f_hi/d lo_j) * r_j;
-4. bound the two children (IBP, or IBP tightened by the linear relaxation),
-   and evaluate points inside them as zero-width boxes (f_lo there is a
-   certified value of f): their centres, and with the relaxation the vertex
+4. bound the two children from above (IBP, or IBP tightened by the linear
+   relaxation; one-sided calls, as only f_hi is used), and evaluate points
+   inside them as zero-width boxes (f_lo there is a certified value of f;
+   lower-bound-only calls): their centres, and with the relaxation the vertex
    that maximises its linear part;
 5. ``ibp_split_update``: root upper bound = the smaller of its previous value
    and the largest leaf f_hi, root lower bound on max f = the best certified
@@ -96,7 +97,8 @@ class BranchAndBound:
         self.root_ub = f_hi.clone()
         mid = 0.5 * lo + 0.5 * hi
         pts = torch.stack([mid, vt], 1) if self.relax else mid[:, None]
-        p_lo, _ = _ibp.ibp_bound_boxes(net, pts.reshape(-1, X), pts.reshape(-1, X), ws=self.ws_c)
+        p_lo, _ = _ibp.ibp_bound_boxes(net, pts.reshape(-1, X), pts.reshape(-1, X), ws=self.ws_c,
+                                       flags=_ibp.IBP_F_LOWER_ONLY)
         p_lo = p_lo.view(R, -1)
         best = torch.nan_to_num(p_lo, nan=-float("inf")).argmax(1)
         self.root_lb = p_lo.gather(1, best[:, None])[:, 0].clone()
@@ -110,9 +112,9 @@ class BranchAndBound:
         if self.relax:
             vt = self.vtx[:n] if n <= self.vtx.shape[0] else torch.empty_like(lo)
             _, f_hi = _ibp.ibp_crown_bound_boxes(self.net, lo, hi, ws=self.ws_f, stream=stream, vertex=vt,
-                                                 ref_iters=self.ref_iters)
+                                                 ref_iters=self.ref_iters, flags=_ibp.IBP_F_UPPER_ONLY)
             return f_hi, vt
-        _, f_hi = _ibp.ibp_bound_boxes(self.net, lo, hi, ws=self.ws_f, stream=stream)
+        _, f_hi = _ibp.ibp_bound_boxes(self.net, lo, hi, ws=self.ws_f, stream=stream, flags=_ibp.IBP_F_UPPER_ONLY)
         return f_hi, None
 
     def screen(self, stream=None):
@@ -148,7 +150,8 @@ class BranchAndBound:
         else:
             pts = self.cen[:2 * n]
         flat = pts.view(-1, X)
-        p_lo, _ = _ibp.ibp_bound_boxes(self.net, flat, flat, ws=self.ws_c, stream=stream)
+        p_lo, _ = _ibp.ibp_bound_boxes(self.net, flat, flat, ws=self.ws_c, stream=stream,
+                                       flags=_ibp.IBP_F_LOWER_ONLY)
         _ibp._check(lib.ibp_split_update(n, _p(roots), S, _p(self.n_leaf), _p(self.sel), _p(kid_fhi), self.P,
                                          _p(p_lo), _p(flat), X, _p(self.leaf_fhi), _p(self.root_ub),
                                          _p(self.root_lb), _p(self.root_x), s))

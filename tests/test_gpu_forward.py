@@ -287,3 +287,34 @@ def test_distinct_contingency_limits():
         for b in range(7):
             assert_encloses(f_lo[b], f_hi[b], refs[b], what=f"box {b} flags {flags}")
             assert_terms_enclose(t[b], refs[b])
+
+
+@pytest.mark.parametrize("n_box", [1, 37])
+def test_one_sided_calls(n_box):
+    """IBP_F_UPPER_ONLY / IBP_F_LOWER_ONLY return the requested bound bit for
+    bit (single-box and box-tiled paths) and a trivially valid other side."""
+    torch = _torch()
+    net, fac, n = setup("c500")
+    blo, bhi = synth.sub_boxes(net, n_box, seed=404)
+    f_lo, f_hi, t = gpu_bounds(n, blo, bhi, terms=True)
+    u_lo, u_hi, tu = gpu_bounds(n, blo, bhi, terms=True, flags=ibp.IBP_F_UPPER_ONLY)
+    l_lo, l_hi, tl = gpu_bounds(n, blo, bhi, terms=True, flags=ibp.IBP_F_LOWER_ONLY)
+    assert np.array_equal(u_hi, f_hi) and np.all(u_lo == -np.inf) and np.all(tu[:, 7] == np.inf)
+    assert np.array_equal(l_lo, f_lo) and np.all(tl[:, 6] == 0.0)
+    assert np.all(l_hi >= f_hi)
+    for b in (0, n_box - 1):
+        r = orc(net, blo[b], bhi[b], fac)
+        assert u_hi[b] >= r["f_hi"] and l_lo[b] <= r["f_lo"]
+        # without the outage penalties' lower bound the upper bound still holds
+        assert l_hi[b] >= r["f_hi"]
+    tlo = torch.from_numpy(blo).cuda()
+    thi = torch.from_numpy(bhi).cuda()
+    with pytest.raises(ibp.IBPError):
+        ibp.ibp_bound_boxes(n, tlo, thi, flags=ibp.IBP_F_UPPER_ONLY | ibp.IBP_F_LOWER_ONLY)
+    with pytest.raises(ibp.IBPError):
+        ibp.ibp_bound_backward(n, tlo, thi, torch.zeros(n_box, dtype=torch.float64),
+                               torch.ones(n_box, dtype=torch.float64), flags=ibp.IBP_F_UPPER_ONLY)
+    c_lo, c_hi = ibp.ibp_crown_bound_boxes(n, tlo, thi)
+    cu_lo, cu_hi = ibp.ibp_crown_bound_boxes(n, tlo, thi, flags=ibp.IBP_F_UPPER_ONLY)
+    torch.cuda.synchronize()
+    assert torch.equal(c_hi, cu_hi) and bool(torch.all(cu_lo == -float("inf")))
