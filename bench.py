@@ -140,6 +140,37 @@ def cpu_baseline(net, lo, hi):
     return r, t, t_build, int(fac["K"])
 
 
+def cpu_batched_sample(synth, n_sample=4):
+    """FP64 oracle on a seeded sample of the 2000-bus period boxes, per box
+    (bound evaluation only); returns (evals per box, seconds per box)."""
+    import oracle
+    net3 = synth.make_config("c2000")
+    fac = oracle.factors(net3)
+    lo, hi, _ = synth.period_boxes(net3, 18, 1024, seed=31)
+    idx = np.random.default_rng(3).choice(lo.shape[0], n_sample, replace=False)
+    t0 = time.perf_counter()
+    for b in idx:
+        oracle.ibp(net3, lo[b], hi[b], fac)
+    t = (time.perf_counter() - t0) / n_sample
+    return int(fac["K"]) * len(net3["line_from"]), t
+
+
+def hbm_probe(torch, ibp):
+    """Measured device bandwidth: torch copy_ of 1 GiB (bytes read + written)
+    and the library's streaming-read probe over 1 GiB (the sweeps' load
+    pattern), 10 times each."""
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    part = torch.empty(2048, dtype=torch.float32, device="cuda")
+    ms_copy = _time(torch, lambda: y.copy_(x), 10)
+    ms_read = _time(torch, lambda: ibp.ibp_read_probe(x, part), 10)
+    del x, y
+    torch.cuda.empty_cache()
+    return {"copy_gbs": round(2 * (1 << 30) / (ms_copy * 1e-3) / 1e9, 1),
+            "read_gbs": round((1 << 30) / (ms_read * 1e-3) / 1e9, 1),
+            "note": "torch copy_ of 1 GiB (read + written bytes); ibp_read_probe over 1 GiB (read bytes)"}
+
+
 VALU_PEAK = 78.6e12  # float32 VALU lane-ops/s: 256 CUs x 128 lanes/clock x 2.4 GHz (FMA = one op)
 MFMA_F64_PEAK = 78.6e12  # float64 dense matrix FLOP/s of MI355X
 OPS_PER_EVAL = 9.25  # VALU ops per box-outage-line evaluation in the outage sweep (from the ISA)
@@ -500,6 +531,10 @@ def main(argv=None):
         "setup_s": round(t_setup, 2),
     }
     g_lo, g_hi = float(f_lo.cpu()[0]), float(f_hi.cpu()[0])
+    probe = hbm_probe(torch, ibp)
+    out["hbm_probe"] = probe
+    roof["frac_of_read_probe"] = round(achieved / probe["read_gbs"], 4)
+    out["step_roofline"]["frac_of_read_probe"] = round(step_gbs / probe["read_gbs"], 4)
     if not args.no_extras:
         out.update(extras(torch, ibp, synth, n, net))
     if not args.no_cpu_baseline:
@@ -509,6 +544,14 @@ def main(argv=None):
                                "sample": f"the full single box ({K} outages x {L} lines), FP64 "
                                          f"numpy; {t_cpu:.2f} s; factor construction "
                                          f"{t_build:.1f} s not timed; elementwise stages single-threaded"}
+        if not args.no_extras:
+            ev3, t3 = cpu_batched_sample(synth)
+            n_b3 = out["batched"]["ms_per_call"]
+            out["cpu_baseline"]["batched_sample"] = {
+                "value": ev3 / t3, "unit": "evals/s", "seconds_per_box": t3,
+                "sample": "4 seeded boxes of the 2000-bus 18 x 1024 period set, FP64 numpy, per box; the "
+                          "18432-box call extrapolates to " + f"{t3 * 18432:.0f} s on the host against "
+                          f"{n_b3:.1f} ms on the GPU"}
         den_lo = max(abs(r["f_lo"]), 1.0)
         den_hi = max(abs(r["f_hi"]), 1.0)
         out["bound_gap_vs_fp64"] = {

@@ -305,6 +305,16 @@ ibp_status ibp_split_update(int64_t n_act, const int64_t* roots, int32_t slots, 
 ibp_status ibp_split_screen(int64_t n_root, const double* root_ub, const double* root_lb, double rel_tol,
                             int32_t* status, int64_t* open_roots, int64_t* n_open, void* stream);
 
+/* ibp_read_probe -- streams n_float4 float4 values from device memory `src`
+ * (16-byte aligned) with the load pattern of the library's HBM-bound sweeps
+ * (nontemporal float4 loads, eight in flight per lane; 2048 blocks x 256
+ * threads, each block a contiguous range) and writes 2048 per-block float32
+ * sums to `partial` (device, caller owned).  For calibration: the caller times
+ * it on `stream` to measure the read rate those sweeps can reach.  Asynchronous.  Errors: INVALID_ARG (NULL or
+ * misaligned pointer, n_float4 < 1), DEVICE. */
+#define IBP_READ_PROBE_PARTIALS 2048
+ibp_status ibp_read_probe(const void* src, int64_t n_float4, float* partial, void* stream);
+
 /* Last error message of the calling thread ("" if none). */
 const char* ibp_last_error(void);
 

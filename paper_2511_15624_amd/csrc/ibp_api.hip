@@ -649,6 +649,15 @@ ibp_status ibp_split_screen(int64_t n_root, const double* root_ub, const double*
   return e == hipSuccess ? IBP_OK : fail(IBP_E_DEVICE, hipGetErrorString(e));
 }
 
+ibp_status ibp_read_probe(const void* src, int64_t n_float4, float* partial, void* stream) {
+  g_err.clear();
+  if (!src || !partial || n_float4 < 1) return fail(IBP_E_INVALID_ARG, "read probe needs a buffer and a size");
+  if (reinterpret_cast<uintptr_t>(src) % 16 != 0) return fail(IBP_E_INVALID_ARG, "read probe source not 16-byte aligned");
+  hipError_t e = ibp::launch_read_probe(static_cast<const float4*>(src), n_float4, partial,
+                                        static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? IBP_OK : fail(IBP_E_DEVICE, hipGetErrorString(e));
+}
+
 const char* ibp_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"

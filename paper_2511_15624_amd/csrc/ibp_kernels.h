@@ -91,6 +91,9 @@ hipError_t launch_split_update(int64_t n, const int64_t* roots, int S, int* n_le
 hipError_t launch_split_screen(int64_t R, const double* root_ub, const double* root_lb, double rel_tol, int* status,
                                int64_t* open_roots, int64_t* n_open, hipStream_t s);
 
+// Streaming-read probe (see ibp_probe.hip): 2048 per-block partial sums.
+hipError_t launch_read_probe(const float4* src, int64_t n, float* partial, hipStream_t s);
+
 // K1..K4 for n_box boxes, each box handled by its own grid slice.
 hipError_t launch_forward_single(const DevNet& net, int64_t n_box, const float* lo, const float* hi,
                                  double* f_lo, double* f_hi, double* terms, void* ws,

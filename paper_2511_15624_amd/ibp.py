@@ -58,6 +58,7 @@ EXPORTED = [
     "ibp_split_bisect",
     "ibp_split_update",
     "ibp_split_screen",
+    "ibp_read_probe",
     "ibp_last_error",
 ]
 
@@ -170,6 +171,8 @@ def load_library(path: str = LIB_PATH):
     lib.ibp_split_update.restype = ctypes.c_int
     lib.ibp_split_screen.argtypes = [i64, vp, vp, ctypes.c_double, vp, vp, vp, vp]
     lib.ibp_split_screen.restype = ctypes.c_int
+    lib.ibp_read_probe.argtypes = [vp, i64, vp, vp]
+    lib.ibp_read_probe.restype = ctypes.c_int
     lib.ibp_last_error.argtypes = []
     lib.ibp_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -389,6 +392,18 @@ def ibp_crown_bound_boxes(net: Network, lo, hi, crown: bool = False, flags: int 
                                                 _dev_ptr(f_lo), _dev_ptr(f_hi), _dev_ptr(c), _dev_ptr(vertex),
                                                 _dev_ptr(buf), buf.numel(), _stream_ptr(stream), flags))
     return (f_lo, f_hi, c) if crown else (f_lo, f_hi)
+
+
+def ibp_read_probe(src, partial, stream=None):
+    """Streams a contiguous 16-byte aligned device tensor with the load pattern
+    of the HBM-bound sweeps; writes 2048 float32 partial sums into `partial`."""
+    torch = _torch()
+    if not (src.is_cuda and src.is_contiguous() and src.numel() * src.element_size() >= 16):
+        raise ValueError("src must be a contiguous device tensor of at least 16 bytes")
+    if partial.dtype != torch.float32 or partial.numel() < 2048 or not partial.is_cuda:
+        raise ValueError("partial must be a float32 device tensor with 2048 entries")
+    n4 = src.numel() * src.element_size() // 16
+    _check(load_library().ibp_read_probe(_dev_ptr(src), n4, _dev_ptr(partial), _stream_ptr(stream)))
 
 
 def ibp_autotune(net: Network, lo, hi, stream=None):

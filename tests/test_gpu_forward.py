@@ -318,3 +318,14 @@ def test_one_sided_calls(n_box):
     cu_lo, cu_hi = ibp.ibp_crown_bound_boxes(n, tlo, thi, flags=ibp.IBP_F_UPPER_ONLY)
     torch.cuda.synchronize()
     assert torch.equal(c_hi, cu_hi) and bool(torch.all(cu_lo == -float("inf")))
+
+
+def test_read_probe_sums_what_it_streams():
+    torch = _torch()
+    x = torch.ones((1 << 20) + 12, dtype=torch.float32, device="cuda")   # ragged against the grid stride
+    part = torch.empty(ibp_partials := 2048, dtype=torch.float32, device="cuda")
+    ibp.ibp_read_probe(x, part)
+    torch.cuda.synchronize()
+    assert part.numel() == ibp_partials and float(part.sum()) == float(x.numel())
+    with pytest.raises(ValueError):
+        ibp.ibp_read_probe(x, torch.empty(16, dtype=torch.float32, device="cuda"))
