@@ -268,13 +268,16 @@ def extras(torch, ibp, synth, n4, net4):
     g1 = torch.ones(4096, dtype=torch.float64, device="cuda")
     wsb = ibp.Workspace(n3)
     msf = _time(torch, lambda: ibp.ibp_bound_boxes(n3, t5l, t5h, ws=wsb), 3)
-    msb = _time(torch, lambda: ibp.ibp_bound_backward(n3, t5l, t5h, g0, g1, ws=wsb), 3)
+    msb = _time(torch, lambda: ibp.ibp_bound_backward(n3, t5l, t5h, None, g1, ws=wsb,
+                                                       flags=ibp.IBP_F_UPPER_ONLY), 3)
+    msb2 = _time(torch, lambda: ibp.ibp_bound_backward(n3, t5l, t5h, g0, g1, ws=wsb), 3)
     sub = 256
-    msbp = _time(torch, lambda: ibp.ibp_bound_backward(n3, t5l[:sub], t5h[:sub], g0[:sub], g1[:sub], ws=wsb,
-                                                        flags=ibp.IBP_F_PLAIN), 1)
+    msbp = _time(torch, lambda: ibp.ibp_bound_backward(n3, t5l[:sub], t5h[:sub], None, g1[:sub], ws=wsb,
+                                                        flags=ibp.IBP_F_PLAIN | ibp.IBP_F_UPPER_ONLY), 1)
     ev5 = 4096 * n3.n_ctg * n3.n_line
-    res["backward"] = {"workload": "2000 buses, 4096 sub-boxes: d(f_hi)/d(box endpoints)",
+    res["backward"] = {"workload": "2000 buses, 4096 sub-boxes: d(f_hi)/d(box endpoints), one-sided call",
                        "value": ev5 / (msb * 1e-3), "unit": "evals/s", "ms_backward": msb,
+                       "ms_backward_two_sided_weights": msb2,
                        "ms_forward": msf, "plain_value": sub * n3.n_ctg * n3.n_line / (msbp * 1e-3),
                        "plain_sample": f"first {sub} boxes, per-box kernels"}
     # piecewise-linear cost and value curves (1-4 segments per device) on the

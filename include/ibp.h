@@ -181,7 +181,10 @@ ibp_status ibp_bound_boxes(const ibp_network* net, int64_t n_box,
  * g_f_lo, g_f_hi: device float64 [n_box].  The workspace must hold
  * ibp_workspace_bytes(net, n_box, flags | IBP_F_BACKWARD); the call recomputes
  * the forward intermediates in it.  A box with invalid endpoints gets NaN
- * gradients.  Errors as the forward call. */
+ * gradients.  flags: 0 or IBP_F_PLAIN, optionally with IBP_F_UPPER_ONLY (the
+ * VJP of f_hi alone: g_f_lo is not read and may be NULL) or IBP_F_LOWER_ONLY
+ * (of f_lo alone: g_f_hi not read); the one-sided sweeps carry only that
+ * side's arithmetic.  Errors as the forward call. */
 ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box,
                               const float* box_lo, const float* box_hi,
                               const double* g_f_lo, const double* g_f_hi,

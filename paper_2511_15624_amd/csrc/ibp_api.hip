@@ -335,8 +335,6 @@ ibp_status check_compute_args(const ibp_network* net, int64_t n_box, const void*
     return fail(IBP_E_INVALID_ARG, "unknown flag bits");
   if ((flags & IBP_F_UPPER_ONLY) && (flags & IBP_F_LOWER_ONLY))
     return fail(IBP_E_INVALID_ARG, "IBP_F_UPPER_ONLY and IBP_F_LOWER_ONLY exclude each other");
-  if ((flags & IBP_F_BACKWARD) && (flags & (IBP_F_UPPER_ONLY | IBP_F_LOWER_ONLY)))
-    return fail(IBP_E_INVALID_ARG, "one-sided flags apply to the forward calls only");
   if (n_box == 0) return IBP_OK;
   if (!lo || !hi || !a || !b) return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
   lay = layout(net, n_box, flags);
@@ -449,10 +447,14 @@ ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box, const float
                               void* stream, uint32_t flags) {
   g_err.clear();
   ibp::WsLayout lay;
-  ibp_status st = check_compute_args(net, n_box, box_lo, box_hi, g_f_lo, g_f_hi, ws, ws_bytes,
-                                     flags | IBP_F_BACKWARD, lay);
+  // one-sided: the weight of the other bound is not read (taken as zero)
+  const bool up = flags & IBP_F_UPPER_ONLY, low = flags & IBP_F_LOWER_ONLY;
+  ibp_status st = check_compute_args(net, n_box, box_lo, box_hi, up ? g_f_hi : g_f_lo, low ? g_f_lo : g_f_hi, ws,
+                                     ws_bytes, flags | IBP_F_BACKWARD, lay);
   if (st != IBP_OK || n_box == 0) return st;
   if (!g_box_lo || !g_box_hi) return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
+  if (up) g_f_lo = nullptr;
+  if (low) g_f_hi = nullptr;
   DeviceGuard g(net->device);
   if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -138,8 +138,8 @@ __global__ __launch_bounds__(256) void k5_outage_vjp(DevNet net, void* ws, WsLay
   const bool on = col < Lp4;
   const int k0 = blockIdx.y * kK5Chunk;
   const int k1 = min(net.K, k0 + kK5Chunk);
-  const float chi = (float)(-net.zeta_f * g_lo[b]);  // weight of an active P_hi
-  const float clo = (float)(-net.zeta_f * g_hi[b]);  // weight of an active P_lo (dR gets -clo)
+  const float chi = (float)(-net.zeta_f * (g_lo ? g_lo[b] : 0.0));  // weight of an active P_hi
+  const float clo = (float)(-net.zeta_f * (g_hi ? g_hi[b] : 0.0));  // weight of an active P_lo (dR gets -clo)
   // lines of this lane (padding lines: zero centre and radius, limit FLT_MAX)
   float4 c4 = make_float4(0.f, 0.f, 0.f, 0.f), rm4, rp4;
   line_radii(net, ws, lay, b, col, on, c4, rm4, rp4);
@@ -194,6 +194,10 @@ __global__ __launch_bounds__(256) void k5_outage_vjp(DevNet net, void* ws, WsLay
 // x 2 fields go through one 32-value butterfly.
 constexpr int kBT5 = 4;
 
+// MODE 1 / 2: the caller asked for the gradient of f_hi / f_lo alone (the
+// other weight pointer is null), so only that side's code is compiled into
+// the kernel (fewer registers, more waves); MODE 3 picks the sides per wave.
+template <int MODE>
 __global__ __launch_bounds__(256) void k5b_outage_vjp(DevNet net, void* ws, WsLayout lay, int64_t n_box,
                                                       const double* __restrict__ g_lo,
                                                       const double* __restrict__ g_hi) {
@@ -214,8 +218,8 @@ __global__ __launch_bounds__(256) void k5b_outage_vjp(DevNet net, void* ws, WsLa
 #pragma unroll
   for (int i = 0; i < kBT5; ++i) {
     bb[i] = min(b0 + i, n_box - 1);
-    chi[i] = (float)(-net.zeta_f * g_lo[bb[i]]);
-    clo[i] = (float)(-net.zeta_f * g_hi[bb[i]]);
+    chi[i] = (float)(-net.zeta_f * (g_lo ? g_lo[bb[i]] : 0.0));
+    clo[i] = (float)(-net.zeta_f * (g_hi ? g_hi[bb[i]] : 0.0));
     line_radii(net, ws, lay, bb[i], col, on, c4[i], rm4[i], rp4[i]);
     cd[i] = ws_ptr<int4>(ws, lay.ctg) + bb[i] * net.K;
   }
@@ -269,7 +273,9 @@ __global__ __launch_bounds__(256) void k5b_outage_vjp(DevNet net, void* ws, WsLa
       }
     }
   };
-  if (no_hi)
+  if (MODE != 3)
+    sweep(std::integral_constant<int, MODE>());
+  else if (no_hi)
     sweep(std::integral_constant<int, 1>());
   else if (no_lo)
     sweep(std::integral_constant<int, 2>());
@@ -301,7 +307,7 @@ __global__ __launch_bounds__(256) void k5r_lines(DevNet net, void* ws, WsLayout 
     grf[l] = 0.0f;
     return;
   }
-  const double zf = net.zeta_f, gl = g_lo[b], gh = g_hi[b];
+  const double zf = net.zeta_f, gl = g_lo ? g_lo[b] : 0.0, gh = g_hi ? g_hi[b] : 0.0;
   const double c = ws_ptr<double>(ws, lay.lcf)[b * net.L + l];
   const double r = ws_ptr<double>(ws, lay.lrf)[b * net.L + l];
   const double a = fabs(c), fb = net.fmax_b[l];
@@ -467,7 +473,7 @@ __global__ __launch_bounds__(256) void k7_endpoints(DevNet net, void* ws, WsLayo
   rI = block_sum256(rI, sh);
   bad = block_sum256(bad, sh);
   if (j >= net.X) return;
-  const double gl = g_lo[b], gh = g_hi[b], zi = net.zeta_inj;
+  const double gl = g_lo ? g_lo[b] : 0.0, gh = g_hi ? g_hi[b] : 0.0, zi = net.zeta_inj;
   const double aI = fabs(cI);
   const double hiI = (aI + rI > 0.0) ? -zi * gl : 0.0;
   const double loI = (aI - rI > 0.0) ? -zi * gh : 0.0;
@@ -507,8 +513,13 @@ hipError_t launch_backward_sweeps(const DevNet& net, int64_t n_box, void* ws, co
   if (n_box >= kBatchMin && lay.batched && net.K > 0) {
     const int t = tm->start(7, s);
     const unsigned groups = (unsigned)(((n_box + kBT5 - 1) / kBT5 + 3) / 4);
-    hipLaunchKernelGGL(k5b_outage_vjp, dim3(lay.k5_tiles, lay.k5_by, groups), dim3(256), 0, s, net, ws, lay, n_box,
-                       g_lo, g_hi);
+    const dim3 grid(lay.k5_tiles, lay.k5_by, groups);
+    if (!g_lo)
+      hipLaunchKernelGGL(k5b_outage_vjp<1>, grid, dim3(256), 0, s, net, ws, lay, n_box, g_lo, g_hi);
+    else if (!g_hi)
+      hipLaunchKernelGGL(k5b_outage_vjp<2>, grid, dim3(256), 0, s, net, ws, lay, n_box, g_lo, g_hi);
+    else
+      hipLaunchKernelGGL(k5b_outage_vjp<3>, grid, dim3(256), 0, s, net, ws, lay, n_box, g_lo, g_hi);
     tm->stop(t, s);
   }
   for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {

@@ -354,12 +354,15 @@ def ibp_bound_boxes(net: Network, lo, hi, terms: bool = False, flags: int = 0, w
 
 def ibp_bound_backward(net: Network, lo, hi, g_lo, g_hi, flags: int = 0, ws: Workspace = None,
                        stream=None):
-    """d(g_lo . f_lo + g_hi . f_hi) / d(lo, hi) as float64 device tensors [n_box, X]."""
+    """d(g_lo . f_lo + g_hi . f_hi) / d(lo, hi) as float64 device tensors [n_box, X].
+    With flags IBP_F_UPPER_ONLY (IBP_F_LOWER_ONLY) g_lo (g_hi) is not read and may be None."""
     torch = _torch()
     lo, hi = _check_boxes(net, lo, hi)
     n = lo.shape[0]
-    g_lo = g_lo.to(device=lo.device, dtype=torch.float64).contiguous()
-    g_hi = g_hi.to(device=lo.device, dtype=torch.float64).contiguous()
+    if g_lo is None and not flags & IBP_F_UPPER_ONLY or g_hi is None and not flags & IBP_F_LOWER_ONLY:
+        raise ValueError("g_lo / g_hi may be None only with the matching one-sided flag")
+    g_lo = None if flags & IBP_F_UPPER_ONLY else g_lo.to(device=lo.device, dtype=torch.float64).contiguous()
+    g_hi = None if flags & IBP_F_LOWER_ONLY else g_hi.to(device=lo.device, dtype=torch.float64).contiguous()
     d_lo = torch.empty((n, net.n_input), dtype=torch.float64, device=lo.device)
     d_hi = torch.empty((n, net.n_input), dtype=torch.float64, device=lo.device)
     ws = ws or Workspace(net)

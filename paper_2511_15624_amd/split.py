@@ -7,7 +7,7 @@ Each root box keeps up to ``rounds + 1`` leaves that partition it.  One round,
 for every open root at once, all on the device:
 
 1. ``ibp_split_select``: the leaf with the largest upper bound f_hi;
-2. ``ibp_bound_backward`` on those leaves with (g_lo, g_hi) = (0, 1): the
+2. ``ibp_bound_backward`` on those leaves, one-sided with g_hi = 1: the
    gradient of f_hi with respect to the leaf endpoints;
 3. ``ibp_split_bisect``: split at the float32 midpoint of the coordinate with
    the largest (d f_hi/d hi_j - d f_hi/d lo_j) * r_j;
@@ -82,7 +82,6 @@ class BranchAndBound:
         self.kid_hi = torch.empty((2 * R, X), dtype=torch.float32, device=dev)
         self.cen = torch.empty((2 * R, X), dtype=torch.float32, device=dev)
         self.vtx = torch.empty((2 * R, X), dtype=torch.float32, device=dev) if self.relax else None
-        self.g_lo = torch.zeros(R, dtype=torch.float64, device=dev)
         self.g_hi = torch.ones(R, dtype=torch.float64, device=dev)
         self.status = torch.zeros(R, dtype=torch.int32, device=dev)
         self.open_roots = torch.arange(R, dtype=torch.int64, device=dev)
@@ -139,8 +138,8 @@ class BranchAndBound:
         roots = self.open_roots[:n] if self.screen_on else None
         _ibp._check(lib.ibp_split_select(n, _p(roots), S, _p(self.n_leaf), X, _p(self.leaf_lo), _p(self.leaf_hi),
                                          _p(self.leaf_fhi), _p(self.sel), _p(self.sel_lo), _p(self.sel_hi), s))
-        d_lo, d_hi = _ibp.ibp_bound_backward(self.net, self.sel_lo[:n], self.sel_hi[:n], self.g_lo[:n],
-                                             self.g_hi[:n], ws=self.ws_b, stream=stream)
+        d_lo, d_hi = _ibp.ibp_bound_backward(self.net, self.sel_lo[:n], self.sel_hi[:n], None, self.g_hi[:n],
+                                             ws=self.ws_b, stream=stream, flags=_ibp.IBP_F_UPPER_ONLY)
         _ibp._check(lib.ibp_split_bisect(n, _p(roots), S, _p(self.n_leaf), X, _p(self.leaf_lo), _p(self.leaf_hi),
                                          _p(self.sel), _p(self.sel_lo), _p(self.sel_hi), _p(d_lo), _p(d_hi),
                                          _p(self.kid_lo), _p(self.kid_hi), _p(self.cen), s))

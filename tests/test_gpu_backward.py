@@ -154,3 +154,25 @@ def test_autograd_function():
     d_lo, d_hi = gpu_grad(n, blo, bhi, np.full(5, -0.5), np.linspace(0.1, 1.0, 5))
     np.testing.assert_allclose(lo.grad.cpu().numpy(), d_lo.astype(np.float32), rtol=1e-6, atol=1e-6)
     np.testing.assert_allclose(hi.grad.cpu().numpy(), d_hi.astype(np.float32), rtol=1e-6, atol=1e-6)
+
+
+def test_one_sided_backward_matches_zero_weights():
+    """IBP_F_UPPER_ONLY (LOWER_ONLY) gives the VJP with g_lo (g_hi) = 0, bit for
+    bit up to the sign of zeros, without reading that weight; box-tiled and
+    per-box paths."""
+    torch = _torch()
+    net, fac, n = setup("c500")
+    blo, bhi = synth.sub_boxes(net, 9, seed=31)
+    tlo, thi = torch.from_numpy(blo).cuda(), torch.from_numpy(bhi).cuda()
+    z = torch.zeros(9, dtype=torch.float64, device="cuda")
+    g = torch.linspace(0.5, 1.5, 9, dtype=torch.float64, device="cuda")
+    for plain in (0, ibp.IBP_F_PLAIN):
+        a_lo, a_hi = ibp.ibp_bound_backward(n, tlo, thi, z, g, flags=plain)
+        b_lo, b_hi = ibp.ibp_bound_backward(n, tlo, thi, None, g, flags=plain | ibp.IBP_F_UPPER_ONLY)
+        c_lo, c_hi = ibp.ibp_bound_backward(n, tlo, thi, g, z, flags=plain)
+        d_lo, d_hi = ibp.ibp_bound_backward(n, tlo, thi, g, None, flags=plain | ibp.IBP_F_LOWER_ONLY)
+        torch.cuda.synchronize()
+        for x, y in ((a_lo, b_lo), (a_hi, b_hi), (c_lo, d_lo), (c_hi, d_hi)):
+            assert torch.equal(x, y), float((x - y).abs().max())
+    with pytest.raises(ValueError):
+        ibp.ibp_bound_backward(n, tlo, thi, None, g)

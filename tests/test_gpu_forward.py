@@ -311,9 +311,6 @@ def test_one_sided_calls(n_box):
     thi = torch.from_numpy(bhi).cuda()
     with pytest.raises(ibp.IBPError):
         ibp.ibp_bound_boxes(n, tlo, thi, flags=ibp.IBP_F_UPPER_ONLY | ibp.IBP_F_LOWER_ONLY)
-    with pytest.raises(ibp.IBPError):
-        ibp.ibp_bound_backward(n, tlo, thi, torch.zeros(n_box, dtype=torch.float64),
-                               torch.ones(n_box, dtype=torch.float64), flags=ibp.IBP_F_UPPER_ONLY)
     c_lo, c_hi = ibp.ibp_crown_bound_boxes(n, tlo, thi)
     cu_lo, cu_hi = ibp.ibp_crown_bound_boxes(n, tlo, thi, flags=ibp.IBP_F_UPPER_ONLY)
     torch.cuda.synchronize()
@@ -329,3 +326,28 @@ def test_read_probe_sums_what_it_streams():
     assert part.numel() == ibp_partials and float(part.sum()) == float(x.numel())
     with pytest.raises(ValueError):
         ibp.ibp_read_probe(x, torch.empty(16, dtype=torch.float32, device="cuda"))
+
+
+def test_three_bus_box_tiled_and_relaxation_paths():
+    """The hand-derived 3-bus box repeated 5 times takes the box-tiled kernels
+    (matrix-core base flows with 3 buses: a partial step of four; relaxation
+    products over one 16-line group) and must give the single-box bounds."""
+    with open(os.path.join(GOLDEN, "three_bus.json")) as f:
+        g = json.load(f)
+    net = {k: (np.asarray(v) if isinstance(v, list) else v) for k, v in g["network"].items()}
+    net["ctg_line"] = None
+    n = ibp.Network(net, device=0)
+    lo = np.repeat(np.asarray(g["box_lo"], np.float32)[None], 5, 0)
+    hi = np.repeat(np.asarray(g["box_hi"], np.float32)[None], 5, 0)
+    f_lo, f_hi = gpu_bounds(n, lo, hi)
+    s_lo, s_hi = gpu_bounds(n, lo[:1], hi[:1])
+    assert np.all(np.abs(f_lo - s_lo[0]) <= 1e-9 * abs(s_lo[0])) and np.all(np.abs(f_hi - s_hi[0]) <= 1e-9 * abs(s_hi[0]))
+    torch = _torch()
+    c_lo, c_hi = ibp.ibp_crown_bound_boxes(n, torch.from_numpy(lo).cuda(), torch.from_numpy(hi).cuda())
+    d_lo, d_hi = ibp.ibp_crown_bound_boxes(n, torch.from_numpy(lo[:1]).cuda(), torch.from_numpy(hi[:1]).cuda())
+    torch.cuda.synchronize()
+    c_hi, d_hi = c_hi.cpu().numpy(), d_hi.cpu().numpy()
+    assert np.all(c_hi <= s_hi[0]) and np.all(np.abs(c_hi - d_hi[0]) <= 1e-9 * max(1.0, abs(d_hi[0])))
+    rc = oracle.crown_upper(net, lo[0].astype(float), hi[0].astype(float), oracle.factors(net))
+    if rc["near"] == 0:
+        assert np.all(c_hi >= rc["f_hi"])
