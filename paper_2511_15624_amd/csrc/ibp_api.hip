@@ -345,6 +345,28 @@ ibp_status check_compute_args(const ibp_network* net, int64_t n_box, const void*
   return IBP_OK;
 }
 
+// Box-tiled calls of more boxes than one launch sequence can take (the outage
+// sweeps put 16 boxes per block along the third grid dimension, at most 65535)
+// run as consecutive chunks on the same stream and workspace.
+constexpr int64_t kTiledChunk = 16 * 65535;
+
+// Calls f(first box, box count, layout) per chunk; the layout of every chunk
+// fits in the workspace the whole call was checked against.
+template <typename F>
+ibp_status for_chunks(const ibp_network* net, int64_t n_box, uint32_t flags, const ibp::WsLayout& lay,
+                      size_t ws_bytes, F f) {
+  if (!lay.batched || n_box <= kTiledChunk) return f(0, n_box, lay);
+  for (int64_t b = 0; b < n_box; b += kTiledChunk) {
+    const int64_t nc = std::min(kTiledChunk, n_box - b);
+    ibp::WsLayout lc = layout(net, nc, flags);
+    lc.sides = lay.sides;
+    if (lc.total > ws_bytes) return fail(IBP_E_WORKSPACE, "workspace too small for a chunk of the call");
+    const ibp_status st = f(b, nc, lc);
+    if (st != IBP_OK) return st;
+  }
+  return IBP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -434,11 +456,14 @@ ibp_status ibp_bound_boxes(const ibp_network* net, int64_t n_box, const float* b
   if (st != IBP_OK || n_box == 0) return st;
   DeviceGuard g(net->device);
   if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
-  hipError_t e = ibp::launch_forward(net->dn, n_box, box_lo, box_hi, f_lo, f_hi, terms, ws, lay,
-                                            static_cast<hipStream_t>(stream),
-                                            const_cast<ibp::KernelTimer*>(&net->timer));
-  if (e != hipSuccess) return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
-  return IBP_OK;
+  const int64_t X = net->dn.X;
+  return for_chunks(net, n_box, flags, lay, ws_bytes, [&](int64_t b, int64_t nc, const ibp::WsLayout& lc) {
+    hipError_t e = ibp::launch_forward(net->dn, nc, box_lo + b * X, box_hi + b * X, f_lo + b, f_hi + b,
+                                       terms ? terms + 8 * b : nullptr, ws, lc, static_cast<hipStream_t>(stream),
+                                       const_cast<ibp::KernelTimer*>(&net->timer));
+    if (e != hipSuccess) return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return IBP_OK;
+  });
 }
 
 ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box, const float* box_lo,
@@ -459,12 +484,19 @@ ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box, const float
   if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
   hipStream_t s = static_cast<hipStream_t>(stream);
   ibp::KernelTimer* tm = const_cast<ibp::KernelTimer*>(&net->timer);
-  hipError_t e = ibp::launch_forward_prep(net->dn, n_box, box_lo, box_hi, ws, lay, s, tm);
-  if (e == hipSuccess)
-    e = ibp::launch_backward_sweeps(net->dn, n_box, ws, lay, box_lo, box_hi, g_f_lo, g_f_hi, g_box_lo, g_box_hi,
-                                    s, tm);
-  if (e != hipSuccess) return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
-  return IBP_OK;
+  const int64_t X = net->dn.X;
+  return for_chunks(net, n_box, flags | IBP_F_BACKWARD, lay, ws_bytes,
+                    [&](int64_t b, int64_t nc, const ibp::WsLayout& lc) {
+                      const float *lo = box_lo + b * X, *hi = box_hi + b * X;
+                      hipError_t e = ibp::launch_forward_prep(net->dn, nc, lo, hi, ws, lc, s, tm);
+                      if (e == hipSuccess)
+                        e = ibp::launch_backward_sweeps(net->dn, nc, ws, lc, lo, hi, g_f_lo ? g_f_lo + b : nullptr,
+                                                        g_f_hi ? g_f_hi + b : nullptr, g_box_lo + b * X,
+                                                        g_box_hi + b * X, s, tm);
+                      if (e != hipSuccess)
+                        return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+                      return IBP_OK;
+                    });
 }
 
 ibp_status ibp_crown_bound_boxes(const ibp_network* net, int64_t n_box, const float* box_lo,
@@ -483,11 +515,16 @@ ibp_status ibp_crown_bound_boxes(const ibp_network* net, int64_t n_box, const fl
   if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
   hipStream_t s = static_cast<hipStream_t>(stream);
   ibp::KernelTimer* tm = const_cast<ibp::KernelTimer*>(&net->timer);
-  hipError_t e = ibp::launch_forward(net->dn, n_box, box_lo, box_hi, f_lo, f_hi, nullptr, ws, lay, s, tm);
-  if (e == hipSuccess)
-    e = ibp::launch_crown(net->dn, n_box, box_lo, box_hi, ref_iters, f_hi, crown_hi, vertex, ws, lay, s, tm);
-  if (e != hipSuccess) return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
-  return IBP_OK;
+  const int64_t X = net->dn.X;
+  return for_chunks(net, n_box, need, lay, ws_bytes, [&](int64_t b, int64_t nc, const ibp::WsLayout& lc) {
+    const float *lo = box_lo + b * X, *hi = box_hi + b * X;
+    hipError_t e = ibp::launch_forward(net->dn, nc, lo, hi, f_lo + b, f_hi + b, nullptr, ws, lc, s, tm);
+    if (e == hipSuccess)
+      e = ibp::launch_crown(net->dn, nc, lo, hi, ref_iters, f_hi + b, crown_hi ? crown_hi + b : nullptr,
+                            vertex ? vertex + b * X : nullptr, ws, lc, s, tm);
+    if (e != hipSuccess) return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return IBP_OK;
+  });
 }
 
 ibp_status ibp_set_kernel_timing(ibp_network* net, int enable) {

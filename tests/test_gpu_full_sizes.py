@@ -14,7 +14,7 @@ import pytest
 import oracle
 from paper_2511_15624_amd import ibp, synth
 from tests.test_gpu_backward import gpu_grad, rel_l2
-from tests.test_gpu_forward import assert_encloses, gpu_bounds, orc, setup
+from tests.test_gpu_forward import _torch, assert_encloses, gpu_bounds, orc, setup
 
 pytestmark = pytest.mark.gpu
 
@@ -66,3 +66,26 @@ def test_c2000_backward_over_4096_boxes():
     for b in idx[:3]:
         o_lo, o_hi, _ = oracle.grad(net, blo[b], bhi[b], 0.0, 1.0, fac)
         assert rel_l2(np.concatenate([d_lo[b], d_hi[b]]), np.concatenate([o_lo, o_hi])) <= 1e-3, b
+
+
+def test_more_boxes_than_one_tiled_launch():
+    """16 x 65535 + 37 boxes: the box-tiled path runs as two chunks; every box
+    gets exactly what the same box gets in a small call (forward and backward)."""
+    torch = _torch()
+    net, fac, n = setup("tiny")
+    blo, bhi = synth.sub_boxes(net, 23, seed=9)
+    nb = 16 * 65535 + 37
+    idx = np.arange(nb) % 23
+    lo, hi = blo[idx], bhi[idx]
+    f_lo, f_hi = gpu_bounds(n, lo, hi)
+    s_lo, s_hi = gpu_bounds(n, blo, bhi)
+    assert np.array_equal(f_lo, s_lo[idx]) and np.array_equal(f_hi, s_hi[idx])
+    tlo, thi = torch.from_numpy(lo).cuda(), torch.from_numpy(hi).cuda()
+    g1 = torch.ones(nb, dtype=torch.float64, device="cuda")
+    d_lo, d_hi = ibp.ibp_bound_backward(n, tlo, thi, None, g1, flags=ibp.IBP_F_UPPER_ONLY)
+    e_lo, e_hi = ibp.ibp_bound_backward(n, tlo[:23], thi[:23], None, g1[:23], flags=ibp.IBP_F_UPPER_ONLY)
+    torch.cuda.synchronize()
+    t = torch.from_numpy(idx).cuda()
+    assert torch.equal(d_lo, e_lo[t]) and torch.equal(d_hi, e_hi[t])
+    del tlo, thi, d_lo, d_hi
+    torch.cuda.empty_cache()
