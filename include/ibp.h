@@ -140,9 +140,9 @@ void ibp_free_network(ibp_network* net);
 #define IBP_F_BACKWARD 4u /* workspace query only: size for ibp_bound_backward (includes the forward's) */
 #define IBP_F_CROWN 8u    /* workspace query only: size for ibp_crown_bound_boxes (includes the forward's) */
 #define IBP_F_CROWN_REF 16u /* workspace query only: ibp_crown_bound_boxes with ref_iters > 0 */
-/* One-sided calls of ibp_bound_boxes / ibp_crown_bound_boxes, for callers that
- * use one bound only (branch and bound bounds children from above and
- * evaluates points from below).  The box-tiled outage sweep then computes only
+/* One-sided calls of ibp_bound_boxes / ibp_crown_bound_boxes (and of
+ * ibp_bound_backward, see there), for callers that use one bound only (branch
+ * and bound bounds children from above and evaluates points from below).  The box-tiled outage sweep then computes only
  * the penalty side that bound needs (about half its arithmetic).  The other
  * output stays a valid bound: with IBP_F_UPPER_ONLY f_lo is -INFINITY (terms:
  * Fc_hi = +INFINITY); with IBP_F_LOWER_ONLY the outage penalties' lower bound
