@@ -486,9 +486,9 @@ def main(argv=None):
     if any(status):
         ibp._check(next(st for st in status if st))
     ms_total = e0.elapsed_time(e1)
-    # kernel pass: the same steps again with the library recording a HIP event
-    # pair around every kernel it queues on this stream (the events add gaps
-    # between kernels, so the step time above is taken without them)
+    # kernel pass: the same steps again with the library timing every kernel it
+    # queues on this stream (HIP events recorded by the dispatches of the
+    # single-box kernels themselves; the step time above is taken without them)
     n.set_kernel_timing(True)
     _ = n.kernel_times()
     for _ in range(args.steps):

@@ -225,8 +225,10 @@ ibp_status ibp_crown_bound_boxes(const ibp_network* net, int64_t n_box,
                                  void* ws, size_t ws_bytes, void* stream, uint32_t flags);
 
 /* Kernel timing for benchmarks and profiling.  While enabled, every compute
- * call on `net` records a HIP event pair around each kernel it queues, on the
- * call's stream.  ibp_kernel_times() waits for those events and returns, per
+ * call on `net` records a HIP event pair for each kernel it queues, on the
+ * call's stream (for the single-box forward kernels the events are recorded by
+ * the dispatch itself, so they time the kernel alone; elsewhere they are queued
+ * around it).  ibp_kernel_times() waits for those events and returns, per
  * kernel id, the summed milliseconds and the number of launches since the last
  * read (then clears them).  Kernel ids: 0 box preparation, 1 base flows,
  * 2 outage sweep, 3 finalize, 4 line epilogue, 5 batched base flows,

@@ -624,14 +624,16 @@ void plan_single(const DevNet& net, int64_t n_box, WsLayout& lay, const Tune& t)
 }
 
 template <int NC>
-static void launch_k2(const DevNet& net, void* ws, const WsLayout& lay, int64_t b0, int nb, hipStream_t s) {
-  hipLaunchKernelGGL(k2_base_flows<NC>, dim3(lay.k2_bx, lay.k2_by, nb), dim3(256), 0, s, net, ws, lay, b0,
-                     reinterpret_cast<const double2*>(static_cast<char*>(ws) + lay.inj));
+static void launch_k2(const DevNet& net, void* ws, const WsLayout& lay, int64_t b0, int nb, hipStream_t s,
+                      KernelTimer* tm) {
+  tm->launch(1, k2_base_flows<NC>, dim3(lay.k2_bx, lay.k2_by, nb), dim3(256), s, net, ws, lay, b0,
+             reinterpret_cast<const double2*>(static_cast<char*>(ws) + lay.inj));
 }
 
 template <int KC>
-static void launch_k3(const DevNet& net, void* ws, const WsLayout& lay, int64_t b0, int nb, hipStream_t s) {
-  hipLaunchKernelGGL(k3_contingency<KC>, dim3(lay.k3_bx, lay.k3_by, nb), dim3(256), 0, s, net, ws, lay, b0);
+static void launch_k3(const DevNet& net, void* ws, const WsLayout& lay, int64_t b0, int nb, hipStream_t s,
+                      KernelTimer* tm) {
+  tm->launch(2, k3_contingency<KC>, dim3(lay.k3_bx, lay.k3_by, nb), dim3(256), s, net, ws, lay, b0);
 }
 
 hipError_t launch_forward_single(const DevNet& net, int64_t n_box, const float* lo, const float* hi,
@@ -639,34 +641,24 @@ hipError_t launch_forward_single(const DevNet& net, int64_t n_box, const float* 
                                  const WsLayout& lay, hipStream_t s, KernelTimer* tm) {
   for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
     const int nb = (int)std::min<int64_t>(65535, n_box - b0);
-    int t = tm->start(0, s);
-    hipLaunchKernelGGL(k1_box_prep, dim3(lay.n_p1, nb), dim3(64), 0, s, net, lo, hi, ws, lay, b0);
-    tm->stop(t, s);
-    t = tm->start(1, s);
+    tm->launch(0, k1_box_prep, dim3(lay.n_p1, nb), dim3(64), s, net, lo, hi, ws, lay, b0);
     switch (lay.k2_nc) {
-      case 32: launch_k2<32>(net, ws, lay, b0, nb, s); break;
-      case 64: launch_k2<64>(net, ws, lay, b0, nb, s); break;
-      case 256: launch_k2<256>(net, ws, lay, b0, nb, s); break;
-      default: launch_k2<128>(net, ws, lay, b0, nb, s); break;
+      case 32: launch_k2<32>(net, ws, lay, b0, nb, s, tm); break;
+      case 64: launch_k2<64>(net, ws, lay, b0, nb, s, tm); break;
+      case 256: launch_k2<256>(net, ws, lay, b0, nb, s, tm); break;
+      default: launch_k2<128>(net, ws, lay, b0, nb, s, tm); break;
     }
-    tm->stop(t, s);
-    t = tm->start(4, s);
-    hipLaunchKernelGGL(k2e_lines, dim3((net.L + kK2eThreads - 1) / kK2eThreads, nb), dim3(kK2eThreads), 0, s,
-                       net, ws, lay, b0);
-    tm->stop(t, s);
+    tm->launch(4, k2e_lines, dim3((net.L + kK2eThreads - 1) / kK2eThreads, nb), dim3(kK2eThreads), s, net, ws,
+               lay, b0);
     if (net.K > 0) {
-      t = tm->start(2, s);
       switch (lay.k3_kc) {
-        case 32: launch_k3<32>(net, ws, lay, b0, nb, s); break;
-        case 64: launch_k3<64>(net, ws, lay, b0, nb, s); break;
-        case 128: launch_k3<128>(net, ws, lay, b0, nb, s); break;
-        default: launch_k3<16>(net, ws, lay, b0, nb, s); break;
+        case 32: launch_k3<32>(net, ws, lay, b0, nb, s, tm); break;
+        case 64: launch_k3<64>(net, ws, lay, b0, nb, s, tm); break;
+        case 128: launch_k3<128>(net, ws, lay, b0, nb, s, tm); break;
+        default: launch_k3<16>(net, ws, lay, b0, nb, s, tm); break;
       }
-      tm->stop(t, s);
     }
-    t = tm->start(3, s);
-    launch_k4(net, ws, lay, b0, nb, f_lo, f_hi, terms, s);
-    tm->stop(t, s);
+    tm->launch(3, k4_finalize<256>, dim3(nb), dim3(256), s, net, ws, lay, b0, f_lo, f_hi, terms);
   }
   return hipGetLastError();
 }
@@ -684,14 +676,12 @@ hipError_t launch_forward_prep(const DevNet& net, int64_t n_box, const float* lo
   } else {
     for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
       const int nb = (int)std::min<int64_t>(65535, n_box - b0);
-      const int t = tm->start(1, s);
       switch (lay.k2_nc) {
-        case 32: launch_k2<32>(net, ws, lay, b0, nb, s); break;
-        case 64: launch_k2<64>(net, ws, lay, b0, nb, s); break;
-        case 256: launch_k2<256>(net, ws, lay, b0, nb, s); break;
-        default: launch_k2<128>(net, ws, lay, b0, nb, s); break;
+        case 32: launch_k2<32>(net, ws, lay, b0, nb, s, tm); break;
+        case 64: launch_k2<64>(net, ws, lay, b0, nb, s, tm); break;
+        case 256: launch_k2<256>(net, ws, lay, b0, nb, s, tm); break;
+        default: launch_k2<128>(net, ws, lay, b0, nb, s, tm); break;
       }
-      tm->stop(t, s);
     }
   }
   for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {

@@ -1,6 +1,7 @@
 // Launchers of the HIP kernels (defined in the .hip sources).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -31,6 +32,16 @@ struct KernelTimer {
   }
   void stop(int idx, hipStream_t s) {
     if (idx >= 0) (void)hipEventRecord(recs[idx].b, s);
+  }
+  // Launches `kernel`; while timing is enabled the start and end are recorded
+  // by the dispatch itself (no event packets queued around it, so the
+  // duration is the kernel's own).
+  template <typename K, typename... A>
+  void launch(int id, K kernel, dim3 grid, dim3 block, hipStream_t s, A... args) {
+    Rec r{id, nullptr, nullptr};
+    if (enabled && (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess)) r.a = r.b = nullptr;
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, r.a, r.b, 0, args...);
+    if (r.a && r.b) recs.push_back(r);
   }
 };
 
