@@ -107,12 +107,37 @@ __device__ __forceinline__ void halving_sum24(double (&v)[24]) {
   for (int i = 0; i < 3; ++i) v[i] += lane_xor<kDppXor1>(v[i]);
 }
 
+// The same reduction for float32 values (the relaxation's per-outage sums:
+// the KC2 error term covers their float32 rounding).
+__device__ __forceinline__ void halving_sum24(float (&v)[24]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) v[i] = halve32(v[i], v[i + 12]);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) v[i] = halve16(v[i], v[i + 6]);
+  {
+    const bool up = lane & 8;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const float send = up ? v[i] : v[i + 3];
+      const float keep = up ? v[i + 3] : v[i];
+      v[i] = keep + lane_xor<kDppXor8>(send);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) v[i] += __shfl_xor(v[i], 4, 64);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) v[i] += lane_xor<kDppXor2>(v[i]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) v[i] += lane_xor<kDppXor1>(v[i]);
+}
+
 // Slopes of four lines x one outage; per-line counts in registers, the
 // outage's three sums (s Lam, |s Lam|, count) into r[0..2].
 // REF: c4 holds the line flows at the reference point and g4 the limits.
 template <bool REF>
 __device__ __forceinline__ void kc1_row(const float4& x, const int4& d, const float4& c4, const float4& g4,
-                                        float (&cs)[4], float (&ca)[4], double* r) {
+                                        float (&cs)[4], float (&ca)[4], float* r) {
   const float cc = __int_as_float(d.y), rk = __int_as_float(d.z);
   float s[4];
   if (REF) {
@@ -128,8 +153,9 @@ __device__ __forceinline__ void kc1_row(const float4& x, const int4& d, const fl
   }
   // s Lam is exact in float32; NaN entries carry s = 0 and a finite stand-in
   const float l[4] = {fminf(x.x, FLT_MAX), fminf(x.y, FLT_MAX), fminf(x.z, FLT_MAX), fminf(x.w, FLT_MAX)};
-  // the four exact products are summed in float32 (error <= 3u of their
-  // absolute sum, covered in KC2) before the float64 reduction
+  // the four exact products are summed in float32, and so is the halving
+  // reduction over the wave's 64 lanes: nine rounding levels, at most 9u of
+  // the absolute sum (covered in KC2)
   float v = 0.0f, a = 0.0f, n = 0.0f;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -139,9 +165,9 @@ __device__ __forceinline__ void kc1_row(const float4& x, const int4& d, const fl
     v += s[i] * l[i];
     a += fabsf(s[i] * l[i]);
   }
-  r[0] = (double)v;
-  r[1] = (double)a;
-  r[2] = (double)n;
+  r[0] = v;
+  r[1] = a;
+  r[2] = n;
 }
 
 // wsr: the reference points' forward workspace (REF), else unused.
@@ -177,9 +203,9 @@ __global__ __launch_bounds__(256) void kc1_sweep(DevNet net, void* ws, const voi
   float cs[4] = {0.f, 0.f, 0.f, 0.f}, ca[4] = {0.f, 0.f, 0.f, 0.f};
   // groups of eight outages: eight rows in flight, then one halving reduction
   for (int kg = k0; kg < k1; kg += 8) {
-    double r[24];
+    float r[24];
 #pragma unroll
-    for (int i = 0; i < 24; ++i) r[i] = 0.0;
+    for (int i = 0; i < 24; ++i) r[i] = 0.0f;
     if (live) {
       float4 x[8];
 #pragma unroll
@@ -192,7 +218,7 @@ __global__ __launch_bounds__(256) void kc1_sweep(DevNet net, void* ws, const voi
     // a wave with no active element in the group skips the reduction
     bool act = false;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) act |= r[3 * i + 2] != 0.0;
+    for (int i = 0; i < 8; ++i) act |= r[3 * i + 2] != 0.0f;
     if (__any(act)) {
       halving_sum24(r);
     }
@@ -258,11 +284,12 @@ __global__ __launch_bounds__(256) void kc2_lines(DevNet net, void* ws, const voi
         A += q.y;
         N += q.z;
       }
-      // float32 sums of four exact products per lane (<= 3u of their absolute
-      // sum), float64 sums over the rest (L + tiles terms); stored-factor errors
+      // float32 sums of exact products within a wave (four per lane, then
+      // six halving levels: <= 9u of their absolute sum), float64 sums over
+      // waves and tiles; stored-factor errors
       const double gam = (net.Lp + lay.kc_bx + 16) * kU64 * 1.01;
-      const double A1 = A * (1.0 + gam) * (1.0 + kKappa0) * (1.0 + 4.0 * kU32);
-      ev = (kKappa0 + net.ctg_eps[k] + gam + 4.0 * kU32) * A1 + 2.0 * net.phi_err_max * net.ctg_inv[k] * N;
+      const double A1 = A * (1.0 + gam) * (1.0 + kKappa0) * (1.0 + 10.0 * kU32);
+      ev = (kKappa0 + net.ctg_eps[k] + gam + 10.0 * kU32) * A1 + 2.0 * net.phi_err_max * net.ctg_inv[k] * N;
       v += V;
       va += A1 + ev;
     }
@@ -498,9 +525,9 @@ __global__ __launch_bounds__(256) void kc1b_sweep(DevNet net, void* ws, const vo
     for (int j = 0; j < 4; ++j) cs[i][j] = ca[i][j] = 0.0f;
   // pairs of outages: 2 outages x 4 boxes x 3 sums in one halving reduction
   for (int kg = k0; kg < k1; kg += 2) {
-    double r[24];
+    float r[24];
 #pragma unroll
-    for (int i = 0; i < 24; ++i) r[i] = 0.0;
+    for (int i = 0; i < 24; ++i) r[i] = 0.0f;
     if (live) {
       float4 x[2];
 #pragma unroll
@@ -515,7 +542,7 @@ __global__ __launch_bounds__(256) void kc1b_sweep(DevNet net, void* ws, const vo
     }
     bool act = false;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) act |= r[3 * i + 2] != 0.0;
+    for (int i = 0; i < 8; ++i) act |= r[3 * i + 2] != 0.0f;
     if (__any(act)) halving_sum24(r);
     // lane 8g holds outage kg + g / 4 of box g % 4
     if ((lane & 7) == 0) {
