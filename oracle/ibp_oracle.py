@@ -37,6 +37,9 @@ DCOPF via Interval Bound Propagation", Tekeler, Chevalier, Zhong, Zhang):
   each convex penalty replaced by a global linear minorant whose slope comes
   from its IBP pre-activation interval, then the exact maximum of the
   resulting linear function over the box.
+* Its counterpart for the lower bound (``crown_lower``): each penalty replaced
+  by its chord over the IBP pre-activation interval (a linear majorant there),
+  then the exact minimum of the resulting linear function over the box.
 
 Readings taken where the paper is silent:
 
@@ -84,6 +87,7 @@ __all__ = [
     "curve_interval",
     "crown_upper",
     "crown_upper_iterated",
+    "crown_lower",
 ]
 
 
@@ -672,6 +676,106 @@ def crown_upper(net, lo, hi, fac=None, chunk: int = 256, near_rel: float = 1e-5,
     f_hi = c0 + math.fsum(G * mu) + math.fsum(np.abs(G) * sg) + P_hi
     vertex = np.where(G >= 0, np.asarray(hi, np.float64), np.asarray(lo, np.float64))
     return dict(f_hi=f_hi, n_active=n_active, near=near, G=G, const=c0, vertex=vertex)
+
+
+def _chord(c, r, t):
+    """Chord of phi(z) = max(|z| - t, 0) over [c - r, c + r]: slope a and
+    intercept b of the line through (z_lo, phi(z_lo)) and (z_hi, phi(z_hi)).
+    phi is convex, so the chord lies above it on the whole interval.  A
+    zero-width interval gets a = 0, b = phi(c)."""
+    zl, zu = c - r, c + r
+    pl = np.maximum(np.abs(zl) - t, 0.0)
+    pu = np.maximum(np.abs(zu) - t, 0.0)
+    w = zu - zl
+    pos = w > 0
+    a = np.where(pos, (pu - pl) / np.where(pos, w, 1.0), 0.0)
+    b = np.where(pos, pl - a * zl, pl)
+    return a, b
+
+
+def crown_lower(net, lo, hi, fac=None, chunk: int = 256, keep_slopes: bool = False) -> dict:
+    """Lower bound on min f over the box from linear relaxations of the
+    penalties (the convex-relaxation family the paper cites beside IBP, Sec. I),
+    the counterpart of ``crown_upper`` for f_lo.
+
+    Every penalty phi(z) = max(|z| - t, 0) (and the imbalance |z|, t = 0) is
+    convex, so on its IBP pre-activation interval [C - R, C + R] (the same
+    centre-radius intervals ``ibp`` forms, exact for these affine nodes) it
+    lies below its chord a z + b.  Hence f(x) >= S(x) - zeta_inj (a_I z_I(x) +
+    b_I) - zeta_f sum_e (a_e z_e(x) + b_e) for every x in the box; the right
+    side is linear in x (plus the curve part) and its minimum over the box is
+    exact: sum_j (G_j c_j - |G_j| r_j) + const, with the curve part through its
+    IBP interval.  Because the minimum of a sum is at least the sum of the
+    minima and each chord's maximum over its interval is IBP's upper penalty,
+    the bound is never below IBP's f_lo.
+
+    Returns ``f_lo``, ``G`` (coefficients of x), ``const``, ``n_active``
+    (elements with a non-zero slope) and ``vertex`` (lo_j where G_j >= 0, else
+    hi_j: the minimiser of the linear part).  With ``keep_slopes`` also the
+    slopes and intercepts: ``chord_imb`` (a_I, b_I), ``chord_base`` (a, b per
+    line) and ``chord_ctg`` (a, b as K x L arrays; the outaged line's own entry
+    is 0).
+    """
+    if fac is None:
+        fac = factors(net)
+    mu, sg = center_radius(lo, hi)
+    W = _injection_map(net)
+    c_inj = W @ mu
+    r_inj = abs(W) @ sg
+    zi, zf = float(net["zeta_inj"]), float(net["zeta_f"])
+    w = np.concatenate([-np.asarray(net["gen_cost"], float), np.asarray(net["load_value"], float)])
+    out = {}
+    # imbalance 1^T |(E^T Phi - I) p_inj| <= a_I z_I + b_I
+    W2 = _imbalance_matrix(net)
+    cz = W2 @ c_inj
+    rz = abs(W2) @ r_inj
+    a_I, b_I = _chord(cz, rz, 0.0)
+    const = [-zi * math.fsum(b_I)]
+    # base lines
+    Phi = fac["Phi"]
+    c_f = Phi @ c_inj
+    r_f = np.abs(Phi) @ r_inj
+    fb = np.asarray(net["fmax_base"], float)
+    a_b, b_b = _chord(c_f, r_f, fb)
+    const.append(-zf * math.fsum(b_b))
+    n_active = int(np.count_nonzero(a_b))
+    # contingency elements, paper form z = M f - B (U p)
+    U, Bm, M = fac["U"], fac["B"], fac["M"]
+    c_u = U @ c_inj
+    r_u = np.abs(U) @ r_inj
+    fc = np.asarray(net["fmax_ctg"], float)
+    K = fac["K"]
+    v_f = a_b.copy()
+    v_u = np.zeros(K)
+    if keep_slopes:
+        A_all = np.zeros((K, Phi.shape[0]))
+        B_all = np.zeros((K, Phi.shape[0]))
+    for k0 in range(0, K, chunk):
+        k1 = min(K, k0 + chunk)
+        Mk, Bk = M[k0:k1], Bm[k0:k1]
+        Cc = Mk * c_f[None, :] - Bk * c_u[k0:k1, None]
+        Rc = np.abs(Mk) * r_f[None, :] + np.abs(Bk) * r_u[k0:k1, None]
+        a, b = _chord(Cc, Rc, fc[None, :])
+        keep = Mk != 0              # the outaged line's own entry carries no penalty
+        a = a * keep
+        b = b * keep
+        n_active += int(np.count_nonzero(a))
+        const.append(-zf * _fsum_pairwise(b))
+        v_f += np.sum(Mk * a, axis=0)
+        v_u[k0:k1] = -np.sum(Bk * a, axis=1)
+        if keep_slopes:
+            A_all[k0:k1] = a
+            B_all[k0:k1] = b
+    # coefficient of x in the relaxed objective: surplus - zeta_inj a_I z_I - zeta_f sum a z
+    G = w - zi * (W.T @ (W2.T @ a_I)) - zf * (W.T @ (Phi.T @ v_f + U.T @ v_u))
+    P_lo, _ = _curve_surplus(net, mu, sg)
+    c0 = math.fsum(const)
+    f_lo = c0 + math.fsum(G * mu) - math.fsum(np.abs(G) * sg) + P_lo
+    vertex = np.where(G >= 0, np.asarray(lo, np.float64), np.asarray(hi, np.float64))
+    out.update(f_lo=f_lo, G=G, const=c0, n_active=n_active, vertex=vertex)
+    if keep_slopes:
+        out.update(chord_imb=(a_I, b_I), chord_base=(a_b, b_b), chord_ctg=(A_all, B_all))
+    return out
 
 
 def crown_upper_iterated(net, lo, hi, fac=None, iters: int = 4, near_rel: float = 1e-5) -> dict:
