@@ -224,6 +224,34 @@ ibp_status ibp_crown_bound_boxes(const ibp_network* net, int64_t n_box,
                                  double* f_lo, double* f_hi, double* crown_hi, float* vertex,
                                  void* ws, size_t ws_bytes, void* stream, uint32_t flags);
 
+/* ibp_crown_lower_boxes -- IBP bounds with f_lo tightened by a linear
+ * relaxation of the penalties (the CROWN family of convex relaxations the
+ * paper cites beside IBP, Sec. I), the counterpart of ibp_crown_bound_boxes
+ * for the lower bound.  Every penalty max(|z| - t, 0) and the imbalance |z| is
+ * convex, so on the IBP interval of its pre-activation it lies below its chord;
+ * with these lines the objective is bounded below by a linear function of the
+ * inputs (plus the interval of any piecewise-linear curves) whose exact
+ * minimum over the box is computed with outward rounding.  Chord slopes are
+ * rounded to multiples of 2^-24 (any slope gives a valid line; the intercept
+ * is formed for the rounded slope).  In exact arithmetic the relaxation is
+ * never below IBP's f_lo; the call keeps the larger of the two.
+ *   f_lo, f_hi : device float64 [n_box]: max(IBP f_lo, relaxation bound), and
+ *                IBP's f_hi -- both certified.
+ *   crown_lo   : device float64 [n_box] or NULL: the relaxation bound alone.
+ *   vertex     : device float32 [n_box x X] or NULL: the box vertex that
+ *                minimises the relaxation's linear part (lo_j where its
+ *                coefficient is >= 0, else hi_j), a candidate point for upper
+ *                bounds on min f.
+ *   ws, ws_bytes: at least ibp_workspace_bytes(net, n_box, flags | IBP_F_CROWN).
+ * flags: 0, IBP_F_PLAIN, IBP_F_LOWER_ONLY (forward kernels as in
+ * ibp_bound_boxes; with LOWER_ONLY f_hi is the one-sided call's).  Invalid
+ * boxes get NaN.
+ * Errors: INVALID_ARG, WORKSPACE, HOST_ONLY, DEVICE. */
+ibp_status ibp_crown_lower_boxes(const ibp_network* net, int64_t n_box,
+                                 const float* box_lo, const float* box_hi,
+                                 double* f_lo, double* f_hi, double* crown_lo, float* vertex,
+                                 void* ws, size_t ws_bytes, void* stream, uint32_t flags);
+
 /* Kernel timing for benchmarks and profiling.  While enabled, every compute
  * call on `net` records a HIP event pair for each kernel it queues, on the
  * call's stream (for the single-box forward kernels the events are recorded by

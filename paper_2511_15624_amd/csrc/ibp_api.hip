@@ -277,12 +277,12 @@ ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
       off = align256(off + bytes);
       return o;
     };
-    lay.ccnt = take(B * d.Lp * 2 * sizeof(int));
+    lay.ccnt = take(B * d.Lp * 2 * sizeof(long long));  // int2 counts, or int64 slope totals
     lay.cv = take(B * lay.kc_bx * std::max(1, d.K) * 4 * sizeof(double));
     lay.lv = take(B * d.Lp * 4 * sizeof(double));
     lay.bpart = take(B * lay.kc3_bx * d.Np * 4 * sizeof(double));
     lay.cp = take(B * lay.n_cp * 2 * sizeof(double));
-    lay.ct = take(B * lay.n_ct * 2 * sizeof(double));
+    lay.ct = take(B * lay.n_ct * 4 * sizeof(double));
     if (flags & IBP_F_CROWN_REF) {
       lay.ref = take(lay.fwd_total);
       lay.xref = take(B * d.X * sizeof(float));
@@ -522,6 +522,33 @@ ibp_status ibp_crown_bound_boxes(const ibp_network* net, int64_t n_box, const fl
     if (e == hipSuccess)
       e = ibp::launch_crown(net->dn, nc, lo, hi, ref_iters, f_hi + b, crown_hi ? crown_hi + b : nullptr,
                             vertex ? vertex + b * X : nullptr, ws, lc, s, tm);
+    if (e != hipSuccess) return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return IBP_OK;
+  });
+}
+
+ibp_status ibp_crown_lower_boxes(const ibp_network* net, int64_t n_box, const float* box_lo,
+                                 const float* box_hi, double* f_lo, double* f_hi, double* crown_lo, float* vertex,
+                                 void* ws, size_t ws_bytes, void* stream, uint32_t flags) {
+  g_err.clear();
+  if (flags & ~uint32_t(IBP_F_PLAIN | IBP_F_LOWER_ONLY))
+    return fail(IBP_E_INVALID_ARG, "flags: only IBP_F_PLAIN and IBP_F_LOWER_ONLY are accepted");
+  ibp::WsLayout lay;
+  const uint32_t need = flags | IBP_F_CROWN;
+  ibp_status st = check_compute_args(net, n_box, box_lo, box_hi, f_lo, f_hi, ws, ws_bytes, need, lay);
+  if (st != IBP_OK) return st;
+  if (n_box == 0) return IBP_OK;
+  DeviceGuard g(net->device);
+  if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ibp::KernelTimer* tm = const_cast<ibp::KernelTimer*>(&net->timer);
+  const int64_t X = net->dn.X;
+  return for_chunks(net, n_box, need, lay, ws_bytes, [&](int64_t b, int64_t nc, const ibp::WsLayout& lc) {
+    const float *lo = box_lo + b * X, *hi = box_hi + b * X;
+    hipError_t e = ibp::launch_forward(net->dn, nc, lo, hi, f_lo + b, f_hi + b, nullptr, ws, lc, s, tm);
+    if (e == hipSuccess)
+      e = ibp::launch_crown_lower(net->dn, nc, lo, hi, f_lo + b, crown_lo ? crown_lo + b : nullptr,
+                                  vertex ? vertex + b * X : nullptr, ws, lc, s, tm);
     if (e != hipSuccess) return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
     return IBP_OK;
   });

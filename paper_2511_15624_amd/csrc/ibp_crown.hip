@@ -300,7 +300,7 @@ __global__ __launch_bounds__(256) void kc2_lines(DevNet net, void* ws, const voi
   if (l < net.Lp) ws_ptr<double4>(ws, lay.lv)[b * net.Lp + l] = make_double4(v, va, ev, 0.0);
   T = block_sum256(T, sh);
   const double S = block_sum256(va, sh);
-  if (threadIdx.x == 0) ws_ptr<double2>(ws, lay.ct)[b * lay.n_ct + blockIdx.x] = make_double2(T, S);
+  if (threadIdx.x == 0) ws_ptr<double4>(ws, lay.ct)[b * lay.n_ct + blockIdx.x] = make_double4(T, S, 0.0, 0.0);
 }
 
 // Per bus n: y = sum_l Phi32[l, n] v_l, ya = sum_l |Phi32| vabs_l,
@@ -367,8 +367,33 @@ __global__ __launch_bounds__(256) void kc3_ptdf_t(DevNet net, void* ws, WsLayout
   }
 }
 
+// Chord of |z| over the total-injection interval [cI - rI - eI, cI + rI + eI]
+// (float64, outward): slope a (sign of cI times alpha in [0, 1]) and an upper
+// bound beta of the line's value at z = 0, so that |z| <= a z + beta on the
+// interval.  With y = sign(cI) z the interval is [tl, th]; |y| at its two ends
+// is th and |tl|, and alpha is the chord slope between them.
+__device__ __forceinline__ void chord_imbalance(double cI, double rI, double eI, double& a, double& beta) {
+  const double w = fabs(cI) + rI + eI;
+  const double th = w * (1.0 + 4.0 * kU64);
+  const double tl = (fabs(cI) - rI - eI) - 4.0 * kU64 * w;
+  a = 0.0;
+  beta = 0.0;
+  if (th > 0.0) {
+    const double ql = fabs(tl);
+    const double al = fmin(fmax((th - ql) / (th - tl), 0.0), 1.0);
+    const double bb = fmax(fma(-al, th, th), fma(-al, tl, ql));
+    beta = bb + 4.0 * kU64 * (fabs(bb) + th + fabs(tl));
+    a = copysign(al, cI);
+  }
+}
+
 // Per input: coefficient G_j, its error bound E_j, and max over [lo_j, hi_j] of
 // G_j x_j (plus the curve interval's upper end); block partials (sum, sum |.|).
+// LOW: the chord relaxation's lower bound instead: min over [lo_j, hi_j] of
+// G_j x_j (minus E_j |x_j|, plus the curve interval's lower end), the
+// imbalance slope from its chord, whose intercept block 0 adds once per box;
+// the vertex is the minimiser.
+template <bool LOW>
 __global__ __launch_bounds__(256) void kc4_inputs(DevNet net, void* ws, const void* wsr, WsLayout lay,
                                                   int64_t box0,
                                                   const float* __restrict__ box_lo,
@@ -379,15 +404,25 @@ __global__ __launch_bounds__(256) void kc4_inputs(DevNet net, void* ws, const vo
   const int j = blockIdx.x * 256 + threadIdx.x;
   // imbalance slope: from the total injection interval, or at the reference point
   const double* p1 = ws_ptr<double>(wsr ? const_cast<void*>(wsr) : ws, lay.p1) + b * lay.n_p1 * kP1Fields;
-  double cI = 0.0, rI = 0.0;
+  double cI = 0.0, rI = 0.0, aI = 0.0;
   for (int q = threadIdx.x; q < lay.n_p1; q += 256) {
     cI += p1[q * kP1Fields + kP1cI];
     rI += p1[q * kP1Fields + kP1rI];
+    if (LOW) aI += p1[q * kP1Fields + kP1cIabs];
   }
   cI = block_sum256(cI, sh);
   rI = block_sum256(rI, sh);  // zero at a reference point
+  double sI, bI = 0.0;
+  if (LOW) {
+    // float64 sums of n_p1 partials of n_p1 terms each: the same enclosure as K4's
+    aI = block_sum256(aI, sh);
+    const double eI = 2.0 * (lay.n_p1 + 16) * kU64 * 1.01 * (aI + rI);
+    chord_imbalance(cI, rI, eI, sI, bI);
+  } else {
+    sI = (fabs(cI) - rI > 0.0) ? copysign(1.0, cI) : 0.0;
+  }
   double SV = 0.0;
-  for (int q = threadIdx.x; q < lay.n_ct; q += 256) SV += ws_ptr<double2>(ws, lay.ct)[b * lay.n_ct + q].y;
+  for (int q = threadIdx.x; q < lay.n_ct; q += 256) SV += ws_ptr<double4>(ws, lay.ct)[b * lay.n_ct + q].y;
   SV = block_sum256(SV, sh) * (1.0 + (lay.n_ct + 16) * kU64 * 1.01);
   double h = 0.0, ha = 0.0;
   if (j < net.X) {
@@ -405,7 +440,6 @@ __global__ __launch_bounds__(256) void kc4_inputs(DevNet net, void* ws, const vo
     ya *= (1.0 + gam);
     ye *= (1.0 + gam);
     const double sj = j < net.G ? 1.0 : -1.0;
-    const double sI = (fabs(cI) - rI > 0.0) ? copysign(1.0, cI) : 0.0;
     const double wj = net.dev_w[j], zi = net.zeta_inj, zf = net.zeta_f;
     const double G = wj - zi * sI * sj - zf * sj * y;
     // |y^ - (Phi_exact^T v_exact)_n| <= (kappa0 + gam) ya + (1 + kappa0) ye + 2 eps_max sum vabs
@@ -413,23 +447,34 @@ __global__ __launch_bounds__(256) void kc4_inputs(DevNet net, void* ws, const vo
                          (1.0 + 8.0 * kU64) +
                      4.0 * kU64 * (fabs(wj) + zi + zf * fabs(y));
     const float l32 = box_lo[b * net.X + j], h32 = box_hi[b * net.X + j];
-    if (vertex) vertex[b * net.X + j] = G >= 0.0 ? h32 : l32;
+    if (vertex) vertex[b * net.X + j] = (G >= 0.0) != LOW ? h32 : l32;
     const double l = l32, hh = h32;
     const double c = 0.5 * (l + hh), r = 0.5 * (hh - l);
     const double m = fabs(c) + r;
-    h = G * c + fabs(G) * r + E * m;
     ha = fabs(G) * m + E * m;
-    h += 4.0 * kU64 * ha;
+    if (LOW) {
+      h = G * c - fabs(G) * r - E * m;
+      h -= 4.0 * kU64 * ha;
+    } else {
+      h = G * c + fabs(G) * r + E * m;
+      h += 4.0 * kU64 * ha;
+    }
     if (net.seg_ptr) {
       const int s0 = net.seg_ptr[j], s1 = net.seg_ptr[j + 1];
       if (s1 > s0) {
         double F_lo, F_hi, e;
         curve_ibp(net.seg, s0, s1, c, r, F_lo, F_hi, e);
-        const double u = (j < net.G ? -F_lo : F_hi) + e + kU64 * (fabs(F_lo) + fabs(F_hi));
+        const double pad = e + kU64 * (fabs(F_lo) + fabs(F_hi));
+        const double u = LOW ? (j < net.G ? -F_hi : F_lo) - pad : (j < net.G ? -F_lo : F_hi) + pad;
         h += u;
         ha += fabs(u);
       }
     }
+  }
+  if (LOW && blockIdx.x == 0 && threadIdx.x == 0) {
+    // the imbalance line's intercept: -zeta_inj beta
+    h -= net.zeta_inj * bI;
+    ha += net.zeta_inj * fabs(bI);
   }
   h = block_sum256(h, sh);
   ha = block_sum256(ha, sh);
@@ -448,7 +493,7 @@ __global__ __launch_bounds__(256) void kc5_finalize(DevNet net, void* ws, WsLayo
     H += t.x;
     Ha += t.y;
   }
-  for (int q = threadIdx.x; q < lay.n_ct; q += 256) T += ws_ptr<double2>(ws, lay.ct)[b * lay.n_ct + q].x;
+  for (int q = threadIdx.x; q < lay.n_ct; q += 256) T += ws_ptr<double4>(ws, lay.ct)[b * lay.n_ct + q].x;
   H = block_sum256(H, sh);
   Ha = block_sum256(Ha, sh);
   T = block_sum256(T, sh);
@@ -723,6 +768,393 @@ __global__ __launch_bounds__(256, 2) void kc3m_ptdf_t(DevNet net, void* ws, WsLa
   }
 }
 
+// ---------------------------------------------------------------- lower bound
+//
+// Chord relaxation: every penalty phi(z) = max(|z| - t, 0) is convex, so on an
+// interval that holds every value its pre-activation takes over the box it
+// lies below the chord between the interval's ends.  With those lines
+//
+//   f(x) >= S(x) - zeta_inj (a_I z_I(x) + b_I) - zeta_f sum_e (a_e z_e(x) + b_e)
+//
+// at every x of the box; the right side is linear in x (plus the curve part),
+// and its minimum over the box, taken with the same coefficient error bounds
+// as the upper bound, is a certified lower bound on min f.
+//
+// Contingency elements (float32, per element): in y = sign(C) z - t the K3
+// interval is [t_lo, t_hi] (exactly the floats K3 forms, which enclose the
+// exact pre-activation range), and the penalty there is
+// q(y) = max(|y + t| - t, 0).  An element with t_hi <= 0 has q = 0 on its whole
+// interval and contributes nothing.  Otherwise the slope alpha (the chord
+// slope, rounded to a multiple of 2^-24 in [0, 1]; any slope gives a valid
+// line) and beta >= max(q(t_hi) - alpha t_hi, q(t_lo) - alpha t_lo) (rounded
+// up) give q(y) <= alpha y + beta on [t_lo, t_hi] by convexity.  Each element's
+// line is written around C' = c_l + Lam c_c (real arithmetic on the float32
+// operands): a (z - C') + m with a = sign(C) alpha and m >= alpha (|C'| - t) +
+// beta, so the constant of the relaxation is
+//   sum_e b_e = sum_e m_e - sum_l c_l sum_k a_kl - sum_k c_c(k) sum_l a_kl Lam_kl,
+// a sum of non-negative m (float32, relative error only) and two terms built
+// from the per-line slope totals (exact integers in units of 2^-24) and the
+// per-outage sums sum_l a Lam that the adjoint needs anyway.
+constexpr int kCKB = 32;  // outages per chord-sweep block
+constexpr float kSlopeQ = 16777216.0f;  // 2^24
+
+// One element: fixed-point slope magnitude q (alpha = q / 2^24), signed slope
+// a and the value bound m (all zero when t_hi <= 0 or the entry is the
+// outaged line's own, whose NaN fails the test).
+__device__ __forceinline__ void chord_elem(float lam, float cc, float rk, float cl, float h, float g, float tq,
+                                           int& q, float& a, float& m) {
+  const float C = fmaf(lam, cc, cl);
+  const float th = fabsf(C) + fmaf(fabsf(lam), rk, h);
+  const float tl = fabsf(C) - fmaf(fabsf(lam), rk, g);
+  // q at the lower end, rounded up: tq <= t, and -tl - 2 tq >= -tl - 2 t
+  const float ql = fmaxf(fmaxf(tl, next_up_f32(fmaf(-2.0f, tq, -tl))), 0.0f);
+  // NaN (zero width) clamps to 0
+  const float al = fminf(fmaxf((th - ql) * __builtin_amdgcn_rcpf(th - tl), 0.0f), 1.0f);
+  const float qf = rintf(al * kSlopeQ);
+  const float alq = qf * (1.0f / kSlopeQ);
+  const float beta = next_up_f32(fmaxf(fmaf(-alq, th, th), fmaf(-alq, tl, ql)));
+  // alpha (|C'| - t) + beta with |C'| <= |C| (1 + u): rounding of d and of the
+  // fma, and the u |C| of C', are inside 4u (|C| + tq + |y|)
+  const float y = fmaf(alq, fabsf(C) - tq, beta);
+  const float mm = fmaxf(next_up_f32(y + 0x1p-22f * (fabsf(C) + tq + fabsf(y))), 0.0f);
+  const bool act = th > 0.0f;
+  q = act ? (int)qf : 0;
+  a = act ? copysignf(alq, C) : 0.0f;
+  m = act ? mm : 0.0f;
+}
+
+// Four lines x one outage of one box: per-line fixed-point slope totals, and
+// the outage's four sums (a Lam, |a Lam|, alpha, m) into r[0..3].
+__device__ __forceinline__ void chord_row(const float4& x, const int4& d, const float4& c4, const float4& h4,
+                                          const float4& g4, const float4& t4, int (&cs)[4], int (&ca)[4],
+                                          float* r) {
+  const float cc = __int_as_float(d.y), rk = __int_as_float(d.z);
+  const float lam[4] = {x.x, x.y, x.z, x.w}, cl[4] = {c4.x, c4.y, c4.z, c4.w};
+  const float hh[4] = {h4.x, h4.y, h4.z, h4.w}, gg[4] = {g4.x, g4.y, g4.z, g4.w};
+  const float tt[4] = {t4.x, t4.y, t4.z, t4.w};
+  float v = 0.0f, va = 0.0f, n = 0.0f, mm = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int q;
+    float a, m;
+    chord_elem(lam[i], cc, rk, cl[i], hh[i], gg[i], tt[i], q, a, m);
+    cs[i] += a < 0.0f ? -q : q;
+    ca[i] += q;
+    // NaN entries carry a = 0 and a finite stand-in
+    const float p = a * fminf(lam[i], FLT_MAX);
+    v += p;
+    va += fabsf(p);
+    n += fabsf(a);
+    mm += m;
+  }
+  r[0] = v;
+  r[1] = va;
+  r[2] = n;
+  r[3] = mm;
+}
+
+// Sums v[0..31] over the 64 lanes of a wave by halving exchanges (16 + 8 + 4 +
+// 2 + 1, then one plain step): afterwards lanes 2g and 2g + 1 hold the total
+// of v[g] in v[0].
+__device__ __forceinline__ void halving_sum32(float (&v)[32]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = halve32(v[i], v[i + 16]);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = halve16(v[i], v[i + 8]);
+  {
+    const bool up = lane & 8;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float send = up ? v[i] : v[i + 4];
+      const float keep = up ? v[i + 4] : v[i];
+      v[i] = keep + lane_xor<kDppXor8>(send);
+    }
+  }
+  {
+    const bool up = lane & 4;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const float send = up ? v[i] : v[i + 2];
+      const float keep = up ? v[i + 2] : v[i];
+      v[i] = keep + __shfl_xor(send, 4, 64);
+    }
+  }
+  {
+    const bool up = lane & 2;
+    const float send = up ? v[0] : v[1];
+    const float keep = up ? v[1] : v[0];
+    v[0] = keep + lane_xor<kDppXor2>(send);
+  }
+  v[0] += lane_xor<kDppXor1>(v[0]);
+}
+
+// Outage sweep of the chord relaxation: NB boxes per lane (1, or 4 sharing
+// every streamed outage-factor tile), four lines per lane, kCKB outages per
+// block; 8 / NB outages x NB boxes x 4 sums per halving reduction.  Grid:
+// (box tiles, line tiles, outage blocks).
+template <int NB>
+__global__ __launch_bounds__(256) void kc1c_chord(DevNet net, void* ws, WsLayout lay, int64_t n_box) {
+  constexpr int OG = 8 / NB;
+  __shared__ float sh[4][kCKB][NB][4];
+  const int64_t bt = (int64_t)blockIdx.x * NB;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int col = (blockIdx.y * 4 + w) * 64 + lane;
+  const int Lp4 = net.Lp / 4;
+  const int k0 = blockIdx.z * kCKB;
+  const int k1 = min(net.K, k0 + kCKB);
+  const bool live = col < Lp4;
+  int64_t bb[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) bb[i] = min(bt + i, n_box - 1);
+  float4 c4[NB], h4[NB], g4[NB], t4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  const int4* cd[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    c4[i] = h4[i] = g4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    cd[i] = ws_ptr<int4>(ws, lay.ctg) + bb[i] * net.K;
+  }
+  if (live) {
+    const float4 e4 = reinterpret_cast<const float4*>(net.line_eps)[col];
+    const float4 f4 = reinterpret_cast<const float4*>(net.fmax_c32)[col];
+    // a float32 limit no larger than the float64 one
+    constexpr float kDown = 1.0f - 0x1p-22f;
+    t4 = make_float4(f4.x * kDown, f4.y * kDown, f4.z * kDown, f4.w * kDown);
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const double* bs = ws_ptr<double>(ws, lay.box) + bb[i] * kBoxSlots;
+      const float vmax = __uint_as_float(*reinterpret_cast<const unsigned int*>(bs + kVmax));
+      const float ex = next_up_f32(e4.x * vmax), ey = next_up_f32(e4.y * vmax);
+      const float ez = next_up_f32(e4.z * vmax), ew = next_up_f32(e4.w * vmax);
+      c4[i] = reinterpret_cast<const float4*>(ws_ptr<float>(ws, lay.lc) + bb[i] * net.Lp)[col];
+      const float4 h = reinterpret_cast<const float4*>(ws_ptr<float>(ws, lay.lh) + bb[i] * net.Lp)[col];
+      const float4 g = reinterpret_cast<const float4*>(ws_ptr<float>(ws, lay.lg) + bb[i] * net.Lp)[col];
+      h4[i] = make_float4(add_ru(h.x, ex), add_ru(h.y, ey), add_ru(h.z, ez), add_ru(h.w, ew));
+      g4[i] = make_float4(add_ru(g.x, ex), add_ru(g.y, ey), add_ru(g.z, ez), add_ru(g.w, ew));
+    }
+  }
+  const float4* lam = reinterpret_cast<const float4*>(net.lodf) + col;
+  int cs[NB][4], ca[NB][4];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) cs[i][j] = ca[i][j] = 0;
+  for (int kg = k0; kg < k1; kg += OG) {
+    float r[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) r[i] = 0.0f;
+    if (live) {
+      float4 x[OG];
+#pragma unroll
+      for (int o = 0; o < OG; ++o)
+        x[o] = (kg + o < k1) ? ld_stream(lam + (size_t)(kg + o) * Lp4) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int o = 0; o < OG; ++o)
+        if (kg + o < k1)
+#pragma unroll
+          for (int i = 0; i < NB; ++i)
+            chord_row(x[o], cd[i][kg + o], c4[i], h4[i], g4[i], t4, cs[i], ca[i], r + 4 * (o * NB + i));
+    }
+    // a wave with no active element in the group skips the reduction
+    bool act = false;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) act |= (r[4 * i + 2] != 0.0f) | (r[4 * i + 3] != 0.0f);
+    if (__any(act)) halving_sum32(r);
+    // lane 2g holds sum g = 4 (o NB + i) + f (zeros when the wave skipped)
+    if ((lane & 1) == 0) {
+      const int g = lane >> 1, o = g / (4 * NB), i = (g >> 2) % NB;
+      if (kg + o < k1) sh[w][kg - k0 + o][i][g & 3] = r[0];
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < (k1 - k0) * NB; t += 256) {
+    const int q = t / NB, i = t % NB;
+    if (bt + i >= n_box) continue;
+    double o[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+      o[f] = ((double)sh[0][q][i][f] + (double)sh[1][q][i][f]) + ((double)sh[2][q][i][f] + (double)sh[3][q][i][f]);
+    ws_ptr<double4>(ws, lay.cv)[((size_t)(bt + i) * lay.kc_bx + blockIdx.y) * net.K + k0 + q] =
+        make_double4(o[0], o[1], o[2], o[3]);
+  }
+  if (live) {
+    // per-line slope totals: 64-bit integer atomics, so the totals do not
+    // depend on the order (at most K 2^24 per line)
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      if (bt + i >= n_box) break;
+      unsigned long long* cnt = ws_ptr<unsigned long long>(ws, lay.ccnt) + 2 * ((bt + i) * net.Lp + 4 * col);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (ca[i][j] != 0) {
+          atomicAdd(&cnt[2 * j], (unsigned long long)(long long)cs[i][j]);
+          atomicAdd(&cnt[2 * j + 1], (unsigned long long)(long long)ca[i][j]);
+        }
+    }
+  }
+}
+
+// Per line of the chord relaxation: the base line's chord (float64), the
+// adjoint v with vabs >= |v_exact| and ev >= |v^ - v_exact| as in KC2, and an
+// upper bound T_l on the line's share of the relaxation's constant:
+//   the base intercept, - c_l sum_k a_kl, and for the line's outage k
+//   sum_l m_kl - c_c(k) sum_l a_kl Lam_kl (whose float32 rounding is bounded
+//   by 12u sum |a Lam|: one product rounding, three in-lane additions, six
+//   halving levels, with a spare u).
+// Block partials (sum T_l, sum vabs, sum |terms of T_l|).
+__global__ __launch_bounds__(256) void kc2c_lines(DevNet net, void* ws, WsLayout lay, int64_t box0) {
+  __shared__ double sh[4];
+  const int64_t b = box0 + blockIdx.y;
+  const int l = blockIdx.x * 256 + threadIdx.x;
+  double v = 0.0, va = 0.0, ev = 0.0, T = 0.0, Ta = 0.0;
+  if (l < net.L) {
+    const double fb = net.fmax_b[l];
+    const double cf = ws_ptr<double>(ws, lay.lcf)[b * net.L + l];
+    const double rf = ws_ptr<double>(ws, lay.lrf)[b * net.L + l];
+    // base line: y = sign(cf) z - fb on [|cf| - rf - fb, |cf| + rf - fb] (outward)
+    double ab = 0.0, tb = 0.0, tba = 0.0;
+    {
+      const double e = 4.0 * kU64 * (fabs(cf) + rf + fb);
+      const double th = fabs(cf) + rf - fb + e;
+      const double tl = fabs(cf) - rf - fb - e;
+      if (th > 0.0) {
+        const double q0 = -tl - 2.0 * fb;
+        const double ql = fmax(fmax(tl, q0 + 4.0 * kU64 * (fabs(tl) + 2.0 * fb)), 0.0);
+        const double al = fmin(fmax((th - ql) / (th - tl), 0.0), 1.0);
+        double be = fmax(fma(-al, th, th), fma(-al, tl, ql));
+        be += 4.0 * kU64 * (fabs(be) + th + fabs(tl) + ql);
+        // the line alpha y + beta in z: a z + (beta - alpha fb)
+        ab = copysign(al, cf);
+        tb = be - al * fb;
+        tba = fabs(be) + al * fb;
+        tb += 2.0 * kU64 * tba;
+      }
+    }
+    const long long* n = ws_ptr<long long>(ws, lay.ccnt) + 2 * (b * net.Lp + l);
+    const double nx = (double)n[0] * (1.0 / 16777216.0), ny = (double)n[1] * (1.0 / 16777216.0);
+    const double cl = (double)ws_ptr<float>(ws, lay.lc)[b * net.Lp + l];
+    v = ab + nx;
+    va = fabs(ab) + ny;
+    T = tb - cl * nx;
+    Ta = tba + fabs(cl * nx);
+    const int k = net.ctg_of_line[l];
+    if (k >= 0) {
+      double V = 0.0, A = 0.0, N = 0.0, M = 0.0;
+      const double4* cv = ws_ptr<double4>(ws, lay.cv) + (size_t)b * lay.kc_bx * net.K + k;
+      for (int t = 0; t < lay.kc_bx; ++t) {
+        const double4 q = cv[(size_t)t * net.K];
+        V += q.x;
+        A += q.y;
+        N += q.z;
+        M += q.w;
+      }
+      const double gam = (net.Lp + lay.kc_bx + 16) * kU64 * 1.01;
+      const double f32 = 1.0 + 12.0 * kU32;
+      const double A1 = A * (1.0 + gam) * (1.0 + kKappa0) * f32;
+      ev = (kKappa0 + net.ctg_eps[k] + gam + 12.0 * kU32) * A1 + 2.0 * net.phi_err_max * net.ctg_inv[k] * N * f32;
+      v += V;
+      va += A1 + ev;
+      // this line is the outage's own: c_c(k) = c_l
+      const double M1 = M * (1.0 + gam) * f32;
+      T += M1 - cl * V + fabs(cl) * 12.0 * kU32 * A1;
+      Ta += M1 + fabs(cl * V) + fabs(cl) * 12.0 * kU32 * A1;
+    }
+    ev = (ev + 2.0 * kU64 * va) * (1.0 + 4.0 * kU64);
+    va = va * (1.0 + 4.0 * kU64) + ev;
+    // products and the additions forming T
+    T += 8.0 * kU64 * Ta;
+    Ta *= (1.0 + 8.0 * kU64);
+  }
+  if (l < net.Lp) ws_ptr<double4>(ws, lay.lv)[b * net.Lp + l] = make_double4(v, va, ev, 0.0);
+  T = block_sum256(T, sh);
+  const double S = block_sum256(va, sh);
+  Ta = block_sum256(Ta, sh);
+  if (threadIdx.x == 0) ws_ptr<double4>(ws, lay.ct)[b * lay.n_ct + blockIdx.x] = make_double4(T, S, Ta, 0.0);
+}
+
+// Per box: lower bound = sum of the input partials - zeta_f sum T_l, padded
+// for the float64 sums; f_lo becomes the larger of IBP's and this bound.
+__global__ __launch_bounds__(256) void kc5c_finalize(DevNet net, void* ws, WsLayout lay, int64_t box0,
+                                                     double* __restrict__ f_lo, double* __restrict__ crown) {
+  __shared__ double sh[4];
+  const int64_t b = box0 + blockIdx.x;
+  double H = 0.0, Ha = 0.0, T = 0.0, Ta = 0.0;
+  for (int q = threadIdx.x; q < lay.n_cp; q += 256) {
+    const double2 t = ws_ptr<double2>(ws, lay.cp)[b * lay.n_cp + q];
+    H += t.x;
+    Ha += t.y;
+  }
+  for (int q = threadIdx.x; q < lay.n_ct; q += 256) {
+    const double4 t = ws_ptr<double4>(ws, lay.ct)[b * lay.n_ct + q];
+    T += t.x;
+    Ta += t.z;
+  }
+  H = block_sum256(H, sh);
+  Ha = block_sum256(Ha, sh);
+  T = block_sum256(T, sh);
+  Ta = block_sum256(Ta, sh);
+  if (threadIdx.x != 0) return;
+  const double gam = (lay.n_cp + lay.n_ct + 300) * kU64 * 1.01;
+  const double zT = net.zeta_f * T;
+  const double lb = (H - zT) - gam * (Ha + fabs(H) + net.zeta_f * Ta + fabs(zT));
+  const double prev = f_lo[b];
+  f_lo[b] = (prev != prev || lb != lb) ? NAN : fmax(prev, lb);
+  if (crown) crown[b] = (prev != prev) ? NAN : lb;
+}
+
+hipError_t launch_crown_lower(const DevNet& net, int64_t n_box, const float* lo, const float* hi, double* f_lo,
+                              double* crown, float* vertex, void* ws, const WsLayout& lay, hipStream_t s,
+                              KernelTimer* tm) {
+  for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
+    const int nb = (int)std::min<int64_t>(65535, n_box - b0);
+    const int t = tm->start(10, s);
+    // two int64 totals per line: zeroed as pairs of int2
+    const int64_t nz = 2 * (int64_t)nb * net.Lp;
+    int2* cnt = reinterpret_cast<int2*>(static_cast<char*>(ws) + lay.ccnt) + 2 * b0 * net.Lp;
+    hipLaunchKernelGGL(kc0_zero, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, cnt, nz);
+    tm->stop(t, s);
+  }
+  if (net.K > 0) {
+    const int t = tm->start(10, s);
+    const unsigned kz = (unsigned)((net.K + kCKB - 1) / kCKB);
+    if (n_box < kCB)
+      hipLaunchKernelGGL(kc1c_chord<1>, dim3((unsigned)n_box, lay.kc_bx, kz), dim3(256), 0, s, net, ws, lay,
+                         n_box);
+    else
+      hipLaunchKernelGGL(kc1c_chord<kCB>, dim3((unsigned)((n_box + kCB - 1) / kCB), lay.kc_bx, kz), dim3(256), 0,
+                         s, net, ws, lay, n_box);
+    tm->stop(t, s);
+  }
+  for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
+    const int nb = (int)std::min<int64_t>(65535, n_box - b0);
+    const int t = tm->start(11, s);
+    hipLaunchKernelGGL(kc2c_lines, dim3(lay.n_ct, nb), dim3(256), 0, s, net, ws, lay, b0);
+    if (n_box < kCB)
+      hipLaunchKernelGGL(kc3_ptdf_t, dim3(lay.kc3_bx, lay.kc3_by, nb), dim3(256), 0, s, net, ws, lay, b0);
+    tm->stop(t, s);
+  }
+  if (n_box >= kCB) {
+    const int t = tm->start(11, s);
+    if (lay.kc3_mfma)
+      hipLaunchKernelGGL(kc3m_ptdf_t, dim3((net.N + 127) / 128, (unsigned)((n_box + 31) / 32), lay.kc3_bx),
+                         dim3(256), 0, s, net, ws, lay, n_box);
+    else
+      hipLaunchKernelGGL(kc3b_ptdf_t, dim3((unsigned)((n_box + kCB - 1) / kCB), lay.kc3_bx, lay.kc3_by),
+                         dim3(256), 0, s, net, ws, lay, n_box);
+    tm->stop(t, s);
+  }
+  for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
+    const int nb = (int)std::min<int64_t>(65535, n_box - b0);
+    const int t = tm->start(12, s);
+    hipLaunchKernelGGL(kc4_inputs<true>, dim3(lay.n_cp, nb), dim3(256), 0, s, net, ws, nullptr, lay, b0, lo, hi,
+                       vertex);
+    hipLaunchKernelGGL(kc5c_finalize, dim3(nb), dim3(256), 0, s, net, ws, lay, b0, f_lo, crown);
+    tm->stop(t, s);
+  }
+  return hipGetLastError();
+}
+
 void plan_crown(const DevNet& net, int64_t n_box, WsLayout& lay, const Tune& t) {
   const int lp4 = net.Lp / 4;
   lay.kc_bx = (lp4 + 255) / 256;
@@ -805,7 +1237,7 @@ static void relax_pass(const DevNet& net, int64_t n_box, const float* lo, const 
   for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
     const int nb = (int)std::min<int64_t>(65535, n_box - b0);
     const int t = tm->start(12, s);
-    hipLaunchKernelGGL(kc4_inputs, dim3(lay.n_cp, nb), dim3(256), 0, s, net, ws, wsr, lay, b0, lo, hi, vertex);
+    hipLaunchKernelGGL(kc4_inputs<false>, dim3(lay.n_cp, nb), dim3(256), 0, s, net, ws, wsr, lay, b0, lo, hi, vertex);
     hipLaunchKernelGGL(kc5_finalize, dim3(nb), dim3(256), 0, s, net, ws, lay, b0, f_hi, crown, again);
     tm->stop(t, s);
   }

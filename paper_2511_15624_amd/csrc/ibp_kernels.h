@@ -87,6 +87,12 @@ void plan_crown(const DevNet& net, int64_t n_box, WsLayout& lay, const Tune& t);
 hipError_t launch_crown(const DevNet& net, int64_t n_box, const float* lo, const float* hi, int ref_iters,
                         double* f_hi, double* crown, float* vertex, void* ws, const WsLayout& lay, hipStream_t s,
                         KernelTimer* tm);
+// Chord-relaxation lower bound after a forward call on the same workspace:
+// f_lo[b] = max(f_lo[b], bound); crown (optional) the bound alone; vertex
+// (optional) the minimiser of the linear part.
+hipError_t launch_crown_lower(const DevNet& net, int64_t n_box, const float* lo, const float* hi, double* f_lo,
+                              double* crown, float* vertex, void* ws, const WsLayout& lay, hipStream_t s,
+                              KernelTimer* tm);
 
 // Branch-and-bound rounds over input boxes (see ibp_split.hip).
 hipError_t launch_split_select(int64_t n, const int64_t* roots, int S, const int* n_leaf, int X,

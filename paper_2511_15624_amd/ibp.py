@@ -50,6 +50,7 @@ EXPORTED = [
     "ibp_bound_boxes",
     "ibp_bound_backward",
     "ibp_crown_bound_boxes",
+    "ibp_crown_lower_boxes",
     "ibp_set_kernel_timing",
     "ibp_kernel_times",
     "ibp_set_tile",
@@ -155,6 +156,8 @@ def load_library(path: str = LIB_PATH):
     lib.ibp_bound_backward.restype = ctypes.c_int
     lib.ibp_crown_bound_boxes.argtypes = [vp, i64, vp, vp, i32, vp, vp, vp, vp, vp, sz, vp, u32]
     lib.ibp_crown_bound_boxes.restype = ctypes.c_int
+    lib.ibp_crown_lower_boxes.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp, u32]
+    lib.ibp_crown_lower_boxes.restype = ctypes.c_int
     lib.ibp_set_kernel_timing.argtypes = [vp, ctypes.c_int]
     lib.ibp_set_kernel_timing.restype = ctypes.c_int
     lib.ibp_kernel_times.argtypes = [vp, ctypes.c_int32, vp, vp]
@@ -393,6 +396,29 @@ def ibp_crown_bound_boxes(net: Network, lo, hi, crown: bool = False, flags: int 
         raise ValueError("vertex must be a contiguous float32 device tensor shaped like the boxes")
     _check(load_library().ibp_crown_bound_boxes(net.handle, n, _dev_ptr(lo), _dev_ptr(hi), int(ref_iters),
                                                 _dev_ptr(f_lo), _dev_ptr(f_hi), _dev_ptr(c), _dev_ptr(vertex),
+                                                _dev_ptr(buf), buf.numel(), _stream_ptr(stream), flags))
+    return (f_lo, f_hi, c) if crown else (f_lo, f_hi)
+
+
+def ibp_crown_lower_boxes(net: Network, lo, hi, crown: bool = False, flags: int = 0, ws: Workspace = None,
+                          stream=None, vertex=None):
+    """IBP bounds with f_lo tightened by the chord relaxation of the penalties:
+    (f_lo, f_hi) or, with crown=True, (f_lo, f_hi, relaxation bound alone).
+    ``vertex``: optional float32 device tensor [n_box, X] that receives the box
+    vertex minimising the relaxation's linear part."""
+    torch = _torch()
+    lo, hi = _check_boxes(net, lo, hi)
+    n = lo.shape[0]
+    f_lo = torch.empty(n, dtype=torch.float64, device=lo.device)
+    f_hi = torch.empty(n, dtype=torch.float64, device=lo.device)
+    c = torch.empty(n, dtype=torch.float64, device=lo.device) if crown else None
+    ws = ws or Workspace(net)
+    buf, need = ws.get(n, flags | IBP_F_CROWN)
+    if vertex is not None and (vertex.dtype != torch.float32 or tuple(vertex.shape) != tuple(lo.shape)
+                               or not vertex.is_contiguous() or vertex.device != lo.device):
+        raise ValueError("vertex must be a contiguous float32 device tensor shaped like the boxes")
+    _check(load_library().ibp_crown_lower_boxes(net.handle, n, _dev_ptr(lo), _dev_ptr(hi), _dev_ptr(f_lo),
+                                                _dev_ptr(f_hi), _dev_ptr(c), _dev_ptr(vertex),
                                                 _dev_ptr(buf), buf.numel(), _stream_ptr(stream), flags))
     return (f_lo, f_hi, c) if crown else (f_lo, f_hi)
 

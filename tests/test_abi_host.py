@@ -119,6 +119,11 @@ def test_compute_calls_need_a_device_handle(lib):
     assert ibp.STATUS[st] == "IBP_E_HOST_ONLY"
     st = lib.ibp_bound_backward(h.handle, 1, None, None, None, None, None, None, None, 0, None, 0)
     assert ibp.STATUS[st] == "IBP_E_HOST_ONLY"
+    st = lib.ibp_crown_lower_boxes(h.handle, 1, None, None, None, None, None, None, None, 0, None, 0)
+    assert ibp.STATUS[st] == "IBP_E_HOST_ONLY"
+    st = lib.ibp_crown_lower_boxes(h.handle, 1, None, None, None, None, None, None, None, 0, None,
+                                   ibp.IBP_F_UPPER_ONLY)
+    assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"
     st = lib.ibp_bound_boxes(None, 1, None, None, None, None, None, None, 0, None, 0)
     assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"
     lib.ibp_free_network(None)
