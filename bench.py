@@ -341,6 +341,31 @@ def extras(torch, ibp, synth, n4, net4):
         "batch_f_hi_tightening_mean_4_reference_points": float(tightr.mean()),
         "batch_f_hi_tightening_max_4_reference_points": float(tightr.max()),
     }
+    # chord-relaxation lower bound: the same two workloads; time and tightening
+    # of f_lo against IBP alone
+    ms_l1 = _time(torch, lambda: ibp.ibp_crown_lower_boxes(n4, s4l, s4h, ws=wsc), 20)
+    n4.set_kernel_timing(True)
+    n4.kernel_times()
+    for _ in range(5):
+        _, _, l_only1 = ibp.ibp_crown_lower_boxes(n4, s4l, s4h, crown=True, ws=wsc)
+    ktl = n4.kernel_times()
+    n4.set_kernel_timing(False)
+    ms_l3 = _time(torch, lambda: ibp.ibp_crown_lower_boxes(n3, c3l, c3h, ws=ws3c), 2)
+    ms_i3l = _time(torch, lambda: ibp.ibp_bound_boxes(n3, c3l, c3h, ws=ws3c, flags=ibp.IBP_F_LOWER_ONLY), 2)
+    ms_l3o = _time(torch, lambda: ibp.ibp_crown_lower_boxes(n3, c3l, c3h, ws=ws3c, flags=ibp.IBP_F_LOWER_ONLY), 2)
+    l_lo3, _ = ibp.ibp_crown_lower_boxes(n3, c3l, c3h, ws=ws3c)
+    i_lo3, _ = ibp.ibp_bound_boxes(n3, c3l, c3h, ws=ws3c)
+    tightl = ((l_lo3 - i_lo3) / i_lo3.abs()).cpu()
+    res["crown_lower"] = {
+        "workload": "chord-relaxation lower bound: the large single box; 1024 sub-boxes (2000 buses)",
+        "single_box_ms": ms_l1, "single_box_ms_ibp_only": ms_lin,
+        "single_box_value": ev1 / (ms_l1 * 1e-3), "unit": "evals/s",
+        "single_box_kernel_us": {k: round(v[0] / v[1] * 1e3, 2) for k, v in ktl.items()},
+        "single_box_f_lo_ibp": float(i_lo1[0]), "single_box_f_lo_chord": float(l_only1[0]),
+        "batch_ms": ms_l3, "batch_ms_lower_only": ms_l3o, "batch_ms_ibp_lower_only": ms_i3l,
+        "batch_value": 1024 * n3.n_ctg * n3.n_line / (ms_l3 * 1e-3),
+        "batch_f_lo_tightening_mean": float(tightl.mean()), "batch_f_lo_tightening_max": float(tightl.max()),
+    }
     # splitting: 4096 roots, 10 rounds of gradient-ranked bisection
     from paper_2511_15624_amd.split import BoxSplitter
     sp = BoxSplitter(n3, t5l, t5h, rounds=10)

@@ -798,29 +798,38 @@ __global__ __launch_bounds__(256, 2) void kc3m_ptdf_t(DevNet net, void* ws, WsLa
 constexpr int kCKB = 32;  // outages per chord-sweep block
 constexpr float kSlopeQ = 16777216.0f;  // 2^24
 
-// One element: fixed-point slope magnitude q (alpha = q / 2^24), signed slope
-// a and the value bound m (all zero when t_hi <= 0 or the entry is the
-// outaged line's own, whose NaN fails the test).
+// One element: fixed-point slope magnitude qa and signed slope qs
+// (a = qs / 2^24, |a| = alpha = qa / 2^24), and the value bound m (all zero
+// when t_hi <= 0 or the entry is the outaged line's own, whose NaN fails the
+// test).  Roundings (u = 2^-24, results in
+// the normal range; FLT_MIN covers the rest):
+//   - q0 = RN(-tl - 2 tq) is within u |q0| of the exact value, and
+//     q0 (1 + 4u) + FLT_MIN, rounded, is above it;
+//   - each of the two intercept candidates is within u of its magnitude, so
+//     beta (1 + 4u), rounded, is above the exact maximum;
+//   - y = alpha (|C| - tq) + beta carries the roundings of d = |C| - tq and
+//     of the fma, and |C'| <= |C| (1 + u): the pad 8u (|C| + tq + |y|) and
+//     FLT_MIN cover them with the final rounding.
 __device__ __forceinline__ void chord_elem(float lam, float cc, float rk, float cl, float h, float g, float tq,
-                                           int& q, float& a, float& m) {
+                                           float& qa, float& qs, float& m) {
   const float C = fmaf(lam, cc, cl);
-  const float th = fabsf(C) + fmaf(fabsf(lam), rk, h);
-  const float tl = fabsf(C) - fmaf(fabsf(lam), rk, g);
-  // q at the lower end, rounded up: tq <= t, and -tl - 2 tq >= -tl - 2 t
-  const float ql = fmaxf(fmaxf(tl, next_up_f32(fmaf(-2.0f, tq, -tl))), 0.0f);
+  const float aC = fabsf(C);
+  const float th = aC + fmaf(fabsf(lam), rk, h);
+  const float tl = aC - fmaf(fabsf(lam), rk, g);
+  const float q0 = fmaf(-2.0f, tq, -tl);
+  const float ql = fmaxf(fmaxf(tl, fmaf(q0, 1.0f + 0x1p-22f, FLT_MIN)), 0.0f);
   // NaN (zero width) clamps to 0
   const float al = fminf(fmaxf((th - ql) * __builtin_amdgcn_rcpf(th - tl), 0.0f), 1.0f);
   const float qf = rintf(al * kSlopeQ);
   const float alq = qf * (1.0f / kSlopeQ);
-  const float beta = next_up_f32(fmaxf(fmaf(-alq, th, th), fmaf(-alq, tl, ql)));
-  // alpha (|C'| - t) + beta with |C'| <= |C| (1 + u): rounding of d and of the
-  // fma, and the u |C| of C', are inside 4u (|C| + tq + |y|)
-  const float y = fmaf(alq, fabsf(C) - tq, beta);
-  const float mm = fmaxf(next_up_f32(y + 0x1p-22f * (fabsf(C) + tq + fabsf(y))), 0.0f);
+  const float beta = fmaxf(fmaf(-alq, th, th), fmaf(-alq, tl, ql));
+  const float bu = fmaf(fabsf(beta), 0x1p-22f, beta);
+  const float y = fmaf(alq, aC - tq, bu);
+  const float mm = fmaf(0x1p-21f, (aC + tq) + fabsf(y), y) + FLT_MIN;
   const bool act = th > 0.0f;
-  q = act ? (int)qf : 0;
-  a = act ? copysignf(alq, C) : 0.0f;
-  m = act ? mm : 0.0f;
+  qa = act ? qf : 0.0f;
+  qs = copysignf(qa, C);
+  m = act ? fmaxf(mm, 0.0f) : 0.0f;
 }
 
 // Four lines x one outage of one box: per-line fixed-point slope totals, and
@@ -835,11 +844,11 @@ __device__ __forceinline__ void chord_row(const float4& x, const int4& d, const 
   float v = 0.0f, va = 0.0f, n = 0.0f, mm = 0.0f;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    int q;
-    float a, m;
-    chord_elem(lam[i], cc, rk, cl[i], hh[i], gg[i], tt[i], q, a, m);
-    cs[i] += a < 0.0f ? -q : q;
-    ca[i] += q;
+    float qa, qs, m;
+    chord_elem(lam[i], cc, rk, cl[i], hh[i], gg[i], tt[i], qa, qs, m);
+    cs[i] += (int)qs;
+    ca[i] += (int)qa;
+    const float a = qs * (1.0f / kSlopeQ);
     // NaN entries carry a = 0 and a finite stand-in
     const float p = a * fminf(lam[i], FLT_MAX);
     v += p;
