@@ -232,6 +232,7 @@ ibp_status to_device(ibp_network* net, int device) {
     if (const char* p = std::strstr(e, "k2nc=")) t.k2_nc = (v = std::atoi(p + 5)) ? v : t.k2_nc;
     if (const char* p = std::strstr(e, "k3kc=")) t.k3_kc = (v = std::atoi(p + 5)) ? v : t.k3_kc;
     if (const char* p = std::strstr(e, "k2b=")) t.k2b_mfma = std::atoi(p + 4) != 0;
+    if (const char* p = std::strstr(e, "ckb=")) t.chord_nb = std::atoi(p + 4);
     if (ibp::tune_valid(t)) net->tune = t;
   }
   return IBP_OK;
@@ -283,6 +284,7 @@ ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
     lay.bpart = take(B * lay.kc3_bx * d.Np * 4 * sizeof(double));
     lay.cp = take(B * lay.n_cp * 2 * sizeof(double));
     lay.ct = take(B * lay.n_ct * 4 * sizeof(double));
+    if (lay.chp_z) lay.chp = take(B * lay.chp_z * d.Lp * 2 * sizeof(int));
     if (flags & IBP_F_CROWN_REF) {
       lay.ref = take(lay.fwd_total);
       lay.xref = take(B * d.X * sizeof(float));

@@ -898,12 +898,15 @@ __device__ __forceinline__ void halving_sum32(float (&v)[32]) {
   v[0] += lane_xor<kDppXor1>(v[0]);
 }
 
-// Outage sweep of the chord relaxation: NB boxes per lane (1, or 4 sharing
-// every streamed outage-factor tile), four lines per lane, kCKB outages per
-// block; 8 / NB outages x NB boxes x 4 sums per halving reduction.  Grid:
-// (box tiles, line tiles, outage blocks).
-template <int NB>
-__global__ __launch_bounds__(256) void kc1c_chord(DevNet net, void* ws, WsLayout lay, int64_t n_box) {
+// Outage sweep of the chord relaxation: NB boxes per lane (1, or 2 or 4
+// sharing every streamed outage-factor tile), four lines per lane, kCKB
+// outages per block; 8 / NB outages x NB boxes x 4 sums per halving
+// reduction.  Grid: (box tiles, line tiles, outage blocks).  Each element is a
+// long dependent chain, so occupancy decides the issue rate: MINB bounds the
+// registers (one box: 6 waves per SIMD; two boxes: 5; four boxes: 3, the
+// most that holds four boxes' line data without spilling).
+template <int NB, int MINB>
+__global__ __launch_bounds__(256, MINB) void kc1c_chord(DevNet net, void* ws, WsLayout lay, int64_t n_box) {
   constexpr int OG = 8 / NB;
   __shared__ float sh[4][kCKB][NB][4];
   const int64_t bt = (int64_t)blockIdx.x * NB;
@@ -987,7 +990,14 @@ __global__ __launch_bounds__(256) void kc1c_chord(DevNet net, void* ws, WsLayout
     ws_ptr<double4>(ws, lay.cv)[((size_t)(bt + i) * lay.kc_bx + blockIdx.y) * net.K + k0 + q] =
         make_double4(o[0], o[1], o[2], o[3]);
   }
-  if (live) {
+  if (live && NB == 1 && lay.chp_z) {
+    // one box: every block of outages targets the same lines, so atomics
+    // would queue on the same addresses; each block stores its line totals
+    // (at most kCKB 2^24 each) for the line kernel to add up
+    int2* part = ws_ptr<int2>(ws, lay.chp) + ((size_t)bt * lay.chp_z + blockIdx.z) * net.Lp + 4 * col;
+    reinterpret_cast<int4*>(part)[0] = make_int4(cs[0][0], ca[0][0], cs[0][1], ca[0][1]);
+    reinterpret_cast<int4*>(part)[1] = make_int4(cs[0][2], ca[0][2], cs[0][3], ca[0][3]);
+  } else if (live) {
     // per-line slope totals: 64-bit integer atomics, so the totals do not
     // depend on the order (at most K 2^24 per line)
 #pragma unroll
@@ -1040,8 +1050,32 @@ __global__ __launch_bounds__(256) void kc2c_lines(DevNet net, void* ws, WsLayout
         tb += 2.0 * kU64 * tba;
       }
     }
-    const long long* n = ws_ptr<long long>(ws, lay.ccnt) + 2 * (b * net.Lp + l);
-    const double nx = (double)n[0] * (1.0 / 16777216.0), ny = (double)n[1] * (1.0 / 16777216.0);
+    long long n0 = 0, n1 = 0;
+    if (lay.chp_z) {
+      // sixteen partials in flight per round (the grid is one thread per line)
+      const int2* part = ws_ptr<int2>(ws, lay.chp) + (size_t)b * lay.chp_z * net.Lp + l;
+      int z = 0;
+      for (; z + 16 <= lay.chp_z; z += 16) {
+        int2 q[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) q[i] = part[(size_t)(z + i) * net.Lp];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          n0 += q[i].x;
+          n1 += q[i].y;
+        }
+      }
+      for (; z < lay.chp_z; ++z) {
+        const int2 q = part[(size_t)z * net.Lp];
+        n0 += q.x;
+        n1 += q.y;
+      }
+    } else {
+      const long long* n = ws_ptr<long long>(ws, lay.ccnt) + 2 * (b * net.Lp + l);
+      n0 = n[0];
+      n1 = n[1];
+    }
+    const double nx = (double)n0 * (1.0 / 16777216.0), ny = (double)n1 * (1.0 / 16777216.0);
     const double cl = (double)ws_ptr<float>(ws, lay.lc)[b * net.Lp + l];
     v = ab + nx;
     va = fabs(ab) + ny;
@@ -1115,7 +1149,7 @@ __global__ __launch_bounds__(256) void kc5c_finalize(DevNet net, void* ws, WsLay
 hipError_t launch_crown_lower(const DevNet& net, int64_t n_box, const float* lo, const float* hi, double* f_lo,
                               double* crown, float* vertex, void* ws, const WsLayout& lay, hipStream_t s,
                               KernelTimer* tm) {
-  for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
+  for (int64_t b0 = 0; b0 < n_box && !lay.chp_z; b0 += 65535) {
     const int nb = (int)std::min<int64_t>(65535, n_box - b0);
     const int t = tm->start(10, s);
     // two int64 totals per line: zeroed as pairs of int2
@@ -1128,11 +1162,14 @@ hipError_t launch_crown_lower(const DevNet& net, int64_t n_box, const float* lo,
     const int t = tm->start(10, s);
     const unsigned kz = (unsigned)((net.K + kCKB - 1) / kCKB);
     if (n_box < kCB)
-      hipLaunchKernelGGL(kc1c_chord<1>, dim3((unsigned)n_box, lay.kc_bx, kz), dim3(256), 0, s, net, ws, lay,
+      hipLaunchKernelGGL((kc1c_chord<1, 5>), dim3((unsigned)n_box, lay.kc_bx, kz), dim3(256), 0, s, net, ws, lay,
                          n_box);
+    else if (lay.chord_nb == 2)
+      hipLaunchKernelGGL((kc1c_chord<2, 5>), dim3((unsigned)((n_box + 1) / 2), lay.kc_bx, kz), dim3(256), 0, s,
+                         net, ws, lay, n_box);
     else
-      hipLaunchKernelGGL(kc1c_chord<kCB>, dim3((unsigned)((n_box + kCB - 1) / kCB), lay.kc_bx, kz), dim3(256), 0,
-                         s, net, ws, lay, n_box);
+      hipLaunchKernelGGL((kc1c_chord<kCB, 1>), dim3((unsigned)((n_box + kCB - 1) / kCB), lay.kc_bx, kz),
+                         dim3(256), 0, s, net, ws, lay, n_box);
     tm->stop(t, s);
   }
   for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
@@ -1183,6 +1220,9 @@ void plan_crown(const DevNet& net, int64_t n_box, WsLayout& lay, const Tune& t) 
   }
   lay.n_cp = (net.X + 255) / 256;
   lay.n_ct = (net.L + 255) / 256;
+  lay.chord_nb = t.chord_nb;
+  // (with no outages there is no sweep: the zeroed totals serve)
+  lay.chp_z = (n_box < kCB && net.K > 0) ? (net.K + kCKB - 1) / kCKB : 0;
 }
 
 // Reference points: the box centre first, then halfway towards the vertex that
