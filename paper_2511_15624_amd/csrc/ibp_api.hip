@@ -233,7 +233,7 @@ ibp_status to_device(ibp_network* net, int device) {
     if (const char* p = std::strstr(e, "k3kc=")) t.k3_kc = (v = std::atoi(p + 5)) ? v : t.k3_kc;
     if (const char* p = std::strstr(e, "k2b=")) t.k2b_mfma = std::atoi(p + 4) != 0;
     if (const char* p = std::strstr(e, "ckb=")) t.chord_nb = std::atoi(p + 4);
-    if (ibp::tune_valid(t)) net->tune = t;
+    if (ibp::tune_valid(t) && (t.chord_nb == 2 || t.chord_nb == 4)) net->tune = t;
   }
   return IBP_OK;
 }

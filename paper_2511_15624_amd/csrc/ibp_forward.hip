@@ -605,7 +605,7 @@ __global__ __launch_bounds__(256) void k3_contingency(DevNet net, void* ws, WsLa
 bool tune_valid(const Tune& t) {
   const bool nc = t.k2_nc == 32 || t.k2_nc == 64 || t.k2_nc == 128 || t.k2_nc == 256;
   const bool kc = t.k3_kc == 16 || t.k3_kc == 32 || t.k3_kc == 64 || t.k3_kc == 128;
-  return nc && kc && (t.chord_nb == 2 || t.chord_nb == 4);
+  return nc && kc;
 }
 
 void plan_single(const DevNet& net, int64_t n_box, WsLayout& lay, const Tune& t) {
