@@ -2,7 +2,8 @@
 input counts that are not multiples of the kernels' tiles; many devices on
 one bus; piecewise-linear curves on some), single-box and box-tiled calls,
 against the FP64 oracle: enclosure and the 1e-5 bar of the forward tests,
-and the one-sided calls against the two-sided ones.
+the one-sided calls against the two-sided ones, and the chord-relaxation
+lower bound (per box and box-tiled) against the oracle's.
 """
 import numpy as np
 import pytest
@@ -45,3 +46,10 @@ def test_random_network(case):
         r = orc(net, LO[b], HI[b], fac)
         assert_encloses(b_lo[b], b_hi[b], r, what=f"{case} box-tiled {b}")
         assert_encloses(p_lo[b], p_hi[b], r, what=f"{case} per-box {b}")
+    # chord-relaxation lower bound: ten boxes (tiled sweep) and the first alone (per-box sweep)
+    from tests.test_gpu_crown_lower import check_box, gpu_lower
+    c_lo, c_hi, c = gpu_lower(n, LO, HI)
+    c1_lo, c1_hi, c1 = gpu_lower(n, LO[:1], HI[:1])
+    for b in range(LO.shape[0]):
+        check_box(net, fac, LO[b], HI[b], c_lo[b], c_hi[b], c[b], b_lo[b], b_hi[b], f"{case} chord {b}")
+    check_box(net, fac, LO[0], HI[0], c1_lo[0], c1_hi[0], c1[0], p_lo[0], p_hi[0], f"{case} chord single")
