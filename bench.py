@@ -31,7 +31,16 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "ibp_traffic_c8316_single_box.json")
-KERNEL_NAMES = {"base_flows": "ibp::k2_base_flows<256>", "outage_sweep": "ibp::k3_contingency<16>"}
+# kernel-name prefixes in rocprofv3 records (the template argument is the tile
+# the network chose)
+KERNEL_NAMES = {"base_flows": "ibp::k2_base_flows<", "outage_sweep": "ibp::k3_contingency<"}
+ALGO_BYTES = {"base_flows": 465696000, "outage_sweep": 448000000}
+
+
+def _record_kernel(kernels: dict, kernel: str):
+    """The record entry of `kernel` (one instantiation per profiled run)."""
+    names = [k for k in kernels if k.startswith(KERNEL_NAMES[kernel])]
+    return kernels[names[0]] if len(names) == 1 else None
 
 
 def measured_traffic(kernel: str):
@@ -48,7 +57,7 @@ def measured_traffic(kernel: str):
                 m.update(g.read())
         if m.hexdigest()[:16] != rec["source_sha256_16"]:
             return None
-        k = rec["kernels"][KERNEL_NAMES[kernel]]
+        k = _record_kernel(rec["kernels"], kernel)
         return k["fetch_bytes"] + k["write_bytes"]
     except Exception:
         return None
@@ -80,13 +89,13 @@ def write_traffic_record(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
     for p in sources:
         with open(os.path.join(ROOT, p), "rb") as g:
             m.update(g.read())
-    algo = {KERNEL_NAMES["base_flows"]: 465696000, KERNEL_NAMES["outage_sweep"]: 448000000}
     kern = {}
     for k in sorted(fetch):
         if not k.startswith("ibp::"):
             continue
+        algo = next((ALGO_BYTES[n] for n, pre in KERNEL_NAMES.items() if k.startswith(pre)), None)
         kern[k] = {"fetch_kib": fetch[k], "write_kib": write.get(k, 0.0), "fetch_bytes": fetch[k] * 1024 * fs,
-                   "write_bytes": write.get(k, 0.0) * 1024 * wsc, "algorithmic_bytes": algo.get(k)}
+                   "write_bytes": write.get(k, 0.0) * 1024 * wsc, "algorithmic_bytes": algo}
     rec = {"workload": "8316 buses, 14000 lines, 8000 outages, single whole box", "fetch_scale": fs,
            "write_scale": wsc, "source_sha256_16": m.hexdigest()[:16], "sources": sources, "kernels": kern}
     with open(TRAFFIC_RECORD, "w") as f:

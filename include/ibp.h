@@ -269,7 +269,7 @@ ibp_status ibp_set_kernel_timing(ibp_network* net, int enable);
 ibp_status ibp_kernel_times(ibp_network* net, int32_t n_ids, double* total_ms, int64_t* count);
 
 /* Tile parameters of the two streaming kernels: k2_nc buses per wave in the
- * base-flow sweep (32, 64, 128, 256) and k3_kc outages per block in the outage
+ * base-flow sweep (32, 64, 128, 256, 512) and k3_kc outages per block in the outage
  * sweep (16, 32, 64, 128).  They change the workspace size; results do not
  * depend on them beyond float64 summation order.  ibp_autotune() times every
  * pair on the caller's boxes (forward calls on `stream`, synchronizing) and

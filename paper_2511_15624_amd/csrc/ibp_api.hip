@@ -213,12 +213,14 @@ ibp_status to_device(ibp_network* net, int device) {
   }
   if (hipDeviceSynchronize() != hipSuccess) return fail(IBP_E_DEVICE, "device synchronize failed");
   // default tiles: the longest bus chunk that still gives the base-flow sweep
-  // about six waves per CU, and short outage chunks (many waves in flight)
+  // about 3.5 waves per CU (longer streams per wave beat more waves: at 8316
+  // buses 512 buses per wave, 3.7 waves per CU, stream faster than 256 at
+  // 7.1), and short outage chunks (many waves in flight)
   {
     const int lt = (d.Lp / 4 + 63) / 64;
     int nc = 32;
-    for (int c : {256, 128, 64}) {
-      if ((int64_t)lt * ((h.N + c - 1) / c) >= 6LL * net->num_cus) {
+    for (int c : {512, 256, 128, 64}) {
+      if ((int64_t)lt * ((h.N + c - 1) / c) * 2 >= 7LL * net->num_cus) {
         nc = c;
         break;
       }
@@ -616,7 +618,7 @@ ibp_status ibp_autotune(ibp_network* net, int64_t n_box, const float* box_lo, co
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  const int ncs[] = {32, 64, 128, 256};
+  const int ncs[] = {32, 64, 128, 256, 512};
   const int kcs[] = {16, 32, 64, 128};
   float best = 1e30f;
   ibp::Tune best_t = net->tune;

@@ -603,7 +603,7 @@ __global__ __launch_bounds__(256) void k3_contingency(DevNet net, void* ws, WsLa
 // ---------------------------------------------------------------- launchers
 
 bool tune_valid(const Tune& t) {
-  const bool nc = t.k2_nc == 32 || t.k2_nc == 64 || t.k2_nc == 128 || t.k2_nc == 256;
+  const bool nc = t.k2_nc == 32 || t.k2_nc == 64 || t.k2_nc == 128 || t.k2_nc == 256 || t.k2_nc == 512;
   const bool kc = t.k3_kc == 16 || t.k3_kc == 32 || t.k3_kc == 64 || t.k3_kc == 128;
   return nc && kc;
 }
@@ -646,6 +646,7 @@ hipError_t launch_forward_single(const DevNet& net, int64_t n_box, const float* 
       case 32: launch_k2<32>(net, ws, lay, b0, nb, s, tm); break;
       case 64: launch_k2<64>(net, ws, lay, b0, nb, s, tm); break;
       case 256: launch_k2<256>(net, ws, lay, b0, nb, s, tm); break;
+      case 512: launch_k2<512>(net, ws, lay, b0, nb, s, tm); break;
       default: launch_k2<128>(net, ws, lay, b0, nb, s, tm); break;
     }
     tm->launch(4, k2e_lines, dim3((net.L + kK2eThreads - 1) / kK2eThreads, nb), dim3(kK2eThreads), s, net, ws,
@@ -680,6 +681,7 @@ hipError_t launch_forward_prep(const DevNet& net, int64_t n_box, const float* lo
         case 32: launch_k2<32>(net, ws, lay, b0, nb, s, tm); break;
         case 64: launch_k2<64>(net, ws, lay, b0, nb, s, tm); break;
         case 256: launch_k2<256>(net, ws, lay, b0, nb, s, tm); break;
+        case 512: launch_k2<512>(net, ws, lay, b0, nb, s, tm); break;
         default: launch_k2<128>(net, ws, lay, b0, nb, s, tm); break;
       }
     }

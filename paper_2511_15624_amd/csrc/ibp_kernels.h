@@ -48,7 +48,7 @@ struct KernelTimer {
 // Tile parameters of the streaming kernels (chosen by the autotuner or the
 // IBP_TILE environment variable, e.g. "k2nc=64,k3kc=32,k2b=0,ckb=4").
 struct Tune {
-  int k2_nc = 128;  // buses per wave in the base-flow sweep: 32, 64, 128 or 256
+  int k2_nc = 128;  // buses per wave in the base-flow sweep: 32, 64, 128, 256 or 512
   int k3_kc = 16;   // outages per block in the outage sweep: 16, 32, 64 or 128
   int k2b_mfma = 1; // box-tiled base flows on the float64 matrix cores (0: vector FMA)
   int chord_nb = 2; // boxes per lane in the box-tiled chord-relaxation sweep: 2 or 4

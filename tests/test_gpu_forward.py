@@ -255,7 +255,7 @@ def test_tile_choices_give_enclosing_bounds():
     net, fac, n = setup("c500")
     lo, hi = synth.full_box(net)
     r = orc(net, lo, hi, fac)
-    for nc in (32, 64, 128, 256):
+    for nc in (32, 64, 128, 256, 512):
         for kc in (16, 32, 64, 128):
             n.set_tile(nc, kc)
             f_lo, f_hi = gpu_bounds(n, lo, hi)
@@ -263,7 +263,7 @@ def test_tile_choices_give_enclosing_bounds():
     tl = torch.from_numpy(lo[None].copy()).cuda()
     th = torch.from_numpy(hi[None].copy()).cuda()
     nc, kc = ibp.ibp_autotune(n, tl, th)
-    assert nc in (32, 64, 128, 256) and kc in (16, 32, 64, 128)
+    assert nc in (32, 64, 128, 256, 512) and kc in (16, 32, 64, 128)
     f_lo, f_hi = gpu_bounds(n, lo, hi)
     assert_encloses(f_lo[0], f_hi[0], r, what="autotuned", strict_f=True)
 
