@@ -177,15 +177,37 @@ __global__ __launch_bounds__(256, 2) void k2b_base_flows_mfma(DevNet net, void* 
 
 // Outage sweep for kBT boxes x 256 lines per wave over one block row of outages.
 // SIDES as in k3_elem: one-sided calls compute only the penalty bound they need.
+//
+// Block order: blocks are dealt to the eight XCDs in turn, each XCD with its
+// own L2.  When the outage factors exceed the last-level cache (lay.k3_xcd),
+// the linear block index is remapped so that each XCD takes a contiguous
+// range of (line tile, outage block) tiles with all their box tiles: the
+// blocks resident on one XCD then stream the same factor rows, fetched into
+// its L2 once (8316 buses, 256 boxes: 5.05 -> 4.61 ms).  With the factors in
+// the last-level cache the plain order is faster (2000 buses: 27.3 against
+// 28.4 ms).  The order changes no sum.
 template <int SIDES>
 __global__ __launch_bounds__(256) void k3b_contingency(DevNet net, void* ws, WsLayout lay, int64_t n_box) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t b0 = ((int64_t)blockIdx.z * 4 + w) * kBT;
+  unsigned bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+  if (lay.k3_xcd) {
+    const unsigned gx = gridDim.x, gy = gridDim.y, gz = gridDim.z, nb = gx * gy * gz;
+    const unsigned bid = bx + gx * (by + gy * bz);
+    // XCD j = bid % 8 takes positions [start_j, start_j + count_j) of the
+    // tile-major order (count_j = nb / 8, plus one for the first nb % 8)
+    const unsigned j = bid & 7u, li = bid >> 3, q = nb >> 3, r = nb & 7u;
+    const unsigned p = (j < r ? j * (q + 1u) : r * (q + 1u) + (j - r) * q) + li;
+    bz = p % gz;
+    const unsigned d = p / gz;
+    bx = d % gx;
+    by = d / gx;
+  }
+  const int64_t b0 = ((int64_t)bz * 4 + w) * kBT;
   if (b0 >= n_box) return;
-  const int col = blockIdx.x * 64 + lane;
+  const int col = bx * 64 + lane;
   const int Lp4 = net.Lp / 4;
-  const int k0 = blockIdx.y * lay.k3_kper;
+  const int k0 = by * lay.k3_kper;
   const int k1 = min(net.K, k0 + lay.k3_kper);
   int64_t bb[kBT];
 #pragma unroll
@@ -276,7 +298,7 @@ __global__ __launch_bounds__(256) void k3b_contingency(DevNet net, void* ws, WsL
     const double ls = wave_sum(acc_lo[i]);
     if (lane == 0 && b0 + i < n_box) {
       double2* p3 = ws_ptr<double2>(ws, lay.p3) + (b0 + i) * lay.n_p3;
-      p3[blockIdx.y * gridDim.x + blockIdx.x] = make_double2(hs, ls);
+      p3[by * gridDim.x + bx] = make_double2(hs, ls);
     }
   }
 }
@@ -287,6 +309,8 @@ void plan_batched(const DevNet& net, int64_t n_box, WsLayout& lay, const Tune& t
   lay.n_p1 = (std::max(net.Np, net.X) + 63) / 64;
   lay.k2_bx = (lp4 + 63) / 64;
   lay.k2_gx = (lay.k2_bx + 7) / 8 * 8;  // blocks of one line tile share an XCD
+  // outage factors larger than the last-level cache: XCD-aware sweep order
+  lay.k3_xcd = (int64_t)net.K * net.Lp * 4 > (128ll << 20) ? 1 : 0;
   lay.k2_by = 1;
   lay.k2_chunk = net.N;
   if (t.k2b_mfma) {

@@ -513,7 +513,8 @@ __global__ __launch_bounds__(256) void kc5_finalize(DevNet net, void* ws, WsLayo
 // Box-tiled forms of KC1 and KC3: every lane keeps four lines of four boxes,
 // so each outage-factor or PTDF tile read from memory serves four boxes; the
 // box tile is the fastest-varying block index, so blocks that read the same
-// tile are dispatched together and share it through the L2.  The partial
+// tile are dispatched together (dealt across the eight XCDs, so each tile is
+// fetched into each XCD's L2 and shared there).  The partial
 // arrays they write are those of the per-box kernels, so KC2, KC4 and KC5 are
 // shared.
 constexpr int kCB = 4;     // boxes per tile
