@@ -796,7 +796,8 @@ __global__ __launch_bounds__(256, 2) void kc3m_ptdf_t(DevNet net, void* ws, WsLa
 // a sum of non-negative m (float32, relative error only) and two terms built
 // from the per-line slope totals (exact integers in units of 2^-24) and the
 // per-outage sums sum_l a Lam that the adjoint needs anyway.
-constexpr int kCKB = 32;  // outages per chord-sweep block
+constexpr int kCKB = 32;   // outages per block of the box-tiled chord sweep
+constexpr int kCKB1 = 64;  // outages per block of the per-box chord sweep (half the per-line totals)
 constexpr float kSlopeQ = 16777216.0f;  // 2^24
 
 // One element: fixed-point slope magnitude qa and signed slope qs
@@ -900,23 +901,25 @@ __device__ __forceinline__ void halving_sum32(float (&v)[32]) {
 }
 
 // Outage sweep of the chord relaxation: NB boxes per lane (1, or 2 or 4
-// sharing every streamed outage-factor tile), four lines per lane, kCKB
+// sharing every streamed outage-factor tile), four lines per lane, KB
 // outages per block; 8 / NB outages x NB boxes x 4 sums per halving
-// reduction.  Grid: (box tiles, line tiles, outage blocks).  Each element is a
-// long dependent chain, so occupancy decides the issue rate: MINB bounds the
+// reduction.  Grid: (box tiles, line tiles, outage blocks).  MINB bounds the
 // registers (one box: 6 waves per SIMD; two boxes: 5; four boxes: 3, the
-// most that holds four boxes' line data without spilling).
-template <int NB, int MINB>
+// most that holds four boxes' line data without spilling).  Each element is
+// a dependent chain of about 45 instructions with one reciprocal; the one-box
+// sweep's time did not move with 3 to 6 waves per SIMD or 16 to 64 outages
+// per block.
+template <int NB, int MINB, int KB>
 __global__ __launch_bounds__(256, MINB) void kc1c_chord(DevNet net, void* ws, WsLayout lay, int64_t n_box) {
   constexpr int OG = 8 / NB;
-  __shared__ float sh[4][kCKB][NB][4];
+  __shared__ float sh[4][KB][NB][4];
   const int64_t bt = (int64_t)blockIdx.x * NB;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int col = (blockIdx.y * 4 + w) * 64 + lane;
   const int Lp4 = net.Lp / 4;
-  const int k0 = blockIdx.z * kCKB;
-  const int k1 = min(net.K, k0 + kCKB);
+  const int k0 = blockIdx.z * KB;
+  const int k1 = min(net.K, k0 + KB);
   const bool live = col < Lp4;
   int64_t bb[NB];
 #pragma unroll
@@ -994,7 +997,7 @@ __global__ __launch_bounds__(256, MINB) void kc1c_chord(DevNet net, void* ws, Ws
   if (live && NB == 1 && lay.chp_z) {
     // one box: every block of outages targets the same lines, so atomics
     // would queue on the same addresses; each block stores its line totals
-    // (at most kCKB 2^24 each) for the line kernel to add up
+    // (at most KB 2^24 each) for the line kernel to add up
     int2* part = ws_ptr<int2>(ws, lay.chp) + ((size_t)bt * lay.chp_z + blockIdx.z) * net.Lp + 4 * col;
     reinterpret_cast<int4*>(part)[0] = make_int4(cs[0][0], ca[0][0], cs[0][1], ca[0][1]);
     reinterpret_cast<int4*>(part)[1] = make_int4(cs[0][2], ca[0][2], cs[0][3], ca[0][3]);
@@ -1163,13 +1166,13 @@ hipError_t launch_crown_lower(const DevNet& net, int64_t n_box, const float* lo,
     const int t = tm->start(10, s);
     const unsigned kz = (unsigned)((net.K + kCKB - 1) / kCKB);
     if (n_box < kCB)
-      hipLaunchKernelGGL((kc1c_chord<1, 5>), dim3((unsigned)n_box, lay.kc_bx, kz), dim3(256), 0, s, net, ws, lay,
-                         n_box);
-    else if (lay.chord_nb == 2)
-      hipLaunchKernelGGL((kc1c_chord<2, 5>), dim3((unsigned)((n_box + 1) / 2), lay.kc_bx, kz), dim3(256), 0, s,
+      hipLaunchKernelGGL((kc1c_chord<1, 5, kCKB1>), dim3((unsigned)n_box, lay.kc_bx, lay.chp_z), dim3(256), 0, s,
                          net, ws, lay, n_box);
+    else if (lay.chord_nb == 2)
+      hipLaunchKernelGGL((kc1c_chord<2, 5, kCKB>), dim3((unsigned)((n_box + 1) / 2), lay.kc_bx, kz), dim3(256), 0,
+                         s, net, ws, lay, n_box);
     else
-      hipLaunchKernelGGL((kc1c_chord<kCB, 1>), dim3((unsigned)((n_box + kCB - 1) / kCB), lay.kc_bx, kz),
+      hipLaunchKernelGGL((kc1c_chord<kCB, 1, kCKB>), dim3((unsigned)((n_box + kCB - 1) / kCB), lay.kc_bx, kz),
                          dim3(256), 0, s, net, ws, lay, n_box);
     tm->stop(t, s);
   }
@@ -1223,7 +1226,7 @@ void plan_crown(const DevNet& net, int64_t n_box, WsLayout& lay, const Tune& t) 
   lay.n_ct = (net.L + 255) / 256;
   lay.chord_nb = t.chord_nb;
   // (with no outages there is no sweep: the zeroed totals serve)
-  lay.chp_z = (n_box < kCB && net.K > 0) ? (net.K + kCKB - 1) / kCKB : 0;
+  lay.chp_z = (n_box < kCB && net.K > 0) ? (net.K + kCKB1 - 1) / kCKB1 : 0;
 }
 
 // Reference points: the box centre first, then halfway towards the vertex that
