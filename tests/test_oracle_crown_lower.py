@@ -3,7 +3,8 @@ against facts other than the oracle: with linear costs f is concave (linear
 surplus minus convex penalties), so its minimum over a box sits at a vertex and
 brute force over all 2^16 vertices of the 14-bus boxes gives it exactly; on a
 box that varies one coordinate, with outage limits out of reach, every IBP
-interval is exact and the relaxation equals that minimum; the linear function
+interval is exact and the relaxation equals that minimum, and so it does on
+boxes small enough that no interval holds a kink; the linear function
 the oracle assembles matches a direct per-element sum of the chord lines over
 flows from direct power-flow solves; IBP's f_lo is never tighter; zero-width
 boxes give the point value; planted mistakes fail.  No GPU."""
@@ -65,6 +66,26 @@ def test_exact_on_one_coordinate_boxes(tiny):
         assert c == pytest.approx(ends.min(), rel=1e-9, abs=1e-7)
         strict += oracle.ibp(net, a, b, fac)["f_lo"] < ends.min() - 1e-6 * abs(ends.min())
     assert strict >= 3
+
+
+def test_exact_where_f_is_affine_on_the_box(tiny):
+    """On boxes of relative half-width 1e-6 where no pre-activation interval
+    holds a kink (the upper relaxation reports no decision near switching),
+    every penalty is affine on its interval, so every chord is the penalty
+    itself, outage elements included: the bound equals the smallest of all
+    2^16 vertex values (direct power flow), and IBP's f_lo is strictly lower."""
+    net, fac = tiny
+    checked = 0
+    for a, b in _tiny_boxes(net, 8, seed=11, delta=1e-6):
+        if oracle.crown_upper(net, a, b, fac)["near"]:
+            continue
+        fv = oracle.point_eval_many(net, _vertices(a, b), fac["ctg"])
+        c = oracle.crown_lower(net, a, b, fac)
+        assert c["f_lo"] == pytest.approx(fv.min(), rel=1e-9, abs=1e-9)
+        assert c["n_active"] > 0
+        assert oracle.ibp(net, a, b, fac)["f_lo"] < fv.min() - 1e-9 * abs(fv.min())
+        checked += 1
+    assert checked >= 6
 
 
 def _imbalance(net, f, p):
