@@ -1102,10 +1102,12 @@ __global__ __launch_bounds__(256) void kc2c_lines(DevNet net, void* ws, WsLayout
       ev = (kKappa0 + net.ctg_eps[k] + gam + 12.0 * kU32) * A1 + 2.0 * net.phi_err_max * net.ctg_inv[k] * N * f32;
       v += V;
       va += A1 + ev;
-      // this line is the outage's own: c_c(k) = c_l
+      // this line is the outage's own: c_c(k) = c_l; V is within 12u A (float32
+      // within a wave) plus gam A (float64 over waves and tiles) of its exact value
       const double M1 = M * (1.0 + gam) * f32;
-      T += M1 - cl * V + fabs(cl) * 12.0 * kU32 * A1;
-      Ta += M1 + fabs(cl * V) + fabs(cl) * 12.0 * kU32 * A1;
+      const double eV = fabs(cl) * (12.0 * kU32 + gam) * A1;
+      T += M1 - cl * V + eV;
+      Ta += M1 + fabs(cl * V) + eV;
     }
     ev = (ev + 2.0 * kU64 * va) * (1.0 + 4.0 * kU64);
     va = va * (1.0 + 4.0 * kU64) + ev;
