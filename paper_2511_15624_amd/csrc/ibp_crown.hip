@@ -170,9 +170,11 @@ __device__ __forceinline__ void kc1_row(const float4& x, const int4& d, const fl
   r[2] = n;
 }
 
-// wsr: the reference points' forward workspace (REF), else unused.
+// wsr: the reference points' forward workspace (REF), else unused.  Four
+// waves per SIMD (111 registers, no spill) instead of the three the compiler
+// picks unbounded: 8316 buses, one box, 85 -> 76 us.
 template <bool REF>
-__global__ __launch_bounds__(256) void kc1_sweep(DevNet net, void* ws, const void* wsr, WsLayout lay,
+__global__ __launch_bounds__(256, 4) void kc1_sweep(DevNet net, void* ws, const void* wsr, WsLayout lay,
                                                  int64_t box0) {
   __shared__ double shv[4][kKC][2];
   __shared__ float shn[4][kKC];
