@@ -282,7 +282,7 @@ ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
     };
     lay.ccnt = take(B * d.Lp * 2 * sizeof(long long));  // int2 counts, or int64 slope totals
     lay.cv = take(B * lay.kc_bx * std::max(1, d.K) * 4 * sizeof(double));
-    lay.lv = take(B * d.Lp * 4 * sizeof(double));
+    lay.lv = take(std::max<size_t>(B, (size_t)lay.kc3_bt) * d.Lp * 4 * sizeof(double));
     lay.bpart = take(B * lay.kc3_bx * d.Np * 4 * sizeof(double));
     lay.cp = take(B * lay.n_cp * 2 * sizeof(double));
     lay.ct = take(B * lay.n_ct * 4 * sizeof(double));

@@ -253,6 +253,13 @@ __global__ __launch_bounds__(256, 4) void kc1_sweep(DevNet net, void* ws, const 
   }
 }
 
+// Position of line l of box b in the adjoint array: box-major for the per-box
+// and vector products, line-major (boxes contiguous) for the matrix-core
+// product, whose lanes then load 16 consecutive boxes of one line.
+__device__ __forceinline__ size_t lv_index(const WsLayout& lay, const DevNet& net, int64_t b, int l) {
+  return lay.kc3_mfma ? (size_t)l * lay.kc3_bt + b : (size_t)b * net.Lp + l;
+}
+
 // Per line: v, vabs >= |v_exact|, ev >= |v^ - v_exact|; block partials of the
 // limit total sum |s| t and of sum vabs.
 __global__ __launch_bounds__(256) void kc2_lines(DevNet net, void* ws, const void* wsr, WsLayout lay,
@@ -299,7 +306,7 @@ __global__ __launch_bounds__(256) void kc2_lines(DevNet net, void* ws, const voi
     ev = (ev + 2.0 * kU64 * va) * (1.0 + 4.0 * kU64);
     va = va * (1.0 + 4.0 * kU64) + ev;
   }
-  if (l < net.Lp) ws_ptr<double4>(ws, lay.lv)[b * net.Lp + l] = make_double4(v, va, ev, 0.0);
+  if (l < net.Lp) ws_ptr<double4>(ws, lay.lv)[lv_index(lay, net, b, l)] = make_double4(v, va, ev, 0.0);
   T = block_sum256(T, sh);
   const double S = block_sum256(va, sh);
   if (threadIdx.x == 0) ws_ptr<double4>(ws, lay.ct)[b * lay.n_ct + blockIdx.x] = make_double4(T, S, 0.0, 0.0);
@@ -724,9 +731,12 @@ __global__ __launch_bounds__(256, 2) void kc3m_ptdf_t(DevNet net, void* ws, WsLa
   const float4* pa0 = reinterpret_cast<const float4*>(net.phiT + (size_t)min(n0 + i16, net.N - 1) * net.Lp + 4 * k4);
   const float4* pa1 =
       reinterpret_cast<const float4*>(net.phiT + (size_t)min(n0 + 16 + i16, net.N - 1) * net.Lp + 4 * k4);
-  const double4* lv = ws_ptr<double4>(ws, lay.lv);
-  const double4* pb0 = lv + min(b0 + i16, n_box - 1) * net.Lp + 4 * k4;
-  const double4* pb1 = lv + min(b0 + 16 + i16, n_box - 1) * net.Lp + 4 * k4;
+  // line-major adjoint: lanes of one k4 read 16 consecutive boxes of a line
+  // (boxes past n_box up to the 32-box tile are in the allocation; their
+  // columns feed only outputs that are not written)
+  const size_t bt = lay.kc3_bt;
+  const double4* pb0 = ws_ptr<double4>(ws, lay.lv) + (size_t)(4 * k4) * bt + b0 + i16;
+  const double4* pb1 = pb0 + 16;
   v4d y[2][2], ya[2][2], ye[2][2];
 #pragma unroll
   for (int fi = 0; fi < 2; ++fi)
@@ -737,7 +747,7 @@ __global__ __launch_bounds__(256, 2) void kc3m_ptdf_t(DevNet net, void* ws, WsLa
     const float a0[4] = {x0.x, x0.y, x0.z, x0.w}, a1[4] = {x1.x, x1.y, x1.z, x1.w};
 #pragma unroll
     for (int st = 0; st < 4; ++st) {
-      const double4 q0 = pb0[l0 + st], q1 = pb1[l0 + st];
+      const double4 q0 = pb0[(size_t)(l0 + st) * bt], q1 = pb1[(size_t)(l0 + st) * bt];
       const double p0 = a0[st], p1 = a1[st];
       y[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(p0, q0.x, y[0][0], 0, 0, 0);
       y[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(p0, q1.x, y[0][1], 0, 0, 0);
@@ -1117,7 +1127,7 @@ __global__ __launch_bounds__(256) void kc2c_lines(DevNet net, void* ws, WsLayout
     T += 8.0 * kU64 * Ta;
     Ta *= (1.0 + 8.0 * kU64);
   }
-  if (l < net.Lp) ws_ptr<double4>(ws, lay.lv)[b * net.Lp + l] = make_double4(v, va, ev, 0.0);
+  if (l < net.Lp) ws_ptr<double4>(ws, lay.lv)[lv_index(lay, net, b, l)] = make_double4(v, va, ev, 0.0);
   T = block_sum256(T, sh);
   const double S = block_sum256(va, sh);
   Ta = block_sum256(Ta, sh);
@@ -1223,6 +1233,7 @@ void plan_crown(const DevNet& net, int64_t n_box, WsLayout& lay, const Tune& t) 
     int sc = (int)std::min<int64_t>(8, (2048 + blocks - 1) / blocks);
     sc = std::max(1, std::min(sc, net.Lp / 256));
     lay.kc3_mfma = 1;
+    lay.kc3_bt = (int)((n_box + 31) / 32 * 32);
     lay.kc3_chunk = ((net.Lp + sc - 1) / sc + 15) & ~15;
     lay.kc3_bx = (net.Lp + lay.kc3_chunk - 1) / lay.kc3_chunk;
   }

@@ -92,7 +92,8 @@ struct WsLayout {
   // linear-relaxation bound (present with the CROWN flag)
   size_t ccnt = 0;                 // int2 [B][Lp]: per-line (sum s, sum |s|) over outages
   size_t cv = 0;                   // double4 [B][kc_bx][K]: per-outage (sum s Lam, sum |s Lam|, count)
-  size_t lv = 0;                   // double4 [B][Lp]: per-line (v, vabs, ev)
+  size_t lv = 0;                   // double4 [B][Lp]: per-line (v, vabs, ev); [Lp][kc3_bt] with kc3_mfma
+  int kc3_bt = 0;                  // box stride of the line-major adjoint (n_box rounded up to 32)
   size_t bpart = 0;                // double4 [B][kc3_bx][Np]: per-bus (y, ya, ye) partials
   size_t cp = 0;                   // double2 [B][n_cp]: per-input partial sums
   size_t ct = 0;                   // double2 [B][n_ct]: per-line partial sums (limit total, sum vabs)
