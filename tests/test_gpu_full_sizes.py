@@ -6,7 +6,8 @@ tests; gradients to the 1e-3 relative L2 bar of the full-size backward test).
 
 - 2000 buses, 18 periods x 1024 sub-boxes in one call (18432 boxes);
 - 8316 buses, 256 sub-boxes in one call;
-- 2000 buses, backward over 4096 sub-boxes in one call.
+- 2000 buses, backward over 4096 sub-boxes in one call;
+- 8316 buses, the chord-relaxation lower bound over 256 sub-boxes.
 """
 import numpy as np
 import pytest
@@ -89,3 +90,22 @@ def test_more_boxes_than_one_tiled_launch():
     assert torch.equal(d_lo, e_lo[t]) and torch.equal(d_hi, e_hi[t])
     del tlo, thi, d_lo, d_hi
     torch.cuda.empty_cache()
+
+
+def test_c8316_256_boxes_lower_relaxation():
+    """The chord-relaxation lower bound at 256 sub-boxes of the 8316-bus network
+    (box-tiled sweep, line-major adjoint for the matrix-core product): every box
+    finite and combined with IBP's f_lo, sampled boxes equal to single-box calls
+    (per-box sweep) up to float64 summation order, and two boxes against the
+    oracle's relaxation."""
+    from tests.test_gpu_crown_lower import check_box, gpu_lower
+    net, fac, n = setup("c8316")
+    blo, bhi = synth.sub_boxes(net, 256, seed=41)
+    f_lo, f_hi, c = gpu_lower(n, blo, bhi)
+    i_lo, i_hi = gpu_bounds(n, blo, bhi)
+    assert np.all(np.isfinite(c)) and np.array_equal(f_lo, np.maximum(i_lo, c)) and np.array_equal(f_hi, i_hi)
+    for b in (0, 131, 255):
+        _, _, c1 = gpu_lower(n, blo[b], bhi[b])
+        assert abs(c1[0] - c[b]) <= 1e-9 * max(1.0, abs(c[b])), (b, c1[0], c[b])
+    for b in (0, 255):
+        check_box(net, fac, blo[b], bhi[b], f_lo[b], f_hi[b], c[b], i_lo[b], i_hi[b], f"c8316 chord box {b}")
