@@ -89,6 +89,7 @@ struct WsLayout {
   int k2_chunk = 0;                // batched base flows: buses per chunk (k2_by chunks, a multiple of 4)
   int k3_kper = 0;                 // batched outage sweep: outages per block row
   int k5_by = 0, k5_tiles = 0;     // backward outage sweep: outage chunks, line tiles
+  int k5_chunk = 0;                // outages per backward chunk
   // linear-relaxation bound (present with the CROWN flag)
   size_t ccnt = 0;                 // int2 [B][Lp]: per-line (sum s, sum |s|) over outages
   size_t cv = 0;                   // double4 [B][kc_bx][K]: per-outage (sum s Lam, sum |s Lam|, count)
