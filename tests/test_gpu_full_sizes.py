@@ -71,7 +71,8 @@ def test_c2000_backward_over_4096_boxes():
 
 def test_more_boxes_than_one_tiled_launch():
     """16 x 65535 + 37 boxes: the box-tiled path runs as two chunks; every box
-    gets exactly what the same box gets in a small call (forward and backward)."""
+    gets exactly what the same box gets in a small call (forward, backward and
+    the chord-relaxation lower bound)."""
     torch = _torch()
     net, fac, n = setup("tiny")
     blo, bhi = synth.sub_boxes(net, 23, seed=9)
@@ -88,7 +89,13 @@ def test_more_boxes_than_one_tiled_launch():
     torch.cuda.synchronize()
     t = torch.from_numpy(idx).cuda()
     assert torch.equal(d_lo, e_lo[t]) and torch.equal(d_hi, e_hi[t])
-    del tlo, thi, d_lo, d_hi
+    del d_lo, d_hi, e_lo, e_hi
+    # the chord-relaxation lower bound over the same chunked call
+    c_lo, c_hi, c = ibp.ibp_crown_lower_boxes(n, tlo, thi, crown=True)
+    s_lo, s_hi, sc = ibp.ibp_crown_lower_boxes(n, tlo[:23].contiguous(), thi[:23].contiguous(), crown=True)
+    torch.cuda.synchronize()
+    assert torch.equal(c, sc[t]) and torch.equal(c_lo, s_lo[t]) and torch.equal(c_hi, s_hi[t])
+    del tlo, thi, c_lo, c_hi, c
     torch.cuda.empty_cache()
 
 
