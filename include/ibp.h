@@ -174,6 +174,30 @@ ibp_status ibp_bound_boxes(const ibp_network* net, int64_t n_box,
                            double* f_lo, double* f_hi, double* terms,
                            void* ws, size_t ws_bytes, void* stream, uint32_t flags);
 
+/* ibp_bound_boxes_noalloc -- ibp_bound_boxes for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels and the same results, bit
+ * for bit, but the workspace is a library-owned device array of
+ * IBP_NOALLOC_SCRATCH_BYTES per GPU (reserved when the library's code is
+ * loaded on a device and held until the process ends; its address is taken at
+ * ibp_build_network, or at the first call on a device).  The call allocates
+ * nothing and queues no memset: every slot the kernels accumulate into is
+ * cleared by the first kernel of the call itself.
+ *   box_lo, box_hi, f_lo, f_hi, terms, flags: as for ibp_bound_boxes.
+ * Every call on one GPU shares that GPU's array and leaves its contents behind:
+ * calls that overlap in time on one GPU (on different streams, from different
+ * threads, or with different networks) race on it and must be serialised by the
+ * caller, for example by issuing them on one stream.
+ * Errors: INVALID_ARG, HOST_ONLY, DEVICE, and WORKSPACE when the call needs more
+ * than IBP_NOALLOC_SCRATCH_BYTES (ibp_workspace_bytes(net, n_box, flags) says
+ * how much; 32 MiB holds one box of an 8316-bus, 14000-line, 8000-outage
+ * network about fifteen times over). */
+#define IBP_NOALLOC_SCRATCH_BYTES (32u << 20)
+ibp_status ibp_bound_boxes_noalloc(const ibp_network* net, int64_t n_box,
+                                   const float* box_lo, const float* box_hi,
+                                   double* f_lo, double* f_hi, double* terms,
+                                   void* stream, uint32_t flags);
+
 /* ibp_bound_backward -- vector-Jacobian product of the (unpadded) IBP map:
  *   g_box_lo[b, j] = d(g_f_lo[b] f_lo[b] + g_f_hi[b] f_hi[b]) / d box_lo[b, j],
  *   g_box_hi likewise (device float64 [n_box x X], overwritten).

@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -27,9 +28,21 @@ struct ibp_network {
   ibp::Tune tune;
 };
 
+// Library-owned workspace of ibp_bound_boxes_noalloc: one copy per GPU the
+// library runs on, held until the process ends.  In host code the name is a
+// host-side stand-in, not a device address: kernels get the per-device address
+// taken by hipGetSymbolAddress (g_scratch below), never the name itself.
+static __device__ __align__(256) unsigned char scratch[IBP_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_err;
+
+// Device address of `scratch` on each device, taken once per device with that
+// device current (at network construction, or at the first no-allocation call).
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxScratchDevices] = {};
 
 ibp_status fail(ibp_status s, const std::string& msg) {
   g_err = msg;
@@ -37,6 +50,23 @@ ibp_status fail(ibp_status s, const std::string& msg) {
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Address of this device's `scratch` copy; the device must be current.
+ibp_status scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxScratchDevices)
+    return fail(IBP_E_DEVICE, "no-allocation scratch: device ordinal beyond " + std::to_string(kMaxScratchDevices));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(IBP_E_DEVICE, std::string("hipGetSymbolAddress of the scratch array failed: ") +
+                                    hipGetErrorString(e));
+    g_scratch[device] = p;
+  }
+  *out = g_scratch[device];
+  return IBP_OK;
+}
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
@@ -94,6 +124,11 @@ ibp_status to_device(ibp_network* net, int device) {
   DeviceGuard g(device);
   if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
   net->device = device;
+  {
+    void* sp = nullptr;
+    const ibp_status ss = scratch_address(device, &sp);
+    if (ss != IBP_OK) return ss;
+  }
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     net->num_cus = cus;
@@ -468,6 +503,45 @@ ibp_status ibp_bound_boxes(const ibp_network* net, int64_t n_box, const float* b
     if (e != hipSuccess) return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
     return IBP_OK;
   });
+}
+
+ibp_status ibp_bound_boxes_noalloc(const ibp_network* net, int64_t n_box, const float* box_lo,
+                                   const float* box_hi, double* f_lo, double* f_hi, double* terms, void* stream,
+                                   uint32_t flags) {
+  g_err.clear();
+  if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
+  if (net->device < 0) return fail(IBP_E_HOST_ONLY, "network was built host-only");
+  if (flags & ~uint32_t(IBP_F_PLAIN | IBP_F_UPPER_ONLY | IBP_F_LOWER_ONLY))
+    return fail(IBP_E_INVALID_ARG, "flags: only IBP_F_PLAIN, IBP_F_UPPER_ONLY and IBP_F_LOWER_ONLY are accepted");
+  if (n_box < 0) return fail(IBP_E_INVALID_ARG, "n_box < 0");
+  if (n_box == 0) return IBP_OK;
+  const size_t need = layout(net, n_box, flags).total;
+  if (need > IBP_NOALLOC_SCRATCH_BYTES)
+    return fail(IBP_E_WORKSPACE, std::to_string(n_box) + " boxes need " + std::to_string(need) +
+                                     " bytes of workspace, more than the " +
+                                     std::to_string((size_t)IBP_NOALLOC_SCRATCH_BYTES) +
+                                     " bytes of the library's scratch: use ibp_bound_boxes with a workspace, "
+                                     "or fewer boxes per call");
+  DeviceGuard g(net->device);
+  if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
+  void* ws = nullptr;
+  ibp_status st = scratch_address(net->device, &ws);
+  if (st != IBP_OK) return st;
+  ibp::WsLayout lay;
+  st = check_compute_args(net, n_box, box_lo, box_hi, f_lo, f_hi, ws, IBP_NOALLOC_SCRATCH_BYTES, flags, lay);
+  if (st != IBP_OK) return st;
+  // no kernel timing here: its events would be created per call
+  ibp::KernelTimer off;
+  const int64_t X = net->dn.X;
+  return for_chunks(net, n_box, flags, lay, IBP_NOALLOC_SCRATCH_BYTES,
+                    [&](int64_t b, int64_t nc, const ibp::WsLayout& lc) {
+                      hipError_t e = ibp::launch_forward(net->dn, nc, box_lo + b * X, box_hi + b * X, f_lo + b,
+                                                         f_hi + b, terms ? terms + 8 * b : nullptr, ws, lc,
+                                                         static_cast<hipStream_t>(stream), &off);
+                      if (e != hipSuccess)
+                        return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+                      return IBP_OK;
+                    });
 }
 
 ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box, const float* box_lo,

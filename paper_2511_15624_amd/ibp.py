@@ -48,6 +48,7 @@ EXPORTED = [
     "ibp_free_network",
     "ibp_workspace_bytes",
     "ibp_bound_boxes",
+    "ibp_bound_boxes_noalloc",
     "ibp_bound_backward",
     "ibp_crown_bound_boxes",
     "ibp_crown_lower_boxes",
@@ -152,6 +153,8 @@ def load_library(path: str = LIB_PATH):
     lib.ibp_workspace_bytes.restype = sz
     lib.ibp_bound_boxes.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, sz, vp, u32]
     lib.ibp_bound_boxes.restype = ctypes.c_int
+    lib.ibp_bound_boxes_noalloc.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, u32]
+    lib.ibp_bound_boxes_noalloc.restype = ctypes.c_int
     lib.ibp_bound_backward.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp, u32]
     lib.ibp_bound_backward.restype = ctypes.c_int
     lib.ibp_crown_bound_boxes.argtypes = [vp, i64, vp, vp, i32, vp, vp, vp, vp, vp, sz, vp, u32]
@@ -353,6 +356,26 @@ def ibp_bound_boxes(net: Network, lo, hi, terms: bool = False, flags: int = 0, w
                                           _dev_ptr(f_hi), _dev_ptr(t), _dev_ptr(buf), buf.numel(),
                                           _stream_ptr(stream), flags))
     return (f_lo, f_hi, t) if terms else (f_lo, f_hi)
+
+
+IBP_NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def ibp_bound_boxes_noalloc(net: Network, lo, hi, f_lo, f_hi, terms=None, flags: int = 0, stream=None):
+    """ibp_bound_boxes on the library's own scratch array: fills the caller's
+    float64 device tensors f_lo, f_hi [n_box] (and terms [n_box, 8] if given);
+    no workspace is allocated here or in the library."""
+    torch = _torch()
+    lo, hi = _check_boxes(net, lo, hi)
+    n = lo.shape[0]
+    for name, t, shape in (("f_lo", f_lo, (n,)), ("f_hi", f_hi, (n,)), ("terms", terms, (n, 8))):
+        if t is None and name == "terms":
+            continue
+        if (t is None or t.dtype != torch.float64 or tuple(t.shape) != shape or not t.is_contiguous()
+                or t.device != lo.device):
+            raise ValueError(f"{name} must be a contiguous float64 device tensor of shape {shape}")
+    _check(load_library().ibp_bound_boxes_noalloc(net.handle, n, _dev_ptr(lo), _dev_ptr(hi), _dev_ptr(f_lo),
+                                                  _dev_ptr(f_hi), _dev_ptr(terms), _stream_ptr(stream), flags))
 
 
 def ibp_bound_backward(net: Network, lo, hi, g_lo, g_hi, flags: int = 0, ws: Workspace = None,

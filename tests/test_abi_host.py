@@ -126,6 +126,10 @@ def test_compute_calls_need_a_device_handle(lib):
     assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"
     st = lib.ibp_bound_boxes(None, 1, None, None, None, None, None, None, 0, None, 0)
     assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"
+    st = lib.ibp_bound_boxes_noalloc(h.handle, 1, None, None, None, None, None, None, 0)
+    assert ibp.STATUS[st] == "IBP_E_HOST_ONLY"
+    st = lib.ibp_bound_boxes_noalloc(None, 1, None, None, None, None, None, None, 0)
+    assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"
     lib.ibp_free_network(None)
     info = ibp.NetworkInfo()
     assert ibp.STATUS[lib.ibp_network_query(None, ctypes.byref(info))] == "IBP_E_INVALID_ARG"
