@@ -21,6 +21,8 @@
 #include <limits>
 #include <cstring>
 #include <functional>
+#include <queue>
+#include <utility>
 #include <thread>
 #include <cstdlib>
 
@@ -290,6 +292,48 @@ void spd_inverse_from_cholesky(const double* C, int64_t n, std::vector<double>& 
 
 }  // namespace
 
+// Largest over buses of the least path resistance sum_j 1/b_j from the slack,
+// rounded up: every 1/b_j and every partial sum carries at most one float64
+// rounding, so (1 + 2 u)^(N + 1) >= 1 + 2.1 (N + 1) u covers them all.
+static double max_path_resistance(const HostNet& net) {
+  const int N = net.N, L = net.L;
+  std::vector<int> head(N + 1, 0), adj(2 * L);
+  for (int l = 0; l < L; ++l) {
+    head[net.line_from[l] + 1]++;
+    head[net.line_to[l] + 1]++;
+  }
+  for (int b = 0; b < N; ++b) head[b + 1] += head[b];
+  std::vector<int> fill(head.begin(), head.end() - 1);
+  for (int l = 0; l < L; ++l) {
+    adj[fill[net.line_from[l]]++] = l;
+    adj[fill[net.line_to[l]]++] = l;
+  }
+  std::vector<double> dist(N, std::numeric_limits<double>::infinity());
+  std::vector<uint8_t> done(N, 0);
+  using Item = std::pair<double, int>;
+  std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
+  dist[net.slack] = 0.0;
+  heap.push({0.0, net.slack});
+  while (!heap.empty()) {
+    const auto [d, v] = heap.top();
+    heap.pop();
+    if (done[v]) continue;
+    done[v] = 1;
+    for (int e = head[v]; e < head[v + 1]; ++e) {
+      const int l = adj[e];
+      const int w = net.line_from[l] == v ? net.line_to[l] : net.line_from[l];
+      const double nd = d + 1.0 / net.line_b[l];
+      if (nd < dist[w]) {
+        dist[w] = nd;
+        heap.push({nd, w});
+      }
+    }
+  }
+  double m = 0.0;
+  for (int b = 0; b < N; ++b) m = std::max(m, dist[b]);
+  return m * (1.0 + 2.1 * (N + 1) * std::ldexp(1.0, -53));
+}
+
 ibp_status build_host(const ibp_network_desc* d, HostNet& net, std::string& err) {
   auto t0 = std::chrono::steady_clock::now();
   if (!d) {
@@ -494,20 +538,14 @@ ibp_status build_host(const ibp_network_desc* d, HostNet& net, std::string& err)
 
   // a-posteriori PTDF error: residual R = Phi Y_B - Y_D E over non-slack columns,
   // row l:  R[l, m] = sum_j b_j (Phi[l, from_j] - Phi[l, to_j]) E[j, m] - b_l E[l, m].
-  // |Phi_r - Phi_exact| <= |R| |Y_Br^{-1}| <= ||R_l||_1 max|Y_Br^{-1}| per row.
-  double inv_max = 0.0;
-  for (int64_t i = 0; i < n; ++i) inv_max = std::max(inv_max, std::fabs(inv[i * n + i]));
-  {
-    std::vector<double> rowmax(n, 0.0);
-    parallel_for(n, 256, [&](int64_t a, int64_t b) {
-      for (int64_t i = a; i < b; ++i) {
-        double m = 0;
-        for (int64_t j = 0; j < n; ++j) m = std::max(m, std::fabs(inv[i * n + j]));
-        rowmax[i] = m;
-      }
-    });
-    for (int64_t i = 0; i < n; ++i) inv_max = std::max(inv_max, rowmax[i]);
-  }
+  // Phi_r - Phi_exact = R Y_Br^{-1}, so per row |Phi_r - Phi_exact| <= ||R_l||_1 max|Y_Br^{-1}|.
+  // max|Y_Br^{-1}| is bounded without trusting the computed inverse: Y_Br^{-1}
+  // is symmetric positive definite, so its largest entry is on the diagonal,
+  // and (Y_Br^{-1})_ii is the effective resistance between bus i and the slack
+  // in the network of conductances b; removing every line off one path can
+  // only raise it (Rayleigh monotonicity), so it is at most the resistance
+  // sum_j 1/b_j of the least-resistance path from the slack (Dijkstra).
+  const double inv_max = max_path_resistance(net);
   std::vector<double>().swap(inv);
   net.phi_err.assign(L, 0.0);
   {
@@ -550,9 +588,8 @@ ibp_status build_host(const ibp_network_desc* d, HostNet& net, std::string& err)
           fp += 2.0 * (deg + 4) * uext * (sa + net.line_b[l]);
         }
         r1 *= 1.0 + 4.0 * N * u64;
-        // residual plus the rounding error of forming it, times max|Y_Br^{-1}|,
-        // with a factor 2 for the error of the computed inverse itself
-        const double bound = 2.0 * (r1 + fp) * inv_max;
+        // residual plus the rounding error of forming it, times the bound on max|Y_Br^{-1}|
+        const double bound = (r1 + fp) * inv_max;
         net.phi_err[l] = bound + 1e-300;
       }
     });

@@ -167,3 +167,42 @@ def test_curve_descriptions_validated():
     _host(dict(net, seg_U=u)).close()
     with pytest.raises(ibp.IBPError):   # lengths are checked by the binding
         _host(dict(net, seg_a=net["seg_a"][:-1]))
+
+
+def test_ptdf_error_bound_holds_against_a_refined_solve():
+    """The library's a-posteriori bound on |Phi64 - Phi_exact| (reported as
+    phi_abs_err) against the PTDF of eq. (line flow ptdf) refined once from a
+    residual formed in 80-bit arithmetic: Phi_exact = Phi - R Y_Br^-1 with
+    R = Phi_r Y_Br - Y_D E_r, so the refined value is exact up to the tiny
+    error of applying an approximate inverse to a residual of order 1e-13.
+    Also: the bound's largest inverse entry (least path resistance from the
+    slack) is at least the largest entry of the inverse the oracle computes."""
+    net = synth.make_config("c500")
+    h = _host(net)
+    ptdf, _ = h.export()
+    fac = oracle.factors(net, with_paper_form=False)
+    keep = fac["keep"]
+    N, L = int(net["n_bus"]), ptdf.shape[0]
+    f, t = np.asarray(net["line_from"]), np.asarray(net["line_to"])
+    b = np.asarray(net["line_b"], float)
+    P = ptdf.astype(np.longdouble)
+    R = np.zeros((L, N), np.longdouble)
+    for j in range(L):
+        fj = np.longdouble(b[j]) * (P[:, f[j]] - P[:, t[j]])
+        R[:, f[j]] += fj
+        R[:, t[j]] -= fj
+    R[np.arange(L), f] -= np.longdouble(1.0) * b
+    R[np.arange(L), t] += np.longdouble(1.0) * b
+    Rr = np.asarray(R[:, keep], dtype=np.float64)
+    D = Rr @ fac["Binv"]                                # Phi_r - Phi_exact
+    err = float(np.max(np.abs(D)))
+    assert err > 0.0
+    assert err <= h.info.phi_abs_err, (err, h.info.phi_abs_err)
+    print(f"[ptdf error] refined {err:.3e}, bound {h.info.phi_abs_err:.3e}")
+    # the bound is an a-posteriori one, not a worst-case a-priori figure
+    assert h.info.phi_abs_err <= 1e4 * err
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import dijkstra
+    W = sp.coo_matrix((1.0 / b, (f, t)), shape=(N, N)).tocsr()
+    path = dijkstra(W, directed=False, indices=int(net["slack_bus"])).max()
+    assert np.max(np.abs(fac["Binv"])) <= np.max(np.diag(fac["Binv"])) <= path
