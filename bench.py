@@ -13,7 +13,9 @@ Prints ONE JSON line:
                          duration (HIP events on the launch stream) vs 8 TB/s
   step_roofline          the same for the whole step (PTDF + outage factors)
   cpu_baseline           the FP64 CPU oracle on the same box (host cores)
-  bound_gap_vs_fp64      relative distance of the GPU bounds to the oracle's
+  bound_gap_vs_fp64      relative distance of the GPU bounds to the oracle's, on
+                         the headline box and on samples of the sub-box workloads
+  paper_context          the paper's own timing (other hardware), for context
 """
 from __future__ import annotations
 
@@ -137,6 +139,24 @@ def _threads():
         return 1
 
 
+def host_info():
+    """Host cores, BLAS threads and CPU model, recorded beside the oracle's timings."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu_count": os.cpu_count(), "cpus_available": avail, "blas_threads": _threads(), "cpu_model": model}
+
+
 def cpu_baseline(net, lo, hi):
     """FP64 oracle on the same box, timed on the host (bound evaluation only)."""
     import oracle
@@ -146,12 +166,12 @@ def cpu_baseline(net, lo, hi):
     t0 = time.perf_counter()
     r = oracle.ibp(net, lo, hi, fac)
     t = time.perf_counter() - t0
-    return r, t, t_build, int(fac["K"])
+    return r, t, t_build, fac
 
 
 def cpu_batched_sample(synth, n_sample=4):
     """FP64 oracle on a seeded sample of the 2000-bus period boxes, per box
-    (bound evaluation only); returns (evals per box, seconds per box)."""
+    (bound evaluation only); returns (evals per box, seconds per box, factors)."""
     import oracle
     net3 = synth.make_config("c2000")
     fac = oracle.factors(net3)
@@ -161,7 +181,65 @@ def cpu_batched_sample(synth, n_sample=4):
     for b in idx:
         oracle.ibp(net3, lo[b], hi[b], fac)
     t = (time.perf_counter() - t0) / n_sample
-    return int(fac["K"]) * len(net3["line_from"]), t
+    return int(fac["K"]) * len(net3["line_from"]), t, fac
+
+
+def sub_box_gaps(torch, ibp, synth, n3, net3, fac3, n4, net4, fac4):
+    """Distance of the GPU bounds to the FP64 oracle's on seeded samples of the
+    sub-box workloads, each computed in the launch configuration timed above
+    (one call over every box of the workload): relative to max(|f|, 1 $), to
+    the term scale T (|S| + zeta_inj I + zeta_f (Fb + Fc) of that side), to the
+    error budget of the float32 padding rules (the largest gap they allow) and
+    to the floor that any method reading float32 factors must leave."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from tests.error_budget import budget
+
+    def gpu(n, lo, hi):
+        f_lo, f_hi = ibp.ibp_bound_boxes(n, torch.from_numpy(lo).cuda(), torch.from_numpy(hi).cuda())
+        torch.cuda.synchronize()
+        return f_lo.cpu().numpy(), f_hi.cpu().numpy()
+
+    rng = np.random.default_rng(2024)
+    lo3, hi3, _ = synth.period_boxes(net3, 18, 1024, seed=31)
+    lo5, hi5 = synth.sub_boxes(net3, 4096, seed=51)
+    lo4, hi4 = synth.sub_boxes(net4, 256, seed=41)
+    cases = [("2000 buses, 18 periods x 1024 sub-boxes (one call)", n3, net3, fac3, lo3, hi3, 48),
+             ("2000 buses, 4096 sub-boxes (one call)", n3, net3, fac3, lo5, hi5, 16),
+             ("8316 buses, 256 sub-boxes (one call)", n4, net4, fac4, lo4, hi4, 8)]
+    out = []
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        for what, n, net, fac, lo, hi, k in cases:
+            g_lo, g_hi = gpu(n, lo, hi)
+            idx = np.sort(rng.choice(lo.shape[0], k, replace=False))
+            pe = float(n.info.phi_abs_err)
+            t0 = time.perf_counter()
+            bus = list(ex.map(lambda b: budget(net, fac, lo[b], hi[b], pe), idx))
+            secs = time.perf_counter() - t0
+            rows = []
+            for b, bu in zip(idx, bus):
+                r = bu["r"]
+                glo, ghi = r["f_lo"] - g_lo[b], g_hi[b] - r["f_hi"]
+                flo, fhi = max(abs(r["f_lo"]), 1.0), max(abs(r["f_hi"]), 1.0)
+                rows.append([glo, ghi, glo / flo, ghi / fhi, glo / bu["T_lo"], ghi / bu["T_hi"],
+                             glo / bu["lo"], ghi / bu["hi"], glo / bu["floor_lo"], ghi / bu["floor_hi"],
+                             bu["lo"] / flo, bu["hi"] / fhi, bu["floor_lo"] / flo, bu["floor_hi"] / fhi])
+            a = np.array(rows)
+
+            def mm(j):
+                return {"max": float(a[:, j].max()), "median": float(np.median(a[:, j]))}
+
+            out.append({"workload": what, "boxes_sampled": int(k), "oracle_seconds": round(secs, 1),
+                        "encloses": bool(np.all(a[:, 0] >= 0) and np.all(a[:, 1] >= 0)),
+                        "lo_rel_f": mm(2), "hi_rel_f": mm(3), "lo_rel_T": mm(4), "hi_rel_T": mm(5),
+                        "over_1e-5_of_f": {"lo": int(np.sum(a[:, 2] > 1e-5)), "hi": int(np.sum(a[:, 3] > 1e-5))},
+                        "gap_over_budget": {"lo": mm(6), "hi": mm(7)},
+                        "gap_over_floor": {"lo": mm(8), "hi": mm(9)},
+                        "budget_over_1e-5_of_f": {"lo": int(np.sum(a[:, 10] > 1e-5)),
+                                                  "hi": int(np.sum(a[:, 11] > 1e-5))},
+                        "floor_over_1e-5_of_f": {"lo": int(np.sum(a[:, 12] > 1e-5)),
+                                                 "hi": int(np.sum(a[:, 13] > 1e-5))}})
+    return out
 
 
 def hbm_probe(torch, ibp):
@@ -574,15 +652,25 @@ def main(argv=None):
     out["step_roofline"]["frac_of_read_probe"] = round(step_gbs / probe["read_gbs"], 4)
     if not args.no_extras:
         out.update(extras(torch, ibp, synth, n, net))
+    out["paper_context"] = {
+        "figure": "mean IBP runtime per time index reaching 23.8 s on the largest instance (8316 buses, 11972 "
+                  "lines, 6289 N-1 outages), alpha,beta-CROWN on an NVIDIA H200, graph construction included; "
+                  "about 6289 x 11972 / 23.8 = 3.2e6 outage x line evaluations/s (derived, not printed)",
+        "source": "Sec. IV-B, Fig. 3; sizes in Table I",
+        "note": "context only: other hardware, software, instances and precision",
+    }
     if not args.no_cpu_baseline:
-        r, t_cpu, t_build, k_or = cpu_baseline(net, lo, hi)
-        out["cpu_baseline"] = {"value": evals / t_cpu, "unit": "evals/s", "cores": _threads(),
+        r, t_cpu, t_build, fac4 = cpu_baseline(net, lo, hi)
+        hinfo = host_info()
+        out["cpu_baseline"] = {"value": evals / t_cpu, "unit": "evals/s", "cores": hinfo["blas_threads"],
                                "kind": "oracle",
                                "sample": f"the full single box ({K} outages x {L} lines), FP64 "
                                          f"numpy; {t_cpu:.2f} s; factor construction "
-                                         f"{t_build:.1f} s not timed; elementwise stages single-threaded"}
+                                         f"{t_build:.1f} s not timed; matrix products on the BLAS threads "
+                                         f"(cores), elementwise stages single-threaded",
+                               "host": hinfo}
         if not args.no_extras:
-            ev3, t3 = cpu_batched_sample(synth)
+            ev3, t3, fac3 = cpu_batched_sample(synth)
             n_b3 = out["batched"]["ms_per_call"]
             out["cpu_baseline"]["batched_sample"] = {
                 "value": ev3 / t3, "unit": "evals/s", "seconds_per_box": t3,
@@ -597,6 +685,10 @@ def main(argv=None):
             "hi_rel": (g_hi - r["f_hi"]) / den_hi,
             "gpu": [g_lo, g_hi], "oracle": [r["f_lo"], r["f_hi"]],
         }
+        if not args.no_extras:
+            net3 = synth.make_config("c2000")
+            n3 = ibp.Network(net3, device=0)
+            out["bound_gap_vs_fp64"]["sub_boxes"] = sub_box_gaps(torch, ibp, synth, n3, net3, fac3, n, net, fac4)
     print(json.dumps(out), flush=True)
     return 0
 

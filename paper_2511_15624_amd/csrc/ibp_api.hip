@@ -146,7 +146,9 @@ ibp_status to_device(ibp_network* net, int device) {
   d.zeta_inj = h.zeta_inj;
   d.zeta_f = h.zeta_f;
   d.phi_err_max = h.phi_err_max;
-  d.gamma64_n = (double)(h.N + 64) * ibp::kU64 * 1.01;
+  // float64 sums of N products of a float32 PTDF entry and a float64
+  // injection: each step rounds the product (when not fused) and the sum
+  d.gamma64_n = (double)(2 * h.N + 64) * ibp::kU64 * 1.01;
 
   ibp_status st;
   {

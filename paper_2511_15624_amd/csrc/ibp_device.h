@@ -22,8 +22,8 @@ enum BoxSlot : int {
 
 // Fields of the per-block partial record written by the box-preparation kernel.
 enum P1Field : int {
-  kP1Mc = 0,   // sum |c32_n|
-  kP1Mbox,     // sum (|c32_n| + r32_n)
+  kP1Mc = 0,   // sum |c_n|
+  kP1Mbox,     // sum (|c_n| + r'_n)
   kP1Sc,       // sum w_j c_j        (surplus centre)
   kP1Sr,       // sum |w_j| r_j      (surplus radius)
   kP1Sabs,     // sum |w_j c_j| + |w_j| r_j

@@ -30,9 +30,11 @@ namespace ibp {
 
 // ---------------------------------------------------------------- K1
 
-// Injection interval of bus n, p_inj = N_g p_g - N_d p_d, rounded outward to
-// float32: out = (c32, r''), where r'' also covers the float32 storage error
-// of the PTDF entries it will multiply; mc = |c32|, mbox = |c32| + r32.  The
+// Injection interval of bus n, p_inj = N_g p_g - N_d p_d, in float64:
+// out = (c, r''), where r'' covers the summation error of c and r and the
+// float32 storage error of the PTDF entries it will multiply; mc = |c|,
+// mbox = |c| + r'.  The centre stays in float64 (the base-flow sweeps multiply
+// it in float64), so no float32 rounding of it enters the radius.  The
 // endpoints of the bus's first four devices are loaded together; further
 // devices (rare) follow in a loop.  Terms are added in device order.
 __device__ __forceinline__ void bus_injection(const DevNet& net, const float* __restrict__ lo,
@@ -64,15 +66,16 @@ __device__ __forceinline__ void bus_injection(const DevNet& net, const float* __
     const int j = net.bus_dev[e];
     add(j, lo[j], hi[j]);
   }
-  // float64 summation error of c and r (cnt terms each)
+  // float64 summation error of c and r (cnt terms each): the computed centre
+  // is off by at most e64, so the radius grows by 2 e64 (and by 4 u64 for the
+  // roundings of these additions)
   const double e64 = (cnt + 1) * kU64 * (a + r) * 1.01;
-  const float c32 = (float)c;
-  const float r32 = ru32((r + 2.0 * e64 + fabs(c - (double)c32)) * (1.0 + 4.0 * kU64));
+  const double r1 = (r + 2.0 * e64) * (1.0 + 4.0 * kU64);
   // radius inflated for the float32 rounding of the PTDF entries
-  const float rp = ru32(((1.0 + kKappa0) * (double)r32 + kKappa0 * fabs((double)c32)) * (1.0 + 4.0 * kU64));
-  out = make_double2((double)c32, (double)rp);
-  mc = fabs((double)c32);
-  mbox = fabs((double)c32) + (double)r32;
+  const double rp = ((1.0 + kKappa0) * r1 + kKappa0 * fabs(c)) * (1.0 + 4.0 * kU64);
+  out = make_double2(c, rp);
+  mc = fabs(c);
+  mbox = fabs(c) + r1;
 }
 
 // Per-input terms of the box-preparation sums: surplus (linear part and
@@ -173,7 +176,7 @@ __device__ __forceinline__ unsigned line_epilogue(const DevNet& net, int l, cons
                                                   double& pb_lo) {
   const double gam = net.gamma64_n;
   // enclosing radius around the float64 centre cf: float64 accumulation of
-  // |Phi32| r'' and Phi32 c32, and the float64 construction error of Phi
+  // |Phi32| r'' and Phi32 c, and the float64 construction error of Phi
   const double rf = (rh * (1.0 + 2.0 * gam) + gam * Mc + q.phi_err * Mbox) * (1.0 + 8.0 * kU64);
   const float cl = (float)cf;
   const double acl = fabs((double)cl);

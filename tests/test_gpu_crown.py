@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from paper_2511_15624_amd import ibp, synth
-from tests.test_gpu_forward import gpu_bounds, orc, setup, term_scale
+from tests.test_gpu_forward import gpu_bounds, orc_plain, setup, term_scale
 from tests.test_oracle_pins import _lp_max
 
 pytestmark = pytest.mark.gpu
@@ -35,7 +35,7 @@ def gpu_crown(n, lo, hi, flags=0):
 
 def check_box(net, fac, lo, hi, g_lo, g_hi, g_c, ibp_lo, ibp_hi, what):
     rc = oracle.crown_upper(net, lo, hi, fac)
-    ri = orc(net, lo, hi, fac)
+    ri = orc_plain(net, lo, hi, fac)
     # the combined outputs
     assert g_lo == ibp_lo, what
     assert g_hi == min(ibp_hi, g_c), what
@@ -157,7 +157,7 @@ def test_reference_point_relaxations_tiny(flags):
         assert f_hi[b] == min(i_hi[b], c1[b])
         if r["near"] == 0:
             # relative to max(|f|, term scale, 1 $), as for the IBP bounds
-            scale = max(abs(r["f_hi"]), term_scale(orc(net, blo[b], bhi[b], fac), "hi"), 1.0)
+            scale = max(abs(r["f_hi"]), term_scale(orc_plain(net, blo[b], bhi[b], fac), "hi"), 1.0)
             assert c1[b] >= r["f_hi"] and (c1[b] - r["f_hi"]) / scale <= 1e-5, (b, c1[b], r["f_hi"])
     _, _, c6 = gpu_crown_ref(n, blo, bhi, 6, flags=flags)
     reached = 0
@@ -178,7 +178,7 @@ def test_reference_point_relaxations_c500_and_c8316():
     for b in range(5):
         r = oracle.crown_upper_iterated(net, blo[b], bhi[b], fac, iters=2)
         assert c2[b] <= c0[b]
-        scale = max(abs(r["f_hi"]), term_scale(orc(net, blo[b], bhi[b], fac), "hi"), 1.0)
+        scale = max(abs(r["f_hi"]), term_scale(orc_plain(net, blo[b], bhi[b], fac), "hi"), 1.0)
         if r["near"] == 0:
             assert c2[b] >= r["f_hi"] and (c2[b] - r["f_hi"]) / scale <= 1e-5, (b, c2[b], r["f_hi"])
         print(f"[c500 box {b}] oracle {r['bounds']} gpu {c2[b]:.6e} near {r['near']}", flush=True)
@@ -188,7 +188,7 @@ def test_reference_point_relaxations_c500_and_c8316():
     r = oracle.crown_upper_iterated(net, lo, hi, fac, iters=1)
     print(f"[c8316] oracle {r['bounds']} gpu {c1[0]:.6e} near {r['near']}", flush=True)
     if r["near"] == 0:
-        scale = max(abs(r["f_hi"]), term_scale(orc(net, lo, hi, fac), "hi"), 1.0)
+        scale = max(abs(r["f_hi"]), term_scale(orc_plain(net, lo, hi, fac), "hi"), 1.0)
         assert c1[0] >= r["f_hi"] and (c1[0] - r["f_hi"]) / scale <= 1e-5
 
 

@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 from paper_2511_15624_amd import ibp, synth
-from tests.test_gpu_forward import gpu_bounds, orc, setup, term_scale
+from tests.test_gpu_forward import gpu_bounds, orc_plain, setup, term_scale
 from tests.test_oracle_crown import _vertices
 
 pytestmark = pytest.mark.gpu
@@ -39,7 +39,7 @@ def gpu_lower(n, lo, hi, flags=0, vertex=False):
 
 def check_box(net, fac, lo, hi, g_lo, g_hi, g_c, ibp_lo, ibp_hi, what):
     rc = oracle.crown_lower(net, lo, hi, fac)
-    ri = orc(net, lo, hi, fac)
+    ri = orc_plain(net, lo, hi, fac)
     assert g_hi == ibp_hi, what
     assert g_lo == max(ibp_lo, g_c), what
     scale = max(abs(rc["f_lo"]), term_scale(ri, "lo"), 1.0)

@@ -1,8 +1,17 @@
 """GPU parity of the forward bounds against the FP64 oracle (through the C ABI).
 
-Bar: the GPU interval encloses the oracle's (gpu_lo <= oracle_lo, gpu_hi >=
-oracle_hi, no slack) and lies within 1e-5 relative of it, relative to
-max(|oracle|, 1 $).
+Bar, per box and side:
+  * enclosure with no slack: gpu_lo <= oracle_lo and gpu_hi >= oracle_hi;
+  * the gap is at most the box's error budget (tests/error_budget.py): the
+    sum of the pads the float32 padding rules put on every element and line
+    whose penalty can be positive, derived from the magnitudes each pad covers
+    (about 4 u of them, u = 2^-24).  Measured gaps sit at about half their
+    budget, so a padding rule that doubled would fail this bar;
+  * on the whole boxes of the headline workloads (``strict_f``), the gap is
+    also within 1e-5 of max(|oracle|, 1 $).
+On sub-boxes whose terms cancel to a small |f| the budget can exceed 1e-5 of
+|f| (the objective is a difference of terms much larger than itself); bench.py
+reports how often that happens on the batched workloads.
 """
 import json
 import os
@@ -12,6 +21,7 @@ import pytest
 
 import oracle
 from paper_2511_15624_amd import ibp, synth
+from tests.error_budget import budget
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -36,8 +46,7 @@ def term_scale(r, side):
     """Magnitude of the objective's terms on one side: |S| + zeta_inj I + zeta_f (Fb + Fc).
 
     f is a difference of these terms; float32 arithmetic cannot resolve f more
-    finely than a small multiple of u times this scale, so the relative gap is
-    measured against max(|f|, this scale, 1 $) (equal to |f| when no
+    finely than a small multiple of u times this scale (equal to |f| when no
     cancellation occurs)."""
     net = r["_net"]
     if side == "hi":
@@ -45,26 +54,45 @@ def term_scale(r, side):
     return abs(r["S_lo"]) + net["zeta_inj"] * r["I_hi"] + net["zeta_f"] * (r["Fb_hi"] + r["Fc_hi"])
 
 
+# phi_abs_err of the device network each oracle factor set belongs to
+_PHI_ERR = {}
+
+
+def register(fac, n):
+    """Records the library network's PTDF error bound for the budget of boxes
+    evaluated with these oracle factors."""
+    _PHI_ERR[id(fac)] = (fac, float(n.info.phi_abs_err))
+
+
 def assert_encloses(g_lo, g_hi, r, tol=TOL, what="", strict_f=False):
-    """Enclosure with no slack, and gap <= tol relative to max(|f|, term scale, 1).
-    strict_f: also require gap <= tol relative to max(|f|, 1)."""
+    """Enclosure with no slack, and each side's gap within the box's error
+    budget; strict_f: also within tol relative to max(|f|, 1)."""
     o_lo, o_hi = r["f_lo"], r["f_hi"]
     assert g_lo <= o_lo, f"{what} lower bound not enclosing: gpu {g_lo!r} > oracle {o_lo!r}"
     assert g_hi >= o_hi, f"{what} upper bound not enclosing: gpu {g_hi!r} < oracle {o_hi!r}"
-    d_lo = max(abs(o_lo), 1.0)
-    d_hi = max(abs(o_hi), 1.0)
-    if "_net" in r:
-        d_lo = max(d_lo, term_scale(r, "lo"))
-        d_hi = max(d_hi, term_scale(r, "hi"))
+    bu = r["_budget"]
+    assert o_lo - g_lo <= bu["lo"], f"{what} lo gap {o_lo - g_lo!r} above its budget {bu['lo']!r}"
+    assert g_hi - o_hi <= bu["hi"], f"{what} hi gap {g_hi - o_hi!r} above its budget {bu['hi']!r}"
     if strict_f:
-        d_lo, d_hi = max(abs(o_lo), 1.0), max(abs(o_hi), 1.0)
-    assert (o_lo - g_lo) / d_lo <= tol, f"{what} lo gap {o_lo - g_lo!r} (oracle {o_lo!r})"
-    assert (g_hi - o_hi) / d_hi <= tol, f"{what} hi gap {g_hi - o_hi!r} (oracle {o_hi!r})"
+        assert (o_lo - g_lo) / max(abs(o_lo), 1.0) <= tol, f"{what} lo gap {o_lo - g_lo!r} (oracle {o_lo!r})"
+        assert (g_hi - o_hi) / max(abs(o_hi), 1.0) <= tol, f"{what} hi gap {g_hi - o_hi!r} (oracle {o_hi!r})"
+
+
+def orc_plain(net, lo, hi, fac):
+    """The oracle's bounds of one box (no error budget)."""
+    r = oracle.ibp(net, lo, hi, fac)
+    r["_net"] = net
+    return r
 
 
 def orc(net, lo, hi, fac):
-    r = oracle.ibp(net, lo, hi, fac)
+    """The oracle's bounds of one box with its error budget attached (the
+    factors must belong to a network passed to register() or setup())."""
+    assert id(fac) in _PHI_ERR, "register(fac, network) first"
+    bu = budget(net, fac, lo, hi, _PHI_ERR[id(fac)][1])
+    r = bu.pop("r")
     r["_net"] = net
+    r["_budget"] = bu
     return r
 
 
@@ -82,6 +110,7 @@ def setup(name):
         net = synth.make_config(name)
         print(f"[setup] {name}: building oracle factors and device network", flush=True)
         _cache[name] = (net, oracle.factors(net), ibp.Network(net, device=0))
+        register(_cache[name][1], _cache[name][2])
     return _cache[name]
 
 
@@ -212,6 +241,7 @@ def test_radial_network_without_outages_and_empty_batch():
     fac = oracle.factors(net)
     assert fac["K"] == 0
     n = ibp.Network(net, device=0)
+    register(fac, n)
     assert n.n_ctg == 0
     lo, hi = synth.full_box(net)
     blo, bhi = synth.sub_boxes(net, 6, seed=2)
@@ -236,6 +266,7 @@ def test_huge_limits_and_zero_penalties():
     f_lo, f_hi, t = gpu_bounds(n, blo, bhi, terms=True)
     assert np.all(t[:, 4:] == 0.0)
     fac = oracle.factors(big)
+    register(fac, n)
     for b in range(4):
         assert_encloses(f_lo[b], f_hi[b], orc(big, blo[b], bhi[b], fac), what=f"box {b}")
     z = dict(net, zeta_inj=0.0, zeta_f=0.0)
@@ -275,6 +306,7 @@ def test_distinct_contingency_limits():
     net = _emergency(synth.make_config("c500"), 4)
     fac = oracle.factors(net)
     n = ibp.Network(net, device=0)
+    register(fac, n)
     lo, hi = synth.full_box(net)
     blo, bhi = synth.sub_boxes(net, 7, seed=31)
     r = orc(net, lo, hi, fac)

@@ -8,7 +8,7 @@ import pytest
 import oracle
 from paper_2511_15624_amd import ibp, synth
 from tests.test_gpu_backward import gpu_grad, rel_l2
-from tests.test_gpu_forward import assert_encloses, assert_terms_enclose, gpu_bounds, orc
+from tests.test_gpu_forward import assert_encloses, assert_terms_enclose, gpu_bounds, orc, register
 
 pytestmark = pytest.mark.gpu
 
@@ -20,6 +20,7 @@ def setup_pwl(name, seed):
         net = synth.with_pwl_costs(synth.make_config(name), seed=seed)
         print(f"[setup] {name} with curves", flush=True)
         _cache[name] = (net, oracle.factors(net), ibp.Network(net, device=0))
+        register(_cache[name][1], _cache[name][2])
     return _cache[name]
 
 

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from paper_2511_15624_amd import ibp, synth
-from tests.test_gpu_forward import assert_encloses, gpu_bounds, orc
+from tests.test_gpu_forward import assert_encloses, gpu_bounds, orc, register
 
 pytestmark = pytest.mark.gpu
 
@@ -33,6 +33,7 @@ def test_random_network(case):
         net = synth.with_pwl_costs(net, seed=seed)
     fac = oracle.factors(net)
     n = ibp.Network(net, device=0)
+    register(fac, n)
     lo, hi = synth.full_box(net)
     blo, bhi = synth.sub_boxes(net, 9, seed=seed + 100)
     LO = np.vstack([lo[None], blo])
