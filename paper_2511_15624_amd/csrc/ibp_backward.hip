@@ -383,7 +383,9 @@ __global__ __launch_bounds__(256) void k6_ptdf_t(DevNet net, void* ws, WsLayout 
 // Many boxes: d c_inj[b, n] = sum_l dC[b, l] Phi[l, n] and d r_inj[b, n] =
 // sum_l dR[b, l] |Phi[l, n]| as one tiled product over lines.  Tile 64 boxes
 // x 64 buses, 32 lines per step staged in LDS; each thread owns a 4 x 4
-// micro-tile of both products (float32 accumulation).
+// micro-tile of both products.  Each step's 32 products are summed in
+// float32 and the step sums in float64, so the rounding error is that of
+// 32-term float32 sums rather than of one float32 sum over every line.
 constexpr int kGB = 64, kGN = 64, kGK = 32;
 
 __global__ __launch_bounds__(256) void k6b_ptdf_t_tiled(DevNet net, void* ws, WsLayout lay, int64_t n_box) {
@@ -396,13 +398,18 @@ __global__ __launch_bounds__(256) void k6b_ptdf_t_tiled(DevNet net, void* ws, Ws
   const int tm = t / 16, tn = t % 16;  // micro-tile row (boxes) and column (buses)
   const float* gc = ws_ptr<float>(ws, lay.gcf);
   const float* gr = ws_ptr<float>(ws, lay.grf);
-  float acc_c[4][4], acc_r[4][4];
+  double sum_c[4][4], sum_r[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc_c[i][j] = acc_r[i][j] = 0.0f;
+    for (int j = 0; j < 4; ++j) sum_c[i][j] = sum_r[i][j] = 0.0;
   // loader mapping: 64 rows x 32 lines = 512 float4 per operand -> 2 per thread
   for (int l0 = 0; l0 < net.Lp; l0 += kGK) {
+    float acc_c[4][4], acc_r[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc_c[i][j] = acc_r[i][j] = 0.0f;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int idx = t + q * 256;      // 0..511
@@ -438,6 +445,13 @@ __global__ __launch_bounds__(256) void k6b_ptdf_t_tiled(DevNet net, void* ws, Ws
           acc_r[i][j] = fmaf(ar[i], fabsf(bp[j]), acc_r[i][j]);
         }
     }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        sum_c[i][j] += (double)acc_c[i][j];
+        sum_r[i][j] += (double)acc_r[i][j];
+      }
     __syncthreads();
   }
   double* gci = ws_ptr<double>(ws, lay.gci);
@@ -450,8 +464,8 @@ __global__ __launch_bounds__(256) void k6b_ptdf_t_tiled(DevNet net, void* ws, Ws
     for (int j = 0; j < 4; ++j) {
       const int n = n0 + tn * 4 + j;
       if (n >= net.Np) continue;
-      gci[b * net.Np + n] = n < net.N ? (double)acc_c[i][j] : 0.0;
-      gri[b * net.Np + n] = n < net.N ? (double)acc_r[i][j] : 0.0;
+      gci[b * net.Np + n] = n < net.N ? sum_c[i][j] : 0.0;
+      gri[b * net.Np + n] = n < net.N ? sum_r[i][j] : 0.0;
     }
   }
 }

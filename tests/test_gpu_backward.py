@@ -176,3 +176,60 @@ def test_one_sided_backward_matches_zero_weights():
             assert torch.equal(x, y), float((x - y).abs().max())
     with pytest.raises(ValueError):
         ibp.ibp_bound_backward(n, tlo, thi, None, g)
+
+
+def test_c2000_gradient_against_central_differences_at_4096_boxes():
+    """The differentiation workload (2000 buses, 4096 sub-boxes, one backward
+    call per bound, as bench.py times it): on 8 seeded boxes and 64 seeded
+    endpoint coordinates each, the GPU's d f_lo and d f_hi agree with central
+    differences (step 1e-4, endpoints moved in float64) of the FP64 oracle's
+    bounds to 1e-4 relative, plus what float32 activity decisions can change:
+    the GPU decides each penalty's activity in float32, so an element within
+    float32 resolution of its kink may count where the oracle's does not, which
+    moves the gradient by zeta_f times that element's own gradient; those
+    elements are listed from the oracle's values and their effect on each
+    coordinate is added to the bar (tests/error_budget.py, flip_allowance).
+    A difference is used where it equals the oracle's analytic gradient to 1e-6
+    (the map is piecewise linear, so that holds where no kink lies within the
+    step); at least 48 of the 64 coordinates of every box and side, and 90% of
+    all, must pass that screen.  The GPU gradient of each box is also within 1e-4 relative L2 of
+    the oracle's over all coordinates."""
+    from tests.error_budget import budget, flip_allowance
+    from tests.fd_check import central_differences, coordinates
+    torch = _torch()
+    net, fac, n = setup("c2000")
+    blo, bhi = synth.sub_boxes(net, 4096, seed=51)
+    tlo, thi = torch.from_numpy(blo).cuda(), torch.from_numpy(bhi).cuda()
+    one = torch.ones(4096, dtype=torch.float64, device="cuda")
+    dl_lo, dl_hi = ibp.ibp_bound_backward(n, tlo, thi, one, None, flags=ibp.IBP_F_LOWER_ONLY)
+    dh_lo, dh_hi = ibp.ibp_bound_backward(n, tlo, thi, None, one, flags=ibp.IBP_F_UPPER_ONLY)
+    torch.cuda.synchronize()
+    gpu = {"lo": (dl_lo.cpu().numpy(), dl_hi.cpu().numpy()), "hi": (dh_lo.cpu().numpy(), dh_hi.cpu().numpy())}
+    del dl_lo, dl_hi, dh_lo, dh_hi
+    rng = np.random.default_rng(88)
+    h = 1e-4
+    worst, n_near, n_lin = 0.0, [], []
+    for b in np.sort(rng.choice(4096, 8, replace=False)):
+        coords = coordinates(blo[b], bhi[b], 64, h, rng)
+        fd = dict(zip(("lo", "hi"), central_differences(net, fac, blo[b], bhi[b], coords, h)))
+        bu = budget(net, fac, blo[b], bhi[b], n.info.phi_abs_err, near=True)
+        for side, gw in (("lo", (1.0, 0.0)), ("hi", (0.0, 1.0))):
+            o = oracle.grad(net, blo[b], bhi[b], gw[0], gw[1], fac)
+            g = gpu[side]
+            assert rel_l2(np.concatenate([g[0][b], g[1][b]]), np.concatenate(o[:2])) <= 1e-4, (b, side)
+            scale = max(np.max(np.abs(o[0])), np.max(np.abs(o[1])))
+            an = np.array([o[s][j] for s, j in coords])
+            got = np.array([g[s][b, j] for s, j in coords])
+            lin = np.abs(fd[side] - an) <= 1e-6 * np.maximum(np.abs(an), 1e-3 * scale)
+            assert lin.sum() >= 48, (b, side, int(lin.sum()))
+            n_lin.append(int(lin.sum()))
+            allow = flip_allowance(net, fac, bu["near_" + side])
+            n_near.append(len(bu["near_" + side]))
+            al = np.array([allow[s][j] for s, j in coords])
+            bar = 1e-4 * np.maximum(np.abs(fd[side]), 1e-3 * scale) + al
+            err = np.abs(got - fd[side])
+            assert np.all(err[lin] <= bar[lin]), (b, side, float(np.max((err - bar)[lin])))
+            worst = max(worst, float(np.max(err[lin] / bar[lin])))
+    assert sum(n_lin) >= 0.9 * 64 * len(n_lin), n_lin
+    print(f"[c2000 central differences] kink-free coordinates {n_lin}; elements near a kink per box and side "
+          f"{n_near}; largest error / bar {worst:.3f}", flush=True)
