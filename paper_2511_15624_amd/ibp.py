@@ -10,6 +10,7 @@ Python names mirror the C entry points: ``ibp_build_network``,
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 
@@ -311,6 +312,13 @@ def _stream_ptr(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _on(stream):
+    """Makes `stream` current for the allocations and the call: memory the
+    call's kernels use then belongs to the stream they run on, so the caching
+    allocator cannot hand it out while they still run."""
+    return contextlib.nullcontext() if stream is None else _torch().cuda.stream(stream)
+
+
 def _dev_ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p()
 
@@ -323,10 +331,14 @@ class Workspace:
         self.buf = None
 
     def get(self, n_box: int, flags: int = 0):
+        """The buffer (grown to the call's size) for a call on the current stream."""
         torch = _torch()
         need = self.net.workspace_bytes(n_box, flags)
         if self.buf is None or self.buf.numel() < need:
             self.buf = torch.empty(max(need, 256), dtype=torch.uint8, device=f"cuda:{self.net.device}")
+        else:
+            # used on this stream too: a later free must wait for its work
+            self.buf.record_stream(torch.cuda.current_stream(self.buf.device))
         return self.buf, need
 
 
@@ -343,18 +355,24 @@ def _check_boxes(net: Network, lo, hi):
 
 def ibp_bound_boxes(net: Network, lo, hi, terms: bool = False, flags: int = 0, ws: Workspace = None,
                     stream=None):
-    """Bounds [f_lo, f_hi] (float64 device tensors) for float32 device boxes [n_box, X]."""
+    """Bounds [f_lo, f_hi] (float64 device tensors) for float32 device boxes [n_box, X].
+
+    ``stream``: the kernels run there (default: the current stream); outputs
+    and a temporary workspace are then allocated on that stream.  The boxes
+    must be ready on it (the caller orders that), and the outputs are ready
+    once it has run them."""
     torch = _torch()
     lo, hi = _check_boxes(net, lo, hi)
     n = lo.shape[0]
-    f_lo = torch.empty(n, dtype=torch.float64, device=lo.device)
-    f_hi = torch.empty(n, dtype=torch.float64, device=lo.device)
-    t = torch.empty((n, 8), dtype=torch.float64, device=lo.device) if terms else None
-    ws = ws or Workspace(net)
-    buf, need = ws.get(n, flags)
-    _check(load_library().ibp_bound_boxes(net.handle, n, _dev_ptr(lo), _dev_ptr(hi), _dev_ptr(f_lo),
-                                          _dev_ptr(f_hi), _dev_ptr(t), _dev_ptr(buf), buf.numel(),
-                                          _stream_ptr(stream), flags))
+    with _on(stream):
+        f_lo = torch.empty(n, dtype=torch.float64, device=lo.device)
+        f_hi = torch.empty(n, dtype=torch.float64, device=lo.device)
+        t = torch.empty((n, 8), dtype=torch.float64, device=lo.device) if terms else None
+        ws = ws or Workspace(net)
+        buf, need = ws.get(n, flags)
+        _check(load_library().ibp_bound_boxes(net.handle, n, _dev_ptr(lo), _dev_ptr(hi), _dev_ptr(f_lo),
+                                              _dev_ptr(f_hi), _dev_ptr(t), _dev_ptr(buf), buf.numel(),
+                                              _stream_ptr(stream), flags))
     return (f_lo, f_hi, t) if terms else (f_lo, f_hi)
 
 
@@ -387,15 +405,16 @@ def ibp_bound_backward(net: Network, lo, hi, g_lo, g_hi, flags: int = 0, ws: Wor
     n = lo.shape[0]
     if g_lo is None and not flags & IBP_F_UPPER_ONLY or g_hi is None and not flags & IBP_F_LOWER_ONLY:
         raise ValueError("g_lo / g_hi may be None only with the matching one-sided flag")
-    g_lo = None if flags & IBP_F_UPPER_ONLY else g_lo.to(device=lo.device, dtype=torch.float64).contiguous()
-    g_hi = None if flags & IBP_F_LOWER_ONLY else g_hi.to(device=lo.device, dtype=torch.float64).contiguous()
-    d_lo = torch.empty((n, net.n_input), dtype=torch.float64, device=lo.device)
-    d_hi = torch.empty((n, net.n_input), dtype=torch.float64, device=lo.device)
-    ws = ws or Workspace(net)
-    buf, need = ws.get(n, flags | IBP_F_BACKWARD)
-    _check(load_library().ibp_bound_backward(net.handle, n, _dev_ptr(lo), _dev_ptr(hi), _dev_ptr(g_lo),
-                                             _dev_ptr(g_hi), _dev_ptr(d_lo), _dev_ptr(d_hi),
-                                             _dev_ptr(buf), buf.numel(), _stream_ptr(stream), flags))
+    with _on(stream):
+        g_lo = None if flags & IBP_F_UPPER_ONLY else g_lo.to(device=lo.device, dtype=torch.float64).contiguous()
+        g_hi = None if flags & IBP_F_LOWER_ONLY else g_hi.to(device=lo.device, dtype=torch.float64).contiguous()
+        d_lo = torch.empty((n, net.n_input), dtype=torch.float64, device=lo.device)
+        d_hi = torch.empty((n, net.n_input), dtype=torch.float64, device=lo.device)
+        ws = ws or Workspace(net)
+        buf, need = ws.get(n, flags | IBP_F_BACKWARD)
+        _check(load_library().ibp_bound_backward(net.handle, n, _dev_ptr(lo), _dev_ptr(hi), _dev_ptr(g_lo),
+                                                 _dev_ptr(g_hi), _dev_ptr(d_lo), _dev_ptr(d_hi),
+                                                 _dev_ptr(buf), buf.numel(), _stream_ptr(stream), flags))
     return d_lo, d_hi
 
 
@@ -409,17 +428,18 @@ def ibp_crown_bound_boxes(net: Network, lo, hi, crown: bool = False, flags: int 
     torch = _torch()
     lo, hi = _check_boxes(net, lo, hi)
     n = lo.shape[0]
-    f_lo = torch.empty(n, dtype=torch.float64, device=lo.device)
-    f_hi = torch.empty(n, dtype=torch.float64, device=lo.device)
-    c = torch.empty(n, dtype=torch.float64, device=lo.device) if crown else None
-    ws = ws or Workspace(net)
-    buf, need = ws.get(n, flags | IBP_F_CROWN | (IBP_F_CROWN_REF if ref_iters > 0 else 0))
     if vertex is not None and (vertex.dtype != torch.float32 or tuple(vertex.shape) != tuple(lo.shape)
                                or not vertex.is_contiguous() or vertex.device != lo.device):
         raise ValueError("vertex must be a contiguous float32 device tensor shaped like the boxes")
-    _check(load_library().ibp_crown_bound_boxes(net.handle, n, _dev_ptr(lo), _dev_ptr(hi), int(ref_iters),
-                                                _dev_ptr(f_lo), _dev_ptr(f_hi), _dev_ptr(c), _dev_ptr(vertex),
-                                                _dev_ptr(buf), buf.numel(), _stream_ptr(stream), flags))
+    with _on(stream):
+        f_lo = torch.empty(n, dtype=torch.float64, device=lo.device)
+        f_hi = torch.empty(n, dtype=torch.float64, device=lo.device)
+        c = torch.empty(n, dtype=torch.float64, device=lo.device) if crown else None
+        ws = ws or Workspace(net)
+        buf, need = ws.get(n, flags | IBP_F_CROWN | (IBP_F_CROWN_REF if ref_iters > 0 else 0))
+        _check(load_library().ibp_crown_bound_boxes(net.handle, n, _dev_ptr(lo), _dev_ptr(hi), int(ref_iters),
+                                                    _dev_ptr(f_lo), _dev_ptr(f_hi), _dev_ptr(c), _dev_ptr(vertex),
+                                                    _dev_ptr(buf), buf.numel(), _stream_ptr(stream), flags))
     return (f_lo, f_hi, c) if crown else (f_lo, f_hi)
 
 
@@ -432,17 +452,18 @@ def ibp_crown_lower_boxes(net: Network, lo, hi, crown: bool = False, flags: int 
     torch = _torch()
     lo, hi = _check_boxes(net, lo, hi)
     n = lo.shape[0]
-    f_lo = torch.empty(n, dtype=torch.float64, device=lo.device)
-    f_hi = torch.empty(n, dtype=torch.float64, device=lo.device)
-    c = torch.empty(n, dtype=torch.float64, device=lo.device) if crown else None
-    ws = ws or Workspace(net)
-    buf, need = ws.get(n, flags | IBP_F_CROWN)
     if vertex is not None and (vertex.dtype != torch.float32 or tuple(vertex.shape) != tuple(lo.shape)
                                or not vertex.is_contiguous() or vertex.device != lo.device):
         raise ValueError("vertex must be a contiguous float32 device tensor shaped like the boxes")
-    _check(load_library().ibp_crown_lower_boxes(net.handle, n, _dev_ptr(lo), _dev_ptr(hi), _dev_ptr(f_lo),
-                                                _dev_ptr(f_hi), _dev_ptr(c), _dev_ptr(vertex),
-                                                _dev_ptr(buf), buf.numel(), _stream_ptr(stream), flags))
+    with _on(stream):
+        f_lo = torch.empty(n, dtype=torch.float64, device=lo.device)
+        f_hi = torch.empty(n, dtype=torch.float64, device=lo.device)
+        c = torch.empty(n, dtype=torch.float64, device=lo.device) if crown else None
+        ws = ws or Workspace(net)
+        buf, need = ws.get(n, flags | IBP_F_CROWN)
+        _check(load_library().ibp_crown_lower_boxes(net.handle, n, _dev_ptr(lo), _dev_ptr(hi), _dev_ptr(f_lo),
+                                                    _dev_ptr(f_hi), _dev_ptr(c), _dev_ptr(vertex),
+                                                    _dev_ptr(buf), buf.numel(), _stream_ptr(stream), flags))
     return (f_lo, f_hi, c) if crown else (f_lo, f_hi)
 
 
@@ -464,8 +485,9 @@ def ibp_autotune(net: Network, lo, hi, stream=None):
     lo, hi = _check_boxes(net, lo, hi)
     n = lo.shape[0]
     need = net.workspace_bytes(n, IBP_F_AUTOTUNE)
-    buf = torch.empty(max(need, 256), dtype=torch.uint8, device=lo.device)
     chosen = np.zeros(2, np.int32)
-    _check(load_library().ibp_autotune(net.handle, n, _dev_ptr(lo), _dev_ptr(hi), _dev_ptr(buf), buf.numel(),
-                                       _stream_ptr(stream), chosen.ctypes.data_as(ctypes.c_void_p)))
+    with _on(stream):
+        buf = torch.empty(max(need, 256), dtype=torch.uint8, device=lo.device)
+        _check(load_library().ibp_autotune(net.handle, n, _dev_ptr(lo), _dev_ptr(hi), _dev_ptr(buf), buf.numel(),
+                                           _stream_ptr(stream), chosen.ctypes.data_as(ctypes.c_void_p)))
     return int(chosen[0]), int(chosen[1])

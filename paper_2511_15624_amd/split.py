@@ -119,14 +119,20 @@ class BranchAndBound:
     def screen(self, stream=None):
         """Classifies every root and compacts the open list; returns the open count."""
         lib = _ibp.load_library()
-        _ibp._check(lib.ibp_split_screen(self.R, _p(self.root_ub), _p(self.root_lb), self.rel_tol,
-                                         _p(self.status), _p(self.open_roots), _p(self.n_open_dev),
-                                         _ibp._stream_ptr(stream)))
-        self.n_open = int(self.n_open_dev.item())
+        with _ibp._on(stream):
+            _ibp._check(lib.ibp_split_screen(self.R, _p(self.root_ub), _p(self.root_lb), self.rel_tol,
+                                             _p(self.status), _p(self.open_roots), _p(self.n_open_dev),
+                                             _ibp._stream_ptr(stream)))
+            self.n_open = int(self.n_open_dev.item())      # waits for this stream
         return self.n_open
 
     def step(self, stream=None):
-        """One round over the open roots; returns False when none is open."""
+        """One round over the open roots, queued on `stream` (default: the
+        current stream); returns False when none is open."""
+        with _ibp._on(stream):
+            return self._step(stream)
+
+    def _step(self, stream):
         n = self.n_open if self.screen_on else self.R
         if n == 0:
             return False
