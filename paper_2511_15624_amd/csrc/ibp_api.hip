@@ -305,6 +305,7 @@ ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
     lay.grf = take(B * d.Lp * sizeof(float));
     lay.gci = take(B * d.Np * sizeof(double));
     lay.gri = take(B * d.Np * sizeof(double));
+    if (lay.batched && d.K > 0) lay.cb = take(B * d.K * 2 * sizeof(float));
     lay.total = off;
   }
   if (flags & (IBP_F_CROWN | IBP_F_CROWN_REF)) {

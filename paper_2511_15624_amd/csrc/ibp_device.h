@@ -77,12 +77,14 @@ struct WsLayout {
   size_t cpart = 0;                // float2 [B][k5_tiles][K]: backward per-outage partials
   size_t gcf = 0, grf = 0;         // float [B][Lp]: backward line gradients (centre, radius)
   size_t gci = 0, gri = 0;         // double [B][Np]: backward injection gradients
+  size_t cb = 0;                   // float2 [B][K]: backward per-outage (centre, unpadded radius); 0: absent
   size_t total = 0;
   int n_p1 = 0, n_p2 = 0, n_p3 = 0;
   int k2_bx = 0, k2_by = 0;        // K2 grid per box (line tiles x bus chunks)
   int k3_bx = 0, k3_by = 0;        // K3 grid per box (line tiles x outage chunks)
   int k2_nc = 0, k3_kc = 0;        // tile parameters used
   int batched = 0;                 // 1: box-tiled kernels (boxes share every streamed tile)
+  int small = 0;                   // 1: smallest networks, one launch and one block per box (km_box)
   int sides = 3;                   // penalty sides of the outage sweep: 3 both, 1 lower (f_hi), 2 upper (f_lo)
   int k2_gx = 0;                   // batched base flows: grid x (line tiles padded to a multiple of 8)
   int k2_mfma = 0;                 // batched base flows on the float64 matrix cores

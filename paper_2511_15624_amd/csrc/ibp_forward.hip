@@ -172,8 +172,8 @@ __device__ __forceinline__ LineConst load_line_const(const DevNet& net, int l) {
 // is an outage line (0 otherwise), for the caller's max reduction.
 __device__ __forceinline__ unsigned line_epilogue(const DevNet& net, int l, const LineConst& q, double cf,
                                                   double rh, double Mc, double Mbox, float* lc, float* lh,
-                                                  float* lg, double* lcf, double* lrf, int4* ctg, double& pb_hi,
-                                                  double& pb_lo) {
+                                                  float* lg, double* lcf, double* lrf, int4* ctg, float2* cb,
+                                                  double& pb_hi, double& pb_lo) {
   const double gam = net.gamma64_n;
   // enclosing radius around the float64 centre cf: float64 accumulation of
   // |Phi32| r'' and Phi32 c, and the float64 construction error of Phi
@@ -208,6 +208,9 @@ __device__ __forceinline__ unsigned line_epilogue(const DevNet& net, int l, cons
     const double rkp = ((rk + u1 * acl) * inv1md) * (1.0 + 16.0 * kU64) + 1e-36;
     // fourth field: the unpadded radius, read by the backward sweep
     ctg[q.k] = make_int4(l, __float_as_int(cl), __float_as_int(ru32(rkp)), __float_as_int((float)rf));
+    // the box-tiled backward sweep reads (centre, unpadded radius) of four
+    // outages as two 16-byte scalar loads
+    if (cb) cb[q.k] = make_float2(cl, (float)rf);
     const float v = ru32((acl + rl) * q.ctg.y * (1.0 + 4.0 * kU64));
     return __float_as_uint(v);
   }
@@ -284,8 +287,8 @@ __global__ __launch_bounds__(kK2eThreads) void k2e_lines(DevNet net, void* ws, W
     vm = line_epilogue(net, l, q, (cf[0] + cf[1]) + (cf[2] + cf[3]), (rh[0] + rh[1]) + (rh[2] + rh[3]), mc, mb,
                        ws_ptr<float>(ws, lay.lc) + b * net.Lp, ws_ptr<float>(ws, lay.lh) + b * net.Lp,
                        ws_ptr<float>(ws, lay.lg) + b * net.Lp, ws_ptr<double>(ws, lay.lcf) + b * net.L,
-                       ws_ptr<double>(ws, lay.lrf) + b * net.L, ws_ptr<int4>(ws, lay.ctg) + b * net.K, pb_hi,
-                       pb_lo);
+                       ws_ptr<double>(ws, lay.lrf) + b * net.L, ws_ptr<int4>(ws, lay.ctg) + b * net.K,
+                       lay.cb ? ws_ptr<float2>(ws, lay.cb) + b * net.K : nullptr, pb_hi, pb_lo);
   // max over the wave (non-negative floats order like their bit patterns)
   vm = wave_max_u32(vm);
   pb_hi = wave_sum(pb_hi);
@@ -379,6 +382,10 @@ __global__ __launch_bounds__(256) void k2_base_flows(DevNet net, void* ws, WsLay
 
 // ---------------------------------------------------------------- K4
 
+__device__ __forceinline__ void objective_interval(const DevNet& net, const WsLayout& lay, int64_t b,
+                                                   const double (&x)[12], double* __restrict__ f_lo,
+                                                   double* __restrict__ f_hi, double* __restrict__ terms);
+
 // Objective interval of one box from all partial sums, run by one block of T
 // threads after every partial is visible.  The first T partials of each kind
 // are loaded in one group (clamped indices, masked adds); loops take the rest.
@@ -457,10 +464,21 @@ __device__ void finalize_box(const DevNet& net, void* ws, const WsLayout& lay, i
   if (tid != 0) return;
 #pragma unroll
   for (int f = 0; f < 12; ++f) x[f] = tot[f];
+  objective_interval(net, lay, b, x, f_lo, f_hi, terms);
+}
+
+// Objective interval of box b from its summed terms: x[0..7] the box-
+// preparation fields from kP1Sc on (surplus centre, radius and magnitude,
+// total injection centre, radius and magnitude, invalid count), x[8], x[9]
+// the base penalties (hi, lo), x[10], x[11] the outage penalties (hi, lo).
+__device__ __forceinline__ void objective_interval(const DevNet& net, const WsLayout& lay, int64_t b,
+                                                   const double (&x)[12], double* __restrict__ f_lo,
+                                                   double* __restrict__ f_hi, double* __restrict__ terms) {
+  double v[kP1Fields];
 #pragma unroll
   for (int f = 0; f < 8; ++f) v[kP1Sc + f] = x[f];
-  bh = x[8];
-  bl = x[9];
+  const double bh = x[8];
+  const double bl = x[9];
   // one-sided calls: the side not computed is bounded trivially (upper bound
   // of the outage penalties +inf, lower bound 0)
   const double chs = lay.sides == 1 ? INFINITY : x[10];
@@ -537,20 +555,19 @@ static void launch_k4(const DevNet& net, void* ws, const WsLayout& lay, int64_t 
 // max(NaN, 0) = 0 (IEEE maxNum), which removes it (the paper's mask M)
 // without a branch.  Eight penalties are summed in float32 (three levels)
 // before the float64 accumulation; K4 scales the totals by (1 +- 4u) for that.
+// The outage sweep of one block: four waves x 256 lines (float4 column `col`
+// of each lane) x outages [k0, k1) of box b, with the construction-error
+// padding of the box's vmax; returns the block's penalty sums (hi, lo) in
+// thread 0.
 template <int KC>
-__global__ __launch_bounds__(256) void k3_contingency(DevNet net, void* ws, WsLayout lay, int64_t box0) {
+__device__ __forceinline__ double2 k3_block(const DevNet& net, void* ws, const WsLayout& lay, int64_t b, int col,
+                                            int k0, int k1, float vmax) {
   __shared__ double sh[8];
-  const int64_t b = box0 + blockIdx.z;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int col = (blockIdx.x * 4 + w) * 64 + lane;  // float4 column
   const int Lp4 = net.Lp / 4;
-  const int k0 = blockIdx.y * KC;
-  const int k1 = min(net.K, k0 + KC);
   double acc_hi = 0.0, acc_lo = 0.0;
   if (col < Lp4) {
-    const double* bs = ws_ptr<double>(ws, lay.box) + b * kBoxSlots;
-    const float vmax = __uint_as_float(*reinterpret_cast<const unsigned int*>(bs + kVmax));
     const float4 c4 = reinterpret_cast<const float4*>(ws_ptr<float>(ws, lay.lc) + b * net.Lp)[col];
     float4 h4 = reinterpret_cast<const float4*>(ws_ptr<float>(ws, lay.lh) + b * net.Lp)[col];
     float4 g4 = reinterpret_cast<const float4*>(ws_ptr<float>(ws, lay.lg) + b * net.Lp)[col];
@@ -594,11 +611,180 @@ __global__ __launch_bounds__(256) void k3_contingency(DevNet net, void* ws, WsLa
     sh[4 + w] = acc_lo;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double2* p3 = ws_ptr<double2>(ws, lay.p3) + b * lay.n_p3;
-    p3[blockIdx.y * gridDim.x + blockIdx.x] =
-        make_double2((sh[0] + sh[1]) + (sh[2] + sh[3]), (sh[4] + sh[5]) + (sh[6] + sh[7]));
+  return make_double2((sh[0] + sh[1]) + (sh[2] + sh[3]), (sh[4] + sh[5]) + (sh[6] + sh[7]));
+}
+
+template <int KC>
+__global__ __launch_bounds__(256) void k3_contingency(DevNet net, void* ws, WsLayout lay, int64_t box0) {
+  const int64_t b = box0 + blockIdx.z;
+  const int col = (blockIdx.x * 4 + (int)(threadIdx.x >> 6)) * 64 + (int)(threadIdx.x & 63);  // float4 column
+  const double* bs = ws_ptr<double>(ws, lay.box) + b * kBoxSlots;
+  const float vmax = __uint_as_float(*reinterpret_cast<const unsigned int*>(bs + kVmax));
+  const int k0 = blockIdx.y * KC;
+  const double2 t = k3_block<KC>(net, ws, lay, b, col, k0, min(net.K, k0 + KC), vmax);
+  if (threadIdx.x == 0) ws_ptr<double2>(ws, lay.p3)[b * lay.n_p3 + blockIdx.y * gridDim.x + blockIdx.x] = t;
+}
+
+// ---------------------------------------------------------------- small networks
+
+// One block per box for the smallest networks (at most kMicroBuses buses,
+// kMicroLines lines and kMicroElems outage elements).  A dispatch costs about
+// 2.4 us on this part, so the five dependent launches of the general path
+// dominate such calls (18.4 us at 14 buses); here the whole call is one
+// launch and one block, its phases separated by block barriers, every
+// intermediate in LDS (the workspace receives the per-line data and the
+// box-preparation record too, for the relaxation and backward kernels that
+// read them).  The arithmetic is that of the multi-kernel path (the same
+// device functions; the outage elements in pairs of outages, k3_pair, so the
+// float32 penalty sums have the same depth), so the padding is unchanged.
+// Every load that does not depend on another is issued before the first use.
+// SWEEP = false stops after the line epilogue (the backward's preparation).
+constexpr int kMicroBuses = 256;
+constexpr int kMicroLines = 1024;
+constexpr int kMicroElems = 65536;
+
+template <bool SWEEP>
+__global__ __launch_bounds__(256) void km_box(DevNet net, const float* __restrict__ box_lo,
+                                              const float* __restrict__ box_hi, void* ws, WsLayout lay, int64_t box0,
+                                              double* __restrict__ f_lo, double* __restrict__ f_hi,
+                                              double* __restrict__ terms) {
+  __shared__ double2 inj[kMicroBuses];
+  __shared__ float s_lc[kMicroLines], s_lh[kMicroLines], s_lg[kMicroLines];
+  __shared__ int4 s_ctg[kMicroElems / 64];
+  __shared__ double red[4][kP1Fields + 4];
+  __shared__ unsigned redm[4];
+  const int64_t b = box0 + blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const float* lo = box_lo + b * net.X;
+  const float* hi = box_hi + b * net.X;
+  // line constants of this thread's first line, loaded with the box
+  const int l0 = min(tid, net.L - 1);
+  const LineConst q0 = load_line_const(net, l0);
+  double v[kP1Fields];
+#pragma unroll
+  for (int f = 0; f < kP1Fields; ++f) v[f] = 0.0;
+  if (tid < net.N) {
+    double2 cr;
+    bus_injection(net, lo, hi, tid, cr, v[kP1Mc], v[kP1Mbox]);
+    inj[tid] = cr;
   }
+  for (int i = tid; i < net.X; i += 256) input_terms(net, i, lo[i], hi[i], net.dev_w[i], v);
+  box_slots_init(net, ws, lay, b);
+  for (int l = net.L + tid; l < net.Lp; l += 256) {
+    s_lc[l] = 0.0f;
+    s_lh[l] = -FLT_MAX;
+    s_lg[l] = FLT_MAX;
+  }
+#pragma unroll
+  for (int f = 0; f < kP1Fields; ++f) v[f] = wave_sum(v[f]);
+  if (lane == 0)
+#pragma unroll
+    for (int f = 0; f < kP1Fields; ++f) red[w][f] = v[f];
+  __syncthreads();
+#pragma unroll
+  for (int f = 0; f < kP1Fields; ++f) v[f] = (red[0][f] + red[1][f]) + (red[2][f] + red[3][f]);
+  if (tid < kP1Fields) ws_ptr<double>(ws, lay.p1)[b * kP1Fields + tid] = v[tid];
+  const double g = (net.N + 64) * kU64 * 1.01;
+  const double mc = v[kP1Mc] * (1.0 + g), mb = v[kP1Mbox] * (1.0 + g);
+
+  // base flows (sixteen PTDF loads in flight per step) and the line epilogue
+  double pb_hi = 0.0, pb_lo = 0.0;
+  unsigned vm = 0u;
+  for (int l = tid; l < net.L; l += 256) {
+    double cf = 0.0, rh = 0.0;
+    for (int n0 = 0; n0 < net.N; n0 += 16) {
+      float x[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) x[u] = n0 + u < net.N ? net.phiT[(size_t)(n0 + u) * net.Lp + l] : 0.0f;
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (n0 + u < net.N) {
+          const double2 cr = inj[n0 + u];
+          cf = fma((double)x[u], cr.x, cf);
+          rh = fma(fabs((double)x[u]), cr.y, rh);
+        }
+    }
+    const LineConst q = l == l0 ? q0 : load_line_const(net, l);
+    vm = max(vm, line_epilogue(net, l, q, cf, rh, mc, mb, s_lc, s_lh, s_lg, ws_ptr<double>(ws, lay.lcf) + b * net.L,
+                               ws_ptr<double>(ws, lay.lrf) + b * net.L, s_ctg,
+                               lay.cb ? ws_ptr<float2>(ws, lay.cb) + b * net.K : nullptr, pb_hi, pb_lo));
+  }
+  vm = wave_max_u32(vm);
+  pb_hi = wave_sum(pb_hi);
+  pb_lo = wave_sum(pb_lo);
+  if (lane == 0) {
+    red[w][kP1Fields] = pb_hi;
+    red[w][kP1Fields + 1] = pb_lo;
+    redm[w] = vm;
+  }
+  __syncthreads();
+  const unsigned vmb = max(max(redm[0], redm[1]), max(redm[2], redm[3]));
+  const float vmax = __uint_as_float(vmb);
+  // the per-line and per-outage data for the kernels that run after this one
+  float* wlc = ws_ptr<float>(ws, lay.lc) + b * net.Lp;
+  float* wlh = ws_ptr<float>(ws, lay.lh) + b * net.Lp;
+  float* wlg = ws_ptr<float>(ws, lay.lg) + b * net.Lp;
+  for (int l = tid; l < net.L; l += 256) {
+    wlc[l] = s_lc[l];
+    wlh[l] = s_lh[l];
+    wlg[l] = s_lg[l];
+  }
+  int4* wctg = ws_ptr<int4>(ws, lay.ctg) + b * net.K;
+  for (int k = tid; k < net.K; k += 256) wctg[k] = s_ctg[k];
+  if (tid == 0) *reinterpret_cast<unsigned*>(ws_ptr<double>(ws, lay.box) + b * kBoxSlots + kVmax) = vmb;
+  if (!SWEEP) return;
+
+  // outage sweep: items (column of four lines, pair of outages), columns fastest
+  const int Lp4 = net.Lp / 4;
+  const int np = net.K / 2;
+  double acc_hi = 0.0, acc_lo = 0.0;
+  const float4* lam = reinterpret_cast<const float4*>(net.lodf);
+  auto column = [&](int col, float4& c4, float4& h4, float4& g4) {
+    const float4 e4 = reinterpret_cast<const float4*>(net.line_eps)[col];
+    c4 = make_float4(s_lc[4 * col], s_lc[4 * col + 1], s_lc[4 * col + 2], s_lc[4 * col + 3]);
+    h4 = make_float4(add_ru(s_lh[4 * col], next_up_f32(e4.x * vmax)), add_ru(s_lh[4 * col + 1], next_up_f32(e4.y * vmax)),
+                     add_ru(s_lh[4 * col + 2], next_up_f32(e4.z * vmax)), add_ru(s_lh[4 * col + 3], next_up_f32(e4.w * vmax)));
+    g4 = make_float4(add_ru(s_lg[4 * col], next_up_f32(e4.x * vmax)), add_ru(s_lg[4 * col + 1], next_up_f32(e4.y * vmax)),
+                     add_ru(s_lg[4 * col + 2], next_up_f32(e4.z * vmax)), add_ru(s_lg[4 * col + 3], next_up_f32(e4.w * vmax)));
+  };
+  for (int it = tid; it < np * Lp4; it += 256) {
+    const int col = it % Lp4, k = 2 * (it / Lp4);
+    const float4 x0 = lam[(size_t)k * Lp4 + col], x1 = lam[(size_t)(k + 1) * Lp4 + col];
+    float4 c4, h4, g4;
+    column(col, c4, h4, g4);
+    k3_pair(x0, s_ctg[k], x1, s_ctg[k + 1], c4, h4, g4, acc_hi, acc_lo);
+  }
+  if (net.K & 1) {  // the last outage of an odd count, alone
+    const int k = net.K - 1;
+    for (int col = tid; col < Lp4; col += 256) {
+      const float4 x0 = lam[(size_t)k * Lp4 + col];
+      float4 c4, h4, g4;
+      column(col, c4, h4, g4);
+      const float cc0 = __int_as_float(s_ctg[k].y), rk0 = __int_as_float(s_ctg[k].z);
+      float a0, a1, a2, a3, q0a, q1, q2, q3;
+      k3_elem(x0.x, cc0, rk0, c4.x, h4.x, g4.x, a0, q0a);
+      k3_elem(x0.y, cc0, rk0, c4.y, h4.y, g4.y, a1, q1);
+      k3_elem(x0.z, cc0, rk0, c4.z, h4.z, g4.z, a2, q2);
+      k3_elem(x0.w, cc0, rk0, c4.w, h4.w, g4.w, a3, q3);
+      acc_hi += (double)((a0 + a1) + (a2 + a3));
+      acc_lo += (double)((q0a + q1) + (q2 + q3));
+    }
+  }
+  acc_hi = wave_sum(acc_hi);
+  acc_lo = wave_sum(acc_lo);
+  if (lane == 0) {
+    red[w][kP1Fields + 2] = acc_hi;
+    red[w][kP1Fields + 3] = acc_lo;
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  double x[12];
+#pragma unroll
+  for (int f = 0; f < 8; ++f) x[f] = v[kP1Sc + f];
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+    x[8 + f] = (red[0][kP1Fields + f] + red[1][kP1Fields + f]) + (red[2][kP1Fields + f] + red[3][kP1Fields + f]);
+  objective_interval(net, lay, b, x, f_lo, f_hi, terms);
 }
 
 // ---------------------------------------------------------------- K4
@@ -616,14 +802,17 @@ void plan_single(const DevNet& net, int64_t n_box, WsLayout& lay, const Tune& t)
   const int lp4 = net.Lp / 4;
   lay.k2_nc = t.k2_nc;
   lay.k3_kc = t.k3_kc;
-  lay.n_p1 = (std::max(net.Np, net.X) + 63) / 64;
+  // the smallest networks: one launch, one block per box (km_box)
+  lay.small = net.N <= kMicroBuses && net.L <= kMicroLines && (int64_t)net.K * net.Lp <= kMicroElems;
+  lay.n_p1 = lay.small ? 1 : (std::max(net.Np, net.X) + 63) / 64;
   lay.k2_bx = (lp4 + 63) / 64;
   lay.k2_by = std::max(1, (net.N + 4 * t.k2_nc - 1) / (4 * t.k2_nc));
-  lay.n_p2 = (net.L + 63) / 64;
+  lay.n_p2 = (net.L + 63) / 64;  // one base-penalty partial per epilogue wave
   // K3: 4 waves x 256 lines per block, k3_kc outages per block
   lay.k3_bx = (lp4 + 255) / 256;
   lay.k3_by = std::max(1, (net.K + t.k3_kc - 1) / t.k3_kc);
   lay.n_p3 = net.K > 0 ? lay.k3_bx * lay.k3_by : 0;
+  if (lay.small) lay.n_p2 = lay.n_p3 = 1;
 }
 
 template <int NC>
@@ -642,6 +831,13 @@ static void launch_k3(const DevNet& net, void* ws, const WsLayout& lay, int64_t 
 hipError_t launch_forward_single(const DevNet& net, int64_t n_box, const float* lo, const float* hi,
                                  double* f_lo, double* f_hi, double* terms, void* ws,
                                  const WsLayout& lay, hipStream_t s, KernelTimer* tm) {
+  if (lay.small) {
+    for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
+      const int nb = (int)std::min<int64_t>(65535, n_box - b0);
+      tm->launch(2, km_box<true>, dim3(nb), dim3(256), s, net, lo, hi, ws, lay, b0, f_lo, f_hi, terms);
+    }
+    return hipGetLastError();
+  }
   for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
     const int nb = (int)std::min<int64_t>(65535, n_box - b0);
     tm->launch(0, k1_box_prep, dim3(lay.n_p1, nb), dim3(64), s, net, lo, hi, ws, lay, b0);
@@ -669,6 +865,16 @@ hipError_t launch_forward_single(const DevNet& net, int64_t n_box, const float* 
 
 hipError_t launch_forward_prep(const DevNet& net, int64_t n_box, const float* lo, const float* hi, void* ws,
                                const WsLayout& lay, hipStream_t s, KernelTimer* tm) {
+  if (lay.small) {
+    for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
+      const int nb = (int)std::min<int64_t>(65535, n_box - b0);
+      const int t = tm->start(0, s);
+      hipLaunchKernelGGL(km_box<false>, dim3(nb), dim3(256), 0, s, net, lo, hi, ws, lay, b0, nullptr, nullptr,
+                         nullptr);
+      tm->stop(t, s);
+    }
+    return hipGetLastError();
+  }
   for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
     const int nb = (int)std::min<int64_t>(65535, n_box - b0);
     const int t = tm->start(0, s);
