@@ -519,6 +519,9 @@ def main(argv=None):
     ap.add_argument("--batched-only", type=int, default=0, metavar="CALLS",
                     help="only run the batched call (2000 buses, 18 x 1024 sub-boxes) CALLS times after one "
                          "warm-up call; for profiler runs")
+    ap.add_argument("--backward-only", type=int, default=0, metavar="CALLS",
+                    help="only run the one-sided backward (2000 buses, 4096 sub-boxes, gradient of f_hi) CALLS "
+                         "times after one warm-up call, and print its per-kernel times; for profiler runs")
     ap.add_argument("--traffic-record", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write the HBM traffic record from four rocprofv3 --pmc output folders (no GPU)")
     args = ap.parse_args(argv)
@@ -556,6 +559,25 @@ def main(argv=None):
         ms3 = _time(torch, lambda: ibp.ibp_bound_boxes(n3, tlo3, thi3, ws=ws3), args.batched_only)
         print(json.dumps({"workload": "2000 buses, 18 x 1024 sub-boxes", "calls": args.batched_only,
                           "ms_per_call": ms3}), flush=True)
+        return 0
+
+    if args.backward_only:
+        net3 = synth.make_config("c2000")
+        n3 = ibp.Network(net3, device=0)
+        blo, bhi = synth.sub_boxes(net3, 4096, seed=51)
+        t5l, t5h = torch.from_numpy(blo).cuda(), torch.from_numpy(bhi).cuda()
+        g1 = torch.ones(4096, dtype=torch.float64, device="cuda")
+        wsb = ibp.Workspace(n3)
+        call = lambda: ibp.ibp_bound_backward(n3, t5l, t5h, None, g1, ws=wsb, flags=ibp.IBP_F_UPPER_ONLY)  # noqa: E731
+        call()
+        ms = _time(torch, call, args.backward_only)
+        n3.set_kernel_timing(True)
+        n3.kernel_times()
+        for _ in range(args.backward_only):
+            call()
+        kt = n3.kernel_times()
+        print(json.dumps({"workload": "2000 buses, 4096 sub-boxes, backward of f_hi", "calls": args.backward_only,
+                          "ms_per_call": ms, "kernel_ms": {k: v[0] / v[1] for k, v in kt.items()}}), flush=True)
         return 0
 
     name = "c8316"

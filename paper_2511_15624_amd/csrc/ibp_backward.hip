@@ -37,11 +37,12 @@
 namespace ibp {
 
 // outages per block row: 128 for the per-box sweep (enough blocks for one
-// box), 256 for the box-tiled sweep, whose per-line partials (one float2 per
+// box), 512 for the box-tiled sweep, whose per-line partials (one float2 per
 // row, box and line) then take half the traffic (4096 boxes: 14.16 -> 13.8 ms;
+// 512 outages per row: 13.99 -> 13.73 ms for the whole backward;
 // the chunk must be a compile-time constant for that: a runtime bound gave 14.07)
 constexpr int kK5Chunk = 128;
-constexpr int kK5ChunkTiled = 256;
+constexpr int kK5ChunkTiled = 512;
 constexpr int kK5Sub = 16;     // outages per butterfly reduction
 
 // Sums v[0..31] over the 64 lanes of a wave; afterwards lanes 2i and 2i+1
@@ -205,7 +206,9 @@ constexpr int kBT5 = 4;
 template <int MODE>
 __global__ __launch_bounds__(256) void k5b_outage_vjp(DevNet net, void* ws, WsLayout lay, int64_t n_box,
                                                       const double* __restrict__ g_lo,
-                                                      const double* __restrict__ g_hi) {
+                                                      const double* __restrict__ g_hi,
+                                                      const float2* __restrict__ cb_all,
+                                                      float2* __restrict__ cpart_all) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t b0 = ((int64_t)blockIdx.z * 4 + w) * kBT5;
@@ -219,14 +222,14 @@ __global__ __launch_bounds__(256) void k5b_outage_vjp(DevNet net, void* ws, WsLa
   int64_t bb[kBT5];
   float chi[kBT5], clo[kBT5];
   float4 c4[kBT5], rm4[kBT5], rp4[kBT5];
-  const int4* cd[kBT5];
+  const float2* cd[kBT5];
 #pragma unroll
   for (int i = 0; i < kBT5; ++i) {
     bb[i] = min(b0 + i, n_box - 1);
     chi[i] = (float)(-net.zeta_f * (g_lo ? g_lo[bb[i]] : 0.0));
     clo[i] = (float)(-net.zeta_f * (g_hi ? g_hi[bb[i]] : 0.0));
     line_radii(net, ws, lay, bb[i], col, on, c4[i], rm4[i], rp4[i]);
-    cd[i] = ws_ptr<int4>(ws, lay.ctg) + bb[i] * net.K;
+    cd[i] = cb_all + bb[i] * net.K;
   }
   const float4* lam = reinterpret_cast<const float4*>(net.lodf) + col;
   float gc[kBT5][4], gr[kBT5][4];
@@ -243,26 +246,44 @@ __global__ __launch_bounds__(256) void k5b_outage_vjp(DevNet net, void* ws, WsLa
     no_hi = no_hi && chi[i] == 0.0f;
     no_lo = no_lo && clo[i] == 0.0f;
   }
+  // Steps of four outages x kBT5 boxes x four lines per lane, each ending in
+  // one butterfly over its 32 per-outage sums.  The outage-factor rows of the
+  // next step are loaded before this step's arithmetic; the per-outage
+  // (centre, radius) pairs come by scalar loads at the start of the step.
   auto sweep = [&](auto sides) {
     constexpr int S = decltype(sides)::value;
+    float4 xn[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      xn[u] = (on && k0 + u < k1) ? lam[(size_t)(k0 + u) * Lp4] : make_float4(0.f, 0.f, 0.f, 0.f);
     for (int ks = k0; ks < k1; ks += 4) {
+      const int nk = min(4, k1 - ks);
+      float4 x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[u] = xn[u];
+      float2 q[kBT5][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int i = 0; i < kBT5; ++i) q[i][u] = u < nk ? cd[i][ks + u] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        xn[u] = (on && ks + 4 + u < k1) ? lam[(size_t)(ks + 4 + u) * Lp4] : make_float4(0.f, 0.f, 0.f, 0.f);
+      __builtin_amdgcn_sched_barrier(0);
       float v[32];
 #pragma unroll
-      for (int q = 0; q < 32; ++q) v[q] = 0.0f;
+      for (int u = 0; u < 32; ++u) v[u] = 0.0f;
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
-        const int k = ks + kk;
-        if (k < k1) {  // uniform
-          const float4 x = on ? lam[(size_t)k * Lp4] : make_float4(0.f, 0.f, 0.f, 0.f);
+        if (kk < nk) {  // uniform
 #pragma unroll
           for (int i = 0; i < kBT5; ++i) {
-            const int4 d = cd[i][k];
-            const float cc = __int_as_float(d.y), rc = __int_as_float(d.w);
+            const float cc = q[i][kk].x, rc = q[i][kk].y;
             float pc = 0.0f, pr = 0.0f;
-            k5_elem<S>(x.x, cc, rc, c4[i].x, rm4[i].x, rp4[i].x, chi[i], clo[i], gc[i][0], gr[i][0], pc, pr);
-            k5_elem<S>(x.y, cc, rc, c4[i].y, rm4[i].y, rp4[i].y, chi[i], clo[i], gc[i][1], gr[i][1], pc, pr);
-            k5_elem<S>(x.z, cc, rc, c4[i].z, rm4[i].z, rp4[i].z, chi[i], clo[i], gc[i][2], gr[i][2], pc, pr);
-            k5_elem<S>(x.w, cc, rc, c4[i].w, rm4[i].w, rp4[i].w, chi[i], clo[i], gc[i][3], gr[i][3], pc, pr);
+            k5_elem<S>(x[kk].x, cc, rc, c4[i].x, rm4[i].x, rp4[i].x, chi[i], clo[i], gc[i][0], gr[i][0], pc, pr);
+            k5_elem<S>(x[kk].y, cc, rc, c4[i].y, rm4[i].y, rp4[i].y, chi[i], clo[i], gc[i][1], gr[i][1], pc, pr);
+            k5_elem<S>(x[kk].z, cc, rc, c4[i].z, rm4[i].z, rp4[i].z, chi[i], clo[i], gc[i][2], gr[i][2], pc, pr);
+            k5_elem<S>(x[kk].w, cc, rc, c4[i].w, rm4[i].w, rp4[i].w, chi[i], clo[i], gc[i][3], gr[i][3], pc, pr);
             v[(kk * kBT5 + i) * 2] = pc;
             v[(kk * kBT5 + i) * 2 + 1] = pr;
           }
@@ -273,7 +294,7 @@ __global__ __launch_bounds__(256) void k5b_outage_vjp(DevNet net, void* ws, WsLa
       const int k = ks + (idx >> 3);
       const int i = (idx >> 1) & 3;
       if ((lane & 1) == 0 && k < k1 && b0 + i < n_box) {
-        float2* cp = ws_ptr<float2>(ws, lay.cpart) + ((size_t)(b0 + i) * lay.k5_tiles + tile) * net.K + k;
+        float2* cp = cpart_all + ((size_t)(b0 + i) * lay.k5_tiles + tile) * net.K + k;
         reinterpret_cast<float*>(cp)[idx & 1] = tot;
       }
     }
@@ -534,12 +555,17 @@ hipError_t launch_backward_sweeps(const DevNet& net, int64_t n_box, void* ws, co
     const int t = tm->start(7, s);
     const unsigned groups = (unsigned)(((n_box + kBT5 - 1) / kBT5 + 3) / 4);
     const dim3 grid(lay.k5_tiles, lay.k5_by, groups);
+    const float2* cb_all = reinterpret_cast<const float2*>(static_cast<char*>(ws) + lay.cb);
+    float2* cpart_all = reinterpret_cast<float2*>(static_cast<char*>(ws) + lay.cpart);
     if (!g_lo)
-      hipLaunchKernelGGL(k5b_outage_vjp<1>, grid, dim3(256), 0, s, net, ws, lay, n_box, g_lo, g_hi);
+      hipLaunchKernelGGL(k5b_outage_vjp<1>, grid, dim3(256), 0, s, net, ws, lay, n_box, g_lo, g_hi, cb_all,
+                         cpart_all);
     else if (!g_hi)
-      hipLaunchKernelGGL(k5b_outage_vjp<2>, grid, dim3(256), 0, s, net, ws, lay, n_box, g_lo, g_hi);
+      hipLaunchKernelGGL(k5b_outage_vjp<2>, grid, dim3(256), 0, s, net, ws, lay, n_box, g_lo, g_hi, cb_all,
+                         cpart_all);
     else
-      hipLaunchKernelGGL(k5b_outage_vjp<3>, grid, dim3(256), 0, s, net, ws, lay, n_box, g_lo, g_hi);
+      hipLaunchKernelGGL(k5b_outage_vjp<3>, grid, dim3(256), 0, s, net, ws, lay, n_box, g_lo, g_hi, cb_all,
+                         cpart_all);
     tm->stop(t, s);
   }
   for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
