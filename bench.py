@@ -261,6 +261,11 @@ def hbm_probe(torch, ibp):
 VALU_PEAK = 78.6e12  # float32 VALU lane-ops/s: 256 CUs x 128 lanes/clock x 2.4 GHz (FMA = one op)
 MFMA_F64_PEAK = 78.6e12  # float64 dense matrix FLOP/s of MI355X
 OPS_PER_EVAL = 9.25  # VALU ops per box-outage-line evaluation in the outage sweep (from the ISA)
+# VALU ops per box-outage-line element of the one-sided backward sweep: the
+# post-outage centre and radius (2 fma), the activity test (subtract, compare,
+# select), the sign transfer of the centre weight (1 three-input bit op) and four
+# accumulations (line centre / radius gradients, outage centre / radius partials)
+OPS_PER_BWD_EVAL = 10.0
 
 
 def _time(torch, fn, reps):
@@ -274,6 +279,21 @@ def _time(torch, fn, reps):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def _tuned(torch, ibp, net, tlo, thi, ws, ev, ms_default):
+    """Autotunes the box-tiled tiles on this very call, times the tuned call,
+    then puts the default tiles back so later figures use the same code."""
+    keep = net.tiles()
+    t0 = time.perf_counter()
+    tiles, _ = ibp.ibp_autotune_batched(net, tlo, thi)
+    tune_s = time.perf_counter() - t0
+    ms = _time(torch, lambda: ibp.ibp_bound_boxes(net, tlo, thi, ws=ws), 3)
+    net.set_tile_batched(keep["k3_bt"], keep["k3_rows"], keep["k3_xcd"], keep["k2_mfma"], keep["k2_by"])
+    return {"tiles": {k: tiles[k] for k in ("k3_bt", "k3_rows", "k3_xcd", "k2_mfma", "k2_by")},
+            "default_tiles": {k: keep[k] for k in ("k3_bt", "k3_rows", "k3_xcd", "k2_mfma", "k2_by")},
+            "ms_per_call": ms, "value": ev / (ms * 1e-3), "speedup_vs_default": ms_default / ms,
+            "tune_seconds": round(tune_s, 3)}
 
 
 def extras(torch, ibp, synth, n4, net4):
@@ -330,6 +350,7 @@ def extras(torch, ibp, synth, n4, net4):
                      "frac": ev * OPS_PER_EVAL / (sweep_ms * 1e-3) / VALU_PEAK,
                      "ops_per_eval": OPS_PER_EVAL},
     }
+    res["batched"]["tuned"] = _tuned(torch, ibp, n3, tlo, thi, ws, ev, ms)
     # the base flows of the same call on the float64 matrix cores: 2 products
     # (centre, radius) x 2 flops x lines x buses x boxes
     bf_ms = kt.get("batched_base_flows", (float("nan"), 1))[0]
@@ -347,7 +368,8 @@ def extras(torch, ibp, synth, n4, net4):
     ev4 = 256 * n4.n_ctg * n4.n_line
     res["batched_large"] = {"workload": "8316 buses, 256 sub-boxes", "value": ev4 / (ms4 * 1e-3),
                             "unit": "evals/s", "ms_per_call": ms4, "plain_value": ev4 / (ms4p * 1e-3),
-                            "speedup_vs_plain": ms4p / ms4}
+                            "speedup_vs_plain": ms4p / ms4,
+                            "tuned": _tuned(torch, ibp, n4, t4l, t4h, ws4, ev4, ms4)}
     # backward: 2000-bus network, 4096 sub-boxes of period 0
     blo, bhi = synth.sub_boxes(net3, 4096, seed=51)
     t5l, t5h = torch.from_numpy(blo).cuda(), torch.from_numpy(bhi).cuda()
@@ -362,11 +384,29 @@ def extras(torch, ibp, synth, n4, net4):
     msbp = _time(torch, lambda: ibp.ibp_bound_backward(n3, t5l[:sub], t5h[:sub], None, g1[:sub], ws=wsb,
                                                         flags=ibp.IBP_F_PLAIN | ibp.IBP_F_UPPER_ONLY), 1)
     ev5 = 4096 * n3.n_ctg * n3.n_line
+    n3.set_kernel_timing(True)
+    n3.kernel_times()
+    for _ in range(3):
+        ibp.ibp_bound_backward(n3, t5l, t5h, None, g1, ws=wsb, flags=ibp.IBP_F_UPPER_ONLY)
+    ktb = {k: v[0] / 3 for k, v in n3.kernel_times().items()}
+    n3.set_kernel_timing(False)
+    k5_ms = ktb.get("backward_outage_sweep", float("nan"))
+    k6_ms = ktb.get("backward_ptdf_t", float("nan"))
+    k6_fma = 2.0 * n3.n_bus * n3.n_line * 4096
     res["backward"] = {"workload": "2000 buses, 4096 sub-boxes: d(f_hi)/d(box endpoints), one-sided call",
                        "value": ev5 / (msb * 1e-3), "unit": "evals/s", "ms_backward": msb,
                        "ms_backward_two_sided_weights": msb2,
                        "ms_forward": msf, "plain_value": sub * n3.n_ctg * n3.n_line / (msbp * 1e-3),
-                       "plain_sample": f"first {sub} boxes, per-box kernels"}
+                       "plain_sample": f"first {sub} boxes, per-box kernels",
+                       "kernel_ms": {k: round(v, 3) for k, v in ktb.items()},
+                       "roofline": {"bound": "alu", "kernel": "backward_outage_sweep",
+                                    "achieved": ev5 * OPS_PER_BWD_EVAL / (k5_ms * 1e-3), "peak": VALU_PEAK,
+                                    "unit": "ops/s", "frac": ev5 * OPS_PER_BWD_EVAL / (k5_ms * 1e-3) / VALU_PEAK,
+                                    "ops_per_eval": OPS_PER_BWD_EVAL},
+                       "roofline_ptdf_t": {"bound": "alu", "kernel": "backward_ptdf_t",
+                                           "achieved": k6_fma / (k6_ms * 1e-3), "peak": VALU_PEAK,
+                                           "unit": "ops/s", "frac": k6_fma / (k6_ms * 1e-3) / VALU_PEAK,
+                                           "ops": k6_fma}}
     # piecewise-linear cost and value curves (1-4 segments per device) on the
     # single large box and on the batched workload, beside the linear-cost runs
     lo4, hi4 = synth.full_box(net4)

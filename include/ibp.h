@@ -286,9 +286,10 @@ ibp_status ibp_crown_lower_boxes(const ibp_network* net, int64_t n_box,
  * 2 outage sweep, 3 finalize, 4 line epilogue, 5 batched base flows,
  * 6 batched outage sweep, 7 backward outage sweep, 8 backward transposed PTDF,
  * 9 backward endpoints, 10 relaxation outage sweep, 11 relaxation line adjoint
- * and transposed PTDF, 12 relaxation inputs and finalize.
+ * and transposed PTDF, 12 relaxation inputs and finalize, 13 backward
+ * per-line (base-case) terms.
  * Not thread-safe with concurrent compute calls on the same handle. */
-#define IBP_N_KERNEL_IDS 13
+#define IBP_N_KERNEL_IDS 14
 ibp_status ibp_set_kernel_timing(ibp_network* net, int enable);
 ibp_status ibp_kernel_times(ibp_network* net, int32_t n_ids, double* total_ms, int64_t* count);
 
@@ -310,6 +311,28 @@ ibp_status ibp_kernel_times(ibp_network* net, int32_t n_ids, double* total_ms, i
 ibp_status ibp_set_tile(ibp_network* net, int32_t k2_nc, int32_t k3_kc);
 ibp_status ibp_autotune(ibp_network* net, int64_t n_box, const float* box_lo, const float* box_hi,
                         void* ws, size_t ws_bytes, void* stream, int32_t* chosen);
+
+/* Tile parameters of the box-tiled path (calls of 4 or more boxes; time
+ * indices and sub-boxes batched into one launch, Sec. IV-A): boxes per wave of
+ * the outage sweep (k3_bt: 2, 4 or 8), its outage rows (k3_rows: 0 for the
+ * built-in rule, else 1..4096), its XCD-aware block order (k3_xcd: 0 off, 1 on,
+ * -1 on when the outage factors exceed 128 MiB), the base-flow engine (k2_mfma:
+ * 1 float64 matrix cores, 0 vector FMA) and its bus chunks (k2_by: 0 for the
+ * rule, else 1..8).  Results do not depend on them beyond float64 summation
+ * order.  ibp_autotune_batched() times the candidates around the current
+ * parameters on the caller's n_box >= 4 boxes (forward kernels on `stream`,
+ * synchronizing; the base flows first, then the outage sweep with the chosen
+ * base flows) and keeps the fastest; `chosen` (host int32[5], nullable)
+ * receives (k3_bt, k3_rows, k3_xcd, k2_mfma, k2_by).  The workspace must hold
+ * ibp_workspace_bytes(net, n_box, IBP_F_AUTOTUNE).  ibp_get_tile() copies the
+ * current parameters (host int32[7]: k2_nc, k3_kc, k3_bt, k3_rows, k3_xcd,
+ * k2_mfma, k2_by).  None of the three may run concurrently with compute calls
+ * on the same handle.  Errors: INVALID_ARG, WORKSPACE, HOST_ONLY, DEVICE. */
+ibp_status ibp_set_tile_batched(ibp_network* net, int32_t k3_bt, int32_t k3_rows, int32_t k3_xcd,
+                                int32_t k2_mfma, int32_t k2_by);
+ibp_status ibp_get_tile(const ibp_network* net, int32_t* out);
+ibp_status ibp_autotune_batched(ibp_network* net, int64_t n_box, const float* box_lo, const float* box_hi,
+                                void* ws, size_t ws_bytes, void* stream, int32_t* chosen);
 
 /* Branch and bound over input boxes (the paper names branch and bound over
  * the inputs as the way to tighten IBP bounds, Sec. I and Sec. V, and screens

@@ -272,20 +272,73 @@ ibp_status to_device(ibp_network* net, int device) {
     if (const char* p = std::strstr(e, "k3kc=")) t.k3_kc = (v = std::atoi(p + 5)) ? v : t.k3_kc;
     if (const char* p = std::strstr(e, "k2b=")) t.k2b_mfma = std::atoi(p + 4) != 0;
     if (const char* p = std::strstr(e, "ckb=")) t.chord_nb = std::atoi(p + 4);
-    if (ibp::tune_valid(t) && (t.chord_nb == 2 || t.chord_nb == 4)) net->tune = t;
+    if (const char* p = std::strstr(e, "bt=")) t.k3_bt = std::atoi(p + 3);
+    if (const char* p = std::strstr(e, "rows=")) t.k3_rows = std::atoi(p + 5);
+    if (const char* p = std::strstr(e, "xcd=")) t.k3_xcd = std::atoi(p + 4);
+    if (const char* p = std::strstr(e, "k2by=")) t.k2_by = std::atoi(p + 5);
+    if (ibp::tune_valid(t) && ibp::tune_batched_valid(t) && (t.chord_nb == 2 || t.chord_nb == 4)) net->tune = t;
   }
   return IBP_OK;
 }
 
 ibp::WsLayout layout_for(const ibp_network* net, int64_t n_box, const ibp::Tune& tune, bool batched);
 
+// Box-tiled candidates of the autotuner around the current tiles `t`: the
+// outage sweep's boxes per wave, outage rows (half, the rule's and twice) and
+// block order, and the base flows' engine and bus chunks.
+std::vector<ibp::Tune> sweep_candidates(const ibp_network* net, int64_t n_box, const ibp::Tune& t) {
+  const ibp::DevNet& d = net->dn;
+  std::vector<ibp::Tune> out;
+  for (int bt : {2, 4, 8}) {
+    const int64_t groups = ((n_box + bt - 1) / bt + 3) / 4;
+    const int r = ibp::batched_rows_rule(d, (d.Lp / 4 + 63) / 64, groups);
+    std::vector<int> rows{r};
+    if (r / 2 >= 1) rows.push_back(r / 2);
+    if (2 * r <= std::max(1, d.K / 16)) rows.push_back(2 * r);
+    for (int rw : rows)
+      for (int x : {0, 1}) {
+        ibp::Tune c = t;
+        c.k3_bt = bt;
+        c.k3_rows = rw;
+        c.k3_xcd = x;
+        out.push_back(c);
+      }
+  }
+  return out;
+}
+
+std::vector<ibp::Tune> flow_candidates(const ibp_network* net, const ibp::Tune& t) {
+  std::vector<ibp::Tune> out;
+  for (int by : {1, 2, 4, 8}) {
+    if (by > 1 && by > net->dn.N / 256) break;
+    ibp::Tune c = t;
+    c.k2b_mfma = 1;
+    c.k2_by = by;
+    out.push_back(c);
+  }
+  ibp::Tune v = t;
+  v.k2b_mfma = 0;
+  v.k2_by = 0;
+  out.push_back(v);
+  return out;
+}
+
 ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
   if (flags & IBP_F_AUTOTUNE) {
-    // the largest layout over every tile pair (smallest tiles give most partials)
-    ibp::Tune t;
+    // the largest layout over every tile pair (smallest tiles give most
+    // partials), and from kBatchMin boxes on over every box-tiled candidate
+    ibp::Tune t = net->tune;
     t.k2_nc = 32;
     t.k3_kc = 16;
-    return layout_for(net, n_box, t, false);
+    ibp::WsLayout big = layout_for(net, n_box, t, false);
+    if (n_box >= ibp::kBatchMin) {
+      for (const ibp::Tune& f : flow_candidates(net, net->tune))
+        for (const ibp::Tune& c : sweep_candidates(net, n_box, f)) {
+          const ibp::WsLayout l = layout_for(net, n_box, c, true);
+          if (l.total > big.total) big = l;
+        }
+    }
+    return big;
   }
   const bool batched = n_box >= ibp::kBatchMin && !(flags & IBP_F_PLAIN);
   ibp::WsLayout lay = layout_for(net, n_box, net->tune, batched);
@@ -732,6 +785,109 @@ ibp_status ibp_autotune(ibp_network* net, int64_t n_box, const float* box_lo, co
   if (chosen) {
     chosen[0] = best_t.k2_nc;
     chosen[1] = best_t.k3_kc;
+  }
+  return IBP_OK;
+}
+
+ibp_status ibp_set_tile_batched(ibp_network* net, int32_t k3_bt, int32_t k3_rows, int32_t k3_xcd, int32_t k2_mfma,
+                                int32_t k2_by) {
+  if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
+  ibp::Tune t = net->tune;
+  t.k3_bt = k3_bt;
+  t.k3_rows = k3_rows;
+  t.k3_xcd = k3_xcd;
+  t.k2b_mfma = k2_mfma;
+  t.k2_by = k2_by;
+  if (!ibp::tune_batched_valid(t)) return fail(IBP_E_INVALID_ARG, "unsupported box-tiled tile parameters");
+  net->tune = t;
+  return IBP_OK;
+}
+
+ibp_status ibp_get_tile(const ibp_network* net, int32_t* out) {
+  if (!net || !out) return fail(IBP_E_INVALID_ARG, "NULL argument");
+  const ibp::Tune& t = net->tune;
+  const int32_t v[7] = {t.k2_nc, t.k3_kc, t.k3_bt, t.k3_rows, t.k3_xcd, t.k2b_mfma, t.k2_by};
+  std::memcpy(out, v, sizeof(v));
+  return IBP_OK;
+}
+
+ibp_status ibp_autotune_batched(ibp_network* net, int64_t n_box, const float* box_lo, const float* box_hi,
+                                void* ws, size_t ws_bytes, void* stream, int32_t* chosen) {
+  g_err.clear();
+  if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
+  if (net->device < 0) return fail(IBP_E_HOST_ONLY, "network was built host-only");
+  if (n_box < ibp::kBatchMin || !box_lo || !box_hi)
+    return fail(IBP_E_INVALID_ARG, "the box-tiled autotuner needs at least 4 device boxes");
+  if (n_box > 16 * 65535) return fail(IBP_E_INVALID_ARG, "too many boxes for one tuning launch");
+  const ibp::WsLayout big = layout(net, n_box, IBP_F_AUTOTUNE);
+  if (!ws || ws_bytes < big.total)
+    return fail(IBP_E_WORKSPACE, "autotune workspace needs " + std::to_string(big.total) + " bytes");
+  DeviceGuard g(net->device);
+  if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(IBP_E_DEVICE, "autotune events");
+  ibp::KernelTimer off;
+  ibp_status st = IBP_OK;
+  auto time_it = [&](auto launch) {
+    float best = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {  // the first run warms up
+      float ms = 0.0f;
+      (void)hipEventRecord(e0, s);
+      if (launch() != hipSuccess) st = fail(IBP_E_DEVICE, "autotune launch failed");
+      (void)hipEventRecord(e1, s);
+      if (hipEventSynchronize(e1) != hipSuccess) st = fail(IBP_E_DEVICE, "autotune synchronize failed");
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) best = std::min(best, ms);
+    }
+    return best;
+  };
+  // base flows: box preparation once, then every engine / chunking (each
+  // writes only its own partials)
+  ibp::Tune best_t = net->tune;
+  {
+    float best = 1e30f;
+    for (const ibp::Tune& c : flow_candidates(net, net->tune)) {
+      ibp::WsLayout lay = layout_for(net, n_box, c, true);
+      if (ibp::launch_forward_prep(net->dn, n_box, box_lo, box_hi, ws, lay, s, &off) != hipSuccess)
+        st = fail(IBP_E_DEVICE, "autotune preparation failed");
+      const float ms = time_it([&] { return ibp::launch_batched_sweeps(net->dn, n_box, ws, lay, s, &off, 0); });
+      if (st == IBP_OK && ms < best) {
+        best = ms;
+        best_t.k2b_mfma = c.k2b_mfma;
+        best_t.k2_by = c.k2_by;
+      }
+    }
+  }
+  // outage sweep: the chosen base flows prepared once, then every candidate
+  // (the line data sit before the per-call partials, at the same offsets)
+  if (st == IBP_OK && net->dn.K > 0) {
+    ibp::WsLayout prep = layout_for(net, n_box, best_t, true);
+    if (ibp::launch_forward_prep(net->dn, n_box, box_lo, box_hi, ws, prep, s, &off) != hipSuccess)
+      st = fail(IBP_E_DEVICE, "autotune preparation failed");
+    float best = 1e30f;
+    ibp::Tune pick = best_t;
+    for (const ibp::Tune& c : sweep_candidates(net, n_box, best_t)) {
+      ibp::WsLayout lay = layout_for(net, n_box, c, true);
+      const float ms = time_it([&] { return ibp::launch_batched_sweeps(net->dn, n_box, ws, lay, s, &off, 1); });
+      if (st == IBP_OK && ms < best) {
+        best = ms;
+        pick = c;
+      }
+    }
+    best_t = pick;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != IBP_OK) return st;
+  net->tune = best_t;
+  if (chosen) {
+    chosen[0] = best_t.k3_bt;
+    chosen[1] = best_t.k3_rows;
+    chosen[2] = best_t.k3_xcd;
+    chosen[3] = best_t.k2b_mfma;
+    chosen[4] = best_t.k2_by;
   }
   return IBP_OK;
 }

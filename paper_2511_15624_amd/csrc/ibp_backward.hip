@@ -570,10 +570,13 @@ hipError_t launch_backward_sweeps(const DevNet& net, int64_t n_box, void* ws, co
   }
   for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
     const int nb = (int)std::min<int64_t>(65535, n_box - b0);
-    const int t = tm->start(7, s);
-    if (net.K > 0 && !(n_box >= kBatchMin && lay.batched))
+    if (net.K > 0 && !(n_box >= kBatchMin && lay.batched)) {
+      const int t = tm->start(7, s);
       hipLaunchKernelGGL(k5_outage_vjp, dim3((lay.k5_tiles + 3) / 4, lay.k5_by, nb), dim3(256), 0, s, net, ws,
                          lay, b0, g_lo, g_hi);
+      tm->stop(t, s);
+    }
+    const int t = tm->start(13, s);
     hipLaunchKernelGGL(k5r_lines, dim3((net.Lp + 255) / 256, nb), dim3(256), 0, s, net, ws, lay, b0, g_lo, g_hi);
     tm->stop(t, s);
   }

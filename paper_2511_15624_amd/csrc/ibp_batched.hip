@@ -17,6 +17,7 @@
 #include <cfloat>
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "ibp_device.h"
 #include "ibp_devfun.h"
@@ -24,7 +25,7 @@
 
 namespace ibp {
 
-constexpr int kBT = 4;  // boxes per wave tile
+constexpr int kBT = 4;  // boxes per wave tile of the vector base-flow sweep (and the outage sweep's default)
 
 // Base flows for kBT boxes x 256 lines per wave, over every bus.
 __global__ __launch_bounds__(256) void k2b_base_flows(DevNet net, void* ws, WsLayout lay, int64_t n_box,
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(256, 2) void k2b_base_flows_mfma(DevNet net, void* 
 // its L2 once (8316 buses, 256 boxes: 5.05 -> 4.61 ms).  With the factors in
 // the last-level cache the plain order is faster (2000 buses: 27.3 against
 // 28.4 ms).  The order changes no sum.
-template <int SIDES>
+template <int SIDES, int kBT>
 __global__ __launch_bounds__(256) void k3b_contingency(DevNet net, void* ws, WsLayout lay, int64_t n_box) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -303,6 +304,22 @@ __global__ __launch_bounds__(256) void k3b_contingency(DevNet net, void* ws, WsL
   }
 }
 
+// Outage rows of the box-tiled sweep chosen by rule: enough waves in flight,
+// at least 32 outages per row, and k3_bx * rows a multiple of 8 when that is
+// near (blocks that share an outage tile then share an XCD).
+int batched_rows_rule(const DevNet& net, int k3_bx, int64_t groups) {
+  int rows = 1;
+  const int max_rows = std::max(1, net.K / 32);
+  while (rows < max_rows && (int64_t)k3_bx * rows * groups * 4 < 16384) rows *= 2;
+  rows = std::min(rows, max_rows);
+  for (int r = rows; r <= std::min(max_rows, rows * 2); ++r)
+    if ((k3_bx * r) % 8 == 0) {
+      rows = r;
+      break;
+    }
+  return rows;
+}
+
 void plan_batched(const DevNet& net, int64_t n_box, WsLayout& lay, const Tune& t) {
   const int lp4 = net.Lp / 4;
   lay.batched = 1;
@@ -319,25 +336,18 @@ void plan_batched(const DevNet& net, int64_t n_box, WsLayout& lay, const Tune& t
     const int64_t blocks = (int64_t)((net.Lp / 64 + 3) / 4) * ((n_box + 31) / 32);
     int by = (int)std::min<int64_t>(8, (2048 + blocks - 1) / blocks);
     by = std::max(1, std::min(by, net.N / 256));
+    if (t.k2_by > 0) by = std::min(t.k2_by, std::max(1, net.N / 4));
     lay.k2_chunk = ((net.N + by - 1) / by + 3) & ~3;
     lay.k2_by = (net.N + lay.k2_chunk - 1) / lay.k2_chunk;
   }
   lay.n_p2 = (net.L + 63) / 64;
-  const int64_t nbt = (n_box + kBT - 1) / kBT;
+  lay.k3_bt = t.k3_bt;
+  const int64_t nbt = (n_box + lay.k3_bt - 1) / lay.k3_bt;
   const int64_t groups = (nbt + 3) / 4;
   lay.k3_bx = (lp4 + 63) / 64;
-  // split the outages so that there are enough waves in flight, keep at least
-  // 32 outages per row, and prefer k3_bx * rows to be a multiple of 8 (blocks
-  // that share an outage tile then share an XCD)
-  int rows = 1;
-  const int max_rows = std::max(1, net.K / 32);
-  while (rows < max_rows && (int64_t)lay.k3_bx * rows * groups * 4 < 16384) rows *= 2;
-  rows = std::min(rows, max_rows);
-  for (int r = rows; r <= std::min(max_rows, rows * 2); ++r)
-    if ((lay.k3_bx * r) % 8 == 0) {
-      rows = r;
-      break;
-    }
+  int rows = batched_rows_rule(net, lay.k3_bx, groups);
+  if (t.k3_rows > 0) rows = std::min(t.k3_rows, std::max(1, net.K));
+  if (t.k3_xcd >= 0) lay.k3_xcd = t.k3_xcd;
   lay.k3_by = rows;
   lay.k3_kper = net.K > 0 ? (net.K + rows - 1) / rows : 0;
   lay.n_p3 = net.K > 0 ? lay.k3_bx * rows : 0;
@@ -350,6 +360,8 @@ hipError_t launch_batched_sweeps(const DevNet& net, int64_t n_box, void* ws, con
                                  KernelTimer* tm, int phase) {
   const int64_t nbt = (n_box + kBT - 1) / kBT;
   const unsigned groups = (unsigned)((nbt + 3) / 4);
+  const int64_t nbt3 = (n_box + lay.k3_bt - 1) / lay.k3_bt;
+  const unsigned groups3 = (unsigned)((nbt3 + 3) / 4);
   if (phase == 0) {
     const int t = tm->start(5, s);
     const double2* inj = reinterpret_cast<const double2*>(static_cast<char*>(ws) + lay.inj);
@@ -362,13 +374,22 @@ hipError_t launch_batched_sweeps(const DevNet& net, int64_t n_box, void* ws, con
     tm->stop(t, s);
   } else if (net.K > 0) {
     const int t = tm->start(6, s);
-    const dim3 grid(lay.k3_bx, lay.k3_by, groups);
-    if (lay.sides == 1)
-      hipLaunchKernelGGL(k3b_contingency<1>, grid, dim3(256), 0, s, net, ws, lay, n_box);
-    else if (lay.sides == 2)
-      hipLaunchKernelGGL(k3b_contingency<2>, grid, dim3(256), 0, s, net, ws, lay, n_box);
+    const dim3 grid(lay.k3_bx, lay.k3_by, groups3);
+    auto go = [&](auto bt) {
+      constexpr int BT = decltype(bt)::value;
+      if (lay.sides == 1)
+        hipLaunchKernelGGL((k3b_contingency<1, BT>), grid, dim3(256), 0, s, net, ws, lay, n_box);
+      else if (lay.sides == 2)
+        hipLaunchKernelGGL((k3b_contingency<2, BT>), grid, dim3(256), 0, s, net, ws, lay, n_box);
+      else
+        hipLaunchKernelGGL((k3b_contingency<3, BT>), grid, dim3(256), 0, s, net, ws, lay, n_box);
+    };
+    if (lay.k3_bt == 2)
+      go(std::integral_constant<int, 2>());
+    else if (lay.k3_bt == 8)
+      go(std::integral_constant<int, 8>());
     else
-      hipLaunchKernelGGL(k3b_contingency<3>, grid, dim3(256), 0, s, net, ws, lay, n_box);
+      go(std::integral_constant<int, 4>());
     tm->stop(t, s);
   }
   return hipGetLastError();

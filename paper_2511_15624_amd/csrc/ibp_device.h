@@ -90,6 +90,7 @@ struct WsLayout {
   int k2_mfma = 0;                 // batched base flows on the float64 matrix cores
   int k2_chunk = 0;                // batched base flows: buses per chunk (k2_by chunks, a multiple of 4)
   int k3_kper = 0;                 // batched outage sweep: outages per block row
+  int k3_bt = 4;                   // batched outage sweep: boxes per wave
   int k5_by = 0, k5_tiles = 0;     // backward outage sweep: outage chunks, line tiles
   int k5_chunk = 0;                // outages per backward chunk
   // linear-relaxation bound (present with the CROWN flag)

@@ -797,6 +797,11 @@ bool tune_valid(const Tune& t) {
   return nc && kc;
 }
 
+bool tune_batched_valid(const Tune& t) {
+  return (t.k3_bt == 2 || t.k3_bt == 4 || t.k3_bt == 8) && t.k3_rows >= 0 && t.k3_rows <= 4096 &&
+         t.k3_xcd >= -1 && t.k3_xcd <= 1 && (t.k2b_mfma == 0 || t.k2b_mfma == 1) && t.k2_by >= 0 && t.k2_by <= 8;
+}
+
 void plan_single(const DevNet& net, int64_t n_box, WsLayout& lay, const Tune& t) {
   (void)n_box;
   const int lp4 = net.Lp / 4;

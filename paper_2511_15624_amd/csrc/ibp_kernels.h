@@ -52,8 +52,15 @@ struct Tune {
   int k3_kc = 16;   // outages per block in the outage sweep: 16, 32, 64 or 128
   int k2b_mfma = 1; // box-tiled base flows on the float64 matrix cores (0: vector FMA)
   int chord_nb = 2; // boxes per lane in the box-tiled chord-relaxation sweep: 2 or 4
+  // box-tiled forward (the autotuner's batched candidates)
+  int k3_bt = 4;    // boxes per wave in the box-tiled outage sweep: 2, 4 or 8
+  int k3_rows = 0;  // outage rows of that sweep (0: the rule of batched_rows_rule)
+  int k3_xcd = -1;  // its XCD-aware block order: 0 off, 1 on, -1 by cache size
+  int k2_by = 0;    // bus chunks of the matrix-core base flows (0: by rule)
 };
 bool tune_valid(const Tune& t);
+bool tune_batched_valid(const Tune& t);
+int batched_rows_rule(const DevNet& net, int k3_bx, int64_t groups);
 
 // Grid shapes and partial-sum counts of the single-box-per-slice forward path.
 void plan_single(const DevNet& net, int64_t n_box, WsLayout& lay, const Tune& t);

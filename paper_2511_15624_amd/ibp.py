@@ -57,6 +57,9 @@ EXPORTED = [
     "ibp_kernel_times",
     "ibp_set_tile",
     "ibp_autotune",
+    "ibp_set_tile_batched",
+    "ibp_get_tile",
+    "ibp_autotune_batched",
     "ibp_split_select",
     "ibp_split_bisect",
     "ibp_split_update",
@@ -67,7 +70,10 @@ EXPORTED = [
 
 KERNEL_IDS = ["box_prep", "base_flows", "outage_sweep", "finalize", "line_epilogue", "batched_base_flows",
               "batched_outage_sweep", "backward_outage_sweep", "backward_ptdf_t", "backward_endpoints",
-              "crown_outage_sweep", "crown_ptdf_t", "crown_inputs"]
+              "crown_outage_sweep", "crown_ptdf_t", "crown_inputs", "backward_line_terms"]
+
+
+TILE_FIELDS = ("k2_nc", "k3_kc", "k3_bt", "k3_rows", "k3_xcd", "k2_mfma", "k2_by")
 
 
 class IBPError(RuntimeError):
@@ -170,6 +176,12 @@ def load_library(path: str = LIB_PATH):
     lib.ibp_set_tile.restype = ctypes.c_int
     lib.ibp_autotune.argtypes = [vp, i64, vp, vp, vp, sz, vp, vp]
     lib.ibp_autotune.restype = ctypes.c_int
+    lib.ibp_set_tile_batched.argtypes = [vp, i32, i32, i32, i32, i32]
+    lib.ibp_set_tile_batched.restype = ctypes.c_int
+    lib.ibp_get_tile.argtypes = [vp, vp]
+    lib.ibp_get_tile.restype = ctypes.c_int
+    lib.ibp_autotune_batched.argtypes = [vp, i64, vp, vp, vp, sz, vp, vp]
+    lib.ibp_autotune_batched.restype = ctypes.c_int
     lib.ibp_split_select.argtypes = [i64, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     lib.ibp_split_select.restype = ctypes.c_int
     lib.ibp_split_bisect.argtypes = [i64, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -282,6 +294,15 @@ class Network:
 
     def set_tile(self, k2_nc: int, k3_kc: int):
         _check(load_library().ibp_set_tile(self._h, int(k2_nc), int(k3_kc)))
+
+    def set_tile_batched(self, k3_bt: int, k3_rows: int, k3_xcd: int, k2_mfma: int, k2_by: int):
+        _check(load_library().ibp_set_tile_batched(self._h, int(k3_bt), int(k3_rows), int(k3_xcd), int(k2_mfma),
+                                                   int(k2_by)))
+
+    def tiles(self) -> dict:
+        out = np.zeros(7, np.int32)
+        _check(load_library().ibp_get_tile(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return dict(zip(TILE_FIELDS, (int(v) for v in out)))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -491,3 +512,47 @@ def ibp_autotune(net: Network, lo, hi, stream=None):
         _check(load_library().ibp_autotune(net.handle, n, _dev_ptr(lo), _dev_ptr(hi), _dev_ptr(buf), buf.numel(),
                                            _stream_ptr(stream), chosen.ctypes.data_as(ctypes.c_void_p)))
     return int(chosen[0]), int(chosen[1])
+
+
+def _tile_cache_key(net: Network, n_box: int) -> str:
+    """(device name, buses, lines, outages, box-count bucket): the box count is
+    rounded up to a power of two, as tiles depend on the batch's size class."""
+    name = _torch().cuda.get_device_name(net.device)
+    bucket = 1 << max(0, int(n_box - 1).bit_length())
+    return f"{name}|N{net.n_bus}|L{net.n_line}|K{net.n_ctg}|B{bucket}"
+
+
+def ibp_autotune_batched(net: Network, lo, hi, stream=None, cache: str = None):
+    """Box-tiled tiles for calls like this one: times the candidates on these
+    device boxes (at least 4) and keeps the fastest.  With ``cache`` (a JSON
+    file path), tiles found before for the same device, network sizes and box
+    bucket are set without timing, and new ones are added to the file.
+    Returns (tiles dict, True if taken from the cache)."""
+    import json as _json
+    torch = _torch()
+    lo, hi = _check_boxes(net, lo, hi)
+    n = lo.shape[0]
+    key = _tile_cache_key(net, n)
+    table = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            table = _json.load(f)
+        if key in table:
+            v = table[key]
+            net.set_tile_batched(v["k3_bt"], v["k3_rows"], v["k3_xcd"], v["k2_mfma"], v["k2_by"])
+            return net.tiles(), True
+    need = net.workspace_bytes(n, IBP_F_AUTOTUNE)
+    chosen = np.zeros(5, np.int32)
+    with _on(stream):
+        buf = torch.empty(max(need, 256), dtype=torch.uint8, device=lo.device)
+        _check(load_library().ibp_autotune_batched(net.handle, n, _dev_ptr(lo), _dev_ptr(hi), _dev_ptr(buf),
+                                                   buf.numel(), _stream_ptr(stream),
+                                                   chosen.ctypes.data_as(ctypes.c_void_p)))
+    tiles = net.tiles()
+    if cache:
+        table[key] = {k: tiles[k] for k in ("k3_bt", "k3_rows", "k3_xcd", "k2_mfma", "k2_by")}
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as f:
+            _json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return tiles, False

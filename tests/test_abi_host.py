@@ -206,3 +206,15 @@ def test_ptdf_error_bound_holds_against_a_refined_solve():
     W = sp.coo_matrix((1.0 / b, (f, t)), shape=(N, N)).tocsr()
     path = dijkstra(W, directed=False, indices=int(net["slack_bus"])).max()
     assert np.max(np.abs(fac["Binv"])) <= np.max(np.diag(fac["Binv"])) <= path
+
+
+def test_tile_setters_validate_on_a_host_handle(lib):
+    h = _host(synth.make_config("tiny"))
+    assert h.tiles()["k3_bt"] == 4
+    h.set_tile_batched(8, 12, 1, 0, 0)
+    assert h.tiles() == dict(h.tiles(), k3_bt=8, k3_rows=12, k3_xcd=1, k2_mfma=0, k2_by=0)
+    for bad in ((3, 0, 0, 1, 0), (4, -1, 0, 1, 0), (4, 0, 2, 1, 0), (4, 0, 0, 2, 0), (4, 0, 0, 1, 9)):
+        with pytest.raises(ibp.IBPError) as e:
+            h.set_tile_batched(*bad)
+        assert e.value.name == "IBP_E_INVALID_ARG"
+    assert ibp.STATUS[lib.ibp_autotune_batched(h.handle, 8, None, None, None, 0, None, None)] == "IBP_E_HOST_ONLY"
