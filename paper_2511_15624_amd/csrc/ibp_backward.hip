@@ -83,12 +83,21 @@ __device__ __forceinline__ float butterfly32(float (&v)[32]) {
 // side only (chi = 0: the gradient of f_hi), 2 the upper side only (clo = 0:
 // the gradient of f_lo); a side whose weight is zero contributes exactly
 // zero, so skipping it changes nothing but the sign of a zero.
+// The outage factors are finite except the outaged line's own entry, which
+// the network builder stores as the positive quiet NaN.  As signed integers,
+// positive NaNs and +inf lie above FLT_MAX and every negative float below it,
+// so one integer min maps that entry to FLT_MAX and leaves the others as they
+// are (fminf would first canonicalise its operand: two instructions).
+__device__ __forceinline__ float finite_factor(float lam) {
+  return __int_as_float(min(__float_as_int(lam), 0x7f7fffff));
+}
+
 template <int SIDES>
-__device__ __forceinline__ void k5_elem(float lam, float cc, float rc, float cl, float rlm, float rlp, float chi,
-                                        float clo, float& gc, float& gr, float& pc, float& pr) {
+__device__ __forceinline__ void k5_elem(float lam, float lam0, float cc, float rc, float cl, float rlm, float rlp,
+                                        float chi, float clo, float& gc, float& gr, float& pc, float& pr) {
   // The outaged line's own entry holds NaN: both activity tests fail and
-  // dC = dR = 0 (the paper's mask M).  fminf(NaN, FLT_MAX) = FLT_MAX (IEEE
-  // minNum) keeps the NaN out of the outage-side products, which then add 0.
+  // dC = dR = 0 (the paper's mask M).  lam0 = finite_factor(lam) keeps the NaN
+  // out of the outage-side products, which then add 0.
   const float C = fmaf(lam, cc, cl);
   const float a = fabsf(C);
   float hi = 0.0f, lo = 0.0f;
@@ -106,7 +115,6 @@ __device__ __forceinline__ void k5_elem(float lam, float cc, float rc, float cl,
   // exactly only happens for a line whose flow interval is {0} here, where no
   // penalty is active and hi + lo = 0
   const float dC = __int_as_float(__float_as_int(s) ^ (__float_as_int(C) & (int)0x80000000));
-  const float lam0 = fminf(lam, FLT_MAX);
   gc += dC;
   gr += dR;
   pc = fmaf(lam0, dC, pc);
@@ -166,10 +174,10 @@ __global__ __launch_bounds__(256) void k5_outage_vjp(DevNet net, void* ws, WsLay
         const float cc = __int_as_float(d.y), rc = __int_as_float(d.w);
         const float4 x = on ? lam[(size_t)k * Lp4] : make_float4(0.f, 0.f, 0.f, 0.f);
         float pc = 0.0f, pr = 0.0f;
-        k5_elem<3>(x.x, cc, rc, c4.x, rm4.x, rp4.x, chi, clo, gc[0], gr[0], pc, pr);
-        k5_elem<3>(x.y, cc, rc, c4.y, rm4.y, rp4.y, chi, clo, gc[1], gr[1], pc, pr);
-        k5_elem<3>(x.z, cc, rc, c4.z, rm4.z, rp4.z, chi, clo, gc[2], gr[2], pc, pr);
-        k5_elem<3>(x.w, cc, rc, c4.w, rm4.w, rp4.w, chi, clo, gc[3], gr[3], pc, pr);
+        k5_elem<3>(x.x, finite_factor(x.x), cc, rc, c4.x, rm4.x, rp4.x, chi, clo, gc[0], gr[0], pc, pr);
+        k5_elem<3>(x.y, finite_factor(x.y), cc, rc, c4.y, rm4.y, rp4.y, chi, clo, gc[1], gr[1], pc, pr);
+        k5_elem<3>(x.z, finite_factor(x.z), cc, rc, c4.z, rm4.z, rp4.z, chi, clo, gc[2], gr[2], pc, pr);
+        k5_elem<3>(x.w, finite_factor(x.w), cc, rc, c4.w, rm4.w, rp4.w, chi, clo, gc[3], gr[3], pc, pr);
         v[2 * i] = pc;
         v[2 * i + 1] = pr;
       }
@@ -199,6 +207,53 @@ __global__ __launch_bounds__(256) void k5_outage_vjp(DevNet net, void* ws, WsLay
 // outage-factor tile serves 16 boxes.  Per-outage sums of 4 outages x 4 boxes
 // x 2 fields go through one 32-value butterfly.
 constexpr int kBT5 = 4;
+
+// One step of the box-tiled backward sweep: outages ks .. ks + 3 (FULL) or
+// ks .. k1 - 1 for kBT5 boxes and the four lines of each lane; per-outage
+// (centre, radius) partials through one 32-value butterfly, stored for box
+// b0 + i at cp[(b0 + i) * box_stride + k].
+template <int S, bool FULL>
+__device__ __forceinline__ void k5b_step(const float4 (&x)[4], const float2 (&q)[kBT5][4], const float4 (&c4)[kBT5],
+                                         const float4 (&rm4)[kBT5], const float4 (&rp4)[kBT5],
+                                         const float (&chi)[kBT5], const float (&clo)[kBT5],
+                                         float (&gc)[kBT5][4], float (&gr)[kBT5][4], int ks, int k1, int lane,
+                                         int64_t b0, int64_t n_box, float2* cp, size_t box_stride) {
+  const int nk = FULL ? 4 : min(4, k1 - ks);
+  float v[32];
+#pragma unroll
+  for (int u = 0; u < 32; ++u) v[u] = 0.0f;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    if (FULL || kk < nk) {  // uniform
+      const float l0x = finite_factor(x[kk].x), l0y = finite_factor(x[kk].y);
+      const float l0z = finite_factor(x[kk].z), l0w = finite_factor(x[kk].w);
+#pragma unroll
+      for (int i = 0; i < kBT5; ++i) {
+        const float cc = q[i][kk].x, rc = q[i][kk].y;
+        float pc = 0.0f, pr = 0.0f;
+        k5_elem<S>(x[kk].x, l0x, cc, rc, c4[i].x, rm4[i].x, rp4[i].x, chi[i], clo[i], gc[i][0], gr[i][0], pc, pr);
+        k5_elem<S>(x[kk].y, l0y, cc, rc, c4[i].y, rm4[i].y, rp4[i].y, chi[i], clo[i], gc[i][1], gr[i][1], pc, pr);
+        k5_elem<S>(x[kk].z, l0z, cc, rc, c4[i].z, rm4[i].z, rp4[i].z, chi[i], clo[i], gc[i][2], gr[i][2], pc, pr);
+        k5_elem<S>(x[kk].w, l0w, cc, rc, c4[i].w, rm4[i].w, rp4[i].w, chi[i], clo[i], gc[i][3], gr[i][3], pc, pr);
+        v[(kk * kBT5 + i) * 2] = pc;
+        v[(kk * kBT5 + i) * 2 + 1] = pr;
+      }
+    }
+    // The line accumulators are updated here, outage by outage: without the
+    // (empty) pin the compiler defers every update of a branch-free step to
+    // its end and holds all 64 elements' terms at once (256 registers).
+#pragma unroll
+    for (int i = 0; i < kBT5 && FULL; ++i)
+      asm volatile("" : "+v"(gc[i][0]), "+v"(gc[i][1]), "+v"(gc[i][2]), "+v"(gc[i][3]), "+v"(gr[i][0]),
+                   "+v"(gr[i][1]), "+v"(gr[i][2]), "+v"(gr[i][3]));
+  }
+  const float tot = butterfly32(v);
+  const int idx = lane >> 1;  // (outage ks + idx / 8, box idx / 2 % 4, field idx % 2)
+  const int k = ks + (idx >> 3);
+  const int i = (idx >> 1) & 3;
+  if ((lane & 1) == 0 && (FULL || k < k1) && b0 + i < n_box)
+    reinterpret_cast<float*>(cp + (size_t)(b0 + i) * box_stride + k)[idx & 1] = tot;
+}
 
 // MODE 1 / 2: the caller asked for the gradient of f_hi / f_lo alone (the
 // other weight pointer is null), so only that side's code is compiled into
@@ -231,7 +286,9 @@ __global__ __launch_bounds__(256) void k5b_outage_vjp(DevNet net, void* ws, WsLa
     line_radii(net, ws, lay, bb[i], col, on, c4[i], rm4[i], rp4[i]);
     cd[i] = cb_all + bb[i] * net.K;
   }
-  const float4* lam = reinterpret_cast<const float4*>(net.lodf) + col;
+  // lanes past the last column read the last one: their radii (line_radii)
+  // keep every activity test false, so they add nothing
+  const float4* lam = reinterpret_cast<const float4*>(net.lodf) + (on ? col : Lp4 - 1);
   float gc[kBT5][4], gr[kBT5][4];
 #pragma unroll
   for (int i = 0; i < kBT5; ++i)
@@ -247,15 +304,74 @@ __global__ __launch_bounds__(256) void k5b_outage_vjp(DevNet net, void* ws, WsLa
     no_lo = no_lo && clo[i] == 0.0f;
   }
   // Steps of four outages x kBT5 boxes x four lines per lane, each ending in
-  // one butterfly over its 32 per-outage sums.  The outage-factor rows of the
-  // next step are loaded before this step's arithmetic; the per-outage
-  // (centre, radius) pairs come by scalar loads at the start of the step.
+  // one butterfly over its 32 per-outage sums.  Full steps go in pairs over
+  // two sets of factor rows, each set loaded one step before its use (rows
+  // clamped to the block row, so full steps carry no bounds tests, and no
+  // register copies between steps); the per-outage (centre, radius) pairs
+  // come by scalar loads at the start of each step.  The last 1-3 outages of
+  // the block row take the guarded step.
   auto sweep = [&](auto sides) {
     constexpr int S = decltype(sides)::value;
     float4 xn[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      xn[u] = (on && k0 + u < k1) ? lam[(size_t)(k0 + u) * Lp4] : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int u = 0; u < 4; ++u) xn[u] = lam[(size_t)min(k0 + u, k1 - 1) * Lp4];
+    int ks = k0;
+    float4 xb[4];
+    for (; ks + 8 <= k1; ks += 8) {
+      float2 q[kBT5][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int i = 0; i < kBT5; ++i) q[i][u] = cd[i][ks + u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xb[u] = lam[(size_t)min(ks + 4 + u, k1 - 1) * Lp4];
+      __builtin_amdgcn_sched_barrier(0);
+      k5b_step<S, true>(xn, q, c4, rm4, rp4, chi, clo, gc, gr, ks, k1, lane, b0, n_box,
+                        cpart_all + (size_t)tile * net.K, (size_t)lay.k5_tiles * net.K);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int i = 0; i < kBT5; ++i) q[i][u] = cd[i][ks + 4 + u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xn[u] = lam[(size_t)min(ks + 8 + u, k1 - 1) * Lp4];
+      __builtin_amdgcn_sched_barrier(0);
+      k5b_step<S, true>(xb, q, c4, rm4, rp4, chi, clo, gc, gr, ks + 4, k1, lane, b0, n_box,
+                        cpart_all + (size_t)tile * net.K, (size_t)lay.k5_tiles * net.K);
+    }
+    for (; ks + 4 <= k1; ks += 4) {
+      float4 x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[u] = xn[u];
+      float2 q[kBT5][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int i = 0; i < kBT5; ++i) q[i][u] = cd[i][ks + u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xn[u] = lam[(size_t)min(ks + 4 + u, k1 - 1) * Lp4];
+      k5b_step<S, true>(x, q, c4, rm4, rp4, chi, clo, gc, gr, ks, k1, lane, b0, n_box,
+                        cpart_all + (size_t)tile * net.K, (size_t)lay.k5_tiles * net.K);
+    }
+    if (ks < k1) {
+      const int nk = k1 - ks;
+      float2 q[kBT5][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int i = 0; i < kBT5; ++i) q[i][u] = u < nk ? cd[i][ks + u] : make_float2(0.f, 0.f);
+      k5b_step<S, false>(xn, q, c4, rm4, rp4, chi, clo, gc, gr, ks, k1, lane, b0, n_box,
+                         cpart_all + (size_t)tile * net.K, (size_t)lay.k5_tiles * net.K);
+    }
+  };
+  // Calls with both weights: the sides are picked per wave, and every step
+  // keeps its per-outage branches, which bound the live temporaries (with
+  // the branch-free steps above, or the step function, the two-sided code
+  // takes 180-195 registers: two waves per SIMD for the whole kernel).
+  auto sweep_guarded = [&](auto sides) {
+    constexpr int S = decltype(sides)::value;
+    float4 xn[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xn[u] = lam[(size_t)min(k0 + u, k1 - 1) * Lp4];
     for (int ks = k0; ks < k1; ks += 4) {
       const int nk = min(4, k1 - ks);
       float4 x[4];
@@ -267,8 +383,7 @@ __global__ __launch_bounds__(256) void k5b_outage_vjp(DevNet net, void* ws, WsLa
 #pragma unroll
         for (int i = 0; i < kBT5; ++i) q[i][u] = u < nk ? cd[i][ks + u] : make_float2(0.f, 0.f);
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        xn[u] = (on && ks + 4 + u < k1) ? lam[(size_t)(ks + 4 + u) * Lp4] : make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int u = 0; u < 4; ++u) xn[u] = lam[(size_t)min(ks + 4 + u, k1 - 1) * Lp4];
       __builtin_amdgcn_sched_barrier(0);
       float v[32];
 #pragma unroll
@@ -280,10 +395,14 @@ __global__ __launch_bounds__(256) void k5b_outage_vjp(DevNet net, void* ws, WsLa
           for (int i = 0; i < kBT5; ++i) {
             const float cc = q[i][kk].x, rc = q[i][kk].y;
             float pc = 0.0f, pr = 0.0f;
-            k5_elem<S>(x[kk].x, cc, rc, c4[i].x, rm4[i].x, rp4[i].x, chi[i], clo[i], gc[i][0], gr[i][0], pc, pr);
-            k5_elem<S>(x[kk].y, cc, rc, c4[i].y, rm4[i].y, rp4[i].y, chi[i], clo[i], gc[i][1], gr[i][1], pc, pr);
-            k5_elem<S>(x[kk].z, cc, rc, c4[i].z, rm4[i].z, rp4[i].z, chi[i], clo[i], gc[i][2], gr[i][2], pc, pr);
-            k5_elem<S>(x[kk].w, cc, rc, c4[i].w, rm4[i].w, rp4[i].w, chi[i], clo[i], gc[i][3], gr[i][3], pc, pr);
+            k5_elem<S>(x[kk].x, finite_factor(x[kk].x), cc, rc, c4[i].x, rm4[i].x, rp4[i].x, chi[i], clo[i],
+                       gc[i][0], gr[i][0], pc, pr);
+            k5_elem<S>(x[kk].y, finite_factor(x[kk].y), cc, rc, c4[i].y, rm4[i].y, rp4[i].y, chi[i], clo[i],
+                       gc[i][1], gr[i][1], pc, pr);
+            k5_elem<S>(x[kk].z, finite_factor(x[kk].z), cc, rc, c4[i].z, rm4[i].z, rp4[i].z, chi[i], clo[i],
+                       gc[i][2], gr[i][2], pc, pr);
+            k5_elem<S>(x[kk].w, finite_factor(x[kk].w), cc, rc, c4[i].w, rm4[i].w, rp4[i].w, chi[i], clo[i],
+                       gc[i][3], gr[i][3], pc, pr);
             v[(kk * kBT5 + i) * 2] = pc;
             v[(kk * kBT5 + i) * 2 + 1] = pr;
           }
@@ -302,11 +421,11 @@ __global__ __launch_bounds__(256) void k5b_outage_vjp(DevNet net, void* ws, WsLa
   if (MODE != 3)
     sweep(std::integral_constant<int, MODE>());
   else if (no_hi)
-    sweep(std::integral_constant<int, 1>());
+    sweep_guarded(std::integral_constant<int, 1>());
   else if (no_lo)
-    sweep(std::integral_constant<int, 2>());
+    sweep_guarded(std::integral_constant<int, 2>());
   else
-    sweep(std::integral_constant<int, 3>());
+    sweep_guarded(std::integral_constant<int, 3>());
   if (on) {
 #pragma unroll
     for (int i = 0; i < kBT5; ++i) {
