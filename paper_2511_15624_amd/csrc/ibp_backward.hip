@@ -39,7 +39,8 @@ namespace ibp {
 // outages per block row: 128 for the per-box sweep (enough blocks for one
 // box), 512 for the box-tiled sweep, whose per-line partials (one float2 per
 // row, box and line) then take half the traffic (4096 boxes: 14.16 -> 13.8 ms;
-// 512 outages per row: 13.99 -> 13.73 ms for the whole backward;
+// 512 outages per row: 13.99 -> 13.73 ms for the whole backward; 1024 per row
+// trades a slower sweep for a faster line pass, no net change;
 // the chunk must be a compile-time constant for that: a runtime bound gave 14.07)
 constexpr int kK5Chunk = 128;
 constexpr int kK5ChunkTiled = 512;
@@ -610,6 +611,82 @@ __global__ __launch_bounds__(256) void k6b_ptdf_t_tiled(DevNet net, void* ws, Ws
   }
 }
 
+// The same two products on the float32 matrix cores (v_mfma_f32_32x32x2f32):
+// a wave owns 32 boxes x 32 buses of both, a block 2 x 2 waves.  Per step of 8
+// lines each lane loads one float4 of its box row of dC and dR and of its bus
+// row of the transposed PTDF (lines 4h .. 4h + 3 of the step for half-wave h),
+// and the four components feed four MFMAs (k = h picks the line); |Phi| is
+// the loaded value with its sign cleared.  Each 32-line chunk is summed in
+// float32 on the matrix cores and the chunk sums in float64, as in the tiled
+// vector kernel.  Blocks are dealt to the XCDs so that each XCD takes every
+// eighth box tile with all of its bus tiles: a box tile's rows stay in that
+// XCD's L2 while the transposed PTDF streams past.
+typedef float v16f __attribute__((ext_vector_type(16)));
+constexpr int kMB = 64, kMN = 64;
+
+__global__ __launch_bounds__(256) void k6m_ptdf_t_mfma(DevNet net, void* ws, WsLayout lay, int64_t n_box, int n_bt,
+                                                      int n_nt) {
+  const int id = blockIdx.x;
+  const int slot = id >> 3;
+  const int bt = (id & 7) + 8 * (slot / n_nt), nt = slot % n_nt;
+  if (bt >= n_bt) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = lane & 31, h = lane >> 5;
+  const int64_t box0 = (int64_t)bt * kMB + (w >> 1) * 32;
+  const int bus = nt * kMN + (w & 1) * 32 + i;
+  const int Lp = net.Lp;
+  const size_t arow = (size_t)min(box0 + i, n_box - 1) * Lp + 4 * h;
+  const float4* pc = reinterpret_cast<const float4*>(ws_ptr<float>(ws, lay.gcf) + arow);
+  const float4* pr = reinterpret_cast<const float4*>(ws_ptr<float>(ws, lay.grf) + arow);
+  const float4* pp = reinterpret_cast<const float4*>(net.phiT + (size_t)min(bus, net.N - 1) * Lp + 4 * h);
+  double sc[16], sr[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) sc[e] = sr[e] = 0.0;
+  for (int l0 = 0; l0 < Lp; l0 += 32) {
+    float4 a[4], r[4], p[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = pc[(l0 + 8 * u) / 4];
+      r[u] = pr[(l0 + 8 * u) / 4];
+      p[u] = pp[(l0 + 8 * u) / 4];
+    }
+    // all twelve loads of the chunk in flight before its first MFMA (the
+    // compiler would otherwise issue each step's loads after the previous
+    // step's MFMAs and wait on them one step at a time)
+    __builtin_amdgcn_sched_barrier(0);
+    v16f ac = {}, ar = {};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      ac = __builtin_amdgcn_mfma_f32_32x32x2f32(a[u].x, p[u].x, ac, 0, 0, 0);
+      ar = __builtin_amdgcn_mfma_f32_32x32x2f32(r[u].x, fabsf(p[u].x), ar, 0, 0, 0);
+      ac = __builtin_amdgcn_mfma_f32_32x32x2f32(a[u].y, p[u].y, ac, 0, 0, 0);
+      ar = __builtin_amdgcn_mfma_f32_32x32x2f32(r[u].y, fabsf(p[u].y), ar, 0, 0, 0);
+      ac = __builtin_amdgcn_mfma_f32_32x32x2f32(a[u].z, p[u].z, ac, 0, 0, 0);
+      ar = __builtin_amdgcn_mfma_f32_32x32x2f32(r[u].z, fabsf(p[u].z), ar, 0, 0, 0);
+      ac = __builtin_amdgcn_mfma_f32_32x32x2f32(a[u].w, p[u].w, ac, 0, 0, 0);
+      ar = __builtin_amdgcn_mfma_f32_32x32x2f32(r[u].w, fabsf(p[u].w), ar, 0, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      sc[e] += (double)ac[e];
+      sr[e] += (double)ar[e];
+    }
+  }
+  // accumulator e of lane (i, h) holds box row 8 (e / 4) + 4 h + e % 4, bus column i
+  if (bus >= net.Np) return;
+  double* gci = ws_ptr<double>(ws, lay.gci);
+  double* gri = ws_ptr<double>(ws, lay.gri);
+  const bool real = bus < net.N;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int64_t b = box0 + 8 * (e >> 2) + 4 * h + (e & 3);
+    if (b < n_box) {
+      gci[b * net.Np + bus] = real ? sc[e] : 0.0;
+      gri[b * net.Np + bus] = real ? sr[e] : 0.0;
+    }
+  }
+}
+
 // Per input: endpoint gradients (injection, surplus and imbalance terms).
 __global__ __launch_bounds__(256) void k7_endpoints(DevNet net, void* ws, WsLayout lay, int64_t box0,
                                                     const float* __restrict__ box_lo,
@@ -701,8 +778,14 @@ hipError_t launch_backward_sweeps(const DevNet& net, int64_t n_box, void* ws, co
   }
   if (n_box >= kBatchMin) {
     const int t = tm->start(8, s);
-    hipLaunchKernelGGL(k6b_ptdf_t_tiled, dim3((net.Np + kGN - 1) / kGN, (unsigned)((n_box + kGB - 1) / kGB)),
-                       dim3(256), 0, s, net, ws, lay, n_box);
+    if (lay.k2_mfma) {
+      const int n_bt = (int)((n_box + kMB - 1) / kMB), n_nt = (net.Np + kMN - 1) / kMN;
+      hipLaunchKernelGGL(k6m_ptdf_t_mfma, dim3((unsigned)(8 * ((n_bt + 7) / 8) * n_nt)), dim3(256), 0, s, net, ws,
+                         lay, n_box, n_bt, n_nt);
+    } else {
+      hipLaunchKernelGGL(k6b_ptdf_t_tiled, dim3((net.Np + kGN - 1) / kGN, (unsigned)((n_box + kGB - 1) / kGB)),
+                         dim3(256), 0, s, net, ws, lay, n_box);
+    }
     tm->stop(t, s);
   }
   for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
