@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <limits>
 #include <mutex>
 #include <new>
@@ -36,7 +37,15 @@ static __device__ __align__(256) unsigned char scratch[IBP_NOALLOC_SCRATCH_BYTES
 
 namespace {
 
-thread_local std::string g_err;
+// Last error message of this thread: a fixed buffer, so that reporting an
+// allocation failure allocates nothing.
+constexpr size_t kErrBytes = 512;
+thread_local char g_err[kErrBytes];
+
+void set_err(const char* msg) {
+  std::strncpy(g_err, msg, kErrBytes - 1);
+  g_err[kErrBytes - 1] = 0;
+}
 
 // Device address of `scratch` on each device, taken once per device with that
 // device current (at network construction, or at the first no-allocation call).
@@ -44,9 +53,28 @@ constexpr int kMaxScratchDevices = 64;
 std::mutex g_scratch_mu;
 void* g_scratch[kMaxScratchDevices] = {};
 
-ibp_status fail(ibp_status s, const std::string& msg) {
-  g_err = msg;
+ibp_status fail(ibp_status s, const char* msg) {
+  set_err(msg);
   return s;
+}
+ibp_status fail(ibp_status s, const std::string& msg) { return fail(s, msg.c_str()); }
+
+// Every entry point runs its body under this guard: no C++ exception crosses
+// the C boundary.  Host allocation failures (std::bad_alloc, and the
+// length errors of impossible sizes) become IBP_E_OUT_OF_MEMORY; anything
+// else thrown is reported the same way with its message.  Whatever the body
+// had allocated is owned by RAII objects or the handle and freed by then.
+template <typename F>
+ibp_status guarded(F&& body) noexcept {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    return fail(IBP_E_OUT_OF_MEMORY, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(IBP_E_OUT_OF_MEMORY, e.what());
+  } catch (...) {
+    return fail(IBP_E_OUT_OF_MEMORY, "host resource exhausted");
+  }
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -467,68 +495,81 @@ ibp_status for_chunks(const ibp_network* net, int64_t n_box, uint32_t flags, con
 extern "C" {
 
 ibp_status ibp_build_network(const ibp_network_desc* desc, int device, ibp_network** out) {
-  g_err.clear();
-  if (!out) return fail(IBP_E_INVALID_ARG, "out is NULL");
-  *out = nullptr;
-  if (device < IBP_DEVICE_HOST_ONLY) return fail(IBP_E_INVALID_ARG, "device ordinal out of range");
-  ibp_network* net = new (std::nothrow) ibp_network();
-  if (!net) return fail(IBP_E_OUT_OF_MEMORY, "host allocation failed");
-  std::string err;
-  ibp_status st;
-  try {
-    st = ibp::build_host(desc, net->h, err);
-  } catch (const std::bad_alloc&) {
-    st = IBP_E_OUT_OF_MEMORY;
-    err = "host allocation failed during construction";
-  }
-  if (st != IBP_OK) {
-    delete net;
-    return fail(st, err);
-  }
-  if (device >= 0) {
+  return guarded([&]() -> ibp_status {
+    g_err[0] = 0;
+    if (!out) return fail(IBP_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (device < IBP_DEVICE_HOST_ONLY) return fail(IBP_E_INVALID_ARG, "device ordinal out of range");
+    // the handle is owned here until construction succeeds: a failure or an
+    // exception at any step frees it and every device allocation it holds
+    struct Owner {
+      ibp_network* p;
+      ~Owner() {
+        if (p) {
+          release_device(p);
+          delete p;
+        }
+      }
+    } own{new (std::nothrow) ibp_network()};
+    if (!own.p) return fail(IBP_E_OUT_OF_MEMORY, "host allocation failed");
+    ibp_network* net = own.p;
+    std::string err;
+    ibp_status st;
     try {
-      st = to_device(net, device);
+      st = ibp::build_host(desc, net->h, err);
     } catch (const std::bad_alloc&) {
-      st = fail(IBP_E_OUT_OF_MEMORY, "host allocation failed while packing float32 factors");
+      st = IBP_E_OUT_OF_MEMORY;
+      err = "host allocation failed during construction";
     }
-    if (st != IBP_OK) {
-      const std::string keep = g_err;
-      release_device(net);
-      delete net;
-      return fail(st, keep);
+    if (st != IBP_OK) return fail(st, err);
+    if (device >= 0) {
+      try {
+        st = to_device(net, device);
+      } catch (const std::bad_alloc&) {
+        st = fail(IBP_E_OUT_OF_MEMORY, "host allocation failed while packing float32 factors");
+      }
+      if (st != IBP_OK) return st;  // the message is set; Owner frees the handle
     }
-  }
-  *out = net;
-  return IBP_OK;
+    own.p = nullptr;
+    *out = net;
+    return IBP_OK;
+  });
 }
 
 ibp_status ibp_network_query(const ibp_network* net, ibp_network_info* info) {
-  if (!net || !info) return fail(IBP_E_INVALID_ARG, "NULL argument");
-  info->n_bus = net->h.N;
-  info->n_line = net->h.L;
-  info->n_ctg = net->h.K;
-  info->n_gen = net->h.G;
-  info->n_load = net->h.D;
-  info->n_input = net->h.G + net->h.D;
-  info->device = net->device;
-  info->min_one_minus_hcc = net->h.min_one_m_hcc;
-  info->phi_abs_err = net->h.phi_err_max;
-  info->device_bytes = net->device_bytes;
-  info->build_seconds = net->h.build_seconds;
-  return IBP_OK;
+  return guarded([&]() -> ibp_status {
+    if (!net || !info) return fail(IBP_E_INVALID_ARG, "NULL argument");
+    info->n_bus = net->h.N;
+    info->n_line = net->h.L;
+    info->n_ctg = net->h.K;
+    info->n_gen = net->h.G;
+    info->n_load = net->h.D;
+    info->n_input = net->h.G + net->h.D;
+    info->device = net->device;
+    info->min_one_minus_hcc = net->h.min_one_m_hcc;
+    info->phi_abs_err = net->h.phi_err_max;
+    info->device_bytes = net->device_bytes;
+    info->build_seconds = net->h.build_seconds;
+    return IBP_OK;
+  });
 }
 
 ibp_status ibp_network_ctg_lines(const ibp_network* net, int32_t* out) {
-  if (!net || (!out && net->h.K > 0)) return fail(IBP_E_INVALID_ARG, "NULL argument");
-  if (net->h.K) std::memcpy(out, net->h.ctg_line.data(), sizeof(int32_t) * net->h.K);
-  return IBP_OK;
+  return guarded([&]() -> ibp_status {
+    if (!net || (!out && net->h.K > 0)) return fail(IBP_E_INVALID_ARG, "NULL argument");
+    if (net->h.K) std::memcpy(out, net->h.ctg_line.data(), sizeof(int32_t) * net->h.K);
+    return IBP_OK;
+  });
 }
 
 ibp_status ibp_network_export(const ibp_network* net, double* ptdf, double* lodf) {
-  if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
-  if (ptdf) std::memcpy(ptdf, net->h.phi.data(), sizeof(double) * net->h.phi.size());
-  if (lodf) std::memcpy(lodf, net->h.lodf.data(), sizeof(double) * net->h.lodf.size());
-  return IBP_OK;
+  return guarded([&]() -> ibp_status {
+    if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
+    // (no copy at all from an empty matrix: K = 0 leaves the outage factors empty)
+    if (ptdf && !net->h.phi.empty()) std::memcpy(ptdf, net->h.phi.data(), sizeof(double) * net->h.phi.size());
+    if (lodf && !net->h.lodf.empty()) std::memcpy(lodf, net->h.lodf.data(), sizeof(double) * net->h.lodf.size());
+    return IBP_OK;
+  });
 }
 
 void ibp_free_network(ibp_network* net) {
@@ -539,428 +580,467 @@ void ibp_free_network(ibp_network* net) {
 
 size_t ibp_workspace_bytes(const ibp_network* net, int64_t n_box, uint32_t flags) {
   if (!net || net->device < 0 || n_box < 0) return 0;
-  return layout(net, n_box, flags).total;
+  try {
+    return layout(net, n_box, flags).total;
+  } catch (...) {
+    set_err("host allocation failed");
+    return 0;
+  }
 }
 
 ibp_status ibp_bound_boxes(const ibp_network* net, int64_t n_box, const float* box_lo,
                            const float* box_hi, double* f_lo, double* f_hi, double* terms, void* ws,
                            size_t ws_bytes, void* stream, uint32_t flags) {
-  g_err.clear();
-  ibp::WsLayout lay;
-  ibp_status st = check_compute_args(net, n_box, box_lo, box_hi, f_lo, f_hi, ws, ws_bytes, flags, lay);
-  if (st != IBP_OK || n_box == 0) return st;
-  DeviceGuard g(net->device);
-  if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
-  const int64_t X = net->dn.X;
-  return for_chunks(net, n_box, flags, lay, ws_bytes, [&](int64_t b, int64_t nc, const ibp::WsLayout& lc) {
-    hipError_t e = ibp::launch_forward(net->dn, nc, box_lo + b * X, box_hi + b * X, f_lo + b, f_hi + b,
-                                       terms ? terms + 8 * b : nullptr, ws, lc, static_cast<hipStream_t>(stream),
-                                       const_cast<ibp::KernelTimer*>(&net->timer));
-    if (e != hipSuccess) return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
-    return IBP_OK;
+  return guarded([&]() -> ibp_status {
+    g_err[0] = 0;
+    ibp::WsLayout lay;
+    ibp_status st = check_compute_args(net, n_box, box_lo, box_hi, f_lo, f_hi, ws, ws_bytes, flags, lay);
+    if (st != IBP_OK || n_box == 0) return st;
+    DeviceGuard g(net->device);
+    if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
+    const int64_t X = net->dn.X;
+    return for_chunks(net, n_box, flags, lay, ws_bytes, [&](int64_t b, int64_t nc, const ibp::WsLayout& lc) {
+      hipError_t e = ibp::launch_forward(net->dn, nc, box_lo + b * X, box_hi + b * X, f_lo + b, f_hi + b,
+                                         terms ? terms + 8 * b : nullptr, ws, lc, static_cast<hipStream_t>(stream),
+                                         const_cast<ibp::KernelTimer*>(&net->timer));
+      if (e != hipSuccess) return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+      return IBP_OK;
+    });
   });
 }
 
 ibp_status ibp_bound_boxes_noalloc(const ibp_network* net, int64_t n_box, const float* box_lo,
                                    const float* box_hi, double* f_lo, double* f_hi, double* terms, void* stream,
                                    uint32_t flags) {
-  g_err.clear();
-  if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
-  if (net->device < 0) return fail(IBP_E_HOST_ONLY, "network was built host-only");
-  if (flags & ~uint32_t(IBP_F_PLAIN | IBP_F_UPPER_ONLY | IBP_F_LOWER_ONLY))
-    return fail(IBP_E_INVALID_ARG, "flags: only IBP_F_PLAIN, IBP_F_UPPER_ONLY and IBP_F_LOWER_ONLY are accepted");
-  if (n_box < 0) return fail(IBP_E_INVALID_ARG, "n_box < 0");
-  if (n_box == 0) return IBP_OK;
-  const size_t need = layout(net, n_box, flags).total;
-  if (need > IBP_NOALLOC_SCRATCH_BYTES)
-    return fail(IBP_E_WORKSPACE, std::to_string(n_box) + " boxes need " + std::to_string(need) +
-                                     " bytes of workspace, more than the " +
-                                     std::to_string((size_t)IBP_NOALLOC_SCRATCH_BYTES) +
-                                     " bytes of the library's scratch: use ibp_bound_boxes with a workspace, "
-                                     "or fewer boxes per call");
-  DeviceGuard g(net->device);
-  if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
-  void* ws = nullptr;
-  ibp_status st = scratch_address(net->device, &ws);
-  if (st != IBP_OK) return st;
-  ibp::WsLayout lay;
-  st = check_compute_args(net, n_box, box_lo, box_hi, f_lo, f_hi, ws, IBP_NOALLOC_SCRATCH_BYTES, flags, lay);
-  if (st != IBP_OK) return st;
-  // no kernel timing here: its events would be created per call
-  ibp::KernelTimer off;
-  const int64_t X = net->dn.X;
-  return for_chunks(net, n_box, flags, lay, IBP_NOALLOC_SCRATCH_BYTES,
-                    [&](int64_t b, int64_t nc, const ibp::WsLayout& lc) {
-                      hipError_t e = ibp::launch_forward(net->dn, nc, box_lo + b * X, box_hi + b * X, f_lo + b,
-                                                         f_hi + b, terms ? terms + 8 * b : nullptr, ws, lc,
-                                                         static_cast<hipStream_t>(stream), &off);
-                      if (e != hipSuccess)
-                        return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
-                      return IBP_OK;
-                    });
+  return guarded([&]() -> ibp_status {
+    g_err[0] = 0;
+    if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
+    if (net->device < 0) return fail(IBP_E_HOST_ONLY, "network was built host-only");
+    if (flags & ~uint32_t(IBP_F_PLAIN | IBP_F_UPPER_ONLY | IBP_F_LOWER_ONLY))
+      return fail(IBP_E_INVALID_ARG, "flags: only IBP_F_PLAIN, IBP_F_UPPER_ONLY and IBP_F_LOWER_ONLY are accepted");
+    if (n_box < 0) return fail(IBP_E_INVALID_ARG, "n_box < 0");
+    if (n_box == 0) return IBP_OK;
+    const size_t need = layout(net, n_box, flags).total;
+    if (need > IBP_NOALLOC_SCRATCH_BYTES)
+      return fail(IBP_E_WORKSPACE, std::to_string(n_box) + " boxes need " + std::to_string(need) +
+                                       " bytes of workspace, more than the " +
+                                       std::to_string((size_t)IBP_NOALLOC_SCRATCH_BYTES) +
+                                       " bytes of the library's scratch: use ibp_bound_boxes with a workspace, "
+                                       "or fewer boxes per call");
+    DeviceGuard g(net->device);
+    if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
+    void* ws = nullptr;
+    ibp_status st = scratch_address(net->device, &ws);
+    if (st != IBP_OK) return st;
+    ibp::WsLayout lay;
+    st = check_compute_args(net, n_box, box_lo, box_hi, f_lo, f_hi, ws, IBP_NOALLOC_SCRATCH_BYTES, flags, lay);
+    if (st != IBP_OK) return st;
+    // no kernel timing here: its events would be created per call
+    ibp::KernelTimer off;
+    const int64_t X = net->dn.X;
+    return for_chunks(net, n_box, flags, lay, IBP_NOALLOC_SCRATCH_BYTES,
+                      [&](int64_t b, int64_t nc, const ibp::WsLayout& lc) {
+                        hipError_t e = ibp::launch_forward(net->dn, nc, box_lo + b * X, box_hi + b * X, f_lo + b,
+                                                           f_hi + b, terms ? terms + 8 * b : nullptr, ws, lc,
+                                                           static_cast<hipStream_t>(stream), &off);
+                        if (e != hipSuccess)
+                          return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+                        return IBP_OK;
+                      });
+  });
 }
 
 ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box, const float* box_lo,
                               const float* box_hi, const double* g_f_lo, const double* g_f_hi,
                               double* g_box_lo, double* g_box_hi, void* ws, size_t ws_bytes,
                               void* stream, uint32_t flags) {
-  g_err.clear();
-  ibp::WsLayout lay;
-  // one-sided: the weight of the other bound is not read (taken as zero)
-  const bool up = flags & IBP_F_UPPER_ONLY, low = flags & IBP_F_LOWER_ONLY;
-  ibp_status st = check_compute_args(net, n_box, box_lo, box_hi, up ? g_f_hi : g_f_lo, low ? g_f_lo : g_f_hi, ws,
-                                     ws_bytes, flags | IBP_F_BACKWARD, lay);
-  if (st != IBP_OK || n_box == 0) return st;
-  if (!g_box_lo || !g_box_hi) return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
-  if (up) g_f_lo = nullptr;
-  if (low) g_f_hi = nullptr;
-  DeviceGuard g(net->device);
-  if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  ibp::KernelTimer* tm = const_cast<ibp::KernelTimer*>(&net->timer);
-  const int64_t X = net->dn.X;
-  return for_chunks(net, n_box, flags | IBP_F_BACKWARD, lay, ws_bytes,
-                    [&](int64_t b, int64_t nc, const ibp::WsLayout& lc) {
-                      const float *lo = box_lo + b * X, *hi = box_hi + b * X;
-                      hipError_t e = ibp::launch_forward_prep(net->dn, nc, lo, hi, ws, lc, s, tm);
-                      if (e == hipSuccess)
-                        e = ibp::launch_backward_sweeps(net->dn, nc, ws, lc, lo, hi, g_f_lo ? g_f_lo + b : nullptr,
-                                                        g_f_hi ? g_f_hi + b : nullptr, g_box_lo + b * X,
-                                                        g_box_hi + b * X, s, tm);
-                      if (e != hipSuccess)
-                        return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
-                      return IBP_OK;
-                    });
+  return guarded([&]() -> ibp_status {
+    g_err[0] = 0;
+    ibp::WsLayout lay;
+    // one-sided: the weight of the other bound is not read (taken as zero)
+    const bool up = flags & IBP_F_UPPER_ONLY, low = flags & IBP_F_LOWER_ONLY;
+    ibp_status st = check_compute_args(net, n_box, box_lo, box_hi, up ? g_f_hi : g_f_lo, low ? g_f_lo : g_f_hi, ws,
+                                       ws_bytes, flags | IBP_F_BACKWARD, lay);
+    if (st != IBP_OK || n_box == 0) return st;
+    if (!g_box_lo || !g_box_hi) return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
+    if (up) g_f_lo = nullptr;
+    if (low) g_f_hi = nullptr;
+    DeviceGuard g(net->device);
+    if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ibp::KernelTimer* tm = const_cast<ibp::KernelTimer*>(&net->timer);
+    const int64_t X = net->dn.X;
+    return for_chunks(net, n_box, flags | IBP_F_BACKWARD, lay, ws_bytes,
+                      [&](int64_t b, int64_t nc, const ibp::WsLayout& lc) {
+                        const float *lo = box_lo + b * X, *hi = box_hi + b * X;
+                        hipError_t e = ibp::launch_forward_prep(net->dn, nc, lo, hi, ws, lc, s, tm);
+                        if (e == hipSuccess)
+                          e = ibp::launch_backward_sweeps(net->dn, nc, ws, lc, lo, hi, g_f_lo ? g_f_lo + b : nullptr,
+                                                          g_f_hi ? g_f_hi + b : nullptr, g_box_lo + b * X,
+                                                          g_box_hi + b * X, s, tm);
+                        if (e != hipSuccess)
+                          return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+                        return IBP_OK;
+                      });
+  });
 }
 
 ibp_status ibp_crown_bound_boxes(const ibp_network* net, int64_t n_box, const float* box_lo,
                                  const float* box_hi, int32_t ref_iters, double* f_lo, double* f_hi,
                                  double* crown_hi, float* vertex, void* ws, size_t ws_bytes, void* stream,
                                  uint32_t flags) {
-  g_err.clear();
-  if (flags & ~uint32_t(IBP_F_PLAIN | IBP_F_UPPER_ONLY))
-    return fail(IBP_E_INVALID_ARG, "flags: only IBP_F_PLAIN and IBP_F_UPPER_ONLY are accepted");
-  if (ref_iters < 0 || ref_iters > 64) return fail(IBP_E_INVALID_ARG, "ref_iters must be in [0, 64]");
-  ibp::WsLayout lay;
-  const uint32_t need = flags | IBP_F_CROWN | (ref_iters > 0 ? IBP_F_CROWN_REF : 0u);
-  ibp_status st = check_compute_args(net, n_box, box_lo, box_hi, f_lo, f_hi, ws, ws_bytes, need, lay);
-  if (st != IBP_OK || n_box == 0) return st;
-  DeviceGuard g(net->device);
-  if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  ibp::KernelTimer* tm = const_cast<ibp::KernelTimer*>(&net->timer);
-  const int64_t X = net->dn.X;
-  return for_chunks(net, n_box, need, lay, ws_bytes, [&](int64_t b, int64_t nc, const ibp::WsLayout& lc) {
-    const float *lo = box_lo + b * X, *hi = box_hi + b * X;
-    hipError_t e = ibp::launch_forward(net->dn, nc, lo, hi, f_lo + b, f_hi + b, nullptr, ws, lc, s, tm);
-    if (e == hipSuccess)
-      e = ibp::launch_crown(net->dn, nc, lo, hi, ref_iters, f_hi + b, crown_hi ? crown_hi + b : nullptr,
-                            vertex ? vertex + b * X : nullptr, ws, lc, s, tm);
-    if (e != hipSuccess) return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
-    return IBP_OK;
+  return guarded([&]() -> ibp_status {
+    g_err[0] = 0;
+    if (flags & ~uint32_t(IBP_F_PLAIN | IBP_F_UPPER_ONLY))
+      return fail(IBP_E_INVALID_ARG, "flags: only IBP_F_PLAIN and IBP_F_UPPER_ONLY are accepted");
+    if (ref_iters < 0 || ref_iters > 64) return fail(IBP_E_INVALID_ARG, "ref_iters must be in [0, 64]");
+    ibp::WsLayout lay;
+    const uint32_t need = flags | IBP_F_CROWN | (ref_iters > 0 ? IBP_F_CROWN_REF : 0u);
+    ibp_status st = check_compute_args(net, n_box, box_lo, box_hi, f_lo, f_hi, ws, ws_bytes, need, lay);
+    if (st != IBP_OK || n_box == 0) return st;
+    DeviceGuard g(net->device);
+    if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ibp::KernelTimer* tm = const_cast<ibp::KernelTimer*>(&net->timer);
+    const int64_t X = net->dn.X;
+    return for_chunks(net, n_box, need, lay, ws_bytes, [&](int64_t b, int64_t nc, const ibp::WsLayout& lc) {
+      const float *lo = box_lo + b * X, *hi = box_hi + b * X;
+      hipError_t e = ibp::launch_forward(net->dn, nc, lo, hi, f_lo + b, f_hi + b, nullptr, ws, lc, s, tm);
+      if (e == hipSuccess)
+        e = ibp::launch_crown(net->dn, nc, lo, hi, ref_iters, f_hi + b, crown_hi ? crown_hi + b : nullptr,
+                              vertex ? vertex + b * X : nullptr, ws, lc, s, tm);
+      if (e != hipSuccess) return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+      return IBP_OK;
+    });
   });
 }
 
 ibp_status ibp_crown_lower_boxes(const ibp_network* net, int64_t n_box, const float* box_lo,
                                  const float* box_hi, double* f_lo, double* f_hi, double* crown_lo, float* vertex,
                                  void* ws, size_t ws_bytes, void* stream, uint32_t flags) {
-  g_err.clear();
-  if (flags & ~uint32_t(IBP_F_PLAIN | IBP_F_LOWER_ONLY))
-    return fail(IBP_E_INVALID_ARG, "flags: only IBP_F_PLAIN and IBP_F_LOWER_ONLY are accepted");
-  ibp::WsLayout lay;
-  const uint32_t need = flags | IBP_F_CROWN;
-  ibp_status st = check_compute_args(net, n_box, box_lo, box_hi, f_lo, f_hi, ws, ws_bytes, need, lay);
-  if (st != IBP_OK) return st;
-  if (n_box == 0) return IBP_OK;
-  DeviceGuard g(net->device);
-  if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  ibp::KernelTimer* tm = const_cast<ibp::KernelTimer*>(&net->timer);
-  const int64_t X = net->dn.X;
-  return for_chunks(net, n_box, need, lay, ws_bytes, [&](int64_t b, int64_t nc, const ibp::WsLayout& lc) {
-    const float *lo = box_lo + b * X, *hi = box_hi + b * X;
-    hipError_t e = ibp::launch_forward(net->dn, nc, lo, hi, f_lo + b, f_hi + b, nullptr, ws, lc, s, tm);
-    if (e == hipSuccess)
-      e = ibp::launch_crown_lower(net->dn, nc, lo, hi, f_lo + b, crown_lo ? crown_lo + b : nullptr,
-                                  vertex ? vertex + b * X : nullptr, ws, lc, s, tm);
-    if (e != hipSuccess) return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
-    return IBP_OK;
+  return guarded([&]() -> ibp_status {
+    g_err[0] = 0;
+    if (flags & ~uint32_t(IBP_F_PLAIN | IBP_F_LOWER_ONLY))
+      return fail(IBP_E_INVALID_ARG, "flags: only IBP_F_PLAIN and IBP_F_LOWER_ONLY are accepted");
+    ibp::WsLayout lay;
+    const uint32_t need = flags | IBP_F_CROWN;
+    ibp_status st = check_compute_args(net, n_box, box_lo, box_hi, f_lo, f_hi, ws, ws_bytes, need, lay);
+    if (st != IBP_OK) return st;
+    if (n_box == 0) return IBP_OK;
+    DeviceGuard g(net->device);
+    if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ibp::KernelTimer* tm = const_cast<ibp::KernelTimer*>(&net->timer);
+    const int64_t X = net->dn.X;
+    return for_chunks(net, n_box, need, lay, ws_bytes, [&](int64_t b, int64_t nc, const ibp::WsLayout& lc) {
+      const float *lo = box_lo + b * X, *hi = box_hi + b * X;
+      hipError_t e = ibp::launch_forward(net->dn, nc, lo, hi, f_lo + b, f_hi + b, nullptr, ws, lc, s, tm);
+      if (e == hipSuccess)
+        e = ibp::launch_crown_lower(net->dn, nc, lo, hi, f_lo + b, crown_lo ? crown_lo + b : nullptr,
+                                    vertex ? vertex + b * X : nullptr, ws, lc, s, tm);
+      if (e != hipSuccess) return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+      return IBP_OK;
+    });
   });
 }
 
 ibp_status ibp_set_kernel_timing(ibp_network* net, int enable) {
-  if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
-  if (net->device < 0) return fail(IBP_E_HOST_ONLY, "network was built host-only");
-  net->timer.enabled = enable != 0;
-  return IBP_OK;
+  return guarded([&]() -> ibp_status {
+    if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
+    if (net->device < 0) return fail(IBP_E_HOST_ONLY, "network was built host-only");
+    net->timer.enabled = enable != 0;
+    return IBP_OK;
+  });
 }
 
 ibp_status ibp_kernel_times(ibp_network* net, int32_t n_ids, double* total_ms, int64_t* count) {
-  if (!net || !total_ms || !count || n_ids < 0) return fail(IBP_E_INVALID_ARG, "NULL argument");
-  if (net->device < 0) return fail(IBP_E_HOST_ONLY, "network was built host-only");
-  DeviceGuard g(net->device);
-  for (int i = 0; i < n_ids; ++i) {
-    total_ms[i] = 0.0;
-    count[i] = 0;
-  }
-  ibp_status st = IBP_OK;
-  for (auto& r : net->timer.recs) {
-    float ms = 0.0f;
-    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
-      st = fail(IBP_E_DEVICE, "reading kernel timing events failed");
-      continue;
+  return guarded([&]() -> ibp_status {
+    if (!net || !total_ms || !count || n_ids < 0) return fail(IBP_E_INVALID_ARG, "NULL argument");
+    if (net->device < 0) return fail(IBP_E_HOST_ONLY, "network was built host-only");
+    DeviceGuard g(net->device);
+    for (int i = 0; i < n_ids; ++i) {
+      total_ms[i] = 0.0;
+      count[i] = 0;
     }
-    if (r.id >= 0 && r.id < n_ids) {
-      total_ms[r.id] += ms;
-      count[r.id] += 1;
+    ibp_status st = IBP_OK;
+    for (auto& r : net->timer.recs) {
+      float ms = 0.0f;
+      if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+        st = fail(IBP_E_DEVICE, "reading kernel timing events failed");
+        continue;
+      }
+      if (r.id >= 0 && r.id < n_ids) {
+        total_ms[r.id] += ms;
+        count[r.id] += 1;
+      }
     }
-  }
-  clear_timer(net);
-  return st;
+    clear_timer(net);
+    return st;
+  });
 }
 
 ibp_status ibp_set_tile(ibp_network* net, int32_t k2_nc, int32_t k3_kc) {
-  if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
-  ibp::Tune t = net->tune;
-  t.k2_nc = k2_nc;
-  t.k3_kc = k3_kc;
-  if (!ibp::tune_valid(t)) return fail(IBP_E_INVALID_ARG, "unsupported tile parameters");
-  net->tune = t;
-  return IBP_OK;
+  return guarded([&]() -> ibp_status {
+    if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
+    ibp::Tune t = net->tune;
+    t.k2_nc = k2_nc;
+    t.k3_kc = k3_kc;
+    if (!ibp::tune_valid(t)) return fail(IBP_E_INVALID_ARG, "unsupported tile parameters");
+    net->tune = t;
+    return IBP_OK;
+  });
 }
 
 ibp_status ibp_autotune(ibp_network* net, int64_t n_box, const float* box_lo, const float* box_hi,
                         void* ws, size_t ws_bytes, void* stream, int32_t* chosen) {
-  g_err.clear();
-  if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
-  if (net->device < 0) return fail(IBP_E_HOST_ONLY, "network was built host-only");
-  if (n_box <= 0 || !box_lo || !box_hi) return fail(IBP_E_INVALID_ARG, "need at least one device box");
-  const ibp::WsLayout big = layout(net, n_box, IBP_F_AUTOTUNE);
-  if (!ws || ws_bytes < big.total)
-    return fail(IBP_E_WORKSPACE, "autotune workspace needs " + std::to_string(big.total) + " bytes");
-  DeviceGuard g(net->device);
-  if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  // scratch outputs for the timing runs
-  double* f = nullptr;
-  if (hipMalloc(&f, sizeof(double) * 2 * n_box) != hipSuccess)
-    return fail(IBP_E_OUT_OF_MEMORY, "autotune output buffer");
-  hipEvent_t e0, e1;
-  (void)hipEventCreate(&e0);
-  (void)hipEventCreate(&e1);
-  const int ncs[] = {32, 64, 128, 256, 512};
-  const int kcs[] = {16, 32, 64, 128};
-  float best = 1e30f;
-  ibp::Tune best_t = net->tune;
-  ibp::KernelTimer off;
-  ibp_status st = IBP_OK;
-  for (int nc : ncs) {
-    for (int kc : kcs) {
-      ibp::Tune t = net->tune;
-      t.k2_nc = nc;
-      t.k3_kc = kc;
-      const ibp::WsLayout lay = layout_for(net, n_box, t, false);
-      float ms = 0.0f;
-      for (int rep = 0; rep < 2; ++rep) {  // first round warms up
-        (void)hipEventRecord(e0, s);
-        for (int it = 0; it < 3; ++it)
-          if (ibp::launch_forward_single(net->dn, n_box, box_lo, box_hi, f, f + n_box, nullptr, ws, lay, s,
-                                         &off) != hipSuccess)
-            st = fail(IBP_E_DEVICE, "autotune launch failed");
-        (void)hipEventRecord(e1, s);
-        if (hipEventSynchronize(e1) != hipSuccess) st = fail(IBP_E_DEVICE, "autotune synchronize failed");
-        (void)hipEventElapsedTime(&ms, e0, e1);
-      }
-      if (st == IBP_OK && ms < best) {
-        best = ms;
-        best_t = t;
+  return guarded([&]() -> ibp_status {
+    g_err[0] = 0;
+    if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
+    if (net->device < 0) return fail(IBP_E_HOST_ONLY, "network was built host-only");
+    if (n_box <= 0 || !box_lo || !box_hi) return fail(IBP_E_INVALID_ARG, "need at least one device box");
+    const ibp::WsLayout big = layout(net, n_box, IBP_F_AUTOTUNE);
+    if (!ws || ws_bytes < big.total)
+      return fail(IBP_E_WORKSPACE, "autotune workspace needs " + std::to_string(big.total) + " bytes");
+    DeviceGuard g(net->device);
+    if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // scratch outputs for the timing runs
+    double* f = nullptr;
+    if (hipMalloc(&f, sizeof(double) * 2 * n_box) != hipSuccess)
+      return fail(IBP_E_OUT_OF_MEMORY, "autotune output buffer");
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const int ncs[] = {32, 64, 128, 256, 512};
+    const int kcs[] = {16, 32, 64, 128};
+    float best = 1e30f;
+    ibp::Tune best_t = net->tune;
+    ibp::KernelTimer off;
+    ibp_status st = IBP_OK;
+    for (int nc : ncs) {
+      for (int kc : kcs) {
+        ibp::Tune t = net->tune;
+        t.k2_nc = nc;
+        t.k3_kc = kc;
+        const ibp::WsLayout lay = layout_for(net, n_box, t, false);
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2; ++rep) {  // first round warms up
+          (void)hipEventRecord(e0, s);
+          for (int it = 0; it < 3; ++it)
+            if (ibp::launch_forward_single(net->dn, n_box, box_lo, box_hi, f, f + n_box, nullptr, ws, lay, s,
+                                           &off) != hipSuccess)
+              st = fail(IBP_E_DEVICE, "autotune launch failed");
+          (void)hipEventRecord(e1, s);
+          if (hipEventSynchronize(e1) != hipSuccess) st = fail(IBP_E_DEVICE, "autotune synchronize failed");
+          (void)hipEventElapsedTime(&ms, e0, e1);
+        }
+        if (st == IBP_OK && ms < best) {
+          best = ms;
+          best_t = t;
+        }
       }
     }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipFree(f);
-  if (st != IBP_OK) return st;
-  net->tune = best_t;
-  if (chosen) {
-    chosen[0] = best_t.k2_nc;
-    chosen[1] = best_t.k3_kc;
-  }
-  return IBP_OK;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(f);
+    if (st != IBP_OK) return st;
+    net->tune = best_t;
+    if (chosen) {
+      chosen[0] = best_t.k2_nc;
+      chosen[1] = best_t.k3_kc;
+    }
+    return IBP_OK;
+  });
 }
 
 ibp_status ibp_set_tile_batched(ibp_network* net, int32_t k3_bt, int32_t k3_rows, int32_t k3_xcd, int32_t k2_mfma,
                                 int32_t k2_by) {
-  if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
-  ibp::Tune t = net->tune;
-  t.k3_bt = k3_bt;
-  t.k3_rows = k3_rows;
-  t.k3_xcd = k3_xcd;
-  t.k2b_mfma = k2_mfma;
-  t.k2_by = k2_by;
-  if (!ibp::tune_batched_valid(t)) return fail(IBP_E_INVALID_ARG, "unsupported box-tiled tile parameters");
-  net->tune = t;
-  return IBP_OK;
+  return guarded([&]() -> ibp_status {
+    if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
+    ibp::Tune t = net->tune;
+    t.k3_bt = k3_bt;
+    t.k3_rows = k3_rows;
+    t.k3_xcd = k3_xcd;
+    t.k2b_mfma = k2_mfma;
+    t.k2_by = k2_by;
+    if (!ibp::tune_batched_valid(t)) return fail(IBP_E_INVALID_ARG, "unsupported box-tiled tile parameters");
+    net->tune = t;
+    return IBP_OK;
+  });
 }
 
 ibp_status ibp_get_tile(const ibp_network* net, int32_t* out) {
-  if (!net || !out) return fail(IBP_E_INVALID_ARG, "NULL argument");
-  const ibp::Tune& t = net->tune;
-  const int32_t v[7] = {t.k2_nc, t.k3_kc, t.k3_bt, t.k3_rows, t.k3_xcd, t.k2b_mfma, t.k2_by};
-  std::memcpy(out, v, sizeof(v));
-  return IBP_OK;
+  return guarded([&]() -> ibp_status {
+    if (!net || !out) return fail(IBP_E_INVALID_ARG, "NULL argument");
+    const ibp::Tune& t = net->tune;
+    const int32_t v[7] = {t.k2_nc, t.k3_kc, t.k3_bt, t.k3_rows, t.k3_xcd, t.k2b_mfma, t.k2_by};
+    std::memcpy(out, v, sizeof(v));
+    return IBP_OK;
+  });
 }
 
 ibp_status ibp_autotune_batched(ibp_network* net, int64_t n_box, const float* box_lo, const float* box_hi,
                                 void* ws, size_t ws_bytes, void* stream, int32_t* chosen) {
-  g_err.clear();
-  if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
-  if (net->device < 0) return fail(IBP_E_HOST_ONLY, "network was built host-only");
-  if (n_box < ibp::kBatchMin || !box_lo || !box_hi)
-    return fail(IBP_E_INVALID_ARG, "the box-tiled autotuner needs at least 4 device boxes");
-  if (n_box > 16 * 65535) return fail(IBP_E_INVALID_ARG, "too many boxes for one tuning launch");
-  const ibp::WsLayout big = layout(net, n_box, IBP_F_AUTOTUNE);
-  if (!ws || ws_bytes < big.total)
-    return fail(IBP_E_WORKSPACE, "autotune workspace needs " + std::to_string(big.total) + " bytes");
-  DeviceGuard g(net->device);
-  if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-    return fail(IBP_E_DEVICE, "autotune events");
-  ibp::KernelTimer off;
-  ibp_status st = IBP_OK;
-  auto time_it = [&](auto launch) {
-    float best = 1e30f;
-    for (int rep = 0; rep < 3; ++rep) {  // the first run warms up
-      float ms = 0.0f;
-      (void)hipEventRecord(e0, s);
-      if (launch() != hipSuccess) st = fail(IBP_E_DEVICE, "autotune launch failed");
-      (void)hipEventRecord(e1, s);
-      if (hipEventSynchronize(e1) != hipSuccess) st = fail(IBP_E_DEVICE, "autotune synchronize failed");
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (rep > 0) best = std::min(best, ms);
+  return guarded([&]() -> ibp_status {
+    g_err[0] = 0;
+    if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
+    if (net->device < 0) return fail(IBP_E_HOST_ONLY, "network was built host-only");
+    if (n_box < ibp::kBatchMin || !box_lo || !box_hi)
+      return fail(IBP_E_INVALID_ARG, "the box-tiled autotuner needs at least 4 device boxes");
+    if (n_box > 16 * 65535) return fail(IBP_E_INVALID_ARG, "too many boxes for one tuning launch");
+    const ibp::WsLayout big = layout(net, n_box, IBP_F_AUTOTUNE);
+    if (!ws || ws_bytes < big.total)
+      return fail(IBP_E_WORKSPACE, "autotune workspace needs " + std::to_string(big.total) + " bytes");
+    DeviceGuard g(net->device);
+    if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+      return fail(IBP_E_DEVICE, "autotune events");
+    ibp::KernelTimer off;
+    ibp_status st = IBP_OK;
+    auto time_it = [&](auto launch) {
+      float best = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {  // the first run warms up
+        float ms = 0.0f;
+        (void)hipEventRecord(e0, s);
+        if (launch() != hipSuccess) st = fail(IBP_E_DEVICE, "autotune launch failed");
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) st = fail(IBP_E_DEVICE, "autotune synchronize failed");
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) best = std::min(best, ms);
+      }
+      return best;
+    };
+    // base flows: box preparation once, then every engine / chunking (each
+    // writes only its own partials)
+    ibp::Tune best_t = net->tune;
+    {
+      float best = 1e30f;
+      for (const ibp::Tune& c : flow_candidates(net, net->tune)) {
+        ibp::WsLayout lay = layout_for(net, n_box, c, true);
+        if (ibp::launch_forward_prep(net->dn, n_box, box_lo, box_hi, ws, lay, s, &off) != hipSuccess)
+          st = fail(IBP_E_DEVICE, "autotune preparation failed");
+        const float ms = time_it([&] { return ibp::launch_batched_sweeps(net->dn, n_box, ws, lay, s, &off, 0); });
+        if (st == IBP_OK && ms < best) {
+          best = ms;
+          best_t.k2b_mfma = c.k2b_mfma;
+          best_t.k2_by = c.k2_by;
+        }
+      }
     }
-    return best;
-  };
-  // base flows: box preparation once, then every engine / chunking (each
-  // writes only its own partials)
-  ibp::Tune best_t = net->tune;
-  {
-    float best = 1e30f;
-    for (const ibp::Tune& c : flow_candidates(net, net->tune)) {
-      ibp::WsLayout lay = layout_for(net, n_box, c, true);
-      if (ibp::launch_forward_prep(net->dn, n_box, box_lo, box_hi, ws, lay, s, &off) != hipSuccess)
+    // outage sweep: the chosen base flows prepared once, then every candidate
+    // (the line data sit before the per-call partials, at the same offsets)
+    if (st == IBP_OK && net->dn.K > 0) {
+      ibp::WsLayout prep = layout_for(net, n_box, best_t, true);
+      if (ibp::launch_forward_prep(net->dn, n_box, box_lo, box_hi, ws, prep, s, &off) != hipSuccess)
         st = fail(IBP_E_DEVICE, "autotune preparation failed");
-      const float ms = time_it([&] { return ibp::launch_batched_sweeps(net->dn, n_box, ws, lay, s, &off, 0); });
-      if (st == IBP_OK && ms < best) {
-        best = ms;
-        best_t.k2b_mfma = c.k2b_mfma;
-        best_t.k2_by = c.k2_by;
+      float best = 1e30f;
+      ibp::Tune pick = best_t;
+      for (const ibp::Tune& c : sweep_candidates(net, n_box, best_t)) {
+        ibp::WsLayout lay = layout_for(net, n_box, c, true);
+        const float ms = time_it([&] { return ibp::launch_batched_sweeps(net->dn, n_box, ws, lay, s, &off, 1); });
+        if (st == IBP_OK && ms < best) {
+          best = ms;
+          pick = c;
+        }
       }
+      best_t = pick;
     }
-  }
-  // outage sweep: the chosen base flows prepared once, then every candidate
-  // (the line data sit before the per-call partials, at the same offsets)
-  if (st == IBP_OK && net->dn.K > 0) {
-    ibp::WsLayout prep = layout_for(net, n_box, best_t, true);
-    if (ibp::launch_forward_prep(net->dn, n_box, box_lo, box_hi, ws, prep, s, &off) != hipSuccess)
-      st = fail(IBP_E_DEVICE, "autotune preparation failed");
-    float best = 1e30f;
-    ibp::Tune pick = best_t;
-    for (const ibp::Tune& c : sweep_candidates(net, n_box, best_t)) {
-      ibp::WsLayout lay = layout_for(net, n_box, c, true);
-      const float ms = time_it([&] { return ibp::launch_batched_sweeps(net->dn, n_box, ws, lay, s, &off, 1); });
-      if (st == IBP_OK && ms < best) {
-        best = ms;
-        pick = c;
-      }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != IBP_OK) return st;
+    net->tune = best_t;
+    if (chosen) {
+      chosen[0] = best_t.k3_bt;
+      chosen[1] = best_t.k3_rows;
+      chosen[2] = best_t.k3_xcd;
+      chosen[3] = best_t.k2b_mfma;
+      chosen[4] = best_t.k2_by;
     }
-    best_t = pick;
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (st != IBP_OK) return st;
-  net->tune = best_t;
-  if (chosen) {
-    chosen[0] = best_t.k3_bt;
-    chosen[1] = best_t.k3_rows;
-    chosen[2] = best_t.k3_xcd;
-    chosen[3] = best_t.k2b_mfma;
-    chosen[4] = best_t.k2_by;
-  }
-  return IBP_OK;
+    return IBP_OK;
+  });
 }
 
 ibp_status ibp_split_select(int64_t n_act, const int64_t* roots, int32_t slots, const int32_t* n_leaf,
                             int32_t n_input, const float* leaf_lo, const float* leaf_hi, const double* leaf_fhi,
                             int64_t* sel, float* sel_lo, float* sel_hi, void* stream) {
-  g_err.clear();
-  if (n_act < 0 || slots < 1 || n_input < 1) return fail(IBP_E_INVALID_ARG, "bad split sizes");
-  if (n_act == 0) return IBP_OK;
-  if (n_act > 0x7fffffff) return fail(IBP_E_INVALID_ARG, "too many roots");
-  if (!n_leaf || !leaf_lo || !leaf_hi || !leaf_fhi || !sel || !sel_lo || !sel_hi)
-    return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
-  hipError_t e = ibp::launch_split_select(n_act, roots, slots, n_leaf, n_input, leaf_lo, leaf_hi, leaf_fhi, sel,
-                                          sel_lo, sel_hi, static_cast<hipStream_t>(stream));
-  return e == hipSuccess ? IBP_OK : fail(IBP_E_DEVICE, hipGetErrorString(e));
+  return guarded([&]() -> ibp_status {
+    g_err[0] = 0;
+    if (n_act < 0 || slots < 1 || n_input < 1) return fail(IBP_E_INVALID_ARG, "bad split sizes");
+    if (n_act == 0) return IBP_OK;
+    if (n_act > 0x7fffffff) return fail(IBP_E_INVALID_ARG, "too many roots");
+    if (!n_leaf || !leaf_lo || !leaf_hi || !leaf_fhi || !sel || !sel_lo || !sel_hi)
+      return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
+    hipError_t e = ibp::launch_split_select(n_act, roots, slots, n_leaf, n_input, leaf_lo, leaf_hi, leaf_fhi, sel,
+                                            sel_lo, sel_hi, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? IBP_OK : fail(IBP_E_DEVICE, hipGetErrorString(e));
+  });
 }
 
 ibp_status ibp_split_bisect(int64_t n_act, const int64_t* roots, int32_t slots, const int32_t* n_leaf,
                             int32_t n_input, float* leaf_lo, float* leaf_hi, const int64_t* sel,
                             const float* sel_lo, const float* sel_hi, const double* g_lo, const double* g_hi,
                             float* kid_lo, float* kid_hi, float* centers, void* stream) {
-  g_err.clear();
-  if (n_act < 0 || slots < 2 || n_input < 1) return fail(IBP_E_INVALID_ARG, "bad split sizes (need slots >= 2)");
-  if (n_act == 0) return IBP_OK;
-  if (n_act > 0x7fffffff) return fail(IBP_E_INVALID_ARG, "too many roots");
-  if (!n_leaf || !leaf_lo || !leaf_hi || !sel || !sel_lo || !sel_hi || !g_lo || !g_hi || !kid_lo || !kid_hi ||
-      !centers)
-    return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
-  hipError_t e = ibp::launch_split_bisect(n_act, roots, slots, n_leaf, n_input, leaf_lo, leaf_hi, sel, sel_lo,
-                                          sel_hi, g_lo, g_hi, kid_lo, kid_hi, centers,
-                                          static_cast<hipStream_t>(stream));
-  return e == hipSuccess ? IBP_OK : fail(IBP_E_DEVICE, hipGetErrorString(e));
+  return guarded([&]() -> ibp_status {
+    g_err[0] = 0;
+    if (n_act < 0 || slots < 2 || n_input < 1) return fail(IBP_E_INVALID_ARG, "bad split sizes (need slots >= 2)");
+    if (n_act == 0) return IBP_OK;
+    if (n_act > 0x7fffffff) return fail(IBP_E_INVALID_ARG, "too many roots");
+    if (!n_leaf || !leaf_lo || !leaf_hi || !sel || !sel_lo || !sel_hi || !g_lo || !g_hi || !kid_lo || !kid_hi ||
+        !centers)
+      return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
+    hipError_t e = ibp::launch_split_bisect(n_act, roots, slots, n_leaf, n_input, leaf_lo, leaf_hi, sel, sel_lo,
+                                            sel_hi, g_lo, g_hi, kid_lo, kid_hi, centers,
+                                            static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? IBP_OK : fail(IBP_E_DEVICE, hipGetErrorString(e));
+  });
 }
 
 ibp_status ibp_split_update(int64_t n_act, const int64_t* roots, int32_t slots, int32_t* n_leaf,
                             const int64_t* sel, const double* kid_fhi, int32_t points_per_root,
                             const double* point_flo, const float* points, int32_t n_input, double* leaf_fhi,
                             double* root_ub, double* root_lb, float* root_x, void* stream) {
-  g_err.clear();
-  if (n_act < 0 || slots < 2 || points_per_root < 0 || n_input < 1)
-    return fail(IBP_E_INVALID_ARG, "bad split sizes");
-  if (n_act == 0) return IBP_OK;
-  if (n_act > 0x7fffffff) return fail(IBP_E_INVALID_ARG, "too many roots");
-  if (!n_leaf || !sel || !kid_fhi || !leaf_fhi || !root_ub || !root_lb ||
-      (points_per_root > 0 && !point_flo) || (root_x && points_per_root > 0 && !points))
-    return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
-  hipError_t e = ibp::launch_split_update(n_act, roots, slots, n_leaf, sel, kid_fhi, points_per_root, point_flo,
-                                          points, n_input, leaf_fhi, root_ub, root_lb, root_x,
-                                          static_cast<hipStream_t>(stream));
-  return e == hipSuccess ? IBP_OK : fail(IBP_E_DEVICE, hipGetErrorString(e));
+  return guarded([&]() -> ibp_status {
+    g_err[0] = 0;
+    if (n_act < 0 || slots < 2 || points_per_root < 0 || n_input < 1)
+      return fail(IBP_E_INVALID_ARG, "bad split sizes");
+    if (n_act == 0) return IBP_OK;
+    if (n_act > 0x7fffffff) return fail(IBP_E_INVALID_ARG, "too many roots");
+    if (!n_leaf || !sel || !kid_fhi || !leaf_fhi || !root_ub || !root_lb ||
+        (points_per_root > 0 && !point_flo) || (root_x && points_per_root > 0 && !points))
+      return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
+    hipError_t e = ibp::launch_split_update(n_act, roots, slots, n_leaf, sel, kid_fhi, points_per_root, point_flo,
+                                            points, n_input, leaf_fhi, root_ub, root_lb, root_x,
+                                            static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? IBP_OK : fail(IBP_E_DEVICE, hipGetErrorString(e));
+  });
 }
 
 ibp_status ibp_split_screen(int64_t n_root, const double* root_ub, const double* root_lb, double rel_tol,
                             int32_t* status, int64_t* open_roots, int64_t* n_open, void* stream) {
-  g_err.clear();
-  if (n_root < 0 || !(rel_tol >= 0.0)) return fail(IBP_E_INVALID_ARG, "bad screening arguments");
-  if (!root_ub || !root_lb || !status || !open_roots || !n_open)
-    return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
-  hipError_t e = ibp::launch_split_screen(n_root, root_ub, root_lb, rel_tol, status, open_roots, n_open,
-                                          static_cast<hipStream_t>(stream));
-  return e == hipSuccess ? IBP_OK : fail(IBP_E_DEVICE, hipGetErrorString(e));
+  return guarded([&]() -> ibp_status {
+    g_err[0] = 0;
+    if (n_root < 0 || !(rel_tol >= 0.0)) return fail(IBP_E_INVALID_ARG, "bad screening arguments");
+    if (!root_ub || !root_lb || !status || !open_roots || !n_open)
+      return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
+    hipError_t e = ibp::launch_split_screen(n_root, root_ub, root_lb, rel_tol, status, open_roots, n_open,
+                                            static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? IBP_OK : fail(IBP_E_DEVICE, hipGetErrorString(e));
+  });
 }
 
 ibp_status ibp_read_probe(const void* src, int64_t n_float4, float* partial, void* stream) {
-  g_err.clear();
-  if (!src || !partial || n_float4 < 1) return fail(IBP_E_INVALID_ARG, "read probe needs a buffer and a size");
-  if (reinterpret_cast<uintptr_t>(src) % 16 != 0) return fail(IBP_E_INVALID_ARG, "read probe source not 16-byte aligned");
-  hipError_t e = ibp::launch_read_probe(static_cast<const float4*>(src), n_float4, partial,
-                                        static_cast<hipStream_t>(stream));
-  return e == hipSuccess ? IBP_OK : fail(IBP_E_DEVICE, hipGetErrorString(e));
+  return guarded([&]() -> ibp_status {
+    g_err[0] = 0;
+    if (!src || !partial || n_float4 < 1) return fail(IBP_E_INVALID_ARG, "read probe needs a buffer and a size");
+    if (reinterpret_cast<uintptr_t>(src) % 16 != 0) return fail(IBP_E_INVALID_ARG, "read probe source not 16-byte aligned");
+    hipError_t e = ibp::launch_read_probe(static_cast<const float4*>(src), n_float4, partial,
+                                          static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? IBP_OK : fail(IBP_E_DEVICE, hipGetErrorString(e));
+  });
 }
 
-const char* ibp_last_error(void) { return g_err.c_str(); }
+const char* ibp_last_error(void) { return g_err; }
 
 }  // extern "C"

@@ -20,7 +20,9 @@
 #include <cmath>
 #include <limits>
 #include <cstring>
+#include <exception>
 #include <functional>
+#include <mutex>
 #include <queue>
 #include <utility>
 #include <thread>
@@ -40,20 +42,38 @@ void parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, in
     body(0, n);
     return;
   }
+  // Workers take chunks until none is left.  A worker that throws stops the
+  // others from taking more and its exception is rethrown here after every
+  // thread has joined; a thread that cannot be started (resource limits)
+  // leaves its share to the others and to the calling thread, which always
+  // works too.  No exception leaves a joinable thread behind.
   std::atomic<int64_t> next{0};
-  std::vector<std::thread> th;
-  th.reserve(nt);
-  for (int64_t t = 0; t < nt; ++t) {
-    th.emplace_back([&]() {
+  std::exception_ptr err;
+  std::mutex err_mu;
+  auto work = [&]() {
+    try {
       for (;;) {
         int64_t c = next.fetch_add(1);
         if (c >= chunks) break;
         int64_t a = c * grain, b = std::min(n, a + grain);
         body(a, b);
       }
-    });
+    } catch (...) {
+      next.store(chunks);
+      std::lock_guard<std::mutex> lock(err_mu);
+      if (!err) err = std::current_exception();
+    }
+  };
+  std::vector<std::thread> th;
+  try {
+    th.reserve(nt - 1);
+    for (int64_t t = 0; t + 1 < nt; ++t) th.emplace_back(work);
+  } catch (...) {
+    // fewer threads than asked for: the ones started and this one finish
   }
+  work();
   for (auto& t : th) t.join();
+  if (err) std::rethrow_exception(err);
 }
 
 std::vector<uint8_t> find_bridges(int N, const std::vector<int32_t>& from,

@@ -887,7 +887,8 @@ hipError_t launch_forward_prep(const DevNet& net, int64_t n_box, const float* lo
     tm->stop(t, s);
   }
   if (lay.batched) {
-    launch_batched_sweeps(net, n_box, ws, lay, s, tm, 0);
+    const hipError_t e = launch_batched_sweeps(net, n_box, ws, lay, s, tm, 0);
+    if (e != hipSuccess) return e;
   } else {
     for (int64_t b0 = 0; b0 < n_box; b0 += 65535) {
       const int nb = (int)std::min<int64_t>(65535, n_box - b0);
