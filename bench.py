@@ -562,6 +562,10 @@ def main(argv=None):
     ap.add_argument("--backward-only", type=int, default=0, metavar="CALLS",
                     help="only run the one-sided backward (2000 buses, 4096 sub-boxes, gradient of f_hi) CALLS "
                          "times after one warm-up call, and print its per-kernel times; for profiler runs")
+    ap.add_argument("--chord-only", type=int, default=0, metavar="CALLS",
+                    help="only run the chord-relaxation lower bound (8316 buses, one whole box; 2000 buses, 1024 "
+                         "sub-boxes, lower side only) CALLS times each after one warm-up call, and print the "
+                         "relaxation sweep's times; for profiler runs")
     ap.add_argument("--traffic-record", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write the HBM traffic record from four rocprofv3 --pmc output folders (no GPU)")
     args = ap.parse_args(argv)
@@ -599,6 +603,32 @@ def main(argv=None):
         ms3 = _time(torch, lambda: ibp.ibp_bound_boxes(n3, tlo3, thi3, ws=ws3), args.batched_only)
         print(json.dumps({"workload": "2000 buses, 18 x 1024 sub-boxes", "calls": args.batched_only,
                           "ms_per_call": ms3}), flush=True)
+        return 0
+
+    if args.chord_only:
+        res = {}
+        for name, nb in (("c8316", 0), ("c2000", 1024)):
+            netc = synth.make_config(name)
+            nc = ibp.Network(netc, device=0)
+            if nb:
+                lo_, hi_ = synth.sub_boxes(netc, nb, seed=61)
+            else:
+                lo_, hi_ = (a[None].copy() for a in synth.full_box(netc))
+            tl, th = torch.from_numpy(lo_).cuda(), torch.from_numpy(hi_).cuda()
+            wsc = ibp.Workspace(nc)
+            fl = ibp.IBP_F_LOWER_ONLY if nb else 0
+            call = lambda: ibp.ibp_crown_lower_boxes(nc, tl, th, ws=wsc, flags=fl)  # noqa: E731
+            call()
+            nc.set_kernel_timing(True)
+            nc.kernel_times()
+            for _ in range(args.chord_only):
+                call()
+            kt = nc.kernel_times()
+            nc.set_kernel_timing(False)
+            res[name] = {k: v[0] / args.chord_only for k, v in kt.items()}  # per call
+            nc.close()
+        print(json.dumps({"workload": "chord relaxation: 8316 buses one whole box; 2000 buses 1024 sub-boxes",
+                          "calls": args.chord_only, "kernel_ms": res}), flush=True)
         return 0
 
     if args.backward_only:

@@ -84,15 +84,6 @@ __device__ __forceinline__ float butterfly32(float (&v)[32]) {
 // side only (chi = 0: the gradient of f_hi), 2 the upper side only (clo = 0:
 // the gradient of f_lo); a side whose weight is zero contributes exactly
 // zero, so skipping it changes nothing but the sign of a zero.
-// The outage factors are finite except the outaged line's own entry, which
-// the network builder stores as the positive quiet NaN.  As signed integers,
-// positive NaNs and +inf lie above FLT_MAX and every negative float below it,
-// so one integer min maps that entry to FLT_MAX and leaves the others as they
-// are (fminf would first canonicalise its operand: two instructions).
-__device__ __forceinline__ float finite_factor(float lam) {
-  return __int_as_float(min(__float_as_int(lam), 0x7f7fffff));
-}
-
 template <int SIDES>
 __device__ __forceinline__ void k5_elem(float lam, float lam0, float cc, float rc, float cl, float rlm, float rlp,
                                         float chi, float clo, float& gc, float& gr, float& pc, float& pr) {

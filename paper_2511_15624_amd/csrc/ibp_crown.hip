@@ -864,7 +864,7 @@ __device__ __forceinline__ void chord_row(const float4& x, const int4& d, const 
     ca[i] += (int)qa;
     const float a = qs * (1.0f / kSlopeQ);
     // NaN entries carry a = 0 and a finite stand-in
-    const float p = a * fminf(lam[i], FLT_MAX);
+    const float p = a * finite_factor(lam[i]);
     v += p;
     va += fabsf(p);
     n += fabsf(a);

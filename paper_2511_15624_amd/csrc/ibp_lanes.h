@@ -66,4 +66,13 @@ __device__ __forceinline__ double lane_xor(double v) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
+// The outage factors are finite except the outaged line's own entry, which
+// the network builder stores as the positive quiet NaN.  As signed integers,
+// positive NaNs and +inf lie above FLT_MAX and every negative float below it,
+// so one integer min maps that entry to FLT_MAX and leaves the others as they
+// are (fminf would first canonicalise its operand: two instructions).
+__device__ __forceinline__ float finite_factor(float lam) {
+  return __int_as_float(min(__float_as_int(lam), 0x7f7fffff));
+}
+
 }  // namespace ibp
