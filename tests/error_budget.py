@@ -192,3 +192,41 @@ def flip_allowance(net, fac, near):
     allow_lo = 0.5 * zf * (acc_c + acc_r)
     allow_hi = 0.5 * zf * (acc_c + acc_r)
     return allow_lo, allow_hi
+
+
+def crown_near_allowance(net, fac, lo, hi, near_rel=1e-5, chunk=256):
+    """How far the box-slope linear relaxation of the upper bound can move if
+    the slope decisions the oracle reports as near their switch (within
+    near_rel of |c| + r + t, the criterion of oracle.crown_upper) go the other
+    way.  Switching one element between s = sign(c) and s = 0 changes its line
+    by sign(c) z - t, which over the element's interval [c - r, c + r] stays
+    within 2 r + | |c| - r - t | of zero; the bound (a maximum of the sum of
+    lines over the box) moves by at most the weight times that.  Returns
+    (number of near elements, allowance in $), summed over the imbalance
+    (weight zeta_inj, t = 0), the base lines and the outage elements (zeta_f)."""
+    r0 = oracle.ibp(net, lo, hi, fac, keep_intermediates=True)
+    c_inj, r_inj = r0["c_inj"], r0["r_inj"]
+    zi, zf = float(net["zeta_inj"]), float(net["zeta_f"])
+    count, allow = 0, 0.0
+
+    def near(c, r, t, w):
+        m = np.abs(c) - r - t
+        sel = (np.abs(m) <= near_rel * (np.abs(c) + r + t)) & (c != 0)
+        return int(np.sum(sel)), w * float(np.sum((2.0 * r + np.abs(m))[sel]))
+
+    W2 = oracle.ibp_oracle._imbalance_matrix(net)
+    n, a = near(W2 @ c_inj, abs(W2) @ r_inj, 0.0, zi)
+    count, allow = count + n, allow + a
+    n, a = near(r0["c_f"], r0["r_f"], np.asarray(net["fmax_base"], float), zf)
+    count, allow = count + n, allow + a
+    M, Bm, K = fac["M"], fac["B"], fac["K"]
+    fc = np.asarray(net["fmax_ctg"], float)
+    for k0 in range(0, K, chunk):
+        k1 = min(K, k0 + chunk)
+        Mk, Bk = M[k0:k1], Bm[k0:k1]
+        Cc = Mk * r0["c_f"][None, :] - Bk * r0["c_u"][k0:k1, None]
+        Rc = np.abs(Mk) * r0["r_f"][None, :] + np.abs(Bk) * r0["r_u"][k0:k1, None]
+        Cc = np.where(Mk != 0, Cc, 0.0)       # the outaged line's own entry has no penalty
+        n, a = near(Cc, Rc, fc[None, :], zf)
+        count, allow = count + n, allow + a
+    return count, allow
