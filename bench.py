@@ -260,6 +260,10 @@ def hbm_probe(torch, ibp):
 
 VALU_PEAK = 78.6e12  # float32 VALU lane-ops/s: 256 CUs x 128 lanes/clock x 2.4 GHz (FMA = one op)
 MFMA_F64_PEAK = 78.6e12  # float64 dense matrix FLOP/s of MI355X
+MFMA_F32_PEAK = 157.3e12  # float32 dense matrix FLOP/s of MI355X
+VALU_PEAK_SOURCE = ("MI355X float32 vector peak 157.3 TFLOP/s with an FMA counted once: 256 CUs x 128 lanes per "
+                    "clock x 2.4 GHz; the box-tiled sweep's counters show 0.414 wave instructions per SIMD per "
+                    "cycle, above what 16 lanes per clock allow (profiles/ibp_batched_counters_c2000.md)")
 OPS_PER_EVAL = 9.25  # VALU ops per box-outage-line evaluation in the outage sweep (from the ISA)
 # VALU ops per box-outage-line element of the one-sided backward sweep: the
 # post-outage centre and radius (2 fma), the activity test (subtract, compare,
@@ -347,6 +351,7 @@ def extras(torch, ibp, synth, n4, net4):
         "kernel_ms": {k: round(v[0], 3) for k, v in kt.items()},
         "roofline": {"bound": "alu", "kernel": "batched_outage_sweep",
                      "achieved": ev * OPS_PER_EVAL / (sweep_ms * 1e-3), "peak": VALU_PEAK, "unit": "ops/s",
+                     "peak_source": VALU_PEAK_SOURCE,
                      "frac": ev * OPS_PER_EVAL / (sweep_ms * 1e-3) / VALU_PEAK,
                      "ops_per_eval": OPS_PER_EVAL},
     }
@@ -401,12 +406,13 @@ def extras(torch, ibp, synth, n4, net4):
                        "kernel_ms": {k: round(v, 3) for k, v in ktb.items()},
                        "roofline": {"bound": "alu", "kernel": "backward_outage_sweep",
                                     "achieved": ev5 * OPS_PER_BWD_EVAL / (k5_ms * 1e-3), "peak": VALU_PEAK,
+                                    "peak_source": VALU_PEAK_SOURCE,
                                     "unit": "ops/s", "frac": ev5 * OPS_PER_BWD_EVAL / (k5_ms * 1e-3) / VALU_PEAK,
                                     "ops_per_eval": OPS_PER_BWD_EVAL},
-                       "roofline_ptdf_t": {"bound": "alu", "kernel": "backward_ptdf_t",
-                                           "achieved": k6_fma / (k6_ms * 1e-3), "peak": VALU_PEAK,
-                                           "unit": "ops/s", "frac": k6_fma / (k6_ms * 1e-3) / VALU_PEAK,
-                                           "ops": k6_fma}}
+                       "roofline_ptdf_t": {"bound": "mfma", "kernel": "backward_ptdf_t",
+                                           "achieved": 2.0 * k6_fma / (k6_ms * 1e-3), "peak": MFMA_F32_PEAK,
+                                           "unit": "FLOP/s", "frac": 2.0 * k6_fma / (k6_ms * 1e-3) / MFMA_F32_PEAK,
+                                           "flops": 2.0 * k6_fma}}
     # piecewise-linear cost and value curves (1-4 segments per device) on the
     # single large box and on the batched workload, beside the linear-cost runs
     lo4, hi4 = synth.full_box(net4)
