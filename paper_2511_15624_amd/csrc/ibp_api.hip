@@ -79,6 +79,22 @@ ibp_status guarded(F&& body) noexcept {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Timing events and scratch output of an autotuning call, released on every
+// exit (hipFree waits for the queued work that may still use the buffer).
+struct TuneScratch {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  void* buf = nullptr;
+  bool init(size_t bytes) {
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return false;
+    return bytes == 0 || hipMalloc(&buf, bytes) == hipSuccess;
+  }
+  ~TuneScratch() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (buf) (void)hipFree(buf);
+  }
+};
+
 // Address of this device's `scratch` copy; the device must be current.
 ibp_status scratch_address(int device, void** out) {
   if (device < 0 || device >= kMaxScratchDevices)
@@ -804,13 +820,11 @@ ibp_status ibp_autotune(ibp_network* net, int64_t n_box, const float* box_lo, co
     DeviceGuard g(net->device);
     if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    // scratch outputs for the timing runs
-    double* f = nullptr;
-    if (hipMalloc(&f, sizeof(double) * 2 * n_box) != hipSuccess)
-      return fail(IBP_E_OUT_OF_MEMORY, "autotune output buffer");
-    hipEvent_t e0, e1;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
+    // events and scratch outputs for the timing runs
+    TuneScratch sc;
+    if (!sc.init(sizeof(double) * 2 * n_box)) return fail(IBP_E_OUT_OF_MEMORY, "autotune events or output buffer");
+    double* f = static_cast<double*>(sc.buf);
+    const hipEvent_t e0 = sc.e0, e1 = sc.e1;
     const int ncs[] = {32, 64, 128, 256, 512};
     const int kcs[] = {16, 32, 64, 128};
     float best = 1e30f;
@@ -840,9 +854,6 @@ ibp_status ibp_autotune(ibp_network* net, int64_t n_box, const float* box_lo, co
         }
       }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipFree(f);
     if (st != IBP_OK) return st;
     net->tune = best_t;
     if (chosen) {
@@ -894,9 +905,9 @@ ibp_status ibp_autotune_batched(ibp_network* net, int64_t n_box, const float* bo
     DeviceGuard g(net->device);
     if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-      return fail(IBP_E_DEVICE, "autotune events");
+    TuneScratch sc;
+    if (!sc.init(0)) return fail(IBP_E_DEVICE, "autotune events");
+    const hipEvent_t e0 = sc.e0, e1 = sc.e1;
     ibp::KernelTimer off;
     ibp_status st = IBP_OK;
     auto time_it = [&](auto launch) {
@@ -947,8 +958,6 @@ ibp_status ibp_autotune_batched(ibp_network* net, int64_t n_box, const float* bo
       }
       best_t = pick;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (st != IBP_OK) return st;
     net->tune = best_t;
     if (chosen) {
