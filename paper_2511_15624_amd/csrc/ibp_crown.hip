@@ -810,6 +810,9 @@ __global__ __launch_bounds__(256, 2) void kc3m_ptdf_t(DevNet net, void* ws, WsLa
 // per-outage sums sum_l a Lam that the adjoint needs anyway.
 constexpr int kCKB = 32;   // outages per block of the box-tiled chord sweep
 constexpr int kCKB1 = 64;  // outages per block of the per-box chord sweep (half the per-line totals)
+// the per-block line totals of the per-box sweep are int32 sums of at most
+// kCKB1 slopes of at most 2^24 each
+static_assert(((long long)kCKB1 << 24) < (1ll << 31), "per-block slope totals must fit in int32");
 constexpr float kSlopeQ = 16777216.0f;  // 2^24
 
 // One element: fixed-point slope magnitude qa and signed slope qs
