@@ -2,7 +2,11 @@
 backward = ibp_bound_backward (the hand-written VJP kernels).
 
 Gradients are taken with respect to the float32 box endpoints; the library
-returns them in float64 and they are cast to the endpoints' dtype.
+returns them in float64 and they are cast to the endpoints' dtype.  The
+forward keeps its intermediates (box preparation, base flows, line and outage
+constants) in a workspace held by the autograd graph, and the backward reuses
+them instead of recomputing them (IBP_F_KEEP_PREP / IBP_F_REUSE_PREP); the
+workspace has the backward's size and lives until the graph is freed.
 """
 from __future__ import annotations
 
@@ -16,10 +20,13 @@ class IBPBound(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, lo, hi, net, flags: int = 0):
-        f_lo, f_hi = _ibp.ibp_bound_boxes(net, lo.detach(), hi.detach(), flags=flags)
-        ctx.save_for_backward(lo.detach(), hi.detach())
+        lo_d, hi_d = lo.detach().contiguous(), hi.detach().contiguous()
+        ws = _ibp.Workspace(net)
+        f_lo, f_hi = _ibp.ibp_bound_boxes(net, lo_d, hi_d, flags=flags | _ibp.IBP_F_KEEP_PREP, ws=ws)
+        ctx.save_for_backward(lo_d, hi_d)
         ctx.net = net
         ctx.flags = flags
+        ctx.ws = ws
         return f_lo, f_hi
 
     @staticmethod
@@ -30,7 +37,17 @@ class IBPBound(torch.autograd.Function):
             g_lo = torch.zeros(n, dtype=torch.float64, device=lo.device)
         if g_hi is None:
             g_hi = torch.zeros(n, dtype=torch.float64, device=lo.device)
-        d_lo, d_hi = _ibp.ibp_bound_backward(ctx.net, lo, hi, g_lo, g_hi, flags=ctx.flags)
+        flags = ctx.flags & (_ibp.IBP_F_PLAIN | _ibp.IBP_F_UPPER_ONLY | _ibp.IBP_F_LOWER_ONLY)
+        try:
+            d_lo, d_hi = _ibp.ibp_bound_backward(ctx.net, lo, hi, g_lo, g_hi, flags=flags | _ibp.IBP_F_REUSE_PREP,
+                                                 ws=ctx.ws)
+        except _ibp.IBPError as e:
+            # the intermediates are gone (the tiles changed since the forward,
+            # or the call was split into chunks): recompute them
+            if e.name != "IBP_E_INVALID_ARG":
+                raise
+            d_lo, d_hi = _ibp.ibp_bound_backward(ctx.net, lo, hi, g_lo, g_hi, flags=flags, ws=ctx.ws)
+        ctx.ws = None
         return d_lo.to(lo.dtype), d_hi.to(hi.dtype), None, None
 
 

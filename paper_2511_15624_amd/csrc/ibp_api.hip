@@ -18,6 +18,18 @@
 #include "ibp_internal.h"
 #include "ibp_kernels.h"
 
+// The forward intermediates a workspace holds after a call that leaves them
+// (ibp_bound_boxes with IBP_F_KEEP_PREP, or any ibp_bound_backward), for
+// ibp_bound_backward with IBP_F_REUSE_PREP.
+struct PrepTag {
+  const void* ws;
+  int64_t n_box;
+  const float* lo;
+  const float* hi;
+  bool plain;
+  uint64_t tiles;  // tile generation of the handle when they were made
+};
+
 struct ibp_network {
   ibp::HostNet h;
   int device = IBP_DEVICE_HOST_ONLY;
@@ -27,6 +39,9 @@ struct ibp_network {
   size_t device_bytes = 0;
   ibp::KernelTimer timer;
   ibp::Tune tune;
+  uint64_t tile_gen = 0;  // bumped whenever the tiles (and so the workspace layout) change
+  mutable std::mutex prep_mu;
+  mutable std::vector<PrepTag> prep;  // at most one record per workspace
 };
 
 // Library-owned workspace of ibp_bound_boxes_noalloc: one copy per GPU the
@@ -94,6 +109,31 @@ struct TuneScratch {
     if (buf) (void)hipFree(buf);
   }
 };
+
+// Records of kept forward intermediates (see PrepTag): every compute call on
+// a workspace first forgets that workspace's record; the calls that leave the
+// intermediates behind then record them.
+void prep_forget(const ibp_network* net, const void* ws) {
+  std::lock_guard<std::mutex> lock(net->prep_mu);
+  auto& v = net->prep;
+  v.erase(std::remove_if(v.begin(), v.end(), [&](const PrepTag& t) { return t.ws == ws; }), v.end());
+}
+
+void prep_record(const ibp_network* net, const PrepTag& tag) {
+  std::lock_guard<std::mutex> lock(net->prep_mu);
+  auto& v = net->prep;
+  v.erase(std::remove_if(v.begin(), v.end(), [&](const PrepTag& t) { return t.ws == tag.ws; }), v.end());
+  v.push_back(tag);
+}
+
+bool prep_matches(const ibp_network* net, const PrepTag& tag) {
+  std::lock_guard<std::mutex> lock(net->prep_mu);
+  for (const PrepTag& t : net->prep)
+    if (t.ws == tag.ws)
+      return t.n_box == tag.n_box && t.lo == tag.lo && t.hi == tag.hi && t.plain == tag.plain &&
+             t.tiles == tag.tiles;
+  return false;
+}
 
 // Address of this device's `scratch` copy; the device must be current.
 ibp_status scratch_address(int device, void** out) {
@@ -386,7 +426,7 @@ ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
   }
   const bool batched = n_box >= ibp::kBatchMin && !(flags & IBP_F_PLAIN);
   ibp::WsLayout lay = layout_for(net, n_box, net->tune, batched);
-  if (flags & IBP_F_BACKWARD) {
+  if (flags & (IBP_F_BACKWARD | IBP_F_KEEP_PREP)) {
     const ibp::DevNet& d = net->dn;
     const size_t B = (size_t)std::max<int64_t>(1, n_box);
     ibp::plan_backward(d, lay);
@@ -470,7 +510,7 @@ ibp_status check_compute_args(const ibp_network* net, int64_t n_box, const void*
   if (net->device < 0) return fail(IBP_E_HOST_ONLY, "network was built host-only");
   if (n_box < 0) return fail(IBP_E_INVALID_ARG, "n_box < 0");
   if (flags & ~uint32_t(IBP_F_PLAIN | IBP_F_BACKWARD | IBP_F_CROWN | IBP_F_CROWN_REF | IBP_F_UPPER_ONLY |
-                        IBP_F_LOWER_ONLY))
+                        IBP_F_LOWER_ONLY | IBP_F_KEEP_PREP | IBP_F_REUSE_PREP))
     return fail(IBP_E_INVALID_ARG, "unknown flag bits");
   if ((flags & IBP_F_UPPER_ONLY) && (flags & IBP_F_LOWER_ONLY))
     return fail(IBP_E_INVALID_ARG, "IBP_F_UPPER_ONLY and IBP_F_LOWER_ONLY exclude each other");
@@ -610,18 +650,24 @@ ibp_status ibp_bound_boxes(const ibp_network* net, int64_t n_box, const float* b
   return guarded([&]() -> ibp_status {
     g_err[0] = 0;
     ibp::WsLayout lay;
+    if (flags & IBP_F_REUSE_PREP) return fail(IBP_E_INVALID_ARG, "IBP_F_REUSE_PREP is a backward flag");
     ibp_status st = check_compute_args(net, n_box, box_lo, box_hi, f_lo, f_hi, ws, ws_bytes, flags, lay);
     if (st != IBP_OK || n_box == 0) return st;
     DeviceGuard g(net->device);
     if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
+    prep_forget(net, ws);
     const int64_t X = net->dn.X;
-    return for_chunks(net, n_box, flags, lay, ws_bytes, [&](int64_t b, int64_t nc, const ibp::WsLayout& lc) {
+    st = for_chunks(net, n_box, flags, lay, ws_bytes, [&](int64_t b, int64_t nc, const ibp::WsLayout& lc) {
       hipError_t e = ibp::launch_forward(net->dn, nc, box_lo + b * X, box_hi + b * X, f_lo + b, f_hi + b,
                                          terms ? terms + 8 * b : nullptr, ws, lc, static_cast<hipStream_t>(stream),
                                          const_cast<ibp::KernelTimer*>(&net->timer));
       if (e != hipSuccess) return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
       return IBP_OK;
     });
+    // one pass over all boxes (a call split into chunks keeps only its last chunk's)
+    if (st == IBP_OK && (flags & IBP_F_KEEP_PREP) && (!lay.batched || n_box <= kTiledChunk))
+      prep_record(net, PrepTag{ws, n_box, box_lo, box_hi, (flags & IBP_F_PLAIN) != 0, net->tile_gen});
+    return st;
   });
 }
 
@@ -681,23 +727,34 @@ ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box, const float
     if (!g_box_lo || !g_box_hi) return fail(IBP_E_INVALID_ARG, "a required device pointer is NULL");
     if (up) g_f_lo = nullptr;
     if (low) g_f_hi = nullptr;
+    if (flags & IBP_F_KEEP_PREP) return fail(IBP_E_INVALID_ARG, "IBP_F_KEEP_PREP is a forward flag");
+    const PrepTag tag{ws, n_box, box_lo, box_hi, (flags & IBP_F_PLAIN) != 0, net->tile_gen};
+    const bool reuse = (flags & IBP_F_REUSE_PREP) != 0;
+    if (reuse && !prep_matches(net, tag))
+      return fail(IBP_E_INVALID_ARG,
+                  "IBP_F_REUSE_PREP: the workspace does not hold the forward intermediates of these boxes (an "
+                  "ibp_bound_boxes call with IBP_F_KEEP_PREP on the same boxes, flags, tiles and workspace)");
     DeviceGuard g(net->device);
     if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
     hipStream_t s = static_cast<hipStream_t>(stream);
     ibp::KernelTimer* tm = const_cast<ibp::KernelTimer*>(&net->timer);
     const int64_t X = net->dn.X;
-    return for_chunks(net, n_box, flags | IBP_F_BACKWARD, lay, ws_bytes,
-                      [&](int64_t b, int64_t nc, const ibp::WsLayout& lc) {
-                        const float *lo = box_lo + b * X, *hi = box_hi + b * X;
-                        hipError_t e = ibp::launch_forward_prep(net->dn, nc, lo, hi, ws, lc, s, tm);
-                        if (e == hipSuccess)
-                          e = ibp::launch_backward_sweeps(net->dn, nc, ws, lc, lo, hi, g_f_lo ? g_f_lo + b : nullptr,
-                                                          g_f_hi ? g_f_hi + b : nullptr, g_box_lo + b * X,
-                                                          g_box_hi + b * X, s, tm);
-                        if (e != hipSuccess)
-                          return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
-                        return IBP_OK;
-                      });
+    if (!reuse) prep_forget(net, ws);
+    st = for_chunks(net, n_box, flags | IBP_F_BACKWARD, lay, ws_bytes,
+                    [&](int64_t b, int64_t nc, const ibp::WsLayout& lc) {
+                      const float *lo = box_lo + b * X, *hi = box_hi + b * X;
+                      hipError_t e = reuse ? hipSuccess : ibp::launch_forward_prep(net->dn, nc, lo, hi, ws, lc, s, tm);
+                      if (e == hipSuccess)
+                        e = ibp::launch_backward_sweeps(net->dn, nc, ws, lc, lo, hi, g_f_lo ? g_f_lo + b : nullptr,
+                                                        g_f_hi ? g_f_hi + b : nullptr, g_box_lo + b * X,
+                                                        g_box_hi + b * X, s, tm);
+                      if (e != hipSuccess)
+                        return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+                      return IBP_OK;
+                    });
+    // the backward leaves the forward intermediates of its boxes in the workspace
+    if (st == IBP_OK && !reuse && (!lay.batched || n_box <= kTiledChunk)) prep_record(net, tag);
+    return st;
   });
 }
 
@@ -716,6 +773,7 @@ ibp_status ibp_crown_bound_boxes(const ibp_network* net, int64_t n_box, const fl
     if (st != IBP_OK || n_box == 0) return st;
     DeviceGuard g(net->device);
     if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
+    prep_forget(net, ws);
     hipStream_t s = static_cast<hipStream_t>(stream);
     ibp::KernelTimer* tm = const_cast<ibp::KernelTimer*>(&net->timer);
     const int64_t X = net->dn.X;
@@ -745,6 +803,7 @@ ibp_status ibp_crown_lower_boxes(const ibp_network* net, int64_t n_box, const fl
     if (n_box == 0) return IBP_OK;
     DeviceGuard g(net->device);
     if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
+    prep_forget(net, ws);
     hipStream_t s = static_cast<hipStream_t>(stream);
     ibp::KernelTimer* tm = const_cast<ibp::KernelTimer*>(&net->timer);
     const int64_t X = net->dn.X;
@@ -803,6 +862,7 @@ ibp_status ibp_set_tile(ibp_network* net, int32_t k2_nc, int32_t k3_kc) {
     t.k3_kc = k3_kc;
     if (!ibp::tune_valid(t)) return fail(IBP_E_INVALID_ARG, "unsupported tile parameters");
     net->tune = t;
+    ++net->tile_gen;
     return IBP_OK;
   });
 }
@@ -819,6 +879,7 @@ ibp_status ibp_autotune(ibp_network* net, int64_t n_box, const float* box_lo, co
       return fail(IBP_E_WORKSPACE, "autotune workspace needs " + std::to_string(big.total) + " bytes");
     DeviceGuard g(net->device);
     if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
+    prep_forget(net, ws);
     hipStream_t s = static_cast<hipStream_t>(stream);
     // events and scratch outputs for the timing runs
     TuneScratch sc;
@@ -856,6 +917,7 @@ ibp_status ibp_autotune(ibp_network* net, int64_t n_box, const float* box_lo, co
     }
     if (st != IBP_OK) return st;
     net->tune = best_t;
+    ++net->tile_gen;
     if (chosen) {
       chosen[0] = best_t.k2_nc;
       chosen[1] = best_t.k3_kc;
@@ -876,6 +938,7 @@ ibp_status ibp_set_tile_batched(ibp_network* net, int32_t k3_bt, int32_t k3_rows
     t.k2_by = k2_by;
     if (!ibp::tune_batched_valid(t)) return fail(IBP_E_INVALID_ARG, "unsupported box-tiled tile parameters");
     net->tune = t;
+    ++net->tile_gen;
     return IBP_OK;
   });
 }
@@ -904,6 +967,7 @@ ibp_status ibp_autotune_batched(ibp_network* net, int64_t n_box, const float* bo
       return fail(IBP_E_WORKSPACE, "autotune workspace needs " + std::to_string(big.total) + " bytes");
     DeviceGuard g(net->device);
     if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
+    prep_forget(net, ws);
     hipStream_t s = static_cast<hipStream_t>(stream);
     TuneScratch sc;
     if (!sc.init(0)) return fail(IBP_E_DEVICE, "autotune events");
@@ -960,6 +1024,7 @@ ibp_status ibp_autotune_batched(ibp_network* net, int64_t n_box, const float* bo
     }
     if (st != IBP_OK) return st;
     net->tune = best_t;
+    ++net->tile_gen;
     if (chosen) {
       chosen[0] = best_t.k3_bt;
       chosen[1] = best_t.k3_rows;

@@ -259,3 +259,102 @@ def test_c2000_gradient_against_central_differences_at_4096_boxes():
     assert sum(n_lin) >= 0.9 * 64 * len(n_lin), n_lin
     print(f"[c2000 central differences] kink-free coordinates {n_lin}; elements near a kink per box and side "
           f"{n_near}; largest error / bar {worst:.3f}", flush=True)
+
+
+@pytest.mark.parametrize("name,nb,flags", [("c500", 37, 0), ("c500", 1, 0), ("c500", 6, ibp.IBP_F_PLAIN),
+                                           ("tiny", 9, 0), ("tiny", 1, 0)])
+def test_backward_reuses_the_forward_intermediates(name, nb, flags):
+    """A forward with IBP_F_KEEP_PREP followed by a backward with
+    IBP_F_REUSE_PREP on the same boxes and workspace gives bitwise the
+    gradient of a standalone backward (both sides, and one-sided), runs none
+    of the preparation kernels, and leaves the record for a second reuse;
+    box-tiled, per-box, single-box and one-block paths."""
+    torch = _torch()
+    net, fac, n = setup(name)
+    blo, bhi = synth.sub_boxes(net, nb, seed=41)
+    lo, hi = torch.from_numpy(blo).cuda(), torch.from_numpy(bhi).cuda()
+    g1 = torch.linspace(-1.0, 0.5, nb, dtype=torch.float64, device="cuda")
+    g2 = torch.linspace(0.3, 1.2, nb, dtype=torch.float64, device="cuda")
+    ref_lo, ref_hi = ibp.ibp_bound_backward(n, lo, hi, g1, g2, flags=flags)
+    ref1_lo, ref1_hi = ibp.ibp_bound_backward(n, lo, hi, None, g2, flags=flags | ibp.IBP_F_UPPER_ONLY)
+    ws = ibp.Workspace(n)
+    assert n.workspace_bytes(nb, flags | ibp.IBP_F_KEEP_PREP) == n.workspace_bytes(nb, flags | ibp.IBP_F_BACKWARD)
+    f_lo, f_hi = ibp.ibp_bound_boxes(n, lo, hi, flags=flags | ibp.IBP_F_KEEP_PREP, ws=ws)
+    p_lo, p_hi = ibp.ibp_bound_boxes(n, lo, hi, flags=flags)
+    assert torch.equal(f_lo, p_lo) and torch.equal(f_hi, p_hi)
+    n.set_kernel_timing(True)
+    n.kernel_times()
+    d_lo, d_hi = ibp.ibp_bound_backward(n, lo, hi, g1, g2, flags=flags | ibp.IBP_F_REUSE_PREP, ws=ws)
+    kt = n.kernel_times()
+    n.set_kernel_timing(False)
+    assert not {"box_prep", "base_flows", "batched_base_flows", "line_epilogue"} & set(kt), kt
+    e1_lo, e1_hi = ibp.ibp_bound_backward(n, lo, hi, None, g2, flags=flags | ibp.IBP_F_UPPER_ONLY |
+                                          ibp.IBP_F_REUSE_PREP, ws=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(d_lo, ref_lo) and torch.equal(d_hi, ref_hi)
+    assert torch.equal(e1_lo, ref1_lo) and torch.equal(e1_hi, ref1_hi)
+
+
+def test_reuse_is_refused_when_the_workspace_holds_something_else():
+    torch = _torch()
+    net, fac, n = setup("c500")
+    blo, bhi = synth.sub_boxes(net, 8, seed=42)
+    lo, hi = torch.from_numpy(blo).cuda(), torch.from_numpy(bhi).cuda()
+    g = torch.ones(8, dtype=torch.float64, device="cuda")
+    up = ibp.IBP_F_UPPER_ONLY
+
+    def refused(ws, lo_=lo, hi_=hi, flags=0):
+        with pytest.raises(ibp.IBPError) as e:
+            ibp.ibp_bound_backward(n, lo_, hi_, None, g, flags=flags | up | ibp.IBP_F_REUSE_PREP, ws=ws)
+        assert e.value.name == "IBP_E_INVALID_ARG"
+
+    ws = ibp.Workspace(n)
+    refused(ws)                                              # nothing kept yet
+    ibp.ibp_bound_boxes(n, lo, hi, ws=ws)                    # a forward without the flag keeps nothing
+    refused(ws)
+    ibp.ibp_bound_boxes(n, lo, hi, flags=ibp.IBP_F_KEEP_PREP, ws=ws)
+    refused(ibp.Workspace(n))                                # another workspace
+    refused(ws, lo.clone(), hi.clone())                      # other box arrays
+    refused(ws, flags=ibp.IBP_F_PLAIN)                       # other kernels
+    ibp.ibp_crown_bound_boxes(n, lo, hi, ws=ws)              # another call on the workspace
+    refused(ws)
+    ibp.ibp_bound_boxes(n, lo, hi, flags=ibp.IBP_F_KEEP_PREP, ws=ws)
+    t = n.tiles()
+    n.set_tile_batched(t["k3_bt"], t["k3_rows"], t["k3_xcd"], t["k2_mfma"], t["k2_by"])   # a tile change
+    refused(ws)
+    ibp.ibp_bound_backward(n, lo, hi, None, g, flags=up, ws=ws)    # a backward leaves its own
+    a = ibp.ibp_bound_backward(n, lo, hi, None, g, flags=up | ibp.IBP_F_REUSE_PREP, ws=ws)
+    b = ibp.ibp_bound_backward(n, lo, hi, None, g, flags=up)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    for bad in ((ibp.ibp_bound_boxes, dict(flags=ibp.IBP_F_REUSE_PREP)),):
+        with pytest.raises(ibp.IBPError):
+            bad[0](n, lo, hi, ws=ws, **bad[1])
+    with pytest.raises(ibp.IBPError):
+        ibp.ibp_bound_backward(n, lo, hi, None, g, flags=up | ibp.IBP_F_KEEP_PREP, ws=ws)
+
+
+def test_autograd_reuses_the_forward_and_falls_back_when_it_cannot():
+    """IBPBound keeps the forward's intermediates for its backward: the
+    gradient equals a standalone backward's bit for bit (37 boxes, box-tiled);
+    a second backward of the same graph, and one after a tile change, recompute
+    them and give the same values."""
+    torch = _torch()
+    from paper_2511_15624_amd.autograd import ibp_bound
+    net, fac, n = setup("c500")
+    blo, bhi = synth.sub_boxes(net, 37, seed=43)
+    w = torch.linspace(0.2, 1.0, 37, dtype=torch.float64, device="cuda")
+    ref_lo, ref_hi = ibp.ibp_bound_backward(n, torch.from_numpy(blo).cuda(), torch.from_numpy(bhi).cuda(),
+                                            -0.5 * torch.ones_like(w), w)
+    ref_lo, ref_hi = ref_lo.float(), ref_hi.float()
+    for tile_change in (False, True):
+        lo = torch.from_numpy(blo).cuda().requires_grad_(True)
+        hi = torch.from_numpy(bhi).cuda().requires_grad_(True)
+        f_lo, f_hi = ibp_bound(n, lo, hi)
+        if tile_change:
+            t = n.tiles()
+            n.set_tile_batched(t["k3_bt"], t["k3_rows"], t["k3_xcd"], t["k2_mfma"], t["k2_by"])
+        loss = (w * f_hi - 0.5 * f_lo).sum()
+        loss.backward(retain_graph=True)
+        assert torch.equal(lo.grad, ref_lo) and torch.equal(hi.grad, ref_hi), tile_change
+        loss.backward()
+        assert torch.equal(lo.grad, 2 * ref_lo) and torch.equal(hi.grad, 2 * ref_hi), tile_change

