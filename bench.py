@@ -394,6 +394,18 @@ def extras(torch, ibp, synth, n4, net4):
     msbp = _time(torch, lambda: ibp.ibp_bound_backward(n3, t5l[:sub], t5h[:sub], None, g1[:sub], ws=wsb,
                                                         flags=ibp.IBP_F_PLAIN | ibp.IBP_F_UPPER_ONLY), 1)
     ev5 = 4096 * n3.n_ctg * n3.n_line
+    # the differentiation form as a training loop runs it: the upper bound, then
+    # its gradient on the same boxes, with and without reusing the forward's
+    # intermediates
+    up = ibp.IBP_F_UPPER_ONLY
+    wsf = ibp.Workspace(n3)
+
+    def fwd_bwd(keep):
+        ibp.ibp_bound_boxes(n3, t5l, t5h, ws=wsf, flags=up | (ibp.IBP_F_KEEP_PREP if keep else 0))
+        ibp.ibp_bound_backward(n3, t5l, t5h, None, g1, ws=wsf, flags=up | (ibp.IBP_F_REUSE_PREP if keep else 0))
+
+    ms_fb_keep = _time(torch, lambda: fwd_bwd(True), 3)
+    ms_fb = _time(torch, lambda: fwd_bwd(False), 3)
     n3.set_kernel_timing(True)
     n3.kernel_times()
     for _ in range(3):
@@ -409,6 +421,10 @@ def extras(torch, ibp, synth, n4, net4):
                        "ms_forward": msf, "plain_value": sub * n3.n_ctg * n3.n_line / (msbp * 1e-3),
                        "plain_sample": f"first {sub} boxes, per-box kernels",
                        "kernel_ms": {k: round(v, 3) for k, v in ktb.items()},
+                       "forward_then_backward": {
+                           "workload": "upper bound then its gradient on the same 4096 boxes (one-sided calls)",
+                           "ms_reusing_forward_intermediates": ms_fb_keep, "ms_recomputing": ms_fb,
+                           "value": ev5 / (ms_fb_keep * 1e-3), "unit": "evals/s (each element forward and back)"},
                        "roofline": {"bound": "alu", "kernel": "backward_outage_sweep",
                                     "achieved": ev5 * OPS_PER_BWD_EVAL / (k5_ms * 1e-3), "peak": VALU_PEAK,
                                     "peak_source": VALU_PEAK_SOURCE,
