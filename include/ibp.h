@@ -308,9 +308,10 @@ ibp_status ibp_crown_lower_boxes(const ibp_network* net, int64_t n_box,
  * 6 batched outage sweep, 7 backward outage sweep, 8 backward transposed PTDF,
  * 9 backward endpoints, 10 relaxation outage sweep, 11 relaxation line adjoint
  * and transposed PTDF, 12 relaxation inputs and finalize, 13 backward
- * per-line (base-case) terms.
+ * per-line (base-case) terms, 14 backward line screen (the gradient of f_hi
+ * alone in box-tiled calls, before its outage sweep).
  * Not thread-safe with concurrent compute calls on the same handle. */
-#define IBP_N_KERNEL_IDS 14
+#define IBP_N_KERNEL_IDS 15
 ibp_status ibp_set_kernel_timing(ibp_network* net, int enable);
 ibp_status ibp_kernel_times(ibp_network* net, int32_t n_ids, double* total_ms, int64_t* count);
 

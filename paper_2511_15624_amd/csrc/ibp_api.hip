@@ -256,6 +256,34 @@ ibp_status to_device(ibp_network* net, int device) {
       row[h.ctg_line[k]] = std::numeric_limits<float>::quiet_NaN();  // outaged line's own entry
     }
     if ((st = upload(net, lodf32.data(), (size_t)h.K * d.Lp, &d.lodf)) != IBP_OK) return st;
+    // line-major copy (the screened backward sweep keeps one line per wave and
+    // the outages on the lanes) and the largest |factor| of each line
+    std::vector<float>().swap(lodf32);
+    d.Kp = round_up(std::max(1, h.K), 64);
+    std::vector<float> lt((size_t)std::max(1, h.L) * d.Kp, 0.0f);
+    std::vector<float> amax(d.Lp, 0.0f);
+    const int n_lb = (h.L + 63) / 64;
+    ibp::parallel_for(n_lb, 1, [&](int64_t a, int64_t b) {
+      for (int64_t lb = a; lb < b; ++lb) {
+        // 64 lines at a time: each outage row is read as one contiguous run
+        const int l0 = (int)lb * 64, l1 = std::min(h.L, l0 + 64);
+        float am[64] = {};
+        for (int k = 0; k < h.K; ++k) {
+          const double* src = h.lodf.data() + (size_t)k * h.L;
+          const int c = h.ctg_line[k];
+          for (int l = l0; l < l1; ++l) {
+            const float v = (float)src[l];
+            lt[(size_t)l * d.Kp + k] = v;
+            if (l != c) am[l - l0] = std::max(am[l - l0], std::fabs(v));
+          }
+        }
+        for (int l = l0; l < l1; ++l)
+          amax[l] = am[l - l0] == 0.0f ? 0.0f : std::nextafter(am[l - l0], std::numeric_limits<float>::infinity());
+      }
+    });
+    for (int k = 0; k < h.K; ++k) lt[(size_t)h.ctg_line[k] * d.Kp + k] = std::numeric_limits<float>::quiet_NaN();
+    if ((st = upload(net, lt.data(), lt.size(), &d.lodfT)) != IBP_OK) return st;
+    if ((st = upload(net, amax.data(), amax.size(), &d.lam_max)) != IBP_OK) return st;
   }
   if ((st = upload(net, h.fmax_base.data(), h.L, &d.fmax_b)) != IBP_OK) return st;
   if ((st = upload(net, h.fmax_ctg.data(), h.L, &d.fmax_c)) != IBP_OK) return st;
@@ -360,6 +388,7 @@ ibp_status to_device(ibp_network* net, int device) {
     if (const char* p = std::strstr(e, "rows=")) t.k3_rows = std::atoi(p + 5);
     if (const char* p = std::strstr(e, "xcd=")) t.k3_xcd = std::atoi(p + 4);
     if (const char* p = std::strstr(e, "k2by=")) t.k2_by = std::atoi(p + 5);
+    if (const char* p = std::strstr(e, "k5s=")) t.k5_sparse = std::atoi(p + 4) != 0;
     if (ibp::tune_valid(t) && ibp::tune_batched_valid(t) && (t.chord_nb == 2 || t.chord_nb == 4)) net->tune = t;
   }
   return IBP_OK;
@@ -442,7 +471,17 @@ ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
     lay.grf = take(B * d.Lp * sizeof(float));
     lay.gci = take(B * d.Np * sizeof(double));
     lay.gri = take(B * d.Np * sizeof(double));
-    if (lay.batched && d.K > 0) lay.cb = take(B * d.K * 2 * sizeof(float));
+    if (lay.batched && d.K > 0) {
+      lay.cb = take(B * d.K * 2 * sizeof(float));
+      lay.k5s_tiles = (int)((B + ibp::kScreenBoxes - 1) / ibp::kScreenBoxes);
+      const size_t tiles = (size_t)lay.k5s_tiles;
+      lay.smask = take(tiles * (d.Lp / 64) * sizeof(uint64_t));
+      lay.srec = take(tiles * d.Lp * 2 * 4 * sizeof(float));
+      lay.lcnt = take(B * d.Lp * sizeof(uint64_t));
+      lay.k5w_bx = (d.Kp + 255) / 256;
+      lay.sw = take(tiles * d.Kp * sizeof(float));
+      lay.sz = take(tiles * lay.k5w_bx * sizeof(float));
+    }
     lay.total = off;
   }
   if (flags & (IBP_F_CROWN | IBP_F_CROWN_REF)) {
@@ -747,7 +786,7 @@ ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box, const float
                       if (e == hipSuccess)
                         e = ibp::launch_backward_sweeps(net->dn, nc, ws, lc, lo, hi, g_f_lo ? g_f_lo + b : nullptr,
                                                         g_f_hi ? g_f_hi + b : nullptr, g_box_lo + b * X,
-                                                        g_box_hi + b * X, s, tm);
+                                                        g_box_hi + b * X, net->tune.k5_sparse != 0, s, tm);
                       if (e != hipSuccess)
                         return fail(IBP_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
                       return IBP_OK;

@@ -429,11 +429,312 @@ __global__ __launch_bounds__(256) void k5b_outage_vjp(DevNet net, void* ws, WsLa
   }
 }
 
+// ---------------------------------------------------------------------------
+// Screened sweep of the gradient of f_hi (box-tiled calls without g_lo).
+//
+// Only elements whose lower penalty max(|C| - R - fmax, 0) is active carry a
+// gradient, and in sub-boxes they are few and sit on few lines (2000 buses,
+// 4096 sub-boxes: 5% of the elements, on 11% of a box's lines).  With
+// w_k = |c_c| - r_c for the outaged line of outage k, every element obeys
+//   |C| - R - fmax <= (|c_l| - (r_l + fmax)) + |Lam_lk| max(w_k, 0),
+// so a line none of whose outages can be active is skipped as a whole.  K5s
+// takes, per tile of kScreenBoxes boxes, the largest of these bounds over
+// the tile's boxes and the outages (one multiply and one max per factor and
+// tile), and marks the lines where it is above -margin; margin covers the
+// float32 rounding of this bound and of the sweep's own test, so no line with
+// an active element goes unmarked.  K5p then runs the sweep's exact test on
+// the marked lines only.
+
+constexpr int kScreenTiles = 16;    // tiles per screen block (share every factor load; 32 gave fewer blocks and took 1.30 instead of 0.72 ms)
+constexpr int kScreenChunk = 128;   // outages per LDS chunk of the screen
+constexpr int kSparseQ = 4;         // outages per lane of the screened sweep
+constexpr int kSparseMaxWords = 512; // candidate-mask words per tile held in LDS (networks up to 32768 lines)
+
+// Per tile and outage: W = max over the tile's boxes of max(|c_c| - r_c, 0)
+// (zero past the last outage); per tile and block of 256 outages the largest
+// |c_c| + r_c, for the screen's margin.
+__global__ __launch_bounds__(256) void k5w_tile_max(DevNet net, void* ws, WsLayout lay, int64_t n_box) {
+  constexpr int S = kScreenBoxes;
+  __shared__ unsigned zs[4];
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  const int64_t t = blockIdx.y;
+  const float2* cb = ws_ptr<float2>(ws, lay.cb);
+  float wv = 0.0f, z = 0.0f;
+  if (k < net.K) {
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      const int64_t b = t * S + i;
+      if (b < n_box) {
+        const float2 v = cb[b * net.K + k];
+        wv = fmaxf(wv, fabsf(v.x) - v.y);
+        z = fmaxf(z, fabsf(v.x) + v.y);
+      }
+    }
+  }
+  if (k < net.Kp) ws_ptr<float>(ws, lay.sw)[t * net.Kp + k] = wv;
+  // non-negative floats order like their bit patterns
+  const unsigned zb = wave_max_u32(__float_as_uint(z));
+  if ((threadIdx.x & 63) == 0) zs[threadIdx.x >> 6] = zb;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    ws_ptr<float>(ws, lay.sz)[t * lay.k5w_bx + blockIdx.x] =
+        __uint_as_float(max(max(zs[0], zs[1]), max(zs[2], zs[3])));
+}
+
+// The screen: one line per lane, kScreenTiles tiles per block (every factor
+// load serves them all), the tiles' W staged in LDS kScreenChunk outages at
+// a time; per factor and tile one multiply and one max.
+__global__ __launch_bounds__(256) void k5s_screen(DevNet net, void* ws, WsLayout lay, int64_t n_box) {
+  constexpr int S = kScreenBoxes, G = kScreenTiles;
+  static_assert(G % 4 == 0, "tiles are read from LDS as float4");
+  __shared__ __align__(16) float wsh[kScreenChunk][G];
+  __shared__ float zsh[G];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l = blockIdx.x * 256 + tid;
+  const bool lon = l < net.L;
+  const int lq = min(l, net.Lp - 1);
+  const int64_t tile0 = (int64_t)blockIdx.y * G;
+  const int ntile = (int)min<int64_t>(G, lay.k5s_tiles - tile0);
+  const float* W = ws_ptr<float>(ws, lay.sw) + tile0 * net.Kp;
+  if (tid < G) {
+    float z = 0.0f;
+    if (tid < ntile)
+      for (int j = 0; j < lay.k5w_bx; ++j) z = fmaxf(z, ws_ptr<float>(ws, lay.sz)[(tile0 + tid) * lay.k5w_bx + j]);
+    zsh[tid] = z;
+  }
+  float m[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) m[g] = 0.0f;
+  const float* lam = net.lodf + lq;
+  for (int k0 = 0; k0 < net.K; k0 += kScreenChunk) {
+    const int nk = min(kScreenChunk, net.K - k0);
+    __syncthreads();
+    for (int idx = tid; idx < kScreenChunk * G; idx += 256) {
+      const int kk = idx % kScreenChunk, g = idx / kScreenChunk;
+      wsh[kk][g] = (g < ntile && kk < nk) ? W[(size_t)g * net.Kp + k0 + kk] : 0.0f;
+    }
+    __syncthreads();
+    // |Lam| W: the outaged line's own factor is NaN, and fmaxf keeps m there;
+    // rows past the chunk's end read a valid row (the chunk's last) against W = 0
+    for (int kk = 0; kk < nk; kk += 4) {
+      float a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = fabsf(lam[(size_t)(k0 + min(kk + u, nk - 1)) * net.Lp]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int g4 = 0; g4 < G / 4; ++g4) {
+          const float4 wv = *reinterpret_cast<const float4*>(&wsh[kk + u][4 * g4]);
+          m[4 * g4 + 0] = fmaxf(m[4 * g4 + 0], a[u] * wv.x);
+          m[4 * g4 + 1] = fmaxf(m[4 * g4 + 1], a[u] * wv.y);
+          m[4 * g4 + 2] = fmaxf(m[4 * g4 + 2], a[u] * wv.z);
+          m[4 * g4 + 3] = fmaxf(m[4 * g4 + 3], a[u] * wv.w);
+        }
+      }
+    }
+  }
+  const float fc = lon ? net.fmax_c32[l] : 0.0f;
+  const float amax = lon ? net.lam_max[l] : 0.0f;
+  const float* lc = ws_ptr<float>(ws, lay.lc);
+  const double* lrf = ws_ptr<double>(ws, lay.lrf);
+  const int words = net.Lp / 64;
+  const int word = blockIdx.x * 4 + w;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    if (g >= ntile) break;  // uniform
+    const int64_t t = tile0 + g;
+    float cv[S], rv[S];
+    float base = -FLT_MAX, sc = 0.0f;
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      const int64_t b = t * S + i;
+      cv[i] = 0.0f;
+      rv[i] = INFINITY;  // a box past the end: never active
+      if (lon && b < n_box) {
+        cv[i] = lc[b * net.Lp + l];
+        rv[i] = (float)lrf[b * net.L + l] + fc;  // as the sweep forms r + fmax
+        base = fmaxf(base, fabsf(cv[i]) - rv[i]);
+        sc = fmaxf(sc, fabsf(cv[i]) + rv[i]);
+      }
+    }
+    // 32 unit roundoffs of the largest magnitude either test adds
+    const float margin = 0x1p-19f * (sc + amax * zsh[g]);
+    const bool flag = lon && base + m[g] > -margin;
+    const uint64_t bits = __builtin_amdgcn_ballot_w64(flag);
+    if (lane == 0 && word < words) ws_ptr<uint64_t>(ws, lay.smask)[t * words + word] = bits;
+    if (flag) {
+      float4* rec = ws_ptr<float4>(ws, lay.srec) + ((size_t)t * net.Lp + l) * 2;
+      rec[0] = make_float4(cv[0], cv[1], cv[2], cv[3]);
+      rec[1] = make_float4(rv[0], rv[1], rv[2], rv[3]);
+#pragma unroll
+      for (int i = 0; i < S; ++i)
+        if (t * S + i < n_box) ws_ptr<uint64_t>(ws, lay.lcnt)[(t * S + i) * net.Lp + l] = 0ull;
+    }
+  }
+  static_assert(S == 4, "a tile's line record holds four boxes");
+}
+
+// The screened sweep: a wave holds 64 Q outages (lanes) of one tile's boxes
+// and walks the tile's candidate lines one at a time, the line's data in
+// scalar registers and its factors one coalesced row segment (the next line's
+// loads issued before the current line's arithmetic).  Per element the test
+// (the dense sweep's, bit for bit) and the outage-side sums run on the vector
+// ALUs; the line side needs two counts per box (active elements, and those
+// among them with negative flow), which the test's lane masks give by scalar
+// popcounts, added to the line's counter by one atomic per box and line.
+template <int Q>
+__global__ __launch_bounds__(256) void k5p_sweep(DevNet net, void* ws, WsLayout lay, int64_t n_box,
+                                                 const double* __restrict__ g_hi, int n_chunk, int n_tg) {
+  constexpr int S = kScreenBoxes;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // Work unit u = (chunk of 64 Q outages, group of 4 tiles: one per wave).
+  // The blocks of one XCD (dispatch order: block id mod 8) take consecutive
+  // units in chunk-major order, so each XCD streams one or two chunks and
+  // their factor columns stay in its L2.
+  const int U = n_chunk * n_tg;
+  const int per = (U + 7) / 8;
+  const int slot = blockIdx.x >> 3;
+  const int u = (blockIdx.x & 7) * per + slot;
+  if (slot >= per || u >= U) return;  // the whole block
+  const int tile = (u % n_tg) * 4 + w;
+  const bool on = tile < lay.k5s_tiles;
+  const int kw = (u / n_tg) * 64 * Q;
+  // the tile's candidate-line masks, staged in LDS: reading them there keeps
+  // the walk free of vector-memory waits
+  __shared__ uint64_t smk_all[4][kSparseMaxWords];
+  uint64_t* smk = smk_all[w];
+  const int words = net.Lp / 64;
+  if (on) {
+    const uint64_t* mask = ws_ptr<uint64_t>(ws, lay.smask) + (size_t)tile * words;
+    for (int j = lane; j < words; j += 64) smk[j] = mask[j];
+  }
+  __syncthreads();
+  if (!on) return;
+  const int64_t b0 = (int64_t)tile * S;
+  const float2* __restrict__ cb = ws_ptr<float2>(ws, lay.cb);
+  float clo[S];
+  int64_t bb[S];
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    bb[i] = min(b0 + i, n_box - 1);
+    clo[i] = (float)(-net.zeta_f * g_hi[bb[i]]);
+  }
+  float cc[Q][S], rc[Q][S], pc[Q][S], pr[Q][S];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int k = kw + 64 * q + lane;
+    const int kq = min(k, net.K - 1);
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      const float2 v = cb[bb[i] * net.K + kq];
+      cc[q][i] = v.x;
+      rc[q][i] = k < net.K ? v.y : INFINITY;  // lanes past the last outage: never active
+      pc[q][i] = pr[q][i] = 0.0f;
+    }
+  }
+  const float4* __restrict__ rec = ws_ptr<float4>(ws, lay.srec) + (size_t)tile * net.Lp * 2;
+  unsigned long long* cnt = ws_ptr<unsigned long long>(ws, lay.lcnt);
+  // lanes past the last outage read its factor (their tests fail: rc = inf)
+  int koff[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) koff[q] = min(kw + 64 * q + lane, net.K - 1);
+  const float* __restrict__ lamT = net.lodfT;
+  // one candidate line: the exact test of the dense sweep on Q x S elements
+  // per lane, outage-side sums in registers, line-side counts by popcount
+  auto line_step = [&](int l, const float4& c4, const float4& r4, const float (&x)[Q]) {
+    const float cl[S] = {c4.x, c4.y, c4.z, c4.w};
+    const float rl[S] = {r4.x, r4.y, r4.z, r4.w};
+    unsigned na[S], nn[S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) na[i] = nn[i] = 0u;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+#pragma unroll
+      for (int i = 0; i < S; ++i) {
+        const float C = fmaf(x[q], cc[q][i], cl[i]);
+        const float T = fmaf(fabsf(x[q]), rc[q][i], rl[i]);
+        // |C| - T > 0 exactly when |C| > T (denormals are kept); the NaN of
+        // the outaged line's own factor fails it
+        const bool act = fabsf(C) > T;
+        const bool neg = C < 0.0f;
+        const float mm = act ? x[q] : 0.0f;
+        pc[q][i] += neg ? -mm : mm;
+        pr[q][i] += fabsf(mm);
+        const uint64_t ba = __builtin_amdgcn_ballot_w64(act);
+        na[i] += (unsigned)__builtin_popcountll(ba);
+        nn[i] += (unsigned)__builtin_popcountll(ba & __builtin_amdgcn_ballot_w64(neg));
+      }
+    }
+    // lane i adds box i's counts
+    int vlo = 0, vhi = 0;
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      vlo = lane == i ? (int)na[i] : vlo;
+      vhi = lane == i ? (int)nn[i] : vhi;
+    }
+    if (lane < S && b0 + lane < n_box && vlo != 0)
+      atomicAdd(cnt + (b0 + lane) * net.Lp + l, ((unsigned long long)(unsigned)vhi << 32) | (unsigned)vlo);
+  };
+  // Walk the candidate lines (wave-uniform); each line's loads are issued
+  // before the previous line's arithmetic.  Lane i holds mask word wb + i
+  // (read out by readlane, so that finding the next line waits on no memory
+  // access; reloaded from LDS every 64 words).
+  int j = 0, wb = 0;
+  uint64_t bits = 0;
+  uint64_t mw = lane < words ? smk[lane] : 0ull;
+  auto next = [&]() -> int {
+    while (bits == 0) {
+      if (j >= words) return -1;
+      if (j - wb >= 64) {
+        wb += 64;
+        mw = wb + lane < words ? smk[wb + lane] : 0ull;
+      }
+      const int i = j - wb;
+      bits = ((uint64_t)(unsigned)__builtin_amdgcn_readlane((int)(mw >> 32), i) << 32) |
+             (unsigned)__builtin_amdgcn_readlane((int)(unsigned)mw, i);
+      ++j;
+    }
+    const int l = (j - 1) * 64 + __builtin_ctzll(bits);
+    bits &= bits - 1;
+    return l;
+  };
+  int pl = -1;
+  float4 pc4 = make_float4(0.f, 0.f, 0.f, 0.f), pr4 = pc4;
+  float px[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) px[q] = 0.0f;
+  for (int l = next(); l >= 0; l = next()) {
+    const float4 c4 = rec[2 * l], r4 = rec[2 * l + 1];
+    float x[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) x[q] = lamT[(size_t)l * net.Kp + koff[q]];
+    if (pl >= 0) line_step(pl, pc4, pr4, px);
+    pl = l;
+    pc4 = c4;
+    pr4 = r4;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) px[q] = x[q];
+  }
+  if (pl >= 0) line_step(pl, pc4, pr4, px);
+  float2* cp = ws_ptr<float2>(ws, lay.cpart);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int k = kw + 64 * q + lane;
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+      if (k < net.K && b0 + i < n_box)
+        cp[(size_t)(b0 + i) * net.K + k] = make_float2(clo[i] * pc[q][i], -clo[i] * pr[q][i]);
+  }
+}
+
 // Per line: base-case penalty gradient + outage-sweep partials (as the line
 // itself and, if it is an outage line, as the outaged line).
+// With `sparse` the outage sweep was the screened one: counts on the tile's
+// candidate lines, per-outage sums as one [B][K] slot.
 __global__ __launch_bounds__(256) void k5r_lines(DevNet net, void* ws, WsLayout lay, int64_t box0,
                                                  const double* __restrict__ g_lo,
-                                                 const double* __restrict__ g_hi) {
+                                                 const double* __restrict__ g_hi, int sparse) {
   const int64_t b = box0 + blockIdx.y;
   const int l = blockIdx.x * 256 + threadIdx.x;
   if (l >= net.Lp) return;
@@ -452,6 +753,27 @@ __global__ __launch_bounds__(256) void k5r_lines(DevNet net, void* ws, WsLayout 
   const double lo = (a - r - fb > 0.0) ? -zf * gh : 0.0;
   const double s = c > 0.0 ? 1.0 : (c < 0.0 ? -1.0 : 0.0);
   double dc = s * (hi + lo), dr = hi - lo;
+  if (sparse) {
+    const int words = net.Lp / 64;
+    const uint64_t m = ws_ptr<uint64_t>(ws, lay.smask)[(b / kScreenBoxes) * words + l / 64];
+    if ((m >> (l & 63)) & 1ull) {
+      // every active element adds sign(C) clo to the centre and -clo to the radius
+      const unsigned long long c = ws_ptr<unsigned long long>(ws, lay.lcnt)[b * net.Lp + l];
+      const double na = (double)(unsigned)c, nn = (double)(unsigned)(c >> 32);
+      const double clo = -zf * gh;
+      dc += clo * (na - 2.0 * nn);
+      dr -= clo * na;
+    }
+    const int k = net.ctg_of_line[l];
+    if (k >= 0) {
+      const float2 q = ws_ptr<float2>(ws, lay.cpart)[(size_t)b * net.K + k];
+      dc += q.x;
+      dr += q.y;
+    }
+    gcf[l] = (float)dc;
+    grf[l] = (float)dr;
+    return;
+  }
   const float2* lp = ws_ptr<float2>(ws, lay.lpart) + (size_t)b * lay.k5_by * net.Lp + l;
   for (int y = 0; y < lay.k5_by; ++y) {
     const float2 t = lp[(size_t)y * net.Lp];
@@ -737,8 +1059,22 @@ void plan_backward(const DevNet& net, WsLayout& lay) {
 
 hipError_t launch_backward_sweeps(const DevNet& net, int64_t n_box, void* ws, const WsLayout& lay,
                                   const float* box_lo, const float* box_hi, const double* g_lo, const double* g_hi, double* d_lo, double* d_hi,
-                                  hipStream_t s, KernelTimer* tm) {
-  if (n_box >= kBatchMin && lay.batched && net.K > 0) {
+                                  bool sparse, hipStream_t s, KernelTimer* tm) {
+  sparse = sparse && !g_lo && g_hi && n_box >= kBatchMin && lay.batched && net.K > 0 && lay.k5s_tiles > 0 &&
+           net.Lp / 64 <= kSparseMaxWords;
+  if (sparse) {
+    int t = tm->start(14, s);
+    hipLaunchKernelGGL(k5w_tile_max, dim3(lay.k5w_bx, lay.k5s_tiles), dim3(256), 0, s, net, ws, lay, n_box);
+    hipLaunchKernelGGL(k5s_screen, dim3((net.Lp + 255) / 256, (lay.k5s_tiles + kScreenTiles - 1) / kScreenTiles),
+                       dim3(256), 0, s, net, ws, lay, n_box);
+    tm->stop(t, s);
+    t = tm->start(7, s);
+    const int n_chunk = (net.K + 64 * kSparseQ - 1) / (64 * kSparseQ), n_tg = (lay.k5s_tiles + 3) / 4;
+    const int per = (n_chunk * n_tg + 7) / 8;
+    hipLaunchKernelGGL(k5p_sweep<kSparseQ>, dim3(8 * per), dim3(256), 0, s, net, ws, lay, n_box, g_hi, n_chunk,
+                       n_tg);
+    tm->stop(t, s);
+  } else if (n_box >= kBatchMin && lay.batched && net.K > 0) {
     const int t = tm->start(7, s);
     const unsigned groups = (unsigned)(((n_box + kBT5 - 1) / kBT5 + 3) / 4);
     const dim3 grid(lay.k5_tiles, lay.k5_by, groups);
@@ -764,7 +1100,8 @@ hipError_t launch_backward_sweeps(const DevNet& net, int64_t n_box, void* ws, co
       tm->stop(t, s);
     }
     const int t = tm->start(13, s);
-    hipLaunchKernelGGL(k5r_lines, dim3((net.Lp + 255) / 256, nb), dim3(256), 0, s, net, ws, lay, b0, g_lo, g_hi);
+    hipLaunchKernelGGL(k5r_lines, dim3((net.Lp + 255) / 256, nb), dim3(256), 0, s, net, ws, lay, b0, g_lo, g_hi,
+                       (int)sparse);
     tm->stop(t, s);
   }
   if (n_box >= kBatchMin) {

@@ -38,8 +38,11 @@ enum P1Field : int {
 struct DevNet {
   int N, L, K, G, D, X;
   int Np, Lp;  // padded row strides of the PTDF (buses) and outage factors (lines)
+  int Kp;      // padded row stride of the line-major outage factors (outages)
   const float* phiT;        // [N x Lp] float32 PTDF transposed (row n = column n of Phi), zero padding
   const float* lodf;        // [K x Lp] float32 outage factors, NaN at (k, c(k)), zero padding
+  const float* lodfT;       // [L x Kp] the same factors line-major (row l: every outage's factor on line l)
+  const float* lam_max;     // [Lp] max over outages of |factor| on the line, rounded up (0 on padding lines)
   const double* fmax_b;     // [L]
   const double* fmax_c;     // [L]
   const double* phi_err;    // [L] absolute float64 PTDF error bound of the row
@@ -93,6 +96,15 @@ struct WsLayout {
   int k3_bt = 4;                   // batched outage sweep: boxes per wave
   int k5_by = 0, k5_tiles = 0;     // backward outage sweep: outage chunks, line tiles
   int k5_chunk = 0;                // outages per backward chunk
+  // screened backward sweep of the gradient of f_hi (box-tiled calls): the
+  // lines that may hold an active lower-penalty element, per tile of boxes
+  int k5s_tiles = 0;               // tiles of kScreenBoxes boxes (0: not laid out)
+  size_t smask = 0;                // uint64 [tiles][Lp / 64]: candidate-line bit masks
+  size_t srec = 0;                 // float4 [tiles][Lp][2]: (centres, r + fmax) of the tile's boxes
+  size_t lcnt = 0;                 // uint64 [B][Lp]: active-element counts (negative-flow count << 32 | count)
+  size_t sw = 0;                   // float [tiles][Kp]: per tile and outage, max over its boxes of max(|c_c| - r_c, 0)
+  size_t sz = 0;                   // float [tiles][k5w_bx]: per tile and 256 outages, max |c_c| + r_c
+  int k5w_bx = 0;                  // blocks of 256 outages (Kp / 256 rounded up)
   // linear-relaxation bound (present with the CROWN flag)
   size_t ccnt = 0;                 // int2 [B][Lp]: per-line (sum s, sum |s|) over outages
   size_t cv = 0;                   // double4 [B][kc_bx][K]: per-outage (sum s Lam, sum |s Lam|, count)

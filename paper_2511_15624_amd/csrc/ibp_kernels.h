@@ -57,7 +57,12 @@ struct Tune {
   int k3_rows = 0;  // outage rows of that sweep (0: the rule of batched_rows_rule)
   int k3_xcd = -1;  // its XCD-aware block order: 0 off, 1 on, -1 by cache size
   int k2_by = 0;    // bus chunks of the matrix-core base flows (0: by rule)
+  int k5_sparse = 1; // box-tiled gradient of f_hi: screened sweep over candidate lines (0: dense sweep)
 };
+
+// Boxes per tile of the screened backward sweep (the tile shares its
+// candidate lines and every factor load).
+constexpr int kScreenBoxes = 4;
 bool tune_valid(const Tune& t);
 bool tune_batched_valid(const Tune& t);
 int batched_rows_rule(const DevNet& net, int k3_bx, int64_t groups);
@@ -84,10 +89,11 @@ hipError_t launch_forward_prep(const DevNet& net, int64_t n_box, const float* lo
                                const WsLayout& lay, hipStream_t s, KernelTimer* tm);
 
 // Backward grid shapes, and the backward kernels after launch_forward_prep.
+// `sparse`: the gradient of f_hi alone (no g_lo) takes the screened sweep.
 void plan_backward(const DevNet& net, WsLayout& lay);
 hipError_t launch_backward_sweeps(const DevNet& net, int64_t n_box, void* ws, const WsLayout& lay,
                                   const float* box_lo, const float* box_hi, const double* g_lo,
-                                  const double* g_hi, double* d_lo, double* d_hi, hipStream_t s,
+                                  const double* g_hi, double* d_lo, double* d_hi, bool sparse, hipStream_t s,
                                   KernelTimer* tm);
 
 // Linear-relaxation upper bound after a forward pass (see ibp_crown.hip).

@@ -183,9 +183,11 @@ def test_autograd_function():
 
 
 def test_one_sided_backward_matches_zero_weights():
-    """IBP_F_UPPER_ONLY (LOWER_ONLY) gives the VJP with g_lo (g_hi) = 0, bit for
-    bit up to the sign of zeros, without reading that weight; box-tiled and
-    per-box paths."""
+    """IBP_F_UPPER_ONLY (LOWER_ONLY) gives the VJP with g_lo (g_hi) = 0 without
+    reading that weight: bit for bit up to the sign of zeros in the per-box
+    path and for LOWER_ONLY; the box-tiled UPPER_ONLY call takes the screened
+    sweep (same activity decisions, other float32 summation order: 2e-5 relative L2
+    per box)."""
     torch = _torch()
     net, fac, n = setup("c500")
     blo, bhi = synth.sub_boxes(net, 9, seed=31)
@@ -198,8 +200,13 @@ def test_one_sided_backward_matches_zero_weights():
         c_lo, c_hi = ibp.ibp_bound_backward(n, tlo, thi, g, z, flags=plain)
         d_lo, d_hi = ibp.ibp_bound_backward(n, tlo, thi, g, None, flags=plain | ibp.IBP_F_LOWER_ONLY)
         torch.cuda.synchronize()
-        for x, y in ((a_lo, b_lo), (a_hi, b_hi), (c_lo, d_lo), (c_hi, d_hi)):
+        for x, y in ((c_lo, d_lo), (c_hi, d_hi)) + (((a_lo, b_lo), (a_hi, b_hi)) if plain else ()):
             assert torch.equal(x, y), float((x - y).abs().max())
+        if not plain:
+            a = torch.cat([a_lo, a_hi], 1)
+            b = torch.cat([b_lo, b_hi], 1)
+            rel = ((a - b).norm(dim=1) / a.norm(dim=1).clamp_min(1e-30)).max().item()
+            assert rel <= 2e-5, rel
     with pytest.raises(ValueError):
         ibp.ibp_bound_backward(n, tlo, thi, None, g)
 
@@ -358,3 +365,60 @@ def test_autograd_reuses_the_forward_and_falls_back_when_it_cannot():
         assert torch.equal(lo.grad, ref_lo) and torch.equal(hi.grad, ref_hi), tile_change
         loss.backward()
         assert torch.equal(lo.grad, 2 * ref_lo) and torch.equal(hi.grad, 2 * ref_hi), tile_change
+
+
+def _sparse_and_dense(monkeypatch, net):
+    n = ibp.Network(net, device=0)
+    monkeypatch.setenv("IBP_TILE", "k5s=0")
+    nd = ibp.Network(net, device=0)
+    monkeypatch.delenv("IBP_TILE")
+    return n, nd
+
+
+@pytest.mark.parametrize("name,nb,seed", [("tiny", 5, 3), ("c500", 37, 5), ("c500", 4, 6), ("c2000", 70, 7)])
+def test_screened_sweep_matches_the_dense_sweep(monkeypatch, name, nb, seed):
+    """The gradient of f_hi alone (IBP_F_UPPER_ONLY, 4 or more boxes) runs the
+    outage sweep on the lines a screen marks per tile of four boxes; the dense
+    sweep (IBP_TILE=k5s=0) runs every line.  Both take every activity decision
+    with the same float32 operations, so the gradients differ only by
+    summation order (float32 sums: 2e-5 relative L2 per box; a line the screen missed would
+    drop whole elements, each worth zeta_f |g| on its line).  Box counts
+    ragged against the 4-box tiles; sampled boxes also match the oracle."""
+    torch = _torch()
+    net = synth.make_config(name)
+    n, nd = _sparse_and_dense(monkeypatch, net)
+    blo, bhi = synth.sub_boxes(net, nb, seed=seed)
+    tlo, thi = torch.from_numpy(blo).cuda(), torch.from_numpy(bhi).cuda()
+    g = torch.linspace(0.5, 1.5, nb, dtype=torch.float64, device="cuda")
+    s_lo, s_hi = ibp.ibp_bound_backward(n, tlo, thi, None, g, flags=ibp.IBP_F_UPPER_ONLY)
+    d_lo, d_hi = ibp.ibp_bound_backward(nd, tlo, thi, None, g, flags=ibp.IBP_F_UPPER_ONLY)
+    torch.cuda.synchronize()
+    s = torch.cat([s_lo, s_hi], 1).cpu().numpy()
+    d = torch.cat([d_lo, d_hi], 1).cpu().numpy()
+    for b in range(nb):
+        assert rel_l2(s[b], d[b]) <= 2e-5, (b, rel_l2(s[b], d[b]))
+    fac = oracle.factors(net)
+    gh = np.linspace(0.5, 1.5, nb)
+    for b in sorted({0, nb // 2, nb - 1}):
+        o_lo, o_hi, _ = oracle.grad(net, blo[b], bhi[b], 0.0, gh[b], fac)
+        assert rel_l2(s[b], np.concatenate([o_lo, o_hi])) <= 1e-4, b
+
+
+@pytest.mark.parametrize("limit", ["tiny", "huge"])
+def test_screened_sweep_when_every_or_no_line_is_a_candidate(monkeypatch, limit):
+    """Outage limits of 1e-6 make every element active (the screen marks every
+    line); limits of 1e30 leave none active (it marks none, and the outage
+    terms of the gradient are exactly zero).  Both agree with the dense sweep."""
+    torch = _torch()
+    net = dict(synth.make_config("c500"))
+    net["fmax_ctg"] = np.full(len(net["fmax_ctg"]), 1e-6 if limit == "tiny" else 1e30)
+    n, nd = _sparse_and_dense(monkeypatch, net)
+    blo, bhi = synth.sub_boxes(net, 13, seed=9)
+    tlo, thi = torch.from_numpy(blo).cuda(), torch.from_numpy(bhi).cuda()
+    g = torch.ones(13, dtype=torch.float64, device="cuda")
+    s = torch.cat(ibp.ibp_bound_backward(n, tlo, thi, None, g, flags=ibp.IBP_F_UPPER_ONLY), 1).cpu().numpy()
+    d = torch.cat(ibp.ibp_bound_backward(nd, tlo, thi, None, g, flags=ibp.IBP_F_UPPER_ONLY), 1).cpu().numpy()
+    for b in range(13):
+        assert rel_l2(s[b], d[b]) <= 2e-5, (b, rel_l2(s[b], d[b]))
+    if limit == "huge":
+        np.testing.assert_array_equal(s, d)
