@@ -270,11 +270,16 @@ VALU_PEAK_SOURCE = ("MI355X float32 vector peak 157.3 TFLOP/s with an FMA counte
                     "clock x 2.4 GHz; the box-tiled sweep's counters show 0.414 wave instructions per SIMD per "
                     "cycle, above what 16 lanes per clock allow (profiles/ibp_batched_counters_c2000.md)")
 OPS_PER_EVAL = 9.25  # VALU ops per box-outage-line evaluation in the outage sweep (from the ISA)
-# VALU ops per box-outage-line element of the one-sided backward sweep: the
-# post-outage centre and radius (2 fma), the activity test (subtract, compare,
-# select), the sign transfer of the centre weight (1 three-input bit op) and four
-# accumulations (line centre / radius gradients, outage centre / radius partials)
-OPS_PER_BWD_EVAL = 10.0
+# VALU ops per box-outage-line element of the screened backward sweep (the
+# gradient of f_hi alone), on the elements of the lines its screen marks: the
+# post-outage centre and radius (2 fma), the activity and sign tests (2
+# compares), the selected factor and its sign (2 selects) and the two
+# outage-side accumulations; the line side is counted from the compare masks on
+# the scalar unit.  The compiled step issues 163 vector instructions per 16
+# elements (the rest is loop and counter overhead).
+OPS_PER_BWD_EVAL = 8.0
+# VALU ops per factor and tile of the backward's line screen (multiply, max)
+OPS_PER_SCREEN_EVAL = 2.0
 
 
 def _time(torch, fn, reps):
@@ -412,12 +417,29 @@ def extras(torch, ibp, synth, n4, net4):
         ibp.ibp_bound_backward(n3, t5l, t5h, None, g1, ws=wsb, flags=ibp.IBP_F_UPPER_ONLY)
     ktb = {k: v[0] / 3 for k, v in n3.kernel_times().items()}
     n3.set_kernel_timing(False)
+    marked, pairs = ibp.ibp_backward_screen_lines(n3, 4096, wsb)
+    # the same call with every line swept (IBP_TILE=k5s=0 keeps the dense sweep)
+    os.environ["IBP_TILE"] = "k5s=0"
+    n3d = ibp.Network(net3, device=0)
+    os.environ.pop("IBP_TILE")
+    msbd = _time(torch, lambda: ibp.ibp_bound_backward(n3d, t5l, t5h, None, g1, ws=wsb,
+                                                        flags=ibp.IBP_F_UPPER_ONLY), 3)
+    n3d.close()
+    k5_ev = marked * n3.n_ctg * 4  # elements the screened sweep evaluates (4 boxes per tile)
+    k5s_ms = ktb.get("backward_line_screen", float("nan"))
+    k5s_ops = OPS_PER_SCREEN_EVAL * n3.n_ctg * n3.n_line * (pairs // n3.n_line)
     k5_ms = ktb.get("backward_outage_sweep", float("nan"))
     k6_ms = ktb.get("backward_ptdf_t", float("nan"))
     k6_fma = 2.0 * n3.n_bus * n3.n_line * 4096
     res["backward"] = {"workload": "2000 buses, 4096 sub-boxes: d(f_hi)/d(box endpoints), one-sided call",
                        "value": ev5 / (msb * 1e-3), "unit": "evals/s", "ms_backward": msb,
                        "ms_backward_two_sided_weights": msb2,
+                       "ms_backward_dense_sweep": msbd,
+                       "screen": {"marked_tile_lines": marked, "tile_lines": pairs,
+                                  "marked_fraction": marked / pairs,
+                                  "note": "per tile of 4 boxes, the lines on which some outage can make the lower "
+                                          "penalty active; only those are swept (value counts every element of "
+                                          "the map, as the dense sweep evaluates them)"},
                        "ms_forward": msf, "plain_value": sub * n3.n_ctg * n3.n_line / (msbp * 1e-3),
                        "plain_sample": f"first {sub} boxes, per-box kernels",
                        "kernel_ms": {k: round(v, 3) for k, v in ktb.items()},
@@ -426,10 +448,14 @@ def extras(torch, ibp, synth, n4, net4):
                            "ms_reusing_forward_intermediates": ms_fb_keep, "ms_recomputing": ms_fb,
                            "value": ev5 / (ms_fb_keep * 1e-3), "unit": "evals/s (each element forward and back)"},
                        "roofline": {"bound": "alu", "kernel": "backward_outage_sweep",
-                                    "achieved": ev5 * OPS_PER_BWD_EVAL / (k5_ms * 1e-3), "peak": VALU_PEAK,
+                                    "achieved": k5_ev * OPS_PER_BWD_EVAL / (k5_ms * 1e-3), "peak": VALU_PEAK,
                                     "peak_source": VALU_PEAK_SOURCE,
-                                    "unit": "ops/s", "frac": ev5 * OPS_PER_BWD_EVAL / (k5_ms * 1e-3) / VALU_PEAK,
-                                    "ops_per_eval": OPS_PER_BWD_EVAL},
+                                    "unit": "ops/s", "frac": k5_ev * OPS_PER_BWD_EVAL / (k5_ms * 1e-3) / VALU_PEAK,
+                                    "ops_per_eval": OPS_PER_BWD_EVAL, "evals": k5_ev},
+                       "roofline_screen": {"bound": "alu", "kernel": "backward_line_screen",
+                                           "achieved": k5s_ops / (k5s_ms * 1e-3), "peak": VALU_PEAK,
+                                           "unit": "ops/s", "frac": k5s_ops / (k5s_ms * 1e-3) / VALU_PEAK,
+                                           "ops": k5s_ops},
                        "roofline_ptdf_t": {"bound": "mfma", "kernel": "backward_ptdf_t",
                                            "achieved": 2.0 * k6_fma / (k6_ms * 1e-3), "peak": MFMA_F32_PEAK,
                                            "unit": "FLOP/s", "frac": 2.0 * k6_fma / (k6_ms * 1e-3) / MFMA_F32_PEAK,

@@ -236,6 +236,24 @@ ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box,
                               double* g_box_lo, double* g_box_hi,
                               void* ws, size_t ws_bytes, void* stream, uint32_t flags);
 
+/* ibp_backward_screen_lines -- what the screened outage sweep of the last
+ * backward call did (the gradient of f_hi alone, Appendix eq. (ibp_f) through
+ * the lower penalties of Sec. III-A eq. (slack-Sc)).  Calls of ibp_bound_backward
+ * with IBP_F_UPPER_ONLY on 4 or more boxes (not IBP_F_PLAIN) first mark, per
+ * tile of 4 boxes, the lines on which some outage can make the lower penalty
+ * active (a bound over the tile, with a rounding margin), then run the outage
+ * sweep on those lines only; the gradient is that of the dense sweep up to
+ * float32 summation order (IBP_TILE=k5s=0 at ibp_build_network keeps the
+ * dense sweep).  After such a call on workspace `ws` with n_box boxes (at most
+ * 16 x 65535; a call split into chunks is not covered), this returns the
+ * number of marked (tile, line) pairs (*n_marked) and of all pairs (*n_pairs =
+ * tiles x lines).  Reads the workspace on `stream` and waits for it.  After
+ * any other call on `ws` the numbers are meaningless.
+ * Errors: INVALID_ARG (NULL, or sizes with no screened sweep), WORKSPACE,
+ * HOST_ONLY, DEVICE. */
+ibp_status ibp_backward_screen_lines(const ibp_network* net, int64_t n_box, const void* ws, size_t ws_bytes,
+                                     void* stream, int64_t* n_marked, int64_t* n_pairs);
+
 /* ibp_crown_bound_boxes -- IBP bounds tightened by a linear relaxation of the
  * penalties (the CROWN family of convex relaxations the paper cites beside
  * IBP, Sec. I).  Every penalty max(|z| - t, 0) and the imbalance |z| is

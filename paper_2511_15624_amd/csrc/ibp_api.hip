@@ -259,7 +259,7 @@ ibp_status to_device(ibp_network* net, int device) {
     // line-major copy (the screened backward sweep keeps one line per wave and
     // the outages on the lanes) and the largest |factor| of each line
     std::vector<float>().swap(lodf32);
-    d.Kp = round_up(std::max(1, h.K), 64);
+    d.Kp = round_up(std::max(1, h.K), 256);  // whole 256-outage chunks of the screened sweep
     std::vector<float> lt((size_t)std::max(1, h.L) * d.Kp, 0.0f);
     std::vector<float> amax(d.Lp, 0.0f);
     const int n_lb = (h.L + 63) / 64;
@@ -794,6 +794,34 @@ ibp_status ibp_bound_backward(const ibp_network* net, int64_t n_box, const float
     // the backward leaves the forward intermediates of its boxes in the workspace
     if (st == IBP_OK && !reuse && (!lay.batched || n_box <= kTiledChunk)) prep_record(net, tag);
     return st;
+  });
+}
+
+ibp_status ibp_backward_screen_lines(const ibp_network* net, int64_t n_box, const void* ws, size_t ws_bytes,
+                                     void* stream, int64_t* n_marked, int64_t* n_pairs) {
+  return guarded([&]() -> ibp_status {
+    g_err[0] = 0;
+    if (!net || !ws || !n_marked || !n_pairs) return fail(IBP_E_INVALID_ARG, "NULL argument");
+    if (net->device < 0) return fail(IBP_E_HOST_ONLY, "the network was built without a device");
+    if (n_box < ibp::kBatchMin || n_box > kTiledChunk || net->dn.K == 0)
+      return fail(IBP_E_INVALID_ARG, "no screened sweep for this number of boxes or network");
+    const ibp::WsLayout lay = layout(net, n_box, IBP_F_BACKWARD);
+    if (!lay.batched || lay.k5s_tiles == 0) return fail(IBP_E_INVALID_ARG, "no screened sweep for these sizes");
+    if (ws_bytes < lay.total) return fail(IBP_E_WORKSPACE, "workspace smaller than the backward call's");
+    DeviceGuard g(net->device);
+    if (!g.ok) return fail(IBP_E_DEVICE, "hipSetDevice failed");
+    const size_t words = (size_t)net->dn.Lp / 64, n = (size_t)lay.k5s_tiles * words;
+    std::vector<uint64_t> m(n);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(m.data(), static_cast<const char*>(ws) + lay.smask, n * sizeof(uint64_t),
+                       hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(IBP_E_DEVICE, "copy of the screen's line masks failed");
+    int64_t c = 0;
+    for (uint64_t v : m) c += __builtin_popcountll(v);
+    *n_marked = c;
+    *n_pairs = (int64_t)lay.k5s_tiles * net->dn.L;
+    return IBP_OK;
   });
 }
 

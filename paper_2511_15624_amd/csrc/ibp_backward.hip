@@ -633,13 +633,15 @@ __global__ __launch_bounds__(256) void k5p_sweep(DevNet net, void* ws, WsLayout 
       pc[q][i] = pr[q][i] = 0.0f;
     }
   }
-  const float4* __restrict__ rec = ws_ptr<float4>(ws, lay.srec) + (size_t)tile * net.Lp * 2;
+  // line records through the constant address space: the kernel does not
+  // write them, so their wave-uniform loads become scalar loads into SGPRs
+  typedef __attribute__((address_space(4))) const float const_float;
+  const_float* rec = (const_float*)(ws_ptr<float4>(ws, lay.srec) + (size_t)tile * net.Lp * 2);
   unsigned long long* cnt = ws_ptr<unsigned long long>(ws, lay.lcnt);
-  // lanes past the last outage read its factor (their tests fail: rc = inf)
-  int koff[Q];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) koff[q] = min(kw + 64 * q + lane, net.K - 1);
-  const float* __restrict__ lamT = net.lodfT;
+  // rows are padded to whole chunks (zero factors past the last outage, whose
+  // tests fail: rc = inf)
+  static_assert(64 * Q <= 256, "a chunk must fit the 256-outage row padding");
+  const float* __restrict__ lamT = net.lodfT + kw + lane;
   // one candidate line: the exact test of the dense sweep on Q x S elements
   // per lane, outage-side sums in registers, line-side counts by popcount
   auto line_step = [&](int l, const float4& c4, const float4& r4, const float (&x)[Q]) {
@@ -705,10 +707,11 @@ __global__ __launch_bounds__(256) void k5p_sweep(DevNet net, void* ws, WsLayout 
 #pragma unroll
   for (int q = 0; q < Q; ++q) px[q] = 0.0f;
   for (int l = next(); l >= 0; l = next()) {
-    const float4 c4 = rec[2 * l], r4 = rec[2 * l + 1];
+    const_float* rp = rec + 8 * (size_t)l;
+    const float4 c4 = make_float4(rp[0], rp[1], rp[2], rp[3]), r4 = make_float4(rp[4], rp[5], rp[6], rp[7]);
     float x[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) x[q] = lamT[(size_t)l * net.Kp + koff[q]];
+    for (int q = 0; q < Q; ++q) x[q] = lamT[(size_t)l * net.Kp + 64 * q];
     if (pl >= 0) line_step(pl, pc4, pr4, px);
     pl = l;
     pc4 = c4;

@@ -38,7 +38,7 @@ enum P1Field : int {
 struct DevNet {
   int N, L, K, G, D, X;
   int Np, Lp;  // padded row strides of the PTDF (buses) and outage factors (lines)
-  int Kp;      // padded row stride of the line-major outage factors (outages)
+  int Kp;      // padded row stride of the line-major outage factors (outages, a multiple of 256; zero padding)
   const float* phiT;        // [N x Lp] float32 PTDF transposed (row n = column n of Phi), zero padding
   const float* lodf;        // [K x Lp] float32 outage factors, NaN at (k, c(k)), zero padding
   const float* lodfT;       // [L x Kp] the same factors line-major (row l: every outage's factor on line l)

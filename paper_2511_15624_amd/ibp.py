@@ -52,6 +52,7 @@ EXPORTED = [
     "ibp_workspace_bytes",
     "ibp_bound_boxes",
     "ibp_bound_boxes_noalloc",
+    "ibp_backward_screen_lines",
     "ibp_bound_backward",
     "ibp_crown_bound_boxes",
     "ibp_crown_lower_boxes",
@@ -167,6 +168,8 @@ def load_library(path: str = LIB_PATH):
     lib.ibp_bound_boxes_noalloc.restype = ctypes.c_int
     lib.ibp_bound_backward.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp, u32]
     lib.ibp_bound_backward.restype = ctypes.c_int
+    lib.ibp_backward_screen_lines.argtypes = [vp, i64, vp, sz, vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.ibp_backward_screen_lines.restype = ctypes.c_int
     lib.ibp_crown_bound_boxes.argtypes = [vp, i64, vp, vp, i32, vp, vp, vp, vp, vp, sz, vp, u32]
     lib.ibp_crown_bound_boxes.restype = ctypes.c_int
     lib.ibp_crown_lower_boxes.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp, u32]
@@ -440,6 +443,17 @@ def ibp_bound_backward(net: Network, lo, hi, g_lo, g_hi, flags: int = 0, ws: Wor
                                                  _dev_ptr(g_hi), _dev_ptr(d_lo), _dev_ptr(d_hi),
                                                  _dev_ptr(buf), buf.numel(), _stream_ptr(stream), flags))
     return d_lo, d_hi
+
+
+def ibp_backward_screen_lines(net: Network, n_box: int, ws: Workspace, stream=None):
+    """(marked, all) (tile, line) pairs of the screened sweep of the last
+    IBP_F_UPPER_ONLY backward call on ``ws`` with ``n_box`` boxes."""
+    marked, pairs = ctypes.c_int64(0), ctypes.c_int64(0)
+    with _on(stream):
+        _check(load_library().ibp_backward_screen_lines(net.handle, int(n_box), _dev_ptr(ws.buf), ws.buf.numel(),
+                                                        _stream_ptr(stream), ctypes.byref(marked),
+                                                        ctypes.byref(pairs)))
+    return marked.value, pairs.value
 
 
 def ibp_crown_bound_boxes(net: Network, lo, hi, crown: bool = False, flags: int = 0, ws: Workspace = None,

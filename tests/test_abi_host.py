@@ -130,6 +130,11 @@ def test_compute_calls_need_a_device_handle(lib):
     assert ibp.STATUS[st] == "IBP_E_HOST_ONLY"
     st = lib.ibp_bound_boxes_noalloc(None, 1, None, None, None, None, None, None, 0)
     assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"
+    a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+    st = lib.ibp_backward_screen_lines(h.handle, 8, None, 0, None, ctypes.byref(a), ctypes.byref(b))
+    assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"
+    st = lib.ibp_backward_screen_lines(h.handle, 8, ctypes.byref(a), 8, None, ctypes.byref(a), ctypes.byref(b))
+    assert ibp.STATUS[st] == "IBP_E_HOST_ONLY"
     lib.ibp_free_network(None)
     info = ibp.NetworkInfo()
     assert ibp.STATUS[lib.ibp_network_query(None, ctypes.byref(info))] == "IBP_E_INVALID_ARG"

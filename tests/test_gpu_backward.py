@@ -406,9 +406,11 @@ def test_screened_sweep_matches_the_dense_sweep(monkeypatch, name, nb, seed):
 
 @pytest.mark.parametrize("limit", ["tiny", "huge"])
 def test_screened_sweep_when_every_or_no_line_is_a_candidate(monkeypatch, limit):
-    """Outage limits of 1e-6 make every element active (the screen marks every
-    line); limits of 1e30 leave none active (it marks none, and the outage
-    terms of the gradient are exactly zero).  Both agree with the dense sweep."""
+    """Outage limits of 1e-6 make every element whose post-outage flow interval
+    excludes zero active (60% of them here, on 82-90% of each box's lines per
+    the oracle; the screen marks at least 80% of the tile-lines); limits of 1e30
+    leave none active (it marks none, and the outage terms of the gradient are
+    exactly zero).  Both agree with the dense sweep."""
     torch = _torch()
     net = dict(synth.make_config("c500"))
     net["fmax_ctg"] = np.full(len(net["fmax_ctg"]), 1e-6 if limit == "tiny" else 1e30)
@@ -420,5 +422,29 @@ def test_screened_sweep_when_every_or_no_line_is_a_candidate(monkeypatch, limit)
     d = torch.cat(ibp.ibp_bound_backward(nd, tlo, thi, None, g, flags=ibp.IBP_F_UPPER_ONLY), 1).cpu().numpy()
     for b in range(13):
         assert rel_l2(s[b], d[b]) <= 2e-5, (b, rel_l2(s[b], d[b]))
+    ws = ibp.Workspace(n)
+    ibp.ibp_bound_backward(n, tlo, thi, None, g, ws=ws, flags=ibp.IBP_F_UPPER_ONLY)
+    marked, pairs = ibp.ibp_backward_screen_lines(n, 13, ws)
+    assert pairs == 4 * n.n_line  # ceil(13 / 4) tiles
+    assert (marked >= 0.8 * pairs) if limit == "tiny" else marked == 0, (marked, pairs)
     if limit == "huge":
         np.testing.assert_array_equal(s, d)
+
+
+def test_screen_marks_a_minority_of_lines_at_the_differentiation_workload():
+    """2000 buses, 4096 sub-boxes: the screen marks the lines of each 4-box
+    tile that can hold an active lower penalty (about a fifth of them); the
+    count query refuses sizes with no screened sweep."""
+    torch = _torch()
+    net, fac, n = setup("c2000")
+    blo, bhi = synth.sub_boxes(net, 4096, seed=51)
+    tlo, thi = torch.from_numpy(blo).cuda(), torch.from_numpy(bhi).cuda()
+    ws = ibp.Workspace(n)
+    ibp.ibp_bound_backward(n, tlo, thi, None, torch.ones(4096, dtype=torch.float64, device="cuda"), ws=ws,
+                           flags=ibp.IBP_F_UPPER_ONLY)
+    marked, pairs = ibp.ibp_backward_screen_lines(n, 4096, ws)
+    assert pairs == 1024 * n.n_line
+    print(f"[screen] {marked} of {pairs} tile-lines marked ({marked / pairs:.3f})", flush=True)
+    assert 0.05 * pairs < marked < 0.4 * pairs
+    with pytest.raises(ibp.IBPError):
+        ibp.ibp_backward_screen_lines(n, 3, ws)

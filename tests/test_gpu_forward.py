@@ -202,8 +202,8 @@ def test_workspace_and_argument_errors():
     st = lib.ibp_bound_boxes(n.handle, 0, None, None, None, None, None, None, 0, None, 0)
     assert st == 0
     st = lib.ibp_bound_boxes(n.handle, 1, vp(tlo.data_ptr()), vp(thi.data_ptr()), vp(out.data_ptr()),
-                             vp(out.data_ptr() + 8), None, vp(ws.data_ptr()), need, None, 0x80)
-    assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"
+                             vp(out.data_ptr() + 8), None, vp(ws.data_ptr()), need, None, 1 << 30)
+    assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"  # an undefined flag bit
 
 
 def test_device_factors_match_oracle():
