@@ -147,8 +147,13 @@ void ibp_free_network(ibp_network* net);
  * output stays a valid bound: with IBP_F_UPPER_ONLY f_lo is -INFINITY (terms:
  * Fc_hi = +INFINITY); with IBP_F_LOWER_ONLY the outage penalties' lower bound
  * is taken as 0, so f_hi is larger than the two-sided call's (terms: Fc_lo = 0).
- * The requested bound is the two-sided call's, bit for bit.  At most one of
- * the two flags. */
+ * The requested bound is the two-sided call's: bit for bit on the per-box
+ * path (fewer than 4 boxes, or IBP_F_PLAIN); on the box-tiled path the sweep
+ * runs only on the lines that a screen (per tile of 4 boxes, a bound over all
+ * outages at once) finds able to hold an active penalty of that side, which
+ * changes the float32 summation order of the outage penalties (1e-6 relative
+ * at most; the bound is certified either way; IBP_TILE=k3s=0 at
+ * ibp_build_network keeps the dense sweep).  At most one of the two flags. */
 #define IBP_F_UPPER_ONLY 32u
 #define IBP_F_LOWER_ONLY 64u
 /* Forward then backward on the same boxes (the differentiation form: the
@@ -327,9 +332,10 @@ ibp_status ibp_crown_lower_boxes(const ibp_network* net, int64_t n_box,
  * 9 backward endpoints, 10 relaxation outage sweep, 11 relaxation line adjoint
  * and transposed PTDF, 12 relaxation inputs and finalize, 13 backward
  * per-line (base-case) terms, 14 backward line screen (the gradient of f_hi
- * alone in box-tiled calls, before its outage sweep).
+ * alone in box-tiled calls, before its outage sweep), 15 forward line screen
+ * (one-sided box-tiled calls, before their outage sweep, id 6).
  * Not thread-safe with concurrent compute calls on the same handle. */
-#define IBP_N_KERNEL_IDS 15
+#define IBP_N_KERNEL_IDS 16
 ibp_status ibp_set_kernel_timing(ibp_network* net, int enable);
 ibp_status ibp_kernel_times(ibp_network* net, int32_t n_ids, double* total_ms, int64_t* count);
 

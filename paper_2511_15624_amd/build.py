@@ -16,8 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libibp.so")
 
-HIP_SOURCES = ["ibp_api.hip", "ibp_forward.hip", "ibp_batched.hip", "ibp_backward.hip", "ibp_split.hip",
-               "ibp_crown.hip", "ibp_probe.hip"]
+HIP_SOURCES = ["ibp_api.hip", "ibp_forward.hip", "ibp_batched.hip", "ibp_backward.hip", "ibp_screen.hip",
+               "ibp_split.hip", "ibp_crown.hip", "ibp_probe.hip"]
 HOST_SOURCES = ["ibp_build.cpp"]
 
 ARCH = os.environ.get("IBP_OFFLOAD_ARCH", "gfx950")

@@ -389,6 +389,7 @@ ibp_status to_device(ibp_network* net, int device) {
     if (const char* p = std::strstr(e, "xcd=")) t.k3_xcd = std::atoi(p + 4);
     if (const char* p = std::strstr(e, "k2by=")) t.k2_by = std::atoi(p + 5);
     if (const char* p = std::strstr(e, "k5s=")) t.k5_sparse = std::atoi(p + 4) != 0;
+    if (const char* p = std::strstr(e, "k3s=")) t.k3_sparse = std::atoi(p + 4) != 0;
     if (ibp::tune_valid(t) && ibp::tune_batched_valid(t) && (t.chord_nb == 2 || t.chord_nb == 4)) net->tune = t;
   }
   return IBP_OK;
@@ -473,16 +474,34 @@ ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
     lay.gri = take(B * d.Np * sizeof(double));
     if (lay.batched && d.K > 0) {
       lay.cb = take(B * d.K * 2 * sizeof(float));
-      lay.k5s_tiles = (int)((B + ibp::kScreenBoxes - 1) / ibp::kScreenBoxes);
-      const size_t tiles = (size_t)lay.k5s_tiles;
-      lay.smask = take(tiles * (d.Lp / 64) * sizeof(uint64_t));
-      lay.srec = take(tiles * d.Lp * 2 * 4 * sizeof(float));
       lay.lcnt = take(B * d.Lp * sizeof(uint64_t));
-      lay.k5w_bx = (d.Kp + 255) / 256;
-      lay.sw = take(tiles * d.Kp * sizeof(float));
-      lay.sz = take(tiles * lay.k5w_bx * sizeof(float));
     }
     lay.total = off;
+  }
+  // the line screen of the one-sided sweeps (the backward's gradient of f_hi,
+  // the forward's one-sided bounds): masks, line records, tile maxima
+  const bool one_sided = (flags & (IBP_F_UPPER_ONLY | IBP_F_LOWER_ONLY)) != 0;
+  if (lay.batched && net->dn.K > 0 && (one_sided || (flags & (IBP_F_BACKWARD | IBP_F_KEEP_PREP)))) {
+    const ibp::DevNet& d = net->dn;
+    const size_t B = (size_t)std::max<int64_t>(1, n_box);
+    size_t off = lay.total;
+    auto take = [&](size_t bytes) {
+      const size_t o = off;
+      off = align256(off + bytes);
+      return o;
+    };
+    lay.k5s_tiles = (int)((B + ibp::kScreenBoxes - 1) / ibp::kScreenBoxes);
+    const size_t tiles = (size_t)lay.k5s_tiles;
+    lay.smask = take(tiles * (d.Lp / 64) * sizeof(uint64_t));
+    lay.srec = take(tiles * d.Lp * 2 * 4 * sizeof(float));
+    lay.k5w_bx = (d.Kp + 255) / 256;
+    lay.sw = take(tiles * d.Kp * sizeof(float));
+    lay.sz = take(tiles * lay.k5w_bx * sizeof(float));
+    lay.total = off;
+    // the screened forward sweep writes one outage-penalty partial per chunk
+    // of 64 kSparseQ outages into the finalize's slots
+    const int n_chunk = (d.K + 64 * ibp::kSparseQ - 1) / (64 * ibp::kSparseQ);
+    lay.fscreen = net->tune.k3_sparse && ibp::screen_fits(d, lay) && n_chunk <= lay.n_p3;
   }
   if (flags & (IBP_F_CROWN | IBP_F_CROWN_REF)) {
     const ibp::DevNet& d = net->dn;

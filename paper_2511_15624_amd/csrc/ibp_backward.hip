@@ -434,145 +434,9 @@ __global__ __launch_bounds__(256) void k5b_outage_vjp(DevNet net, void* ws, WsLa
 //
 // Only elements whose lower penalty max(|C| - R - fmax, 0) is active carry a
 // gradient, and in sub-boxes they are few and sit on few lines (2000 buses,
-// 4096 sub-boxes: 5% of the elements, on 11% of a box's lines).  With
-// w_k = |c_c| - r_c for the outaged line of outage k, every element obeys
-//   |C| - R - fmax <= (|c_l| - (r_l + fmax)) + |Lam_lk| max(w_k, 0),
-// so a line none of whose outages can be active is skipped as a whole.  K5s
-// takes, per tile of kScreenBoxes boxes, the largest of these bounds over
-// the tile's boxes and the outages (one multiply and one max per factor and
-// tile), and marks the lines where it is above -margin; margin covers the
-// float32 rounding of this bound and of the sweep's own test, so no line with
-// an active element goes unmarked.  K5p then runs the sweep's exact test on
-// the marked lines only.
-
-constexpr int kScreenTiles = 16;    // tiles per screen block (share every factor load; 32 gave fewer blocks and took 1.30 instead of 0.72 ms)
-constexpr int kScreenChunk = 128;   // outages per LDS chunk of the screen
-constexpr int kSparseQ = 4;         // outages per lane of the screened sweep
-constexpr int kSparseMaxWords = 512; // candidate-mask words per tile held in LDS (networks up to 32768 lines)
-
-// Per tile and outage: W = max over the tile's boxes of max(|c_c| - r_c, 0)
-// (zero past the last outage); per tile and block of 256 outages the largest
-// |c_c| + r_c, for the screen's margin.
-__global__ __launch_bounds__(256) void k5w_tile_max(DevNet net, void* ws, WsLayout lay, int64_t n_box) {
-  constexpr int S = kScreenBoxes;
-  __shared__ unsigned zs[4];
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  const int64_t t = blockIdx.y;
-  const float2* cb = ws_ptr<float2>(ws, lay.cb);
-  float wv = 0.0f, z = 0.0f;
-  if (k < net.K) {
-#pragma unroll
-    for (int i = 0; i < S; ++i) {
-      const int64_t b = t * S + i;
-      if (b < n_box) {
-        const float2 v = cb[b * net.K + k];
-        wv = fmaxf(wv, fabsf(v.x) - v.y);
-        z = fmaxf(z, fabsf(v.x) + v.y);
-      }
-    }
-  }
-  if (k < net.Kp) ws_ptr<float>(ws, lay.sw)[t * net.Kp + k] = wv;
-  // non-negative floats order like their bit patterns
-  const unsigned zb = wave_max_u32(__float_as_uint(z));
-  if ((threadIdx.x & 63) == 0) zs[threadIdx.x >> 6] = zb;
-  __syncthreads();
-  if (threadIdx.x == 0)
-    ws_ptr<float>(ws, lay.sz)[t * lay.k5w_bx + blockIdx.x] =
-        __uint_as_float(max(max(zs[0], zs[1]), max(zs[2], zs[3])));
-}
-
-// The screen: one line per lane, kScreenTiles tiles per block (every factor
-// load serves them all), the tiles' W staged in LDS kScreenChunk outages at
-// a time; per factor and tile one multiply and one max.
-__global__ __launch_bounds__(256) void k5s_screen(DevNet net, void* ws, WsLayout lay, int64_t n_box) {
-  constexpr int S = kScreenBoxes, G = kScreenTiles;
-  static_assert(G % 4 == 0, "tiles are read from LDS as float4");
-  __shared__ __align__(16) float wsh[kScreenChunk][G];
-  __shared__ float zsh[G];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int l = blockIdx.x * 256 + tid;
-  const bool lon = l < net.L;
-  const int lq = min(l, net.Lp - 1);
-  const int64_t tile0 = (int64_t)blockIdx.y * G;
-  const int ntile = (int)min<int64_t>(G, lay.k5s_tiles - tile0);
-  const float* W = ws_ptr<float>(ws, lay.sw) + tile0 * net.Kp;
-  if (tid < G) {
-    float z = 0.0f;
-    if (tid < ntile)
-      for (int j = 0; j < lay.k5w_bx; ++j) z = fmaxf(z, ws_ptr<float>(ws, lay.sz)[(tile0 + tid) * lay.k5w_bx + j]);
-    zsh[tid] = z;
-  }
-  float m[G];
-#pragma unroll
-  for (int g = 0; g < G; ++g) m[g] = 0.0f;
-  const float* lam = net.lodf + lq;
-  for (int k0 = 0; k0 < net.K; k0 += kScreenChunk) {
-    const int nk = min(kScreenChunk, net.K - k0);
-    __syncthreads();
-    for (int idx = tid; idx < kScreenChunk * G; idx += 256) {
-      const int kk = idx % kScreenChunk, g = idx / kScreenChunk;
-      wsh[kk][g] = (g < ntile && kk < nk) ? W[(size_t)g * net.Kp + k0 + kk] : 0.0f;
-    }
-    __syncthreads();
-    // |Lam| W: the outaged line's own factor is NaN, and fmaxf keeps m there;
-    // rows past the chunk's end read a valid row (the chunk's last) against W = 0
-    for (int kk = 0; kk < nk; kk += 4) {
-      float a[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] = fabsf(lam[(size_t)(k0 + min(kk + u, nk - 1)) * net.Lp]);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-#pragma unroll
-        for (int g4 = 0; g4 < G / 4; ++g4) {
-          const float4 wv = *reinterpret_cast<const float4*>(&wsh[kk + u][4 * g4]);
-          m[4 * g4 + 0] = fmaxf(m[4 * g4 + 0], a[u] * wv.x);
-          m[4 * g4 + 1] = fmaxf(m[4 * g4 + 1], a[u] * wv.y);
-          m[4 * g4 + 2] = fmaxf(m[4 * g4 + 2], a[u] * wv.z);
-          m[4 * g4 + 3] = fmaxf(m[4 * g4 + 3], a[u] * wv.w);
-        }
-      }
-    }
-  }
-  const float fc = lon ? net.fmax_c32[l] : 0.0f;
-  const float amax = lon ? net.lam_max[l] : 0.0f;
-  const float* lc = ws_ptr<float>(ws, lay.lc);
-  const double* lrf = ws_ptr<double>(ws, lay.lrf);
-  const int words = net.Lp / 64;
-  const int word = blockIdx.x * 4 + w;
-#pragma unroll
-  for (int g = 0; g < G; ++g) {
-    if (g >= ntile) break;  // uniform
-    const int64_t t = tile0 + g;
-    float cv[S], rv[S];
-    float base = -FLT_MAX, sc = 0.0f;
-#pragma unroll
-    for (int i = 0; i < S; ++i) {
-      const int64_t b = t * S + i;
-      cv[i] = 0.0f;
-      rv[i] = INFINITY;  // a box past the end: never active
-      if (lon && b < n_box) {
-        cv[i] = lc[b * net.Lp + l];
-        rv[i] = (float)lrf[b * net.L + l] + fc;  // as the sweep forms r + fmax
-        base = fmaxf(base, fabsf(cv[i]) - rv[i]);
-        sc = fmaxf(sc, fabsf(cv[i]) + rv[i]);
-      }
-    }
-    // 32 unit roundoffs of the largest magnitude either test adds
-    const float margin = 0x1p-19f * (sc + amax * zsh[g]);
-    const bool flag = lon && base + m[g] > -margin;
-    const uint64_t bits = __builtin_amdgcn_ballot_w64(flag);
-    if (lane == 0 && word < words) ws_ptr<uint64_t>(ws, lay.smask)[t * words + word] = bits;
-    if (flag) {
-      float4* rec = ws_ptr<float4>(ws, lay.srec) + ((size_t)t * net.Lp + l) * 2;
-      rec[0] = make_float4(cv[0], cv[1], cv[2], cv[3]);
-      rec[1] = make_float4(rv[0], rv[1], rv[2], rv[3]);
-#pragma unroll
-      for (int i = 0; i < S; ++i)
-        if (t * S + i < n_box) ws_ptr<uint64_t>(ws, lay.lcnt)[(t * S + i) * net.Lp + l] = 0ull;
-    }
-  }
-  static_assert(S == 4, "a tile's line record holds four boxes");
-}
+// 4096 sub-boxes: 5% of the elements, on 11% of a box's lines).  The line
+// screen of ibp_screen.hip marks, per tile of kScreenBoxes boxes, the lines
+// that can hold one; K5p runs the dense sweep's exact test on those only.
 
 // The screened sweep: a wave holds 64 Q outages (lanes) of one tile's boxes
 // and walks the tile's candidate lines one at a time, the line's data in
@@ -1063,13 +927,10 @@ void plan_backward(const DevNet& net, WsLayout& lay) {
 hipError_t launch_backward_sweeps(const DevNet& net, int64_t n_box, void* ws, const WsLayout& lay,
                                   const float* box_lo, const float* box_hi, const double* g_lo, const double* g_hi, double* d_lo, double* d_hi,
                                   bool sparse, hipStream_t s, KernelTimer* tm) {
-  sparse = sparse && !g_lo && g_hi && n_box >= kBatchMin && lay.batched && net.K > 0 && lay.k5s_tiles > 0 &&
-           net.Lp / 64 <= kSparseMaxWords;
+  sparse = sparse && !g_lo && g_hi && n_box >= kBatchMin && lay.batched && net.K > 0 && screen_fits(net, lay);
   if (sparse) {
     int t = tm->start(14, s);
-    hipLaunchKernelGGL(k5w_tile_max, dim3(lay.k5w_bx, lay.k5s_tiles), dim3(256), 0, s, net, ws, lay, n_box);
-    hipLaunchKernelGGL(k5s_screen, dim3((net.Lp + 255) / 256, (lay.k5s_tiles + kScreenTiles - 1) / kScreenTiles),
-                       dim3(256), 0, s, net, ws, lay, n_box);
+    launch_line_screen(net, n_box, ws, lay, kScreenBackwardLower, s);
     tm->stop(t, s);
     t = tm->start(7, s);
     const int n_chunk = (net.K + 64 * kSparseQ - 1) / (64 * kSparseQ), n_tg = (lay.k5s_tiles + 3) / 4;

@@ -99,6 +99,7 @@ struct WsLayout {
   // screened backward sweep of the gradient of f_hi (box-tiled calls): the
   // lines that may hold an active lower-penalty element, per tile of boxes
   int k5s_tiles = 0;               // tiles of kScreenBoxes boxes (0: not laid out)
+  int fscreen = 0;                 // one-sided box-tiled forward calls take the screened sweep
   size_t smask = 0;                // uint64 [tiles][Lp / 64]: candidate-line bit masks
   size_t srec = 0;                 // float4 [tiles][Lp][2]: (centres, r + fmax) of the tile's boxes
   size_t lcnt = 0;                 // uint64 [B][Lp]: active-element counts (negative-flow count << 32 | count)

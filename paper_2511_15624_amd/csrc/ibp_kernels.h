@@ -58,11 +58,32 @@ struct Tune {
   int k3_xcd = -1;  // its XCD-aware block order: 0 off, 1 on, -1 by cache size
   int k2_by = 0;    // bus chunks of the matrix-core base flows (0: by rule)
   int k5_sparse = 1; // box-tiled gradient of f_hi: screened sweep over candidate lines (0: dense sweep)
+  int k3_sparse = 1; // box-tiled one-sided forward: screened sweep over candidate lines (0: dense sweep)
 };
 
-// Boxes per tile of the screened backward sweep (the tile shares its
-// candidate lines and every factor load).
+// Line screen of the one-sided sweeps (see ibp_screen.hip): boxes per tile
+// (the tile shares its marked lines and every factor load), outages per lane
+// of the screened sweeps, and the mask words per tile they stage in LDS.
 constexpr int kScreenBoxes = 4;
+constexpr int kSparseQ = 4;
+constexpr int kSparseMaxWords = 512;  // networks up to 32768 lines
+// What a screen bounds: the lower penalties with the backward's unpadded
+// radii (gradient of f_hi), or the forward's padded lower / upper penalties
+// (one-sided bound f_hi / f_lo).
+enum ScreenMode : int { kScreenBackwardLower = 0, kScreenForwardLower = 1, kScreenForwardUpper = 2 };
+// The screen's regions are laid out and the network fits the sweeps' LDS masks.
+inline bool screen_fits(const DevNet& net, const WsLayout& lay) {
+  return lay.k5s_tiles > 0 && net.Lp / 64 <= kSparseMaxWords;
+}
+// Marks, per tile of kScreenBoxes boxes, the lines that can hold an active
+// penalty of the mode's kind (masks, line records; for the backward also
+// zeroed line counters).
+void launch_line_screen(const DevNet& net, int64_t n_box, void* ws, const WsLayout& lay, int mode, hipStream_t s);
+// The one-sided box-tiled forward sweep over the marked lines (sides 1: lower
+// penalties, 2: upper), after launch_line_screen with the matching mode;
+// writes the outage-penalty partials that the finalize reads.
+void launch_screened_forward_sweep(const DevNet& net, int64_t n_box, void* ws, const WsLayout& lay, int sides,
+                                   hipStream_t s);
 bool tune_valid(const Tune& t);
 bool tune_batched_valid(const Tune& t);
 int batched_rows_rule(const DevNet& net, int k3_bx, int64_t groups);

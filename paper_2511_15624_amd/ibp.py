@@ -74,7 +74,7 @@ EXPORTED = [
 KERNEL_IDS = ["box_prep", "base_flows", "outage_sweep", "finalize", "line_epilogue", "batched_base_flows",
               "batched_outage_sweep", "backward_outage_sweep", "backward_ptdf_t", "backward_endpoints",
               "crown_outage_sweep", "crown_ptdf_t", "crown_inputs", "backward_line_terms",
-              "backward_line_screen"]
+              "backward_line_screen", "forward_line_screen"]
 
 
 TILE_FIELDS = ("k2_nc", "k3_kc", "k3_bt", "k3_rows", "k3_xcd", "k2_mfma", "k2_by")

@@ -83,11 +83,15 @@ def test_single_box_calls_match_the_tiled_call():
 
 
 def test_lower_only_flag_gives_the_same_lower_bound():
+    """With IBP_F_LOWER_ONLY the chord bound is the same, bit for bit; the IBP
+    lower bound it is combined with comes from the screened one-sided sweep
+    (the same outage penalties in another float32 order: 1e-6 relative)."""
+    from tests.test_gpu_forward import one_sided_close
     net, fac, n = setup("c500")
     blo, bhi = synth.sub_boxes(net, 6, seed=5)
     a_lo, a_hi, a_c = gpu_lower(n, blo, bhi)
     b_lo, b_hi, b_c = gpu_lower(n, blo, bhi, flags=ibp.IBP_F_LOWER_ONLY)
-    assert np.array_equal(a_lo, b_lo) and np.array_equal(a_c, b_c)
+    assert one_sided_close(a_lo, b_lo) and np.array_equal(a_c, b_c)
     assert np.all(b_hi >= a_hi)
 
 
