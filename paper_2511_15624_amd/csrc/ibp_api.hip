@@ -501,7 +501,8 @@ ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
     // the screened forward sweep writes one outage-penalty partial per chunk
     // of 64 kSparseQ outages into the finalize's slots
     const int n_chunk = (d.K + 64 * ibp::kSparseQ - 1) / (64 * ibp::kSparseQ);
-    lay.fscreen = net->tune.k3_sparse && ibp::screen_fits(d, lay) && n_chunk <= lay.n_p3;
+    const bool side_ok = (flags & IBP_F_UPPER_ONLY) || ((flags & IBP_F_LOWER_ONLY) && (flags & IBP_F_SCREEN_UPPER));
+    lay.fscreen = side_ok && net->tune.k3_sparse && ibp::screen_fits(d, lay) && n_chunk <= lay.n_p3;
   }
   if (flags & (IBP_F_CROWN | IBP_F_CROWN_REF)) {
     const ibp::DevNet& d = net->dn;
@@ -568,8 +569,10 @@ ibp_status check_compute_args(const ibp_network* net, int64_t n_box, const void*
   if (net->device < 0) return fail(IBP_E_HOST_ONLY, "network was built host-only");
   if (n_box < 0) return fail(IBP_E_INVALID_ARG, "n_box < 0");
   if (flags & ~uint32_t(IBP_F_PLAIN | IBP_F_BACKWARD | IBP_F_CROWN | IBP_F_CROWN_REF | IBP_F_UPPER_ONLY |
-                        IBP_F_LOWER_ONLY | IBP_F_KEEP_PREP | IBP_F_REUSE_PREP))
+                        IBP_F_LOWER_ONLY | IBP_F_KEEP_PREP | IBP_F_REUSE_PREP | IBP_F_SCREEN_UPPER))
     return fail(IBP_E_INVALID_ARG, "unknown flag bits");
+  if ((flags & IBP_F_SCREEN_UPPER) && !(flags & IBP_F_LOWER_ONLY))
+    return fail(IBP_E_INVALID_ARG, "IBP_F_SCREEN_UPPER goes with IBP_F_LOWER_ONLY");
   if ((flags & IBP_F_UPPER_ONLY) && (flags & IBP_F_LOWER_ONLY))
     return fail(IBP_E_INVALID_ARG, "IBP_F_UPPER_ONLY and IBP_F_LOWER_ONLY exclude each other");
   if (n_box == 0) return IBP_OK;
@@ -736,8 +739,11 @@ ibp_status ibp_bound_boxes_noalloc(const ibp_network* net, int64_t n_box, const 
     g_err[0] = 0;
     if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
     if (net->device < 0) return fail(IBP_E_HOST_ONLY, "network was built host-only");
-    if (flags & ~uint32_t(IBP_F_PLAIN | IBP_F_UPPER_ONLY | IBP_F_LOWER_ONLY))
-      return fail(IBP_E_INVALID_ARG, "flags: only IBP_F_PLAIN, IBP_F_UPPER_ONLY and IBP_F_LOWER_ONLY are accepted");
+    if (flags & ~uint32_t(IBP_F_PLAIN | IBP_F_UPPER_ONLY | IBP_F_LOWER_ONLY | IBP_F_SCREEN_UPPER))
+      return fail(IBP_E_INVALID_ARG,
+                  "flags: only IBP_F_PLAIN, IBP_F_UPPER_ONLY, IBP_F_LOWER_ONLY and IBP_F_SCREEN_UPPER are accepted");
+    if ((flags & IBP_F_SCREEN_UPPER) && !(flags & IBP_F_LOWER_ONLY))
+      return fail(IBP_E_INVALID_ARG, "IBP_F_SCREEN_UPPER goes with IBP_F_LOWER_ONLY");
     if (n_box < 0) return fail(IBP_E_INVALID_ARG, "n_box < 0");
     if (n_box == 0) return IBP_OK;
     const size_t need = layout(net, n_box, flags).total;

@@ -17,9 +17,9 @@
 //
 // K5w takes per tile and outage the largest max(w_k, 0) over the tile's
 // boxes; K5s, per tile and line, the largest |Lam_lk| W_k over the outages
-// (one multiply and one max per factor and tile, 16 tiles per block sharing
-// each factor load) and marks the line where base + that > -margin.  margin
-// is 32 float32 unit roundoffs of the largest magnitude either test adds
+// (one multiply and one max per factor and tile, 16 or 4 tiles per block
+// sharing each factor load) and marks the line where base + that > -margin.
+// margin is 32 float32 unit roundoffs of the largest magnitude either test adds
 // (the screen's own bound and the sweep's test take 12 between them), so no
 // line with an active element goes unmarked.  The radii and limits are those
 // of the sweep the screen serves: the backward's unpadded ones, or the
@@ -39,8 +39,16 @@
 
 namespace ibp {
 
-constexpr int kScreenTiles = 16;   // tiles per screen block (32 gave too few blocks: 1.30 instead of 0.72 ms)
 constexpr int kScreenChunk = 128;  // outages per LDS chunk of the screen
+
+// Tiles per screen block: 16 share every factor load when that still gives
+// about two blocks per CU (4096 boxes at 2000 buses: 0.69 ms; 32 tiles gave
+// too few blocks, 1.30 ms), otherwise 4 (1024 boxes: 16 tiles left the chip
+// under-filled with 208 blocks).
+inline int screen_tiles(const DevNet& net, const WsLayout& lay) {
+  const int64_t line_blocks = (net.Lp + 255) / 256;
+  return ((int64_t)lay.k5s_tiles + 15) / 16 * line_blocks >= 512 ? 16 : 4;
+}
 
 // The per-outage (centre, radius) the sweep of `mode` uses: the backward's
 // (centre, unpadded radius) pairs, or the forward's (centre, padded r').
@@ -96,11 +104,11 @@ __global__ __launch_bounds__(256) void k5w_tile_max(DevNet net, void* ws, WsLayo
         __uint_as_float(max(max(zs[0], zs[1]), max(zs[2], zs[3])));
 }
 
-// K5s: one line per lane, kScreenTiles tiles per block, the tiles' W staged
+// K5s: one line per lane, G tiles per block, the tiles' W staged
 // in LDS kScreenChunk outages at a time.
-template <int MODE>
+template <int MODE, int G>
 __global__ __launch_bounds__(256) void k5s_screen(DevNet net, void* ws, WsLayout lay, int64_t n_box) {
-  constexpr int S = kScreenBoxes, G = kScreenTiles;
+  constexpr int S = kScreenBoxes;
   static_assert(S == 4, "a tile's line record holds four boxes");
   static_assert(G % 4 == 0, "tiles are read from LDS as float4");
   __shared__ __align__(16) float wsh[kScreenChunk][G];
@@ -191,22 +199,25 @@ __global__ __launch_bounds__(256) void k5s_screen(DevNet net, void* ws, WsLayout
   }
 }
 
+template <int MODE>
+static void launch_screen_mode(const DevNet& net, int64_t n_box, void* ws, const WsLayout& lay, hipStream_t s) {
+  hipLaunchKernelGGL(k5w_tile_max<MODE>, dim3(lay.k5w_bx, lay.k5s_tiles), dim3(256), 0, s, net, ws, lay, n_box);
+  const unsigned gx = (net.Lp + 255) / 256;
+  if (screen_tiles(net, lay) == 16)
+    hipLaunchKernelGGL((k5s_screen<MODE, 16>), dim3(gx, (lay.k5s_tiles + 15) / 16), dim3(256), 0, s, net, ws, lay,
+                       n_box);
+  else
+    hipLaunchKernelGGL((k5s_screen<MODE, 4>), dim3(gx, (lay.k5s_tiles + 3) / 4), dim3(256), 0, s, net, ws, lay,
+                       n_box);
+}
+
 void launch_line_screen(const DevNet& net, int64_t n_box, void* ws, const WsLayout& lay, int mode, hipStream_t s) {
-  const dim3 gw(lay.k5w_bx, lay.k5s_tiles), gs((net.Lp + 255) / 256, (lay.k5s_tiles + kScreenTiles - 1) / kScreenTiles);
-  switch (mode) {
-    case kScreenBackwardLower:
-      hipLaunchKernelGGL(k5w_tile_max<kScreenBackwardLower>, gw, dim3(256), 0, s, net, ws, lay, n_box);
-      hipLaunchKernelGGL(k5s_screen<kScreenBackwardLower>, gs, dim3(256), 0, s, net, ws, lay, n_box);
-      break;
-    case kScreenForwardLower:
-      hipLaunchKernelGGL(k5w_tile_max<kScreenForwardLower>, gw, dim3(256), 0, s, net, ws, lay, n_box);
-      hipLaunchKernelGGL(k5s_screen<kScreenForwardLower>, gs, dim3(256), 0, s, net, ws, lay, n_box);
-      break;
-    default:
-      hipLaunchKernelGGL(k5w_tile_max<kScreenForwardUpper>, gw, dim3(256), 0, s, net, ws, lay, n_box);
-      hipLaunchKernelGGL(k5s_screen<kScreenForwardUpper>, gs, dim3(256), 0, s, net, ws, lay, n_box);
-      break;
-  }
+  if (mode == kScreenBackwardLower)
+    launch_screen_mode<kScreenBackwardLower>(net, n_box, ws, lay, s);
+  else if (mode == kScreenForwardLower)
+    launch_screen_mode<kScreenForwardLower>(net, n_box, ws, lay, s);
+  else
+    launch_screen_mode<kScreenForwardUpper>(net, n_box, ws, lay, s);
 }
 
 // K3p: the one-sided forward sweep over the marked lines.  A wave holds 64 Q

@@ -97,7 +97,7 @@ class BranchAndBound:
         mid = 0.5 * lo + 0.5 * hi
         pts = torch.stack([mid, vt], 1) if self.relax else mid[:, None]
         p_lo, _ = _ibp.ibp_bound_boxes(net, pts.reshape(-1, X), pts.reshape(-1, X), ws=self.ws_c,
-                                       flags=_ibp.IBP_F_LOWER_ONLY)
+                                       flags=_ibp.IBP_F_LOWER_ONLY | _ibp.IBP_F_SCREEN_UPPER)
         p_lo = p_lo.view(R, -1)
         best = torch.nan_to_num(p_lo, nan=-float("inf")).argmax(1)
         self.root_lb = p_lo.gather(1, best[:, None])[:, 0].clone()
@@ -156,7 +156,7 @@ class BranchAndBound:
             pts = self.cen[:2 * n]
         flat = pts.view(-1, X)
         p_lo, _ = _ibp.ibp_bound_boxes(self.net, flat, flat, ws=self.ws_c, stream=stream,
-                                       flags=_ibp.IBP_F_LOWER_ONLY)
+                                       flags=_ibp.IBP_F_LOWER_ONLY | _ibp.IBP_F_SCREEN_UPPER)
         _ibp._check(lib.ibp_split_update(n, _p(roots), S, _p(self.n_leaf), _p(self.sel), _p(kid_fhi), self.P,
                                          _p(p_lo), _p(flat), X, _p(self.leaf_fhi), _p(self.root_ub),
                                          _p(self.root_lb), _p(self.root_x), s))

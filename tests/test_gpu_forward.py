@@ -204,6 +204,9 @@ def test_workspace_and_argument_errors():
     st = lib.ibp_bound_boxes(n.handle, 1, vp(tlo.data_ptr()), vp(thi.data_ptr()), vp(out.data_ptr()),
                              vp(out.data_ptr() + 8), None, vp(ws.data_ptr()), need, None, 1 << 30)
     assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"  # an undefined flag bit
+    st = lib.ibp_bound_boxes(n.handle, 1, vp(tlo.data_ptr()), vp(thi.data_ptr()), vp(out.data_ptr()),
+                             vp(out.data_ptr() + 8), None, vp(ws.data_ptr()), need, None, ibp.IBP_F_SCREEN_UPPER)
+    assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"  # only with IBP_F_LOWER_ONLY
 
 
 def test_device_factors_match_oracle():
@@ -330,9 +333,10 @@ def one_sided_close(a, b, rtol=1e-6):
 @pytest.mark.parametrize("n_box", [1, 37])
 def test_one_sided_calls(n_box):
     """IBP_F_UPPER_ONLY / IBP_F_LOWER_ONLY return the requested bound (bit for
-    bit on the per-box path; on the box-tiled path the screened sweep sums the
-    same outage penalties in another float32 order: 1e-6 relative) and a
-    trivially valid other side."""
+    bit on the per-box path and for IBP_F_LOWER_ONLY alone; on the box-tiled
+    path IBP_F_UPPER_ONLY, and IBP_F_LOWER_ONLY with IBP_F_SCREEN_UPPER, take
+    the screened sweep, which sums the same outage penalties in another
+    float32 order: 1e-6 relative) and a trivially valid other side."""
     torch = _torch()
     net, fac, n = setup("c500")
     blo, bhi = synth.sub_boxes(net, n_box, seed=404)
@@ -341,7 +345,9 @@ def test_one_sided_calls(n_box):
     l_lo, l_hi, tl = gpu_bounds(n, blo, bhi, terms=True, flags=ibp.IBP_F_LOWER_ONLY)
     same = np.array_equal if n_box < 4 else one_sided_close
     assert same(u_hi, f_hi) and np.all(u_lo == -np.inf) and np.all(tu[:, 7] == np.inf)
-    assert same(l_lo, f_lo) and np.all(tl[:, 6] == 0.0)
+    assert np.array_equal(l_lo, f_lo) and np.all(tl[:, 6] == 0.0)
+    s_lo, _ = gpu_bounds(n, blo, bhi, flags=ibp.IBP_F_LOWER_ONLY | ibp.IBP_F_SCREEN_UPPER)
+    assert same(s_lo, f_lo)
     assert np.all(l_hi >= f_hi)
     for b in (0, n_box - 1):
         r = orc(net, blo[b], bhi[b], fac)
@@ -397,8 +403,9 @@ def test_three_bus_box_tiled_and_relaxation_paths():
 @pytest.mark.parametrize("name,nb,seed", [("tiny", 5, 3), ("c500", 37, 5), ("c2000", 70, 7)])
 @pytest.mark.parametrize("side", ["upper", "lower"])
 def test_screened_one_sided_forward_matches_the_dense_sweep(monkeypatch, name, nb, seed, side):
-    """One-sided box-tiled calls sweep only the lines a screen marks per tile
-    of 4 boxes (IBP_TILE=k3s=0: every line).  Each element's penalty is the
+    """One-sided box-tiled calls (IBP_F_UPPER_ONLY; IBP_F_LOWER_ONLY with
+    IBP_F_SCREEN_UPPER) sweep only the lines a screen marks per tile of 4
+    boxes (IBP_TILE=k3s=0: every line).  Each element's penalty is the
     dense sweep's, bit for bit, so the bounds differ only by the float32
     summation order of the outage penalties (1e-6 relative; a missed line
     would drop whole penalties); both enclose the oracle.  Box counts ragged
@@ -412,7 +419,7 @@ def test_screened_one_sided_forward_matches_the_dense_sweep(monkeypatch, name, n
     monkeypatch.delenv("IBP_TILE")
     blo, bhi = synth.sub_boxes(net, nb, seed=seed)
     mid = (0.5 * (blo + bhi)).astype(np.float32)
-    flag = ibp.IBP_F_UPPER_ONLY if side == "upper" else ibp.IBP_F_LOWER_ONLY
+    flag = ibp.IBP_F_UPPER_ONLY if side == "upper" else ibp.IBP_F_LOWER_ONLY | ibp.IBP_F_SCREEN_UPPER
     for lo, hi in ((blo, bhi), (mid, mid)):
         s_lo, s_hi = gpu_bounds(n, lo, hi, flags=flag)
         d_lo, d_hi = gpu_bounds(nd, lo, hi, flags=flag)
@@ -434,7 +441,7 @@ def test_screened_one_sided_forward_with_extreme_limits(monkeypatch, limit):
     nd = ibp.Network(net, device=0)
     monkeypatch.delenv("IBP_TILE")
     blo, bhi = synth.sub_boxes(net, 13, seed=9)
-    for flag, pick in ((ibp.IBP_F_UPPER_ONLY, 1), (ibp.IBP_F_LOWER_ONLY, 0)):
+    for flag, pick in ((ibp.IBP_F_UPPER_ONLY, 1), (ibp.IBP_F_LOWER_ONLY | ibp.IBP_F_SCREEN_UPPER, 0)):
         s = gpu_bounds(n, blo, bhi, flags=flag)[pick]
         d = gpu_bounds(nd, blo, bhi, flags=flag)[pick]
         assert one_sided_close(s, d), (flag, float(np.max(np.abs(s - d) / np.maximum(np.abs(d), 1.0))))
