@@ -6,7 +6,9 @@ returns them in float64 and they are cast to the endpoints' dtype.  The
 forward keeps its intermediates (box preparation, base flows, line and outage
 constants) in a workspace held by the autograd graph, and the backward reuses
 them instead of recomputing them (IBP_F_KEEP_PREP / IBP_F_REUSE_PREP); the
-workspace has the backward's size and lives until the graph is freed.
+workspace has the backward's size and lives until the graph is freed.  When
+only one bound reaches the loss, the backward is the one-sided call (the
+gradient of f_hi alone takes the screened sweep).
 """
 from __future__ import annotations
 
@@ -24,6 +26,9 @@ class IBPBound(torch.autograd.Function):
         ws = _ibp.Workspace(net)
         f_lo, f_hi = _ibp.ibp_bound_boxes(net, lo_d, hi_d, flags=flags | _ibp.IBP_F_KEEP_PREP, ws=ws)
         ctx.save_for_backward(lo_d, hi_d)
+        # an output that does not reach the loss gets None, not zeros, so
+        # that the backward can take the one-sided call
+        ctx.set_materialize_grads(False)
         ctx.net = net
         ctx.flags = flags
         ctx.ws = ws
@@ -32,12 +37,14 @@ class IBPBound(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g_lo, g_hi):
         lo, hi = ctx.saved_tensors
-        n = lo.shape[0]
+        if g_lo is None and g_hi is None:
+            ctx.ws = None
+            return torch.zeros_like(lo), torch.zeros_like(hi), None, None
+        flags = ctx.flags & _ibp.IBP_F_PLAIN
         if g_lo is None:
-            g_lo = torch.zeros(n, dtype=torch.float64, device=lo.device)
-        if g_hi is None:
-            g_hi = torch.zeros(n, dtype=torch.float64, device=lo.device)
-        flags = ctx.flags & (_ibp.IBP_F_PLAIN | _ibp.IBP_F_UPPER_ONLY | _ibp.IBP_F_LOWER_ONLY)
+            flags |= _ibp.IBP_F_UPPER_ONLY  # the weight of f_lo is not read
+        elif g_hi is None:
+            flags |= _ibp.IBP_F_LOWER_ONLY
         try:
             d_lo, d_hi = _ibp.ibp_bound_backward(ctx.net, lo, hi, g_lo, g_hi, flags=flags | _ibp.IBP_F_REUSE_PREP,
                                                  ws=ctx.ws)

@@ -367,6 +367,35 @@ def test_autograd_reuses_the_forward_and_falls_back_when_it_cannot():
         assert torch.equal(lo.grad, 2 * ref_lo) and torch.equal(hi.grad, 2 * ref_hi), tile_change
 
 
+def test_autograd_takes_the_one_sided_backward_when_one_bound_reaches_the_loss():
+    """A loss on f_hi alone gives the one-sided backward (the screened sweep)
+    bit for bit, and a loss on f_lo alone the LOWER_ONLY call; both within
+    float32 summation order of the two-sided call with a zero weight."""
+    torch = _torch()
+    from paper_2511_15624_amd.autograd import ibp_bound
+    net, fac, n = setup("c500")
+    blo, bhi = synth.sub_boxes(net, 37, seed=47)
+    tlo, thi = torch.from_numpy(blo).cuda(), torch.from_numpy(bhi).cuda()
+    w = torch.linspace(0.2, 1.0, 37, dtype=torch.float64, device="cuda")
+    z = torch.zeros_like(w)
+    for side in ("hi", "lo"):
+        lo = tlo.clone().requires_grad_(True)
+        hi = thi.clone().requires_grad_(True)
+        f_lo, f_hi = ibp_bound(n, lo, hi)
+        ((w * f_hi) if side == "hi" else (w * f_lo)).sum().backward()
+        if side == "hi":
+            one = ibp.ibp_bound_backward(n, tlo, thi, None, w, flags=ibp.IBP_F_UPPER_ONLY)
+            two = ibp.ibp_bound_backward(n, tlo, thi, z, w)
+        else:
+            one = ibp.ibp_bound_backward(n, tlo, thi, w, None, flags=ibp.IBP_F_LOWER_ONLY)
+            two = ibp.ibp_bound_backward(n, tlo, thi, w, z)
+        assert torch.equal(lo.grad, one[0].float()) and torch.equal(hi.grad, one[1].float()), side
+        a = torch.cat([lo.grad.double(), hi.grad.double()], 1)
+        b = torch.cat([two[0], two[1]], 1)
+        rel = ((a - b).norm(dim=1) / b.norm(dim=1).clamp_min(1e-30)).max().item()
+        assert rel <= 2e-5, (side, rel)
+
+
 def _sparse_and_dense(monkeypatch, net):
     n = ibp.Network(net, device=0)
     monkeypatch.setenv("IBP_TILE", "k5s=0")
