@@ -477,3 +477,33 @@ def test_screen_marks_a_minority_of_lines_at_the_differentiation_workload():
     assert 0.05 * pairs < marked < 0.4 * pairs
     with pytest.raises(ibp.IBPError):
         ibp.ibp_backward_screen_lines(n, 3, ws)
+
+
+def test_screened_paths_with_invalid_boxes_in_a_tile(monkeypatch):
+    """A box with a NaN endpoint and an inverted box share 4-box tiles with
+    valid ones: the screened one-sided forward and backward give the valid
+    boxes the dense sweeps' results (summation order aside) and the invalid
+    ones NaN."""
+    torch = _torch()
+    net = synth.make_config("c500")
+    n = ibp.Network(net, device=0)
+    monkeypatch.setenv("IBP_TILE", "k3s=0,k5s=0")
+    nd = ibp.Network(net, device=0)
+    monkeypatch.delenv("IBP_TILE")
+    blo, bhi = synth.sub_boxes(net, 11, seed=21)
+    blo[1, 3] = np.nan
+    blo[6, 0], bhi[6, 0] = bhi[6, 0] + 1.0, blo[6, 0]
+    bad = np.zeros(11, bool)
+    bad[[1, 6]] = True
+    tlo, thi = torch.from_numpy(blo).cuda(), torch.from_numpy(bhi).cuda()
+    g = torch.linspace(0.5, 1.5, 11, dtype=torch.float64, device="cuda")
+    for flag, pick in ((ibp.IBP_F_UPPER_ONLY, 1), (ibp.IBP_F_LOWER_ONLY | ibp.IBP_F_SCREEN_UPPER, 0)):
+        s = ibp.ibp_bound_boxes(n, tlo, thi, flags=flag)[pick].cpu().numpy()
+        d = ibp.ibp_bound_boxes(nd, tlo, thi, flags=flag)[pick].cpu().numpy()
+        assert np.all(np.isnan(s[bad])) and np.all(np.isnan(d[bad]))
+        assert np.all(np.abs(s[~bad] - d[~bad]) <= 1e-6 * np.maximum(np.abs(d[~bad]), 1.0)), flag
+    s = torch.cat(ibp.ibp_bound_backward(n, tlo, thi, None, g, flags=ibp.IBP_F_UPPER_ONLY), 1).cpu().numpy()
+    d = torch.cat(ibp.ibp_bound_backward(nd, tlo, thi, None, g, flags=ibp.IBP_F_UPPER_ONLY), 1).cpu().numpy()
+    assert np.all(np.isnan(s[bad])) and np.all(np.isnan(d[bad]))
+    for b in np.flatnonzero(~bad):
+        assert rel_l2(s[b], d[b]) <= 2e-5, (b, rel_l2(s[b], d[b]))
