@@ -366,6 +366,20 @@ def extras(torch, ibp, synth, n4, net4):
                      "ops_per_eval": OPS_PER_EVAL},
     }
     res["batched"]["tuned"] = _tuned(torch, ibp, n3, tlo, thi, ws, ev, ms)
+    # the same call with the upper-penalty line screen (IBP_F_SCREEN_UPPER):
+    # both penalty sums over the lines that can hold an active penalty
+    scr = ibp.IBP_F_SCREEN_UPPER
+    ms_s = _time(torch, lambda: ibp.ibp_bound_boxes(n3, tlo, thi, ws=ws, flags=scr), 3)
+    n3.set_kernel_timing(True)
+    n3.kernel_times()
+    ibp.ibp_bound_boxes(n3, tlo, thi, ws=ws, flags=scr)
+    kts = n3.kernel_times()
+    n3.set_kernel_timing(False)
+    res["batched"]["screened"] = {"flags": "IBP_F_SCREEN_UPPER", "ms_per_call": ms_s, "value": ev / (ms_s * 1e-3),
+                                  "speedup_vs_default": ms / ms_s,
+                                  "kernel_ms": {k: round(v[0], 3) for k, v in kts.items()},
+                                  "note": "bounds equal the default call's within float32 summation order "
+                                          "(1e-6 relative), both certified"}
     # the base flows of the same call on the float64 matrix cores: 2 products
     # (centre, radius) x 2 flops x lines x buses x boxes
     bf_ms = kt.get("batched_base_flows", (float("nan"), 1))[0]

@@ -155,11 +155,16 @@ void ibp_free_network(ibp_network* net);
  * at most; the bound is certified either way; IBP_TILE=k3s=0 at
  * ibp_build_network keeps the dense sweep).  IBP_F_UPPER_ONLY calls always
  * take the screen (the lower penalties of f_hi are active on few lines:
- * 2000 buses, 8192 sub-boxes, 12.2 -> 7.8 ms); IBP_F_LOWER_ONLY calls take it
- * only with IBP_F_SCREEN_UPPER, which pays where few lines carry an active
- * upper penalty (the centre points of sub-boxes: 12.3 -> 9.3 ms at 8192
- * points) and costs more than it saves on wide sub-boxes (1024 of them:
- * 2.1 against 1.6 ms).  At most one of the two side flags. */
+ * 2000 buses, 8192 sub-boxes, 12.2 -> 7.8 ms).  Calls that bound f_lo (two-
+ * sided, or IBP_F_LOWER_ONLY) take it only with IBP_F_SCREEN_UPPER: the
+ * screen then bounds the upper penalties (a line with none active has no
+ * active lower penalty either) and the sweep sums both sides, or the upper
+ * side alone, over the marked lines.  That pays where few lines carry an
+ * active upper penalty (the centre points of sub-boxes: 12.3 -> 9.3 ms at
+ * 8192 points; 18 x 1024 period sub-boxes, two-sided: 37.1 -> 30.1 ms) and
+ * costs more than it saves on wide sub-boxes (1024 of them, lower bound
+ * alone: 2.1 against 1.6 ms).  At most one of the two side flags;
+ * IBP_F_SCREEN_UPPER not with IBP_F_UPPER_ONLY. */
 #define IBP_F_UPPER_ONLY 32u
 #define IBP_F_LOWER_ONLY 64u
 #define IBP_F_SCREEN_UPPER 512u
@@ -196,8 +201,8 @@ size_t ibp_workspace_bytes(const ibp_network* net, int64_t n_box, uint32_t flags
  *                    (1^T s_fb), Fc_lo, Fc_hi (s_agg), each already padded.
  *   ws, ws_bytes   : device workspace of at least ibp_workspace_bytes(net, n_box, flags).
  * flags: 0, IBP_F_PLAIN, IBP_F_UPPER_ONLY or IBP_F_LOWER_ONLY (or PLAIN with one
- * of the other two; IBP_F_LOWER_ONLY optionally with IBP_F_SCREEN_UPPER), each
- * optionally with IBP_F_KEEP_PREP.
+ * of the other two; 0 and IBP_F_LOWER_ONLY optionally with IBP_F_SCREEN_UPPER),
+ * each optionally with IBP_F_KEEP_PREP.
  * A box with a non-finite endpoint or lo > hi gets NaN outputs; other boxes are
  * unaffected.  Concurrent calls on one handle are safe with distinct workspaces.
  * Errors: INVALID_ARG, WORKSPACE, HOST_ONLY, DEVICE. */

@@ -481,7 +481,8 @@ ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
   // the line screen of the one-sided sweeps (the backward's gradient of f_hi,
   // the forward's one-sided bounds): masks, line records, tile maxima
   const bool one_sided = (flags & (IBP_F_UPPER_ONLY | IBP_F_LOWER_ONLY)) != 0;
-  if (lay.batched && net->dn.K > 0 && (one_sided || (flags & (IBP_F_BACKWARD | IBP_F_KEEP_PREP)))) {
+  if (lay.batched && net->dn.K > 0 &&
+      (one_sided || (flags & (IBP_F_BACKWARD | IBP_F_KEEP_PREP | IBP_F_SCREEN_UPPER)))) {
     const ibp::DevNet& d = net->dn;
     const size_t B = (size_t)std::max<int64_t>(1, n_box);
     size_t off = lay.total;
@@ -493,7 +494,7 @@ ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
     lay.k5s_tiles = (int)((B + ibp::kScreenBoxes - 1) / ibp::kScreenBoxes);
     const size_t tiles = (size_t)lay.k5s_tiles;
     lay.smask = take(tiles * (d.Lp / 64) * sizeof(uint64_t));
-    lay.srec = take(tiles * d.Lp * 2 * 4 * sizeof(float));
+    lay.srec = take(tiles * d.Lp * ibp::kScreenRecFloats * sizeof(float));
     lay.k5w_bx = (d.Kp + 255) / 256;
     lay.sw = take(tiles * d.Kp * sizeof(float));
     lay.sz = take(tiles * lay.k5w_bx * sizeof(float));
@@ -501,7 +502,7 @@ ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
     // the screened forward sweep writes one outage-penalty partial per chunk
     // of 64 kSparseQ outages into the finalize's slots
     const int n_chunk = (d.K + 64 * ibp::kSparseQ - 1) / (64 * ibp::kSparseQ);
-    const bool side_ok = (flags & IBP_F_UPPER_ONLY) || ((flags & IBP_F_LOWER_ONLY) && (flags & IBP_F_SCREEN_UPPER));
+    const bool side_ok = (flags & IBP_F_UPPER_ONLY) || (flags & IBP_F_SCREEN_UPPER);
     lay.fscreen = side_ok && net->tune.k3_sparse && ibp::screen_fits(d, lay) && n_chunk <= lay.n_p3;
   }
   if (flags & (IBP_F_CROWN | IBP_F_CROWN_REF)) {
@@ -571,8 +572,8 @@ ibp_status check_compute_args(const ibp_network* net, int64_t n_box, const void*
   if (flags & ~uint32_t(IBP_F_PLAIN | IBP_F_BACKWARD | IBP_F_CROWN | IBP_F_CROWN_REF | IBP_F_UPPER_ONLY |
                         IBP_F_LOWER_ONLY | IBP_F_KEEP_PREP | IBP_F_REUSE_PREP | IBP_F_SCREEN_UPPER))
     return fail(IBP_E_INVALID_ARG, "unknown flag bits");
-  if ((flags & IBP_F_SCREEN_UPPER) && !(flags & IBP_F_LOWER_ONLY))
-    return fail(IBP_E_INVALID_ARG, "IBP_F_SCREEN_UPPER goes with IBP_F_LOWER_ONLY");
+  if ((flags & IBP_F_SCREEN_UPPER) && (flags & IBP_F_UPPER_ONLY))
+    return fail(IBP_E_INVALID_ARG, "IBP_F_SCREEN_UPPER is for calls that bound f_lo");
   if ((flags & IBP_F_UPPER_ONLY) && (flags & IBP_F_LOWER_ONLY))
     return fail(IBP_E_INVALID_ARG, "IBP_F_UPPER_ONLY and IBP_F_LOWER_ONLY exclude each other");
   if (n_box == 0) return IBP_OK;
@@ -742,8 +743,8 @@ ibp_status ibp_bound_boxes_noalloc(const ibp_network* net, int64_t n_box, const 
     if (flags & ~uint32_t(IBP_F_PLAIN | IBP_F_UPPER_ONLY | IBP_F_LOWER_ONLY | IBP_F_SCREEN_UPPER))
       return fail(IBP_E_INVALID_ARG,
                   "flags: only IBP_F_PLAIN, IBP_F_UPPER_ONLY, IBP_F_LOWER_ONLY and IBP_F_SCREEN_UPPER are accepted");
-    if ((flags & IBP_F_SCREEN_UPPER) && !(flags & IBP_F_LOWER_ONLY))
-      return fail(IBP_E_INVALID_ARG, "IBP_F_SCREEN_UPPER goes with IBP_F_LOWER_ONLY");
+    if ((flags & IBP_F_SCREEN_UPPER) && (flags & IBP_F_UPPER_ONLY))
+      return fail(IBP_E_INVALID_ARG, "IBP_F_SCREEN_UPPER is for calls that bound f_lo");
     if (n_box < 0) return fail(IBP_E_INVALID_ARG, "n_box < 0");
     if (n_box == 0) return IBP_OK;
     const size_t need = layout(net, n_box, flags).total;

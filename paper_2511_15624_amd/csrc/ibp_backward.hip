@@ -500,7 +500,7 @@ __global__ __launch_bounds__(256) void k5p_sweep(DevNet net, void* ws, WsLayout 
   // line records through the constant address space: the kernel does not
   // write them, so their wave-uniform loads become scalar loads into SGPRs
   typedef __attribute__((address_space(4))) const float const_float;
-  const_float* rec = (const_float*)(ws_ptr<float4>(ws, lay.srec) + (size_t)tile * net.Lp * 2);
+  const_float* rec = (const_float*)(ws_ptr<float>(ws, lay.srec) + (size_t)tile * net.Lp * kScreenRecFloats);
   unsigned long long* cnt = ws_ptr<unsigned long long>(ws, lay.lcnt);
   // rows are padded to whole chunks (zero factors past the last outage, whose
   // tests fail: rc = inf)
@@ -571,7 +571,7 @@ __global__ __launch_bounds__(256) void k5p_sweep(DevNet net, void* ws, WsLayout 
 #pragma unroll
   for (int q = 0; q < Q; ++q) px[q] = 0.0f;
   for (int l = next(); l >= 0; l = next()) {
-    const_float* rp = rec + 8 * (size_t)l;
+    const_float* rp = rec + kScreenRecFloats * (size_t)l;
     const float4 c4 = make_float4(rp[0], rp[1], rp[2], rp[3]), r4 = make_float4(rp[4], rp[5], rp[6], rp[7]);
     float x[Q];
 #pragma unroll

@@ -372,10 +372,12 @@ hipError_t launch_batched_sweeps(const DevNet& net, int64_t n_box, void* ws, con
     else
       hipLaunchKernelGGL(k2b_base_flows, dim3(lay.k2_gx, groups), dim3(256), 0, s, net, ws, lay, n_box, inj);
     tm->stop(t, s);
-  } else if (net.K > 0 && lay.fscreen && lay.sides != 3) {
-    // one-sided: the line screen, then the sweep over the marked lines only
+  } else if (net.K > 0 && lay.fscreen) {
+    // the line screen, then the sweep over the marked lines only
     int t = tm->start(15, s);
-    launch_line_screen(net, n_box, ws, lay, lay.sides == 1 ? kScreenForwardLower : kScreenForwardUpper, s);
+    launch_line_screen(net, n_box, ws, lay,
+                       lay.sides == 1 ? kScreenForwardLower : lay.sides == 2 ? kScreenForwardUpper : kScreenForwardBoth,
+                       s);
     tm->stop(t, s);
     t = tm->start(6, s);
     launch_screened_forward_sweep(net, n_box, ws, lay, lay.sides, s);

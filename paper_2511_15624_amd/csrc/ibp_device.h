@@ -101,7 +101,7 @@ struct WsLayout {
   int k5s_tiles = 0;               // tiles of kScreenBoxes boxes (0: not laid out)
   int fscreen = 0;                 // one-sided box-tiled forward calls take the screened sweep
   size_t smask = 0;                // uint64 [tiles][Lp / 64]: candidate-line bit masks
-  size_t srec = 0;                 // float4 [tiles][Lp][2]: (centres, r + fmax) of the tile's boxes
+  size_t srec = 0;                 // float [tiles][Lp][12]: the tile's boxes' centres and radius terms
   size_t lcnt = 0;                 // uint64 [B][Lp]: active-element counts (negative-flow count << 32 | count)
   size_t sw = 0;                   // float [tiles][Kp]: per tile and outage, max over its boxes of max(|c_c| - r_c, 0)
   size_t sz = 0;                   // float [tiles][k5w_bx]: per tile and 256 outages, max |c_c| + r_c

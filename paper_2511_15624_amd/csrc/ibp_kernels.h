@@ -70,7 +70,17 @@ constexpr int kSparseMaxWords = 512;  // networks up to 32768 lines
 // What a screen bounds: the lower penalties with the backward's unpadded
 // radii (gradient of f_hi), or the forward's padded lower / upper penalties
 // (one-sided bound f_hi / f_lo).
-enum ScreenMode : int { kScreenBackwardLower = 0, kScreenForwardLower = 1, kScreenForwardUpper = 2 };
+// kScreenForwardBoth: the upper-penalty screen of a two-sided forward (a line
+// with no active upper penalty has no active lower one either), recording
+// both sides' terms.
+enum ScreenMode : int {
+  kScreenBackwardLower = 0,
+  kScreenForwardLower = 1,
+  kScreenForwardUpper = 2,
+  kScreenForwardBoth = 3
+};
+// Floats per (tile, line) record: the four boxes' centres and two radius terms.
+constexpr int kScreenRecFloats = 12;
 // The screen's regions are laid out and the network fits the sweeps' LDS masks.
 inline bool screen_fits(const DevNet& net, const WsLayout& lay) {
   return lay.k5s_tiles > 0 && net.Lp / 64 <= kSparseMaxWords;
@@ -79,9 +89,9 @@ inline bool screen_fits(const DevNet& net, const WsLayout& lay) {
 // penalty of the mode's kind (masks, line records; for the backward also
 // zeroed line counters).
 void launch_line_screen(const DevNet& net, int64_t n_box, void* ws, const WsLayout& lay, int mode, hipStream_t s);
-// The one-sided box-tiled forward sweep over the marked lines (sides 1: lower
-// penalties, 2: upper), after launch_line_screen with the matching mode;
-// writes the outage-penalty partials that the finalize reads.
+// The box-tiled forward sweep over the marked lines (sides 1: lower
+// penalties, 2: upper, 3: both), after launch_line_screen with the matching
+// mode; writes the outage-penalty partials that the finalize reads.
 void launch_screened_forward_sweep(const DevNet& net, int64_t n_box, void* ws, const WsLayout& lay, int sides,
                                    hipStream_t s);
 bool tune_valid(const Tune& t);

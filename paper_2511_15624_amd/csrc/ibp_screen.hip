@@ -74,6 +74,14 @@ __device__ __forceinline__ float line_term(const DevNet& net, void* ws, const Ws
   return add_ru(v, ex);
 }
 
+// The forward sweep's padded g of box b and line l (the lower penalties' term
+// of a two-sided sweep), formed as K3b forms it.
+__device__ __forceinline__ float line_g(const DevNet& net, void* ws, const WsLayout& lay, int64_t b, int l) {
+  const double* bs = ws_ptr<double>(ws, lay.box) + b * kBoxSlots;
+  const float vmax = __uint_as_float(*reinterpret_cast<const unsigned int*>(bs + kVmax));
+  return add_ru(ws_ptr<float>(ws, lay.lg)[b * net.Lp + l], next_up_f32(net.line_eps[l] * vmax));
+}
+
 // K5w: per tile and outage W (zero past the last outage); per tile and block
 // of 256 outages the largest |c_c| + r_c, for the margin.
 template <int MODE>
@@ -89,7 +97,7 @@ __global__ __launch_bounds__(256) void k5w_tile_max(DevNet net, void* ws, WsLayo
       const int64_t b = t * S + i;
       if (b < n_box) {
         const float2 v = outage_cr<MODE>(net, ws, lay, b, k);
-        wv = fmaxf(wv, MODE == kScreenForwardUpper ? fabsf(v.x) + v.y : fabsf(v.x) - v.y);
+        wv = fmaxf(wv, MODE >= kScreenForwardUpper ? fabsf(v.x) + v.y : fabsf(v.x) - v.y);
         z = fmaxf(z, fabsf(v.x) + v.y);
       }
     }
@@ -163,22 +171,23 @@ __global__ __launch_bounds__(256) void k5s_screen(DevNet net, void* ws, WsLayout
   const int words = net.Lp / 64;
   const int word = blockIdx.x * 4 + w;
   // a box past the end gets a record that never tests active
-  constexpr float kOff = MODE == kScreenForwardUpper ? -INFINITY : INFINITY;
+  constexpr float kOff = MODE >= kScreenForwardUpper ? -INFINITY : INFINITY;
 #pragma unroll
   for (int g = 0; g < G; ++g) {
     if (g >= ntile) break;  // uniform
     const int64_t t = tile0 + g;
-    float cv[S], rv[S];
+    float cv[S], rv[S], gv[S];
     float base = -FLT_MAX, sc = 0.0f;
 #pragma unroll
     for (int i = 0; i < S; ++i) {
       const int64_t b = t * S + i;
       cv[i] = 0.0f;
       rv[i] = kOff;
+      gv[i] = INFINITY;
       if (lon && b < n_box) {
         cv[i] = lc[b * net.Lp + l];
         rv[i] = line_term<MODE>(net, ws, lay, b, l, fc);
-        base = fmaxf(base, MODE == kScreenForwardUpper ? fabsf(cv[i]) + rv[i] : fabsf(cv[i]) - rv[i]);
+        base = fmaxf(base, MODE >= kScreenForwardUpper ? fabsf(cv[i]) + rv[i] : fabsf(cv[i]) - rv[i]);
         sc = fmaxf(sc, fabsf(cv[i]) + fabsf(rv[i]));
       }
     }
@@ -187,9 +196,15 @@ __global__ __launch_bounds__(256) void k5s_screen(DevNet net, void* ws, WsLayout
     const uint64_t bits = __builtin_amdgcn_ballot_w64(flag);
     if (lane == 0 && word < words) ws_ptr<uint64_t>(ws, lay.smask)[t * words + word] = bits;
     if (flag) {
-      float4* rec = ws_ptr<float4>(ws, lay.srec) + ((size_t)t * net.Lp + l) * 2;
+      float4* rec = reinterpret_cast<float4*>(ws_ptr<float>(ws, lay.srec) + ((size_t)t * net.Lp + l) * kScreenRecFloats);
       rec[0] = make_float4(cv[0], cv[1], cv[2], cv[3]);
       rec[1] = make_float4(rv[0], rv[1], rv[2], rv[3]);
+      if (MODE == kScreenForwardBoth) {
+#pragma unroll
+        for (int i = 0; i < S; ++i)
+          if (lon && t * S + i < n_box) gv[i] = line_g(net, ws, lay, t * S + i, l);
+        rec[2] = make_float4(gv[0], gv[1], gv[2], gv[3]);
+      }
       if (MODE == kScreenBackwardLower) {
 #pragma unroll
         for (int i = 0; i < S; ++i)
@@ -216,8 +231,10 @@ void launch_line_screen(const DevNet& net, int64_t n_box, void* ws, const WsLayo
     launch_screen_mode<kScreenBackwardLower>(net, n_box, ws, lay, s);
   else if (mode == kScreenForwardLower)
     launch_screen_mode<kScreenForwardLower>(net, n_box, ws, lay, s);
-  else
+  else if (mode == kScreenForwardUpper)
     launch_screen_mode<kScreenForwardUpper>(net, n_box, ws, lay, s);
+  else
+    launch_screen_mode<kScreenForwardBoth>(net, n_box, ws, lay, s);
 }
 
 // K3p: the one-sided forward sweep over the marked lines.  A wave holds 64 Q
@@ -272,27 +289,32 @@ __global__ __launch_bounds__(256) void k3p_sweep(DevNet net, void* ws, WsLayout 
       rk[q][i] = k < net.K ? __int_as_float(d.z) : INFINITY;
     }
   }
-  double acc[S];
+  double acc[S], acc2[S];  // SIDES 3: acc the upper penalties, acc2 the lower
 #pragma unroll
-  for (int i = 0; i < S; ++i) acc[i] = 0.0;
+  for (int i = 0; i < S; ++i) acc[i] = acc2[i] = 0.0;
   typedef __attribute__((address_space(4))) const float const_float;
-  const_float* rec = (const_float*)(ws_ptr<float4>(ws, lay.srec) + (size_t)tile * net.Lp * 2);
+  const_float* rec = (const_float*)(ws_ptr<float>(ws, lay.srec) + (size_t)tile * net.Lp * kScreenRecFloats);
   static_assert(64 * Q <= 256, "a chunk must fit the 256-outage row padding");
   const float* __restrict__ lamT = net.lodfT + kw + lane;
-  auto line_step = [&](const float4& c4, const float4& r4, const float (&x)[Q]) {
+  // records: SIDES 1 (centres, g), SIDES 2 (centres, h), SIDES 3 (centres,
+  // h, g)
+  auto line_step = [&](const float4& c4, const float4& r4, const float4& g4, const float (&x)[Q]) {
     const float cl[S] = {c4.x, c4.y, c4.z, c4.w};
     const float rl[S] = {r4.x, r4.y, r4.z, r4.w};
+    const float gl[S] = {g4.x, g4.y, g4.z, g4.w};
 #pragma unroll
     for (int i = 0; i < S; ++i) {
-      float p[Q];
+      float p[Q], p2[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         float a, b;
-        k3_elem<SIDES>(x[q], cc[q][i], rk[q][i], cl[i], rl[i], rl[i], a, b);
+        k3_elem<SIDES>(x[q], cc[q][i], rk[q][i], cl[i], rl[i], SIDES == 3 ? gl[i] : rl[i], a, b);
         p[q] = SIDES == 1 ? b : a;
+        p2[q] = b;
       }
       static_assert(Q == 4, "the float32 sum is written for four outages");
       acc[i] += (double)((p[0] + p[1]) + (p[2] + p[3]));
+      if (SIDES == 3) acc2[i] += (double)((p2[0] + p2[1]) + (p2[2] + p2[3]));
     }
   };
   // marked-line walk (wave-uniform): lane i holds mask word wb + i, read out
@@ -317,30 +339,33 @@ __global__ __launch_bounds__(256) void k3p_sweep(DevNet net, void* ws, WsLayout 
     return l;
   };
   bool pending = false;
-  float4 pc4 = make_float4(0.f, 0.f, 0.f, 0.f), pr4 = pc4;
+  float4 pc4 = make_float4(0.f, 0.f, 0.f, 0.f), pr4 = pc4, pg4 = pc4;
   float px[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) px[q] = 0.0f;
   for (int l = next(); l >= 0; l = next()) {
-    const_float* rp = rec + 8 * (size_t)l;
+    const_float* rp = rec + kScreenRecFloats * (size_t)l;
     const float4 c4 = make_float4(rp[0], rp[1], rp[2], rp[3]), r4 = make_float4(rp[4], rp[5], rp[6], rp[7]);
+    const float4 g4 = SIDES == 3 ? make_float4(rp[8], rp[9], rp[10], rp[11]) : r4;
     float x[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) x[q] = lamT[(size_t)l * net.Kp + 64 * q];
-    if (pending) line_step(pc4, pr4, px);
+    if (pending) line_step(pc4, pr4, pg4, px);
     pending = true;
     pc4 = c4;
     pr4 = r4;
+    pg4 = g4;
 #pragma unroll
     for (int q = 0; q < Q; ++q) px[q] = x[q];
   }
-  if (pending) line_step(pc4, pr4, px);
+  if (pending) line_step(pc4, pr4, pg4, px);
   double2* p3 = ws_ptr<double2>(ws, lay.p3);
 #pragma unroll
   for (int i = 0; i < S; ++i) {
     const double t = wave_sum(acc[i]);
+    const double t2 = SIDES == 3 ? wave_sum(acc2[i]) : 0.0;
     if (lane == 0 && b0 + i < n_box) {
-      p3[(b0 + i) * lay.n_p3 + chunk] = SIDES == 1 ? make_double2(0.0, t) : make_double2(t, 0.0);
+      p3[(b0 + i) * lay.n_p3 + chunk] = SIDES == 1 ? make_double2(0.0, t) : make_double2(t, t2);
       if (chunk == 0)
         for (int c = n_chunk; c < lay.n_p3; ++c) p3[(b0 + i) * lay.n_p3 + c] = make_double2(0.0, 0.0);
     }
@@ -353,8 +378,10 @@ void launch_screened_forward_sweep(const DevNet& net, int64_t n_box, void* ws, c
   const int per = (n_chunk * n_tg + 7) / 8;
   if (sides == 1)
     hipLaunchKernelGGL((k3p_sweep<1, kSparseQ>), dim3(8 * per), dim3(256), 0, s, net, ws, lay, n_box, n_chunk, n_tg);
-  else
+  else if (sides == 2)
     hipLaunchKernelGGL((k3p_sweep<2, kSparseQ>), dim3(8 * per), dim3(256), 0, s, net, ws, lay, n_box, n_chunk, n_tg);
+  else
+    hipLaunchKernelGGL((k3p_sweep<3, kSparseQ>), dim3(8 * per), dim3(256), 0, s, net, ws, lay, n_box, n_chunk, n_tg);
 }
 
 }  // namespace ibp

@@ -30,7 +30,7 @@ IBP_F_UPPER_ONLY = 32   # only f_hi is needed (f_lo = -inf)
 IBP_F_LOWER_ONLY = 64   # only f_lo is needed (f_hi valid but looser)
 IBP_F_KEEP_PREP = 128   # forward: leave the intermediates for a backward on the same boxes
 IBP_F_REUSE_PREP = 256  # backward: take them instead of recomputing
-IBP_F_SCREEN_UPPER = 512  # with IBP_F_LOWER_ONLY: screen the upper penalties (narrow boxes, points)
+IBP_F_SCREEN_UPPER = 512  # calls bounding f_lo: screen the upper penalties (narrow boxes, points)
 
 STATUS = {
     0: "IBP_OK",

@@ -205,8 +205,9 @@ def test_workspace_and_argument_errors():
                              vp(out.data_ptr() + 8), None, vp(ws.data_ptr()), need, None, 1 << 30)
     assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"  # an undefined flag bit
     st = lib.ibp_bound_boxes(n.handle, 1, vp(tlo.data_ptr()), vp(thi.data_ptr()), vp(out.data_ptr()),
-                             vp(out.data_ptr() + 8), None, vp(ws.data_ptr()), need, None, ibp.IBP_F_SCREEN_UPPER)
-    assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"  # only with IBP_F_LOWER_ONLY
+                             vp(out.data_ptr() + 8), None, vp(ws.data_ptr()), need, None,
+                             ibp.IBP_F_SCREEN_UPPER | ibp.IBP_F_UPPER_ONLY)
+    assert ibp.STATUS[st] == "IBP_E_INVALID_ARG"  # only for calls that bound f_lo
 
 
 def test_device_factors_match_oracle():
@@ -398,6 +399,25 @@ def test_three_bus_box_tiled_and_relaxation_paths():
     rc = oracle.crown_upper(net, lo[0].astype(float), hi[0].astype(float), oracle.factors(net))
     if rc["near"] == 0:
         assert np.all(c_hi >= rc["f_hi"])
+
+
+@pytest.mark.parametrize("name,nb,seed", [("tiny", 5, 3), ("c500", 37, 5), ("c2000", 70, 7)])
+def test_screened_two_sided_forward_matches_the_dense_sweep(monkeypatch, name, nb, seed):
+    """IBP_F_SCREEN_UPPER on a two-sided box-tiled call: both penalty sums
+    over the lines the upper-penalty screen marks (a line with no active upper
+    penalty has no active lower one), each element k3_elem's bit for bit:
+    both bounds within 1e-6 relative of the dense sweep's, enclosing the
+    oracle."""
+    net = synth.make_config(name)
+    fac = oracle.factors(net)
+    n = ibp.Network(net, device=0)
+    blo, bhi = synth.sub_boxes(net, nb, seed=seed)
+    s_lo, s_hi = gpu_bounds(n, blo, bhi, flags=ibp.IBP_F_SCREEN_UPPER)
+    d_lo, d_hi = gpu_bounds(n, blo, bhi)
+    assert one_sided_close(s_lo, d_lo) and one_sided_close(s_hi, d_hi)
+    for b in sorted({0, nb // 2, nb - 1}):
+        r = orc_plain(net, blo[b], bhi[b], fac)
+        assert s_lo[b] <= r["f_lo"] and s_hi[b] >= r["f_hi"], (b, s_lo[b], s_hi[b], r)
 
 
 @pytest.mark.parametrize("name,nb,seed", [("tiny", 5, 3), ("c500", 37, 5), ("c2000", 70, 7)])
