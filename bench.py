@@ -399,6 +399,9 @@ def extras(torch, ibp, synth, n4, net4):
                             "unit": "evals/s", "ms_per_call": ms4, "plain_value": ev4 / (ms4p * 1e-3),
                             "speedup_vs_plain": ms4p / ms4,
                             "tuned": _tuned(torch, ibp, n4, t4l, t4h, ws4, ev4, ms4)}
+    ms4s = _time(torch, lambda: ibp.ibp_bound_boxes(n4, t4l, t4h, ws=ws4, flags=ibp.IBP_F_SCREEN_UPPER), 3)
+    res["batched_large"]["screened"] = {"flags": "IBP_F_SCREEN_UPPER", "ms_per_call": ms4s,
+                                        "value": ev4 / (ms4s * 1e-3), "speedup_vs_default": ms4 / ms4s}
     # backward: 2000-bus network, 4096 sub-boxes of period 0
     blo, bhi = synth.sub_boxes(net3, 4096, seed=51)
     t5l, t5h = torch.from_numpy(blo).cuda(), torch.from_numpy(bhi).cuda()
