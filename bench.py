@@ -304,8 +304,9 @@ def _tuned(torch, ibp, net, tlo, thi, ws, ev, ms_default):
     tune_s = time.perf_counter() - t0
     ms = _time(torch, lambda: ibp.ibp_bound_boxes(net, tlo, thi, ws=ws), 3)
     net.set_tile_batched(keep["k3_bt"], keep["k3_rows"], keep["k3_xcd"], keep["k2_mfma"], keep["k2_by"])
-    return {"tiles": {k: tiles[k] for k in ("k3_bt", "k3_rows", "k3_xcd", "k2_mfma", "k2_by")},
-            "default_tiles": {k: keep[k] for k in ("k3_bt", "k3_rows", "k3_xcd", "k2_mfma", "k2_by")},
+    net.set_screen_upper(keep["screen_upper"])
+    names = ("k3_bt", "k3_rows", "k3_xcd", "k2_mfma", "k2_by", "screen_upper")
+    return {"tiles": {k: tiles[k] for k in names}, "default_tiles": {k: keep[k] for k in names},
             "ms_per_call": ms, "value": ev / (ms * 1e-3), "speedup_vs_default": ms_default / ms,
             "tune_seconds": round(tune_s, 3)}
 

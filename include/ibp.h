@@ -381,8 +381,10 @@ ibp_status ibp_autotune(ibp_network* net, int64_t n_box, const float* box_lo, co
  * order.  ibp_autotune_batched() times the candidates around the current
  * parameters on the caller's n_box >= 4 boxes (forward kernels on `stream`,
  * synchronizing; the base flows first, then the outage sweep with the chosen
- * base flows) and keeps the fastest; `chosen` (host int32[5], nullable)
- * receives (k3_bt, k3_rows, k3_xcd, k2_mfma, k2_by).  The workspace must hold
+ * base flows, then the same sweep over the lines the upper-penalty screen
+ * marks, kept in the screen-upper setting below if faster) and keeps the
+ * fastest; `chosen` (host int32[5], nullable) receives (k3_bt, k3_rows,
+ * k3_xcd, k2_mfma, k2_by).  The workspace must hold
  * ibp_workspace_bytes(net, n_box, IBP_F_AUTOTUNE).  ibp_get_tile() copies the
  * current parameters (host int32[7]: k2_nc, k3_kc, k3_bt, k3_rows, k3_xcd,
  * k2_mfma, k2_by).  None of the three may run concurrently with compute calls
@@ -392,6 +394,18 @@ ibp_status ibp_set_tile_batched(ibp_network* net, int32_t k3_bt, int32_t k3_rows
 ibp_status ibp_get_tile(const ibp_network* net, int32_t* out);
 ibp_status ibp_autotune_batched(ibp_network* net, int64_t n_box, const float* box_lo, const float* box_hi,
                                 void* ws, size_t ws_bytes, void* stream, int32_t* chosen);
+
+/* Screen-upper setting of the box-tiled path: with `on` = 1 every box-tiled
+ * call that bounds f_lo (two-sided or IBP_F_LOWER_ONLY) behaves as if it
+ * carried IBP_F_SCREEN_UPPER (bounds within the 1e-6 relative reordering that
+ * flag states, still certified; the workspace those calls need
+ * grows by the screen's regions, so query ibp_workspace_bytes after changing
+ * it).  Default 0; ibp_autotune_batched() sets it; IBP_TILE "scru=1" sets it
+ * at network build.  ibp_get_screen_upper() reads it into *on (host int32).
+ * Not concurrently with compute calls on the same handle.  Errors:
+ * INVALID_ARG. */
+ibp_status ibp_set_screen_upper(ibp_network* net, int32_t on);
+ibp_status ibp_get_screen_upper(const ibp_network* net, int32_t* on);
 
 /* Branch and bound over input boxes (the paper names branch and bound over
  * the inputs as the way to tighten IBP bounds, Sec. I and Sec. V, and screens

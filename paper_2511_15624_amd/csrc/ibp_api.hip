@@ -390,6 +390,7 @@ ibp_status to_device(ibp_network* net, int device) {
     if (const char* p = std::strstr(e, "k2by=")) t.k2_by = std::atoi(p + 5);
     if (const char* p = std::strstr(e, "k5s=")) t.k5_sparse = std::atoi(p + 4) != 0;
     if (const char* p = std::strstr(e, "k3s=")) t.k3_sparse = std::atoi(p + 4) != 0;
+    if (const char* p = std::strstr(e, "scru=")) t.k3_scr = std::atoi(p + 5) != 0;
     if (ibp::tune_valid(t) && ibp::tune_batched_valid(t) && (t.chord_nb == 2 || t.chord_nb == 4)) net->tune = t;
   }
   return IBP_OK;
@@ -437,6 +438,30 @@ std::vector<ibp::Tune> flow_candidates(const ibp_network* net, const ibp::Tune& 
   return out;
 }
 
+// Appends the line screen's regions (masks, line records, tile maxima) to a
+// box-tiled layout; fscreen says whether the screened forward sweep fits it
+// (one outage-penalty partial per chunk of 64 kSparseQ outages in the
+// finalize's slots).
+void add_screen(const ibp::DevNet& d, const ibp::Tune& tune, int64_t n_box, ibp::WsLayout& lay) {
+  const size_t B = (size_t)std::max<int64_t>(1, n_box);
+  size_t off = lay.total;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  lay.k5s_tiles = (int)((B + ibp::kScreenBoxes - 1) / ibp::kScreenBoxes);
+  const size_t tiles = (size_t)lay.k5s_tiles;
+  lay.smask = take(tiles * (d.Lp / 64) * sizeof(uint64_t));
+  lay.srec = take(tiles * d.Lp * ibp::kScreenRecFloats * sizeof(float));
+  lay.k5w_bx = (d.Kp + 255) / 256;
+  lay.sw = take(tiles * d.Kp * sizeof(float));
+  lay.sz = take(tiles * lay.k5w_bx * sizeof(float));
+  lay.total = off;
+  const int n_chunk = (d.K + 64 * ibp::kSparseQ - 1) / (64 * ibp::kSparseQ);
+  lay.fscreen = tune.k3_sparse && ibp::screen_fits(d, lay) && n_chunk <= lay.n_p3;
+}
+
 ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
   if (flags & IBP_F_AUTOTUNE) {
     // the largest layout over every tile pair (smallest tiles give most
@@ -448,7 +473,9 @@ ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
     if (n_box >= ibp::kBatchMin) {
       for (const ibp::Tune& f : flow_candidates(net, net->tune))
         for (const ibp::Tune& c : sweep_candidates(net, n_box, f)) {
-          const ibp::WsLayout l = layout_for(net, n_box, c, true);
+          ibp::WsLayout l = layout_for(net, n_box, c, true);
+          // and the upper-penalty screen, timed on the chosen tiles
+          if (net->dn.K > 0) add_screen(net->dn, c, n_box, l);
           if (l.total > big.total) big = l;
         }
     }
@@ -479,31 +506,15 @@ ibp::WsLayout layout(const ibp_network* net, int64_t n_box, uint32_t flags) {
     lay.total = off;
   }
   // the line screen of the one-sided sweeps (the backward's gradient of f_hi,
-  // the forward's one-sided bounds): masks, line records, tile maxima
+  // the forward's one-sided bounds) and of screened calls bounding f_lo
   const bool one_sided = (flags & (IBP_F_UPPER_ONLY | IBP_F_LOWER_ONLY)) != 0;
-  if (lay.batched && net->dn.K > 0 &&
-      (one_sided || (flags & (IBP_F_BACKWARD | IBP_F_KEEP_PREP | IBP_F_SCREEN_UPPER)))) {
-    const ibp::DevNet& d = net->dn;
-    const size_t B = (size_t)std::max<int64_t>(1, n_box);
-    size_t off = lay.total;
-    auto take = [&](size_t bytes) {
-      const size_t o = off;
-      off = align256(off + bytes);
-      return o;
-    };
-    lay.k5s_tiles = (int)((B + ibp::kScreenBoxes - 1) / ibp::kScreenBoxes);
-    const size_t tiles = (size_t)lay.k5s_tiles;
-    lay.smask = take(tiles * (d.Lp / 64) * sizeof(uint64_t));
-    lay.srec = take(tiles * d.Lp * ibp::kScreenRecFloats * sizeof(float));
-    lay.k5w_bx = (d.Kp + 255) / 256;
-    lay.sw = take(tiles * d.Kp * sizeof(float));
-    lay.sz = take(tiles * lay.k5w_bx * sizeof(float));
-    lay.total = off;
-    // the screened forward sweep writes one outage-penalty partial per chunk
-    // of 64 kSparseQ outages into the finalize's slots
-    const int n_chunk = (d.K + 64 * ibp::kSparseQ - 1) / (64 * ibp::kSparseQ);
-    const bool side_ok = (flags & IBP_F_UPPER_ONLY) || (flags & IBP_F_SCREEN_UPPER);
-    lay.fscreen = side_ok && net->tune.k3_sparse && ibp::screen_fits(d, lay) && n_chunk <= lay.n_p3;
+  const bool scr_upper = (flags & IBP_F_SCREEN_UPPER) || (net->tune.k3_scr && !(flags & IBP_F_UPPER_ONLY));
+  if (lay.batched && net->dn.K > 0 && (one_sided || scr_upper || (flags & (IBP_F_BACKWARD | IBP_F_KEEP_PREP)))) {
+    add_screen(net->dn, net->tune, n_box, lay);
+    const bool side_ok = (flags & IBP_F_UPPER_ONLY) || scr_upper;
+    lay.fscreen = side_ok && lay.fscreen;
+  } else {
+    lay.fscreen = 0;
   }
   if (flags & (IBP_F_CROWN | IBP_F_CROWN_REF)) {
     const ibp::DevNet& d = net->dn;
@@ -1036,6 +1047,24 @@ ibp_status ibp_set_tile_batched(ibp_network* net, int32_t k3_bt, int32_t k3_rows
   });
 }
 
+ibp_status ibp_set_screen_upper(ibp_network* net, int32_t on) {
+  return guarded([&]() -> ibp_status {
+    if (!net) return fail(IBP_E_INVALID_ARG, "network handle is NULL");
+    if (on != 0 && on != 1) return fail(IBP_E_INVALID_ARG, "on must be 0 or 1");
+    net->tune.k3_scr = on;
+    ++net->tile_gen;
+    return IBP_OK;
+  });
+}
+
+ibp_status ibp_get_screen_upper(const ibp_network* net, int32_t* on) {
+  return guarded([&]() -> ibp_status {
+    if (!net || !on) return fail(IBP_E_INVALID_ARG, "NULL argument");
+    *on = net->tune.k3_scr;
+    return IBP_OK;
+  });
+}
+
 ibp_status ibp_get_tile(const ibp_network* net, int32_t* out) {
   return guarded([&]() -> ibp_status {
     if (!net || !out) return fail(IBP_E_INVALID_ARG, "NULL argument");
@@ -1114,6 +1143,19 @@ ibp_status ibp_autotune_batched(ibp_network* net, int64_t n_box, const float* bo
         }
       }
       best_t = pick;
+      // the two-sided sweep over the lines the upper-penalty screen marks,
+      // against the dense one just picked (it pays where few lines carry an
+      // active upper penalty: narrow boxes)
+      ibp::Tune ts = best_t;
+      ts.k3_sparse = 1;
+      ibp::WsLayout lay = layout_for(net, n_box, ts, true);
+      add_screen(net->dn, ts, n_box, lay);
+      best_t.k3_scr = 0;
+      if (lay.fscreen) {
+        lay.sides = 3;
+        const float ms = time_it([&] { return ibp::launch_batched_sweeps(net->dn, n_box, ws, lay, s, &off, 1); });
+        if (st == IBP_OK && ms < best) best_t.k3_scr = 1;
+      }
     }
     if (st != IBP_OK) return st;
     net->tune = best_t;

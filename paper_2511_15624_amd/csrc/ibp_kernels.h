@@ -59,6 +59,7 @@ struct Tune {
   int k2_by = 0;    // bus chunks of the matrix-core base flows (0: by rule)
   int k5_sparse = 1; // box-tiled gradient of f_hi: screened sweep over candidate lines (0: dense sweep)
   int k3_sparse = 1; // box-tiled one-sided forward: screened sweep over candidate lines (0: dense sweep)
+  int k3_scr = 0;    // box-tiled calls bounding f_lo screen the upper penalties (as IBP_F_SCREEN_UPPER)
 };
 
 // Line screen of the one-sided sweeps (see ibp_screen.hip): boxes per tile

@@ -63,6 +63,8 @@ EXPORTED = [
     "ibp_autotune",
     "ibp_set_tile_batched",
     "ibp_get_tile",
+    "ibp_set_screen_upper",
+    "ibp_get_screen_upper",
     "ibp_autotune_batched",
     "ibp_split_select",
     "ibp_split_bisect",
@@ -187,6 +189,10 @@ def load_library(path: str = LIB_PATH):
     lib.ibp_set_tile_batched.restype = ctypes.c_int
     lib.ibp_get_tile.argtypes = [vp, vp]
     lib.ibp_get_tile.restype = ctypes.c_int
+    lib.ibp_set_screen_upper.argtypes = [vp, i32]
+    lib.ibp_set_screen_upper.restype = ctypes.c_int
+    lib.ibp_get_screen_upper.argtypes = [vp, vp]
+    lib.ibp_get_screen_upper.restype = ctypes.c_int
     lib.ibp_autotune_batched.argtypes = [vp, i64, vp, vp, vp, sz, vp, vp]
     lib.ibp_autotune_batched.restype = ctypes.c_int
     lib.ibp_split_select.argtypes = [i64, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp]
@@ -309,7 +315,17 @@ class Network:
     def tiles(self) -> dict:
         out = np.zeros(7, np.int32)
         _check(load_library().ibp_get_tile(self._h, out.ctypes.data_as(ctypes.c_void_p)))
-        return dict(zip(TILE_FIELDS, (int(v) for v in out)))
+        t = dict(zip(TILE_FIELDS, (int(v) for v in out)))
+        t["screen_upper"] = int(self.screen_upper())
+        return t
+
+    def set_screen_upper(self, on: bool):
+        _check(load_library().ibp_set_screen_upper(self._h, int(bool(on))))
+
+    def screen_upper(self) -> bool:
+        out = ctypes.c_int32(0)
+        _check(load_library().ibp_get_screen_upper(self._h, ctypes.byref(out)))
+        return bool(out.value)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -558,6 +574,7 @@ def ibp_autotune_batched(net: Network, lo, hi, stream=None, cache: str = None):
         if key in table:
             v = table[key]
             net.set_tile_batched(v["k3_bt"], v["k3_rows"], v["k3_xcd"], v["k2_mfma"], v["k2_by"])
+            net.set_screen_upper(v.get("screen_upper", 0))
             return net.tiles(), True
     need = net.workspace_bytes(n, IBP_F_AUTOTUNE)
     chosen = np.zeros(5, np.int32)
@@ -568,7 +585,7 @@ def ibp_autotune_batched(net: Network, lo, hi, stream=None, cache: str = None):
                                                    chosen.ctypes.data_as(ctypes.c_void_p)))
     tiles = net.tiles()
     if cache:
-        table[key] = {k: tiles[k] for k in ("k3_bt", "k3_rows", "k3_xcd", "k2_mfma", "k2_by")}
+        table[key] = {k: tiles[k] for k in ("k3_bt", "k3_rows", "k3_xcd", "k2_mfma", "k2_by", "screen_upper")}
         tmp = cache + ".tmp"
         with open(tmp, "w") as f:
             _json.dump(table, f, indent=1, sort_keys=True)

@@ -223,3 +223,11 @@ def test_tile_setters_validate_on_a_host_handle(lib):
             h.set_tile_batched(*bad)
         assert e.value.name == "IBP_E_INVALID_ARG"
     assert ibp.STATUS[lib.ibp_autotune_batched(h.handle, 8, None, None, None, 0, None, None)] == "IBP_E_HOST_ONLY"
+    assert h.tiles()["screen_upper"] == 0 and not h.screen_upper()
+    h.set_screen_upper(1)
+    assert h.screen_upper() and h.tiles()["screen_upper"] == 1
+    with pytest.raises(ibp.IBPError) as e:
+        ibp._check(lib.ibp_set_screen_upper(h.handle, 2))
+    assert e.value.name == "IBP_E_INVALID_ARG"
+    assert ibp.STATUS[lib.ibp_get_screen_upper(h.handle, None)] == "IBP_E_INVALID_ARG"
+    h.set_screen_upper(0)

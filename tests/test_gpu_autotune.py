@@ -56,11 +56,14 @@ def test_autotune_picks_a_candidate_and_caches_it(tmp_path):
     try:
         tiles, cached = ibp.ibp_autotune_batched(n, lo, hi, cache=cache)
         assert not cached and tiles["k3_bt"] in (2, 4, 8) and tiles["k2_mfma"] in (0, 1)
+        assert tiles["screen_upper"] in (0, 1)
         with open(cache) as f:
             table = json.load(f)
         key = ibp._tile_cache_key(n, 96)
         assert key.endswith("|B128") and table[key]["k3_bt"] == tiles["k3_bt"]
+        assert table[key]["screen_upper"] == tiles["screen_upper"]
         n.set_tile_batched(4, 0, -1, 1, 0)
+        n.set_screen_upper(1 - tiles["screen_upper"])
         again, cached = ibp.ibp_autotune_batched(n, lo, hi, cache=cache)
         assert cached and again == tiles
         f_lo, f_hi = gpu_bounds(n, blo, bhi)
@@ -68,4 +71,35 @@ def test_autotune_picks_a_candidate_and_caches_it(tmp_path):
             assert_encloses(f_lo[b], f_hi[b], orc(net, blo[b], bhi[b], fac), what=f"tuned box {b}")
     finally:
         n.set_tile_batched(4, 0, -1, 1, 0)
+        n.set_screen_upper(0)
     assert os.path.exists(cache)
+
+
+@pytest.mark.parametrize("name,nb", [("c500", 37), ("c2000", 70)])
+def test_screen_upper_setting_is_the_flag(name, nb):
+    """The screen-upper setting makes box-tiled calls that bound f_lo take the
+    upper-penalty screen as IBP_F_SCREEN_UPPER does: the same kernels, so the
+    same bits; calls bounding f_hi alone are untouched; the workspace those
+    calls need grows by the screen's regions."""
+    net, fac, n = setup(name)
+    blo, bhi = synth.sub_boxes(net, nb, seed=517)
+    assert not n.screen_upper()
+    base_ws = n.workspace_bytes(nb, 0)
+    f2 = gpu_bounds(n, blo, bhi, flags=ibp.IBP_F_SCREEN_UPPER)
+    fl = gpu_bounds(n, blo, bhi, flags=ibp.IBP_F_LOWER_ONLY | ibp.IBP_F_SCREEN_UPPER)
+    fu = gpu_bounds(n, blo, bhi, flags=ibp.IBP_F_UPPER_ONLY)
+    try:
+        n.set_screen_upper(1)
+        assert n.screen_upper() and n.tiles()["screen_upper"] == 1
+        assert n.workspace_bytes(nb, 0) > base_ws
+        for got, want in ((gpu_bounds(n, blo, bhi), f2),
+                          (gpu_bounds(n, blo, bhi, flags=ibp.IBP_F_LOWER_ONLY), fl),
+                          (gpu_bounds(n, blo, bhi, flags=ibp.IBP_F_UPPER_ONLY), fu)):
+            np.testing.assert_array_equal(got[0], want[0])
+            np.testing.assert_array_equal(got[1], want[1])
+    finally:
+        n.set_screen_upper(0)
+    assert n.workspace_bytes(nb, 0) == base_ws
+    for b in (0, nb - 1):
+        r = orc(net, blo[b], bhi[b], fac)
+        assert_encloses(f2[0][b], f2[1][b], r, what=f"{name} screened box {b}")
