@@ -263,12 +263,29 @@ def hbm_probe(torch, ibp):
             "note": "torch copy_ of 1 GiB (read + written bytes); ibp_read_probe over 1 GiB (read bytes)"}
 
 
+def alu_probe(torch, ibp):
+    """Measured float32 FMA issue rate: the library's probe (eight chains per
+    lane, 2^19 lanes, 16384 steps), with every operand in a vector register and
+    with one in a scalar register, 10 calls each."""
+    out = torch.empty(ibp.ALU_PROBE_LANES, dtype=torch.float32, device="cuda")
+    iters = 16384
+    ops = ibp.ALU_PROBE_LANES * 8 * iters
+    ms_v = _time(torch, lambda: ibp.ibp_alu_probe(out, iters, False), 10)
+    ms_s = _time(torch, lambda: ibp.ibp_alu_probe(out, iters, True), 10)
+    return {"fma_vector_operands_ops_per_s": ops / (ms_v * 1e-3), "fma_scalar_operand_ops_per_s": ops / (ms_s * 1e-3),
+            "frac_of_valu_peak": round(ops / (ms_v * 1e-3) / VALU_PEAK, 4),
+            "note": "lane FMAs per second of ibp_alu_probe; VALU_PEAK is 256 CUs x 128 float32 lanes per clock "
+                    "x 2.4 GHz, which FMAs with all-vector-register operands reach (one scalar-register operand: "
+                    "half the rate)"}
+
+
 VALU_PEAK = 78.6e12  # float32 VALU lane-ops/s: 256 CUs x 128 lanes/clock x 2.4 GHz (FMA = one op)
 MFMA_F64_PEAK = 78.6e12  # float64 dense matrix FLOP/s of MI355X
 MFMA_F32_PEAK = 157.3e12  # float32 dense matrix FLOP/s of MI355X
 VALU_PEAK_SOURCE = ("MI355X float32 vector peak 157.3 TFLOP/s with an FMA counted once: 256 CUs x 128 lanes per "
                     "clock x 2.4 GHz; the box-tiled sweep's counters show 0.414 wave instructions per SIMD per "
-                    "cycle, above what 16 lanes per clock allow (profiles/ibp_batched_counters_c2000.md)")
+                    "cycle, above what 16 lanes per clock allow (profiles/ibp_batched_counters_c2000.md), and "
+                    "the FMA probe's measured rate is reported beside it (alu_probe)")
 OPS_PER_EVAL = 9.25  # VALU ops per box-outage-line evaluation in the outage sweep (from the ISA)
 # VALU ops per box-outage-line element of the screened backward sweep (the
 # gradient of f_hi alone), on the elements of the lines its screen marks: the
@@ -640,6 +657,8 @@ def main(argv=None):
     ap.add_argument("--batched-only", type=int, default=0, metavar="CALLS",
                     help="only run the batched call (2000 buses, 18 x 1024 sub-boxes) CALLS times after one "
                          "warm-up call; for profiler runs")
+    ap.add_argument("--probes-only", action="store_true",
+                    help="only run the read-bandwidth and FMA issue-rate probes; for profiler runs")
     ap.add_argument("--backward-only", type=int, default=0, metavar="CALLS",
                     help="only run the one-sided backward (2000 buses, 4096 sub-boxes, gradient of f_hi) CALLS "
                          "times after one warm-up call, and print its per-kernel times; for profiler runs")
@@ -684,6 +703,10 @@ def main(argv=None):
         ms3 = _time(torch, lambda: ibp.ibp_bound_boxes(n3, tlo3, thi3, ws=ws3), args.batched_only)
         print(json.dumps({"workload": "2000 buses, 18 x 1024 sub-boxes", "calls": args.batched_only,
                           "ms_per_call": ms3}), flush=True)
+        return 0
+
+    if args.probes_only:
+        print(json.dumps({"hbm_probe": hbm_probe(torch, ibp), "alu_probe": alu_probe(torch, ibp)}), flush=True)
         return 0
 
     if args.chord_only:
@@ -821,6 +844,7 @@ def main(argv=None):
     g_lo, g_hi = float(f_lo.cpu()[0]), float(f_hi.cpu()[0])
     probe = hbm_probe(torch, ibp)
     out["hbm_probe"] = probe
+    out["alu_probe"] = alu_probe(torch, ibp)
     roof["frac_of_read_probe"] = round(achieved / probe["read_gbs"], 4)
     out["step_roofline"]["frac_of_read_probe"] = round(step_gbs / probe["read_gbs"], 4)
     if not args.no_extras:

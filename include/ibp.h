@@ -470,6 +470,18 @@ ibp_status ibp_split_screen(int64_t n_root, const double* root_ub, const double*
 #define IBP_READ_PROBE_PARTIALS 2048
 ibp_status ibp_read_probe(const void* src, int64_t n_float4, float* partial, void* stream);
 
+/* ibp_alu_probe -- float32 FMA issue-rate probe: 2048 blocks x 256 threads,
+ * each lane running eight independent chains a <- 0.5 a + 1 (fused
+ * multiply-add) for `iters` steps (1 .. 2^24), then writing the sum of its
+ * chains to out[lane] (device float32[IBP_ALU_PROBE_LANES], caller owned;
+ * 16.0 exactly once iters >= 64).  scalar_operand = 0 keeps every operand in a
+ * vector register; 1 reads the multiplier from a scalar register.  For
+ * calibration: the caller times it on `stream`; 2^22 x 8 x iters lane FMAs over
+ * the time is the vector-ALU rate the ALU-bound sweeps are priced against.
+ * Asynchronous.  Errors: INVALID_ARG, DEVICE. */
+#define IBP_ALU_PROBE_LANES 524288
+ibp_status ibp_alu_probe(float* out, int64_t iters, int32_t scalar_operand, void* stream);
+
 /* Last error message of the calling thread ("" if none). */
 const char* ibp_last_error(void);
 

@@ -1250,6 +1250,16 @@ ibp_status ibp_read_probe(const void* src, int64_t n_float4, float* partial, voi
   });
 }
 
+ibp_status ibp_alu_probe(float* out, int64_t iters, int32_t scalar_operand, void* stream) {
+  return guarded([&]() -> ibp_status {
+    g_err[0] = 0;
+    if (!out || iters < 1 || iters > (int64_t(1) << 24) || (scalar_operand != 0 && scalar_operand != 1))
+      return fail(IBP_E_INVALID_ARG, "ALU probe needs an output, 1 <= iters <= 2^24 and an operand mode of 0 or 1");
+    hipError_t e = ibp::launch_alu_probe(out, iters, scalar_operand, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? IBP_OK : fail(IBP_E_DEVICE, hipGetErrorString(e));
+  });
+}
+
 const char* ibp_last_error(void) { return g_err; }
 
 }  // extern "C"

@@ -509,8 +509,9 @@ __global__ __launch_bounds__(256) void k5p_sweep(DevNet net, void* ws, WsLayout 
   // one candidate line: the exact test of the dense sweep on Q x S elements
   // per lane, outage-side sums in registers, line-side counts by popcount
   auto line_step = [&](int l, const float4& c4, const float4& r4, const float (&x)[Q]) {
-    const float cl[S] = {c4.x, c4.y, c4.z, c4.w};
-    const float rl[S] = {r4.x, r4.y, r4.z, r4.w};
+    // each record value is read by Q elements' instructions: vector copies
+    const float cl[S] = {vcopy(c4.x), vcopy(c4.y), vcopy(c4.z), vcopy(c4.w)};
+    const float rl[S] = {vcopy(r4.x), vcopy(r4.y), vcopy(r4.z), vcopy(r4.w)};
     unsigned na[S], nn[S];
 #pragma unroll
     for (int i = 0; i < S; ++i) na[i] = nn[i] = 0u;

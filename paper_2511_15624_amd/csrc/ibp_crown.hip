@@ -851,10 +851,14 @@ __device__ __forceinline__ void chord_elem(float lam, float cc, float rk, float 
 
 // Four lines x one outage of one box: per-line fixed-point slope totals, and
 // the outage's four sums (a Lam, |a Lam|, alpha, m) into r[0..3].
+template <bool VCOPY>
 __device__ __forceinline__ void chord_row(const float4& x, const int4& d, const float4& c4, const float4& h4,
                                           const float4& g4, const float4& t4, int (&cs)[4], int (&ca)[4],
                                           float* r) {
-  const float cc = __int_as_float(d.y), rk = __int_as_float(d.z);
+  // the outage's record (scalar loads) is read by three instructions per
+  // line: vector copies where the registers allow (one box per lane)
+  const float cc = VCOPY ? vcopy(__int_as_float(d.y)) : __int_as_float(d.y);
+  const float rk = VCOPY ? vcopy(__int_as_float(d.z)) : __int_as_float(d.z);
   const float lam[4] = {x.x, x.y, x.z, x.w}, cl[4] = {c4.x, c4.y, c4.z, c4.w};
   const float hh[4] = {h4.x, h4.y, h4.z, h4.w}, gg[4] = {g4.x, g4.y, g4.z, g4.w};
   const float tt[4] = {t4.x, t4.y, t4.z, t4.w};
@@ -985,7 +989,7 @@ __global__ __launch_bounds__(256, MINB) void kc1c_chord(DevNet net, void* ws, Ws
         if (kg + o < k1)
 #pragma unroll
           for (int i = 0; i < NB; ++i)
-            chord_row(x[o], cd[i][kg + o], c4[i], h4[i], g4[i], t4, cs[i], ca[i], r + 4 * (o * NB + i));
+            chord_row<NB == 1>(x[o], cd[i][kg + o], c4[i], h4[i], g4[i], t4, cs[i], ca[i], r + 4 * (o * NB + i));
     }
     // a wave with no active element in the group skips the reduction
     bool act = false;

@@ -156,6 +156,7 @@ hipError_t launch_split_screen(int64_t R, const double* root_ub, const double* r
 
 // Streaming-read probe (see ibp_probe.hip): 2048 per-block partial sums.
 hipError_t launch_read_probe(const float4* src, int64_t n, float* partial, hipStream_t s);
+hipError_t launch_alu_probe(float* out, int64_t iters, int scalar, hipStream_t s);
 
 // K1..K4 for n_box boxes, each box handled by its own grid slice.
 hipError_t launch_forward_single(const DevNet& net, int64_t n_box, const float* lo, const float* hi,

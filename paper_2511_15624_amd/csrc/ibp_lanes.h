@@ -47,6 +47,20 @@ __device__ __forceinline__ double halve16(double a, double b) {
   return r0 + r1;
 }
 
+// A wave-uniform value held in a scalar register, copied into a vector
+// register.  On gfx950 a float32 VALU instruction that reads a scalar
+// register issues at half the rate of one whose operands are all vector
+// registers or constants (8 independent chains per lane, 8 waves per SIMD:
+// about 4.7 against 2.7 cycles per wave instruction), so a record value that
+// many instructions read is moved once.  The move is written out so that the
+// compiler cannot fold the scalar register back into its users; `s` must be
+// uniform across the wave (a scalar-loaded record).
+__device__ __forceinline__ float vcopy(float s) {
+  float v;
+  __asm__("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
+  return v;
+}
+
 // DPP moves within a row of 16 lanes: lane t receives lane t ^ 8 (row
 // rotation by 8), t ^ 2 (quad permutation [2,3,0,1]) or t ^ 1 ([1,0,3,2]).
 constexpr int kDppXor8 = 0x128;

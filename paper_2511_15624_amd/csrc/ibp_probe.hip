@@ -1,13 +1,18 @@
-// Streaming-read bandwidth probe: the load pattern of the library's HBM-bound
-// sweeps (float4 nontemporal loads, eight in flight per lane; 2048 blocks x 256
-// threads, each block streaming a contiguous range) with a trivial sum, so that
-// a caller can measure the read rate those sweeps can reach on this device.
+// Calibration probes.  Streaming-read bandwidth: the load pattern of the
+// library's HBM-bound sweeps (float4 nontemporal loads, eight in flight per
+// lane; 2048 blocks x 256 threads, each block streaming a contiguous range)
+// with a trivial sum, so that a caller can measure the read rate those sweeps
+// can reach on this device.  Float32 FMA issue rate: eight independent FMA
+// chains per lane on the same grid (eight waves per SIMD), with every operand
+// in a vector register or one in a scalar register, so that a caller can
+// measure the vector-ALU rate the ALU-bound sweeps are priced against.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
 #include "ibp_devfun.h"
 #include "ibp_kernels.h"
+#include "ibp_lanes.h"
 
 namespace ibp {
 
@@ -43,6 +48,41 @@ __global__ __launch_bounds__(256) void read_probe(const float4* __restrict__ src
 
 hipError_t launch_read_probe(const float4* src, int64_t n, float* partial, hipStream_t s) {
   hipLaunchKernelGGL(read_probe, dim3(kProbeBlocks), dim3(256), 0, s, src, n, partial);
+  return hipGetLastError();
+}
+
+// a <- a b + c per chain (b = 0.5, c = 1 from the caller: every chain reaches
+// the fixed point 2 exactly after a few dozen steps); SCALAR = 1 reads b from
+// its scalar register, SCALAR = 0 from a vector copy.
+template <int SCALAR>
+__global__ __launch_bounds__(256) void alu_probe(float* out, int64_t iters, float b, float c) {
+  const float vb = vcopy(b), vc = vcopy(c);
+  float a[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) a[j] = 1.0f + 0.125f * j;
+  // 32 FMAs between loop branches
+  int64_t it = 0;
+  for (; it + 4 <= iters; it += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) a[j] = fmaf(a[j], SCALAR ? b : vb, vc);
+  }
+  for (; it < iters; ++it) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a[j] = fmaf(a[j], SCALAR ? b : vb, vc);
+  }
+  float t = 0.0f;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) t += a[j];
+  out[(size_t)blockIdx.x * 256 + threadIdx.x] = t;
+}
+
+hipError_t launch_alu_probe(float* out, int64_t iters, int scalar, hipStream_t s) {
+  if (scalar)
+    hipLaunchKernelGGL(alu_probe<1>, dim3(kProbeBlocks), dim3(256), 0, s, out, iters, 0.5f, 1.0f);
+  else
+    hipLaunchKernelGGL(alu_probe<0>, dim3(kProbeBlocks), dim3(256), 0, s, out, iters, 0.5f, 1.0f);
   return hipGetLastError();
 }
 

@@ -36,6 +36,7 @@
 #include "ibp_device.h"
 #include "ibp_devfun.h"
 #include "ibp_kernels.h"
+#include "ibp_lanes.h"
 
 namespace ibp {
 
@@ -299,9 +300,11 @@ __global__ __launch_bounds__(256) void k3p_sweep(DevNet net, void* ws, WsLayout 
   // records: SIDES 1 (centres, g), SIDES 2 (centres, h), SIDES 3 (centres,
   // h, g)
   auto line_step = [&](const float4& c4, const float4& r4, const float4& g4, const float (&x)[Q]) {
-    const float cl[S] = {c4.x, c4.y, c4.z, c4.w};
-    const float rl[S] = {r4.x, r4.y, r4.z, r4.w};
-    const float gl[S] = {g4.x, g4.y, g4.z, g4.w};
+    // each record value is read by Q elements' instructions: vector copies
+    const float cl[S] = {vcopy(c4.x), vcopy(c4.y), vcopy(c4.z), vcopy(c4.w)};
+    const float rl[S] = {vcopy(r4.x), vcopy(r4.y), vcopy(r4.z), vcopy(r4.w)};
+    const float gl[S] = {SIDES == 3 ? vcopy(g4.x) : 0.0f, SIDES == 3 ? vcopy(g4.y) : 0.0f,
+                         SIDES == 3 ? vcopy(g4.z) : 0.0f, SIDES == 3 ? vcopy(g4.w) : 0.0f};
 #pragma unroll
     for (int i = 0; i < S; ++i) {
       float p[Q], p2[Q];

@@ -71,6 +71,7 @@ EXPORTED = [
     "ibp_split_update",
     "ibp_split_screen",
     "ibp_read_probe",
+    "ibp_alu_probe",
     "ibp_last_error",
 ]
 
@@ -205,6 +206,8 @@ def load_library(path: str = LIB_PATH):
     lib.ibp_split_screen.restype = ctypes.c_int
     lib.ibp_read_probe.argtypes = [vp, i64, vp, vp]
     lib.ibp_read_probe.restype = ctypes.c_int
+    lib.ibp_alu_probe.argtypes = [vp, i64, i32, vp]
+    lib.ibp_alu_probe.restype = ctypes.c_int
     lib.ibp_last_error.argtypes = []
     lib.ibp_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -532,6 +535,19 @@ def ibp_read_probe(src, partial, stream=None):
         raise ValueError("partial must be a float32 device tensor with 2048 entries")
     n4 = src.numel() * src.element_size() // 16
     _check(load_library().ibp_read_probe(_dev_ptr(src), n4, _dev_ptr(partial), _stream_ptr(stream)))
+
+
+ALU_PROBE_LANES = 524288
+
+
+def ibp_alu_probe(out, iters: int, scalar_operand: bool = False, stream=None):
+    """Float32 FMA issue-rate probe: eight FMA chains per lane over 2^19 lanes
+    for `iters` steps; writes each lane's chain sum (16.0 once iters >= 64)
+    into `out` (float32 device tensor of 2^19 entries)."""
+    torch = _torch()
+    if out.dtype != torch.float32 or out.numel() < ALU_PROBE_LANES or not out.is_cuda or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 device tensor with 524288 entries")
+    _check(load_library().ibp_alu_probe(_dev_ptr(out), int(iters), int(bool(scalar_operand)), _stream_ptr(stream)))
 
 
 def ibp_autotune(net: Network, lo, hi, stream=None):

@@ -376,6 +376,20 @@ def test_read_probe_sums_what_it_streams():
         ibp.ibp_read_probe(x, torch.empty(16, dtype=torch.float32, device="cuda"))
 
 
+def test_alu_probe_reaches_the_chains_fixed_point():
+    torch = _torch()
+    out = torch.empty(ibp.ALU_PROBE_LANES, dtype=torch.float32, device="cuda")
+    for scalar in (False, True):
+        out.fill_(0.0)
+        ibp.ibp_alu_probe(out, 64, scalar)
+        torch.cuda.synchronize()
+        assert bool(torch.all(out == 16.0)), scalar
+    with pytest.raises(ibp.IBPError):
+        ibp.ibp_alu_probe(out, 0)
+    with pytest.raises(ValueError):
+        ibp.ibp_alu_probe(out[:16], 64)
+
+
 def test_three_bus_box_tiled_and_relaxation_paths():
     """The hand-derived 3-bus box repeated 5 times takes the box-tiled kernels
     (matrix-core base flows with 3 buses: a partial step of four; relaxation
