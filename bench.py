@@ -287,6 +287,12 @@ VALU_PEAK_SOURCE = ("MI355X float32 vector peak 157.3 TFLOP/s with an FMA counte
                     "cycle, above what 16 lanes per clock allow (profiles/ibp_batched_counters_c2000.md), and "
                     "the FMA probe's measured rate is reported beside it (alu_probe)")
 OPS_PER_EVAL = 9.25  # VALU ops per box-outage-line evaluation in the outage sweep (from the ISA)
+# VALU ops per element of the chord-relaxation sweep: post-outage centre and
+# the two interval ends (5), the clipped lower end (3), the slope and its
+# quantisation (8), the intercept and its padding (4), the value bound (6),
+# activity, selects and sign (5), the fixed-point line totals (4) and the
+# outage's four sums with the factor product (8)
+CHORD_OPS_PER_ELEM = 43.0
 # VALU ops per box-outage-line element of the screened backward sweep (the
 # gradient of f_hi alone), on the elements of the lines its screen marks: the
 # post-outage centre and radius (2 fma), the activity and sign tests (2
@@ -571,8 +577,24 @@ def extras(torch, ibp, synth, n4, net4):
     l_lo3, _ = ibp.ibp_crown_lower_boxes(n3, c3l, c3h, ws=ws3c)
     i_lo3, _ = ibp.ibp_bound_boxes(n3, c3l, c3h, ws=ws3c)
     tightl = ((l_lo3 - i_lo3) / i_lo3.abs()).cpu()
+    n3.set_kernel_timing(True)
+    n3.kernel_times()
+    ibp.ibp_crown_lower_boxes(n3, c3l, c3h, ws=ws3c)
+    ktl3 = n3.kernel_times()
+    n3.set_kernel_timing(False)
+    # per call (the box-tiled call's timer slot also holds its small zeroing kernel)
+    sw1 = ktl["crown_outage_sweep"][0] / 5
+    sw3 = ktl3["crown_outage_sweep"][0]
+    e3 = 1024 * n3.n_ctg * n3.n_line
     res["crown_lower"] = {
         "workload": "chord-relaxation lower bound: the large single box; 1024 sub-boxes (2000 buses)",
+        "roofline_chord_sweep": {
+            "bound": "alu", "kernel": "crown_outage_sweep", "peak": VALU_PEAK, "unit": "ops/s",
+            "peak_source": VALU_PEAK_SOURCE, "ops_per_element": CHORD_OPS_PER_ELEM,
+            "single_box": {"ms": sw1, "achieved": ev1 * CHORD_OPS_PER_ELEM / (sw1 * 1e-3),
+                           "frac": ev1 * CHORD_OPS_PER_ELEM / (sw1 * 1e-3) / VALU_PEAK},
+            "batch": {"ms": sw3, "achieved": e3 * CHORD_OPS_PER_ELEM / (sw3 * 1e-3),
+                      "frac": e3 * CHORD_OPS_PER_ELEM / (sw3 * 1e-3) / VALU_PEAK}},
         "single_box_ms": ms_l1, "single_box_ms_ibp_only": ms_lin,
         "single_box_value": ev1 / (ms_l1 * 1e-3), "unit": "evals/s",
         "single_box_kernel_us": {k: round(v[0] / v[1] * 1e3, 2) for k, v in ktl.items()},
@@ -845,10 +867,23 @@ def main(argv=None):
     probe = hbm_probe(torch, ibp)
     out["hbm_probe"] = probe
     out["alu_probe"] = alu_probe(torch, ibp)
+    # every ALU roofline also against the probe's measured FMA rate
+    rate = out["alu_probe"]["fma_vector_operands_ops_per_s"]
+
+    def _frac_of_probe(d):
+        if isinstance(d, dict):
+            if d.get("bound") == "alu":
+                for sub in [d] + [v for v in d.values() if isinstance(v, dict) and "achieved" in v]:
+                    if "achieved" in sub:
+                        sub["frac_of_alu_probe"] = round(sub["achieved"] / rate, 4)
+            for v in d.values():
+                _frac_of_probe(v)
+
     roof["frac_of_read_probe"] = round(achieved / probe["read_gbs"], 4)
     out["step_roofline"]["frac_of_read_probe"] = round(step_gbs / probe["read_gbs"], 4)
     if not args.no_extras:
         out.update(extras(torch, ibp, synth, n, net))
+    _frac_of_probe(out)
     out["paper_context"] = {
         "figure": "mean IBP runtime per time index reaching 23.8 s on the largest instance (8316 buses, 11972 "
                   "lines, 6289 N-1 outages), alpha,beta-CROWN on an NVIDIA H200, graph construction included; "

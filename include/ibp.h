@@ -363,9 +363,10 @@ ibp_status ibp_kernel_times(ibp_network* net, int32_t n_ids, double* total_ms, i
  * The environment variable IBP_TILE, read by ibp_build_network, sets the same
  * parameters ("k2nc=64,k3kc=32"); "k2b=0" in it makes calls of 4 or more
  * boxes compute their base flows with vector float64 FMA instead of the
- * float64 matrix cores (the default; both sum the same products); "ckb=4"
- * makes the box-tiled chord-relaxation sweep of ibp_crown_lower_boxes keep four
- * boxes per lane instead of two (same results). */
+ * float64 matrix cores (the default; both sum the same products); "ckb=2"
+ * or "ckb=4" makes the box-tiled chord-relaxation sweep of
+ * ibp_crown_lower_boxes keep two or four boxes per lane instead of one (same
+ * results). */
 #define IBP_F_AUTOTUNE 2u /* workspace query only: size for every tile pair */
 ibp_status ibp_set_tile(ibp_network* net, int32_t k2_nc, int32_t k3_kc);
 ibp_status ibp_autotune(ibp_network* net, int64_t n_box, const float* box_lo, const float* box_hi,

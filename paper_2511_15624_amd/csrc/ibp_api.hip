@@ -391,7 +391,7 @@ ibp_status to_device(ibp_network* net, int device) {
     if (const char* p = std::strstr(e, "k5s=")) t.k5_sparse = std::atoi(p + 4) != 0;
     if (const char* p = std::strstr(e, "k3s=")) t.k3_sparse = std::atoi(p + 4) != 0;
     if (const char* p = std::strstr(e, "scru=")) t.k3_scr = std::atoi(p + 5) != 0;
-    if (ibp::tune_valid(t) && ibp::tune_batched_valid(t) && (t.chord_nb == 2 || t.chord_nb == 4)) net->tune = t;
+    if (ibp::tune_valid(t) && ibp::tune_batched_valid(t) && (t.chord_nb == 1 || t.chord_nb == 2 || t.chord_nb == 4)) net->tune = t;
   }
   return IBP_OK;
 }

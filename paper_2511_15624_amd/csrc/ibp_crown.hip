@@ -1189,6 +1189,9 @@ hipError_t launch_crown_lower(const DevNet& net, int64_t n_box, const float* lo,
     if (n_box < kCB)
       hipLaunchKernelGGL((kc1c_chord<1, 5, kCKB1>), dim3((unsigned)n_box, lay.kc_bx, lay.chp_z), dim3(256), 0, s,
                          net, ws, lay, n_box);
+    else if (lay.chord_nb == 1)
+      hipLaunchKernelGGL((kc1c_chord<1, 5, kCKB>), dim3((unsigned)n_box, lay.kc_bx, kz), dim3(256), 0, s, net, ws,
+                         lay, n_box);
     else if (lay.chord_nb == 2)
       hipLaunchKernelGGL((kc1c_chord<2, 5, kCKB>), dim3((unsigned)((n_box + 1) / 2), lay.kc_bx, kz), dim3(256), 0,
                          s, net, ws, lay, n_box);

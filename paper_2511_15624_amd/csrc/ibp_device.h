@@ -115,7 +115,7 @@ struct WsLayout {
   size_t cp = 0;                   // double2 [B][n_cp]: per-input partial sums
   size_t ct = 0;                   // double2 [B][n_ct]: per-line partial sums (limit total, sum vabs)
   int kc_bx = 0, kc_by = 0, kc3_bx = 0, kc3_by = 0, n_cp = 0, n_ct = 0;
-  int chord_nb = 2;                // boxes per lane of the box-tiled chord sweep
+  int chord_nb = 1;                // boxes per lane of the box-tiled chord sweep
   int k3_xcd = 0;                  // box-tiled outage sweep in XCD-aware block order
   size_t chp = 0;                  // int2 [B][chp_z][Lp]: per-box chord sweep, per-block line totals
   int chp_z = 0;                   // outage blocks of the per-box chord sweep (0: box-tiled, atomics)

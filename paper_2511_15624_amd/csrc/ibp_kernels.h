@@ -51,7 +51,7 @@ struct Tune {
   int k2_nc = 128;  // buses per wave in the base-flow sweep: 32, 64, 128, 256 or 512
   int k3_kc = 16;   // outages per block in the outage sweep: 16, 32, 64 or 128
   int k2b_mfma = 1; // box-tiled base flows on the float64 matrix cores (0: vector FMA)
-  int chord_nb = 2; // boxes per lane in the box-tiled chord-relaxation sweep: 2 or 4
+  int chord_nb = 1; // boxes per lane in the box-tiled chord-relaxation sweep: 1, 2 or 4
   // box-tiled forward (the autotuner's batched candidates)
   int k3_bt = 4;    // boxes per wave in the box-tiled outage sweep: 2, 4 or 8
   int k3_rows = 0;  // outage rows of that sweep (0: the rule of batched_rows_rule)

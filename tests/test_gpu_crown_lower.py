@@ -203,15 +203,18 @@ def test_c2000_1024_boxes_sampled():
         check_box(net, fac, blo[b], bhi[b], f_lo[b], f_hi[b], c[b], i_lo[b], i_hi[b], f"c2000 box {b}")
 
 
-def test_two_and_four_boxes_per_lane_agree(monkeypatch):
-    """The box-tiled sweep keeps two boxes per lane by default; IBP_TILE=ckb=4
-    keeps four.  Every per-box sum is formed in the same order either way, so
-    the bounds are bitwise equal (37 boxes: ragged against both tiles)."""
+def test_one_two_and_four_boxes_per_lane_agree(monkeypatch):
+    """The box-tiled sweep keeps one box per lane by default; IBP_TILE=ckb=2
+    and ckb=4 keep two and four.  Every per-box sum is formed in the same
+    order either way, so the bounds are bitwise equal (37 boxes: ragged
+    against every tile)."""
     net, fac, n = setup("c500")
-    monkeypatch.setenv("IBP_TILE", "ckb=4")
-    n4 = ibp.Network(net, device=0)
-    monkeypatch.delenv("IBP_TILE")
     blo, bhi = synth.sub_boxes(net, 37, seed=14)
     a_lo, a_hi, a_c = gpu_lower(n, blo, bhi)
-    b_lo, b_hi, b_c = gpu_lower(n4, blo, bhi)
-    assert np.array_equal(a_c, b_c) and np.array_equal(a_lo, b_lo) and np.array_equal(a_hi, b_hi)
+    for ckb in ("2", "4"):
+        monkeypatch.setenv("IBP_TILE", "ckb=" + ckb)
+        nk = ibp.Network(net, device=0)
+        monkeypatch.delenv("IBP_TILE")
+        b_lo, b_hi, b_c = gpu_lower(nk, blo, bhi)
+        assert np.array_equal(a_c, b_c) and np.array_equal(a_lo, b_lo) and np.array_equal(a_hi, b_hi), ckb
+        nk.close()
