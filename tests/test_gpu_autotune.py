@@ -103,3 +103,15 @@ def test_screen_upper_setting_is_the_flag(name, nb):
     for b in (0, nb - 1):
         r = orc(net, blo[b], bhi[b], fac)
         assert_encloses(f2[0][b], f2[1][b], r, what=f"{name} screened box {b}")
+
+
+def test_tile_environment_sets_the_screen_upper_setting(monkeypatch):
+    net = synth.make_config("tiny")
+    monkeypatch.setenv("IBP_TILE", "scru=1")
+    n = ibp.Network(net, device=0)
+    monkeypatch.delenv("IBP_TILE")
+    assert n.screen_upper() and n.tiles()["screen_upper"] == 1
+    n.close()
+    n = ibp.Network(net, device=0)
+    assert not n.screen_upper()
+    n.close()
